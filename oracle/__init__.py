@@ -1,0 +1,223 @@
+"""FP64 CPU oracle for the D2Q9 momentum-exchange path (test infrastructure).
+
+This package is the independent reference for the GPU library: only the test
+suite, the smoke check and the benchmark's CPU-baseline leg may import it.  The
+arithmetic lives in ``lbm_oracle.c`` (plain C, built with ``-O2
+-ffp-contract=off``); this module only marshals arrays through ctypes.  It
+shares no code with the GPU path.
+
+Method: Wen et al., arXiv:1303.0625 -- LBE collision/advection (Sec. II,
+Eqs. 1-3), Eq. 8 equilibrium, half-way bounce-back with the moving-boundary
+term (Sec. III.A), CME (Eq. 4) and GME (Eq. 5) link forces, total force and
+torque (Eqs. 6-7), newborn refill A1/A2/A3 (Sec. IV.B).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_oracle.c")
+_LIB = os.path.join(_HERE, "liblbm_oracle.so")
+
+DISC, BOX = 0, 1
+CME, GME = 0, 1
+A1, A2, A3 = 0, 1, 2
+
+# D2Q9 set in the order of Sec. III.C (the oracle's own copy; tests use it to
+# build inputs and closed forms).
+EX = (0, 1, 0, -1, 0, 1, -1, -1, 1)
+EY = (0, 0, 1, 0, -1, 1, 1, -1, -1)
+OPP = (0, 3, 4, 1, 2, 7, 8, 5, 6)
+W = (4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with gcc; returns its path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
+               "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Body(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("moves", ctypes.c_int),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("vx", ctypes.c_double), ("vy", ctypes.c_double)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.orc_create.restype = ctypes.c_void_p
+    lib.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(_Body)]
+    lib.orc_destroy.argtypes = [ctypes.c_void_p]
+    lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+    lib.orc_time.argtypes = [ctypes.c_void_p]
+    lib.orc_time.restype = ctypes.c_long
+    lib.orc_fields.argtypes = [ctypes.c_void_p, dp, dp, dp, ip]
+    lib.orc_force.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp]
+    lib.orc_force.restype = ctypes.c_int
+    lib.orc_links.argtypes = [ctypes.c_void_p, ctypes.c_long, dp]
+    lib.orc_links.restype = ctypes.c_long
+    lib.orc_get_f.argtypes = [ctypes.c_void_p, dp]
+    lib.orc_set_f.argtypes = [ctypes.c_void_p, dp]
+    lib.orc_init_fields.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    lib.orc_feq.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    lib.orc_link_force.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+    lib.orc_collide_node.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+    lib.orc_refill_node.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ip,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, dp]
+    lib.orc_refill_node.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def feq(rho: float, ux: float, uy: float) -> np.ndarray:
+    """Eq. 8 equilibrium, nine directions."""
+    out = np.zeros(9)
+    _load().orc_feq(rho, ux, uy, _dp(out))
+    return out
+
+
+def link_force(i: int, a: float, b: float, vx: float, vy: float, scheme: int) -> np.ndarray:
+    """Eq. 4 (CME) or Eq. 5 (GME) for one link in direction i."""
+    out = np.zeros(2)
+    _load().orc_link_force(i, a, b, vx, vy, scheme, _dp(out))
+    return out
+
+
+def collide_node(f, tau: float, gx: float = 0.0, gy: float = 0.0) -> np.ndarray:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros(9)
+    _load().orc_collide_node(_dp(f), tau, gx, gy, _dp(out))
+    return out
+
+
+def refill_node(fpost: np.ndarray, oldfluid: np.ndarray, x: int, y: int, scheme: int,
+                walls_y: bool = False, rho0: float = 1.0, v=(0.0, 0.0)):
+    """Refill of one newborn node; returns (f[9], number of participating links)."""
+    fpost = np.ascontiguousarray(fpost, dtype=np.float64)
+    oldfluid = np.ascontiguousarray(oldfluid, dtype=np.int32)
+    _, ny, nx = fpost.shape
+    out = np.zeros(9)
+    n = _load().orc_refill_node(nx, ny, int(walls_y), _dp(fpost), _ip(oldfluid), x, y, scheme,
+                                rho0, v[0], v[1], _dp(out))
+    return out, n
+
+
+class OracleSim:
+    """One D2Q9 simulation held by the C oracle.
+
+    ``bodies`` is a sequence of dicts with keys kind ('disc'|'box' or 0|1),
+    cx, cy, r (or hx), hy, vx, vy, moves.
+    """
+
+    def __init__(self, nx, ny, tau, *, walls_y=False, rho0=1.0, gx=0.0, gy=0.0, u0=(0.0, 0.0),
+                 wall_v=(0.0, 0.0), refill=A1, rho_w_local=False, bodies=()):
+        lib = _load()
+        self.nx, self.ny = int(nx), int(ny)
+        self.nb = len(bodies)
+        arr = (_Body * max(1, self.nb))()
+        for k, b in enumerate(bodies):
+            kind = b.get("kind", DISC)
+            if isinstance(kind, str):
+                kind = DISC if kind == "disc" else BOX
+            arr[k].kind = kind
+            arr[k].moves = int(b.get("moves", 0))
+            arr[k].cx = float(b["cx"])
+            arr[k].cy = float(b["cy"])
+            arr[k].a = float(b.get("r", b.get("hx", 0.0)))
+            arr[k].b = float(b.get("hy", 0.0))
+            arr[k].vx = float(b.get("vx", 0.0))
+            arr[k].vy = float(b.get("vy", 0.0))
+        self._lib = lib
+        self._h = lib.orc_create(self.nx, self.ny, int(walls_y), tau, rho0, gx, gy, u0[0], u0[1],
+                                 wall_v[0], wall_v[1], int(refill), int(rho_w_local), self.nb, arr)
+        if not self._h:
+            raise ValueError("oracle rejected the configuration")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_destroy(h)
+            self._h = None
+
+    @property
+    def t(self) -> int:
+        return self._lib.orc_time(self._h)
+
+    def step(self, n: int = 1) -> None:
+        self._lib.orc_step(self._h, int(n))
+
+    def fields(self):
+        shp = (self.ny, self.nx)
+        rho, ux, uy = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        own = np.zeros(shp, dtype=np.int32)
+        self._lib.orc_fields(self._h, _dp(rho), _dp(ux), _dp(uy), _ip(own))
+        return rho, ux, uy, own
+
+    def force(self, solid: int, scheme: int, step: int | None = None) -> np.ndarray:
+        out = np.zeros(3)
+        if step is None:
+            step = self.t - 1
+        if self._lib.orc_force(self._h, int(step), int(solid), int(scheme), _dp(out)) != 0:
+            raise IndexError("no force record for that step/solid")
+        return out
+
+    def force_history(self, scheme: int) -> np.ndarray:
+        """[steps][n_bodies+1][3] array of {Fx, Fy, Tz}."""
+        T = self.t
+        h = np.zeros((T, self.nb + 1, 3))
+        for st in range(T):
+            for s in range(self.nb + 1):
+                h[st, s] = self.force(s, scheme, st)
+        return h
+
+    def links(self) -> np.ndarray:
+        n = self._lib.orc_links(self._h, 0, None)
+        rec = np.zeros((max(n, 1), 8))
+        self._lib.orc_links(self._h, n, _dp(rec))
+        return rec[:n]
+
+    def get_f(self) -> np.ndarray:
+        f = np.zeros((9, self.ny, self.nx))
+        self._lib.orc_get_f(self._h, _dp(f))
+        return f
+
+    def set_f(self, f: np.ndarray) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        assert f.shape == (9, self.ny, self.nx)
+        self._lib.orc_set_f(self._h, _dp(f))
+
+    def init_fields(self, rho, ux, uy) -> None:
+        rho, ux, uy = (np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy))
+        self._lib.orc_init_fields(self._h, _dp(rho), _dp(ux), _dp(uy))

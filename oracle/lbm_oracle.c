@@ -1,0 +1,499 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see the
+ * header).  Every loop is a direct statement of the method; nothing is
+ * blocked, fused or reordered for speed.  Build with -ffp-contract=off so that
+ * no multiply-add is fused: the solid/fluid decision of the rasterisation must
+ * be taken with separately rounded products and sums.
+ *
+ * One time step t -> t+1 on geometry G_t (Sec. II, Sec. III.A-B, Sec. IV.B):
+ *   O1 moments       rho = sum f_i, rho*u = sum e_i f_i + rho*g/2
+ *   O2 collision     Eq. 2 with the single-relaxation-time (BGK) operator,
+ *                    Eq. 8 equilibrium and Guo's forcing term
+ *   O3 link forces   Eq. 4 (CME) and Eq. 5 (GME) on every fluid-solid link,
+ *                    summed per solid (Eq. 6) with torque (Eq. 7)
+ *   O4 advection     Eq. 3; a population whose source node is solid is the
+ *                    half-way bounce-back of the node's own opposite population
+ *                    plus the moving-boundary term 6 w_i rho_w (e_i . v)
+ *   O5 move bodies   positions at t+1, rasterise G_{t+1}
+ *   O6 covered nodes populations dropped
+ *   O7 newborn nodes refilled by extrapolation along the participating links
+ *                    (A1 second order, A2 linear, A3 neighbour value), averaged
+ *   O8 t <- t+1
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* D2Q9 velocity set in the order given in Sec. III.C. */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+/* ibar: the direction opposite to i. */
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+/* Weights of Eq. 8 (the D2Q9 set; Eq. 10 reproduces the pressure rho/3 only
+ * with these). */
+static const double W[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                            1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+struct orc_sim {
+    int nx, ny, walls_y;
+    double tau, rho0, gx, gy;
+    double wall_vx, wall_vy;
+    int refill, rho_w_local;
+    int nb;
+    orc_body* body;
+    long t;
+    double* f;       /* pre-collision f(t), [9][ny][nx] */
+    double* ft;      /* post-collision f~(t) */
+    double* fn;      /* post-advection f(t+1) */
+    int* own;        /* owner map of G_t: 0 fluid, s > 0 body s */
+    int* own_next;   /* owner map of G_{t+1} */
+    int* oldfluid;   /* fluid in both G_t and G_{t+1} */
+    /* force history: [step][nb+1][6] = CME {Fx, Fy, Tz}, GME {Fx, Fy, Tz} */
+    long hist_len, hist_cap;
+    double* hist;
+    /* per-link records of the last step */
+    long nlink, link_cap;
+    double* link;
+};
+
+static long idx(const orc_sim* s, int x, int y) { return (long)y * s->nx + x; }
+static long pidx(const orc_sim* s, int i, int x, int y) {
+    return ((long)i * s->ny + y) * s->nx + x;
+}
+
+static int wrap(int v, int n) {
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Position of body b at step t. */
+static void body_pos(const orc_body* b, long t, double* X, double* Y) {
+    if (b->moves) {
+        *X = b->cx + (double)t * b->vx;
+        *Y = b->cy + (double)t * b->vy;
+    } else {
+        *X = b->cx;
+        *Y = b->cy;
+    }
+}
+
+/* Whether the point with integer coordinates (x, y) lies inside body b
+ * centred at (X, Y).  Disc: dx*dx + dy*dy <= r*r.  Box: |dx| <= a, |dy| <= b. */
+static int inside(const orc_body* b, double X, double Y, long x, long y) {
+    double dx = (double)x - X;
+    double dy = (double)y - Y;
+    if (b->kind == ORC_DISC) {
+        double d2 = dx * dx;
+        d2 = d2 + dy * dy;
+        return d2 <= b->a * b->a;
+    }
+    return fabs(dx) <= b->a && fabs(dy) <= b->b;
+}
+
+/* Rasterise all bodies at step t into own (0 = fluid).  Every integer point
+ * of each body's bounding range is tested and mapped to its periodic image. */
+static void rasterise(const orc_sim* s, long t, int* own) {
+    memset(own, 0, sizeof(int) * (size_t)s->nx * (size_t)s->ny);
+    for (int k = 0; k < s->nb; ++k) {
+        const orc_body* b = &s->body[k];
+        double X, Y;
+        body_pos(b, t, &X, &Y);
+        double hx = b->a;
+        double hy = (b->kind == ORC_DISC) ? b->a : b->b;
+        long x0 = (long)floor(X - hx) - 1, x1 = (long)ceil(X + hx) + 1;
+        long y0 = (long)floor(Y - hy) - 1, y1 = (long)ceil(Y + hy) + 1;
+        for (long y = y0; y <= y1; ++y) {
+            for (long x = x0; x <= x1; ++x) {
+                if (!inside(b, X, Y, x, y)) continue;
+                int xi = wrap((int)x, s->nx);
+                int yi;
+                if (s->walls_y) {
+                    if (y < 0 || y >= s->ny) continue; /* validated never to happen */
+                    yi = (int)y;
+                } else {
+                    yi = wrap((int)y, s->ny);
+                }
+                own[idx(s, xi, yi)] = k + 1;
+            }
+        }
+    }
+}
+
+/* Neighbour of (x, y) in direction +e_i (sign = +1) or -e_i (sign = -1).
+ * Returns 0 and the wrapped node, or 1 if it is a virtual wall node. */
+static int neighbour(const orc_sim* s, int x, int y, int i, int sign, int* xo, int* yo) {
+    int xn = x + sign * EX[i];
+    int yn = y + sign * EY[i];
+    *xo = wrap(xn, s->nx);
+    if (s->walls_y) {
+        if (yn < 0 || yn >= s->ny) return 1;
+        *yo = yn;
+    } else {
+        *yo = wrap(yn, s->ny);
+    }
+    return 0;
+}
+
+void orc_feq(double rho, double ux, double uy, double out[9]) {
+    double uu = ux * ux + uy * uy;
+    for (int i = 0; i < 9; ++i) {
+        double eu = EX[i] * ux + EY[i] * uy;
+        out[i] = rho * W[i] * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+}
+
+/* O1 + O2 for one node. */
+void orc_collide_node(const double f[9], double tau, double gx, double gy, double out[9]) {
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        rho += f[i];
+        jx += EX[i] * f[i];
+        jy += EY[i] * f[i];
+    }
+    /* Guo et al.: the velocity includes half the body force. */
+    double ux = (jx + 0.5 * rho * gx) / rho;
+    double uy = (jy + 0.5 * rho * gy) / rho;
+    double feq[9];
+    orc_feq(rho, ux, uy, feq);
+    double pref = 1.0 - 1.0 / (2.0 * tau);
+    for (int i = 0; i < 9; ++i) {
+        double eu = EX[i] * ux + EY[i] * uy;
+        double sx = 3.0 * (EX[i] - ux) + 9.0 * eu * EX[i];
+        double sy = 3.0 * (EY[i] - uy) + 9.0 * eu * EY[i];
+        double src = pref * W[i] * (sx * rho * gx + sy * rho * gy);
+        out[i] = f[i] - (f[i] - feq[i]) / tau + src;
+    }
+}
+
+void orc_link_force(int i, double a, double b, double vx, double vy, int scheme, double out[2]) {
+    int ib = OPP[i];
+    if (scheme == ORC_CME) {
+        /* Eq. 4: e_i f~_i(x_f) - e_ibar f~_ibar(x_b) */
+        out[0] = EX[i] * a - EX[ib] * b;
+        out[1] = EY[i] * a - EY[ib] * b;
+    } else {
+        /* Eq. 5: (e_i - v) f~_i(x_f) - (e_ibar - v) f~_ibar(x_b) */
+        out[0] = (EX[i] - vx) * a - (EX[ib] - vx) * b;
+        out[1] = (EY[i] - vy) * a - (EY[ib] - vy) * b;
+    }
+}
+
+int orc_refill_node(int nx, int ny, int walls_y, const double* fpost, const int* oldfluid,
+                    int x, int y, int scheme, double rho0, double vx, double vy, double out[9]) {
+    double acc[9] = {0};
+    int npart = 0;
+    for (int k = 1; k < 9; ++k) {
+        /* node positions x + m e_k, m = 1, 2, 3; ok[m] = old-fluid there */
+        int ok[4] = {0, 0, 0, 0};
+        long at[4] = {0, 0, 0, 0};
+        for (int m = 1; m <= 3; ++m) {
+            int xm = x + m * EX[k], ym = y + m * EY[k];
+            if (walls_y && (ym < 0 || ym >= ny)) break;
+            xm = wrap(xm, nx);
+            ym = wrap(ym, ny);
+            at[m] = (long)ym * nx + xm;
+            ok[m] = oldfluid[at[m]] != 0;
+            if (!ok[m]) break;
+        }
+        if (!ok[1]) continue; /* direction k does not participate */
+        npart++;
+        int use = scheme;
+        if (use == ORC_A1 && !(ok[2] && ok[3])) use = ORC_A2;
+        if (use == ORC_A2 && !ok[2]) use = ORC_A3;
+        for (int j = 0; j < 9; ++j) {
+            long plane = (long)j * nx * ny;
+            double v1 = fpost[plane + at[1]];
+            double val;
+            if (use == ORC_A1) {
+                /* quadratic through m = 1, 2, 3 evaluated at m = 0 */
+                double v2 = fpost[plane + at[2]], v3 = fpost[plane + at[3]];
+                val = 3.0 * v1 - 3.0 * v2 + v3;
+            } else if (use == ORC_A2) {
+                /* line through m = 1, 2 evaluated at m = 0 */
+                double v2 = fpost[plane + at[2]];
+                val = 2.0 * v1 - v2;
+            } else {
+                val = v1;
+            }
+            acc[j] += val;
+        }
+    }
+    if (npart == 0) {
+        orc_feq(rho0, vx, vy, out);
+        return 0;
+    }
+    for (int j = 0; j < 9; ++j) out[j] = acc[j] / npart;
+    return npart;
+}
+
+orc_sim* orc_create(int nx, int ny, int walls_y, double tau, double rho0, double gx, double gy,
+                    double u0x, double u0y, double wall_vx, double wall_vy, int refill,
+                    int rho_w_local, int n_bodies, const orc_body* bodies) {
+    if (nx < 1 || ny < 1 || !(tau > 0.5) || refill < 0 || refill > 2 || n_bodies < 0) return NULL;
+    orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
+    s->nx = nx;
+    s->ny = ny;
+    s->walls_y = walls_y ? 1 : 0;
+    s->tau = tau;
+    s->rho0 = rho0;
+    s->gx = gx;
+    s->gy = gy;
+    s->wall_vx = wall_vx;
+    s->wall_vy = wall_vy;
+    s->refill = refill;
+    s->rho_w_local = rho_w_local ? 1 : 0;
+    s->nb = n_bodies;
+    s->body = (orc_body*)calloc((size_t)(n_bodies > 0 ? n_bodies : 1), sizeof(orc_body));
+    for (int k = 0; k < n_bodies; ++k) s->body[k] = bodies[k];
+    size_t n = (size_t)nx * (size_t)ny;
+    s->f = (double*)calloc(9 * n, sizeof(double));
+    s->ft = (double*)calloc(9 * n, sizeof(double));
+    s->fn = (double*)calloc(9 * n, sizeof(double));
+    s->own = (int*)calloc(n, sizeof(int));
+    s->own_next = (int*)calloc(n, sizeof(int));
+    s->oldfluid = (int*)calloc(n, sizeof(int));
+    s->t = 0;
+    rasterise(s, 0, s->own);
+    double feq[9];
+    orc_feq(rho0, u0x, u0y, feq);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            if (s->own[idx(s, x, y)] == 0)
+                for (int i = 0; i < 9; ++i) s->f[pidx(s, i, x, y)] = feq[i];
+    return s;
+}
+
+void orc_destroy(orc_sim* s) {
+    if (!s) return;
+    free(s->body);
+    free(s->f);
+    free(s->ft);
+    free(s->fn);
+    free(s->own);
+    free(s->own_next);
+    free(s->oldfluid);
+    free(s->hist);
+    free(s->link);
+    free(s);
+}
+
+long orc_time(const orc_sim* s) { return s->t; }
+
+static double* hist_row(orc_sim* s, long step) {
+    if (step >= s->hist_cap) {
+        long cap = s->hist_cap ? s->hist_cap * 2 : 1024;
+        while (cap <= step) cap *= 2;
+        s->hist = (double*)realloc(s->hist, sizeof(double) * (size_t)cap * (size_t)(s->nb + 1) * 6);
+        s->hist_cap = cap;
+    }
+    return s->hist + (size_t)step * (size_t)(s->nb + 1) * 6;
+}
+
+static void push_link(orc_sim* s, const double rec[8]) {
+    if (s->nlink == s->link_cap) {
+        s->link_cap = s->link_cap ? s->link_cap * 2 : 4096;
+        s->link = (double*)realloc(s->link, sizeof(double) * 8 * (size_t)s->link_cap);
+    }
+    memcpy(s->link + 8 * s->nlink, rec, 8 * sizeof(double));
+    s->nlink++;
+}
+
+/* Minimum-image difference of a coordinate on a periodic axis of length n. */
+static double min_image(double d, int n) {
+    while (d > 0.5 * n) d -= n;
+    while (d < -0.5 * n) d += n;
+    return d;
+}
+
+static void one_step(orc_sim* s) {
+    const int nx = s->nx, ny = s->ny;
+    const long t = s->t;
+
+    /* O1-O2: collide every fluid node of G_t. */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (s->own[idx(s, x, y)] != 0) continue;
+            double fl[9], out[9];
+            for (int i = 0; i < 9; ++i) fl[i] = s->f[pidx(s, i, x, y)];
+            orc_collide_node(fl, s->tau, s->gx, s->gy, out);
+            for (int i = 0; i < 9; ++i) s->ft[pidx(s, i, x, y)] = out[i];
+        }
+
+    /* O3: forces on every fluid-solid link of G_t, summed per solid in the
+     * order (y, x, i), with torque about the body's centre (Eqs. 4-7). */
+    double* h = hist_row(s, t);
+    memset(h, 0, sizeof(double) * (size_t)(s->nb + 1) * 6);
+    s->nlink = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (s->own[idx(s, x, y)] != 0) continue;
+            for (int i = 1; i < 9; ++i) {
+                int xb, yb, sid;
+                double vx, vy;
+                if (neighbour(s, x, y, i, +1, &xb, &yb)) {
+                    sid = 0;
+                    vx = s->wall_vx;
+                    vy = s->wall_vy;
+                } else {
+                    sid = s->own[idx(s, xb, yb)];
+                    if (sid == 0) continue;
+                    vx = s->body[sid - 1].vx;
+                    vy = s->body[sid - 1].vy;
+                }
+                double rho_w = s->rho0;
+                if (s->rho_w_local) {
+                    rho_w = 0.0;
+                    for (int j = 0; j < 9; ++j) rho_w += s->ft[pidx(s, j, x, y)];
+                }
+                double a = s->ft[pidx(s, i, x, y)];
+                /* population leaving the boundary node towards x_f: HWBB with
+                 * the moving-boundary term */
+                double b = a - 6.0 * W[i] * rho_w * (EX[i] * vx + EY[i] * vy);
+                double fc[2], fg[2];
+                orc_link_force(i, a, b, vx, vy, ORC_CME, fc);
+                orc_link_force(i, a, b, vx, vy, ORC_GME, fg);
+                double tc = 0.0, tg = 0.0;
+                if (sid > 0) {
+                    double X, Y;
+                    body_pos(&s->body[sid - 1], t, &X, &Y);
+                    /* intersection point S at the link midpoint */
+                    double rx = min_image(x + 0.5 * EX[i] - X, nx);
+                    double ry = s->walls_y ? (y + 0.5 * EY[i] - Y) : min_image(y + 0.5 * EY[i] - Y, ny);
+                    tc = rx * fc[1] - ry * fc[0];
+                    tg = rx * fg[1] - ry * fg[0];
+                }
+                double* hs = h + 6 * sid;
+                hs[0] += fc[0];
+                hs[1] += fc[1];
+                hs[2] += tc;
+                hs[3] += fg[0];
+                hs[4] += fg[1];
+                hs[5] += tg;
+                double rec[8] = {x, y, i, sid, fc[0], fc[1], fg[0], fg[1]};
+                push_link(s, rec);
+            }
+        }
+    s->hist_len = t + 1;
+
+    /* O4: advection (Eq. 3) with half-way bounce-back on G_t. */
+    memset(s->fn, 0, sizeof(double) * 9 * (size_t)nx * (size_t)ny);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (s->own[idx(s, x, y)] != 0) continue;
+            for (int i = 0; i < 9; ++i) {
+                int xs, ys, sid;
+                double vx, vy;
+                if (neighbour(s, x, y, i, -1, &xs, &ys)) {
+                    sid = 0;
+                    vx = s->wall_vx;
+                    vy = s->wall_vy;
+                } else {
+                    sid = s->own[idx(s, xs, ys)];
+                    if (sid == 0) {
+                        s->fn[pidx(s, i, x, y)] = s->ft[pidx(s, i, xs, ys)];
+                        continue;
+                    }
+                    vx = s->body[sid - 1].vx;
+                    vy = s->body[sid - 1].vy;
+                }
+                double rho_w = s->rho0;
+                if (s->rho_w_local) {
+                    rho_w = 0.0;
+                    for (int j = 0; j < 9; ++j) rho_w += s->ft[pidx(s, j, x, y)];
+                }
+                s->fn[pidx(s, i, x, y)] =
+                    s->ft[pidx(s, OPP[i], x, y)] + 6.0 * W[i] * rho_w * (EX[i] * vx + EY[i] * vy);
+            }
+        }
+
+    /* O5: move bodies, rasterise G_{t+1}. */
+    rasterise(s, t + 1, s->own_next);
+    for (long n = 0; n < (long)nx * ny; ++n)
+        s->oldfluid[n] = (s->own[n] == 0 && s->own_next[n] == 0);
+
+    /* O6-O7: drop covered nodes, refill newborn nodes from old-fluid
+     * neighbours' post-advection values. */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long n = idx(s, x, y);
+            if (s->own[n] == 0 && s->own_next[n] != 0) {
+                for (int i = 0; i < 9; ++i) s->fn[pidx(s, i, x, y)] = 0.0;
+            } else if (s->own[n] != 0 && s->own_next[n] == 0) {
+                const orc_body* b = &s->body[s->own[n] - 1];
+                double out[9];
+                orc_refill_node(nx, ny, s->walls_y, s->fn, s->oldfluid, x, y, s->refill, s->rho0,
+                                b->vx, b->vy, out);
+                for (int i = 0; i < 9; ++i) s->fn[pidx(s, i, x, y)] = out[i];
+            }
+        }
+
+    /* O8 */
+    double* tmp = s->f;
+    s->f = s->fn;
+    s->fn = tmp;
+    int* to = s->own;
+    s->own = s->own_next;
+    s->own_next = to;
+    s->t = t + 1;
+}
+
+void orc_step(orc_sim* s, long n) {
+    for (long k = 0; k < n; ++k) one_step(s);
+}
+
+void orc_fields(const orc_sim* s, double* rho, double* ux, double* uy, int* owner) {
+    for (int y = 0; y < s->ny; ++y)
+        for (int x = 0; x < s->nx; ++x) {
+            long n = idx(s, x, y);
+            double r = 0.0, jx = 0.0, jy = 0.0;
+            int o = s->own[n];
+            if (o == 0) {
+                for (int i = 0; i < 9; ++i) {
+                    double fi = s->f[pidx(s, i, x, y)];
+                    r += fi;
+                    jx += EX[i] * fi;
+                    jy += EY[i] * fi;
+                }
+            }
+            if (rho) rho[n] = r;
+            if (ux) ux[n] = (o == 0) ? (jx + 0.5 * r * s->gx) / r : 0.0;
+            if (uy) uy[n] = (o == 0) ? (jy + 0.5 * r * s->gy) / r : 0.0;
+            if (owner) owner[n] = o;
+        }
+}
+
+int orc_force(const orc_sim* s, long step, int solid, int scheme, double out[3]) {
+    if (step < 0 || step >= s->hist_len || solid < 0 || solid > s->nb) return -1;
+    const double* h = s->hist + ((size_t)step * (size_t)(s->nb + 1) + (size_t)solid) * 6;
+    int off = scheme == ORC_CME ? 0 : 3;
+    out[0] = h[off];
+    out[1] = h[off + 1];
+    out[2] = h[off + 2];
+    return 0;
+}
+
+long orc_links(const orc_sim* s, long max, double* rec) {
+    long n = s->nlink < max ? s->nlink : max;
+    if (rec && n > 0) memcpy(rec, s->link, sizeof(double) * 8 * (size_t)n);
+    return s->nlink;
+}
+
+void orc_get_f(const orc_sim* s, double* f) {
+    memcpy(f, s->f, sizeof(double) * 9 * (size_t)s->nx * (size_t)s->ny);
+}
+
+void orc_set_f(orc_sim* s, const double* f) {
+    memcpy(s->f, f, sizeof(double) * 9 * (size_t)s->nx * (size_t)s->ny);
+}
+
+void orc_init_fields(orc_sim* s, const double* rho, const double* ux, const double* uy) {
+    for (int y = 0; y < s->ny; ++y)
+        for (int x = 0; x < s->nx; ++x) {
+            long n = idx(s, x, y);
+            double feq[9] = {0};
+            if (s->own[n] == 0) orc_feq(rho[n], ux[n] - 0.5 * s->gx, uy[n] - 0.5 * s->gy, feq);
+            for (int i = 0; i < 9; ++i) s->f[pidx(s, i, x, y)] = feq[i];
+        }
+}
