@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the D2Q9 momentum-exchange hot path on one MI355X.
+
+Workload: the FP32 2048 x 1024 channel with 32 seeded cylinders (radii
+U(6, 12)), 16 fixed and 16 translating at |v| in [0.01, 0.05] with A1 refill
+of newborn nodes, tau = 0.6, CME and GME force and torque of every cylinder
+every step.  A "step" is one full time step of the hot path (forces, body
+motion, link rebuild, fused advection + bounce-back + collision, refill).
+
+Prints one JSON line: MLUPS over all nodes, the roofline of the dominant
+kernel (the fused lattice update, timed with HIP events around each launch on
+the library's stream), an additional HBM-bound measurement on a 4096 x 4096
+periodic lattice (its A/B working set is 4.7x the 256 MB Infinity Cache), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS and % HBM roofline; time-to-steady drag at 1e-4 (learned+mixed vs plain)"
+BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.h", "lbm_device.h", "lbm_capi.hip"):
+        with open(os.path.join(ROOT, "paper_1303_0625_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str, launches_bytes: float):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    source (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration);
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(case, dtype, steps, warmup, torch, pkg):
+    """Warm up, time `steps` steps (whole-step throughput), then time another
+    `steps` steps with HIP events around each lattice-update launch (kernel
+    roofline).  The two passes are separate so that the event records do not
+    perturb the throughput figure."""
+    lat = pkg.Lattice(case, dtype=dtype, history_steps=2 * steps + warmup + 1)
+    stream = lat.stream
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    lat.profile(True)
+    lat.step(steps)
+    upd_ms, n_upd = lat.profile_read()
+    lat.profile(False)
+    lat.check()
+    _, _, _, own = lat.fields("f32")
+    n_fluid = int((own == 0).sum().item())
+    return lat, total_ms, upd_ms, n_upd, n_fluid
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--dtype", default="f32", choices=list(BYTES))
+    ap.add_argument("--cpu-sample-steps", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hbm-case", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import lbm_cases as lc
+    import paper_1303_0625_amd as pkg
+
+    pkg.lbm.load_library()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+
+    case = lc.moving_cylinders()
+    nx, ny = case["nx"], case["ny"]
+    lat, total_ms, upd_ms, n_upd, n_fluid = run_gpu(case, args.dtype, args.steps, args.warmup,
+                                                    torch, pkg)
+    ms_per_step = total_ms / args.steps
+    mlups = nx * ny * args.steps / (total_ms * 1e-3) / 1e6
+    upd_avg_s = (upd_ms / max(n_upd, 1)) * 1e-3
+    alg_bytes = 18 * BYTES[args.dtype] * n_fluid
+    achieved = alg_bytes / upd_avg_s / 1e9
+    wl = "moving_cylinders_2048x1024"
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(wl, alg_bytes),
+                "kernel": "k_step", "update_us": round(upd_avg_s * 1e6, 3),
+                "alg_bytes_per_launch": alg_bytes}
+    del lat
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.no_hbm_case:
+        big = lc.periodic_cylinders()
+        big_steps = 200
+        lat2, tms2, ums2, n2, nf2 = run_gpu(big, args.dtype, big_steps, 20, torch, pkg)
+        avg2 = ums2 / max(n2, 1) * 1e-3
+        ab2 = 18 * BYTES[args.dtype] * nf2
+        extra["periodic_4096x4096"] = {
+            "mlups": round(big["nx"] * big["ny"] * big_steps / (tms2 * 1e-3) / 1e6, 1),
+            "ms_per_step": round(tms2 / big_steps, 4),
+            "update_us": round(avg2 * 1e6, 2),
+            "achieved_GBs": round(ab2 / avg2 / 1e9, 1),
+            "frac": round(ab2 / avg2 / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic("periodic_4096x4096", ab2),
+            "cylinders": len(big["bodies"]), "fixed_geometry": True}
+        del lat2
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        o = oracle.OracleSim(nx, ny, case["tau"], walls_y=True, refill=case["refill"],
+                             bodies=case["bodies"])
+        o.step(2)
+        t0 = time.perf_counter()
+        o.step(args.cpu_sample_steps)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(nx * ny * args.cpu_sample_steps / dt / 1e6, 3), "unit": "MLUPS",
+               "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_sample_steps} steps of the same 2048x1024 workload, FP64, "
+                         f"single thread ({dt:.1f} s)"}
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{wl}: 32 cylinders r~U(6,12) seed 2002, 16 translating "
+                               "|v|~U(0.01,0.05) with A1 refill, tau 0.6, CME+GME force/torque "
+                               "every step", "nx": nx, "ny": ny, "fluid_nodes": n_fluid},
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

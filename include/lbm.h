@@ -1,0 +1,197 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 lattice Boltzmann library with
+ * half-way bounce-back on moving solids, newborn-node refill and the
+ * conventional / Galilean-invariant momentum-exchange force.
+ *
+ * Method: Wen, Zhang, Tu, Wang, Fang, "Galilean Invariant Fluid-Solid
+ * Interfacial Dynamics in Lattice Boltzmann Simulations", arXiv:1303.0625.
+ *   - lattice Boltzmann equation, collision and advection: Sec. II, Eqs. 1-3;
+ *     single-relaxation-time (BGK) collision with the Eq. 8 equilibrium and the
+ *     D2Q9 velocity set of Sec. III.C;
+ *   - half-way bounce-back with the moving-boundary term: Sec. I and III.A;
+ *   - conventional momentum exchange (CME): Eq. 4; Galilean-invariant
+ *     momentum exchange (GME): Eq. 5; total force and torque: Eqs. 6-7;
+ *   - refill of newborn fluid nodes (A1 second-order extrapolation, A2 linear
+ *     extrapolation, A3 neighbour value, averaged over participating links):
+ *     Sec. IV.B.
+ *
+ * Units are lattice units (dx = dt = 1, c_s^2 = 1/3).  Node (x, y) sits at
+ * integer coordinates, 0 <= x < nx, 0 <= y < ny.  Fields are row-major
+ * [y][x] with x fastest.  x is periodic; y is periodic unless walls_y = 1,
+ * which places half-way walls at y = -1/2 and y = ny - 1/2 (solid id 0).
+ * Bodies have ids 1..n in the order given.  Forces are those exerted on the
+ * solid by the fluid; torque is about the body's prescribed centre (z out of
+ * plane).  The walls' torque is reported as 0.
+ *
+ * Ownership.  The caller owns every buffer passed in (workspace, field and
+ * output buffers) and the HIP stream; they must outlive the context.  The
+ * library allocates no device memory: all device state lives in the caller's
+ * workspace, whose size lbm_workspace_bytes() reports.  The grid and solid
+ * structs are copied at create.
+ *
+ * Streams and synchronisation.  Every call that launches work enqueues it on
+ * the context's stream and returns without waiting, except lbm_force,
+ * lbm_save and lbm_status_check, which synchronise that stream.
+ *
+ * Errors.  Every call returns an lbm_status and, on failure, records a message
+ * that lbm_last_error() returns.  Faults detected on the device (link-list
+ * overflow, non-finite or non-positive density found by lbm_fields) are
+ * latched in the workspace and reported as LBM_EGEOM / LBM_ENUMERIC by the
+ * next synchronising call.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; created by lbm_create, freed by lbm_destroy */
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,   /* invalid argument (NULL pointer, tau <= 1/2, |v| >= 0.3, ...) */
+    LBM_ESIZE = -2,    /* workspace or output buffer too small */
+    LBM_EDEVICE = -3,  /* a HIP runtime call failed */
+    LBM_ENUMERIC = -4, /* non-finite or non-positive density detected */
+    LBM_ESTATE = -5,   /* call not valid in the context's current state */
+    LBM_EGEOM = -6     /* bodies overlap, touch the walls, or a link list overflowed */
+} lbm_status;
+
+/* Storage type of the populations.  All storage types keep the deviation
+ * f_i - w_i rho0 from the rest equilibrium.  F64 computes in double, the
+ * others collide in float.  Force and torque are always accumulated in double. */
+typedef enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 } lbm_dtype;
+
+typedef enum { LBM_CME = 0, LBM_GME = 1 } lbm_scheme; /* Eq. 4 / Eq. 5 */
+
+typedef enum { LBM_REFILL_A1 = 0, LBM_REFILL_A2 = 1, LBM_REFILL_A3 = 2 } lbm_refill;
+
+typedef enum { LBM_DISC = 0, LBM_BOX = 1 } lbm_shape;
+
+typedef struct {
+    int32_t nx, ny;       /* lattice size, nx >= 4, ny >= 4 */
+    int32_t walls_y;      /* 1: half-way walls at y = -1/2 and ny - 1/2 */
+    int32_t dtype;        /* lbm_dtype of the stored populations */
+    int32_t refill;       /* lbm_refill used for newborn nodes */
+    int32_t rho_w_local;  /* reserved, must be 0: the wall term uses rho0 */
+    double rho0;          /* reference density; initial density */
+    double gx, gy;        /* body-force acceleration (force density rho*g) */
+    double u0x, u0y;      /* initial populations f_eq(rho0, u0) */
+    double wall_vx, wall_vy; /* velocity of the walls (solid id 0) */
+} lbm_grid;
+
+typedef struct {
+    int32_t shape;        /* lbm_shape */
+    int32_t moves;        /* 0: geometry fixed, v enters only bounce-back and GME;
+                             1: the geometry translates at v */
+    double cx, cy;        /* centre at t = 0 */
+    double a;             /* disc radius, or box half-width along x */
+    double b;             /* box half-height along y (ignored for a disc) */
+    double vx, vy;        /* prescribed velocity, |v| < 0.3 */
+} lbm_solid;
+/* A node (x, y) belongs to a body at step t when an integer image
+ * (x + k nx, y + l ny) of it lies inside the shape centred at
+ * (cx + t vx, cy + t vy) (moving) or (cx, cy) (fixed): a disc holds the points
+ * with dx*dx + dy*dy <= a*a, a box those with |dx| <= a and |dy| <= b, each
+ * product and sum rounded separately in double. */
+
+/* Version of this ABI (LBM_ABI_VERSION). */
+int32_t lbm_abi_version(void);
+
+/* Bytes of device workspace a context needs for this configuration, keeping
+ * a force history of history_steps steps (a ring; >= 1).  Returns LBM_EINVAL
+ * on invalid arguments. */
+lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_solid* solids, int32_t n_solids,
+                               int64_t history_steps, size_t* bytes);
+
+/* Validate the configuration, lay out the caller's device workspace
+ * (d_workspace, at least lbm_workspace_bytes() bytes, 256-byte aligned),
+ * rasterise the bodies, build the link lists and initialise the populations
+ * to f_eq(rho0, u0) (Eq. 8), collided once.  hip_stream is a hipStream_t
+ * (NULL: the default stream).  tau is the BGK relaxation time, > 1/2.
+ * On success *out receives the context. */
+lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids, int32_t n_solids,
+                      int64_t history_steps, void* d_workspace, size_t bytes, void* hip_stream,
+                      lbm_ctx** out);
+
+/* Enqueue n time steps.  Each step evaluates the CME and GME force and torque
+ * of every solid from the current post-collision populations (Eqs. 4-7),
+ * streams with half-way bounce-back (Eq. 3), moves the translating bodies,
+ * refills newborn nodes and collides (Eq. 2).  Asynchronous.  Returns
+ * LBM_EGEOM if a translating body would come within 2 nodes of another body
+ * or a wall during these steps. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Number of completed time steps. */
+int64_t lbm_time(const lbm_ctx* ctx);
+
+/* Force and torque {Fx, Fy, Tz} on solid solid_id (0 = walls) by scheme
+ * (lbm_scheme) at the most recent completed step, into host memory out[3].
+ * Synchronises the stream.  LBM_ESTATE before the first step. */
+lbm_status lbm_force(lbm_ctx* ctx, int32_t solid_id, int32_t scheme, double out[3]);
+
+/* Copy the force records of steps [first, first + count) into device memory
+ * d_out as double [count][n_solids + 1][6] = {CME Fx, Fy, Tz, GME Fx, Fy, Tz}.
+ * The steps must still be held by the history ring.  Asynchronous. */
+lbm_status lbm_force_history(lbm_ctx* ctx, int64_t first, int64_t count, double* d_out);
+
+/* Density and Guo velocity of the current state into device buffers of
+ * nx*ny elements of type out_dtype (LBM_F64 or LBM_F32); 0 at solid nodes.
+ * d_owner (optional) receives the owner map as uint8 (0 = fluid, else body
+ * id).  Any output pointer may be NULL.  Latches LBM_ENUMERIC if a fluid node
+ * has a non-finite or non-positive density.  Asynchronous. */
+lbm_status lbm_fields(lbm_ctx* ctx, void* d_rho, void* d_ux, void* d_uy, int32_t out_dtype,
+                      uint8_t* d_owner);
+
+/* Replace the state of every fluid node by f_eq(rho, u - g/2), collided once,
+ * so that its Guo velocity is u (warm start).  Inputs are device buffers of
+ * nx*ny elements of type in_dtype (LBM_F64 or LBM_F32).  Asynchronous. */
+lbm_status lbm_init_fields(lbm_ctx* ctx, const void* d_rho, const void* d_ux, const void* d_uy,
+                           int32_t in_dtype);
+
+/* Post-collision populations f~_i(x, t) of the current state as absolute
+ * values in double, [9][ny][nx] device memory; 0 at solid nodes.  Asynchronous. */
+lbm_status lbm_populations(lbm_ctx* ctx, double* d_out);
+
+/* Per-link CME/GME forces that the next step will evaluate from the current
+ * state, in summation order: d_out double [max][8] =
+ * {x, y, i, solid, CME Fx, CME Fy, GME Fx, GME Fy}; *n receives the number
+ * of links (host).  Synchronises the stream.  LBM_ESIZE if max is too small. */
+lbm_status lbm_link_forces(lbm_ctx* ctx, double* d_out, int64_t max, int64_t* n);
+
+/* Checkpoint: bytes needed, save into / load from a device buffer.  The
+ * record holds the populations, owner maps, link lists and the step counter;
+ * the force history is not saved.  lbm_save synchronises. */
+lbm_status lbm_checkpoint_bytes(const lbm_ctx* ctx, size_t* bytes);
+lbm_status lbm_save(lbm_ctx* ctx, void* d_dst, size_t bytes);
+lbm_status lbm_load(lbm_ctx* ctx, const void* d_src, size_t bytes);
+
+/* Kernel timing (instrumentation).  While enabled, every lattice-update
+ * launch (the fused advection + bounce-back + collision kernel, the one that
+ * moves 18 populations per fluid node) is bracketed by a pair of HIP events
+ * on the context's stream; lbm_profile_read synchronises and returns the
+ * summed elapsed milliseconds and the number of launches since enabling.
+ * Enabling resets the sums.  At most 65536 launches are recorded. */
+lbm_status lbm_profile(lbm_ctx* ctx, int32_t enable);
+lbm_status lbm_profile_read(lbm_ctx* ctx, double* update_ms, int64_t* launches);
+
+/* Synchronise the stream and report any latched device fault. */
+lbm_status lbm_status_check(lbm_ctx* ctx);
+
+/* Release the context (not the caller's buffers). NULL is ignored. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Message of the last failure on this context, or of the last failed
+ * lbm_create / lbm_workspace_bytes in this thread when ctx is NULL. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

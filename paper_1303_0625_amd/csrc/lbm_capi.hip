@@ -1,0 +1,827 @@
+// lbm_capi.hip -- host side of the C ABI declared in include/lbm.h: argument
+// validation, workspace layout inside the caller's device buffer, and the
+// per-step launch sequence on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void set_err(char* buf, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+size_t dtype_size(int dt) {
+    switch (dt) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16: return 2;
+        case LBM_BF16: return 2;
+        default: return 0;
+    }
+}
+
+// Workspace layout (byte offsets inside the caller's buffer).
+struct Layout {
+    int pitch, opitch;
+    int64_t plane;
+    size_t f[2], own[2], links, seg_off, seg_cap, seg_cnt, rec_off, sol, vtab, movers, all, hist,
+        tctr, err, total;
+    int64_t link_total;
+    int n_movers;
+};
+
+// Conservative link capacity of one body: every fluid node adjacent to a
+// compact body lies in the ring of its bounding range, each with at most 8
+// links.
+int body_link_cap(const lbm_solid& s, int nx, int ny) {
+    double hx = s.a, hy = s.shape == LBM_DISC ? s.a : s.b;
+    long w = std::min<long>(2 * (long)std::ceil(hx) + 5, nx);
+    long h = std::min<long>(2 * (long)std::ceil(hy) + 5, ny);
+    long ring = 2 * (w + h) + 8;
+    return (int)std::min<long>(8 * ring, 8L * w * h);
+}
+
+bool make_layout(const lbm_grid& g, const lbm_solid* solids, int n, int64_t hist_steps, Layout& L) {
+    const size_t es = dtype_size(g.dtype);
+    L.pitch = (g.nx + 63) / 64 * 64;
+    L.opitch = (g.nx + 63) / 64 * 64;
+    L.plane = (int64_t)g.ny * L.pitch;
+    size_t off = 0;
+    for (int k = 0; k < 2; ++k) {
+        L.f[k] = off;
+        off = align256(off + 9 * (size_t)L.plane * es);
+    }
+    L.n_movers = 0;
+    for (int k = 0; k < n; ++k) L.n_movers += solids[k].moves ? 1 : 0;
+    for (int k = 0; k < 2; ++k) {
+        L.own[k] = off;
+        off = align256(off + (size_t)g.ny * L.opitch);
+    }
+    int64_t tot = g.walls_y ? 6LL * g.nx : 0;
+    for (int k = 0; k < n; ++k) tot += body_link_cap(solids[k], g.nx, g.ny);
+    L.link_total = tot;
+    L.links = off;
+    off = align256(off + 4 * (size_t)std::max<int64_t>(tot, 1));
+    const size_t ns = (size_t)n + 1;
+    L.seg_off = off; off = align256(off + 4 * ns);
+    L.seg_cap = off; off = align256(off + 4 * ns);
+    L.seg_cnt = off; off = align256(off + 4 * ns);
+    L.rec_off = off; off = align256(off + 4 * ns);
+    L.sol = off; off = align256(off + sizeof(SolidDev) * ns);
+    L.vtab = off; off = align256(off + 16 * ns);
+    L.movers = off; off = align256(off + 4 * (size_t)std::max(L.n_movers, 1));
+    L.all = off; off = align256(off + 4 * ns);
+    L.hist = off; off = align256(off + 48 * ns * (size_t)hist_steps);
+    L.tctr = off; off = align256(off + 16);
+    L.err = off; off = align256(off + 4);
+    L.total = off;
+    return true;
+}
+
+// Distance between the surfaces of two bodies, with bounding boxes for any box
+// shape (conservative) and the minimum image on periodic axes.
+double body_gap(const lbm_solid& p, double px, double py, const lbm_solid& q, double qx,
+                double qy, const lbm_grid& g) {
+    double dx = std::fabs(px - qx);
+    dx = std::fmod(dx, (double)g.nx);
+    dx = std::min(dx, g.nx - dx);
+    double dy = std::fabs(py - qy);
+    if (!g.walls_y) {
+        dy = std::fmod(dy, (double)g.ny);
+        dy = std::min(dy, g.ny - dy);
+    }
+    if (p.shape == LBM_DISC && q.shape == LBM_DISC) return std::hypot(dx, dy) - p.a - q.a;
+    double phx = p.a, phy = p.shape == LBM_DISC ? p.a : p.b;
+    double qhx = q.a, qhy = q.shape == LBM_DISC ? q.a : q.b;
+    return std::max(dx - phx - qhx, dy - phy - qhy);
+}
+
+const char* validate(const lbm_grid* g, double tau, const lbm_solid* s, int n, char* buf) {
+    if (!g) return "grid is NULL";
+    if (g->nx < 4 || g->ny < 4) return "nx and ny must be >= 4";
+    if ((int64_t)g->nx * g->ny >= (1LL << 28)) return "nx*ny must be < 2^28";
+    if (!(tau > 0.5)) return "tau must be > 1/2";
+    if (dtype_size(g->dtype) == 0) return "unknown dtype";
+    if (g->refill < 0 || g->refill > 2) return "unknown refill scheme";
+    if (g->rho_w_local != 0) return "rho_w_local is not supported (must be 0)";
+    if (!(g->rho0 > 0.0) || !std::isfinite(g->rho0)) return "rho0 must be > 0";
+    if (!std::isfinite(g->gx) || !std::isfinite(g->gy)) return "body force must be finite";
+    if (std::hypot(g->u0x, g->u0y) >= 0.3) return "|u0| must be < 0.3";
+    if (std::hypot(g->wall_vx, g->wall_vy) >= 0.3) return "|wall velocity| must be < 0.3";
+    if (n < 0 || n > kMaxSolids) return "n_solids must be in [0, 254]";
+    if (n > 0 && !s) return "solids is NULL";
+    for (int k = 0; k < n; ++k) {
+        const lbm_solid& b = s[k];
+        if (b.shape != LBM_DISC && b.shape != LBM_BOX) return "unknown solid shape";
+        if (!std::isfinite(b.cx) || !std::isfinite(b.cy)) return "solid centre must be finite";
+        if (b.shape == LBM_DISC && !(b.a > 0.0)) return "disc radius must be > 0";
+        if (b.shape == LBM_BOX && !(b.a >= 0.0 && b.b >= 0.0)) return "box half-extents must be >= 0";
+        if (std::hypot(b.vx, b.vy) >= 0.3) return "|solid velocity| must be < 0.3";
+        double hx = b.a, hy = b.shape == LBM_DISC ? b.a : b.b;
+        bool full_x = b.shape == LBM_BOX && 2 * hx + 1 >= g->nx;
+        if (!full_x && 2 * hx + 6 >= g->nx) return "solid too wide for the lattice";
+        if (b.moves && full_x) return "a translating solid must not span the lattice";
+        if (g->walls_y) {
+            if (b.cy - hy < 2.0 || b.cy + hy > g->ny - 3.0)
+                return "solids must keep a gap of 2 nodes to the walls";
+        } else if (2 * hy + 6 >= g->ny && !(b.shape == LBM_BOX && 2 * hy + 1 >= g->ny && !b.moves)) {
+            return "solid too tall for the lattice";
+        }
+    }
+    for (int p = 0; p < n; ++p)
+        for (int q = p + 1; q < n; ++q)
+            if (body_gap(s[p], s[p].cx, s[p].cy, s[q], s[q].cx, s[q].cy, *g) < 2.0) {
+                snprintf(buf, 512, "solids %d and %d are closer than 2 nodes", p + 1, q + 1);
+                return buf;
+            }
+    return nullptr;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_grid g;
+    double tau;
+    std::vector<lbm_solid> solids;
+    int n;
+    int64_t hist_cap;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    Layout L;
+    int64_t t;
+    std::vector<int> seg_off, seg_cap;
+    int64_t link_cap_total;
+    char err[512];
+    // instrumentation: event pairs around the lattice-update kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    double prof_ms = 0.0;
+    int64_t prof_n = 0;
+};
+
+namespace {
+
+template <typename T>
+T* wsp(lbm_ctx* c, size_t off) {
+    return reinterpret_cast<T*>(c->ws + off);
+}
+
+StepArgs step_args(const lbm_ctx* c) {
+    StepArgs a;
+    a.nx = c->g.nx;
+    a.ny = c->g.ny;
+    a.pitch = c->L.pitch;
+    a.opitch = c->L.opitch;
+    a.plane = c->L.plane;
+    a.walls = c->g.walls_y;
+    a.rho0 = c->g.rho0;
+    return a;
+}
+
+template <typename C>
+CollideParams<C> collide_params(const lbm_ctx* c) {
+    CollideParams<C> p;
+    p.rho0 = (C)c->g.rho0;
+    p.omega = (C)(1.0 / c->tau);
+    p.gx = (C)c->g.gx;
+    p.gy = (C)c->g.gy;
+    p.pref = (C)(1.0 - 1.0 / (2.0 * c->tau));
+    return p;
+}
+
+ForceArgs force_args(const lbm_ctx* c) {
+    ForceArgs a;
+    a.nx = c->g.nx;
+    a.ny = c->g.ny;
+    a.pitch = c->L.pitch;
+    a.walls = c->g.walls_y;
+    a.plane = c->L.plane;
+    a.rho0 = c->g.rho0;
+    a.hist_cap = c->hist_cap;
+    a.nsol = c->n + 1;
+    return a;
+}
+
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* what) {
+    set_err(c ? c->err : g_err, "%s: %s", what, hipGetErrorString(e));
+    return LBM_EDEVICE;
+}
+
+#define HIPCHK(ctx, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+int64_t node_blocks(const lbm_ctx* c) {
+    return ((int64_t)c->g.ny * c->L.pitch + kBlock - 1) / kBlock;
+}
+
+// The two owner maps; with no translating body both views are the same map.
+uint8_t* own_ptr(lbm_ctx* c, int k) {
+    if (c->L.n_movers == 0) k = 0;
+    return wsp<uint8_t>(c, c->L.own[k]);
+}
+
+// Enqueue one time step at parity p = t & 1 for storage type T.
+template <typename T>
+lbm_status enqueue_step(lbm_ctx* c) {
+    using C = typename Sto<T>::C;
+    const int p = (int)(c->t & 1);
+    const T* fin = wsp<T>(c, c->L.f[p]);
+    T* fout = wsp<T>(c, c->L.f[p ^ 1]);
+    const uint8_t* own_t = own_ptr(c, p);
+    uint8_t* own_n = own_ptr(c, p ^ 1);
+    int64_t* tctr = wsp<int64_t>(c, c->L.tctr);
+    int* errf = wsp<int>(c, c->L.err);
+    const SolidDev* sol = wsp<SolidDev>(c, c->L.sol);
+    k_force<T><<<c->n + 1, kBlock, 0, c->stream>>>(fin, wsp<uint32_t>(c, c->L.links),
+                                                   wsp<int>(c, c->L.seg_cnt),
+                                                   wsp<int>(c, c->L.seg_off), sol,
+                                                   wsp<double>(c, c->L.hist), tctr, p,
+                                                   force_args(c));
+    LinkArgs la{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y};
+    if (c->L.n_movers > 0) {
+        k_move<<<c->L.n_movers, kBlock, 0, c->stream>>>(
+            own_n, wsp<uint32_t>(c, c->L.links), wsp<int>(c, c->L.seg_cnt),
+            wsp<int>(c, c->L.seg_off), wsp<int>(c, c->L.seg_cap), sol, wsp<int>(c, c->L.movers),
+            tctr, p, la, errf);
+    }
+    StepArgs sa = step_args(c);
+    CollideParams<C> cp = collide_params<C>(c);
+    const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
+    if (timed) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    k_step<T><<<(unsigned)node_blocks(c), kBlock, 0, c->stream>>>(fin, fout, own_t, own_n,
+                                                                wsp<double>(c, c->L.vtab), sa, cp);
+    if (timed) {
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+    }
+    if (c->L.n_movers > 0) {
+        k_refill<T><<<c->L.n_movers, kBlock, 0, c->stream>>>(
+            fin, fout, own_t, own_n, wsp<double>(c, c->L.vtab), sol, wsp<int>(c, c->L.movers),
+            tctr, p, sa, cp, c->g.refill);
+    }
+    c->t += 1;
+    return LBM_OK;
+}
+
+lbm_status dispatch_step(lbm_ctx* c) {
+    switch (c->g.dtype) {
+        case LBM_F64: return enqueue_step<double>(c);
+        case LBM_F32: return enqueue_step<float>(c);
+        case LBM_F16: return enqueue_step<_Float16>(c);
+        default: return enqueue_step<bf16_t>(c);
+    }
+}
+
+template <typename T, typename FT>
+void enqueue_init(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
+    using C = typename Sto<T>::C;
+    const int p = (int)(c->t & 1);
+    k_init<T, FT><<<(unsigned)node_blocks(c), kBlock, 0, c->stream>>>(
+        wsp<T>(c, c->L.f[p]), own_ptr(c, p), step_args(c), collide_params<C>(c), c->g.u0x,
+        c->g.u0y, rho, ux, uy);
+}
+
+template <typename FT>
+void dispatch_init(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
+    switch (c->g.dtype) {
+        case LBM_F64: enqueue_init<double, FT>(c, rho, ux, uy); break;
+        case LBM_F32: enqueue_init<float, FT>(c, rho, ux, uy); break;
+        case LBM_F16: enqueue_init<_Float16, FT>(c, rho, ux, uy); break;
+        default: enqueue_init<bf16_t, FT>(c, rho, ux, uy); break;
+    }
+}
+
+// Host-side check that translating bodies keep their gaps over steps
+// [t0, t1]: sampled so that relative displacement between samples is <= 0.1.
+const char* check_paths(const lbm_ctx* c, int64_t t0, int64_t t1, char* buf) {
+    const auto& S = c->solids;
+    const lbm_grid& g = c->g;
+    for (int p = 0; p < c->n; ++p) {
+        if (!S[p].moves) continue;
+        double hy = S[p].shape == LBM_DISC ? S[p].a : S[p].b;
+        if (g.walls_y && S[p].vy != 0.0) {
+            for (int64_t t : {t0, t1}) {
+                double y = S[p].cy + (double)t * S[p].vy;
+                if (y - hy < 2.0 || y + hy > g.ny - 3.0) {
+                    snprintf(buf, 512, "solid %d reaches the walls before step %lld", p + 1, (long long)t1);
+                    return buf;
+                }
+            }
+        }
+        for (int q = 0; q < c->n; ++q) {
+            if (q == p || (S[q].moves && q < p)) continue;
+            double rvx = S[p].vx - (S[q].moves ? S[q].vx : 0.0);
+            double rvy = S[p].vy - (S[q].moves ? S[q].vy : 0.0);
+            double rv = std::hypot(rvx, rvy);
+            int64_t dt = rv > 0 ? std::max<int64_t>(1, (int64_t)(0.1 / rv)) : (t1 - t0 + 1);
+            for (int64_t t = t0;; t += dt) {
+                if (t > t1) t = t1;
+                double px = S[p].cx + (double)t * S[p].vx, py = S[p].cy + (double)t * S[p].vy;
+                double qx = S[q].moves ? S[q].cx + (double)t * S[q].vx : S[q].cx;
+                double qy = S[q].moves ? S[q].cy + (double)t * S[q].vy : S[q].cy;
+                if (body_gap(S[p], px, py, S[q], qx, qy, g) < 2.0) {
+                    snprintf(buf, 512, "solids %d and %d come closer than 2 nodes at step %lld", p + 1,
+                             q + 1, (long long)t);
+                    return buf;
+                }
+                if (t == t1) break;
+            }
+        }
+    }
+    return nullptr;
+}
+
+lbm_status read_err(lbm_ctx* c) {
+    int e = 0;
+    HIPCHK(c, hipMemcpyAsync(&e, wsp<int>(c, c->L.err), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (e & 1) {
+        set_err(c->err, "a link list overflowed its capacity");
+        return LBM_EGEOM;
+    }
+    if (e & 2) {
+        set_err(c->err, "non-finite or non-positive density detected");
+        return LBM_ENUMERIC;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+lbm_status lbm_workspace_bytes(const lbm_grid* grid, const lbm_solid* solids, int32_t n_solids,
+                               int64_t history_steps, size_t* bytes) {
+    char buf[512];
+    if (!bytes) {
+        set_err(g_err, "bytes is NULL");
+        return LBM_EINVAL;
+    }
+    const char* why = validate(grid, 0.75, solids, n_solids, buf);
+    if (why) {
+        set_err(g_err, "%s", why);
+        return strstr(why, "closer") || strstr(why, "gap") ? LBM_EGEOM : LBM_EINVAL;
+    }
+    if (history_steps < 1) {
+        set_err(g_err, "history_steps must be >= 1");
+        return LBM_EINVAL;
+    }
+    Layout L;
+    make_layout(*grid, solids, n_solids, history_steps, L);
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids, int32_t n_solids,
+                      int64_t history_steps, void* d_workspace, size_t bytes, void* hip_stream,
+                      lbm_ctx** out) {
+    char buf[512];
+    if (!out) {
+        set_err(g_err, "out is NULL");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    const char* why = validate(grid, tau, solids, n_solids, buf);
+    if (why) {
+        set_err(g_err, "%s", why);
+        return strstr(why, "closer") || strstr(why, "gap") ? LBM_EGEOM : LBM_EINVAL;
+    }
+    if (history_steps < 1) {
+        set_err(g_err, "history_steps must be >= 1");
+        return LBM_EINVAL;
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace & 255) != 0) {
+        set_err(g_err, "workspace must be a non-NULL 256-byte aligned device pointer");
+        return LBM_EINVAL;
+    }
+    Layout L;
+    make_layout(*grid, solids, n_solids, history_steps, L);
+    if (bytes < L.total) {
+        set_err(g_err, "workspace too small: %zu < %zu bytes", bytes, L.total);
+        return LBM_ESIZE;
+    }
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) {
+        set_err(g_err, "out of host memory");
+        return LBM_EINVAL;
+    }
+    c->g = *grid;
+    c->tau = tau;
+    c->solids.assign(solids, solids + n_solids);
+    c->n = n_solids;
+    c->hist_cap = history_steps;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (char*)d_workspace;
+    c->ws_bytes = bytes;
+    c->L = L;
+    c->t = 0;
+    c->err[0] = 0;
+
+    // host tables
+    const int ns = n_solids + 1;
+    std::vector<SolidDev> sol(ns);
+    std::vector<double> vtab(2 * ns);
+    sol[0] = SolidDev{0, 0, 0, 0, grid->wall_vx, grid->wall_vy, 0, 0};
+    vtab[0] = grid->wall_vx;
+    vtab[1] = grid->wall_vy;
+    std::vector<int> movers, all;
+    for (int k = 0; k < n_solids; ++k) {
+        const lbm_solid& b = solids[k];
+        sol[k + 1] = SolidDev{b.cx, b.cy, b.a, b.b, b.vx, b.vy, b.shape, b.moves ? 1 : 0};
+        vtab[2 * (k + 1)] = b.vx;
+        vtab[2 * (k + 1) + 1] = b.vy;
+        all.push_back(k + 1);
+        if (b.moves) movers.push_back(k + 1);
+    }
+    c->seg_off.resize(ns);
+    c->seg_cap.resize(ns);
+    std::vector<int> seg_cnt(ns, 0), rec_off(ns, 0);
+    int off = 0;
+    c->seg_cap[0] = grid->walls_y ? 6 * grid->nx : 0;
+    c->seg_off[0] = 0;
+    seg_cnt[0] = c->seg_cap[0];
+    off = c->seg_cap[0];
+    for (int k = 0; k < n_solids; ++k) {
+        c->seg_off[k + 1] = off;
+        c->seg_cap[k + 1] = body_link_cap(solids[k], grid->nx, grid->ny);
+        off += c->seg_cap[k + 1];
+    }
+    c->link_cap_total = off;
+
+    hipStream_t st = c->stream;
+    auto up = [&](size_t dst, const void* src, size_t n) {
+        return hipMemcpyAsync(c->ws + dst, src, n, hipMemcpyHostToDevice, st);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(L.sol, sol.data(), sizeof(SolidDev) * ns);
+    if (e == hipSuccess) e = up(L.vtab, vtab.data(), sizeof(double) * 2 * ns);
+    if (e == hipSuccess) e = up(L.seg_off, c->seg_off.data(), sizeof(int) * ns);
+    if (e == hipSuccess) e = up(L.seg_cap, c->seg_cap.data(), sizeof(int) * ns);
+    if (e == hipSuccess) e = up(L.seg_cnt, seg_cnt.data(), sizeof(int) * ns);
+    if (e == hipSuccess && !movers.empty()) e = up(L.movers, movers.data(), sizeof(int) * movers.size());
+    if (e == hipSuccess && !all.empty()) e = up(L.all, all.data(), sizeof(int) * all.size());
+    // the uploads read pageable host vectors: finish them before they go away
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_err(g_err, "upload failed: %s", hipGetErrorString(e));
+        delete c;
+        return LBM_EDEVICE;
+    }
+
+    const int64_t own_bytes = (int64_t)grid->ny * L.opitch;
+    k_set_counters<<<1, 1, 0, st>>>(wsp<int64_t>(c, L.tctr), 0, wsp<int>(c, L.err));
+    k_fill_u8<<<(unsigned)((own_bytes + 255) / 256), 256, 0, st>>>(wsp<uint8_t>(c, L.own[0]), own_bytes, 0);
+    GeomArgs ga{grid->nx, grid->ny, L.opitch, grid->walls_y};
+    if (n_solids > 0)
+        k_raster<<<n_solids, kBlock, 0, st>>>(wsp<uint8_t>(c, L.own[0]), wsp<SolidDev>(c, L.sol),
+                                              wsp<int>(c, L.all), 0, ga);
+    if (!movers.empty())
+        e = hipMemcpyAsync(c->ws + L.own[1], c->ws + L.own[0], (size_t)own_bytes,
+                           hipMemcpyDeviceToDevice, st);
+    if (grid->walls_y)
+        k_wall_links<<<(2 * grid->nx + 255) / 256, 256, 0, st>>>(wsp<uint32_t>(c, L.links), grid->nx,
+                                                                 grid->ny);
+    LinkArgs la{grid->nx, grid->ny, L.opitch, grid->walls_y};
+    if (n_solids > 0)
+        k_links<<<n_solids, kBlock, 0, st>>>(wsp<uint8_t>(c, L.own[0]), wsp<uint32_t>(c, L.links),
+                                             wsp<int>(c, L.seg_cnt), wsp<int>(c, L.seg_off),
+                                             wsp<int>(c, L.seg_cap), wsp<SolidDev>(c, L.sol),
+                                             wsp<int>(c, L.all), 0, la, wsp<int>(c, L.err));
+    dispatch_init<double>(c, nullptr, nullptr, nullptr);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_err(g_err, "initialisation failed: %s", hipGetErrorString(e));
+        delete c;
+        return LBM_EDEVICE;
+    }
+    lbm_status rs = read_err(c);
+    if (rs != LBM_OK) {
+        set_err(g_err, "%s", c->err);
+        delete c;
+        return rs;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c) return LBM_EINVAL;
+    if (n < 0) {
+        set_err(c->err, "n must be >= 0");
+        return LBM_EINVAL;
+    }
+    if (n == 0) return LBM_OK;
+    if (c->L.n_movers > 0) {
+        char buf[512];
+        const char* why = check_paths(c, c->t, c->t + n + 1, buf);
+        if (why) {
+            set_err(c->err, "%s", why);
+            return LBM_EGEOM;
+        }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        lbm_status s = dispatch_step(c);
+        if (s != LBM_OK) return s;
+    }
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm_force(lbm_ctx* c, int32_t solid_id, int32_t scheme, double out[3]) {
+    if (!c || !out) return LBM_EINVAL;
+    if (solid_id < 0 || solid_id > c->n) {
+        set_err(c->err, "solid_id %d out of range [0, %d]", solid_id, c->n);
+        return LBM_EINVAL;
+    }
+    if (scheme != LBM_CME && scheme != LBM_GME) {
+        set_err(c->err, "unknown scheme %d", scheme);
+        return LBM_EINVAL;
+    }
+    if (c->t == 0) {
+        set_err(c->err, "no step has been taken yet");
+        return LBM_ESTATE;
+    }
+    double rec[6];
+    const int64_t slot = (c->t - 1) % c->hist_cap;
+    const double* src = wsp<double>(c, c->L.hist) + (slot * (c->n + 1) + solid_id) * 6;
+    HIPCHK(c, hipMemcpyAsync(rec, src, sizeof(rec), hipMemcpyDeviceToHost, c->stream));
+    lbm_status rs = read_err(c);  // synchronises the stream
+    if (rs != LBM_OK) return rs;
+    const int o = scheme == LBM_CME ? 0 : 3;
+    out[0] = rec[o];
+    out[1] = rec[o + 1];
+    out[2] = rec[o + 2];
+    return LBM_OK;
+}
+
+lbm_status lbm_force_history(lbm_ctx* c, int64_t first, int64_t count, double* d_out) {
+    if (!c || !d_out) return LBM_EINVAL;
+    if (first < 0 || count < 0 || first + count > c->t || first < c->t - c->hist_cap) {
+        set_err(c->err, "steps [%lld, %lld) are not held by the history ring (t = %lld, capacity %lld)",
+                (long long)first, (long long)(first + count), (long long)c->t, (long long)c->hist_cap);
+        return LBM_EINVAL;
+    }
+    const size_t row = (size_t)(c->n + 1) * 6 * sizeof(double);
+    const char* base = c->ws + c->L.hist;
+    int64_t k = 0;
+    while (k < count) {
+        int64_t slot = (first + k) % c->hist_cap;
+        int64_t run = std::min<int64_t>(count - k, c->hist_cap - slot);
+        HIPCHK(c, hipMemcpyAsync((char*)d_out + k * row, base + slot * row, run * row,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        k += run;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_fields(lbm_ctx* c, void* d_rho, void* d_ux, void* d_uy, int32_t out_dtype,
+                      uint8_t* d_owner) {
+    if (!c) return LBM_EINVAL;
+    if (out_dtype != LBM_F64 && out_dtype != LBM_F32) {
+        set_err(c->err, "fields are written as LBM_F64 or LBM_F32");
+        return LBM_EINVAL;
+    }
+    const int p = (int)(c->t & 1);
+    StepArgs sa = step_args(c);
+    const uint8_t* own = own_ptr(c, p);
+    int* errf = wsp<int>(c, c->L.err);
+    const unsigned nb = (unsigned)node_blocks(c);
+#define FIELDS_T(T)                                                                              \
+    if (out_dtype == LBM_F64)                                                                    \
+        k_fields<T, double><<<nb, kBlock, 0, c->stream>>>(wsp<T>(c, c->L.f[p]), own, sa, c->g.gx,  \
+                                                          c->g.gy, (double*)d_rho, (double*)d_ux, \
+                                                          (double*)d_uy, d_owner, errf);          \
+    else                                                                                         \
+        k_fields<T, float><<<nb, kBlock, 0, c->stream>>>(wsp<T>(c, c->L.f[p]), own, sa, c->g.gx,   \
+                                                         c->g.gy, (float*)d_rho, (float*)d_ux,    \
+                                                         (float*)d_uy, d_owner, errf);
+    switch (c->g.dtype) {
+        case LBM_F64: FIELDS_T(double) break;
+        case LBM_F32: FIELDS_T(float) break;
+        case LBM_F16: FIELDS_T(_Float16) break;
+        default: FIELDS_T(bf16_t) break;
+    }
+#undef FIELDS_T
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const void* d_rho, const void* d_ux, const void* d_uy,
+                           int32_t in_dtype) {
+    if (!c) return LBM_EINVAL;
+    if (!d_rho || !d_ux || !d_uy) {
+        set_err(c->err, "field pointers must not be NULL");
+        return LBM_EINVAL;
+    }
+    if (in_dtype == LBM_F64)
+        dispatch_init<double>(c, (const double*)d_rho, (const double*)d_ux, (const double*)d_uy);
+    else if (in_dtype == LBM_F32)
+        dispatch_init<float>(c, (const float*)d_rho, (const float*)d_ux, (const float*)d_uy);
+    else {
+        set_err(c->err, "fields are read as LBM_F64 or LBM_F32");
+        return LBM_EINVAL;
+    }
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_populations(lbm_ctx* c, double* d_out) {
+    if (!c || !d_out) return LBM_EINVAL;
+    const int p = (int)(c->t & 1);
+    StepArgs sa = step_args(c);
+    const unsigned nb = (unsigned)node_blocks(c);
+    const uint8_t* own = own_ptr(c, p);
+    switch (c->g.dtype) {
+        case LBM_F64: k_populations<double><<<nb, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.f[p]), own, sa, d_out); break;
+        case LBM_F32: k_populations<float><<<nb, kBlock, 0, c->stream>>>(wsp<float>(c, c->L.f[p]), own, sa, d_out); break;
+        case LBM_F16: k_populations<_Float16><<<nb, kBlock, 0, c->stream>>>(wsp<_Float16>(c, c->L.f[p]), own, sa, d_out); break;
+        default: k_populations<bf16_t><<<nb, kBlock, 0, c->stream>>>(wsp<bf16_t>(c, c->L.f[p]), own, sa, d_out); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_link_forces(lbm_ctx* c, double* d_out, int64_t max, int64_t* n) {
+    if (!c || !n) return LBM_EINVAL;
+    const int ns = c->n + 1;
+    std::vector<int> cnt(ns), roff(ns);
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), wsp<int>(c, c->L.seg_cnt), sizeof(int) * ns,
+                             hipMemcpyDeviceToHost, c->stream));
+    lbm_status rs = read_err(c);
+    if (rs != LBM_OK) return rs;
+    int64_t tot = 0;
+    for (int s = 0; s < ns; ++s) {
+        roff[s] = (int)tot;
+        tot += cnt[s];
+    }
+    *n = tot;
+    if (tot > max || (!d_out && tot > 0)) {
+        set_err(c->err, "output holds %lld records, %lld needed", (long long)max, (long long)tot);
+        return LBM_ESIZE;
+    }
+    if (tot == 0) return LBM_OK;
+    HIPCHK(c, hipMemcpyAsync(wsp<int>(c, c->L.rec_off), roff.data(), sizeof(int) * ns,
+                             hipMemcpyHostToDevice, c->stream));
+    const int p = (int)(c->t & 1);
+    ForceArgs fa = force_args(c);
+    const uint32_t* links = wsp<uint32_t>(c, c->L.links);
+    const int* sc = wsp<int>(c, c->L.seg_cnt);
+    const int* so = wsp<int>(c, c->L.seg_off);
+    const int* ro = wsp<int>(c, c->L.rec_off);
+    const SolidDev* sol = wsp<SolidDev>(c, c->L.sol);
+    switch (c->g.dtype) {
+        case LBM_F64: k_link_records<double><<<ns, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
+        case LBM_F32: k_link_records<float><<<ns, kBlock, 0, c->stream>>>(wsp<float>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
+        case LBM_F16: k_link_records<_Float16><<<ns, kBlock, 0, c->stream>>>(wsp<_Float16>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
+        default: k_link_records<bf16_t><<<ns, kBlock, 0, c->stream>>>(wsp<bf16_t>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_checkpoint_bytes(const lbm_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return LBM_EINVAL;
+    // populations (current buffer), both owner maps, links + counts, counters
+    *bytes = 64 + (c->L.f[1] - c->L.f[0]) + 2 * (c->L.own[1] - c->L.own[0]) +
+             4 * (size_t)std::max<int64_t>(c->link_cap_total, 1) + 4 * (size_t)(c->n + 1);
+    return LBM_OK;
+}
+
+lbm_status lbm_save(lbm_ctx* c, void* d_dst, size_t bytes) {
+    if (!c || !d_dst) return LBM_EINVAL;
+    size_t need;
+    lbm_checkpoint_bytes(c, &need);
+    if (bytes < need) {
+        set_err(c->err, "checkpoint buffer too small: %zu < %zu", bytes, need);
+        return LBM_ESIZE;
+    }
+    char* d = (char*)d_dst;
+    int64_t hdr[8] = {0x6c626d63, (int64_t)LBM_ABI_VERSION, c->t, c->g.nx, c->g.ny, c->g.dtype, c->n, 0};
+    const int p = (int)(c->t & 1);
+    const size_t fb = c->L.f[1] - c->L.f[0];
+    const size_t ob = c->L.own[1] - c->L.own[0];
+    HIPCHK(c, hipMemcpyAsync(d, hdr, 64, hipMemcpyHostToDevice, c->stream));
+    size_t o = 64;
+    HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.f[p], fb, hipMemcpyDeviceToDevice, c->stream));
+    o += fb;
+    HIPCHK(c, hipMemcpyAsync(d + o, own_ptr(c, p), ob, hipMemcpyDeviceToDevice, c->stream));
+    o += ob;
+    HIPCHK(c, hipMemcpyAsync(d + o, own_ptr(c, p ^ 1), ob, hipMemcpyDeviceToDevice, c->stream));
+    o += ob;
+    const size_t lb = 4 * (size_t)std::max<int64_t>(c->link_cap_total, 1);
+    HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.links, lb, hipMemcpyDeviceToDevice, c->stream));
+    o += lb;
+    HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.seg_cnt, 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
+    return read_err(c);
+}
+
+lbm_status lbm_load(lbm_ctx* c, const void* d_src, size_t bytes) {
+    if (!c || !d_src) return LBM_EINVAL;
+    size_t need;
+    lbm_checkpoint_bytes(c, &need);
+    if (bytes < need) {
+        set_err(c->err, "checkpoint buffer too small: %zu < %zu", bytes, need);
+        return LBM_ESIZE;
+    }
+    const char* s = (const char*)d_src;
+    int64_t hdr[8];
+    HIPCHK(c, hipMemcpyAsync(hdr, s, 64, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (hdr[0] != 0x6c626d63 || hdr[1] != LBM_ABI_VERSION || hdr[3] != c->g.nx || hdr[4] != c->g.ny ||
+        hdr[5] != c->g.dtype || hdr[6] != c->n || hdr[2] < 0) {
+        set_err(c->err, "checkpoint does not match this context");
+        return LBM_EINVAL;
+    }
+    c->t = hdr[2];
+    const int p = (int)(c->t & 1);
+    const size_t fb = c->L.f[1] - c->L.f[0];
+    const size_t ob = c->L.own[1] - c->L.own[0];
+    size_t o = 64;
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.f[p], s + o, fb, hipMemcpyDeviceToDevice, c->stream));
+    o += fb;
+    HIPCHK(c, hipMemcpyAsync(own_ptr(c, p), s + o, ob, hipMemcpyDeviceToDevice, c->stream));
+    o += ob;
+    if (c->L.n_movers > 0)
+        HIPCHK(c, hipMemcpyAsync(own_ptr(c, p ^ 1), s + o, ob, hipMemcpyDeviceToDevice, c->stream));
+    o += ob;
+    const size_t lb = 4 * (size_t)std::max<int64_t>(c->link_cap_total, 1);
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.links, s + o, lb, hipMemcpyDeviceToDevice, c->stream));
+    o += lb;
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.seg_cnt, s + o, 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
+    k_set_counters<<<1, 1, 0, c->stream>>>(wsp<int64_t>(c, c->L.tctr), c->t, wsp<int>(c, c->L.err));
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_profile(lbm_ctx* c, int32_t enable) {
+    if (!c) return LBM_EINVAL;
+    c->prof = enable != 0;
+    c->ev_used = 0;
+    c->prof_ms = 0.0;
+    c->prof_n = 0;
+    if (c->prof && c->ev.empty()) {
+        c->ev.resize(2 * 65536);
+        for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_profile_read(lbm_ctx* c, double* update_ms, int64_t* launches) {
+    if (!c || !update_ms || !launches) return LBM_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+        c->prof_ms += ms;
+        c->prof_n += 1;
+    }
+    c->ev_used = 0;
+    *update_ms = c->prof_ms;
+    *launches = c->prof_n;
+    return LBM_OK;
+}
+
+lbm_status lbm_status_check(lbm_ctx* c) {
+    if (!c) return LBM_EINVAL;
+    return read_err(c);
+}
+
+void lbm_destroy(lbm_ctx* c) {
+    if (!c) return;
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_err; }
+
+}  // extern "C"

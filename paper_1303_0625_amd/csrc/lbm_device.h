@@ -1,0 +1,186 @@
+// lbm_device.h -- device-side building blocks of the D2Q9 hot path (gfx950).
+//
+// Lattice: D2Q9 velocity set in the order of Sec. III.C of Wen et al.
+// (arXiv:1303.0625); weights 4/9, 1/9, 1/36.  Populations are stored as
+// deviations d_i = f_i - w_i rho0 from the rest equilibrium, in one of four
+// storage types; collision arithmetic runs in double (double storage) or float
+// (float, half and bfloat16 storage).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------- lattice
+__host__ __device__ constexpr int ex_(int i) {
+    return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey_(int i) {
+    return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+// opposite direction ibar
+__host__ __device__ constexpr int opp_(int i) {
+    return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+template <typename C>
+__host__ __device__ constexpr C w_(int i) {
+    return i == 0 ? C(4.0 / 9.0) : (i <= 4 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+}
+static_assert(opp_(1) == 3 && opp_(2) == 4 && opp_(3) == 1 && opp_(4) == 2, "opp");
+static_assert(opp_(5) == 7 && opp_(6) == 8 && opp_(7) == 5 && opp_(8) == 6, "opp");
+
+// ---------------------------------------------------------------- storage
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <typename T>
+struct Sto;
+template <>
+struct Sto<double> {
+    using C = double;
+    __device__ static inline double ld(double v) { return v; }
+    __device__ static inline double st(double c) { return c; }
+};
+template <>
+struct Sto<float> {
+    using C = float;
+    __device__ static inline float ld(float v) { return v; }
+    __device__ static inline float st(float c) { return c; }
+};
+template <>
+struct Sto<_Float16> {
+    using C = float;
+    __device__ static inline float ld(_Float16 v) { return (float)v; }
+    // hardware conversion rounds to nearest even; subnormals are kept
+    __device__ static inline _Float16 st(float c) { return (_Float16)c; }
+};
+template <>
+struct Sto<bf16_t> {
+    using C = float;
+    __device__ static inline float ld(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+    // round to nearest even on the upper 16 bits; NaN stays NaN
+    __device__ static inline bf16_t st(float c) {
+        uint32_t u = __float_as_uint(c);
+        bf16_t r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) {
+            r.bits = (uint16_t)((u >> 16) | 0x40u);
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            r.bits = (uint16_t)(u >> 16);
+        }
+        return r;
+    }
+};
+
+// ---------------------------------------------------------------- collision
+// BGK collision with Guo forcing on the deviations d_i (Eq. 2 with the Eq. 8
+// equilibrium).  rho = rho0 + sum d_i; rho*u = sum e_i d_i + rho*g/2;
+//   d~_i = d_i - omega (d_i - deq_i) + (1 - 1/(2 tau)) w_i [3(e_i - u) + 9 (e_i.u) e_i] . rho g
+// with deq_i = w_i [drho + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u)].
+template <typename C>
+struct CollideParams {
+    C rho0, omega, gx, gy, pref;  // pref = 1 - 1/(2 tau)
+};
+
+template <typename C>
+__device__ inline void collide(C d[9], const CollideParams<C>& p) {
+    C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    C rho = p.rho0 + drho;
+    C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    C inv = C(1) / rho;
+    C ux = jx * inv + C(0.5) * p.gx;
+    C uy = jy * inv + C(0.5) * p.gy;
+    C uu = ux * ux + uy * uy;
+    C Fx = rho * p.gx, Fy = rho * p.gy;
+    C uF = ux * Fx + uy * Fy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const C w = w_<C>(i);
+        C eu = C(ex_(i)) * ux + C(ey_(i)) * uy;
+        C eF = C(ex_(i)) * Fx + C(ey_(i)) * Fy;
+        C deq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+        C src = p.pref * w * (C(3) * (eF - uF) + C(9) * eu * eF);
+        d[i] = d[i] - p.omega * (d[i] - deq) + src;
+    }
+}
+
+// Equilibrium deviation f_eq(rho, u) - w rho0 of Eq. 8.
+template <typename C>
+__device__ inline void feq_dev(C rho, C rho0, C ux, C uy, C out[9]) {
+    C uu = ux * ux + uy * uy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const C w = w_<C>(i);
+        C eu = C(ex_(i)) * ux + C(ey_(i)) * uy;
+        out[i] = w * ((rho - rho0) + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+    }
+}
+
+// ---------------------------------------------------------------- misc
+__host__ __device__ inline int wrapi(long v, int n) {
+    long r = v % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+// Solid record on the device (id 0 is the walls).
+struct SolidDev {
+    double x0, y0;   // centre at t = 0
+    double a, b;     // disc radius / box half-extents
+    double vx, vy;   // velocity
+    int32_t shape;   // 0 disc, 1 box
+    int32_t moves;   // geometry translates
+};
+
+// Centre of a solid at step t: X = x0 + t*vx with separately rounded product
+// and sum (contraction into a fused multiply-add is switched off here and in
+// solid_inside), so that the solid/fluid decision of every node is the one a
+// plain IEEE double evaluation takes.
+__device__ inline void solid_pos(const SolidDev& s, int64_t t, double& X, double& Y) {
+#pragma clang fp contract(off)
+    if (s.moves) {
+        X = s.x0 + (double)t * s.vx;
+        Y = s.y0 + (double)t * s.vy;
+    } else {
+        X = s.x0;
+        Y = s.y0;
+    }
+}
+
+// Whether integer point (x, y) lies inside solid s centred at (X, Y).
+__device__ inline bool solid_inside(const SolidDev& s, double X, double Y, long x, long y) {
+#pragma clang fp contract(off)
+    double dx = (double)x - X;
+    double dy = (double)y - Y;
+    if (s.shape == 0) {
+        double d2 = dx * dx;
+        d2 = d2 + dy * dy;
+        return d2 <= s.a * s.a;
+    }
+    return fabs(dx) <= s.a && fabs(dy) <= s.b;
+}
+
+// Integer bounding range (with a margin) of solid s centred at (X, Y).
+__device__ inline void solid_range(const SolidDev& s, double X, double Y, int margin, long& x0,
+                                   long& x1, long& y0, long& y1) {
+    double hx = s.a, hy = s.shape == 0 ? s.a : s.b;
+    x0 = (long)floor(X - hx) - margin;
+    x1 = (long)ceil(X + hx) + margin;
+    y0 = (long)floor(Y - hy) - margin;
+    y1 = (long)ceil(Y + hy) + margin;
+}
+
+// XCD-aware block order: the hardware hands consecutive workgroups to the 8
+// XCDs in turn; remap so that each XCD walks a contiguous band of tiles and
+// the halo lines shared by neighbouring tiles stay in one L2.
+__device__ inline uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+    const uint32_t nxcd = 8;
+    uint32_t per = nb / nxcd;
+    uint32_t full = per * nxcd;
+    if (b >= full) return b;
+    return (b % nxcd) * per + b / nxcd;
+}
+
+}  // namespace lbm

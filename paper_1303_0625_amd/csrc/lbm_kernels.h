@@ -1,0 +1,621 @@
+// lbm_kernels.h -- HIP kernels of the D2Q9 momentum-exchange hot path.
+//
+// State convention: the workspace holds the post-collision deviations
+// d~_i(x, t) = f~_i(x, t) - w_i rho0 of every fluid node of geometry G_t, SoA
+// [9][ny][pitch], in two ping-pong buffers selected by the parity of t.  One
+// time step t -> t+1 is
+//   k_force    Eqs. 4-7 on the link list of G_t (reads f~(t))
+//   k_move     translating bodies: owner map of G_{t+1}, their link lists
+//   k_step     pull-advection (Eq. 3) with half-way bounce-back on G_t, then
+//              collision (Eq. 2), for nodes fluid in both G_t and G_{t+1}
+//   k_refill   newborn nodes (solid in G_t, fluid in G_{t+1}): extrapolated
+//              from old-fluid neighbours' post-advection values, then collided
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+constexpr int kBlock = 256;
+constexpr int kMaxSolids = 254;
+
+struct StepArgs {
+    int nx, ny;
+    int pitch;    // elements per population row
+    int opitch;   // bytes per owner-map row
+    int64_t plane;  // elements per population plane (ny * pitch)
+    int walls;
+    double rho0;
+};
+
+// ------------------------------------------------------------------ pull
+// Post-advection deviation of direction i at node (x, y) from the
+// post-collision buffer: the value streaming in from x - e_i, or, when that
+// node is solid in G_t (or is a wall row), the half-way bounce-back of the
+// node's own opposite population plus 6 w_i rho0 (e_i . v_solid).
+template <typename T, typename C>
+__device__ inline C pull_one(const T* __restrict__ f, const uint8_t* __restrict__ own,
+                             const double* __restrict__ vtab, const StepArgs& a, int x, int y,
+                             int i) {
+    int xs = x - ex_(i), ys = y - ey_(i);
+    xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+    int sid;
+    if (a.walls && (ys < 0 || ys >= a.ny)) {
+        sid = 0;
+    } else {
+        ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
+        int o = own[(int64_t)ys * a.opitch + xs];
+        if (o == 0) return Sto<T>::ld(f[(int64_t)i * a.plane + (int64_t)ys * a.pitch + xs]);
+        sid = o;
+    }
+    C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+    C m = C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
+    return Sto<T>::ld(f[(int64_t)opp_(i) * a.plane + (int64_t)y * a.pitch + x]) + m;
+}
+
+// ------------------------------------------------------------------ step
+// One thread per node.  Fast path: none of the eight source nodes is solid or
+// a wall, so the nine loads are issued unconditionally.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* __restrict__ fout,
+                                                 const uint8_t* __restrict__ own_t,
+                                                 const uint8_t* __restrict__ own_n,
+                                                 const double* __restrict__ vtab, StepArgs a,
+                                                 CollideParams<typename Sto<T>::C> cp) {
+    using C = typename Sto<T>::C;
+    // each wave takes 64 consecutive nodes of one row (pitch is a multiple of
+    // 64), so the row and column base are wave-uniform scalars
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t wpr = (uint32_t)a.pitch >> 6;
+    const uint32_t gw = b * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int y = (int)(gw / wpr);
+    const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
+    if (y >= a.ny || x >= a.nx) return;
+    const int64_t orow = (int64_t)y * a.opitch;
+    if (own_t[orow + x] | own_n[orow + x]) return;  // solid, newborn or covered
+
+    const int xm = x == 0 ? a.nx - 1 : x - 1;
+    const int xp = x == a.nx - 1 ? 0 : x + 1;
+    bool wall_lo = false, wall_hi = false;  // source rows y-1 / y+1 are walls
+    int ym, yp;
+    if (a.walls) {
+        wall_lo = (y == 0);
+        wall_hi = (y == a.ny - 1);
+        ym = wall_lo ? y : y - 1;
+        yp = wall_hi ? y : y + 1;
+    } else {
+        ym = y == 0 ? a.ny - 1 : y - 1;
+        yp = y == a.ny - 1 ? 0 : y + 1;
+    }
+    const uint8_t* om = own_t + (int64_t)ym * a.opitch;
+    const uint8_t* o0 = own_t + orow;
+    const uint8_t* op = own_t + (int64_t)yp * a.opitch;
+    // owners of the sources x - e_i
+    const uint32_t s1 = o0[xm], s3 = o0[xp];
+    const uint32_t s2 = om[x], s5 = om[xm], s6 = om[xp];
+    const uint32_t s4 = op[x], s7 = op[xp], s8 = op[xm];
+    const bool special = (s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0 || wall_lo || wall_hi;
+
+    const int64_t P = a.plane;
+    const T* r0 = fin + (int64_t)y * a.pitch;
+    const T* rm = fin + (int64_t)ym * a.pitch;
+    const T* rp = fin + (int64_t)yp * a.pitch;
+    C d[9];
+    if (!special) {
+        d[0] = Sto<T>::ld(r0[x]);
+        d[1] = Sto<T>::ld(r0[P + xm]);
+        d[2] = Sto<T>::ld(rm[2 * P + x]);
+        d[3] = Sto<T>::ld(r0[3 * P + xp]);
+        d[4] = Sto<T>::ld(rp[4 * P + x]);
+        d[5] = Sto<T>::ld(rm[5 * P + xm]);
+        d[6] = Sto<T>::ld(rm[6 * P + xp]);
+        d[7] = Sto<T>::ld(rp[7 * P + xp]);
+        d[8] = Sto<T>::ld(rp[8 * P + xm]);
+    } else {
+        d[0] = Sto<T>::ld(r0[x]);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) d[i] = pull_one<T, C>(fin, own_t, vtab, a, x, y, i);
+    }
+    collide<C>(d, cp);
+    T* w0 = fout + (int64_t)y * a.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) w0[i * P] = Sto<T>::st(d[i]);
+}
+
+// ------------------------------------------------------------------ init
+// f = f_eq(rho, u) at every fluid node (uniform rho0, u0 when the field
+// pointers are NULL; otherwise u - g/2 from the fields so that the Guo
+// velocity is u), collided once.  Solid nodes are zeroed.
+template <typename T, typename FT>
+__global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_t* __restrict__ own,
+                                                 StepArgs a, CollideParams<typename Sto<T>::C> cp,
+                                                 double u0x, double u0y, const FT* __restrict__ rho,
+                                                 const FT* __restrict__ ux,
+                                                 const FT* __restrict__ uy) {
+    using C = typename Sto<T>::C;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int y = (int)(idx / a.pitch);
+    const int x = (int)(idx - (int64_t)y * a.pitch);
+    if (y >= a.ny || x >= a.nx) return;
+    T* w0 = f + (int64_t)y * a.pitch + x;
+    if (own[(int64_t)y * a.opitch + x] != 0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) w0[i * a.plane] = Sto<T>::st(C(0));
+        return;
+    }
+    C d[9];
+    if (rho == nullptr) {
+        feq_dev<C>((C)a.rho0, (C)a.rho0, (C)u0x, (C)u0y, d);
+    } else {
+        int64_t n = (int64_t)y * a.nx + x;
+        feq_dev<C>((C)rho[n], (C)a.rho0, (C)ux[n] - C(0.5) * cp.gx, (C)uy[n] - C(0.5) * cp.gy, d);
+    }
+    collide<C>(d, cp);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) w0[i * a.plane] = Sto<T>::st(d[i]);
+}
+
+// ------------------------------------------------------------------ fields
+// rho and the Guo velocity of the pre-collision state f(t), from the stored
+// post-collision populations: collision keeps mass and adds rho*g to the
+// momentum, so rho*u = sum e_i f~_i - rho*g/2.
+template <typename T, typename OT>
+__global__ __launch_bounds__(kBlock) void k_fields(const T* __restrict__ f,
+                                                   const uint8_t* __restrict__ own, StepArgs a,
+                                                   double gx, double gy, OT* __restrict__ rho_o,
+                                                   OT* __restrict__ ux_o, OT* __restrict__ uy_o,
+                                                   uint8_t* __restrict__ own_o,
+                                                   int* __restrict__ errflag) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int y = (int)(idx / a.pitch);
+    const int x = (int)(idx - (int64_t)y * a.pitch);
+    if (y >= a.ny || x >= a.nx) return;
+    const int64_t n = (int64_t)y * a.nx + x;
+    const uint8_t o = own[(int64_t)y * a.opitch + x];
+    double r = 0.0, ux = 0.0, uy = 0.0;
+    if (o == 0) {
+        double d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = (double)Sto<T>::ld(f[i * a.plane + (int64_t)y * a.pitch + x]);
+        double drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+        r = a.rho0 + drho;
+        double jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+        double jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+        ux = jx / r - 0.5 * gx;
+        uy = jy / r - 0.5 * gy;
+        if (!(r > 0.0) || !isfinite(r) || !isfinite(ux) || !isfinite(uy)) atomicOr(errflag, 2);
+    }
+    if (rho_o) rho_o[n] = (OT)r;
+    if (ux_o) ux_o[n] = (OT)ux;
+    if (uy_o) uy_o[n] = (OT)uy;
+    if (own_o) own_o[n] = o;
+}
+
+// Absolute post-collision populations in double, [9][ny][nx]; 0 at solids.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_populations(const T* __restrict__ f,
+                                                        const uint8_t* __restrict__ own,
+                                                        StepArgs a, double* __restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int y = (int)(idx / a.pitch);
+    const int x = (int)(idx - (int64_t)y * a.pitch);
+    if (y >= a.ny || x >= a.nx) return;
+    const bool fl = own[(int64_t)y * a.opitch + x] == 0;
+    const int64_t nn = (int64_t)a.nx * a.ny;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        double v = fl ? w_<double>(i) * a.rho0 + (double)Sto<T>::ld(f[i * a.plane + (int64_t)y * a.pitch + x])
+                      : 0.0;
+        out[i * nn + (int64_t)y * a.nx + x] = v;
+    }
+}
+
+// ------------------------------------------------------------------ geometry
+struct GeomArgs {
+    int nx, ny, opitch, walls;
+};
+
+// Clear an owner map (fill kernel: graph-safe, no memset node).
+__global__ void k_fill_u8(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Rasterise solids list[blockIdx.x] at step t into own (one workgroup per
+// solid; the bodies do not overlap, so every node is written by one solid).
+__global__ __launch_bounds__(kBlock) void k_raster(uint8_t* __restrict__ own,
+                                                   const SolidDev* __restrict__ sol,
+                                                   const int* __restrict__ list, int64_t t,
+                                                   GeomArgs g) {
+    const int s = list[blockIdx.x];
+    const SolidDev S = sol[s];
+    double X, Y;
+    solid_pos(S, t, X, Y);
+    long x0, x1, y0, y1;
+    solid_range(S, X, Y, 1, x0, x1, y0, y1);
+    const long W = x1 - x0 + 1, H = y1 - y0 + 1;
+    for (long q = threadIdx.x; q < W * H; q += kBlock) {
+        long yy = y0 + q / W, xx = x0 + q % W;
+        if (!solid_inside(S, X, Y, xx, yy)) continue;
+        if (g.walls && (yy < 0 || yy >= g.ny)) continue;
+        own[(int64_t)wrapi(yy, g.ny) * g.opitch + wrapi(xx, g.nx)] = (uint8_t)s;
+    }
+}
+
+// ------------------------------------------------------------------ links
+// Link code: (y*nx + x) << 4 | i, for a fluid node x_f and direction i whose
+// neighbour x_f + e_i is solid.
+struct LinkArgs {
+    int nx, ny, opitch, walls;
+};
+
+// Wall links (solid 0): rows 0 and ny-1 are always fluid (bodies keep a gap
+// to the walls); row 0 links to the wall through i = 4, 7, 8 and row ny-1
+// through i = 2, 5, 6.  Order (y, x, i).
+__global__ void k_wall_links(uint32_t* __restrict__ links, int nx, int ny) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2 * nx) return;
+    int top = k >= nx;
+    int x = top ? k - nx : k;
+    int y = top ? ny - 1 : 0;
+    uint32_t node = (uint32_t)y * (uint32_t)nx + (uint32_t)x;
+    uint32_t* L = links + 3 * k;
+    if (!top) {
+        L[0] = node << 4 | 4u;
+        L[1] = node << 4 | 7u;
+        L[2] = node << 4 | 8u;
+    } else {
+        L[0] = node << 4 | 2u;
+        L[1] = node << 4 | 5u;
+        L[2] = node << 4 | 6u;
+    }
+}
+
+// Block-wide exclusive scan of one int per thread (kBlock threads).
+__device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int t = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    total = sh[kBlock - 1];
+    int ex = sh[tid] - v;
+    __syncthreads();
+    return ex;
+}
+
+// Build the link list of solid s from owner map own over its bounding range
+// at step t.  Each thread takes a contiguous run of the range's nodes, so the
+// scan keeps row-major (y, x, i) order.
+__device__ inline void build_links_block(const uint8_t* __restrict__ own, uint32_t* __restrict__ links,
+                                         int* __restrict__ seg_cnt, const int* __restrict__ seg_off,
+                                         const int* __restrict__ seg_cap, const SolidDev& S, int s,
+                                         int64_t t, const LinkArgs& g, int* __restrict__ errflag,
+                                         int* sh) {
+    double X, Y;
+    solid_pos(S, t, X, Y);
+    long x0, x1, y0, y1;
+    solid_range(S, X, Y, 2, x0, x1, y0, y1);
+    if (x1 - x0 + 1 > g.nx) { x0 = 0; x1 = g.nx - 1; }
+    if (!g.walls && y1 - y0 + 1 > g.ny) { y0 = 0; y1 = g.ny - 1; }
+    if (g.walls) { y0 = y0 < 0 ? 0 : y0; y1 = y1 >= g.ny ? g.ny - 1 : y1; }
+    const long W = x1 - x0 + 1, H = y1 - y0 + 1, N = W * H;
+    const long chunk = (N + kBlock - 1) / kBlock;
+    const long q0 = (long)threadIdx.x * chunk;
+    const long q1 = q0 + chunk < N ? q0 + chunk : N;
+    auto links_of = [&](long q, uint32_t* out, int base) -> int {
+        long yy = y0 + q / W, xx = x0 + q % W;
+        int x = wrapi(xx, g.nx), y = wrapi(yy, g.ny);
+        if (own[(int64_t)y * g.opitch + x] != 0) return 0;
+        int c = 0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            int yn = y + ey_(i);
+            if (g.walls && (yn < 0 || yn >= g.ny)) continue;
+            int xn = wrapi(x + ex_(i), g.nx);
+            yn = wrapi(yn, g.ny);
+            if (own[(int64_t)yn * g.opitch + xn] == s) {
+                if (out) out[base + c] = ((uint32_t)y * (uint32_t)g.nx + (uint32_t)x) << 4 | (uint32_t)i;
+                ++c;
+            }
+        }
+        return c;
+    };
+    int cnt = 0;
+    for (long q = q0; q < q1; ++q) cnt += links_of(q, nullptr, 0);
+    int total;
+    int off = block_exclusive_scan(cnt, sh, total);
+    const int cap = seg_cap[s];
+    uint32_t* L = links + seg_off[s];
+    if (total <= cap) {
+        for (long q = q0; q < q1; ++q) off += links_of(q, L, off);
+    }
+    if (threadIdx.x == 0) {
+        seg_cnt[s] = total <= cap ? total : 0;
+        if (total > cap) atomicOr(errflag, 1);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_links(const uint8_t* __restrict__ own,
+                                                  uint32_t* __restrict__ links,
+                                                  int* __restrict__ seg_cnt,
+                                                  const int* __restrict__ seg_off,
+                                                  const int* __restrict__ seg_cap,
+                                                  const SolidDev* __restrict__ sol,
+                                                  const int* __restrict__ list, int64_t t,
+                                                  LinkArgs g, int* __restrict__ errflag) {
+    __shared__ int sh[kBlock];
+    const int s = list[blockIdx.x];
+    build_links_block(own, links, seg_cnt, seg_off, seg_cap, sol[s], s, t, g, errflag, sh);
+}
+
+// Translating bodies, one workgroup per mover: bring the owner map own_n
+// (which holds G_{t-1}) to G_{t+1} over the range swept from t-1 to t+1, then
+// rebuild the mover's link list for G_{t+1}.  Bodies keep a gap of at least
+// two nodes, so no other solid owns a node adjacent to this one.
+__global__ __launch_bounds__(kBlock) void k_move(uint8_t* __restrict__ own_n,
+                                                 uint32_t* __restrict__ links,
+                                                 int* __restrict__ seg_cnt,
+                                                 const int* __restrict__ seg_off,
+                                                 const int* __restrict__ seg_cap,
+                                                 const SolidDev* __restrict__ sol,
+                                                 const int* __restrict__ movers,
+                                                 const int64_t* __restrict__ tctr, int parity,
+                                                 LinkArgs g, int* __restrict__ errflag) {
+    __shared__ int sh[kBlock];
+    const int s = movers[blockIdx.x];
+    const SolidDev S = sol[s];
+    const int64_t t = tctr[parity];
+    double Xa, Ya, Xb, Yb;
+    solid_pos(S, t - 1, Xa, Ya);
+    solid_pos(S, t + 1, Xb, Yb);
+    long ax0, ax1, ay0, ay1, bx0, bx1, by0, by1;
+    solid_range(S, Xa, Ya, 1, ax0, ax1, ay0, ay1);
+    solid_range(S, Xb, Yb, 1, bx0, bx1, by0, by1);
+    const long x0 = ax0 < bx0 ? ax0 : bx0, x1 = ax1 > bx1 ? ax1 : bx1;
+    const long y0 = ay0 < by0 ? ay0 : by0, y1 = ay1 > by1 ? ay1 : by1;
+    const long W = x1 - x0 + 1, H = y1 - y0 + 1;
+    for (long q = threadIdx.x; q < W * H; q += kBlock) {
+        long yy = y0 + q / W, xx = x0 + q % W;
+        if (g.walls && (yy < 0 || yy >= g.ny)) continue;
+        int64_t o = (int64_t)wrapi(yy, g.ny) * g.opitch + wrapi(xx, g.nx);
+        if (solid_inside(S, Xb, Yb, xx, yy))
+            own_n[o] = (uint8_t)s;
+        else if (own_n[o] == s)
+            own_n[o] = 0;
+    }
+    __syncthreads();
+    build_links_block(own_n, links, seg_cnt, seg_off, seg_cap, S, s, t + 1, g, errflag, sh);
+}
+
+// ------------------------------------------------------------------ forces
+struct ForceArgs {
+    int nx, ny, pitch, walls;
+    int64_t plane;
+    double rho0;
+    int64_t hist_cap;
+    int nsol;  // bodies + 1
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One workgroup per solid.  Per link (x_f, i) with a = f~_i(x_f) and the
+// bounced population b = a - 6 w_i rho0 (e_i . v):
+//   CME (Eq. 4) F = e_i a - e_ibar b
+//   GME (Eq. 5) F = (e_i - v) a - (e_ibar - v) b
+//   T_z (Eq. 7) = (x_s - R) x F with x_s = x_f + e_i/2, R the body centre.
+// Each thread sums a fixed strided subset of the links; the wave and
+// workgroup combine in a fixed tree, so the result is run-to-run identical.
+// Block 0 also advances the step counter into the other parity slot.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_force(const T* __restrict__ f,
+                                                  const uint32_t* __restrict__ links,
+                                                  const int* __restrict__ seg_cnt,
+                                                  const int* __restrict__ seg_off,
+                                                  const SolidDev* __restrict__ sol,
+                                                  double* __restrict__ hist,
+                                                  int64_t* __restrict__ tctr, int parity,
+                                                  ForceArgs a) {
+    __shared__ double sh[kBlock / 64][6];
+    const int s = blockIdx.x;
+    const int64_t t = tctr[parity];
+    const int n = seg_cnt[s];
+    const uint32_t* L = links + seg_off[s];
+    const SolidDev S = sol[s];
+    double X = 0.0, Y = 0.0;
+    if (s > 0) solid_pos(S, t, X, Y);
+    const double vx = S.vx, vy = S.vy;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+        const uint32_t code = L[k];
+        const int i = (int)(code & 15u);
+        const uint32_t node = code >> 4;
+        const int y = (int)(node / (uint32_t)a.nx);
+        const int x = (int)(node - (uint32_t)y * (uint32_t)a.nx);
+        double ex = 0, ey = 0, w = 0;
+        switch (i) {  // direction table of Sec. III.C
+            case 1: ex = 1; ey = 0; w = 1.0 / 9.0; break;
+            case 2: ex = 0; ey = 1; w = 1.0 / 9.0; break;
+            case 3: ex = -1; ey = 0; w = 1.0 / 9.0; break;
+            case 4: ex = 0; ey = -1; w = 1.0 / 9.0; break;
+            case 5: ex = 1; ey = 1; w = 1.0 / 36.0; break;
+            case 6: ex = -1; ey = 1; w = 1.0 / 36.0; break;
+            case 7: ex = -1; ey = -1; w = 1.0 / 36.0; break;
+            default: ex = 1; ey = -1; w = 1.0 / 36.0; break;
+        }
+        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.plane + (int64_t)y * a.pitch + x]);
+        const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
+        // CME: e_i a - e_ibar b, e_ibar = -e_i
+        const double cfx = ex * av + ex * bv;
+        const double cfy = ey * av + ey * bv;
+        // GME: (e_i - v) a - (e_ibar - v) b
+        const double gfx = (ex - vx) * av - (-ex - vx) * bv;
+        const double gfy = (ey - vy) * av - (-ey - vy) * bv;
+        acc[0] += cfx;
+        acc[1] += cfy;
+        acc[3] += gfx;
+        acc[4] += gfy;
+        if (s > 0) {
+            double rx = ((double)x + 0.5 * ex) - X;
+            rx -= (double)a.nx * rint(rx / (double)a.nx);
+            double ry = ((double)y + 0.5 * ey) - Y;
+            if (!a.walls) ry -= (double)a.ny * rint(ry / (double)a.ny);
+            acc[2] += rx * cfy - ry * cfx;
+            acc[5] += rx * gfy - ry * gfx;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double v = wave_sum(acc[c]);
+        if (lane == 0) sh[wv][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int c = threadIdx.x;
+        double v = ((sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]));
+        hist[((t % a.hist_cap) * a.nsol + s) * 6 + c] = v;
+    }
+    if (s == 0 && threadIdx.x == 0) tctr[parity ^ 1] = t + 1;
+}
+
+// Per-link force records of the current state (test and inspection path).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f,
+                                                         const uint32_t* __restrict__ links,
+                                                         const int* __restrict__ seg_cnt,
+                                                         const int* __restrict__ seg_off,
+                                                         const int* __restrict__ rec_off,
+                                                         const SolidDev* __restrict__ sol,
+                                                         double* __restrict__ out, ForceArgs a) {
+    const int s = blockIdx.x;
+    const int n = seg_cnt[s];
+    const uint32_t* L = links + seg_off[s];
+    const double vx = sol[s].vx, vy = sol[s].vy;
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+        const uint32_t code = L[k];
+        const int i = (int)(code & 15u);
+        const uint32_t node = code >> 4;
+        const int y = (int)(node / (uint32_t)a.nx);
+        const int x = (int)(node - (uint32_t)y * (uint32_t)a.nx);
+        const double ex = ex_(i), ey = ey_(i), w = w_<double>(i);
+        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.plane + (int64_t)y * a.pitch + x]);
+        const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
+        double* r = out + 8 * (int64_t)(rec_off[s] + k);
+        r[0] = x;
+        r[1] = y;
+        r[2] = i;
+        r[3] = s;
+        r[4] = ex * av + ex * bv;
+        r[5] = ey * av + ey * bv;
+        r[6] = (ex - vx) * av - (-ex - vx) * bv;
+        r[7] = (ey - vy) * av - (-ey - vy) * bv;
+    }
+}
+
+// ------------------------------------------------------------------ refill
+// Newborn nodes of the movers (one workgroup per mover): solid in G_t, fluid
+// in G_{t+1}.  For every direction k whose first node x + e_k is old-fluid
+// (fluid in both geometries), extrapolate each population from the
+// post-advection values at x + m e_k: A1 3f1 - 3f2 + f3 (needs m = 1..3
+// old-fluid), else A2 2f1 - f2 (needs m = 1, 2), else A3 f1; average over the
+// participating directions; with none, take f_eq(rho0, v) of the body.  Then
+// collide and store.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_refill(const T* __restrict__ fin, T* __restrict__ fout,
+                                                   const uint8_t* __restrict__ own_t,
+                                                   const uint8_t* __restrict__ own_n,
+                                                   const double* __restrict__ vtab,
+                                                   const SolidDev* __restrict__ sol,
+                                                   const int* __restrict__ movers,
+                                                   const int64_t* __restrict__ tctr, int parity,
+                                                   StepArgs a, CollideParams<typename Sto<T>::C> cp,
+                                                   int scheme) {
+    using C = typename Sto<T>::C;
+    const int s = movers[blockIdx.x];
+    const SolidDev S = sol[s];
+    const int64_t t = tctr[parity];
+    double Xa, Ya, Xb, Yb;
+    solid_pos(S, t, Xa, Ya);
+    solid_pos(S, t + 1, Xb, Yb);
+    long ax0, ax1, ay0, ay1, bx0, bx1, by0, by1;
+    solid_range(S, Xa, Ya, 1, ax0, ax1, ay0, ay1);
+    solid_range(S, Xb, Yb, 1, bx0, bx1, by0, by1);
+    const long x0 = ax0 < bx0 ? ax0 : bx0, x1 = ax1 > bx1 ? ax1 : bx1;
+    const long y0 = ay0 < by0 ? ay0 : by0, y1 = ay1 > by1 ? ay1 : by1;
+    const long W = x1 - x0 + 1, H = y1 - y0 + 1;
+    for (long q = threadIdx.x; q < W * H; q += kBlock) {
+        const long yy = y0 + q / W, xx = x0 + q % W;
+        if (a.walls && (yy < 0 || yy >= a.ny)) continue;
+        const int x = wrapi(xx, a.nx), y = wrapi(yy, a.ny);
+        const int64_t o = (int64_t)y * a.opitch + x;
+        if (!(own_t[o] == s && own_n[o] == 0)) continue;
+        C acc[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) acc[j] = C(0);
+        int npart = 0;
+        for (int k = 1; k < 9; ++k) {
+            int px[4], py[4];
+            bool ok[4] = {false, false, false, false};
+            for (int m = 1; m <= 3; ++m) {
+                int xm = x + m * ex_(k), ym = y + m * ey_(k);
+                if (a.walls && (ym < 0 || ym >= a.ny)) break;
+                px[m] = wrapi(xm, a.nx);
+                py[m] = wrapi(ym, a.ny);
+                const int64_t om = (int64_t)py[m] * a.opitch + px[m];
+                ok[m] = own_t[om] == 0 && own_n[om] == 0;
+                if (!ok[m]) break;
+            }
+            if (!ok[1]) continue;
+            ++npart;
+            int use = scheme;
+            if (use == 0 && !(ok[2] && ok[3])) use = 1;
+            if (use == 1 && !ok[2]) use = 2;
+            for (int j = 0; j < 9; ++j) {
+                C v1 = pull_one<T, C>(fin, own_t, vtab, a, px[1], py[1], j);
+                C val;
+                if (use == 0) {
+                    C v2 = pull_one<T, C>(fin, own_t, vtab, a, px[2], py[2], j);
+                    C v3 = pull_one<T, C>(fin, own_t, vtab, a, px[3], py[3], j);
+                    val = C(3) * v1 - C(3) * v2 + v3;
+                } else if (use == 1) {
+                    C v2 = pull_one<T, C>(fin, own_t, vtab, a, px[2], py[2], j);
+                    val = C(2) * v1 - v2;
+                } else {
+                    val = v1;
+                }
+                acc[j] += val;
+            }
+        }
+        C d[9];
+        if (npart == 0) {
+            feq_dev<C>((C)a.rho0, (C)a.rho0, (C)S.vx, (C)S.vy, d);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 9; ++j) d[j] = acc[j] / C(npart);
+        }
+        collide<C>(d, cp);
+        T* w0 = fout + (int64_t)y * a.pitch + x;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) w0[j * a.plane] = Sto<T>::st(d[j]);
+    }
+}
+
+// ------------------------------------------------------------------ misc
+__global__ void k_set_counters(int64_t* tctr, int64_t t, int* errflag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        tctr[0] = t;
+        tctr[1] = t;
+        *errflag = 0;
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,353 @@
+"""ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function of the header is exposed under the same name; ``Lattice``
+wraps a context whose device workspace and stream come from PyTorch.  All
+arithmetic of the time step, the forces and the fields runs in the HIP
+kernels of liblbm.so: there is no host fallback, and loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ESIZE, LBM_EDEVICE, LBM_ENUMERIC, LBM_ESTATE, LBM_EGEOM = 0, -1, -2, -3, -4, -5, -6
+LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
+LBM_CME, LBM_GME = 0, 1
+LBM_REFILL_A1, LBM_REFILL_A2, LBM_REFILL_A3 = 0, 1, 2
+LBM_DISC, LBM_BOX = 0, 1
+
+STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ESIZE", -3: "LBM_EDEVICE",
+                -4: "LBM_ENUMERIC", -5: "LBM_ESTATE", -6: "LBM_EGEOM"}
+DTYPES = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
+
+
+class lbm_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("walls_y", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("refill", ctypes.c_int32),
+                ("rho_w_local", ctypes.c_int32), ("rho0", ctypes.c_double),
+                ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("u0x", ctypes.c_double),
+                ("u0y", ctypes.c_double), ("wall_vx", ctypes.c_double),
+                ("wall_vy", ctypes.c_double)]
+
+
+class lbm_solid(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("moves", ctypes.c_int32), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("vx", ctypes.c_double), ("vy", ctypes.c_double)]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SIG = {
+    "lbm_abi_version": (_I32, []),
+    "lbm_workspace_bytes": (_I32, [ctypes.POINTER(lbm_grid), ctypes.POINTER(lbm_solid), _I32, _I64,
+                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_create": (_I32, [ctypes.POINTER(lbm_grid), ctypes.c_double, ctypes.POINTER(lbm_solid), _I32,
+                          _I64, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "lbm_step": (_I32, [_VP, _I64]),
+    "lbm_time": (_I64, [_VP]),
+    "lbm_force": (_I32, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_double)]),
+    "lbm_force_history": (_I32, [_VP, _I64, _I64, _VP]),
+    "lbm_fields": (_I32, [_VP, _VP, _VP, _VP, _I32, _VP]),
+    "lbm_init_fields": (_I32, [_VP, _VP, _VP, _VP, _I32]),
+    "lbm_populations": (_I32, [_VP, _VP]),
+    "lbm_link_forces": (_I32, [_VP, _VP, _I64, ctypes.POINTER(_I64)]),
+    "lbm_checkpoint_bytes": (_I32, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_save": (_I32, [_VP, _VP, ctypes.c_size_t]),
+    "lbm_load": (_I32, [_VP, _VP, ctypes.c_size_t]),
+    "lbm_profile": (_I32, [_VP, _I32]),
+    "lbm_profile_read": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "lbm_status_check": (_I32, [_VP]),
+    "lbm_destroy": (None, [_VP]),
+    "lbm_last_error": (ctypes.c_char_p, [_VP]),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load liblbm.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_1303_0625_amd.build.build_library()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIG.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIG)
+
+
+def _check(status, ctx=None):
+    if status != LBM_OK:
+        msg = load_library().lbm_last_error(ctx)
+        raise LBMError(status, msg.decode() if msg else "")
+
+
+# ---- thin wrappers with the header's names --------------------------------
+def lbm_abi_version() -> int:
+    return load_library().lbm_abi_version()
+
+
+def lbm_workspace_bytes(grid: lbm_grid, solids, history_steps: int) -> int:
+    arr, n = _solid_array(solids)
+    out = ctypes.c_size_t(0)
+    _check(load_library().lbm_workspace_bytes(ctypes.byref(grid), arr, n, history_steps,
+                                              ctypes.byref(out)))
+    return out.value
+
+
+def lbm_create(grid: lbm_grid, tau: float, solids, history_steps: int, d_workspace: int,
+               nbytes: int, stream: int):
+    arr, n = _solid_array(solids)
+    ctx = _VP()
+    _check(load_library().lbm_create(ctypes.byref(grid), tau, arr, n, history_steps, d_workspace,
+                                     nbytes, stream, ctypes.byref(ctx)))
+    return ctx
+
+
+def lbm_step(ctx, n: int) -> None:
+    _check(load_library().lbm_step(ctx, n), ctx)
+
+
+def lbm_time(ctx) -> int:
+    return load_library().lbm_time(ctx)
+
+
+def lbm_force(ctx, solid_id: int, scheme: int):
+    out = (ctypes.c_double * 3)()
+    _check(load_library().lbm_force(ctx, solid_id, scheme, out), ctx)
+    return list(out)
+
+
+def lbm_force_history(ctx, first: int, count: int, d_out: int) -> None:
+    _check(load_library().lbm_force_history(ctx, first, count, d_out), ctx)
+
+
+def lbm_fields(ctx, d_rho, d_ux, d_uy, out_dtype: int, d_owner) -> None:
+    _check(load_library().lbm_fields(ctx, d_rho, d_ux, d_uy, out_dtype, d_owner), ctx)
+
+
+def lbm_init_fields(ctx, d_rho, d_ux, d_uy, in_dtype: int) -> None:
+    _check(load_library().lbm_init_fields(ctx, d_rho, d_ux, d_uy, in_dtype), ctx)
+
+
+def lbm_populations(ctx, d_out) -> None:
+    _check(load_library().lbm_populations(ctx, d_out), ctx)
+
+
+def lbm_link_forces(ctx, d_out, max_records: int) -> int:
+    n = _I64(0)
+    _check(load_library().lbm_link_forces(ctx, d_out, max_records, ctypes.byref(n)), ctx)
+    return n.value
+
+
+def lbm_checkpoint_bytes(ctx) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().lbm_checkpoint_bytes(ctx, ctypes.byref(out)), ctx)
+    return out.value
+
+
+def lbm_save(ctx, d_dst, nbytes: int) -> None:
+    _check(load_library().lbm_save(ctx, d_dst, nbytes), ctx)
+
+
+def lbm_load(ctx, d_src, nbytes: int) -> None:
+    _check(load_library().lbm_load(ctx, d_src, nbytes), ctx)
+
+
+def lbm_profile(ctx, enable: bool) -> None:
+    _check(load_library().lbm_profile(ctx, int(bool(enable))), ctx)
+
+
+def lbm_profile_read(ctx):
+    ms = ctypes.c_double(0.0)
+    n = _I64(0)
+    _check(load_library().lbm_profile_read(ctx, ctypes.byref(ms), ctypes.byref(n)), ctx)
+    return ms.value, n.value
+
+
+def lbm_status_check(ctx) -> None:
+    _check(load_library().lbm_status_check(ctx), ctx)
+
+
+def lbm_destroy(ctx) -> None:
+    load_library().lbm_destroy(ctx)
+
+
+def lbm_last_error(ctx=None) -> str:
+    m = load_library().lbm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+# ---- helpers ---------------------------------------------------------------
+def _solid_array(solids):
+    solids = list(solids)
+    n = len(solids)
+    arr = (lbm_solid * max(n, 1))()
+    for k, b in enumerate(solids):
+        if isinstance(b, lbm_solid):
+            arr[k] = b
+            continue
+        kind = b.get("kind", "disc")
+        box = kind in ("box", LBM_BOX)
+        arr[k].shape = LBM_BOX if box else LBM_DISC
+        arr[k].moves = int(bool(b.get("moves", False)))
+        arr[k].cx = float(b["cx"])
+        arr[k].cy = float(b["cy"])
+        arr[k].a = float(b["hx"] if box else b["r"])
+        arr[k].b = float(b.get("hy", 0.0)) if box else 0.0
+        arr[k].vx = float(b.get("vx", 0.0))
+        arr[k].vy = float(b.get("vy", 0.0))
+    return arr, n
+
+
+def make_grid(case: dict, dtype="f64") -> lbm_grid:
+    g = lbm_grid()
+    g.nx, g.ny = case["nx"], case["ny"]
+    g.walls_y = int(case.get("walls_y", False))
+    g.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    g.refill = int(case.get("refill", 0))
+    g.rho_w_local = 0
+    g.rho0 = float(case.get("rho0", 1.0))
+    g.gx, g.gy = float(case.get("gx", 0.0)), float(case.get("gy", 0.0))
+    u0 = case.get("u0", (0.0, 0.0))
+    g.u0x, g.u0y = float(u0[0]), float(u0[1])
+    wv = case.get("wall_v", (0.0, 0.0))
+    g.wall_vx, g.wall_vy = float(wv[0]), float(wv[1])
+    return g
+
+
+class Lattice:
+    """One simulation on the current CUDA (HIP) device.
+
+    The workspace is a torch uint8 tensor; kernels are enqueued on torch's
+    current stream at creation time.
+    """
+
+    def __init__(self, case: dict, dtype="f64", history_steps=None, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.case = case
+        self.dtype = dtype
+        self.nx, self.ny = case["nx"], case["ny"]
+        self.n_solids = len(case.get("bodies", ()))
+        self.grid = make_grid(case, dtype)
+        if history_steps is None:
+            history_steps = max(1, int(case.get("steps", 0)) or 1024)
+        self.history_steps = int(history_steps)
+        solids = case.get("bodies", ())
+        nbytes = lbm_workspace_bytes(self.grid, solids, self.history_steps)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.ctx = lbm_create(self.grid, float(case["tau"]), solids, self.history_steps,
+                              self._ws_ptr, nbytes, self.stream.cuda_stream)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                self.stream.synchronize()
+            except Exception:
+                pass
+            lbm_destroy(ctx)
+            self.ctx = None
+
+    @property
+    def t(self) -> int:
+        return lbm_time(self.ctx)
+
+    def step(self, n: int = 1) -> None:
+        lbm_step(self.ctx, int(n))
+
+    def force(self, solid_id: int, scheme: int):
+        return lbm_force(self.ctx, solid_id, scheme)
+
+    def force_history(self, first=0, count=None):
+        """float64 tensor [count][n_solids+1][6] (CME Fx Fy Tz, GME Fx Fy Tz)."""
+        t = self.t
+        if count is None:
+            count = t - first
+        out = self.torch.empty((count, self.n_solids + 1, 6), dtype=self.torch.float64,
+                               device=self.workspace.device)
+        lbm_force_history(self.ctx, first, count, out.data_ptr())
+        return out
+
+    def fields(self, out_dtype="f64"):
+        tdt = self.torch.float64 if out_dtype == "f64" else self.torch.float32
+        shp = (self.ny, self.nx)
+        dev = self.workspace.device
+        rho = self.torch.empty(shp, dtype=tdt, device=dev)
+        ux = self.torch.empty(shp, dtype=tdt, device=dev)
+        uy = self.torch.empty(shp, dtype=tdt, device=dev)
+        own = self.torch.empty(shp, dtype=self.torch.uint8, device=dev)
+        lbm_fields(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), DTYPES[out_dtype],
+                   own.data_ptr())
+        return rho, ux, uy, own
+
+    def init_fields(self, rho, ux, uy):
+        dt = LBM_F64 if rho.dtype == self.torch.float64 else LBM_F32
+        rho, ux, uy = (a.contiguous() for a in (rho, ux, uy))
+        lbm_init_fields(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), dt)
+        self._keep = (rho, ux, uy)
+
+    def populations(self):
+        out = self.torch.empty((9, self.ny, self.nx), dtype=self.torch.float64,
+                               device=self.workspace.device)
+        lbm_populations(self.ctx, out.data_ptr())
+        return out
+
+    def link_forces(self):
+        """float64 tensor [n_links][8] of the links the next step evaluates."""
+        lib = load_library()
+        n = _I64(0)
+        st = lib.lbm_link_forces(self.ctx, None, 0, ctypes.byref(n))
+        if st not in (LBM_OK, LBM_ESIZE):
+            _check(st, self.ctx)
+        out = self.torch.empty((max(n.value, 1), 8), dtype=self.torch.float64,
+                               device=self.workspace.device)
+        got = lbm_link_forces(self.ctx, out.data_ptr(), out.shape[0])
+        return out[:got]
+
+    def checkpoint_bytes(self) -> int:
+        return lbm_checkpoint_bytes(self.ctx)
+
+    def save(self):
+        nb = self.checkpoint_bytes()
+        buf = self.torch.empty(nb, dtype=self.torch.uint8, device=self.workspace.device)
+        lbm_save(self.ctx, buf.data_ptr(), nb)
+        return buf
+
+    def load(self, buf) -> None:
+        lbm_load(self.ctx, buf.data_ptr(), buf.numel())
+
+    def check(self) -> None:
+        lbm_status_check(self.ctx)
+
+    def profile(self, enable: bool = True) -> None:
+        lbm_profile(self.ctx, enable)
+
+    def profile_read(self):
+        """(summed ms, launches) of the lattice-update kernel since profile()."""
+        return lbm_profile_read(self.ctx)

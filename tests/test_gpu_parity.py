@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Bars: FP64 storage within 1e-12 relative on fields and 1e-10 on forces; FP32
+storage within 1e-5 relative on drag.  Fields are compared per field over
+fluid nodes, relative to the field's largest magnitude; forces relative to the
+largest magnitude of that component over the compared history.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lbm_cases as lc
+from tests.helpers import oracle_history, oracle_sim, rel_field_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lbm_mod(torch_mod):
+    import paper_1303_0625_amd as pkg
+
+    pkg.lbm.load_library()
+    return pkg
+
+
+def run_pair(oracle_mod, lbm_mod, case, steps, dtype="f64", chunks=1):
+    _say(f"{case['name']} {case['nx']}x{case['ny']} steps={steps} dtype={dtype}")
+    lat = lbm_mod.Lattice(case, dtype=dtype, history_steps=max(steps, 1))
+    osim = oracle_sim(oracle_mod, case)
+    per = steps // chunks
+    for _ in range(chunks):
+        lat.step(per)
+        osim.step(per)
+    return lat, osim
+
+
+def compare_fields(lat, osim, tol):
+    rho, ux, uy, own = (a.cpu().numpy() for a in lat.fields("f64"))
+    orho, oux, ouy, oown = osim.fields()
+    assert (own.astype(np.int32) == oown).all(), "owner maps differ"
+    m = oown == 0
+    e = (rel_field_err(rho, orho, m), rel_field_err(ux, oux, m), rel_field_err(uy, ouy, m))
+    _say(f"field rel err rho={e[0]:.3e} ux={e[1]:.3e} uy={e[2]:.3e}")
+    assert max(e) <= tol, e
+    return e
+
+
+def compare_forces(lat, osim, nb, tol, solids=None, comps=(0, 1, 3, 4), steps=None):
+    h = lat.force_history().cpu().numpy()
+    oh = oracle_history(osim, nb)
+    assert h.shape == oh.shape
+    solids = range(nb + 1) if solids is None else solids
+    worst = 0.0
+    for s in solids:
+        for c in comps:
+            scale = np.abs(oh[:, s, c]).max()
+            if scale == 0:
+                assert np.abs(h[:, s, c]).max() <= 1e-14
+                continue
+            err = np.abs(h[:, s, c] - oh[:, s, c]).max() / scale
+            worst = max(worst, err)
+    _say(f"force rel err (history max) = {worst:.3e}")
+    assert worst <= tol
+    return worst
+
+
+# --------------------------------------------------------------- FP64 parity
+@pytest.mark.parametrize("frame", ["rest", "moving", "translating"])
+def test_channel_cylinder_f64(oracle_mod, lbm_mod, frame):
+    """Driven 128x64 channel with a centred D=10 cylinder, 5000 steps, FP64,
+    at rest and seen from a frame moving at -0.05 (geometry fixed, or
+    translating with refill)."""
+    c = lc.channel_cylinder(frame)
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, c["steps"], chunks=5)
+    compare_fields(lat, osim, 1e-12)
+    compare_forces(lat, osim, 1, 1e-10, comps=(0, 1, 2, 3, 4, 5))
+
+
+def test_uniform_and_channel_invariants_f64(oracle_mod, lbm_mod):
+    """Uniform equilibrium stays put; obstacle-free channel matches the oracle."""
+    c = lc.make_case(64, 32, 0.7, u0=(0.05, 0.02), name="uniform")
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 100)
+    f = lat.populations().cpu().numpy()
+    import oracle
+
+    fe = oracle.collide_node(oracle.feq(1.0, 0.05, 0.02), 0.7)
+    assert np.abs(f - fe[:, None, None]).max() <= 1e-15
+    c = lc.channel_empty("moving", nx=16, ny=32)
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 500)
+    compare_fields(lat, osim, 1e-12)
+
+
+def test_moving_bodies_f64(oracle_mod, lbm_mod):
+    """256x128 channel, two translating and two fixed cylinders, refill A1,
+    2000 steps (covered and newborn nodes every few steps)."""
+    bodies = [lc.disc(60.3, 30.2, 9.1, vx=0.043, moves=True),
+              lc.disc(180.7, 95.6, 7.4, vx=-0.031, vy=0.004, moves=True),
+              lc.disc(130.2, 64.5, 8.3),
+              lc.disc(30.5, 100.1, 6.6, vx=0.01)]
+    for refill in (0, 1, 2):
+        c = lc.make_case(256, 128, 0.7, walls_y=True, gx=2e-6, refill=refill, bodies=bodies,
+                         name=f"movers_refill{refill}")
+        steps = 2000 if refill == 0 else 400
+        lat, osim = run_pair(oracle_mod, lbm_mod, c, steps, chunks=4)
+        compare_fields(lat, osim, 1e-12)
+        compare_forces(lat, osim, 4, 1e-10, comps=(0, 1, 2, 3, 4, 5))
+
+
+def test_thin_plate_link_forces_gpu(oracle_mod, lbm_mod):
+    """Fig. 1(b) on the GPU: one-sided GME pressure rho0 L/3 in every frame,
+    CME rho0 L (1/3 + V^2); per-link records match the oracle."""
+    L = 16
+    for V in (0.0, 0.05, 0.1):
+        plate = lc.box(8.0, 5 + (L - 1) / 2, 0.0, (L - 1) / 2, vx=V)
+        c = lc.make_case(16, L + 10, 0.6, u0=(V, 0.0), bodies=[plate], name=f"plate_V{V}")
+        lat, osim = run_pair(oracle_mod, lbm_mod, c, 3)
+        rec = lat.link_forces().cpu().numpy()
+        osim.step(1)  # oracle records of step 3 = links of the GPU's current state
+        orec = osim.links()
+        key = lambda r: (r[:, 3] * 1e9 + r[:, 1] * 1e5 + r[:, 0] * 10 + r[:, 2])
+        rec = rec[np.argsort(key(rec))]
+        orec = orec[np.argsort(key(orec))]
+        assert rec.shape == orec.shape
+        np.testing.assert_array_equal(rec[:, :4], orec[:, :4])
+        assert np.abs(rec[:, 4:] - orec[:, 4:]).max() <= 1e-15
+        left = rec[(rec[:, 3] == 1) & (rec[:, 0] == 7)]
+        assert abs(left[:, 6].sum() - L / 3) <= 1e-13 * L
+        assert abs(left[:, 4].sum() - L * (1 / 3 + V * V)) <= 1e-13 * L
+
+
+def test_poiseuille_gpu_f64(lbm_mod):
+    """Exact discrete Poiseuille profile on the GPU FP64 path."""
+    tau, ny, g = 0.8, 16, 1e-5
+    c = lc.make_case(64, ny, tau, walls_y=True, gx=g, name="poiseuille")
+    lat = lbm_mod.Lattice(c, dtype="f64", history_steps=16)
+    lat.step(30000)
+    rho, ux, uy, own = (a.cpu().numpy() for a in lat.fields("f64"))
+    nu = (tau - 0.5) / 3
+    y = np.arange(ny)
+    slip = g * (4 * (2 * tau - 1) ** 2 - 3) / (4 * (2 * tau - 1))
+    exact = g / (2 * nu) * ((ny / 2) ** 2 - (y - (ny - 1) / 2) ** 2) + slip
+    err = np.abs(ux - exact[:, None]).max() / exact.max()
+    _say(f"poiseuille rel err {err:.3e}")
+    assert err <= 1e-10
+
+
+# --------------------------------------------------------------- FP32
+def test_channel_cylinder_f32_drag(oracle_mod, lbm_mod):
+    """FP32 offset storage: drag history within 1e-5 of the FP64 oracle."""
+    c = lc.channel_cylinder("rest")
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, c["steps"], dtype="f32")
+    h = lat.force_history().cpu().numpy()
+    oh = oracle_history(osim, 1)
+    for comp in (0, 3):
+        err = np.abs(h[-1, 1, comp] - oh[-1, 1, comp]) / abs(oh[-1, 1, comp])
+        _say(f"f32 final drag rel err comp{comp} = {err:.3e}")
+        assert err <= 1e-5
+    rel_hist = np.abs(h[100:, 1, 0] - oh[100:, 1, 0]).max() / np.abs(oh[100:, 1, 0]).max()
+    _say(f"f32 drag history rel err = {rel_hist:.3e}")
+    assert rel_hist <= 1e-5
+
+
+def test_moving_bodies_f32_drag(oracle_mod, lbm_mod):
+    bodies = [lc.disc(60.3, 30.2, 9.1, vx=0.043, moves=True),
+              lc.disc(130.2, 64.5, 8.3)]
+    c = lc.make_case(256, 128, 0.7, walls_y=True, gx=2e-6, bodies=bodies, name="movers_f32")
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 1000, dtype="f32")
+    h = lat.force_history().cpu().numpy()
+    oh = oracle_history(osim, 2)
+    for s in (1, 2):
+        scale = np.abs(oh[-200:, s, 0]).max()
+        err = np.abs(h[-200:, s, 0] - oh[-200:, s, 0]).max() / scale
+        _say(f"f32 mover drag rel err solid {s} = {err:.3e}")
+        assert err <= 1e-5
+
+
+# --------------------------------------------------------------- determinism / checkpoint
+def test_determinism_and_checkpoint(lbm_mod):
+    bodies = [lc.disc(60.3, 30.2, 9.1, vx=0.043, moves=True), lc.disc(130.2, 64.5, 8.3)]
+    c = lc.make_case(256, 128, 0.7, walls_y=True, gx=2e-6, bodies=bodies, name="determinism")
+    _say("determinism")
+    a = lbm_mod.Lattice(c, dtype="f32", history_steps=600)
+    b = lbm_mod.Lattice(c, dtype="f32", history_steps=600)
+    a.step(300)
+    ck = a.save()
+    a.step(300)
+    b.step(600)
+    pa, pb = a.populations(), b.populations()
+    assert bool((pa == pb).all())
+    assert bool((a.force_history() == b.force_history()).all())
+    # resume from the checkpoint in a fresh context
+    r = lbm_mod.Lattice(c, dtype="f32", history_steps=600)
+    r.load(ck)
+    assert r.t == 300
+    r.step(300)
+    assert bool((r.populations() == pa).all())
