@@ -3,8 +3,9 @@
 // Lattice: D2Q9 velocity set in the order of Sec. III.C of Wen et al.
 // (arXiv:1303.0625); weights 4/9, 1/9, 1/36.  Populations are stored as
 // deviations d_i = f_i - w_i rho0 from the rest equilibrium, in one of four
-// storage types; collision arithmetic runs in double (double storage) or float
-// (float, half and bfloat16 storage).
+// storage types; collision arithmetic runs in double (double and float
+// storage) or float (half and bfloat16 storage, whose error is set by the
+// 11- and 8-bit significands, not by the arithmetic).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,11 +44,17 @@ struct Sto<double> {
     __device__ static inline double ld(double v) { return v; }
     __device__ static inline double st(double c) { return c; }
 };
+// FP32 storage collides in double: the moment sums and the equilibrium are
+// formed from deviations ~1e-4 whose float partial sums lose digits in a way
+// that accumulates over thousands of steps (~1e-5 relative drag drift on the
+// driven-cylinder channel, against ~1e-7 with one rounding per stored value).
+// Double FMA issues at the non-packed FP32 rate on gfx950, so the
+// bandwidth-bound update does not slow down.
 template <>
 struct Sto<float> {
-    using C = float;
-    __device__ static inline float ld(float v) { return v; }
-    __device__ static inline float st(float c) { return c; }
+    using C = double;
+    __device__ static inline double ld(float v) { return (double)v; }
+    __device__ static inline float st(double c) { return (float)c; }
 };
 template <>
 struct Sto<_Float16> {

@@ -1,7 +1,13 @@
 """Shared test helpers: build oracle and GPU runs from one seeded case and
-compare them.  Comparisons follow one rule: per field, max |gpu - oracle| over
-fluid nodes divided by max |oracle| over fluid nodes (density is compared
-relative to its own size, ~rho0)."""
+compare them.
+
+Comparison rules.  Density: max |gpu - oracle| over fluid nodes relative to
+max |rho|.  Velocity: max over both components of |gpu - oracle| relative to
+the largest velocity magnitude (a component that is roundoff in a symmetric
+flow is not compared with itself).  Force of a solid: relative to
+max(largest force magnitude of that solid over the history, 1e-3 x the
+largest body force in the case), torque additionally times the body's
+half-size."""
 from __future__ import annotations
 
 import numpy as np
@@ -38,3 +44,42 @@ def oracle_history(osim, nb):
             h[st, s, :3] = osim.force(s, 0, st)
             h[st, s, 3:] = osim.force(s, 1, st)
     return h
+
+
+def field_errors(gpu_fields, oracle_fields):
+    rho, ux, uy, own = gpu_fields
+    orho, oux, ouy, oown = oracle_fields
+    assert (np.asarray(own).astype(np.int32) == oown).all(), "owner maps differ"
+    m = oown == 0
+    e_rho = float(np.abs(rho - orho)[m].max() / np.abs(orho[m]).max())
+    umag = np.sqrt(oux ** 2 + ouy ** 2)[m].max()
+    du = max(np.abs(ux - oux)[m].max(), np.abs(uy - ouy)[m].max())
+    e_u = float(du / umag) if umag > 0 else float(du)
+    return e_rho, e_u
+
+
+def force_errors(h, oh, case):
+    """Worst relative force/torque error and where (solid, component)."""
+    nb = h.shape[1] - 1
+    body_scale = [np.abs(oh[:, s, [0, 1, 3, 4]]).max() for s in range(nb + 1)]
+    floor = 1e-3 * max(body_scale[1:]) if nb > 0 else 0.0
+    worst, where = 0.0, None
+    for s in range(nb + 1):
+        fscale = max(body_scale[s], floor)
+        if fscale == 0:
+            err = float(np.abs(h[:, s, :]).max())
+            if err > worst:
+                worst, where = err, (s, "abs")
+            continue
+        size = 1.0
+        if s > 0:
+            b = case["bodies"][s - 1]
+            size = b.get("r", max(b.get("hx", 0.0), b.get("hy", 0.0), 1.0))
+        for c in range(6):
+            if s == 0 and c in (2, 5):
+                continue
+            scale = fscale * (size if c in (2, 5) else 1.0)
+            err = float(np.abs(h[:, s, c] - oh[:, s, c]).max() / scale)
+            if err > worst:
+                worst, where = err, (s, c)
+    return worst, where

@@ -2,9 +2,9 @@
 same seeded inputs.
 
 Bars: FP64 storage within 1e-12 relative on fields and 1e-10 on forces; FP32
-storage within 1e-5 relative on drag.  Fields are compared per field over
-fluid nodes, relative to the field's largest magnitude; forces relative to the
-largest magnitude of that component over the compared history.
+storage within 1e-5 relative on drag.  The comparison rules are those of
+tests/helpers.py (density relative to rho, velocity relative to the largest
+speed, forces relative to the solid's force scale).
 """
 import sys
 
@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import lbm_cases as lc
-from tests.helpers import oracle_history, oracle_sim, rel_field_err
+from tests.helpers import field_errors, force_errors, oracle_history, oracle_sim
 
 pytestmark = pytest.mark.gpu
 
@@ -51,31 +51,18 @@ def run_pair(oracle_mod, lbm_mod, case, steps, dtype="f64", chunks=1):
 
 
 def compare_fields(lat, osim, tol):
-    rho, ux, uy, own = (a.cpu().numpy() for a in lat.fields("f64"))
-    orho, oux, ouy, oown = osim.fields()
-    assert (own.astype(np.int32) == oown).all(), "owner maps differ"
-    m = oown == 0
-    e = (rel_field_err(rho, orho, m), rel_field_err(ux, oux, m), rel_field_err(uy, ouy, m))
-    _say(f"field rel err rho={e[0]:.3e} ux={e[1]:.3e} uy={e[2]:.3e}")
+    e = field_errors([a.cpu().numpy() for a in lat.fields("f64")], osim.fields())
+    _say(f"field rel err rho={e[0]:.3e} u={e[1]:.3e}")
     assert max(e) <= tol, e
     return e
 
 
-def compare_forces(lat, osim, nb, tol, solids=None, comps=(0, 1, 3, 4), steps=None):
+def compare_forces(lat, osim, case, tol):
     h = lat.force_history().cpu().numpy()
-    oh = oracle_history(osim, nb)
+    oh = oracle_history(osim, len(case["bodies"]))
     assert h.shape == oh.shape
-    solids = range(nb + 1) if solids is None else solids
-    worst = 0.0
-    for s in solids:
-        for c in comps:
-            scale = np.abs(oh[:, s, c]).max()
-            if scale == 0:
-                assert np.abs(h[:, s, c]).max() <= 1e-14
-                continue
-            err = np.abs(h[:, s, c] - oh[:, s, c]).max() / scale
-            worst = max(worst, err)
-    _say(f"force rel err (history max) = {worst:.3e}")
+    worst, where = force_errors(h, oh, case)
+    _say(f"force rel err (history max) = {worst:.3e} at solid/comp {where}")
     assert worst <= tol
     return worst
 
@@ -89,7 +76,7 @@ def test_channel_cylinder_f64(oracle_mod, lbm_mod, frame):
     c = lc.channel_cylinder(frame)
     lat, osim = run_pair(oracle_mod, lbm_mod, c, c["steps"], chunks=5)
     compare_fields(lat, osim, 1e-12)
-    compare_forces(lat, osim, 1, 1e-10, comps=(0, 1, 2, 3, 4, 5))
+    compare_forces(lat, osim, c, 1e-10)
 
 
 def test_uniform_and_channel_invariants_f64(oracle_mod, lbm_mod):
@@ -119,7 +106,7 @@ def test_moving_bodies_f64(oracle_mod, lbm_mod):
         steps = 2000 if refill == 0 else 400
         lat, osim = run_pair(oracle_mod, lbm_mod, c, steps, chunks=4)
         compare_fields(lat, osim, 1e-12)
-        compare_forces(lat, osim, 4, 1e-10, comps=(0, 1, 2, 3, 4, 5))
+        compare_forces(lat, osim, c, 1e-10)
 
 
 def test_thin_plate_link_forces_gpu(oracle_mod, lbm_mod):
