@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import lbm_cases as lc
-from tests.helpers import field_errors, force_errors, oracle_history, oracle_sim, rel_l2
+from tests.helpers import field_errors, force_errors, link_load, oracle_history, oracle_sim, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -49,9 +49,9 @@ def test_moving_cylinders_fullsize_f64_vs_oracle(oracle_mod, pkg):
     assert max(e) <= 1e-12
     h = lat.force_history().cpu().numpy()
     oh = oracle_history(o, len(c["bodies"]))
-    worst, where = force_errors(h, oh, c)
-    _say(f"force rel err {worst:.3e} at {where}")
-    assert worst <= 1e-10
+    norm, rel, where = force_errors(h, oh, c, 1e-10, link_load(o, len(c["bodies"])))
+    _say(f"force rel err {rel:.3e}; normalised {norm:.3f} at {where}")
+    assert norm <= 1.0
 
 
 def test_moving_cylinders_fullsize_f32_vs_f64(pkg):

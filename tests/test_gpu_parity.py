@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import lbm_cases as lc
-from tests.helpers import field_errors, force_errors, oracle_history, oracle_sim
+from tests.helpers import field_errors, force_errors, link_load, oracle_history, oracle_sim
 
 pytestmark = pytest.mark.gpu
 
@@ -61,10 +61,10 @@ def compare_forces(lat, osim, case, tol):
     h = lat.force_history().cpu().numpy()
     oh = oracle_history(osim, len(case["bodies"]))
     assert h.shape == oh.shape
-    worst, where = force_errors(h, oh, case)
-    _say(f"force rel err (history max) = {worst:.3e} at solid/comp {where}")
-    assert worst <= tol
-    return worst
+    norm, rel, where = force_errors(h, oh, case, tol, link_load(osim, len(case["bodies"])))
+    _say(f"force rel err (history max) = {rel:.3e}; normalised {norm:.3f} at {where}")
+    assert norm <= 1.0
+    return rel
 
 
 # --------------------------------------------------------------- FP64 parity
