@@ -1,6 +1,7 @@
 // lbm_capi.hip -- host side of the C ABI declared in include/lbm.h: argument
 // validation, workspace layout inside the caller's device buffer, and the
 // per-step launch sequence on the caller's stream.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,10 +44,12 @@ size_t dtype_size(int dt) {
 struct Layout {
     int pitch, opitch;
     int64_t plane;
-    size_t f[2], own[2], links, seg_off, seg_cap, seg_cnt, rec_off, sol, vtab, movers, all, hist,
-        tctr, err, total;
+    size_t f[2], own[2], links[2], seg_off, seg_cap, seg_cnt[2], rec_off, sol, vtab, movers, all,
+        chunk_solid, chunk_start, solid_chunk0, partial, ticket, hist, tctr, err, total;
     int64_t link_total;
     int n_movers;
+    int nchunks;
+    int box_bytes;  // LDS byte map per translating body (k_move)
 };
 
 // Conservative link capacity of one body: every fluid node adjacent to a
@@ -77,14 +80,37 @@ bool make_layout(const lbm_grid& g, const lbm_solid* solids, int n, int64_t hist
         off = align256(off + (size_t)g.ny * L.opitch);
     }
     int64_t tot = g.walls_y ? 6LL * g.nx : 0;
-    for (int k = 0; k < n; ++k) tot += body_link_cap(solids[k], g.nx, g.ny);
+    int nch = std::max<int64_t>(1, (tot + kForceChunk - 1) / kForceChunk);
+    L.box_bytes = 16;
+    for (int k = 0; k < n; ++k) {
+        int cap = body_link_cap(solids[k], g.nx, g.ny);
+        tot += cap;
+        nch += std::max(1, (cap + kForceChunk - 1) / kForceChunk);
+        if (solids[k].moves) {
+            double hx = solids[k].a, hy = solids[k].shape == LBM_DISC ? solids[k].a : solids[k].b;
+            int w = (int)std::ceil(2 * hx + 0.6) + 2 * kBoxMargin + 4;
+            int h = (int)std::ceil(2 * hy + 0.6) + 2 * kBoxMargin + 4;
+            L.box_bytes = std::max(L.box_bytes, (w * h + 15) / 16 * 16);
+        }
+    }
     L.link_total = tot;
-    L.links = off;
-    off = align256(off + 4 * (size_t)std::max<int64_t>(tot, 1));
+    L.nchunks = nch;
+    for (int k = 0; k < 2; ++k) {
+        L.links[k] = off;
+        off = align256(off + 4 * (size_t)std::max<int64_t>(tot, 1));
+    }
     const size_t ns = (size_t)n + 1;
     L.seg_off = off; off = align256(off + 4 * ns);
     L.seg_cap = off; off = align256(off + 4 * ns);
-    L.seg_cnt = off; off = align256(off + 4 * ns);
+    for (int k = 0; k < 2; ++k) {
+        L.seg_cnt[k] = off;
+        off = align256(off + 4 * ns);
+    }
+    L.chunk_solid = off; off = align256(off + 4 * (size_t)nch);
+    L.chunk_start = off; off = align256(off + 4 * (size_t)nch);
+    L.solid_chunk0 = off; off = align256(off + 4 * (ns + 1));
+    L.partial = off; off = align256(off + 48 * (size_t)nch);
+    L.ticket = off; off = align256(off + 4);
     L.rec_off = off; off = align256(off + 4 * ns);
     L.sol = off; off = align256(off + sizeof(SolidDev) * ns);
     L.vtab = off; off = align256(off + 16 * ns);
@@ -148,11 +174,13 @@ const char* validate(const lbm_grid* g, double tau, const lbm_solid* s, int n, c
         }
     }
     for (int p = 0; p < n; ++p)
-        for (int q = p + 1; q < n; ++q)
-            if (body_gap(s[p], s[p].cx, s[p].cy, s[q], s[q].cx, s[q].cy, *g) < 2.0) {
-                snprintf(buf, 512, "solids %d and %d are closer than 2 nodes", p + 1, q + 1);
+        for (int q = p + 1; q < n; ++q) {
+            const double need = (s[p].moves && s[q].moves) ? (double)kMoverGap : 2.0;
+            if (body_gap(s[p], s[p].cx, s[p].cy, s[q], s[q].cx, s[q].cy, *g) < need) {
+                snprintf(buf, 512, "solids %d and %d are closer than %g nodes", p + 1, q + 1, need);
                 return buf;
             }
+        }
     return nullptr;
 }
 
@@ -220,6 +248,7 @@ ForceArgs force_args(const lbm_ctx* c) {
     a.rho0 = c->g.rho0;
     a.hist_cap = c->hist_cap;
     a.nsol = c->n + 1;
+    a.nchunks = c->L.nchunks;
     return a;
 }
 
@@ -244,7 +273,9 @@ uint8_t* own_ptr(lbm_ctx* c, int k) {
     return wsp<uint8_t>(c, c->L.own[k]);
 }
 
-// Enqueue one time step at parity p = t & 1 for storage type T.
+// Enqueue one time step at parity p = t & 1 for storage type T: forces on
+// G_t, translating bodies (G_{t+1}, links, refill), fused update.  The three
+// kernels read only step-t data and write disjoint outputs.
 template <typename T>
 lbm_status enqueue_step(lbm_ctx* c) {
     using C = typename Sto<T>::C;
@@ -256,32 +287,30 @@ lbm_status enqueue_step(lbm_ctx* c) {
     int64_t* tctr = wsp<int64_t>(c, c->L.tctr);
     int* errf = wsp<int>(c, c->L.err);
     const SolidDev* sol = wsp<SolidDev>(c, c->L.sol);
-    k_force<T><<<c->n + 1, kBlock, 0, c->stream>>>(fin, wsp<uint32_t>(c, c->L.links),
-                                                   wsp<int>(c, c->L.seg_cnt),
-                                                   wsp<int>(c, c->L.seg_off), sol,
-                                                   wsp<double>(c, c->L.hist), tctr, p,
-                                                   force_args(c));
-    LinkArgs la{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y};
+    k_force<T><<<c->L.nchunks, kBlock, 0, c->stream>>>(
+        fin, wsp<uint32_t>(c, c->L.links[p]), wsp<int>(c, c->L.seg_cnt[p]), wsp<int>(c, c->L.seg_off),
+        wsp<int>(c, c->L.chunk_solid), wsp<int>(c, c->L.chunk_start), wsp<int>(c, c->L.solid_chunk0),
+        sol, wsp<double>(c, c->L.partial), wsp<unsigned int>(c, c->L.ticket),
+        wsp<double>(c, c->L.hist), tctr, p, force_args(c));
+    CollideParams<C> cp = collide_params<C>(c);
     if (c->L.n_movers > 0) {
-        k_move<<<c->L.n_movers, kBlock, 0, c->stream>>>(
-            own_n, wsp<uint32_t>(c, c->L.links), wsp<int>(c, c->L.seg_cnt),
-            wsp<int>(c, c->L.seg_off), wsp<int>(c, c->L.seg_cap), sol, wsp<int>(c, c->L.movers),
-            tctr, p, la, errf);
+        MoveArgs ma{c->g.nx, c->g.ny, c->L.pitch, c->L.opitch, c->g.walls_y, c->L.plane, c->g.rho0,
+                    c->g.refill, c->L.box_bytes};
+        k_move<T><<<c->L.n_movers, kBlock, 2 * c->L.box_bytes, c->stream>>>(
+            fin, fout, own_t, own_n, wsp<uint32_t>(c, c->L.links[p ^ 1]),
+            wsp<int>(c, c->L.seg_cnt[p ^ 1]), wsp<int>(c, c->L.seg_off), wsp<int>(c, c->L.seg_cap),
+            sol, wsp<double>(c, c->L.vtab), wsp<int>(c, c->L.movers), tctr, p, ma, cp, errf);
     }
     StepArgs sa = step_args(c);
-    CollideParams<C> cp = collide_params<C>(c);
     const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
-    if (timed) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
-    k_step<T><<<(unsigned)node_blocks(c), kBlock, 0, c->stream>>>(fin, fout, own_t, own_n,
-                                                                wsp<double>(c, c->L.vtab), sa, cp);
     if (timed) {
-        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        hipExtLaunchKernelGGL(k_step<T>, dim3((unsigned)node_blocks(c)), dim3(kBlock), 0, c->stream,
+                              c->ev[c->ev_used], c->ev[c->ev_used + 1], 0, fin, fout, own_t,
+                              (const double*)wsp<double>(c, c->L.vtab), sa, cp);
         c->ev_used += 2;
-    }
-    if (c->L.n_movers > 0) {
-        k_refill<T><<<c->L.n_movers, kBlock, 0, c->stream>>>(
-            fin, fout, own_t, own_n, wsp<double>(c, c->L.vtab), sol, wsp<int>(c, c->L.movers),
-            tctr, p, sa, cp, c->g.refill);
+    } else {
+        k_step<T><<<(unsigned)node_blocks(c), kBlock, 0, c->stream>>>(fin, fout, own_t,
+                                                                    wsp<double>(c, c->L.vtab), sa, cp);
     }
     c->t += 1;
     return LBM_OK;
@@ -343,9 +372,10 @@ const char* check_paths(const lbm_ctx* c, int64_t t0, int64_t t1, char* buf) {
                 double px = S[p].cx + (double)t * S[p].vx, py = S[p].cy + (double)t * S[p].vy;
                 double qx = S[q].moves ? S[q].cx + (double)t * S[q].vx : S[q].cx;
                 double qy = S[q].moves ? S[q].cy + (double)t * S[q].vy : S[q].cy;
-                if (body_gap(S[p], px, py, S[q], qx, qy, g) < 2.0) {
-                    snprintf(buf, 512, "solids %d and %d come closer than 2 nodes at step %lld", p + 1,
-                             q + 1, (long long)t);
+                const double need = S[q].moves ? (double)kMoverGap : 2.0;
+                if (body_gap(S[p], px, py, S[q], qx, qy, g) < need) {
+                    snprintf(buf, 512, "solids %d and %d come closer than %g nodes at step %lld", p + 1,
+                             q + 1, need, (long long)t);
                     return buf;
                 }
                 if (t == t1) break;
@@ -473,6 +503,23 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
         off += c->seg_cap[k + 1];
     }
     c->link_cap_total = off;
+    // force chunks: each solid's segment split into kForceChunk-link pieces
+    // (at least one per solid, so the final reduction always runs)
+    std::vector<int> chunk_solid, chunk_start, solid_chunk0(ns + 1, 0);
+    for (int sdx = 0; sdx < ns; ++sdx) {
+        solid_chunk0[sdx] = (int)chunk_solid.size();
+        const int nchk = std::max(1, (c->seg_cap[sdx] + kForceChunk - 1) / kForceChunk);
+        for (int k = 0; k < nchk; ++k) {
+            chunk_solid.push_back(sdx);
+            chunk_start.push_back(k * kForceChunk);
+        }
+    }
+    solid_chunk0[ns] = (int)chunk_solid.size();
+    if ((int)chunk_solid.size() != L.nchunks) {
+        set_err(g_err, "internal: chunk count mismatch");
+        delete c;
+        return LBM_EINVAL;
+    }
 
     hipStream_t st = c->stream;
     auto up = [&](size_t dst, const void* src, size_t n) {
@@ -483,7 +530,10 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
     if (e == hipSuccess) e = up(L.vtab, vtab.data(), sizeof(double) * 2 * ns);
     if (e == hipSuccess) e = up(L.seg_off, c->seg_off.data(), sizeof(int) * ns);
     if (e == hipSuccess) e = up(L.seg_cap, c->seg_cap.data(), sizeof(int) * ns);
-    if (e == hipSuccess) e = up(L.seg_cnt, seg_cnt.data(), sizeof(int) * ns);
+    if (e == hipSuccess) e = up(L.seg_cnt[0], seg_cnt.data(), sizeof(int) * ns);
+    if (e == hipSuccess) e = up(L.chunk_solid, chunk_solid.data(), sizeof(int) * chunk_solid.size());
+    if (e == hipSuccess) e = up(L.chunk_start, chunk_start.data(), sizeof(int) * chunk_start.size());
+    if (e == hipSuccess) e = up(L.solid_chunk0, solid_chunk0.data(), sizeof(int) * solid_chunk0.size());
     if (e == hipSuccess && !movers.empty()) e = up(L.movers, movers.data(), sizeof(int) * movers.size());
     if (e == hipSuccess && !all.empty()) e = up(L.all, all.data(), sizeof(int) * all.size());
     // the uploads read pageable host vectors: finish them before they go away
@@ -495,7 +545,8 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
     }
 
     const int64_t own_bytes = (int64_t)grid->ny * L.opitch;
-    k_set_counters<<<1, 1, 0, st>>>(wsp<int64_t>(c, L.tctr), 0, wsp<int>(c, L.err));
+    k_set_counters<<<1, 1, 0, st>>>(wsp<int64_t>(c, L.tctr), 0, wsp<int>(c, L.err),
+                                    wsp<unsigned int>(c, L.ticket));
     k_fill_u8<<<(unsigned)((own_bytes + 255) / 256), 256, 0, st>>>(wsp<uint8_t>(c, L.own[0]), own_bytes, 0);
     GeomArgs ga{grid->nx, grid->ny, L.opitch, grid->walls_y};
     if (n_solids > 0)
@@ -505,14 +556,22 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
         e = hipMemcpyAsync(c->ws + L.own[1], c->ws + L.own[0], (size_t)own_bytes,
                            hipMemcpyDeviceToDevice, st);
     if (grid->walls_y)
-        k_wall_links<<<(2 * grid->nx + 255) / 256, 256, 0, st>>>(wsp<uint32_t>(c, L.links), grid->nx,
+        k_wall_links<<<(2 * grid->nx + 255) / 256, 256, 0, st>>>(wsp<uint32_t>(c, L.links[0]), grid->nx,
                                                                  grid->ny);
     LinkArgs la{grid->nx, grid->ny, L.opitch, grid->walls_y};
     if (n_solids > 0)
-        k_links<<<n_solids, kBlock, 0, st>>>(wsp<uint8_t>(c, L.own[0]), wsp<uint32_t>(c, L.links),
-                                             wsp<int>(c, L.seg_cnt), wsp<int>(c, L.seg_off),
+        k_links<<<n_solids, kBlock, 0, st>>>(wsp<uint8_t>(c, L.own[0]), wsp<uint32_t>(c, L.links[0]),
+                                             wsp<int>(c, L.seg_cnt[0]), wsp<int>(c, L.seg_off),
                                              wsp<int>(c, L.seg_cap), wsp<SolidDev>(c, L.sol),
                                              wsp<int>(c, L.all), 0, la, wsp<int>(c, L.err));
+    // both link buffers start as the lists of G_0 (translating bodies rewrite
+    // theirs in the other buffer every step)
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + L.links[1], c->ws + L.links[0],
+                           4 * (size_t)std::max<int64_t>(c->link_cap_total, 1), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + L.seg_cnt[1], c->ws + L.seg_cnt[0], 4 * (size_t)ns,
+                           hipMemcpyDeviceToDevice, st);
     dispatch_init<double>(c, nullptr, nullptr, nullptr);
     if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -674,7 +733,8 @@ lbm_status lbm_link_forces(lbm_ctx* c, double* d_out, int64_t max, int64_t* n) {
     if (!c || !n) return LBM_EINVAL;
     const int ns = c->n + 1;
     std::vector<int> cnt(ns), roff(ns);
-    HIPCHK(c, hipMemcpyAsync(cnt.data(), wsp<int>(c, c->L.seg_cnt), sizeof(int) * ns,
+    const int pc = (int)(c->t & 1);
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), wsp<int>(c, c->L.seg_cnt[pc]), sizeof(int) * ns,
                              hipMemcpyDeviceToHost, c->stream));
     lbm_status rs = read_err(c);
     if (rs != LBM_OK) return rs;
@@ -693,8 +753,8 @@ lbm_status lbm_link_forces(lbm_ctx* c, double* d_out, int64_t max, int64_t* n) {
                              hipMemcpyHostToDevice, c->stream));
     const int p = (int)(c->t & 1);
     ForceArgs fa = force_args(c);
-    const uint32_t* links = wsp<uint32_t>(c, c->L.links);
-    const int* sc = wsp<int>(c, c->L.seg_cnt);
+    const uint32_t* links = wsp<uint32_t>(c, c->L.links[p]);
+    const int* sc = wsp<int>(c, c->L.seg_cnt[p]);
     const int* so = wsp<int>(c, c->L.seg_off);
     const int* ro = wsp<int>(c, c->L.rec_off);
     const SolidDev* sol = wsp<SolidDev>(c, c->L.sol);
@@ -739,9 +799,9 @@ lbm_status lbm_save(lbm_ctx* c, void* d_dst, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(d + o, own_ptr(c, p ^ 1), ob, hipMemcpyDeviceToDevice, c->stream));
     o += ob;
     const size_t lb = 4 * (size_t)std::max<int64_t>(c->link_cap_total, 1);
-    HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.links, lb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.links[p], lb, hipMemcpyDeviceToDevice, c->stream));
     o += lb;
-    HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.seg_cnt, 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.seg_cnt[p], 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
     return read_err(c);
 }
 
@@ -775,10 +835,11 @@ lbm_status lbm_load(lbm_ctx* c, const void* d_src, size_t bytes) {
         HIPCHK(c, hipMemcpyAsync(own_ptr(c, p ^ 1), s + o, ob, hipMemcpyDeviceToDevice, c->stream));
     o += ob;
     const size_t lb = 4 * (size_t)std::max<int64_t>(c->link_cap_total, 1);
-    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.links, s + o, lb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.links[p], s + o, lb, hipMemcpyDeviceToDevice, c->stream));
     o += lb;
-    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.seg_cnt, s + o, 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
-    k_set_counters<<<1, 1, 0, c->stream>>>(wsp<int64_t>(c, c->L.tctr), c->t, wsp<int>(c, c->L.err));
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->L.seg_cnt[p], s + o, 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
+    k_set_counters<<<1, 1, 0, c->stream>>>(wsp<int64_t>(c, c->L.tctr), c->t, wsp<int>(c, c->L.err),
+                                           wsp<unsigned int>(c, c->L.ticket));
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
 }

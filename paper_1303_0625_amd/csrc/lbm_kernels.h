@@ -3,13 +3,18 @@
 // State convention: the workspace holds the post-collision deviations
 // d~_i(x, t) = f~_i(x, t) - w_i rho0 of every fluid node of geometry G_t, SoA
 // [9][ny][pitch], in two ping-pong buffers selected by the parity of t.  One
-// time step t -> t+1 is
-//   k_force    Eqs. 4-7 on the link list of G_t (reads f~(t))
-//   k_move     translating bodies: owner map of G_{t+1}, their link lists
+// time step t -> t+1 is three kernels that read only step-t data and write
+// disjoint outputs, so they may run in any order or concurrently:
+//   k_force    Eqs. 4-7 on the link lists of G_t (reads f~(t)), chunked over
+//              workgroups, with a fixed-order final sum per solid
+//   k_move     per translating body: owner map of G_{t+1} in its swept box,
+//              its link list for G_{t+1} (into the other link buffer), and the
+//              refill of its newborn nodes (solid in G_t, fluid in G_{t+1}),
+//              extrapolated from old-fluid neighbours' post-advection values
+//              and collided
 //   k_step     pull-advection (Eq. 3) with half-way bounce-back on G_t, then
-//              collision (Eq. 2), for nodes fluid in both G_t and G_{t+1}
-//   k_refill   newborn nodes (solid in G_t, fluid in G_{t+1}): extrapolated
-//              from old-fluid neighbours' post-advection values, then collided
+//              collision (Eq. 2), for every node fluid in G_t (a node covered
+//              by a body at t+1 is written too and never read again)
 #pragma once
 
 #include "lbm_device.h"
@@ -59,7 +64,6 @@ __device__ inline C pull_one(const T* __restrict__ f, const uint8_t* __restrict_
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* __restrict__ fout,
                                                  const uint8_t* __restrict__ own_t,
-                                                 const uint8_t* __restrict__ own_n,
                                                  const double* __restrict__ vtab, StepArgs a,
                                                  CollideParams<typename Sto<T>::C> cp) {
     using C = typename Sto<T>::C;
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* _
     const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
     if (y >= a.ny || x >= a.nx) return;
     const int64_t orow = (int64_t)y * a.opitch;
-    if (own_t[orow + x] | own_n[orow + x]) return;  // solid, newborn or covered
+    if (own_t[orow + x]) return;  // solid at t (newborn nodes are refilled by k_move)
 
     const int xm = x == 0 ? a.nx - 1 : x - 1;
     const int xp = x == a.nx - 1 ? 0 : x + 1;
@@ -353,52 +357,254 @@ __global__ __launch_bounds__(kBlock) void k_links(const uint8_t* __restrict__ ow
     build_links_block(own, links, seg_cnt, seg_off, seg_cap, sol[s], s, t, g, errflag, sh);
 }
 
-// Translating bodies, one workgroup per mover: bring the owner map own_n
-// (which holds G_{t-1}) to G_{t+1} over the range swept from t-1 to t+1, then
-// rebuild the mover's link list for G_{t+1}.  Bodies keep a gap of at least
-// two nodes, so no other solid owns a node adjacent to this one.
-__global__ __launch_bounds__(kBlock) void k_move(uint8_t* __restrict__ own_n,
-                                                 uint32_t* __restrict__ links,
-                                                 int* __restrict__ seg_cnt,
-                                                 const int* __restrict__ seg_off,
-                                                 const int* __restrict__ seg_cap,
-                                                 const SolidDev* __restrict__ sol,
-                                                 const int* __restrict__ movers,
-                                                 const int64_t* __restrict__ tctr, int parity,
-                                                 LinkArgs g, int* __restrict__ errflag) {
-    __shared__ int sh[kBlock];
-    const int s = movers[blockIdx.x];
-    const SolidDev S = sol[s];
-    const int64_t t = tctr[parity];
+// ------------------------------------------------------------------ movers
+// One workgroup per translating body s.  The body's swept range from t-1 to
+// t+1, widened by kBoxMargin nodes, is staged in LDS as two byte maps: ot
+// (owners of G_t) and on (the second owner map, which holds G_{t-1} on entry
+// and G_{t+1} on exit).  Virtual wall rows are marked kWallMark.  Translating
+// bodies keep a gap of at least kMoverGap nodes to each other, so no other
+// workgroup changes an owner that this one reads.
+constexpr int kBoxMargin = 5;
+constexpr uint8_t kWallMark = 255;
+constexpr int kMoverGap = 8;
+constexpr int kNewbornBatch = 16;
+
+struct MoveArgs {
+    int nx, ny, pitch, opitch, walls;
+    int64_t plane;
+    double rho0;
+    int refill;     // 0 A1, 1 A2, 2 A3
+    int box_bytes;  // capacity of each LDS byte map
+};
+
+__device__ inline void swept_box(const SolidDev& S, int64_t t, long& x0, long& x1, long& y0, long& y1) {
     double Xa, Ya, Xb, Yb;
     solid_pos(S, t - 1, Xa, Ya);
     solid_pos(S, t + 1, Xb, Yb);
     long ax0, ax1, ay0, ay1, bx0, bx1, by0, by1;
-    solid_range(S, Xa, Ya, 1, ax0, ax1, ay0, ay1);
-    solid_range(S, Xb, Yb, 1, bx0, bx1, by0, by1);
-    const long x0 = ax0 < bx0 ? ax0 : bx0, x1 = ax1 > bx1 ? ax1 : bx1;
-    const long y0 = ay0 < by0 ? ay0 : by0, y1 = ay1 > by1 ? ay1 : by1;
-    const long W = x1 - x0 + 1, H = y1 - y0 + 1;
-    for (long q = threadIdx.x; q < W * H; q += kBlock) {
+    solid_range(S, Xa, Ya, kBoxMargin, ax0, ax1, ay0, ay1);
+    solid_range(S, Xb, Yb, kBoxMargin, bx0, bx1, by0, by1);
+    x0 = ax0 < bx0 ? ax0 : bx0;
+    x1 = ax1 > bx1 ? ax1 : bx1;
+    y0 = ay0 < by0 ? ay0 : by0;
+    y1 = ay1 > by1 ? ay1 : by1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* __restrict__ fout,
+                                                 const uint8_t* __restrict__ own_t,
+                                                 uint8_t* __restrict__ own_n,
+                                                 uint32_t* __restrict__ links_n,
+                                                 int* __restrict__ seg_cnt_n,
+                                                 const int* __restrict__ seg_off,
+                                                 const int* __restrict__ seg_cap,
+                                                 const SolidDev* __restrict__ sol,
+                                                 const double* __restrict__ vtab,
+                                                 const int* __restrict__ movers,
+                                                 const int64_t* __restrict__ tctr, int parity,
+                                                 MoveArgs a, CollideParams<typename Sto<T>::C> cp,
+                                                 int* __restrict__ errflag) {
+    using C = typename Sto<T>::C;
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ int sh_scan[kBlock];
+    __shared__ int nb_list[kNewbornBatch];
+    __shared__ int8_t nb_use[kNewbornBatch][8];  // -1: no participation, else 0/1/2
+    __shared__ C nb_val[kNewbornBatch][8][3][9];
+    __shared__ C nb_new[kNewbornBatch][9];
+    uint8_t* ot = lds;
+    uint8_t* on = lds + a.box_bytes;
+
+    const int s = movers[blockIdx.x];
+    const SolidDev S = sol[s];
+    const int64_t t = tctr[parity];
+    long x0, x1, y0, y1;
+    swept_box(S, t, x0, x1, y0, y1);
+    const int W = (int)(x1 - x0 + 1), H = (int)(y1 - y0 + 1), N = W * H;
+    if (N > a.box_bytes) {  // host sizes the box; never expected
+        if (threadIdx.x == 0) atomicOr(errflag, 4);
+        return;
+    }
+    auto gidx = [&](int q, int& gx, int& gy) -> bool {  // box index -> lattice node
         long yy = y0 + q / W, xx = x0 + q % W;
-        if (g.walls && (yy < 0 || yy >= g.ny)) continue;
-        int64_t o = (int64_t)wrapi(yy, g.ny) * g.opitch + wrapi(xx, g.nx);
-        if (solid_inside(S, Xb, Yb, xx, yy))
-            own_n[o] = (uint8_t)s;
-        else if (own_n[o] == s)
-            own_n[o] = 0;
+        if (a.walls && (yy < 0 || yy >= a.ny)) return false;
+        gx = wrapi(xx, a.nx);
+        gy = wrapi(yy, a.ny);
+        return true;
+    };
+    // 1. stage both owner maps
+    for (int q = threadIdx.x; q < N; q += kBlock) {
+        int gx, gy;
+        if (gidx(q, gx, gy)) {
+            const int64_t o = (int64_t)gy * a.opitch + gx;
+            ot[q] = own_t[o];
+            on[q] = own_n[o];
+        } else {
+            ot[q] = kWallMark;
+            on[q] = kWallMark;
+        }
     }
     __syncthreads();
-    build_links_block(own_n, links, seg_cnt, seg_off, seg_cap, S, s, t + 1, g, errflag, sh);
+    // 2. G_{t+1}: rasterise the body at t+1, clear what it left
+    double Xn, Yn;
+    solid_pos(S, t + 1, Xn, Yn);
+    for (int q = threadIdx.x; q < N; q += kBlock) {
+        if (on[q] == kWallMark) continue;
+        const long yy = y0 + q / W, xx = x0 + q % W;
+        uint8_t v = on[q];
+        uint8_t nv = solid_inside(S, Xn, Yn, xx, yy) ? (uint8_t)s : (v == s ? (uint8_t)0 : v);
+        if (nv != v) {
+            on[q] = nv;
+            int gx, gy;
+            gidx(q, gx, gy);
+            own_n[(int64_t)gy * a.opitch + gx] = nv;
+        }
+    }
+    __syncthreads();
+    // 3. link list of G_{t+1}, row-major (y, x, i) over the box interior
+    {
+        const int chunk = (N + kBlock - 1) / kBlock;
+        const int q0 = threadIdx.x * chunk;
+        const int q1 = q0 + chunk < N ? q0 + chunk : N;
+        auto links_at = [&](int q, uint32_t* out, int base) -> int {
+            const int qx = q % W, qy = q / W;
+            if (qx == 0 || qy == 0 || qx == W - 1 || qy == H - 1 || on[q] != 0) return 0;
+            int c = 0;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                if (on[q + ey_(i) * W + ex_(i)] == s) {
+                    if (out) {
+                        int gx, gy;
+                        gidx(q, gx, gy);
+                        out[base + c] = ((uint32_t)gy * (uint32_t)a.nx + (uint32_t)gx) << 4 | (uint32_t)i;
+                    }
+                    ++c;
+                }
+            }
+            return c;
+        };
+        int cnt = 0;
+        for (int q = q0; q < q1; ++q) cnt += links_at(q, nullptr, 0);
+        int total;
+        int off = block_exclusive_scan(cnt, sh_scan, total);
+        const int cap = seg_cap[s];
+        if (total <= cap) {
+            uint32_t* L = links_n + seg_off[s];
+            for (int q = q0; q < q1; ++q) off += links_at(q, L, off);
+        }
+        if (threadIdx.x == 0) {
+            seg_cnt_n[s] = total <= cap ? total : 0;
+            if (total > cap) atomicOr(errflag, 1);
+        }
+    }
+    // 4. newborn nodes, in batches: refill and collide
+    const C rho0 = (C)a.rho0;
+    for (int qb = 0; qb < N; qb += kBlock) {
+        const int q = qb + threadIdx.x;
+        const int born = (q < N && ot[q] == s && on[q] == 0) ? 1 : 0;
+        int total;
+        const int pos = block_exclusive_scan(born, sh_scan, total);
+        for (int base = 0; base < total; base += kNewbornBatch) {
+            if (born && pos >= base && pos < base + kNewbornBatch) nb_list[pos - base] = q;
+            const int nbat = total - base < kNewbornBatch ? total - base : kNewbornBatch;
+            __syncthreads();
+            // 4a. participation and scheme per (newborn, direction)
+            if (threadIdx.x < nbat * 8) {
+                const int b = threadIdx.x / 8, k = threadIdx.x % 8 + 1;
+                const int qn = nb_list[b];
+                bool ok[4] = {false, false, false, false};
+                for (int m = 1; m <= 3; ++m) {
+                    const int qm = qn + m * (ey_(k) * W + ex_(k));
+                    ok[m] = ot[qm] == 0 && on[qm] == 0;
+                    if (!ok[m]) break;
+                }
+                int use = -1;
+                if (ok[1]) {
+                    use = a.refill;
+                    if (use == 0 && !(ok[2] && ok[3])) use = 1;
+                    if (use == 1 && !ok[2]) use = 2;
+                }
+                nb_use[b][k - 1] = (int8_t)use;
+            }
+            __syncthreads();
+            // 4b. post-advection values at the stencil nodes, in parallel
+            for (int w = threadIdx.x; w < nbat * 216; w += kBlock) {
+                const int b = w / 216, r = w % 216;
+                const int k = r / 27 + 1, m = (r % 27) / 9 + 1, j = r % 9;
+                const int use = nb_use[b][k - 1];
+                const int need = use == 0 ? 3 : (use == 1 ? 2 : (use == 2 ? 1 : 0));
+                if (m > need) continue;
+                const int qm = nb_list[b] + m * (ey_(k) * W + ex_(k));
+                int gx, gy;
+                gidx(qm, gx, gy);
+                const int qs = qm - (ey_(j) * W + ex_(j));  // source of population j
+                const uint8_t o = ot[qs];
+                C v;
+                if (j != 0 && o != 0) {
+                    const int sid = o == kWallMark ? 0 : o;
+                    const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                    v = Sto<T>::ld(fin[(int64_t)opp_(j) * a.plane + (int64_t)gy * a.pitch + gx]) +
+                        C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
+                } else {
+                    int sx, sy;
+                    gidx(qs, sx, sy);
+                    v = Sto<T>::ld(fin[(int64_t)j * a.plane + (int64_t)sy * a.pitch + sx]);
+                }
+                nb_val[b][k - 1][m - 1][j] = v;
+            }
+            __syncthreads();
+            // 4c. extrapolate along each participating link, average
+            if (threadIdx.x < nbat * 9) {
+                const int b = threadIdx.x / 9, j = threadIdx.x % 9;
+                C acc = C(0);
+                int np = 0;
+                for (int k = 0; k < 8; ++k) {
+                    const int use = nb_use[b][k];
+                    if (use < 0) continue;
+                    ++np;
+                    const C v1 = nb_val[b][k][0][j];
+                    if (use == 0)
+                        acc += C(3) * v1 - C(3) * nb_val[b][k][1][j] + nb_val[b][k][2][j];
+                    else if (use == 1)
+                        acc += C(2) * v1 - nb_val[b][k][1][j];
+                    else
+                        acc += v1;
+                }
+                if (np > 0) {
+                    nb_new[b][j] = acc / C(np);
+                } else {  // no participant: equilibrium at the body velocity
+                    C fe[9];
+                    feq_dev<C>(rho0, rho0, (C)S.vx, (C)S.vy, fe);
+                    nb_new[b][j] = fe[j];
+                }
+            }
+            __syncthreads();
+            // 4d. collide and store
+            if (threadIdx.x < nbat) {
+                C d[9];
+#pragma unroll
+                for (int j = 0; j < 9; ++j) d[j] = nb_new[threadIdx.x][j];
+                collide<C>(d, cp);
+                int gx, gy;
+                gidx(nb_list[threadIdx.x], gx, gy);
+                T* w0 = fout + (int64_t)gy * a.pitch + gx;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) w0[j * a.plane] = Sto<T>::st(d[j]);
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // ------------------------------------------------------------------ forces
+constexpr int kForceChunk = 512;  // links per workgroup
+
 struct ForceArgs {
     int nx, ny, pitch, walls;
     int64_t plane;
     double rho0;
     int64_t hist_cap;
-    int nsol;  // bodies + 1
+    int nsol;     // bodies + 1
+    int nchunks;  // workgroups of k_force
 };
 
 __device__ inline double wave_sum(double v) {
@@ -407,34 +613,46 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// One workgroup per solid.  Per link (x_f, i) with a = f~_i(x_f) and the
+// Chunked link forces.  Workgroup c takes links [start, start + kForceChunk)
+// of solid chunk_solid[c].  Per link (x_f, i) with a = f~_i(x_f) and the
 // bounced population b = a - 6 w_i rho0 (e_i . v):
 //   CME (Eq. 4) F = e_i a - e_ibar b
 //   GME (Eq. 5) F = (e_i - v) a - (e_ibar - v) b
 //   T_z (Eq. 7) = (x_s - R) x F with x_s = x_f + e_i/2, R the body centre.
-// Each thread sums a fixed strided subset of the links; the wave and
-// workgroup combine in a fixed tree, so the result is run-to-run identical.
-// Block 0 also advances the step counter into the other parity slot.
+// Each thread sums a fixed strided subset, the wave and workgroup combine in
+// a fixed tree into partial[c]; the last workgroup to finish (ticket counter,
+// control only) sums each solid's chunk partials in chunk order.  The result
+// is therefore independent of scheduling.  That workgroup also advances the
+// step counter into the other parity slot.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_force(const T* __restrict__ f,
                                                   const uint32_t* __restrict__ links,
                                                   const int* __restrict__ seg_cnt,
                                                   const int* __restrict__ seg_off,
+                                                  const int* __restrict__ chunk_solid,
+                                                  const int* __restrict__ chunk_start,
+                                                  const int* __restrict__ solid_chunk0,
                                                   const SolidDev* __restrict__ sol,
+                                                  double* __restrict__ partial,
+                                                  unsigned int* __restrict__ ticket,
                                                   double* __restrict__ hist,
                                                   int64_t* __restrict__ tctr, int parity,
                                                   ForceArgs a) {
     __shared__ double sh[kBlock / 64][6];
-    const int s = blockIdx.x;
-    const int64_t t = tctr[parity];
+    __shared__ int is_last;
+    const int c = blockIdx.x;
+    const int s = chunk_solid[c];
+    const int start = chunk_start[c];
     const int n = seg_cnt[s];
+    const int end = start + kForceChunk < n ? start + kForceChunk : n;
+    const int64_t t = tctr[parity];
     const uint32_t* L = links + seg_off[s];
     const SolidDev S = sol[s];
     double X = 0.0, Y = 0.0;
     if (s > 0) solid_pos(S, t, X, Y);
     const double vx = S.vx, vy = S.vy;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = threadIdx.x; k < n; k += kBlock) {
+    for (int k = start + threadIdx.x; k < end; k += kBlock) {
         const uint32_t code = L[k];
         const int i = (int)(code & 15u);
         const uint32_t node = code >> 4;
@@ -474,17 +692,32 @@ __global__ __launch_bounds__(kBlock) void k_force(const T* __restrict__ f,
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        double v = wave_sum(acc[c]);
-        if (lane == 0) sh[wv][c] = v;
+    for (int q = 0; q < 6; ++q) {
+        double v = wave_sum(acc[q]);
+        if (lane == 0) sh[wv][q] = v;
     }
     __syncthreads();
     if (threadIdx.x < 6) {
-        const int c = threadIdx.x;
-        double v = ((sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]));
-        hist[((t % a.hist_cap) * a.nsol + s) * 6 + c] = v;
+        const int q = threadIdx.x;
+        partial[c * 6 + q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
     }
-    if (s == 0 && threadIdx.x == 0) tctr[parity ^ 1] = t + 1;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1u) == (unsigned)(a.nchunks - 1);
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    const int64_t slot = t % a.hist_cap;
+    for (int r = threadIdx.x; r < a.nsol * 6; r += kBlock) {
+        const int sid = r / 6, q = r % 6;
+        double v = 0.0;
+        for (int cc = solid_chunk0[sid]; cc < solid_chunk0[sid + 1]; ++cc) v += partial[cc * 6 + q];
+        hist[(slot * a.nsol + sid) * 6 + q] = v;
+    }
+    if (threadIdx.x == 0) {
+        *ticket = 0u;
+        tctr[parity ^ 1] = t + 1;
+    }
 }
 
 // Per-link force records of the current state (test and inspection path).
@@ -521,100 +754,13 @@ __global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f
     }
 }
 
-// ------------------------------------------------------------------ refill
-// Newborn nodes of the movers (one workgroup per mover): solid in G_t, fluid
-// in G_{t+1}.  For every direction k whose first node x + e_k is old-fluid
-// (fluid in both geometries), extrapolate each population from the
-// post-advection values at x + m e_k: A1 3f1 - 3f2 + f3 (needs m = 1..3
-// old-fluid), else A2 2f1 - f2 (needs m = 1, 2), else A3 f1; average over the
-// participating directions; with none, take f_eq(rho0, v) of the body.  Then
-// collide and store.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_refill(const T* __restrict__ fin, T* __restrict__ fout,
-                                                   const uint8_t* __restrict__ own_t,
-                                                   const uint8_t* __restrict__ own_n,
-                                                   const double* __restrict__ vtab,
-                                                   const SolidDev* __restrict__ sol,
-                                                   const int* __restrict__ movers,
-                                                   const int64_t* __restrict__ tctr, int parity,
-                                                   StepArgs a, CollideParams<typename Sto<T>::C> cp,
-                                                   int scheme) {
-    using C = typename Sto<T>::C;
-    const int s = movers[blockIdx.x];
-    const SolidDev S = sol[s];
-    const int64_t t = tctr[parity];
-    double Xa, Ya, Xb, Yb;
-    solid_pos(S, t, Xa, Ya);
-    solid_pos(S, t + 1, Xb, Yb);
-    long ax0, ax1, ay0, ay1, bx0, bx1, by0, by1;
-    solid_range(S, Xa, Ya, 1, ax0, ax1, ay0, ay1);
-    solid_range(S, Xb, Yb, 1, bx0, bx1, by0, by1);
-    const long x0 = ax0 < bx0 ? ax0 : bx0, x1 = ax1 > bx1 ? ax1 : bx1;
-    const long y0 = ay0 < by0 ? ay0 : by0, y1 = ay1 > by1 ? ay1 : by1;
-    const long W = x1 - x0 + 1, H = y1 - y0 + 1;
-    for (long q = threadIdx.x; q < W * H; q += kBlock) {
-        const long yy = y0 + q / W, xx = x0 + q % W;
-        if (a.walls && (yy < 0 || yy >= a.ny)) continue;
-        const int x = wrapi(xx, a.nx), y = wrapi(yy, a.ny);
-        const int64_t o = (int64_t)y * a.opitch + x;
-        if (!(own_t[o] == s && own_n[o] == 0)) continue;
-        C acc[9];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) acc[j] = C(0);
-        int npart = 0;
-        for (int k = 1; k < 9; ++k) {
-            int px[4], py[4];
-            bool ok[4] = {false, false, false, false};
-            for (int m = 1; m <= 3; ++m) {
-                int xm = x + m * ex_(k), ym = y + m * ey_(k);
-                if (a.walls && (ym < 0 || ym >= a.ny)) break;
-                px[m] = wrapi(xm, a.nx);
-                py[m] = wrapi(ym, a.ny);
-                const int64_t om = (int64_t)py[m] * a.opitch + px[m];
-                ok[m] = own_t[om] == 0 && own_n[om] == 0;
-                if (!ok[m]) break;
-            }
-            if (!ok[1]) continue;
-            ++npart;
-            int use = scheme;
-            if (use == 0 && !(ok[2] && ok[3])) use = 1;
-            if (use == 1 && !ok[2]) use = 2;
-            for (int j = 0; j < 9; ++j) {
-                C v1 = pull_one<T, C>(fin, own_t, vtab, a, px[1], py[1], j);
-                C val;
-                if (use == 0) {
-                    C v2 = pull_one<T, C>(fin, own_t, vtab, a, px[2], py[2], j);
-                    C v3 = pull_one<T, C>(fin, own_t, vtab, a, px[3], py[3], j);
-                    val = C(3) * v1 - C(3) * v2 + v3;
-                } else if (use == 1) {
-                    C v2 = pull_one<T, C>(fin, own_t, vtab, a, px[2], py[2], j);
-                    val = C(2) * v1 - v2;
-                } else {
-                    val = v1;
-                }
-                acc[j] += val;
-            }
-        }
-        C d[9];
-        if (npart == 0) {
-            feq_dev<C>((C)a.rho0, (C)a.rho0, (C)S.vx, (C)S.vy, d);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 9; ++j) d[j] = acc[j] / C(npart);
-        }
-        collide<C>(d, cp);
-        T* w0 = fout + (int64_t)y * a.pitch + x;
-#pragma unroll
-        for (int j = 0; j < 9; ++j) w0[j * a.plane] = Sto<T>::st(d[j]);
-    }
-}
-
 // ------------------------------------------------------------------ misc
-__global__ void k_set_counters(int64_t* tctr, int64_t t, int* errflag) {
+__global__ void k_set_counters(int64_t* tctr, int64_t t, int* errflag, unsigned int* ticket) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         tctr[0] = t;
         tctr[1] = t;
         *errflag = 0;
+        *ticket = 0u;
     }
 }
 
