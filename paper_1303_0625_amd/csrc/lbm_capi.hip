@@ -302,16 +302,27 @@ lbm_status enqueue_step(lbm_ctx* c) {
             sol, wsp<double>(c, c->L.vtab), wsp<int>(c, c->L.movers), tctr, p, ma, cp, errf);
     }
     StepArgs sa = step_args(c);
+    const double* vt = wsp<double>(c, c->L.vtab);
     const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
-    if (timed) {
-        hipExtLaunchKernelGGL(k_step<T>, dim3((unsigned)node_blocks(c)), dim3(kBlock), 0, c->stream,
-                              c->ev[c->ev_used], c->ev[c->ev_used + 1], 0, fin, fout, own_t,
-                              (const double*)wsp<double>(c, c->L.vtab), sa, cp);
-        c->ev_used += 2;
+    hipEvent_t e0 = timed ? c->ev[c->ev_used] : nullptr, e1 = timed ? c->ev[c->ev_used + 1] : nullptr;
+    if (c->g.nx % 4 == 0) {
+        // four nodes per lane, 256 columns per wave
+        const int64_t waves = (int64_t)c->g.ny * ((c->g.nx + 255) / 256);
+        const dim3 grid((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)));
+        if (timed)
+            hipExtLaunchKernelGGL(k_step4<T>, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt,
+                                  sa, cp);
+        else
+            k_step4<T><<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
     } else {
-        k_step<T><<<(unsigned)node_blocks(c), kBlock, 0, c->stream>>>(fin, fout, own_t,
-                                                                    wsp<double>(c, c->L.vtab), sa, cp);
+        const dim3 grid((unsigned)node_blocks(c));
+        if (timed)
+            hipExtLaunchKernelGGL(k_step<T>, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt,
+                                  sa, cp);
+        else
+            k_step<T><<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
     }
+    if (timed) c->ev_used += 2;
     c->t += 1;
     return LBM_OK;
 }

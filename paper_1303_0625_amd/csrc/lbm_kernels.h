@@ -126,6 +126,182 @@ __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* _
     for (int i = 0; i < 9; ++i) w0[i * P] = Sto<T>::st(d[i]);
 }
 
+// ------------------------------------------------------------------ step, 4 nodes per lane
+// Same arithmetic as k_step, four consecutive x per lane (a wave covers 256
+// columns of one row).  Each population row is read with one aligned
+// 4-element load per lane; the populations streaming in along +x / -x need
+// the neighbouring lane's last / first element, which comes through a
+// cross-lane shift (the wave's edge lanes and the row ends load it
+// directly, with periodic wrap).  Needs nx % 4 == 0.  A lane whose 4 nodes
+// or their 18 source nodes touch a solid or a wall row takes the per-node
+// path of k_step.
+template <typename T>
+struct alignas(4 * sizeof(T)) Pack4 {
+    T v[4];
+};
+
+template <typename T>
+__device__ inline T shfl_up1(T v) { return __shfl_up(v, 1, 64); }
+template <typename T>
+__device__ inline T shfl_down1(T v) { return __shfl_down(v, 1, 64); }
+template <>
+__device__ inline _Float16 shfl_up1(_Float16 v) {
+    int b = (int)__builtin_bit_cast(uint16_t, v);
+    return __builtin_bit_cast(_Float16, (uint16_t)__shfl_up(b, 1, 64));
+}
+template <>
+__device__ inline _Float16 shfl_down1(_Float16 v) {
+    int b = (int)__builtin_bit_cast(uint16_t, v);
+    return __builtin_bit_cast(_Float16, (uint16_t)__shfl_down(b, 1, 64));
+}
+template <>
+__device__ inline bf16_t shfl_up1(bf16_t v) {
+    bf16_t r;
+    r.bits = (uint16_t)__shfl_up((int)v.bits, 1, 64);
+    return r;
+}
+template <>
+__device__ inline bf16_t shfl_down1(bf16_t v) {
+    bf16_t r;
+    r.bits = (uint16_t)__shfl_down((int)v.bits, 1, 64);
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_step4(const T* __restrict__ fin, T* __restrict__ fout,
+                                                  const uint8_t* __restrict__ own_t,
+                                                  const double* __restrict__ vtab, StepArgs a,
+                                                  CollideParams<typename Sto<T>::C> cp) {
+    using C = typename Sto<T>::C;
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t wpr = ((uint32_t)a.nx + 255u) >> 8;  // waves per row
+    const uint32_t gw = b * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int y = (int)(gw / wpr);
+    if (y >= a.ny) return;  // whole wave
+    const int lane = (int)(threadIdx.x & 63);
+    const int x = (int)((gw - (uint32_t)y * wpr) << 8) + 4 * lane;
+    const bool active = x < a.nx;
+    // highest active lane of this wave: it fetches the column right of its group
+    const int ll = (a.nx - 1 - (int)((gw - (uint32_t)y * wpr) << 8)) >> 2;
+    const int last_lane = ll < 63 ? ll : 63;
+
+    bool wall_lo = false, wall_hi = false;
+    int ym, yp;
+    if (a.walls) {
+        wall_lo = (y == 0);
+        wall_hi = (y == a.ny - 1);
+        ym = wall_lo ? y : y - 1;
+        yp = wall_hi ? y : y + 1;
+    } else {
+        ym = y == 0 ? a.ny - 1 : y - 1;
+        yp = y == a.ny - 1 ? 0 : y + 1;
+    }
+    const int xl = x == 0 ? a.nx - 1 : x - 1;          // column left of the group
+    const int xr = x + 4 >= a.nx ? x + 4 - a.nx : x + 4;  // column right of the group
+
+    // ---- owners: 4 bytes per row at x, plus the bytes at x-1 and x+4
+    const uint8_t* om = own_t + (int64_t)ym * a.opitch;
+    const uint8_t* o0 = own_t + (int64_t)y * a.opitch;
+    const uint8_t* op = own_t + (int64_t)yp * a.opitch;
+    uint32_t wm = 0, w0 = 0, wp = 0;
+    if (active) {
+        wm = *reinterpret_cast<const uint32_t*>(om + x);
+        w0 = *reinterpret_cast<const uint32_t*>(o0 + x);
+        wp = *reinterpret_cast<const uint32_t*>(op + x);
+    }
+    // neighbour lanes' edge bytes
+    uint32_t lm = (uint32_t)__shfl_up((int)(wm >> 24), 1, 64);
+    uint32_t l0 = (uint32_t)__shfl_up((int)(w0 >> 24), 1, 64);
+    uint32_t lp = (uint32_t)__shfl_up((int)(wp >> 24), 1, 64);
+    uint32_t rm = (uint32_t)__shfl_down((int)(wm & 0xffu), 1, 64);
+    uint32_t r0 = (uint32_t)__shfl_down((int)(w0 & 0xffu), 1, 64);
+    uint32_t rp = (uint32_t)__shfl_down((int)(wp & 0xffu), 1, 64);
+    if (active && lane == 0) {
+        lm = om[xl];
+        l0 = o0[xl];
+        lp = op[xl];
+    }
+    if (active && lane == last_lane) {
+        rm = om[xr];
+        r0 = o0[xr];
+        rp = op[xr];
+    }
+    const bool special = (wm | w0 | wp | lm | l0 | lp | rm | r0 | rp) != 0 || wall_lo || wall_hi;
+
+    // ---- populations: one 4-wide load per direction (row y - e_iy)
+    const int64_t P = a.plane;
+    const T* r_0 = fin + (int64_t)y * a.pitch;
+    const T* r_m = fin + (int64_t)ym * a.pitch;
+    const T* r_p = fin + (int64_t)yp * a.pitch;
+    const T* rowp[9] = {r_0, r_0, r_m, r_0, r_p, r_m, r_m, r_p, r_p};
+    Pack4<T> V[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (active) {
+            V[i] = *reinterpret_cast<const Pack4<T>*>(rowp[i] + i * P + x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) V[i].v[k] = Sto<T>::st(C(0));
+        }
+    }
+    // ---- the x-shifted elements: +x movers need x-1, -x movers need x+4
+    T L1 = shfl_up1(V[1].v[3]), L5 = shfl_up1(V[5].v[3]), L8 = shfl_up1(V[8].v[3]);
+    T R3 = shfl_down1(V[3].v[0]), R6 = shfl_down1(V[6].v[0]), R7 = shfl_down1(V[7].v[0]);
+    if (active && lane == 0) {
+        L1 = rowp[1][1 * P + xl];
+        L5 = rowp[5][5 * P + xl];
+        L8 = rowp[8][8 * P + xl];
+    }
+    if (active && lane == last_lane) {
+        R3 = rowp[3][3 * P + xr];
+        R6 = rowp[6][6 * P + xr];
+        R7 = rowp[7][7 * P + xr];
+    }
+    if (!active) return;
+
+    const int64_t orow_f = (int64_t)y * a.pitch;
+    if (!special) {
+        // nodes in increasing x; L* roll forward (node k+1's left value is
+        // node k's original element), the -x movers read element k+1, which
+        // is still unmodified
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            C d[9];
+            d[0] = Sto<T>::ld(V[0].v[k]);
+            d[1] = Sto<T>::ld(L1);
+            d[2] = Sto<T>::ld(V[2].v[k]);
+            d[3] = Sto<T>::ld(k == 3 ? R3 : V[3].v[k < 3 ? k + 1 : 3]);
+            d[4] = Sto<T>::ld(V[4].v[k]);
+            d[5] = Sto<T>::ld(L5);
+            d[6] = Sto<T>::ld(k == 3 ? R6 : V[6].v[k < 3 ? k + 1 : 3]);
+            d[7] = Sto<T>::ld(k == 3 ? R7 : V[7].v[k < 3 ? k + 1 : 3]);
+            d[8] = Sto<T>::ld(L8);
+            L1 = V[1].v[k];
+            L5 = V[5].v[k];
+            L8 = V[8].v[k];
+            collide<C>(d, cp);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) V[i].v[k] = Sto<T>::st(d[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) *reinterpret_cast<Pack4<T>*>(fout + i * P + orow_f + x) = V[i];
+    } else {
+        // per-node path for the nodes fluid at t; solid nodes are not written
+        // (a newborn node among them belongs to the mover kernel)
+        for (int k = 0; k < 4; ++k) {
+            const int xk = x + k;
+            if (o0[xk] != 0) continue;
+            C d[9];
+            d[0] = Sto<T>::ld(r_0[xk]);
+#pragma unroll
+            for (int i = 1; i < 9; ++i) d[i] = pull_one<T, C>(fin, own_t, vtab, a, xk, y, i);
+            collide<C>(d, cp);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fout[i * P + orow_f + xk] = Sto<T>::st(d[i]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ init
 // f = f_eq(rho, u) at every fluid node (uniform rho0, u0 when the field
 // pointers are NULL; otherwise u - g/2 from the fields so that the Guo

@@ -197,3 +197,23 @@ def test_determinism_and_checkpoint(lbm_mod):
     assert r.t == 300
     r.step(300)
     assert bool((r.populations() == pa).all())
+
+
+def test_scalar_update_path_f64(oracle_mod, lbm_mod):
+    """nx not a multiple of 4 takes the one-node-per-lane update kernel; a
+    translating cylinder and a fixed one, 130 x 66 channel."""
+    bodies = [lc.disc(40.3, 20.2, 6.1, vx=0.037, moves=True), lc.disc(95.2, 44.5, 7.3)]
+    c = lc.make_case(130, 66, 0.75, walls_y=True, gx=3e-6, bodies=bodies, name="scalar_path")
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 1500, chunks=3)
+    compare_fields(lat, osim, 1e-12)
+    compare_forces(lat, osim, c, 1e-10)
+
+
+def test_periodic_no_walls_f64(oracle_mod, lbm_mod):
+    """Fully periodic lattice (no walls) with a body crossing the periodic
+    boundary in x and in y."""
+    bodies = [lc.disc(2.5, 61.0, 6.4, vx=0.05, vy=-0.02, moves=True), lc.disc(40.0, 30.0, 5.5)]
+    c = lc.make_case(96, 64, 0.7, gx=1e-5, gy=2e-6, bodies=bodies, name="periodic_cross")
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 800, chunks=2)
+    compare_fields(lat, osim, 1e-12)
+    compare_forces(lat, osim, c, 1e-10)
