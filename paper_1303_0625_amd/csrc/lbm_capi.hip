@@ -65,9 +65,9 @@ int body_link_cap(const lbm_solid& s, int nx, int ny) {
 
 bool make_layout(const lbm_grid& g, const lbm_solid* solids, int n, int64_t hist_steps, Layout& L) {
     const size_t es = dtype_size(g.dtype);
-    L.pitch = (g.nx + 63) / 64 * 64;
+    L.pitch = (g.nx + 63) / 64 * 64;  // padded row length (elements)
     L.opitch = (g.nx + 63) / 64 * 64;
-    L.plane = (int64_t)g.ny * L.pitch;
+    L.plane = (int64_t)g.ny * L.pitch;  // elements per population (all rows)
     size_t off = 0;
     for (int k = 0; k < 2; ++k) {
         L.f[k] = off;
@@ -219,9 +219,10 @@ StepArgs step_args(const lbm_ctx* c) {
     StepArgs a;
     a.nx = c->g.nx;
     a.ny = c->g.ny;
-    a.pitch = c->L.pitch;
+    a.rowlen = c->L.pitch;
     a.opitch = c->L.opitch;
-    a.plane = c->L.plane;
+    a.istride = c->L.pitch;
+    a.ystride = 9 * (int64_t)c->L.pitch;
     a.walls = c->g.walls_y;
     a.rho0 = c->g.rho0;
     return a;
@@ -242,9 +243,9 @@ ForceArgs force_args(const lbm_ctx* c) {
     ForceArgs a;
     a.nx = c->g.nx;
     a.ny = c->g.ny;
-    a.pitch = c->L.pitch;
     a.walls = c->g.walls_y;
-    a.plane = c->L.plane;
+    a.istride = c->L.pitch;
+    a.ystride = 9 * (int64_t)c->L.pitch;
     a.rho0 = c->g.rho0;
     a.hist_cap = c->hist_cap;
     a.nsol = c->n + 1;
@@ -294,8 +295,8 @@ lbm_status enqueue_step(lbm_ctx* c) {
         wsp<double>(c, c->L.hist), tctr, p, force_args(c));
     CollideParams<C> cp = collide_params<C>(c);
     if (c->L.n_movers > 0) {
-        MoveArgs ma{c->g.nx, c->g.ny, c->L.pitch, c->L.opitch, c->g.walls_y, c->L.plane, c->g.rho0,
-                    c->g.refill, c->L.box_bytes};
+        MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
+                    9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes};
         k_move<T><<<c->L.n_movers, kBlock, 2 * c->L.box_bytes, c->stream>>>(
             fin, fout, own_t, own_n, wsp<uint32_t>(c, c->L.links[p ^ 1]),
             wsp<int>(c, c->L.seg_cnt[p ^ 1]), wsp<int>(c, c->L.seg_off), wsp<int>(c, c->L.seg_cap),
@@ -305,23 +306,12 @@ lbm_status enqueue_step(lbm_ctx* c) {
     const double* vt = wsp<double>(c, c->L.vtab);
     const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
     hipEvent_t e0 = timed ? c->ev[c->ev_used] : nullptr, e1 = timed ? c->ev[c->ev_used + 1] : nullptr;
-    if (c->g.nx % 4 == 0) {
-        // four nodes per lane, 256 columns per wave
-        const int64_t waves = (int64_t)c->g.ny * ((c->g.nx + 255) / 256);
-        const dim3 grid((unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64)));
-        if (timed)
-            hipExtLaunchKernelGGL(k_step4<T>, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt,
-                                  sa, cp);
-        else
-            k_step4<T><<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
-    } else {
-        const dim3 grid((unsigned)node_blocks(c));
-        if (timed)
-            hipExtLaunchKernelGGL(k_step<T>, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt,
-                                  sa, cp);
-        else
-            k_step<T><<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
-    }
+    const dim3 grid((unsigned)node_blocks(c));
+    if (timed)
+        hipExtLaunchKernelGGL(k_step<T>, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt, sa,
+                              cp);
+    else
+        k_step<T><<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
     if (timed) c->ev_used += 2;
     c->t += 1;
     return LBM_OK;

@@ -24,11 +24,16 @@ namespace lbm {
 constexpr int kBlock = 256;
 constexpr int kMaxSolids = 254;
 
+// Population layout: element (i, y, x) at i*istride + y*ystride + x.  The
+// library uses the row-interleaved layout istride = rowlen, ystride =
+// 9*rowlen (the nine population rows of lattice row y are contiguous), which
+// keeps the 18 streams of the update kernel within a few DRAM pages.
 struct StepArgs {
     int nx, ny;
-    int pitch;    // elements per population row
-    int opitch;   // bytes per owner-map row
-    int64_t plane;  // elements per population plane (ny * pitch)
+    int rowlen;        // padded row length in elements (multiple of 64)
+    int opitch;        // bytes per owner-map row
+    int64_t istride;   // elements between populations i and i+1 of a node
+    int64_t ystride;   // elements between rows y and y+1
     int walls;
     double rho0;
 };
@@ -50,33 +55,47 @@ __device__ inline C pull_one(const T* __restrict__ f, const uint8_t* __restrict_
     } else {
         ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
         int o = own[(int64_t)ys * a.opitch + xs];
-        if (o == 0) return Sto<T>::ld(f[(int64_t)i * a.plane + (int64_t)ys * a.pitch + xs]);
+        if (o == 0) return Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)ys * a.ystride + xs]);
         sid = o;
     }
     C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
     C m = C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
-    return Sto<T>::ld(f[(int64_t)opp_(i) * a.plane + (int64_t)y * a.pitch + x]) + m;
+    return Sto<T>::ld(f[(int64_t)opp_(i) * a.istride + (int64_t)y * a.ystride + x]) + m;
 }
 
 // ------------------------------------------------------------------ step
-// One thread per node.  Fast path: none of the eight source nodes is solid or
-// a wall, so the nine loads are issued unconditionally.
+// Streaming memory access: every population is read once and written once per
+// step, so both directions bypass cache retention (nontemporal hint).
+template <typename T>
+__device__ inline T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
+template <>
+__device__ inline bf16_t ld_stream(const bf16_t* p) {
+    bf16_t r;
+    r.bits = __builtin_nontemporal_load(&p->bits);
+    return r;
+}
+template <typename T>
+__device__ inline void st_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+template <>
+__device__ inline void st_stream(bf16_t* p, bf16_t v) { __builtin_nontemporal_store(v.bits, &p->bits); }
+
+// One thread per node, each wave 64 consecutive nodes of one row.  The nine
+// pull loads of the interior case are issued together with the owner loads;
+// only when a source node is solid (or a wall row) are they replaced by the
+// per-direction bounce-back values.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* __restrict__ fout,
                                                  const uint8_t* __restrict__ own_t,
                                                  const double* __restrict__ vtab, StepArgs a,
                                                  CollideParams<typename Sto<T>::C> cp) {
     using C = typename Sto<T>::C;
-    // each wave takes 64 consecutive nodes of one row (pitch is a multiple of
-    // 64), so the row and column base are wave-uniform scalars
+    // row and column base are wave-uniform scalars
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t wpr = (uint32_t)a.pitch >> 6;
+    const uint32_t wpr = (uint32_t)a.rowlen >> 6;
     const uint32_t gw = b * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int y = (int)(gw / wpr);
     const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
     if (y >= a.ny || x >= a.nx) return;
-    const int64_t orow = (int64_t)y * a.opitch;
-    if (own_t[orow + x]) return;  // solid at t (newborn nodes are refilled by k_move)
 
     const int xm = x == 0 ? a.nx - 1 : x - 1;
     const int xp = x == a.nx - 1 ? 0 : x + 1;
@@ -92,214 +111,40 @@ __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* _
         yp = y == a.ny - 1 ? 0 : y + 1;
     }
     const uint8_t* om = own_t + (int64_t)ym * a.opitch;
-    const uint8_t* o0 = own_t + orow;
+    const uint8_t* o0 = own_t + (int64_t)y * a.opitch;
     const uint8_t* op = own_t + (int64_t)yp * a.opitch;
+    const uint32_t self = o0[x];
     // owners of the sources x - e_i
     const uint32_t s1 = o0[xm], s3 = o0[xp];
     const uint32_t s2 = om[x], s5 = om[xm], s6 = om[xp];
     const uint32_t s4 = op[x], s7 = op[xp], s8 = op[xm];
-    const bool special = (s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0 || wall_lo || wall_hi;
 
-    const int64_t P = a.plane;
-    const T* r0 = fin + (int64_t)y * a.pitch;
-    const T* rm = fin + (int64_t)ym * a.pitch;
-    const T* rp = fin + (int64_t)yp * a.pitch;
+    const int64_t P = a.istride;
+    const T* r0 = fin + (int64_t)y * a.ystride;
+    const T* rm = fin + (int64_t)ym * a.ystride;
+    const T* rp = fin + (int64_t)yp * a.ystride;
+    T raw[9];
+    raw[0] = ld_stream(r0 + x);
+    raw[1] = ld_stream(r0 + P + xm);
+    raw[2] = ld_stream(rm + 2 * P + x);
+    raw[3] = ld_stream(r0 + 3 * P + xp);
+    raw[4] = ld_stream(rp + 4 * P + x);
+    raw[5] = ld_stream(rm + 5 * P + xm);
+    raw[6] = ld_stream(rm + 6 * P + xp);
+    raw[7] = ld_stream(rp + 7 * P + xp);
+    raw[8] = ld_stream(rp + 8 * P + xm);
+    if (self) return;  // solid at t (a newborn node is refilled by k_move)
     C d[9];
-    if (!special) {
-        d[0] = Sto<T>::ld(r0[x]);
-        d[1] = Sto<T>::ld(r0[P + xm]);
-        d[2] = Sto<T>::ld(rm[2 * P + x]);
-        d[3] = Sto<T>::ld(r0[3 * P + xp]);
-        d[4] = Sto<T>::ld(rp[4 * P + x]);
-        d[5] = Sto<T>::ld(rm[5 * P + xm]);
-        d[6] = Sto<T>::ld(rm[6 * P + xp]);
-        d[7] = Sto<T>::ld(rp[7 * P + xp]);
-        d[8] = Sto<T>::ld(rp[8 * P + xm]);
-    } else {
-        d[0] = Sto<T>::ld(r0[x]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
+    if ((s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0 || wall_lo || wall_hi) {
 #pragma unroll
         for (int i = 1; i < 9; ++i) d[i] = pull_one<T, C>(fin, own_t, vtab, a, x, y, i);
     }
     collide<C>(d, cp);
-    T* w0 = fout + (int64_t)y * a.pitch + x;
+    T* w0 = fout + (int64_t)y * a.ystride + x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) w0[i * P] = Sto<T>::st(d[i]);
-}
-
-// ------------------------------------------------------------------ step, 4 nodes per lane
-// Same arithmetic as k_step, four consecutive x per lane (a wave covers 256
-// columns of one row).  Each population row is read with one aligned
-// 4-element load per lane; the populations streaming in along +x / -x need
-// the neighbouring lane's last / first element, which comes through a
-// cross-lane shift (the wave's edge lanes and the row ends load it
-// directly, with periodic wrap).  Needs nx % 4 == 0.  A lane whose 4 nodes
-// or their 18 source nodes touch a solid or a wall row takes the per-node
-// path of k_step.
-template <typename T>
-struct alignas(4 * sizeof(T)) Pack4 {
-    T v[4];
-};
-
-template <typename T>
-__device__ inline T shfl_up1(T v) { return __shfl_up(v, 1, 64); }
-template <typename T>
-__device__ inline T shfl_down1(T v) { return __shfl_down(v, 1, 64); }
-template <>
-__device__ inline _Float16 shfl_up1(_Float16 v) {
-    int b = (int)__builtin_bit_cast(uint16_t, v);
-    return __builtin_bit_cast(_Float16, (uint16_t)__shfl_up(b, 1, 64));
-}
-template <>
-__device__ inline _Float16 shfl_down1(_Float16 v) {
-    int b = (int)__builtin_bit_cast(uint16_t, v);
-    return __builtin_bit_cast(_Float16, (uint16_t)__shfl_down(b, 1, 64));
-}
-template <>
-__device__ inline bf16_t shfl_up1(bf16_t v) {
-    bf16_t r;
-    r.bits = (uint16_t)__shfl_up((int)v.bits, 1, 64);
-    return r;
-}
-template <>
-__device__ inline bf16_t shfl_down1(bf16_t v) {
-    bf16_t r;
-    r.bits = (uint16_t)__shfl_down((int)v.bits, 1, 64);
-    return r;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_step4(const T* __restrict__ fin, T* __restrict__ fout,
-                                                  const uint8_t* __restrict__ own_t,
-                                                  const double* __restrict__ vtab, StepArgs a,
-                                                  CollideParams<typename Sto<T>::C> cp) {
-    using C = typename Sto<T>::C;
-    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t wpr = ((uint32_t)a.nx + 255u) >> 8;  // waves per row
-    const uint32_t gw = b * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int y = (int)(gw / wpr);
-    if (y >= a.ny) return;  // whole wave
-    const int lane = (int)(threadIdx.x & 63);
-    const int x = (int)((gw - (uint32_t)y * wpr) << 8) + 4 * lane;
-    const bool active = x < a.nx;
-    // highest active lane of this wave: it fetches the column right of its group
-    const int ll = (a.nx - 1 - (int)((gw - (uint32_t)y * wpr) << 8)) >> 2;
-    const int last_lane = ll < 63 ? ll : 63;
-
-    bool wall_lo = false, wall_hi = false;
-    int ym, yp;
-    if (a.walls) {
-        wall_lo = (y == 0);
-        wall_hi = (y == a.ny - 1);
-        ym = wall_lo ? y : y - 1;
-        yp = wall_hi ? y : y + 1;
-    } else {
-        ym = y == 0 ? a.ny - 1 : y - 1;
-        yp = y == a.ny - 1 ? 0 : y + 1;
-    }
-    const int xl = x == 0 ? a.nx - 1 : x - 1;          // column left of the group
-    const int xr = x + 4 >= a.nx ? x + 4 - a.nx : x + 4;  // column right of the group
-
-    // ---- owners: 4 bytes per row at x, plus the bytes at x-1 and x+4
-    const uint8_t* om = own_t + (int64_t)ym * a.opitch;
-    const uint8_t* o0 = own_t + (int64_t)y * a.opitch;
-    const uint8_t* op = own_t + (int64_t)yp * a.opitch;
-    uint32_t wm = 0, w0 = 0, wp = 0;
-    if (active) {
-        wm = *reinterpret_cast<const uint32_t*>(om + x);
-        w0 = *reinterpret_cast<const uint32_t*>(o0 + x);
-        wp = *reinterpret_cast<const uint32_t*>(op + x);
-    }
-    // neighbour lanes' edge bytes
-    uint32_t lm = (uint32_t)__shfl_up((int)(wm >> 24), 1, 64);
-    uint32_t l0 = (uint32_t)__shfl_up((int)(w0 >> 24), 1, 64);
-    uint32_t lp = (uint32_t)__shfl_up((int)(wp >> 24), 1, 64);
-    uint32_t rm = (uint32_t)__shfl_down((int)(wm & 0xffu), 1, 64);
-    uint32_t r0 = (uint32_t)__shfl_down((int)(w0 & 0xffu), 1, 64);
-    uint32_t rp = (uint32_t)__shfl_down((int)(wp & 0xffu), 1, 64);
-    if (active && lane == 0) {
-        lm = om[xl];
-        l0 = o0[xl];
-        lp = op[xl];
-    }
-    if (active && lane == last_lane) {
-        rm = om[xr];
-        r0 = o0[xr];
-        rp = op[xr];
-    }
-    const bool special = (wm | w0 | wp | lm | l0 | lp | rm | r0 | rp) != 0 || wall_lo || wall_hi;
-
-    // ---- populations: one 4-wide load per direction (row y - e_iy)
-    const int64_t P = a.plane;
-    const T* r_0 = fin + (int64_t)y * a.pitch;
-    const T* r_m = fin + (int64_t)ym * a.pitch;
-    const T* r_p = fin + (int64_t)yp * a.pitch;
-    const T* rowp[9] = {r_0, r_0, r_m, r_0, r_p, r_m, r_m, r_p, r_p};
-    Pack4<T> V[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        if (active) {
-            V[i] = *reinterpret_cast<const Pack4<T>*>(rowp[i] + i * P + x);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) V[i].v[k] = Sto<T>::st(C(0));
-        }
-    }
-    // ---- the x-shifted elements: +x movers need x-1, -x movers need x+4
-    T L1 = shfl_up1(V[1].v[3]), L5 = shfl_up1(V[5].v[3]), L8 = shfl_up1(V[8].v[3]);
-    T R3 = shfl_down1(V[3].v[0]), R6 = shfl_down1(V[6].v[0]), R7 = shfl_down1(V[7].v[0]);
-    if (active && lane == 0) {
-        L1 = rowp[1][1 * P + xl];
-        L5 = rowp[5][5 * P + xl];
-        L8 = rowp[8][8 * P + xl];
-    }
-    if (active && lane == last_lane) {
-        R3 = rowp[3][3 * P + xr];
-        R6 = rowp[6][6 * P + xr];
-        R7 = rowp[7][7 * P + xr];
-    }
-    if (!active) return;
-
-    const int64_t orow_f = (int64_t)y * a.pitch;
-    if (!special) {
-        // nodes in increasing x; L* roll forward (node k+1's left value is
-        // node k's original element), the -x movers read element k+1, which
-        // is still unmodified
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            C d[9];
-            d[0] = Sto<T>::ld(V[0].v[k]);
-            d[1] = Sto<T>::ld(L1);
-            d[2] = Sto<T>::ld(V[2].v[k]);
-            d[3] = Sto<T>::ld(k == 3 ? R3 : V[3].v[k < 3 ? k + 1 : 3]);
-            d[4] = Sto<T>::ld(V[4].v[k]);
-            d[5] = Sto<T>::ld(L5);
-            d[6] = Sto<T>::ld(k == 3 ? R6 : V[6].v[k < 3 ? k + 1 : 3]);
-            d[7] = Sto<T>::ld(k == 3 ? R7 : V[7].v[k < 3 ? k + 1 : 3]);
-            d[8] = Sto<T>::ld(L8);
-            L1 = V[1].v[k];
-            L5 = V[5].v[k];
-            L8 = V[8].v[k];
-            collide<C>(d, cp);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) V[i].v[k] = Sto<T>::st(d[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i) *reinterpret_cast<Pack4<T>*>(fout + i * P + orow_f + x) = V[i];
-    } else {
-        // per-node path for the nodes fluid at t; solid nodes are not written
-        // (a newborn node among them belongs to the mover kernel)
-        for (int k = 0; k < 4; ++k) {
-            const int xk = x + k;
-            if (o0[xk] != 0) continue;
-            C d[9];
-            d[0] = Sto<T>::ld(r_0[xk]);
-#pragma unroll
-            for (int i = 1; i < 9; ++i) d[i] = pull_one<T, C>(fin, own_t, vtab, a, xk, y, i);
-            collide<C>(d, cp);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fout[i * P + orow_f + xk] = Sto<T>::st(d[i]);
-        }
-    }
+    for (int i = 0; i < 9; ++i) st_stream(w0 + i * P, Sto<T>::st(d[i]));
 }
 
 // ------------------------------------------------------------------ init
@@ -314,13 +159,13 @@ __global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_
                                                  const FT* __restrict__ uy) {
     using C = typename Sto<T>::C;
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int y = (int)(idx / a.pitch);
-    const int x = (int)(idx - (int64_t)y * a.pitch);
+    const int y = (int)(idx / a.rowlen);
+    const int x = (int)(idx - (int64_t)y * a.rowlen);
     if (y >= a.ny || x >= a.nx) return;
-    T* w0 = f + (int64_t)y * a.pitch + x;
+    T* w0 = f + (int64_t)y * a.ystride + x;
     if (own[(int64_t)y * a.opitch + x] != 0) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) w0[i * a.plane] = Sto<T>::st(C(0));
+        for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(C(0));
         return;
     }
     C d[9];
@@ -332,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_
     }
     collide<C>(d, cp);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) w0[i * a.plane] = Sto<T>::st(d[i]);
+    for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(d[i]);
 }
 
 // ------------------------------------------------------------------ fields
@@ -347,8 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_fields(const T* __restrict__ f,
                                                    uint8_t* __restrict__ own_o,
                                                    int* __restrict__ errflag) {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int y = (int)(idx / a.pitch);
-    const int x = (int)(idx - (int64_t)y * a.pitch);
+    const int y = (int)(idx / a.rowlen);
+    const int x = (int)(idx - (int64_t)y * a.rowlen);
     if (y >= a.ny || x >= a.nx) return;
     const int64_t n = (int64_t)y * a.nx + x;
     const uint8_t o = own[(int64_t)y * a.opitch + x];
@@ -356,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(const T* __restrict__ f,
     if (o == 0) {
         double d[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = (double)Sto<T>::ld(f[i * a.plane + (int64_t)y * a.pitch + x]);
+        for (int i = 0; i < 9; ++i) d[i] = (double)Sto<T>::ld(f[i * a.istride + (int64_t)y * a.ystride + x]);
         double drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
         r = a.rho0 + drho;
         double jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
@@ -377,14 +222,14 @@ __global__ __launch_bounds__(kBlock) void k_populations(const T* __restrict__ f,
                                                         const uint8_t* __restrict__ own,
                                                         StepArgs a, double* __restrict__ out) {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int y = (int)(idx / a.pitch);
-    const int x = (int)(idx - (int64_t)y * a.pitch);
+    const int y = (int)(idx / a.rowlen);
+    const int x = (int)(idx - (int64_t)y * a.rowlen);
     if (y >= a.ny || x >= a.nx) return;
     const bool fl = own[(int64_t)y * a.opitch + x] == 0;
     const int64_t nn = (int64_t)a.nx * a.ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        double v = fl ? w_<double>(i) * a.rho0 + (double)Sto<T>::ld(f[i * a.plane + (int64_t)y * a.pitch + x])
+        double v = fl ? w_<double>(i) * a.rho0 + (double)Sto<T>::ld(f[i * a.istride + (int64_t)y * a.ystride + x])
                       : 0.0;
         out[i * nn + (int64_t)y * a.nx + x] = v;
     }
@@ -546,8 +391,8 @@ constexpr int kMoverGap = 8;
 constexpr int kNewbornBatch = 16;
 
 struct MoveArgs {
-    int nx, ny, pitch, opitch, walls;
-    int64_t plane;
+    int nx, ny, opitch, walls;
+    int64_t istride, ystride;
     double rho0;
     int refill;     // 0 A1, 1 A2, 2 A3
     int box_bytes;  // capacity of each LDS byte map
@@ -718,12 +563,12 @@ __global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* _
                 if (j != 0 && o != 0) {
                     const int sid = o == kWallMark ? 0 : o;
                     const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-                    v = Sto<T>::ld(fin[(int64_t)opp_(j) * a.plane + (int64_t)gy * a.pitch + gx]) +
+                    v = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]) +
                         C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
                 } else {
                     int sx, sy;
                     gidx(qs, sx, sy);
-                    v = Sto<T>::ld(fin[(int64_t)j * a.plane + (int64_t)sy * a.pitch + sx]);
+                    v = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)sy * a.ystride + sx]);
                 }
                 nb_val[b][k - 1][m - 1][j] = v;
             }
@@ -762,9 +607,9 @@ __global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* _
                 collide<C>(d, cp);
                 int gx, gy;
                 gidx(nb_list[threadIdx.x], gx, gy);
-                T* w0 = fout + (int64_t)gy * a.pitch + gx;
+                T* w0 = fout + (int64_t)gy * a.ystride + gx;
 #pragma unroll
-                for (int j = 0; j < 9; ++j) w0[j * a.plane] = Sto<T>::st(d[j]);
+                for (int j = 0; j < 9; ++j) w0[j * a.istride] = Sto<T>::st(d[j]);
             }
             __syncthreads();
         }
@@ -775,8 +620,8 @@ __global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* _
 constexpr int kForceChunk = 512;  // links per workgroup
 
 struct ForceArgs {
-    int nx, ny, pitch, walls;
-    int64_t plane;
+    int nx, ny, walls;
+    int64_t istride, ystride;
     double rho0;
     int64_t hist_cap;
     int nsol;     // bodies + 1
@@ -845,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_force(const T* __restrict__ f,
             case 7: ex = -1; ey = -1; w = 1.0 / 36.0; break;
             default: ex = 1; ey = -1; w = 1.0 / 36.0; break;
         }
-        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.plane + (int64_t)y * a.pitch + x]);
+        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
         const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
         // CME: e_i a - e_ibar b, e_ibar = -e_i
         const double cfx = ex * av + ex * bv;
@@ -916,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f
         const int y = (int)(node / (uint32_t)a.nx);
         const int x = (int)(node - (uint32_t)y * (uint32_t)a.nx);
         const double ex = ex_(i), ey = ey_(i), w = w_<double>(i);
-        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.plane + (int64_t)y * a.pitch + x]);
+        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
         const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
         double* r = out + 8 * (int64_t)(rec_off[s] + k);
         r[0] = x;
