@@ -30,6 +30,10 @@ void set_err(char* buf, const char* fmt, ...) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Working sets above this use nontemporal loads/stores in the update kernel
+// (MI355X has a 256 MB Infinity Cache).
+constexpr size_t kStreamBytes = 256ull << 20;
+
 size_t dtype_size(int dt) {
     switch (dt) {
         case LBM_F64: return 8;
@@ -307,11 +311,13 @@ lbm_status enqueue_step(lbm_ctx* c) {
     const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
     hipEvent_t e0 = timed ? c->ev[c->ev_used] : nullptr, e1 = timed ? c->ev[c->ev_used + 1] : nullptr;
     const dim3 grid((unsigned)node_blocks(c));
+    // both population buffers larger than the Infinity Cache: stream them
+    const bool nt = 2 * (c->L.f[1] - c->L.f[0]) > kStreamBytes;
+    auto kern = nt ? k_step<T, true> : k_step<T, false>;
     if (timed)
-        hipExtLaunchKernelGGL(k_step<T>, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt, sa,
-                              cp);
+        hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt, sa, cp);
     else
-        k_step<T><<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
+        kern<<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
     if (timed) c->ev_used += 2;
     c->t += 1;
     return LBM_OK;

@@ -66,24 +66,36 @@ __device__ inline C pull_one(const T* __restrict__ f, const uint8_t* __restrict_
 // ------------------------------------------------------------------ step
 // Streaming memory access: every population is read once and written once per
 // step, so both directions bypass cache retention (nontemporal hint).
-template <typename T>
-__device__ inline T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
-template <>
+// NT = false keeps ordinary loads and stores (a working set that fits the
+// 256 MB Infinity Cache is better served from it).
+template <bool NT, typename T>
+__device__ inline T ld_stream(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT>
 __device__ inline bf16_t ld_stream(const bf16_t* p) {
     bf16_t r;
-    r.bits = __builtin_nontemporal_load(&p->bits);
+    if constexpr (NT) r.bits = __builtin_nontemporal_load(&p->bits);
+    else r.bits = p->bits;
     return r;
 }
-template <typename T>
-__device__ inline void st_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
-template <>
-__device__ inline void st_stream(bf16_t* p, bf16_t v) { __builtin_nontemporal_store(v.bits, &p->bits); }
+template <bool NT, typename T>
+__device__ inline void st_stream(T* p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <bool NT>
+__device__ inline void st_stream(bf16_t* p, bf16_t v) {
+    if constexpr (NT) __builtin_nontemporal_store(v.bits, &p->bits);
+    else p->bits = v.bits;
+}
 
 // One thread per node, each wave 64 consecutive nodes of one row.  The nine
 // pull loads of the interior case are issued together with the owner loads;
 // only when a source node is solid (or a wall row) are they replaced by the
 // per-direction bounce-back values.
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* __restrict__ fout,
                                                  const uint8_t* __restrict__ own_t,
                                                  const double* __restrict__ vtab, StepArgs a,
@@ -124,15 +136,15 @@ __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* _
     const T* rm = fin + (int64_t)ym * a.ystride;
     const T* rp = fin + (int64_t)yp * a.ystride;
     T raw[9];
-    raw[0] = ld_stream(r0 + x);
-    raw[1] = ld_stream(r0 + P + xm);
-    raw[2] = ld_stream(rm + 2 * P + x);
-    raw[3] = ld_stream(r0 + 3 * P + xp);
-    raw[4] = ld_stream(rp + 4 * P + x);
-    raw[5] = ld_stream(rm + 5 * P + xm);
-    raw[6] = ld_stream(rm + 6 * P + xp);
-    raw[7] = ld_stream(rp + 7 * P + xp);
-    raw[8] = ld_stream(rp + 8 * P + xm);
+    raw[0] = ld_stream<NT>(r0 + x);
+    raw[1] = ld_stream<NT>(r0 + P + xm);
+    raw[2] = ld_stream<NT>(rm + 2 * P + x);
+    raw[3] = ld_stream<NT>(r0 + 3 * P + xp);
+    raw[4] = ld_stream<NT>(rp + 4 * P + x);
+    raw[5] = ld_stream<NT>(rm + 5 * P + xm);
+    raw[6] = ld_stream<NT>(rm + 6 * P + xp);
+    raw[7] = ld_stream<NT>(rp + 7 * P + xp);
+    raw[8] = ld_stream<NT>(rp + 8 * P + xm);
     if (self) return;  // solid at t (a newborn node is refilled by k_move)
     C d[9];
 #pragma unroll
@@ -144,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* _
     collide<C>(d, cp);
     T* w0 = fout + (int64_t)y * a.ystride + x;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_stream(w0 + i * P, Sto<T>::st(d[i]));
+    for (int i = 0; i < 9; ++i) st_stream<NT>(w0 + i * P, Sto<T>::st(d[i]));
 }
 
 // ------------------------------------------------------------------ init
