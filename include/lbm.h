@@ -172,12 +172,13 @@ lbm_status lbm_checkpoint_bytes(const lbm_ctx* ctx, size_t* bytes);
 lbm_status lbm_save(lbm_ctx* ctx, void* d_dst, size_t bytes);
 lbm_status lbm_load(lbm_ctx* ctx, const void* d_src, size_t bytes);
 
-/* Kernel timing (instrumentation).  While enabled, every lattice-update
- * launch (the fused advection + bounce-back + collision kernel, the one that
- * moves 18 populations per fluid node) is bracketed by a pair of HIP events
- * on the context's stream; lbm_profile_read synchronises and returns the
- * summed elapsed milliseconds and the number of launches since enabling.
- * Enabling resets the sums.  At most 65536 launches are recorded. */
+/* Kernel timing (instrumentation).  While enabled, every time-step launch
+ * (one kernel per step: force, moving-body and fused advection + bounce-back
+ * + collision workgroups, the last moving 18 populations per fluid node) is
+ * timed by a pair of HIP events attached to its dispatch on the context's
+ * stream; lbm_profile_read synchronises and returns the summed elapsed
+ * milliseconds and the number of launches since enabling.  Enabling resets
+ * the sums.  At most 65536 launches are recorded. */
 lbm_status lbm_profile(lbm_ctx* ctx, int32_t enable);
 lbm_status lbm_profile_read(lbm_ctx* ctx, double* update_ms, int64_t* launches);
 

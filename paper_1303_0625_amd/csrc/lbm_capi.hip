@@ -53,7 +53,7 @@ struct Layout {
     int64_t link_total;
     int n_movers;
     int nchunks;
-    int box_bytes;  // LDS byte map per translating body (k_move)
+    int box_bytes;  // LDS byte map per translating body (mover role)
 };
 
 // Conservative link capacity of one body: every fluid node adjacent to a
@@ -278,47 +278,57 @@ uint8_t* own_ptr(lbm_ctx* c, int k) {
     return wsp<uint8_t>(c, c->L.own[k]);
 }
 
-// Enqueue one time step at parity p = t & 1 for storage type T: forces on
-// G_t, translating bodies (G_{t+1}, links, refill), fused update.  The three
-// kernels read only step-t data and write disjoint outputs.
+// Enqueue one time step at parity p = t & 1 for storage type T: a single
+// launch whose workgroups compute the forces on G_t, move the translating
+// bodies (G_{t+1}, links, refill) and run the fused update.
 template <typename T>
 lbm_status enqueue_step(lbm_ctx* c) {
     using C = typename Sto<T>::C;
     const int p = (int)(c->t & 1);
-    const T* fin = wsp<T>(c, c->L.f[p]);
-    T* fout = wsp<T>(c, c->L.f[p ^ 1]);
-    const uint8_t* own_t = own_ptr(c, p);
-    uint8_t* own_n = own_ptr(c, p ^ 1);
-    int64_t* tctr = wsp<int64_t>(c, c->L.tctr);
-    int* errf = wsp<int>(c, c->L.err);
-    const SolidDev* sol = wsp<SolidDev>(c, c->L.sol);
-    k_force<T><<<c->L.nchunks, kBlock, 0, c->stream>>>(
-        fin, wsp<uint32_t>(c, c->L.links[p]), wsp<int>(c, c->L.seg_cnt[p]), wsp<int>(c, c->L.seg_off),
-        wsp<int>(c, c->L.chunk_solid), wsp<int>(c, c->L.chunk_start), wsp<int>(c, c->L.solid_chunk0),
-        sol, wsp<double>(c, c->L.partial), wsp<unsigned int>(c, c->L.ticket),
-        wsp<double>(c, c->L.hist), tctr, p, force_args(c));
-    CollideParams<C> cp = collide_params<C>(c);
-    if (c->L.n_movers > 0) {
-        MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
-                    9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes};
-        k_move<T><<<c->L.n_movers, kBlock, 2 * c->L.box_bytes, c->stream>>>(
-            fin, fout, own_t, own_n, wsp<uint32_t>(c, c->L.links[p ^ 1]),
-            wsp<int>(c, c->L.seg_cnt[p ^ 1]), wsp<int>(c, c->L.seg_off), wsp<int>(c, c->L.seg_cap),
-            sol, wsp<double>(c, c->L.vtab), wsp<int>(c, c->L.movers), tctr, p, ma, cp, errf);
-    }
+    StepPtrs<T> sp;
+    sp.fin = wsp<T>(c, c->L.f[p]);
+    sp.fout = wsp<T>(c, c->L.f[p ^ 1]);
+    sp.own_t = own_ptr(c, p);
+    sp.own_n = own_ptr(c, p ^ 1);
+    sp.links_t = wsp<uint32_t>(c, c->L.links[p]);
+    sp.seg_cnt_t = wsp<int>(c, c->L.seg_cnt[p]);
+    sp.links_n = wsp<uint32_t>(c, c->L.links[p ^ 1]);
+    sp.seg_cnt_n = wsp<int>(c, c->L.seg_cnt[p ^ 1]);
+    sp.seg_off = wsp<int>(c, c->L.seg_off);
+    sp.seg_cap = wsp<int>(c, c->L.seg_cap);
+    sp.chunk_solid = wsp<int>(c, c->L.chunk_solid);
+    sp.chunk_start = wsp<int>(c, c->L.chunk_start);
+    sp.solid_chunk0 = wsp<int>(c, c->L.solid_chunk0);
+    sp.sol = wsp<SolidDev>(c, c->L.sol);
+    sp.vtab = wsp<double>(c, c->L.vtab);
+    sp.movers = wsp<int>(c, c->L.movers);
+    sp.partial = wsp<double>(c, c->L.partial);
+    sp.ticket = wsp<unsigned int>(c, c->L.ticket);
+    sp.hist = wsp<double>(c, c->L.hist);
+    sp.tctr = wsp<int64_t>(c, c->L.tctr);
+    sp.errflag = wsp<int>(c, c->L.err);
+    RoleCounts rc;
+    rc.n_force = c->L.nchunks;
+    rc.n_move = c->L.n_movers;
+    rc.n_lead = (rc.n_force + rc.n_move + 7) / 8 * 8;
+    MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
+                9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes};
     StepArgs sa = step_args(c);
-    const double* vt = wsp<double>(c, c->L.vtab);
-    const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
-    hipEvent_t e0 = timed ? c->ev[c->ev_used] : nullptr, e1 = timed ? c->ev[c->ev_used + 1] : nullptr;
-    const dim3 grid((unsigned)node_blocks(c));
+    ForceArgs fa = force_args(c);
+    CollideParams<C> cp = collide_params<C>(c);
+    const dim3 grid((unsigned)(rc.n_lead + node_blocks(c)));
+    const size_t lds = c->L.n_movers > 0 ? 2 * (size_t)c->L.box_bytes : 0;
     // both population buffers larger than the Infinity Cache: stream them
     const bool nt = 2 * (c->L.f[1] - c->L.f[0]) > kStreamBytes;
-    auto kern = nt ? k_step<T, true> : k_step<T, false>;
-    if (timed)
-        hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), 0, c->stream, e0, e1, 0, fin, fout, own_t, vt, sa, cp);
-    else
-        kern<<<grid, kBlock, 0, c->stream>>>(fin, fout, own_t, vt, sa, cp);
-    if (timed) c->ev_used += 2;
+    auto kern = nt ? k_fused<T, true> : k_fused<T, false>;
+    const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
+    if (timed) {
+        hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), lds, c->stream, c->ev[c->ev_used],
+                              c->ev[c->ev_used + 1], 0, sp, p, rc, sa, ma, fa, cp);
+        c->ev_used += 2;
+    } else {
+        kern<<<grid, kBlock, lds, c->stream>>>(sp, p, rc, sa, ma, fa, cp);
+    }
     c->t += 1;
     return LBM_OK;
 }

@@ -3,16 +3,17 @@
 // State convention: the workspace holds the post-collision deviations
 // d~_i(x, t) = f~_i(x, t) - w_i rho0 of every fluid node of geometry G_t, SoA
 // [9][ny][pitch], in two ping-pong buffers selected by the parity of t.  One
-// time step t -> t+1 is three kernels that read only step-t data and write
-// disjoint outputs, so they may run in any order or concurrently:
-//   k_force    Eqs. 4-7 on the link lists of G_t (reads f~(t)), chunked over
+// time step t -> t+1 is one launch of k_fused whose workgroups take one of
+// three roles; the roles read only step-t data and write disjoint outputs,
+// so they run concurrently:
+//   force      Eqs. 4-7 on the link lists of G_t (reads f~(t)), chunked over
 //              workgroups, with a fixed-order final sum per solid
-//   k_move     per translating body: owner map of G_{t+1} in its swept box,
+//   move       per translating body: owner map of G_{t+1} in its swept box,
 //              its link list for G_{t+1} (into the other link buffer), and the
 //              refill of its newborn nodes (solid in G_t, fluid in G_{t+1}),
 //              extrapolated from old-fluid neighbours' post-advection values
 //              and collided
-//   k_step     pull-advection (Eq. 3) with half-way bounce-back on G_t, then
+//   step       pull-advection (Eq. 3) with half-way bounce-back on G_t, then
 //              collision (Eq. 2), for every node fluid in G_t (a node covered
 //              by a body at t+1 is written too and never read again)
 #pragma once
@@ -94,15 +95,16 @@ __device__ inline void st_stream(bf16_t* p, bf16_t v) {
 // One thread per node, each wave 64 consecutive nodes of one row.  The nine
 // pull loads of the interior case are issued together with the owner loads;
 // only when a source node is solid (or a wall row) are they replaced by the
-// per-direction bounce-back values.
+// per-direction bounce-back values.  bid/nblk: this workgroup's index among
+// the update workgroups (remapped so that each XCD walks a contiguous band).
 template <typename T, bool NT>
-__global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* __restrict__ fout,
-                                                 const uint8_t* __restrict__ own_t,
-                                                 const double* __restrict__ vtab, StepArgs a,
-                                                 CollideParams<typename Sto<T>::C> cp) {
+__device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restrict__ fin,
+                                 T* __restrict__ fout, const uint8_t* __restrict__ own_t,
+                                 const double* __restrict__ vtab, const StepArgs& a,
+                                 const CollideParams<typename Sto<T>::C>& cp) {
     using C = typename Sto<T>::C;
     // row and column base are wave-uniform scalars
-    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t b = xcd_remap(bid, nblk);
     const uint32_t wpr = (uint32_t)a.rowlen >> 6;
     const uint32_t gw = b * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int y = (int)(gw / wpr);
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const T* __restrict__ fin, T* _
     raw[6] = ld_stream<NT>(rm + 6 * P + xp);
     raw[7] = ld_stream<NT>(rp + 7 * P + xp);
     raw[8] = ld_stream<NT>(rp + 8 * P + xm);
-    if (self) return;  // solid at t (a newborn node is refilled by k_move)
+    if (self) return;  // solid at t (a newborn node is refilled by the mover role)
     C d[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
@@ -400,7 +402,8 @@ __global__ __launch_bounds__(kBlock) void k_links(const uint8_t* __restrict__ ow
 constexpr int kBoxMargin = 5;
 constexpr uint8_t kWallMark = 255;
 constexpr int kMoverGap = 8;
-constexpr int kNewbornBatch = 16;
+constexpr int kNewbornBatch = 8;   // newborn nodes refilled together
+constexpr int kNewbornMax = 128;   // newborn nodes of one body in one step
 
 struct MoveArgs {
     int nx, ny, opitch, walls;
@@ -424,36 +427,37 @@ __device__ inline void swept_box(const SolidDev& S, int64_t t, long& x0, long& x
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* __restrict__ fout,
-                                                 const uint8_t* __restrict__ own_t,
-                                                 uint8_t* __restrict__ own_n,
-                                                 uint32_t* __restrict__ links_n,
-                                                 int* __restrict__ seg_cnt_n,
-                                                 const int* __restrict__ seg_off,
-                                                 const int* __restrict__ seg_cap,
-                                                 const SolidDev* __restrict__ sol,
-                                                 const double* __restrict__ vtab,
-                                                 const int* __restrict__ movers,
-                                                 const int64_t* __restrict__ tctr, int parity,
-                                                 MoveArgs a, CollideParams<typename Sto<T>::C> cp,
-                                                 int* __restrict__ errflag) {
+struct MoveShared {
     using C = typename Sto<T>::C;
-    extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ int sh_scan[kBlock];
-    __shared__ int nb_list[kNewbornBatch];
-    __shared__ int8_t nb_use[kNewbornBatch][8];  // -1: no participation, else 0/1/2
-    __shared__ C nb_val[kNewbornBatch][8][3][9];
-    __shared__ C nb_new[kNewbornBatch][9];
+    int scan[kBlock];
+    int nb_count;
+    int nb_list[kNewbornMax];
+    int8_t nb_use[kNewbornBatch][8];  // -1: no participation, else 0/1/2
+    C nb_val[kNewbornBatch][8][3][9];
+    C nb_new[kNewbornBatch][9];
+};
+
+// Mover role for body movers[m]; lds holds the two byte maps (2 * box_bytes).
+template <typename T>
+__device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>& sm,
+                                 const T* __restrict__ fin, T* __restrict__ fout,
+                                 const uint8_t* __restrict__ own_t, uint8_t* __restrict__ own_n,
+                                 uint32_t* __restrict__ links_n, int* __restrict__ seg_cnt_n,
+                                 const int* __restrict__ seg_off, const int* __restrict__ seg_cap,
+                                 const SolidDev* __restrict__ sol, const double* __restrict__ vtab,
+                                 const int* __restrict__ movers, const int64_t* __restrict__ tctr,
+                                 int parity, const MoveArgs& a,
+                                 const CollideParams<typename Sto<T>::C>& cp, int* __restrict__ errflag) {
+    using C = typename Sto<T>::C;
     uint8_t* ot = lds;
     uint8_t* on = lds + a.box_bytes;
-
-    const int s = movers[blockIdx.x];
+    const int s = movers[m];
     const SolidDev S = sol[s];
     const int64_t t = tctr[parity];
     long x0, x1, y0, y1;
     swept_box(S, t, x0, x1, y0, y1);
     const int W = (int)(x1 - x0 + 1), H = (int)(y1 - y0 + 1), N = W * H;
-    if (N > a.box_bytes) {  // host sizes the box; never expected
+    if (N > a.box_bytes) {  // the host sizes the box for the largest mover
         if (threadIdx.x == 0) atomicOr(errflag, 4);
         return;
     }
@@ -464,32 +468,51 @@ __global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* _
         gy = wrapi(yy, a.ny);
         return true;
     };
-    // 1. stage both owner maps
-    for (int q = threadIdx.x; q < N; q += kBlock) {
-        int gx, gy;
-        if (gidx(q, gx, gy)) {
-            const int64_t o = (int64_t)gy * a.opitch + gx;
-            ot[q] = own_t[o];
-            on[q] = own_n[o];
-        } else {
-            ot[q] = kWallMark;
-            on[q] = kWallMark;
+    if (threadIdx.x == 0) sm.nb_count = 0;
+    // 1. stage both owner maps; loads of a round are issued before any store
+    constexpr int R = 8;
+    for (int q0 = 0; q0 < N; q0 += R * kBlock) {
+        uint8_t vt[R], vn[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int q = q0 + r * kBlock + threadIdx.x;
+            int gx, gy;
+            vt[r] = vn[r] = kWallMark;
+            if (q < N && gidx(q, gx, gy)) {
+                const int64_t o = (int64_t)gy * a.opitch + gx;
+                vt[r] = own_t[o];
+                vn[r] = own_n[o];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int q = q0 + r * kBlock + threadIdx.x;
+            if (q < N) {
+                ot[q] = vt[r];
+                on[q] = vn[r];
+            }
         }
     }
     __syncthreads();
-    // 2. G_{t+1}: rasterise the body at t+1, clear what it left
+    // 2. G_{t+1}: rasterise the body at t+1, clear what it left; collect the
+    // newborn nodes (solid at t, fluid at t+1); their order in the list does
+    // not affect any value
     double Xn, Yn;
     solid_pos(S, t + 1, Xn, Yn);
     for (int q = threadIdx.x; q < N; q += kBlock) {
         if (on[q] == kWallMark) continue;
         const long yy = y0 + q / W, xx = x0 + q % W;
-        uint8_t v = on[q];
-        uint8_t nv = solid_inside(S, Xn, Yn, xx, yy) ? (uint8_t)s : (v == s ? (uint8_t)0 : v);
+        const uint8_t v = on[q];
+        const uint8_t nv = solid_inside(S, Xn, Yn, xx, yy) ? (uint8_t)s : (v == s ? (uint8_t)0 : v);
         if (nv != v) {
             on[q] = nv;
             int gx, gy;
             gidx(q, gx, gy);
             own_n[(int64_t)gy * a.opitch + gx] = nv;
+        }
+        if (ot[q] == s && nv == 0) {
+            const int k = atomicAdd(&sm.nb_count, 1);
+            if (k < kNewbornMax) sm.nb_list[k] = q;
         }
     }
     __syncthreads();
@@ -518,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* _
         int cnt = 0;
         for (int q = q0; q < q1; ++q) cnt += links_at(q, nullptr, 0);
         int total;
-        int off = block_exclusive_scan(cnt, sh_scan, total);
+        int off = block_exclusive_scan(cnt, sm.scan, total);
         const int cap = seg_cap[s];
         if (total <= cap) {
             uint32_t* L = links_n + seg_off[s];
@@ -529,102 +552,99 @@ __global__ __launch_bounds__(kBlock) void k_move(const T* __restrict__ fin, T* _
             if (total > cap) atomicOr(errflag, 1);
         }
     }
-    // 4. newborn nodes, in batches: refill and collide
+    // 4. refill the newborn nodes in batches, then collide and store
+    const int nborn = sm.nb_count;
+    if (nborn > kNewbornMax) {
+        if (threadIdx.x == 0) atomicOr(errflag, 4);
+        return;
+    }
     const C rho0 = (C)a.rho0;
-    for (int qb = 0; qb < N; qb += kBlock) {
-        const int q = qb + threadIdx.x;
-        const int born = (q < N && ot[q] == s && on[q] == 0) ? 1 : 0;
-        int total;
-        const int pos = block_exclusive_scan(born, sh_scan, total);
-        for (int base = 0; base < total; base += kNewbornBatch) {
-            if (born && pos >= base && pos < base + kNewbornBatch) nb_list[pos - base] = q;
-            const int nbat = total - base < kNewbornBatch ? total - base : kNewbornBatch;
-            __syncthreads();
-            // 4a. participation and scheme per (newborn, direction)
-            if (threadIdx.x < nbat * 8) {
-                const int b = threadIdx.x / 8, k = threadIdx.x % 8 + 1;
-                const int qn = nb_list[b];
-                bool ok[4] = {false, false, false, false};
-                for (int m = 1; m <= 3; ++m) {
-                    const int qm = qn + m * (ey_(k) * W + ex_(k));
-                    ok[m] = ot[qm] == 0 && on[qm] == 0;
-                    if (!ok[m]) break;
-                }
-                int use = -1;
-                if (ok[1]) {
-                    use = a.refill;
-                    if (use == 0 && !(ok[2] && ok[3])) use = 1;
-                    if (use == 1 && !ok[2]) use = 2;
-                }
-                nb_use[b][k - 1] = (int8_t)use;
+    for (int base = 0; base < nborn; base += kNewbornBatch) {
+        const int nbat = nborn - base < kNewbornBatch ? nborn - base : kNewbornBatch;
+        // 4a. participation and scheme per (newborn, direction)
+        if (threadIdx.x < nbat * 8) {
+            const int bb = threadIdx.x / 8, k = threadIdx.x % 8 + 1;
+            const int qn = sm.nb_list[base + bb];
+            bool ok[4] = {false, false, false, false};
+            for (int mm = 1; mm <= 3; ++mm) {
+                const int qm = qn + mm * (ey_(k) * W + ex_(k));
+                ok[mm] = ot[qm] == 0 && on[qm] == 0;
+                if (!ok[mm]) break;
             }
-            __syncthreads();
-            // 4b. post-advection values at the stencil nodes, in parallel
-            for (int w = threadIdx.x; w < nbat * 216; w += kBlock) {
-                const int b = w / 216, r = w % 216;
-                const int k = r / 27 + 1, m = (r % 27) / 9 + 1, j = r % 9;
-                const int use = nb_use[b][k - 1];
-                const int need = use == 0 ? 3 : (use == 1 ? 2 : (use == 2 ? 1 : 0));
-                if (m > need) continue;
-                const int qm = nb_list[b] + m * (ey_(k) * W + ex_(k));
-                int gx, gy;
-                gidx(qm, gx, gy);
-                const int qs = qm - (ey_(j) * W + ex_(j));  // source of population j
-                const uint8_t o = ot[qs];
-                C v;
-                if (j != 0 && o != 0) {
-                    const int sid = o == kWallMark ? 0 : o;
-                    const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-                    v = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]) +
-                        C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
-                } else {
-                    int sx, sy;
-                    gidx(qs, sx, sy);
-                    v = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)sy * a.ystride + sx]);
-                }
-                nb_val[b][k - 1][m - 1][j] = v;
+            int use = -1;
+            if (ok[1]) {
+                use = a.refill;
+                if (use == 0 && !(ok[2] && ok[3])) use = 1;
+                if (use == 1 && !ok[2]) use = 2;
             }
-            __syncthreads();
-            // 4c. extrapolate along each participating link, average
-            if (threadIdx.x < nbat * 9) {
-                const int b = threadIdx.x / 9, j = threadIdx.x % 9;
-                C acc = C(0);
-                int np = 0;
-                for (int k = 0; k < 8; ++k) {
-                    const int use = nb_use[b][k];
-                    if (use < 0) continue;
-                    ++np;
-                    const C v1 = nb_val[b][k][0][j];
-                    if (use == 0)
-                        acc += C(3) * v1 - C(3) * nb_val[b][k][1][j] + nb_val[b][k][2][j];
-                    else if (use == 1)
-                        acc += C(2) * v1 - nb_val[b][k][1][j];
-                    else
-                        acc += v1;
-                }
-                if (np > 0) {
-                    nb_new[b][j] = acc / C(np);
-                } else {  // no participant: equilibrium at the body velocity
-                    C fe[9];
-                    feq_dev<C>(rho0, rho0, (C)S.vx, (C)S.vy, fe);
-                    nb_new[b][j] = fe[j];
-                }
-            }
-            __syncthreads();
-            // 4d. collide and store
-            if (threadIdx.x < nbat) {
-                C d[9];
-#pragma unroll
-                for (int j = 0; j < 9; ++j) d[j] = nb_new[threadIdx.x][j];
-                collide<C>(d, cp);
-                int gx, gy;
-                gidx(nb_list[threadIdx.x], gx, gy);
-                T* w0 = fout + (int64_t)gy * a.ystride + gx;
-#pragma unroll
-                for (int j = 0; j < 9; ++j) w0[j * a.istride] = Sto<T>::st(d[j]);
-            }
-            __syncthreads();
+            sm.nb_use[bb][k - 1] = (int8_t)use;
         }
+        __syncthreads();
+        // 4b. post-advection values at the stencil nodes, in parallel
+        for (int w = threadIdx.x; w < nbat * 216; w += kBlock) {
+            const int bb = w / 216, r = w % 216;
+            const int k = r / 27 + 1, mm = (r % 27) / 9 + 1, j = r % 9;
+            const int use = sm.nb_use[bb][k - 1];
+            const int need = use == 0 ? 3 : (use == 1 ? 2 : (use == 2 ? 1 : 0));
+            if (mm > need) continue;
+            const int qm = sm.nb_list[base + bb] + mm * (ey_(k) * W + ex_(k));
+            int gx, gy;
+            gidx(qm, gx, gy);
+            const int qs = qm - (ey_(j) * W + ex_(j));  // source of population j
+            const uint8_t o = ot[qs];
+            C v;
+            if (j != 0 && o != 0) {
+                const int sid = o == kWallMark ? 0 : o;
+                const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                v = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]) +
+                    C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
+            } else {
+                int sx, sy;
+                gidx(qs, sx, sy);
+                v = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)sy * a.ystride + sx]);
+            }
+            sm.nb_val[bb][k - 1][mm - 1][j] = v;
+        }
+        __syncthreads();
+        // 4c. extrapolate along each participating link, average
+        if (threadIdx.x < nbat * 9) {
+            const int bb = threadIdx.x / 9, j = threadIdx.x % 9;
+            C acc = C(0);
+            int np = 0;
+            for (int k = 0; k < 8; ++k) {
+                const int use = sm.nb_use[bb][k];
+                if (use < 0) continue;
+                ++np;
+                const C v1 = sm.nb_val[bb][k][0][j];
+                if (use == 0)
+                    acc += C(3) * v1 - C(3) * sm.nb_val[bb][k][1][j] + sm.nb_val[bb][k][2][j];
+                else if (use == 1)
+                    acc += C(2) * v1 - sm.nb_val[bb][k][1][j];
+                else
+                    acc += v1;
+            }
+            if (np > 0) {
+                sm.nb_new[bb][j] = acc / C(np);
+            } else {  // no participant: equilibrium at the body velocity
+                C fe[9];
+                feq_dev<C>(rho0, rho0, (C)S.vx, (C)S.vy, fe);
+                sm.nb_new[bb][j] = fe[j];
+            }
+        }
+        __syncthreads();
+        // 4d. collide and store
+        if (threadIdx.x < nbat) {
+            C d[9];
+#pragma unroll
+            for (int j = 0; j < 9; ++j) d[j] = sm.nb_new[threadIdx.x][j];
+            collide<C>(d, cp);
+            int gx, gy;
+            gidx(sm.nb_list[base + threadIdx.x], gx, gy);
+            T* w0 = fout + (int64_t)gy * a.ystride + gx;
+#pragma unroll
+            for (int j = 0; j < 9; ++j) w0[j * a.istride] = Sto<T>::st(d[j]);
+        }
+        __syncthreads();
     }
 }
 
@@ -637,7 +657,7 @@ struct ForceArgs {
     double rho0;
     int64_t hist_cap;
     int nsol;     // bodies + 1
-    int nchunks;  // workgroups of k_force
+    int nchunks;  // force workgroups
 };
 
 __device__ inline double wave_sum(double v) {
@@ -657,23 +677,21 @@ __device__ inline double wave_sum(double v) {
 // control only) sums each solid's chunk partials in chunk order.  The result
 // is therefore independent of scheduling.  That workgroup also advances the
 // step counter into the other parity slot.
+struct ForceShared {
+    double red[kBlock / 64][6];
+    int is_last;
+};
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_force(const T* __restrict__ f,
-                                                  const uint32_t* __restrict__ links,
-                                                  const int* __restrict__ seg_cnt,
-                                                  const int* __restrict__ seg_off,
-                                                  const int* __restrict__ chunk_solid,
-                                                  const int* __restrict__ chunk_start,
-                                                  const int* __restrict__ solid_chunk0,
-                                                  const SolidDev* __restrict__ sol,
-                                                  double* __restrict__ partial,
-                                                  unsigned int* __restrict__ ticket,
-                                                  double* __restrict__ hist,
-                                                  int64_t* __restrict__ tctr, int parity,
-                                                  ForceArgs a) {
-    __shared__ double sh[kBlock / 64][6];
-    __shared__ int is_last;
-    const int c = blockIdx.x;
+__device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ f,
+                                  const uint32_t* __restrict__ links,
+                                  const int* __restrict__ seg_cnt, const int* __restrict__ seg_off,
+                                  const int* __restrict__ chunk_solid,
+                                  const int* __restrict__ chunk_start,
+                                  const int* __restrict__ solid_chunk0,
+                                  const SolidDev* __restrict__ sol, double* __restrict__ partial,
+                                  unsigned int* __restrict__ ticket, double* __restrict__ hist,
+                                  int64_t* __restrict__ tctr, int parity, const ForceArgs& a) {
     const int s = chunk_solid[c];
     const int start = chunk_start[c];
     const int n = seg_cnt[s];
@@ -727,18 +745,18 @@ __global__ __launch_bounds__(kBlock) void k_force(const T* __restrict__ f,
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         double v = wave_sum(acc[q]);
-        if (lane == 0) sh[wv][q] = v;
+        if (lane == 0) fs.red[wv][q] = v;
     }
     __syncthreads();
     if (threadIdx.x < 6) {
         const int q = threadIdx.x;
-        partial[c * 6 + q] = (sh[0][q] + sh[1][q]) + (sh[2][q] + sh[3][q]);
+        partial[c * 6 + q] = (fs.red[0][q] + fs.red[1][q]) + (fs.red[2][q] + fs.red[3][q]);
     }
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) is_last = atomicAdd(ticket, 1u) == (unsigned)(a.nchunks - 1);
+    if (threadIdx.x == 0) fs.is_last = atomicAdd(ticket, 1u) == (unsigned)(a.nchunks - 1);
     __syncthreads();
-    if (!is_last) return;
+    if (!fs.is_last) return;
     __threadfence();
     const int64_t slot = t % a.hist_cap;
     for (int r = threadIdx.x; r < a.nsol * 6; r += kBlock) {
@@ -751,6 +769,66 @@ __global__ __launch_bounds__(kBlock) void k_force(const T* __restrict__ f,
         *ticket = 0u;
         tctr[parity ^ 1] = t + 1;
     }
+}
+
+// ------------------------------------------------------------------ fused step
+// One launch per time step: workgroups [0, n_force) are force chunks,
+// [n_force, n_force + n_move) are translating bodies, and from n_lead (a
+// multiple of 8, so that update workgroup j sits on XCD j % 8) on the fused
+// update.  The roles read only step-t data and write disjoint outputs, so
+// the small latency-bound roles run alongside the bandwidth-bound update.
+template <typename T>
+struct StepPtrs {
+    const T* fin;
+    T* fout;
+    const uint8_t* own_t;
+    uint8_t* own_n;
+    const uint32_t* links_t;
+    const int* seg_cnt_t;
+    uint32_t* links_n;
+    int* seg_cnt_n;
+    const int* seg_off;
+    const int* seg_cap;
+    const int* chunk_solid;
+    const int* chunk_start;
+    const int* solid_chunk0;
+    const SolidDev* sol;
+    const double* vtab;
+    const int* movers;
+    double* partial;
+    unsigned int* ticket;
+    double* hist;
+    int64_t* tctr;
+    int* errflag;
+};
+
+struct RoleCounts {
+    int n_force, n_move, n_lead;
+};
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fused(
+    StepPtrs<T> p, int parity, RoleCounts rc, StepArgs sa, MoveArgs ma, ForceArgs fa,
+    CollideParams<typename Sto<T>::C> cp) {
+    extern __shared__ __align__(16) uint8_t dyn_lds[];
+    __shared__ union Shared {
+        ForceShared f;
+        MoveShared<T> m;
+    } sh;
+    const int b = (int)blockIdx.x;
+    if (b < rc.n_lead) {
+        if (b < rc.n_force) {
+            force_role<T>(b, sh.f, p.fin, p.links_t, p.seg_cnt_t, p.seg_off, p.chunk_solid, p.chunk_start,
+                          p.solid_chunk0, p.sol, p.partial, p.ticket, p.hist, p.tctr, parity, fa);
+        } else if (b < rc.n_force + rc.n_move) {
+            move_role<T>(b - rc.n_force, dyn_lds, sh.m, p.fin, p.fout, p.own_t, p.own_n, p.links_n,
+                         p.seg_cnt_n, p.seg_off, p.seg_cap, p.sol, p.vtab, p.movers, p.tctr, parity, ma,
+                         cp, p.errflag);
+        }
+        return;
+    }
+    step_role<T, NT>((uint32_t)(b - rc.n_lead), gridDim.x - (uint32_t)rc.n_lead, p.fin, p.fout, p.own_t,
+                     p.vtab, sa, cp);
 }
 
 // Per-link force records of the current state (test and inspection path).
