@@ -49,7 +49,7 @@ struct Layout {
     int pitch, opitch;
     int64_t plane;
     size_t f[2], own[2], links[2], seg_off, seg_cap, seg_cnt[2], rec_off, sol, vtab, movers, all,
-        chunk_solid, chunk_start, solid_chunk0, partial, ticket, hist, tctr, err, total;
+        chunk_solid, chunk_start, solid_chunk0, partial, hist, tctr, err, total;
     int64_t link_total;
     int n_movers;
     int nchunks;
@@ -113,8 +113,7 @@ bool make_layout(const lbm_grid& g, const lbm_solid* solids, int n, int64_t hist
     L.chunk_solid = off; off = align256(off + 4 * (size_t)nch);
     L.chunk_start = off; off = align256(off + 4 * (size_t)nch);
     L.solid_chunk0 = off; off = align256(off + 4 * (ns + 1));
-    L.partial = off; off = align256(off + 48 * (size_t)nch);
-    L.ticket = off; off = align256(off + 4);
+    L.partial = off; off = align256(off + 2 * 48 * (size_t)nch);
     L.rec_off = off; off = align256(off + 4 * ns);
     L.sol = off; off = align256(off + sizeof(SolidDev) * ns);
     L.vtab = off; off = align256(off + 16 * ns);
@@ -201,6 +200,7 @@ struct lbm_ctx {
     size_t ws_bytes;
     Layout L;
     int64_t t;
+    int64_t hist_first = 0;  // first step whose force record is held
     std::vector<int> seg_off, seg_cap;
     int64_t link_cap_total;
     char err[512];
@@ -303,14 +303,13 @@ lbm_status enqueue_step(lbm_ctx* c) {
     sp.vtab = wsp<double>(c, c->L.vtab);
     sp.movers = wsp<int>(c, c->L.movers);
     sp.partial = wsp<double>(c, c->L.partial);
-    sp.ticket = wsp<unsigned int>(c, c->L.ticket);
     sp.hist = wsp<double>(c, c->L.hist);
     sp.tctr = wsp<int64_t>(c, c->L.tctr);
     sp.errflag = wsp<int>(c, c->L.err);
     RoleCounts rc;
     rc.n_force = c->L.nchunks;
     rc.n_move = c->L.n_movers;
-    rc.n_lead = (rc.n_force + rc.n_move + 7) / 8 * 8;
+    rc.n_lead = (rc.n_force + rc.n_move + 1 + 7) / 8 * 8;
     MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
                 9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes};
     StepArgs sa = step_args(c);
@@ -562,8 +561,7 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
     }
 
     const int64_t own_bytes = (int64_t)grid->ny * L.opitch;
-    k_set_counters<<<1, 1, 0, st>>>(wsp<int64_t>(c, L.tctr), 0, wsp<int>(c, L.err),
-                                    wsp<unsigned int>(c, L.ticket));
+    k_set_counters<<<1, 1, 0, st>>>(wsp<int64_t>(c, L.tctr), 0, wsp<int>(c, L.err));
     k_fill_u8<<<(unsigned)((own_bytes + 255) / 256), 256, 0, st>>>(wsp<uint8_t>(c, L.own[0]), own_bytes, 0);
     GeomArgs ga{grid->nx, grid->ny, L.opitch, grid->walls_y};
     if (n_solids > 0)
@@ -626,6 +624,10 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
         lbm_status s = dispatch_step(c);
         if (s != LBM_OK) return s;
     }
+    // totals of the last step (every earlier step was finalized by the launch after it)
+    k_finalize<<<1, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.partial), wsp<int>(c, c->L.solid_chunk0),
+                                            wsp<double>(c, c->L.hist), wsp<int64_t>(c, c->L.tctr),
+                                            (int)(c->t & 1), force_args(c));
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
 }
@@ -642,8 +644,8 @@ lbm_status lbm_force(lbm_ctx* c, int32_t solid_id, int32_t scheme, double out[3]
         set_err(c->err, "unknown scheme %d", scheme);
         return LBM_EINVAL;
     }
-    if (c->t == 0) {
-        set_err(c->err, "no step has been taken yet");
+    if (c->t == 0 || c->t - 1 < c->hist_first) {
+        set_err(c->err, "no step has been taken yet (since create or load)");
         return LBM_ESTATE;
     }
     double rec[6];
@@ -661,7 +663,7 @@ lbm_status lbm_force(lbm_ctx* c, int32_t solid_id, int32_t scheme, double out[3]
 
 lbm_status lbm_force_history(lbm_ctx* c, int64_t first, int64_t count, double* d_out) {
     if (!c || !d_out) return LBM_EINVAL;
-    if (first < 0 || count < 0 || first + count > c->t || first < c->t - c->hist_cap) {
+    if (first < c->hist_first || count < 0 || first + count > c->t || first < c->t - c->hist_cap) {
         set_err(c->err, "steps [%lld, %lld) are not held by the history ring (t = %lld, capacity %lld)",
                 (long long)first, (long long)(first + count), (long long)c->t, (long long)c->hist_cap);
         return LBM_EINVAL;
@@ -855,8 +857,8 @@ lbm_status lbm_load(lbm_ctx* c, const void* d_src, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.links[p], s + o, lb, hipMemcpyDeviceToDevice, c->stream));
     o += lb;
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.seg_cnt[p], s + o, 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
-    k_set_counters<<<1, 1, 0, c->stream>>>(wsp<int64_t>(c, c->L.tctr), c->t, wsp<int>(c, c->L.err),
-                                           wsp<unsigned int>(c, c->L.ticket));
+    k_set_counters<<<1, 1, 0, c->stream>>>(wsp<int64_t>(c, c->L.tctr), c->t, wsp<int>(c, c->L.err));
+    c->hist_first = c->t;  // force records before the checkpoint are not restored
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
 }

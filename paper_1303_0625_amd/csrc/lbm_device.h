@@ -91,39 +91,59 @@ struct CollideParams {
     C rho0, omega, gx, gy, pref;  // pref = 1 - 1/(2 tau)
 };
 
+// Moments of one node: drho = sum d_i, rho = rho0 + drho, Guo velocity u.
 template <typename C>
-__device__ inline void collide(C d[9], const CollideParams<C>& p) {
-    C drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-    C rho = p.rho0 + drho;
+struct Moments {
+    C drho, rho, ux, uy;
+};
+
+template <typename C>
+__device__ inline Moments<C> moments(const C d[9], const CollideParams<C>& p) {
+    Moments<C> m;
+    m.drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    m.rho = p.rho0 + m.drho;
     C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-    C inv = C(1) / rho;
-    C ux = jx * inv + C(0.5) * p.gx;
-    C uy = jy * inv + C(0.5) * p.gy;
-    C uu = ux * ux + uy * uy;
-    C Fx = rho * p.gx, Fy = rho * p.gy;
-    C uF = ux * Fx + uy * Fy;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const C w = w_<C>(i);
-        C eu = C(ex_(i)) * ux + C(ey_(i)) * uy;
-        C eF = C(ex_(i)) * Fx + C(ey_(i)) * Fy;
-        C deq = w * (drho + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
-        C src = p.pref * w * (C(3) * (eF - uF) + C(9) * eu * eF);
-        d[i] = d[i] - p.omega * (d[i] - deq) + src;
-    }
+    C inv = C(1) / m.rho;
+    m.ux = jx * inv + C(0.5) * p.gx;
+    m.uy = jy * inv + C(0.5) * p.gy;
+    return m;
 }
 
-// Equilibrium deviation f_eq(rho, u) - w rho0 of Eq. 8.
+// Post-collision deviation of direction i from its pre-collision value di.
+template <typename C>
+__device__ inline C relax_one(int i, C di, const Moments<C>& m, const CollideParams<C>& p) {
+    const C w = w_<C>(i);
+    const C uu = m.ux * m.ux + m.uy * m.uy;
+    const C Fx = m.rho * p.gx, Fy = m.rho * p.gy;
+    const C uF = m.ux * Fx + m.uy * Fy;
+    const C eu = C(ex_(i)) * m.ux + C(ey_(i)) * m.uy;
+    const C eF = C(ex_(i)) * Fx + C(ey_(i)) * Fy;
+    const C deq = w * (m.drho + m.rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+    const C src = p.pref * w * (C(3) * (eF - uF) + C(9) * eu * eF);
+    return di - p.omega * (di - deq) + src;
+}
+
+template <typename C>
+__device__ inline void collide(C d[9], const CollideParams<C>& p) {
+    const Moments<C> m = moments<C>(d, p);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = relax_one<C>(i, d[i], m, p);
+}
+
+// Equilibrium deviation f_eq(rho, u) - w rho0 of Eq. 8, one direction.
+template <typename C>
+__device__ inline C feq_one(int i, C rho, C rho0, C ux, C uy) {
+    const C uu = ux * ux + uy * uy;
+    const C eu = C(ex_(i)) * ux + C(ey_(i)) * uy;
+    return w_<C>(i) * ((rho - rho0) + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
+}
+
+// All nine directions.
 template <typename C>
 __device__ inline void feq_dev(C rho, C rho0, C ux, C uy, C out[9]) {
-    C uu = ux * ux + uy * uy;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const C w = w_<C>(i);
-        C eu = C(ex_(i)) * ux + C(ey_(i)) * uy;
-        out[i] = w * ((rho - rho0) + rho * (C(3) * eu + C(4.5) * eu * eu - C(1.5) * uu));
-    }
+    for (int i = 0; i < 9; ++i) out[i] = feq_one<C>(i, rho, rho0, ux, uy);
 }
 
 // ---------------------------------------------------------------- misc

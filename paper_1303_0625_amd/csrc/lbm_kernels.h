@@ -429,12 +429,14 @@ __device__ inline void swept_box(const SolidDev& S, int64_t t, long& x0, long& x
 template <typename T>
 struct MoveShared {
     using C = typename Sto<T>::C;
+    SolidDev body;  // the mover's record (kept here rather than in registers)
     int scan[kBlock];
     int nb_count;
     int nb_list[kNewbornMax];
     int8_t nb_use[kNewbornBatch][8];  // -1: no participation, else 0/1/2
     C nb_val[kNewbornBatch][8][3][9];
     C nb_new[kNewbornBatch][9];
+    C nb_mom[kNewbornBatch][4];
 };
 
 // Mover role for body movers[m]; lds holds the two byte maps (2 * box_bytes).
@@ -452,7 +454,9 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
     uint8_t* ot = lds;
     uint8_t* on = lds + a.box_bytes;
     const int s = movers[m];
-    const SolidDev S = sol[s];
+    if (threadIdx.x == 0) sm.body = sol[s];
+    __syncthreads();
+    const SolidDev& S = sm.body;
     const int64_t t = tctr[parity];
     long x0, x1, y0, y1;
     swept_box(S, t, x0, x1, y0, y1);
@@ -470,7 +474,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
     };
     if (threadIdx.x == 0) sm.nb_count = 0;
     // 1. stage both owner maps; loads of a round are issued before any store
-    constexpr int R = 8;
+    constexpr int R = 4;
     for (int q0 = 0; q0 < N; q0 += R * kBlock) {
         uint8_t vt[R], vn[R];
 #pragma unroll
@@ -623,26 +627,30 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                 else
                     acc += v1;
             }
-            if (np > 0) {
-                sm.nb_new[bb][j] = acc / C(np);
-            } else {  // no participant: equilibrium at the body velocity
-                C fe[9];
-                feq_dev<C>(rho0, rho0, (C)S.vx, (C)S.vy, fe);
-                sm.nb_new[bb][j] = fe[j];
-            }
+            // no participant: equilibrium at the body velocity
+            sm.nb_new[bb][j] = np > 0 ? acc / C(np) : feq_one<C>(j, rho0, rho0, (C)S.vx, (C)S.vy);
         }
         __syncthreads();
-        // 4d. collide and store
+        // 4d. collide: moments per newborn node, then one direction per thread
         if (threadIdx.x < nbat) {
-            C d[9];
-#pragma unroll
-            for (int j = 0; j < 9; ++j) d[j] = sm.nb_new[threadIdx.x][j];
-            collide<C>(d, cp);
+            const Moments<C> mo = moments<C>(sm.nb_new[threadIdx.x], cp);
+            sm.nb_mom[threadIdx.x][0] = mo.drho;
+            sm.nb_mom[threadIdx.x][1] = mo.rho;
+            sm.nb_mom[threadIdx.x][2] = mo.ux;
+            sm.nb_mom[threadIdx.x][3] = mo.uy;
+        }
+        __syncthreads();
+        if (threadIdx.x < nbat * 9) {
+            const int bb = threadIdx.x / 9, j = threadIdx.x % 9;
+            Moments<C> mo;
+            mo.drho = sm.nb_mom[bb][0];
+            mo.rho = sm.nb_mom[bb][1];
+            mo.ux = sm.nb_mom[bb][2];
+            mo.uy = sm.nb_mom[bb][3];
+            const C dj = relax_one<C>(j, sm.nb_new[bb][j], mo, cp);
             int gx, gy;
-            gidx(sm.nb_list[base + threadIdx.x], gx, gy);
-            T* w0 = fout + (int64_t)gy * a.ystride + gx;
-#pragma unroll
-            for (int j = 0; j < 9; ++j) w0[j * a.istride] = Sto<T>::st(d[j]);
+            gidx(sm.nb_list[base + bb], gx, gy);
+            fout[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx] = Sto<T>::st(dj);
         }
         __syncthreads();
     }
@@ -673,13 +681,11 @@ __device__ inline double wave_sum(double v) {
 //   GME (Eq. 5) F = (e_i - v) a - (e_ibar - v) b
 //   T_z (Eq. 7) = (x_s - R) x F with x_s = x_f + e_i/2, R the body centre.
 // Each thread sums a fixed strided subset, the wave and workgroup combine in
-// a fixed tree into partial[c]; the last workgroup to finish (ticket counter,
-// control only) sums each solid's chunk partials in chunk order.  The result
-// is therefore independent of scheduling.  That workgroup also advances the
-// step counter into the other parity slot.
+// a fixed tree into partial[c].  The per-solid totals are formed later, in
+// chunk order, by finalize_forces (in the next launch), so no workgroup
+// waits on another and the result is independent of scheduling.
 struct ForceShared {
     double red[kBlock / 64][6];
-    int is_last;
 };
 
 template <typename T>
@@ -688,15 +694,12 @@ __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ 
                                   const int* __restrict__ seg_cnt, const int* __restrict__ seg_off,
                                   const int* __restrict__ chunk_solid,
                                   const int* __restrict__ chunk_start,
-                                  const int* __restrict__ solid_chunk0,
                                   const SolidDev* __restrict__ sol, double* __restrict__ partial,
-                                  unsigned int* __restrict__ ticket, double* __restrict__ hist,
-                                  int64_t* __restrict__ tctr, int parity, const ForceArgs& a) {
+                                  int64_t t, const ForceArgs& a) {
     const int s = chunk_solid[c];
     const int start = chunk_start[c];
     const int n = seg_cnt[s];
     const int end = start + kForceChunk < n ? start + kForceChunk : n;
-    const int64_t t = tctr[parity];
     const uint32_t* L = links + seg_off[s];
     const SolidDev S = sol[s];
     double X = 0.0, Y = 0.0;
@@ -752,30 +755,40 @@ __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ 
         const int q = threadIdx.x;
         partial[c * 6 + q] = (fs.red[0][q] + fs.red[1][q]) + (fs.red[2][q] + fs.red[3][q]);
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) fs.is_last = atomicAdd(ticket, 1u) == (unsigned)(a.nchunks - 1);
-    __syncthreads();
-    if (!fs.is_last) return;
-    __threadfence();
-    const int64_t slot = t % a.hist_cap;
+}
+
+// Per-solid totals of step `step` from its chunk partials, summed in chunk
+// order, into the history ring (one workgroup).
+__device__ inline void finalize_forces(const double* __restrict__ partial,
+                                       const int* __restrict__ solid_chunk0, double* __restrict__ hist,
+                                       int64_t step, const ForceArgs& a) {
+    const int64_t slot = step % a.hist_cap;
     for (int r = threadIdx.x; r < a.nsol * 6; r += kBlock) {
         const int sid = r / 6, q = r % 6;
         double v = 0.0;
         for (int cc = solid_chunk0[sid]; cc < solid_chunk0[sid + 1]; ++cc) v += partial[cc * 6 + q];
         hist[(slot * a.nsol + sid) * 6 + q] = v;
     }
-    if (threadIdx.x == 0) {
-        *ticket = 0u;
-        tctr[parity ^ 1] = t + 1;
-    }
+}
+
+// Finalize the forces of step tctr[parity] - 1 (after the last launch of a
+// batch of steps); partials of step u live in partial[(u & 1)].
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partial2,
+                                                     const int* __restrict__ solid_chunk0,
+                                                     double* __restrict__ hist,
+                                                     const int64_t* __restrict__ tctr, int parity,
+                                                     ForceArgs a) {
+    const int64_t t = tctr[parity];
+    if (t < 1) return;
+    finalize_forces(partial2 + (size_t)((t - 1) & 1) * a.nchunks * 6, solid_chunk0, hist, t - 1, a);
 }
 
 // ------------------------------------------------------------------ fused step
 // One launch per time step: workgroups [0, n_force) are force chunks,
-// [n_force, n_force + n_move) are translating bodies, and from n_lead (a
-// multiple of 8, so that update workgroup j sits on XCD j % 8) on the fused
-// update.  The roles read only step-t data and write disjoint outputs, so
+// [n_force, n_force + n_move) are translating bodies, workgroup
+// n_force + n_move finalizes the previous step's forces and advances the step
+// counter, and from n_lead (a multiple of 8, so that update workgroup j sits
+// on XCD j % 8) on the fused update.  The roles read only step-t data and write disjoint outputs, so
 // the small latency-bound roles run alongside the bandwidth-bound update.
 template <typename T>
 struct StepPtrs {
@@ -795,8 +808,7 @@ struct StepPtrs {
     const SolidDev* sol;
     const double* vtab;
     const int* movers;
-    double* partial;
-    unsigned int* ticket;
+    double* partial;  // [2][nchunks][6], by step parity
     double* hist;
     int64_t* tctr;
     int* errflag;
@@ -817,13 +829,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     } sh;
     const int b = (int)blockIdx.x;
     if (b < rc.n_lead) {
+        const int64_t t = p.tctr[parity];
         if (b < rc.n_force) {
             force_role<T>(b, sh.f, p.fin, p.links_t, p.seg_cnt_t, p.seg_off, p.chunk_solid, p.chunk_start,
-                          p.solid_chunk0, p.sol, p.partial, p.ticket, p.hist, p.tctr, parity, fa);
+                          p.sol, p.partial + (size_t)(t & 1) * fa.nchunks * 6, t, fa);
         } else if (b < rc.n_force + rc.n_move) {
             move_role<T>(b - rc.n_force, dyn_lds, sh.m, p.fin, p.fout, p.own_t, p.own_n, p.links_n,
                          p.seg_cnt_n, p.seg_off, p.seg_cap, p.sol, p.vtab, p.movers, p.tctr, parity, ma,
                          cp, p.errflag);
+        } else if (b == rc.n_force + rc.n_move) {
+            // previous step's totals (its partials are complete: the
+            // previous launch has ended); then advance the step counter
+            if (t >= 1)
+                finalize_forces(p.partial + (size_t)((t - 1) & 1) * fa.nchunks * 6, p.solid_chunk0, p.hist,
+                                t - 1, fa);
+            if (threadIdx.x == 0) p.tctr[parity ^ 1] = t + 1;
         }
         return;
     }
@@ -866,12 +886,11 @@ __global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f
 }
 
 // ------------------------------------------------------------------ misc
-__global__ void k_set_counters(int64_t* tctr, int64_t t, int* errflag, unsigned int* ticket) {
+__global__ void k_set_counters(int64_t* tctr, int64_t t, int* errflag) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         tctr[0] = t;
         tctr[1] = t;
         *errflag = 0;
-        *ticket = 0u;
     }
 }
 
