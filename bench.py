@@ -8,15 +8,15 @@ every step.  A "step" is one full time step of the hot path (forces, body
 motion, link rebuild, fused advection + bounce-back + collision, refill).
 
 Prints one JSON line: MLUPS over all nodes, the roofline of the dominant
-kernel (the fused lattice update, timed with HIP events around each launch on
-the library's stream), an additional HBM-bound measurement on a 4096 x 4096
-periodic lattice (its A/B working set is 4.7x the 256 MB Infinity Cache), and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+kernel (the one-per-step launch whose update role moves 18 populations per
+fluid node, timed with HIP events attached to each dispatch on the library's
+stream), an additional HBM-bound measurement on a 4096 x 4096 periodic lattice
+(its A/B working set is 4.7x the 256 MB Infinity Cache), and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,31 +30,25 @@ METRIC = "MLUPS and % HBM roofline; time-to-steady drag at 1e-4 (learned+mixed v
 BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("lbm_kernels.h", "lbm_device.h", "lbm_capi.hip"):
-        with open(os.path.join(ROOT, "paper_1303_0625_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def stored_traffic(workload: str):
+    """HBM bytes per launch of the time-step kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size);
+    None when absent or taken on other kernel sources."""
+    from paper_1303_0625_amd.build import source_hash
 
-
-def stored_traffic(workload: str, launches_bytes: float):
-    """HBM bytes per launch from the committed counter summary of this kernel
-    source (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration);
-    None when absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"k_fused_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return round(rec.get("hbm_bytes_per_launch"))
 
 
 def run_gpu(case, dtype, steps, warmup, torch, pkg):
     """Warm up, time `steps` steps (whole-step throughput), then time another
-    `steps` steps with HIP events around each lattice-update launch (kernel
+    `steps` steps with HIP events attached to each time-step launch (kernel
     roofline).  The two passes are separate so that the event records do not
     perturb the throughput figure."""
     lat = pkg.Lattice(case, dtype=dtype, history_steps=2 * steps + warmup + 1)
@@ -87,6 +81,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-case", action="store_true")
+    ap.add_argument("--only-hbm-case", action="store_true",
+                    help="run only the 4096 x 4096 measurement (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -106,6 +102,14 @@ def main() -> int:
 
     case = lc.moving_cylinders()
     nx, ny = case["nx"], case["ny"]
+    if args.only_hbm_case:
+        big = lc.periodic_cylinders()
+        lat2, tms2, ums2, n2, nf2 = run_gpu(big, args.dtype, args.steps, args.warmup, torch, pkg)
+        avg2 = ums2 / max(n2, 1) * 1e-3
+        print(json.dumps({"periodic_4096x4096_kernel_us": round(avg2 * 1e6, 2),
+                          "alg_bytes_per_launch": 18 * BYTES[args.dtype] * nf2,
+                          "achieved_GBs": round(18 * BYTES[args.dtype] * nf2 / avg2 / 1e9, 1)}), flush=True)
+        return 0
     lat, total_ms, upd_ms, n_upd, n_fluid = run_gpu(case, args.dtype, args.steps, args.warmup,
                                                     torch, pkg)
     ms_per_step = total_ms / args.steps
@@ -115,9 +119,10 @@ def main() -> int:
     achieved = alg_bytes / upd_avg_s / 1e9
     wl = "moving_cylinders_2048x1024"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(wl, alg_bytes),
-                "kernel": "k_step", "update_us": round(upd_avg_s * 1e6, 3),
-                "alg_bytes_per_launch": alg_bytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(wl),
+                "kernel": "k_fused (one launch per step: force, mover and fused-update roles)",
+                "kernel_us": round(upd_avg_s * 1e6, 3), "alg_bytes_per_launch": alg_bytes,
+                "alg_bytes_per_fluid_node": 18 * BYTES[args.dtype]}
     del lat
     torch.cuda.empty_cache()
 
@@ -131,10 +136,10 @@ def main() -> int:
         extra["periodic_4096x4096"] = {
             "mlups": round(big["nx"] * big["ny"] * big_steps / (tms2 * 1e-3) / 1e6, 1),
             "ms_per_step": round(tms2 / big_steps, 4),
-            "update_us": round(avg2 * 1e6, 2),
+            "kernel_us": round(avg2 * 1e6, 2),
             "achieved_GBs": round(ab2 / avg2 / 1e9, 1),
             "frac": round(ab2 / avg2 / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic("periodic_4096x4096", ab2),
+            "traffic": stored_traffic("periodic_4096x4096"),
             "cylinders": len(big["bodies"]), "fixed_geometry": True}
         del lat2
         torch.cuda.empty_cache()

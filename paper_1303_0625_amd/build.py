@@ -21,6 +21,17 @@ FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """Short hash of the kernel sources (ties measurements to a kernel version)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.h", "lbm_device.h", "lbm_capi.hip"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build_library(verbose: bool = False) -> str:
     """Compile liblbm.so (always recompiles)."""
     tmp = LIB + ".tmp"

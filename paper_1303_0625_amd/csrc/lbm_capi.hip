@@ -54,6 +54,7 @@ struct Layout {
     int n_movers;
     int nchunks;
     int box_bytes;  // LDS byte map per translating body (mover role)
+    size_t fbytes;  // bytes of one population buffer
 };
 
 // Conservative link capacity of one body: every fluid node adjacent to a
@@ -73,9 +74,16 @@ bool make_layout(const lbm_grid& g, const lbm_solid* solids, int n, int64_t hist
     L.opitch = (g.nx + 63) / 64 * 64;
     L.plane = (int64_t)g.ny * L.pitch;  // elements per population (all rows)
     size_t off = 0;
+    const size_t fbytes = 9 * (size_t)L.plane * es;
+    L.fbytes = fbytes;
+    // The second buffer starts off a large power-of-two distance from the
+    // first: reads of row y and writes of row y then fall on different HBM
+    // channels (measured on 4096 x 4096: 231.6 us with no offset, 208.4 us
+    // with 3 MiB or more).
+    const size_t skew = std::min<size_t>(4u << 20, align256(fbytes / 8));
     for (int k = 0; k < 2; ++k) {
         L.f[k] = off;
-        off = align256(off + 9 * (size_t)L.plane * es);
+        off = align256(off + fbytes) + (k == 0 ? skew : 0);
     }
     L.n_movers = 0;
     for (int k = 0; k < n; ++k) L.n_movers += solids[k].moves ? 1 : 0;
@@ -318,7 +326,7 @@ lbm_status enqueue_step(lbm_ctx* c) {
     const dim3 grid((unsigned)(rc.n_lead + node_blocks(c)));
     const size_t lds = c->L.n_movers > 0 ? 2 * (size_t)c->L.box_bytes : 0;
     // both population buffers larger than the Infinity Cache: stream them
-    const bool nt = 2 * (c->L.f[1] - c->L.f[0]) > kStreamBytes;
+    const bool nt = 2 * c->L.fbytes > kStreamBytes;
     auto kern = nt ? k_fused<T, true> : k_fused<T, false>;
     const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
     if (timed) {
@@ -791,7 +799,7 @@ lbm_status lbm_link_forces(lbm_ctx* c, double* d_out, int64_t max, int64_t* n) {
 lbm_status lbm_checkpoint_bytes(const lbm_ctx* c, size_t* bytes) {
     if (!c || !bytes) return LBM_EINVAL;
     // populations (current buffer), both owner maps, links + counts, counters
-    *bytes = 64 + (c->L.f[1] - c->L.f[0]) + 2 * (c->L.own[1] - c->L.own[0]) +
+    *bytes = 64 + c->L.fbytes + 2 * (c->L.own[1] - c->L.own[0]) +
              4 * (size_t)std::max<int64_t>(c->link_cap_total, 1) + 4 * (size_t)(c->n + 1);
     return LBM_OK;
 }
@@ -807,7 +815,7 @@ lbm_status lbm_save(lbm_ctx* c, void* d_dst, size_t bytes) {
     char* d = (char*)d_dst;
     int64_t hdr[8] = {0x6c626d63, (int64_t)LBM_ABI_VERSION, c->t, c->g.nx, c->g.ny, c->g.dtype, c->n, 0};
     const int p = (int)(c->t & 1);
-    const size_t fb = c->L.f[1] - c->L.f[0];
+    const size_t fb = c->L.fbytes;
     const size_t ob = c->L.own[1] - c->L.own[0];
     HIPCHK(c, hipMemcpyAsync(d, hdr, 64, hipMemcpyHostToDevice, c->stream));
     size_t o = 64;
@@ -843,7 +851,7 @@ lbm_status lbm_load(lbm_ctx* c, const void* d_src, size_t bytes) {
     }
     c->t = hdr[2];
     const int p = (int)(c->t & 1);
-    const size_t fb = c->L.f[1] - c->L.f[0];
+    const size_t fb = c->L.fbytes;
     const size_t ob = c->L.own[1] - c->L.own[0];
     size_t o = 64;
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.f[p], s + o, fb, hipMemcpyDeviceToDevice, c->stream));
