@@ -152,8 +152,20 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
 #pragma unroll
     for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
     if ((s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0 || wall_lo || wall_hi) {
+        // half-way bounce-back for the directions whose source is solid or a
+        // wall row: the node's own opposite population plus the moving-wall
+        // term; the loads are independent and issue together
+        const uint32_t src[9] = {0u, s1, s2, s3, s4, s5, s6, s7, s8};
 #pragma unroll
-        for (int i = 1; i < 9; ++i) d[i] = pull_one<T, C>(fin, own_t, vtab, a, x, y, i);
+        for (int i = 1; i < 9; ++i) {
+            const bool wall = (ey_(i) == 1 && wall_lo) || (ey_(i) == -1 && wall_hi);
+            const uint32_t sid = wall ? 0u : src[i];
+            if (wall || sid != 0u) {
+                const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                d[i] = Sto<T>::ld(r0[opp_(i) * P + x]) +
+                       C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
+            }
+        }
     }
     collide<C>(d, cp);
     T* w0 = fout + (int64_t)y * a.ystride + x;
