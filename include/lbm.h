@@ -192,6 +192,111 @@ void lbm_destroy(lbm_ctx* ctx);
  * lbm_create / lbm_workspace_bytes in this thread when ctx is NULL. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched steady-state solver: many independent lattices of uneven sizes
+ * (fixed geometry, moves = 0) advanced together until each one is steady.
+ *
+ * One launch per time step updates the tiles of every active case (the same
+ * per-node arithmetic as lbm_step, so a case advanced here matches the same
+ * case advanced alone bit for bit).  Every check interval of k steps a
+ * monitor evaluates on the device, per case:
+ *   - the residual r = ||u_t - u_{t-k}||_2 / (k ||u_t||_2) over fluid nodes,
+ *     u the Guo velocity (steady-state criterion; the paper runs its steady
+ *     cases to convergence, Sec. V, Eq. 11 defines the drag coefficient);
+ *   - CME and GME force and torque on every solid (Eqs. 4-7), summed in a
+ *     fixed order (deterministic);
+ * and retires a case once r < tol: its state freezes and its tiles leave the
+ * launch.  lbm_batch_run captures one interval (k steps + monitor) as a HIP
+ * graph and replays it.  Work runs on a stream the batch owns, ordered after
+ * the work enqueued on hip_stream so far; every lbm_batch_* call that
+ * launches work synchronises before it returns.
+ *
+ * Device state (populations, owner maps, links, snapshots, tables) lives in
+ * the caller's workspace; the batch allocates no device memory itself.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch; /* opaque; lbm_batch_create / lbm_batch_destroy */
+
+/* Workspace bytes of a batch.  grids[n_cases] and taus[n_cases] describe the
+ * cases (one dtype for all); solids holds the bodies of case 0, then of case
+ * 1, ..., n_solids[c] of them for case c; no body may move. */
+lbm_status lbm_batch_workspace_bytes(const lbm_grid* grids, const double* taus, const lbm_solid* solids,
+                                     const int32_t* n_solids, int32_t n_cases, size_t* bytes);
+
+/* Validate every case (as lbm_create does), lay out the workspace, build the
+ * geometry and links and initialise every case to f_eq(rho0, u0), collided
+ * once.  The initial tiling is 4 waves (256 nodes of one row band) per
+ * workgroup.  Synchronises.  *out receives the batch. */
+lbm_status lbm_batch_create(const lbm_grid* grids, const double* taus, const lbm_solid* solids,
+                            const int32_t* n_solids, int32_t n_cases, void* d_workspace, size_t bytes,
+                            void* hip_stream, lbm_batch** out);
+
+/* Time the step launch over the candidate tilings (1, 2, 4 or 8 waves per
+ * workgroup, cached or nontemporal streaming) and keep the fastest; then
+ * reset every case to its initial state.  Only before the first step
+ * (LBM_ESTATE otherwise).  cache_path (optional) is a text file of
+ * "signature|waves|nontemporal|us" lines: a matching line is used without
+ * timing, a new result is appended. */
+lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path);
+
+/* Waves per workgroup of the current tiling; *nontemporal (optional) receives
+ * 1 when the update streams with nontemporal loads and stores. */
+int32_t lbm_batch_tiling(const lbm_batch* b, int32_t* nontemporal);
+
+/* Set the tiling: waves (1, 2, 4 or 8 per workgroup) and nontemporal (1:
+ * the update streams with nontemporal loads and stores).  Any tiling gives
+ * the same results bit for bit; only the speed differs. */
+lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t waves, int32_t nontemporal);
+
+/* Enable (1, the default) or disable (0) graph capture in lbm_batch_run. */
+lbm_status lbm_batch_set_graph(lbm_batch* b, int32_t enable);
+
+/* Advance every active case by n steps (no monitor).  Synchronises. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Run the monitor at the current step with the interval since the previous
+ * monitor; retire the cases with r < tol (tol < 0 retires none).  The first
+ * monitor only records the snapshot (residual -1).  Synchronises. */
+lbm_status lbm_batch_monitor(lbm_batch* b, double tol);
+
+/* Run intervals of k steps (check_every rounded up to even, >= 2), each
+ * followed by the monitor, until every case has retired or another interval
+ * would exceed max_steps steps in this call.  *steps_done (optional, host)
+ * receives the steps taken.  Synchronises. */
+lbm_status lbm_batch_run(lbm_batch* b, int64_t max_steps, double tol, int32_t check_every,
+                         int64_t* steps_done);
+
+/* Per-case results of the last monitor into host arrays of n_cases entries
+ * (each pointer optional): converged flag, steps (the step at retirement, or
+ * the current step), residual (-1 before the second monitor) and drag[2c],
+ * drag[2c+1] = sum over the case's bodies of the CME and GME x-force. */
+lbm_status lbm_batch_status(lbm_batch* b, int32_t* converged, int64_t* steps, double* residual,
+                            double* drag);
+
+/* {Fx, Fy, Tz} on solid solid_id (0 = walls) of case case_id by scheme, as of
+ * the last monitor, into host memory. */
+lbm_status lbm_batch_force(lbm_batch* b, int32_t case_id, int32_t solid_id, int32_t scheme,
+                           double out[3]);
+
+/* Density and Guo velocity of case case_id (at its retirement step if it has
+ * retired) into device buffers of nx*ny elements (LBM_F64 or LBM_F32); 0 at
+ * solid nodes.  Synchronises. */
+lbm_status lbm_batch_fields(lbm_batch* b, int32_t case_id, void* d_rho, void* d_ux, void* d_uy,
+                            int32_t out_dtype);
+
+/* Warm start of case case_id, as lbm_init_fields.  Synchronises. */
+lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t case_id, const void* d_rho, const void* d_ux,
+                                 const void* d_uy, int32_t in_dtype);
+
+/* Completed steps of the batch (cases advanced together). */
+int64_t lbm_batch_time(const lbm_batch* b);
+
+/* Release the batch (not the caller's buffers).  NULL is ignored. */
+void lbm_batch_destroy(lbm_batch* b);
+
+/* Message of the last failure on this batch, or (b NULL) of the last failed
+ * lbm_batch_create / lbm_batch_workspace_bytes in this thread. */
+const char* lbm_batch_last_error(const lbm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -913,3 +913,5 @@ void lbm_destroy(lbm_ctx* c) {
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err : g_err; }
 
 }  // extern "C"
+
+#include "lbm_batch_capi.h"

@@ -98,11 +98,15 @@ __device__ inline void st_stream(bf16_t* p, bf16_t v) {
 // per-direction bounce-back values.  bid/nblk: this workgroup's index among
 // the update workgroups (remapped so that each XCD walks a contiguous band).
 template <typename T, bool NT>
+__device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
+                                 const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
+                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp);
+
+template <typename T, bool NT>
 __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restrict__ fin,
                                  T* __restrict__ fout, const uint8_t* __restrict__ own_t,
                                  const double* __restrict__ vtab, const StepArgs& a,
                                  const CollideParams<typename Sto<T>::C>& cp) {
-    using C = typename Sto<T>::C;
     // row and column base are wave-uniform scalars
     const uint32_t b = xcd_remap(bid, nblk);
     const uint32_t wpr = (uint32_t)a.rowlen >> 6;
@@ -110,6 +114,15 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
     const int y = (int)(gw / wpr);
     const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
     if (y >= a.ny || x >= a.nx) return;
+    step_node<T, NT>(x, y, fin, fout, own_t, vtab, a, cp);
+}
+
+// The update of node (x, y): pull, bounce-back, collide, store.
+template <typename T, bool NT>
+__device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
+                                 const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
+                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp) {
+    using C = typename Sto<T>::C;
 
     const int xm = x == 0 ? a.nx - 1 : x - 1;
     const int xp = x == a.nx - 1 ? 0 : x + 1;

@@ -73,6 +73,27 @@ _SIG = {
     "lbm_status_check": (_I32, [_VP]),
     "lbm_destroy": (None, [_VP]),
     "lbm_last_error": (ctypes.c_char_p, [_VP]),
+    "lbm_batch_workspace_bytes": (_I32, [ctypes.POINTER(lbm_grid), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(lbm_solid), ctypes.POINTER(_I32), _I32,
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_batch_create": (_I32, [ctypes.POINTER(lbm_grid), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(lbm_solid), ctypes.POINTER(_I32), _I32, _VP,
+                                ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "lbm_batch_autotune": (_I32, [_VP, ctypes.c_char_p]),
+    "lbm_batch_tiling": (_I32, [_VP, ctypes.POINTER(_I32)]),
+    "lbm_batch_set_tiling": (_I32, [_VP, _I32, _I32]),
+    "lbm_batch_set_graph": (_I32, [_VP, _I32]),
+    "lbm_batch_step": (_I32, [_VP, _I64]),
+    "lbm_batch_monitor": (_I32, [_VP, ctypes.c_double]),
+    "lbm_batch_run": (_I32, [_VP, _I64, ctypes.c_double, _I32, ctypes.POINTER(_I64)]),
+    "lbm_batch_status": (_I32, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I64),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "lbm_batch_force": (_I32, [_VP, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_double)]),
+    "lbm_batch_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32]),
+    "lbm_batch_init_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32]),
+    "lbm_batch_time": (_I64, [_VP]),
+    "lbm_batch_destroy": (None, [_VP]),
+    "lbm_batch_last_error": (ctypes.c_char_p, [_VP]),
 }
 
 
@@ -195,6 +216,106 @@ def lbm_destroy(ctx) -> None:
 
 def lbm_last_error(ctx=None) -> str:
     m = load_library().lbm_last_error(ctx)
+    return m.decode() if m else ""
+
+
+# ---- batched steady-state solver -------------------------------------------
+def _bcheck(status, b=None):
+    if status != LBM_OK:
+        msg = load_library().lbm_batch_last_error(b)
+        raise LBMError(status, msg.decode() if msg else "")
+
+
+def _batch_arrays(grids, taus, solids_per_case):
+    n = len(grids)
+    garr = (lbm_grid * n)(*grids)
+    tarr = (ctypes.c_double * n)(*[float(t) for t in taus])
+    flat = [b for case in solids_per_case for b in case]
+    sarr, _ = _solid_array(flat)
+    narr = (_I32 * n)(*[len(case) for case in solids_per_case])
+    return garr, tarr, sarr, narr, n
+
+
+def lbm_batch_workspace_bytes(grids, taus, solids_per_case) -> int:
+    garr, tarr, sarr, narr, n = _batch_arrays(grids, taus, solids_per_case)
+    out = ctypes.c_size_t(0)
+    _bcheck(load_library().lbm_batch_workspace_bytes(garr, tarr, sarr, narr, n, ctypes.byref(out)))
+    return out.value
+
+
+def lbm_batch_create(grids, taus, solids_per_case, d_workspace: int, nbytes: int, stream: int):
+    garr, tarr, sarr, narr, n = _batch_arrays(grids, taus, solids_per_case)
+    b = _VP()
+    _bcheck(load_library().lbm_batch_create(garr, tarr, sarr, narr, n, d_workspace, nbytes, stream,
+                                            ctypes.byref(b)))
+    return b
+
+
+def lbm_batch_autotune(b, cache_path=None) -> None:
+    _bcheck(load_library().lbm_batch_autotune(b, cache_path.encode() if cache_path else None), b)
+
+
+def lbm_batch_tiling(b):
+    nt = _I32(0)
+    w = load_library().lbm_batch_tiling(b, ctypes.byref(nt))
+    return w, nt.value
+
+
+def lbm_batch_set_tiling(b, waves: int, nontemporal: bool) -> None:
+    _bcheck(load_library().lbm_batch_set_tiling(b, int(waves), int(bool(nontemporal))), b)
+
+
+def lbm_batch_set_graph(b, enable: bool) -> None:
+    _bcheck(load_library().lbm_batch_set_graph(b, int(bool(enable))), b)
+
+
+def lbm_batch_step(b, n: int) -> None:
+    _bcheck(load_library().lbm_batch_step(b, n), b)
+
+
+def lbm_batch_monitor(b, tol: float) -> None:
+    _bcheck(load_library().lbm_batch_monitor(b, tol), b)
+
+
+def lbm_batch_run(b, max_steps: int, tol: float, check_every: int) -> int:
+    done = _I64(0)
+    _bcheck(load_library().lbm_batch_run(b, max_steps, tol, check_every, ctypes.byref(done)), b)
+    return done.value
+
+
+def lbm_batch_status(b, n_cases: int):
+    conv = (_I32 * n_cases)()
+    steps = (_I64 * n_cases)()
+    res = (ctypes.c_double * n_cases)()
+    drag = (ctypes.c_double * (2 * n_cases))()
+    _bcheck(load_library().lbm_batch_status(b, conv, steps, res, drag), b)
+    return list(conv), list(steps), list(res), [(drag[2 * k], drag[2 * k + 1]) for k in range(n_cases)]
+
+
+def lbm_batch_force(b, case_id: int, solid_id: int, scheme: int):
+    out = (ctypes.c_double * 3)()
+    _bcheck(load_library().lbm_batch_force(b, case_id, solid_id, scheme, out), b)
+    return list(out)
+
+
+def lbm_batch_fields(b, case_id: int, d_rho, d_ux, d_uy, out_dtype: int) -> None:
+    _bcheck(load_library().lbm_batch_fields(b, case_id, d_rho, d_ux, d_uy, out_dtype), b)
+
+
+def lbm_batch_init_fields(b, case_id: int, d_rho, d_ux, d_uy, in_dtype: int) -> None:
+    _bcheck(load_library().lbm_batch_init_fields(b, case_id, d_rho, d_ux, d_uy, in_dtype), b)
+
+
+def lbm_batch_time(b) -> int:
+    return load_library().lbm_batch_time(b)
+
+
+def lbm_batch_destroy(b) -> None:
+    load_library().lbm_batch_destroy(b)
+
+
+def lbm_batch_last_error(b=None) -> str:
+    m = load_library().lbm_batch_last_error(b)
     return m.decode() if m else ""
 
 
@@ -351,3 +472,81 @@ class Lattice:
     def profile_read(self):
         """(summed ms, launches) of the lattice-update kernel since profile()."""
         return lbm_profile_read(self.ctx)
+
+
+class LatticeBatch:
+    """Many fixed-geometry lattices advanced together to steady state.
+
+    ``cases`` is a list of case dicts (as for ``Lattice``; bodies must not
+    move), all with one storage dtype.  The workspace is a torch uint8 tensor.
+    """
+
+    def __init__(self, cases, dtype="f32", device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.cases = list(cases)
+        self.n = len(self.cases)
+        self.dtype = dtype
+        self.grids = [make_grid(c, dtype) for c in self.cases]
+        self.taus = [float(c["tau"]) for c in self.cases]
+        solids = [list(c.get("bodies", ())) for c in self.cases]
+        self.n_solids = [len(s) for s in solids]
+        nbytes = lbm_batch_workspace_bytes(self.grids, self.taus, solids)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.b = lbm_batch_create(self.grids, self.taus, solids, self._ws_ptr, nbytes,
+                                  self.stream.cuda_stream)
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b:
+            lbm_batch_destroy(b)
+            self.b = None
+
+    @property
+    def t(self) -> int:
+        return lbm_batch_time(self.b)
+
+    def autotune(self, cache_path=None) -> None:
+        lbm_batch_autotune(self.b, cache_path)
+
+    def tiling(self):
+        return lbm_batch_tiling(self.b)
+
+    def set_tiling(self, waves: int, nontemporal: bool = False) -> None:
+        lbm_batch_set_tiling(self.b, waves, nontemporal)
+
+    def set_graph(self, enable: bool) -> None:
+        lbm_batch_set_graph(self.b, enable)
+
+    def step(self, n: int = 1) -> None:
+        lbm_batch_step(self.b, int(n))
+
+    def monitor(self, tol: float = -1.0) -> None:
+        lbm_batch_monitor(self.b, float(tol))
+
+    def run(self, max_steps: int, tol: float, check_every: int = 100) -> int:
+        return lbm_batch_run(self.b, int(max_steps), float(tol), int(check_every))
+
+    def status(self):
+        """(converged, steps, residual, [(CME drag, GME drag)]) per case."""
+        return lbm_batch_status(self.b, self.n)
+
+    def force(self, case_id: int, solid_id: int, scheme: int):
+        return lbm_batch_force(self.b, case_id, solid_id, scheme)
+
+    def fields(self, case_id: int, out_dtype="f64"):
+        c = self.cases[case_id]
+        tdt = self.torch.float64 if out_dtype == "f64" else self.torch.float32
+        shp = (c["ny"], c["nx"])
+        dev = self.workspace.device
+        rho, ux, uy = (self.torch.empty(shp, dtype=tdt, device=dev) for _ in range(3))
+        lbm_batch_fields(self.b, case_id, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), DTYPES[out_dtype])
+        return rho, ux, uy
+
+    def init_fields(self, case_id: int, rho, ux, uy) -> None:
+        dt = LBM_F64 if rho.dtype == self.torch.float64 else LBM_F32
+        rho, ux, uy = (a.contiguous() for a in (rho, ux, uy))
+        lbm_batch_init_fields(self.b, case_id, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), dt)

@@ -31,7 +31,7 @@ def header_functions():
 
 def test_every_declared_symbol_is_exported(L):
     names = header_functions()
-    assert len(names) >= 19
+    assert len(names) >= 34
     lib = ctypes.CDLL(L.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
@@ -76,3 +76,26 @@ def test_workspace_scales_with_dtype(L):
     assert sizes["f64"] > sizes["f32"] > sizes["f16"] == sizes["bf16"]
     # two population buffers dominate: 2 * 9 * ny * pitch * bytes
     assert sizes["f32"] >= 2 * 9 * 64 * 128 * 4
+
+
+def test_batch_workspace_validation(L):
+    a = lc.make_case(130, 66, 0.8, walls_y=True, gx=2e-6, bodies=[lc.disc(40.3, 32.7, 7.2)])
+    b = lc.make_case(64, 16, 1.0, walls_y=True, gx=1e-5)
+    grids = [L.make_grid(a, "f32"), L.make_grid(b, "f32")]
+    solids = [a["bodies"], b["bodies"]]
+    nbytes = L.lbm_batch_workspace_bytes(grids, [0.8, 1.0], solids)
+    # both cases' two population buffers (rows padded to 64 nodes)
+    assert nbytes >= 2 * 9 * 4 * (66 * 192 + 16 * 64)
+    with pytest.raises(L.LBMError) as e:
+        L.lbm_batch_workspace_bytes(grids, [0.8, 0.5], solids)
+    assert "case 1" in str(e.value) and "tau" in str(e.value)
+    moving = [[lc.disc(40.3, 32.7, 7.2, vx=0.01, moves=True)], []]
+    with pytest.raises(L.LBMError) as e:
+        L.lbm_batch_workspace_bytes(grids, [0.8, 1.0], moving)
+    assert "moves" in str(e.value)
+    mixed = [L.make_grid(a, "f32"), L.make_grid(b, "f16")]
+    with pytest.raises(L.LBMError) as e:
+        L.lbm_batch_workspace_bytes(mixed, [0.8, 1.0], solids)
+    assert "dtype" in str(e.value)
+    with pytest.raises(L.LBMError):
+        L.lbm_batch_workspace_bytes([], [], [])
