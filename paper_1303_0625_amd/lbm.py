@@ -382,6 +382,7 @@ class Lattice:
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._destroy = load_library().lbm_destroy  # usable at interpreter exit
         self.ctx = lbm_create(self.grid, float(case["tau"]), solids, self.history_steps,
                               self._ws_ptr, nbytes, self.stream.cuda_stream)
 
@@ -392,7 +393,7 @@ class Lattice:
                 self.stream.synchronize()
             except Exception:
                 pass
-            lbm_destroy(ctx)
+            self._destroy(ctx)
             self.ctx = None
 
     @property
@@ -496,13 +497,14 @@ class LatticeBatch:
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._destroy = load_library().lbm_batch_destroy  # usable at interpreter exit
         self.b = lbm_batch_create(self.grids, self.taus, solids, self._ws_ptr, nbytes,
                                   self.stream.cuda_stream)
 
     def __del__(self):
         b = getattr(self, "b", None)
         if b:
-            lbm_batch_destroy(b)
+            self._destroy(b)
             self.b = None
 
     @property
