@@ -31,13 +31,13 @@ METRIC = "MLUPS and % HBM roofline; time-to-steady drag at 1e-4 (learned+mixed v
 BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
-def stored_traffic(workload: str):
-    """HBM bytes per launch of the time-step kernel from the committed counter
+def stored_traffic(workload: str, kernel: str = "k_fused"):
+    """HBM bytes per launch of a time-step kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size);
     None when absent or taken on other kernel sources."""
     from paper_1303_0625_amd.build import source_hash
 
-    path = os.path.join(ROOT, "profiles", f"k_fused_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -95,11 +95,13 @@ def run_batch(lc, pkg, torch, steps):
     dt = time.perf_counter() - t0
     conv, _, res, _ = b.status()
     gbs = 72 * n_fluid * done / dt / 1e9
+    traffic = stored_traffic("batched_uneven_256", "k_batch_step")
     del b
     return {"mlups": round(nodes * done / dt / 1e6, 1), "ms_per_step": round(dt / done * 1e3, 4),
             "steps": done, "cases": len(cases), "nodes": nodes, "fluid_nodes": n_fluid,
             "achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "tiling": {"waves_per_workgroup": waves, "nontemporal": bool(nt)},
+            "traffic_per_step": traffic, "alg_bytes_per_step": 72 * n_fluid,
             "check_every": 100, "converged": int(sum(conv)), "max_residual": max(res),
             "timing": "wall clock around graph replays, monitor included"}
 

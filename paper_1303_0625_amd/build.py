@@ -26,9 +26,11 @@ def source_hash() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("lbm_kernels.h", "lbm_device.h", "lbm_capi.hip"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
