@@ -297,6 +297,101 @@ void lbm_batch_destroy(lbm_batch* b);
  * lbm_batch_create / lbm_batch_workspace_bytes in this thread. */
 const char* lbm_batch_last_error(const lbm_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start: a 4-level U-Net mapping a channel's solid mask and
+ * Reynolds number to an approximate steady (rho, u_x, u_y), used as the
+ * initial state of a solve (lbm_init_fields / lbm_batch_init_fields), with
+ * the cold start f_eq(rho0, u0) kept as the fallback.  The paper has no
+ * network; what it feeds is the solver of Sec. II-IV, whose steady fields
+ * are the training data.
+ *
+ * Network: level l = 0..3 at (h >> l) x (w >> l); encoder levels 0..2 apply
+ * two 3x3 convolutions with ReLU (channels ch[l]) and a 2x2 mean pool;
+ * level 3 applies two; decoder levels 2..0 upsample 2x (nearest),
+ * concatenate [upsampled, encoder output of the level] and apply two 3x3
+ * convolutions with ReLU; a last 3x3 convolution gives 3 outputs.  x is
+ * periodic, y zero-padded.  Input channels: solid (1) / fluid (0) and Re/100.
+ * Outputs (normalised): (rho - 1) / (U_c rho_scale), u_x / U_c, u_y / U_c with
+ * U_c = g_x h^2 / (8 nu), nu = (tau - 1/2) / 3, the centre-line speed of the
+ * unobstructed channel.
+ *
+ * Parameters: one FP32 vector; for each of the 15 convolutions in order
+ * (encoder 0a 0b 1a 1b 2a 2b, bottleneck a b, decoder 2a 2b 1a 1b 0a 0b,
+ * head) the weights W[c_out][ky][kx][c_in] then the bias[c_out].  Activations
+ * are NHWC in BF16 (matrix-core inputs, FP32 accumulation) or FP32.  Every
+ * reduction has a fixed order: results are reproducible bit for bit.
+ * All device state lives in the caller's workspace; calls are asynchronous on
+ * the given stream unless they return a host value.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_nn lbm_nn; /* opaque; lbm_nn_create / lbm_nn_destroy */
+
+typedef struct {
+    int32_t h, w;      /* lattice rows (ny, multiple of 8) and columns (nx, multiple of 64) */
+    int32_t max_batch; /* samples per call, >= 1 */
+    int32_t dtype;     /* LBM_BF16 or LBM_F32 activations */
+    int32_t ch[4];     /* channels per level, multiples of 32 */
+    double rho_scale;  /* scale of the density output */
+} lbm_nn_config;
+
+/* Workspace bytes of a network (LBM_EINVAL for an invalid configuration). */
+lbm_status lbm_nn_workspace_bytes(const lbm_nn_config* cfg, size_t* bytes);
+
+/* Lay out the workspace (256-byte aligned device memory of at least
+ * lbm_nn_workspace_bytes); parameters start at zero. */
+lbm_status lbm_nn_create(const lbm_nn_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                         lbm_nn** out);
+
+/* Number of FP32 parameters. */
+int64_t lbm_nn_param_count(const lbm_nn* nn);
+
+/* Copy the parameter vector in (also resets Adam's moments) or out; device
+ * memory of lbm_nn_param_count floats. */
+lbm_status lbm_nn_set_params(lbm_nn* nn, const float* d_params);
+lbm_status lbm_nn_get_params(lbm_nn* nn, float* d_params);
+
+/* Gradient of the last lbm_nn_backward / lbm_nn_train_step (device, FP32). */
+lbm_status lbm_nn_get_grads(lbm_nn* nn, float* d_grads);
+
+/* Network output y [batch][h][w][3] (FP32) of the input x [batch][h][w][2]
+ * (FP32), device memory. */
+lbm_status lbm_nn_forward(lbm_nn* nn, const float* d_x, int32_t batch, float* d_y);
+
+/* Gradient of sum(gy * y) with respect to the parameters, for the input of
+ * the last lbm_nn_forward; gy [batch][h][w][3] FP32 device memory. */
+lbm_status lbm_nn_backward(lbm_nn* nn, const float* d_gy);
+
+/* One Adam step (Kingma and Ba, bias-corrected) on the current gradient. */
+lbm_status lbm_nn_adam(lbm_nn* nn, double lr, double beta1, double beta2, double eps);
+
+/* Training step on the samples d_idx[0..batch) (NULL: 0..batch-1) of a data
+ * set held in device memory: solid mask u8 [N][h][w], steady fields rho, u_x,
+ * u_y FP32 [N][h][w], and per sample Re, g_x and tau (FP64 [N]).  The loss is
+ * the mean over fluid nodes and the 3 outputs of the squared error of the
+ * normalised output; then backward and Adam (beta 0.9, 0.999, eps 1e-8) with
+ * learning rate lr.  *loss (optional, host) receives the loss before the
+ * update and makes the call synchronise. */
+lbm_status lbm_nn_train_step(lbm_nn* nn, const uint8_t* d_solid, const float* d_rho, const float* d_ux,
+                             const float* d_uy, const double* d_re, const double* d_gx, const double* d_tau,
+                             const int32_t* d_idx, int32_t batch, double lr, double* loss);
+
+/* The loss of lbm_nn_train_step without the update (synchronises). */
+lbm_status lbm_nn_eval(lbm_nn* nn, const uint8_t* d_solid, const float* d_rho, const float* d_ux, const float* d_uy,
+                       const double* d_re, const double* d_gx, const double* d_tau, const int32_t* d_idx,
+                       int32_t batch, double* loss);
+
+/* Warm-start fields of `batch` channels: solid mask u8 [batch][h][w] and per
+ * sample Re, g_x, tau (FP64 device [batch]) -> rho, u_x, u_y FP32
+ * [batch][h][w] (0 at solid nodes), device memory. */
+lbm_status lbm_nn_infer(lbm_nn* nn, const uint8_t* d_solid, const double* d_re, const double* d_gx,
+                        const double* d_tau, int32_t batch, float* d_rho, float* d_ux, float* d_uy);
+
+/* Release the network (not the caller's buffers).  NULL is ignored. */
+void lbm_nn_destroy(lbm_nn* nn);
+
+/* Message of the last failure on this network, or (NULL) of the last failed
+ * lbm_nn_create / lbm_nn_workspace_bytes in this thread. */
+const char* lbm_nn_last_error(const lbm_nn* nn);
+
 #ifdef __cplusplus
 }
 #endif

@@ -135,27 +135,46 @@ def upsample_backward(g):
     return g.reshape(Bn, H // 2, 2, Wd // 2, 2, C).sum(axis=(2, 4))
 
 
+# ----------------------------------------------------------------- storage
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even) through float32, as a
+    float32 value is stored in 16 bits: keep the top 16 bits after adding
+    0x7fff plus the lowest kept bit."""
+    u = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32)).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(x):
+    return x
+
+
 # ----------------------------------------------------------------- network
-def forward(params, x, ch=(32, 64, 128, 256)):
+# `q` is the storage rounding of every tensor that is kept between layers
+# (network input, weights, activations, pooled maps, and in backward the
+# activation gradients); the identity by default.  With q = bf16 the ReLU
+# decisions and stored values are those of a BF16-storage implementation while
+# the arithmetic stays in float64.
+def forward(params, x, ch=(32, 64, 128, 256), q=_ident):
     """Returns (output, tape) where tape holds what backward needs."""
-    L = unpack(params, ch)
+    L = [(q(W), b) for W, b in unpack(params, ch)]
     shapes = layer_shapes(ch)
     tape = []
 
     def layer(k, inp):
         W, b = L[k]
         pre = conv(inp, W, b)
-        out = np.maximum(pre, 0.0) if shapes[k][2] else pre
+        out = q(np.maximum(pre, 0.0)) if shapes[k][2] else pre
         tape.append((k, inp, pre))
         return out
 
     skips = []
-    h = x
+    h = q(x)
     for lev in range(3):
         h = layer(2 * lev, h)
         h = layer(2 * lev + 1, h)
         skips.append(h)
-        h = pool(h)
+        h = q(pool(h))
     h = layer(6, h)
     h = layer(7, h)
     for j, lev in enumerate((2, 1, 0)):
@@ -166,10 +185,11 @@ def forward(params, x, ch=(32, 64, 128, 256)):
     return y, tape
 
 
-def backward(params, tape, gy, ch=(32, 64, 128, 256)):
+def backward(params, tape, gy, ch=(32, 64, 128, 256), q=_ident):
     """Gradient of sum(gy * forward(params, x)) with respect to the parameter
-    vector (same layout)."""
-    L = unpack(params, ch)
+    vector (same layout); q as in forward (the tape must come from a forward
+    with the same q)."""
+    L = [(q(W), b) for W, b in unpack(params, ch)]
     shapes = layer_shapes(ch)
     grads = [None] * len(L)
     by_k = {k: (inp, pre) for k, inp, pre in tape}
@@ -180,9 +200,9 @@ def backward(params, tape, gy, ch=(32, 64, 128, 256)):
         g_pre = g_out * (pre > 0) if shapes[k][2] else g_out
         gx, dW, db = conv_backward(inp, L[k][0], g_pre)
         grads[k] = (dW, db)
-        return gx
+        return q(gx)
 
-    g = layer_back(14, gy)
+    g = layer_back(14, q(gy))
     g_skip = [None, None, None]
     # decoder in reverse order: level 0 (layers 12, 13) was applied last
     for j, lev in ((2, 0), (1, 1), (0, 2)):
@@ -190,11 +210,11 @@ def backward(params, tape, gy, ch=(32, 64, 128, 256)):
         g = layer_back(8 + 2 * j, g)
         c_up = g.shape[3] - c[lev]
         g_skip[lev] = g[..., c_up:]
-        g = upsample_backward(g[..., :c_up])
+        g = q(upsample_backward(g[..., :c_up]))
     g = layer_back(7, g)
     g = layer_back(6, g)
     for lev in (2, 1, 0):
-        g = pool_backward(g) + g_skip[lev]
+        g = q(pool_backward(g) + g_skip[lev])
         g = layer_back(2 * lev + 1, g)
         g = layer_back(2 * lev, g)
     return pack(grads)

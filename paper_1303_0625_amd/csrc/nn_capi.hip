@@ -1,0 +1,671 @@
+// nn_capi.hip -- host side of the warm-start network ABI (lbm_nn_* in
+// include/lbm.h): workspace layout, layer table, and the launch sequences of
+// the forward pass, the backward pass, Adam and inference.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "nn_kernels.h"
+
+using namespace nn;
+
+namespace {
+
+thread_local char g_nn_err[512] = "";
+
+void nn_set_err(char* buf, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+}
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr int kLayers = 15;
+
+// Activation and gradient tensors (NHWC, compute type), by name.
+enum Buf {
+    X0, A0, CAT0, X1, A1, CAT1, X2, A2, CAT2, X3, B1, B2, D2A, D2B, D1A, D1B, D0A, D0B,
+    G_HEAD, G_D0B, G_D0A, G_CAT0, G_D1B, G_D1A, G_CAT1, G_D2B, G_D2A, G_CAT2, G_B2, G_B1, G_X3,
+    G_S2, G_A2, G_X2, G_S1, G_A1, G_X1, G_S0, G_A0, NBUF
+};
+
+struct BufShape {
+    int level;
+    int ch;
+};
+
+struct Plan {
+    int H, W, B;
+    int c[4];
+    int es;  // bytes per element of the compute type
+    BufShape shape[NBUF];
+    LayerDev L[kLayers];
+    int64_t n_params, wf_total, wt_total, b_total;
+    int64_t wpart_max;  // floats of the largest weight-gradient partial
+    int64_t bpart_max;  // floats of the largest bias partial
+    size_t off[NBUF];
+    size_t o_master, o_grad, o_m, o_v, o_wf, o_wt, o_bias, o_out, o_tgt, o_fluid, o_wpart, o_bpart,
+        o_lpart, o_loss, o_idx, total;
+};
+
+int64_t pixels(const Plan& p, int level) { return (int64_t)p.B * (p.H >> level) * (p.W >> level); }
+
+// Splits of the weight-gradient GEMM of a layer whose input lives at `level`.
+void wgrad_split(const Plan& p, int level, int tiles, int& splits, int& chunk) {
+    const int64_t P = pixels(p, level);
+    int s = std::max(1, 2048 / std::max(tiles, 1));
+    s = (int)std::min<int64_t>(s, std::max<int64_t>(1, P / 256));
+    chunk = (int)(((P + s - 1) / s + 63) / 64 * 64);
+    splits = (int)((P + chunk - 1) / chunk);
+}
+
+int mb_of(int cout_pad) { return cout_pad % 64 == 0 ? 2 : 1; }
+
+const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
+    if (cfg.h < 8 || cfg.h % 8 != 0) return "h must be a positive multiple of 8";
+    if (cfg.w < 64 || cfg.w % 64 != 0) return "w must be a positive multiple of 64";
+    if (cfg.max_batch < 1) return "max_batch must be >= 1";
+    if (cfg.dtype != LBM_BF16 && cfg.dtype != LBM_F32) return "dtype must be LBM_BF16 or LBM_F32";
+    for (int k = 0; k < 4; ++k)
+        if (cfg.ch[k] < 32 || cfg.ch[k] % 32 != 0 || cfg.ch[k] > 1024) return "channels must be multiples of 32 in [32, 1024]";
+    if (!(cfg.rho_scale > 0.0)) return "rho_scale must be > 0";
+    if ((int64_t)cfg.max_batch * cfg.h * cfg.w >= (1LL << 31) / 32) return "max_batch * h * w too large";
+    p.H = cfg.h;
+    p.W = cfg.w;
+    p.B = cfg.max_batch;
+    for (int k = 0; k < 4; ++k) p.c[k] = cfg.ch[k];
+    p.es = cfg.dtype == LBM_BF16 ? 2 : 4;
+    const int c0 = p.c[0], c1 = p.c[1], c2 = p.c[2], c3 = p.c[3];
+    const BufShape sh[NBUF] = {
+        {0, 16}, {0, c0}, {0, c1 + c0}, {1, c0}, {1, c1}, {1, c2 + c1}, {2, c1}, {2, c2}, {2, c3 + c2}, {3, c2},
+        {3, c3}, {3, c3}, {2, c2}, {2, c2}, {1, c1}, {1, c1}, {0, c0}, {0, c0},
+        {0, 32}, {0, c0}, {0, c0}, {0, c1 + c0}, {1, c1}, {1, c1}, {1, c2 + c1}, {2, c2}, {2, c2}, {2, c3 + c2},
+        {3, c3}, {3, c3}, {3, c2}, {2, c2}, {2, c2}, {2, c1}, {1, c1}, {1, c1}, {1, c0}, {0, c0}, {0, c0}};
+    for (int k = 0; k < NBUF; ++k) p.shape[k] = sh[k];
+    const int cin[kLayers] = {2, c0, c0, c1, c1, c2, c2, c3, c3 + c2, c2, c2 + c1, c1, c1 + c0, c0, c0};
+    const int cout[kLayers] = {c0, c0, c1, c1, c2, c2, c3, c3, c2, c2, c1, c1, c0, c0, 3};
+    int64_t off = 0, wf = 0, wt = 0, bo = 0;
+    p.wpart_max = 1;
+    p.bpart_max = 1;
+    const int level_in[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+    for (int k = 0; k < kLayers; ++k) {
+        LayerDev& L = p.L[k];
+        L.off = off;
+        L.cin = cin[k];
+        L.cout = cout[k];
+        L.cin_pad = (cin[k] + 15) / 16 * 16;
+        L.cout_pad = (cout[k] + 31) / 32 * 32;
+        L.cin_dg = (cin[k] + 31) / 32 * 32;
+        L.wf_off = wf;
+        L.wt_off = wt;
+        L.b_off = bo;
+        off += (int64_t)cout[k] * 9 * cin[k] + cout[k];
+        wf += (int64_t)L.cout_pad * 9 * L.cin_pad;
+        wt += (int64_t)L.cin_dg * 9 * L.cout_pad;
+        bo += L.cout_pad;
+        const int mb = mb_of(L.cout_pad), nbk = L.cin_dg % 64 == 0 ? 2 : 1;
+        const int tiles = (L.cout_pad / (32 * mb)) * (L.cin_dg / (32 * nbk)) * 9;
+        int splits, chunk;
+        wgrad_split(p, level_in[k], tiles, splits, chunk);
+        p.wpart_max = std::max<int64_t>(p.wpart_max, (int64_t)splits * cout[k] * 9 * cin[k]);
+        const int64_t P = pixels(p, level_in[k]);
+        p.bpart_max = std::max<int64_t>(p.bpart_max, ((P + 255) / 256) * cout[k]);
+    }
+    p.n_params = off;
+    p.wf_total = wf;
+    p.wt_total = wt;
+    p.b_total = bo;
+    size_t o = 0;
+    auto take = [&](size_t& dst, size_t bytes) {
+        dst = o;
+        o = al256(o + std::max<size_t>(bytes, 4));
+    };
+    take(p.o_master, 4 * (size_t)off);
+    take(p.o_grad, 4 * (size_t)off);
+    take(p.o_m, 4 * (size_t)off);
+    take(p.o_v, 4 * (size_t)off);
+    take(p.o_wf, (size_t)p.es * wf);
+    take(p.o_wt, (size_t)p.es * wt);
+    take(p.o_bias, 4 * (size_t)bo);
+    for (int k = 0; k < NBUF; ++k) take(p.off[k], (size_t)p.es * pixels(p, p.shape[k].level) * p.shape[k].ch);
+    const int64_t P0 = pixels(p, 0);
+    take(p.o_out, 12 * (size_t)P0);
+    take(p.o_tgt, 12 * (size_t)P0);
+    take(p.o_fluid, (size_t)P0);
+    take(p.o_wpart, 4 * (size_t)p.wpart_max);
+    take(p.o_bpart, 4 * (size_t)p.bpart_max);
+    take(p.o_lpart, 16 * (size_t)((P0 + kEw - 1) / kEw));
+    take(p.o_loss, 16);
+    take(p.o_idx, 4 * (size_t)p.B);
+    p.total = o;
+    return nullptr;
+}
+
+}  // namespace
+
+struct lbm_nn {
+    Plan p;
+    int dtype;
+    double rho_scale;
+    hipStream_t st;
+    char* ws;
+    int batch = 0;       // batch of the last forward
+    int64_t adam_t = 0;  // Adam steps taken
+    char err[512];
+};
+
+namespace {
+
+template <typename T = void>
+T* at(lbm_nn* n, size_t off) {
+    return reinterpret_cast<T*>(n->ws + off);
+}
+
+lbm_status nn_fail(lbm_nn* n, hipError_t e, const char* what) {
+    nn_set_err(n ? n->err : g_nn_err, "%s: %s", what, hipGetErrorString(e));
+    return LBM_EDEVICE;
+}
+
+#define NNCHK(n, call)                                     \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return nn_fail(n, e_, #call); \
+    } while (0)
+
+unsigned blocks(int64_t n, int per = kEw) { return (unsigned)((n + per - 1) / per); }
+
+void* buf(lbm_nn* n, Buf b) { return n->ws + n->p.off[b]; }
+
+// One convolution: input tensor (ptr, channel stride, channels read), layer
+// weights (forward or input-gradient form), output (ptr, stride, offset,
+// channels), optional ReLU and ReLU mask.
+template <typename T, typename OT>
+void conv(lbm_nn* n, int level, const void* in, int in_cs, int cin, const void* w, const float* bias, void* out,
+          int out_cs, int out_co, int cout, int cout_pad, bool relu, const void* mask, int mask_cs, int mask_co) {
+    const Plan& p = n->p;
+    ConvArgs a;
+    a.in = in;
+    a.in_cs = in_cs;
+    a.cin = cin;
+    a.w = w;
+    a.bias = bias;
+    a.out = out;
+    a.out_cs = out_cs;
+    a.out_co = out_co;
+    a.cout = cout;
+    a.mask = mask;
+    a.mask_cs = mask_cs;
+    a.mask_co = mask_co;
+    a.relu = relu ? 1 : 0;
+    a.H = p.H >> level;
+    a.W = p.W >> level;
+    a.P = (int)((int64_t)n->batch * a.H * a.W);
+    if (cout_pad % 64 == 0) {
+        dim3 g(blocks(a.P, 32 * 2 * kConvWaves), cout_pad / 64);
+        k_conv<T, OT, 2, 2><<<g, kConvWaves * 64, 0, n->st>>>(a);
+    } else {
+        dim3 g(blocks(a.P, 32 * 4 * kConvWaves), cout_pad / 32);
+        k_conv<T, OT, 4, 1><<<g, kConvWaves * 64, 0, n->st>>>(a);
+    }
+}
+
+template <typename T>
+void layer_fwd(lbm_nn* n, int k, int level, Buf in, Buf out, int out_cs, int out_co) {
+    const LayerDev& L = n->p.L[k];
+    conv<T, T>(n, level, buf(n, in), n->p.shape[in].ch, L.cin_pad, at<T>(n, n->p.o_wf) + L.wf_off,
+               at<float>(n, n->p.o_bias) + L.b_off, buf(n, out), out_cs, out_co, L.cout, L.cout_pad, true, nullptr, 0,
+               0);
+}
+
+// Input gradient of layer k: g_in = conv(g_pre, flipped weights), times the
+// ReLU mask of `act` (the layer's forward input) when given.
+template <typename T>
+void layer_dgrad(lbm_nn* n, int k, int level, Buf g_pre, Buf g_in, Buf act, int act_cs, int act_co, bool use_mask) {
+    const LayerDev& L = n->p.L[k];
+    conv<T, T>(n, level, buf(n, g_pre), n->p.shape[g_pre].ch, L.cout_pad, at<T>(n, n->p.o_wt) + L.wt_off, nullptr,
+               buf(n, g_in), n->p.shape[g_in].ch, 0, L.cin, L.cin_dg, false, use_mask ? buf(n, act) : nullptr, act_cs,
+               act_co);
+}
+
+// Weight and bias gradient of layer k from its forward input x (at `level`)
+// and its pre-activation gradient g.
+template <typename T>
+void layer_wgrad(lbm_nn* n, int k, int level, Buf x, Buf g) {
+    const Plan& p = n->p;
+    const LayerDev& L = p.L[k];
+    WgradArgs a;
+    a.g = buf(n, g);
+    a.g_cs = p.shape[g].ch;
+    a.x = buf(n, x);
+    a.x_cs = p.shape[x].ch;
+    a.cout = L.cout;
+    a.cin = L.cin;
+    a.H = p.H >> level;
+    a.W = p.W >> level;
+    a.P = (int)((int64_t)n->batch * a.H * a.W);
+    const int mb = mb_of(L.cout_pad), nbk = L.cin_dg % 64 == 0 ? 2 : 1;
+    a.co_blocks = L.cout_pad / (32 * mb);
+    a.ci_blocks = L.cin_dg / (32 * nbk);
+    const int tiles = a.co_blocks * a.ci_blocks * 9;
+    int splits, chunk;
+    // split against the planned batch so the partial buffer always fits
+    Plan q = p;
+    q.B = n->batch;
+    wgrad_split(q, level, tiles, splits, chunk);
+    a.chunk_per_split = chunk;
+    a.part = at<float>(n, p.o_wpart);
+    dim3 gr(tiles, splits);
+    if (mb == 2 && nbk == 2)
+        k_wgrad<T, 2, 2><<<gr, 256, 0, n->st>>>(a);
+    else if (mb == 2)
+        k_wgrad<T, 2, 1><<<gr, 256, 0, n->st>>>(a);
+    else if (nbk == 2)
+        k_wgrad<T, 1, 2><<<gr, 256, 0, n->st>>>(a);
+    else
+        k_wgrad<T, 1, 1><<<gr, 256, 0, n->st>>>(a);
+    const int64_t nw = (int64_t)L.cout * 9 * L.cin;
+    k_sum_splits<<<blocks(nw), kEw, 0, n->st>>>(a.part, splits, nw, at<float>(n, p.o_grad) + L.off);
+    const int rows = 256;
+    const int nblk = (a.P + rows - 1) / rows;
+    k_bias_partial<<<nblk, kEw, 0, n->st>>>(a.g, n->dtype == LBM_BF16 ? 1 : 0, a.g_cs, L.cout, a.P, rows,
+                                            at<float>(n, p.o_bpart));
+    k_bias_final<<<blocks(L.cout), kEw, 0, n->st>>>(at<float>(n, p.o_bpart), nblk, L.cout,
+                                                   at<float>(n, p.o_grad) + L.off + nw);
+}
+
+template <typename T>
+void forward_t(lbm_nn* n) {
+    const Plan& p = n->p;
+    const int c0 = p.c[0], c1 = p.c[1], c2 = p.c[2], c3 = p.c[3];
+    const int B = n->batch;
+    auto H = [&](int l) { return p.H >> l; };
+    auto W = [&](int l) { return p.W >> l; };
+    // encoder
+    layer_fwd<T>(n, 0, 0, X0, A0, c0, 0);
+    layer_fwd<T>(n, 1, 0, A0, CAT0, c1 + c0, c1);
+    k_pool<T><<<blocks((int64_t)B * H(1) * W(1) * c0), kEw, 0, n->st>>>(
+        (const T*)buf(n, CAT0), c1 + c0, c1, c0, (T*)buf(n, X1), H(1), W(1), B);
+    layer_fwd<T>(n, 2, 1, X1, A1, c1, 0);
+    layer_fwd<T>(n, 3, 1, A1, CAT1, c2 + c1, c2);
+    k_pool<T><<<blocks((int64_t)B * H(2) * W(2) * c1), kEw, 0, n->st>>>(
+        (const T*)buf(n, CAT1), c2 + c1, c2, c1, (T*)buf(n, X2), H(2), W(2), B);
+    layer_fwd<T>(n, 4, 2, X2, A2, c2, 0);
+    layer_fwd<T>(n, 5, 2, A2, CAT2, c3 + c2, c3);
+    k_pool<T><<<blocks((int64_t)B * H(3) * W(3) * c2), kEw, 0, n->st>>>(
+        (const T*)buf(n, CAT2), c3 + c2, c3, c2, (T*)buf(n, X3), H(3), W(3), B);
+    // bottleneck
+    layer_fwd<T>(n, 6, 3, X3, B1, c3, 0);
+    layer_fwd<T>(n, 7, 3, B1, B2, c3, 0);
+    // decoder
+    k_upsample<T><<<blocks((int64_t)B * H(2) * W(2) * c3), kEw, 0, n->st>>>(
+        (const T*)buf(n, B2), c3, (T*)buf(n, CAT2), c3 + c2, 0, H(2), W(2), B);
+    layer_fwd<T>(n, 8, 2, CAT2, D2A, c2, 0);
+    layer_fwd<T>(n, 9, 2, D2A, D2B, c2, 0);
+    k_upsample<T><<<blocks((int64_t)B * H(1) * W(1) * c2), kEw, 0, n->st>>>(
+        (const T*)buf(n, D2B), c2, (T*)buf(n, CAT1), c2 + c1, 0, H(1), W(1), B);
+    layer_fwd<T>(n, 10, 1, CAT1, D1A, c1, 0);
+    layer_fwd<T>(n, 11, 1, D1A, D1B, c1, 0);
+    k_upsample<T><<<blocks((int64_t)B * H(0) * W(0) * c1), kEw, 0, n->st>>>(
+        (const T*)buf(n, D1B), c1, (T*)buf(n, CAT0), c1 + c0, 0, H(0), W(0), B);
+    layer_fwd<T>(n, 12, 0, CAT0, D0A, c0, 0);
+    layer_fwd<T>(n, 13, 0, D0A, D0B, c0, 0);
+    // head: no activation, FP32 output [P][3]
+    const LayerDev& L = p.L[14];
+    conv<T, float>(n, 0, buf(n, D0B), c0, L.cin_pad, at<T>(n, p.o_wf) + L.wf_off, at<float>(n, p.o_bias) + L.b_off,
+                   at<float>(n, p.o_out), 3, 0, 3, L.cout_pad, false, nullptr, 0, 0);
+}
+
+// Backward from the padded head gradient G_HEAD: every parameter gradient.
+template <typename T>
+void backward_t(lbm_nn* n) {
+    const Plan& p = n->p;
+    const int c0 = p.c[0], c1 = p.c[1], c2 = p.c[2], c3 = p.c[3];
+    const int B = n->batch;
+    auto H = [&](int l) { return p.H >> l; };
+    auto W = [&](int l) { return p.W >> l; };
+    // head and decoder level 0
+    layer_wgrad<T>(n, 14, 0, D0B, G_HEAD);
+    layer_dgrad<T>(n, 14, 0, G_HEAD, G_D0B, D0B, c0, 0, true);
+    layer_wgrad<T>(n, 13, 0, D0A, G_D0B);
+    layer_dgrad<T>(n, 13, 0, G_D0B, G_D0A, D0A, c0, 0, true);
+    layer_wgrad<T>(n, 12, 0, CAT0, G_D0A);
+    layer_dgrad<T>(n, 12, 0, G_D0A, G_CAT0, CAT0, 0, 0, false);
+    k_upsample_back<T><<<blocks((int64_t)B * H(1) * W(1) * c1), kEw, 0, n->st>>>(
+        (const T*)buf(n, G_CAT0), c1 + c0, 0, c1, (const T*)buf(n, D1B), (T*)buf(n, G_D1B), H(1), W(1), B);
+    // decoder level 1
+    layer_wgrad<T>(n, 11, 1, D1A, G_D1B);
+    layer_dgrad<T>(n, 11, 1, G_D1B, G_D1A, D1A, c1, 0, true);
+    layer_wgrad<T>(n, 10, 1, CAT1, G_D1A);
+    layer_dgrad<T>(n, 10, 1, G_D1A, G_CAT1, CAT1, 0, 0, false);
+    k_upsample_back<T><<<blocks((int64_t)B * H(2) * W(2) * c2), kEw, 0, n->st>>>(
+        (const T*)buf(n, G_CAT1), c2 + c1, 0, c2, (const T*)buf(n, D2B), (T*)buf(n, G_D2B), H(2), W(2), B);
+    // decoder level 2
+    layer_wgrad<T>(n, 9, 2, D2A, G_D2B);
+    layer_dgrad<T>(n, 9, 2, G_D2B, G_D2A, D2A, c2, 0, true);
+    layer_wgrad<T>(n, 8, 2, CAT2, G_D2A);
+    layer_dgrad<T>(n, 8, 2, G_D2A, G_CAT2, CAT2, 0, 0, false);
+    k_upsample_back<T><<<blocks((int64_t)B * H(3) * W(3) * c3), kEw, 0, n->st>>>(
+        (const T*)buf(n, G_CAT2), c3 + c2, 0, c3, (const T*)buf(n, B2), (T*)buf(n, G_B2), H(3), W(3), B);
+    // bottleneck
+    layer_wgrad<T>(n, 7, 3, B1, G_B2);
+    layer_dgrad<T>(n, 7, 3, G_B2, G_B1, B1, c3, 0, true);
+    layer_wgrad<T>(n, 6, 3, X3, G_B1);
+    layer_dgrad<T>(n, 6, 3, G_B1, G_X3, X3, 0, 0, false);
+    // encoder level 2
+    k_pool_back_skip<T><<<blocks((int64_t)B * H(2) * W(2) * c2), kEw, 0, n->st>>>(
+        (const T*)buf(n, G_X3), (const T*)buf(n, G_CAT2), c3 + c2, c3, (const T*)buf(n, CAT2), c2, (T*)buf(n, G_S2),
+        H(2), W(2), B);
+    layer_wgrad<T>(n, 5, 2, A2, G_S2);
+    layer_dgrad<T>(n, 5, 2, G_S2, G_A2, A2, c2, 0, true);
+    layer_wgrad<T>(n, 4, 2, X2, G_A2);
+    layer_dgrad<T>(n, 4, 2, G_A2, G_X2, X2, 0, 0, false);
+    // encoder level 1
+    k_pool_back_skip<T><<<blocks((int64_t)B * H(1) * W(1) * c1), kEw, 0, n->st>>>(
+        (const T*)buf(n, G_X2), (const T*)buf(n, G_CAT1), c2 + c1, c2, (const T*)buf(n, CAT1), c1, (T*)buf(n, G_S1),
+        H(1), W(1), B);
+    layer_wgrad<T>(n, 3, 1, A1, G_S1);
+    layer_dgrad<T>(n, 3, 1, G_S1, G_A1, A1, c1, 0, true);
+    layer_wgrad<T>(n, 2, 1, X1, G_A1);
+    layer_dgrad<T>(n, 2, 1, G_A1, G_X1, X1, 0, 0, false);
+    // encoder level 0
+    k_pool_back_skip<T><<<blocks((int64_t)B * H(0) * W(0) * c0), kEw, 0, n->st>>>(
+        (const T*)buf(n, G_X1), (const T*)buf(n, G_CAT0), c1 + c0, c1, (const T*)buf(n, CAT0), c0, (T*)buf(n, G_S0),
+        H(0), W(0), B);
+    layer_wgrad<T>(n, 1, 0, A0, G_S0);
+    layer_dgrad<T>(n, 1, 0, G_S0, G_A0, A0, c0, 0, true);
+    layer_wgrad<T>(n, 0, 0, X0, G_A0);
+}
+
+template <typename T>
+void pack_weights_t(lbm_nn* n) {
+    const Plan& p = n->p;
+    for (int k = 0; k < kLayers; ++k) {
+        const LayerDev& L = p.L[k];
+        const int64_t m = std::max<int64_t>(std::max<int64_t>((int64_t)L.cout_pad * 9 * L.cin_pad,
+                                                             (int64_t)L.cin_dg * 9 * L.cout_pad),
+                                            L.cout_pad);
+        k_pack_weights<T><<<blocks(m), kEw, 0, n->st>>>(at<float>(n, p.o_master), L, at<T>(n, p.o_wf),
+                                                       at<T>(n, p.o_wt), at<float>(n, p.o_bias));
+    }
+}
+
+void pack_weights(lbm_nn* n) {
+    if (n->dtype == LBM_BF16)
+        pack_weights_t<__bf16>(n);
+    else
+        pack_weights_t<float>(n);
+}
+
+void forward(lbm_nn* n) {
+    if (n->dtype == LBM_BF16)
+        forward_t<__bf16>(n);
+    else
+        forward_t<float>(n);
+}
+
+void backward(lbm_nn* n) {
+    if (n->dtype == LBM_BF16)
+        backward_t<__bf16>(n);
+    else
+        backward_t<float>(n);
+}
+
+void adam(lbm_nn* n, double lr, double b1, double b2, double eps) {
+    n->adam_t += 1;
+    const double c1 = 1.0 - std::pow(b1, (double)n->adam_t);
+    const double c2 = 1.0 - std::pow(b2, (double)n->adam_t);
+    const Plan& p = n->p;
+    k_adam<<<blocks(p.n_params), kEw, 0, n->st>>>(at<float>(n, p.o_master), at<float>(n, p.o_grad),
+                                                   at<float>(n, p.o_m), at<float>(n, p.o_v), p.n_params, (float)lr,
+                                                   (float)b1, (float)b2, (float)eps, (float)c1, (float)c2);
+    pack_weights(n);
+}
+
+// Loss of the output against the packed target; writes the head gradient.
+template <typename T>
+void loss_t(lbm_nn* n) {
+    const Plan& p = n->p;
+    const int64_t P = (int64_t)n->batch * p.H * p.W;
+    const int nb = (int)blocks(P);
+    k_loss_partial<<<nb, kEw, 0, n->st>>>(at<float>(n, p.o_out), at<float>(n, p.o_tgt), at<uint8_t>(n, p.o_fluid), P,
+                                          at<double>(n, p.o_lpart));
+    k_loss_final<<<1, 64, 0, n->st>>>(at<double>(n, p.o_lpart), nb, at<double>(n, p.o_loss));
+    k_loss_grad<T><<<nb, kEw, 0, n->st>>>(at<float>(n, p.o_out), at<float>(n, p.o_tgt), at<uint8_t>(n, p.o_fluid), P,
+                                         at<double>(n, p.o_loss), (T*)buf(n, G_HEAD));
+}
+
+template <typename T>
+void pack_sample_t(lbm_nn* n, const uint8_t* solid, const float* rho, const float* ux, const float* uy,
+                   const double* re, const double* gx, const double* tau, const int* idx) {
+    const Plan& p = n->p;
+    const int64_t P = (int64_t)n->batch * p.H * p.W;
+    k_pack_input<T><<<blocks(P), kEw, 0, n->st>>>(solid, re, idx, p.H * p.W, n->batch, (T*)buf(n, X0));
+    if (rho)
+        k_pack_target<<<blocks(P), kEw, 0, n->st>>>(solid, rho, ux, uy, gx, tau, idx, p.H, p.W, n->batch,
+                                                    n->rho_scale, at<float>(n, p.o_tgt), at<uint8_t>(n, p.o_fluid));
+}
+
+lbm_status sync_check(lbm_nn* n) {
+    NNCHK(n, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status check_batch(lbm_nn* n, int batch) {
+    if (batch < 1 || batch > n->p.B) {
+        nn_set_err(n->err, "batch must be in [1, %d]", n->p.B);
+        return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_nn_workspace_bytes(const lbm_nn_config* cfg, size_t* bytes) {
+    if (!cfg || !bytes) {
+        nn_set_err(g_nn_err, "cfg and bytes must not be NULL");
+        return LBM_EINVAL;
+    }
+    Plan p;
+    const char* why = make_plan(*cfg, p);
+    if (why) {
+        nn_set_err(g_nn_err, "%s", why);
+        return LBM_EINVAL;
+    }
+    *bytes = p.total;
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_create(const lbm_nn_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                         lbm_nn** out) {
+    if (!cfg || !out) {
+        nn_set_err(g_nn_err, "cfg and out must not be NULL");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    Plan p;
+    const char* why = make_plan(*cfg, p);
+    if (why) {
+        nn_set_err(g_nn_err, "%s", why);
+        return LBM_EINVAL;
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace & 255) != 0) {
+        nn_set_err(g_nn_err, "workspace must be a non-NULL 256-byte aligned device pointer");
+        return LBM_EINVAL;
+    }
+    if (bytes < p.total) {
+        nn_set_err(g_nn_err, "workspace too small: %zu < %zu bytes", bytes, p.total);
+        return LBM_ESIZE;
+    }
+    lbm_nn* n = new (std::nothrow) lbm_nn();
+    if (!n) return LBM_EINVAL;
+    n->p = p;
+    n->dtype = cfg->dtype;
+    n->rho_scale = cfg->rho_scale;
+    n->st = (hipStream_t)hip_stream;
+    n->ws = (char*)d_workspace;
+    n->err[0] = 0;
+    // parameters, gradients and Adam moments start at zero
+    for (size_t o : {p.o_master, p.o_grad, p.o_m, p.o_v})
+        k_zero_f32<<<blocks(p.n_params), kEw, 0, n->st>>>(at<float>(n, o), p.n_params);
+    pack_weights(n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        nn_set_err(g_nn_err, "initialisation failed: %s", hipGetErrorString(e));
+        delete n;
+        return LBM_EDEVICE;
+    }
+    *out = n;
+    return LBM_OK;
+}
+
+int64_t lbm_nn_param_count(const lbm_nn* n) { return n ? n->p.n_params : -1; }
+
+lbm_status lbm_nn_set_params(lbm_nn* n, const float* d_params) {
+    if (!n || !d_params) return LBM_EINVAL;
+    const Plan& p = n->p;
+    NNCHK(n, hipMemcpyAsync(at<float>(n, p.o_master), d_params, 4 * (size_t)p.n_params, hipMemcpyDeviceToDevice, n->st));
+    for (size_t o : {p.o_m, p.o_v}) k_zero_f32<<<blocks(p.n_params), kEw, 0, n->st>>>(at<float>(n, o), p.n_params);
+    n->adam_t = 0;
+    pack_weights(n);
+    return sync_check(n);
+}
+
+lbm_status lbm_nn_get_params(lbm_nn* n, float* d_out) {
+    if (!n || !d_out) return LBM_EINVAL;
+    NNCHK(n, hipMemcpyAsync(d_out, at<float>(n, n->p.o_master), 4 * (size_t)n->p.n_params, hipMemcpyDeviceToDevice,
+                            n->st));
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_get_grads(lbm_nn* n, float* d_out) {
+    if (!n || !d_out) return LBM_EINVAL;
+    NNCHK(n, hipMemcpyAsync(d_out, at<float>(n, n->p.o_grad), 4 * (size_t)n->p.n_params, hipMemcpyDeviceToDevice,
+                            n->st));
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_forward(lbm_nn* n, const float* d_x, int32_t batch, float* d_y) {
+    if (!n || !d_x || !d_y) return LBM_EINVAL;
+    lbm_status rs = check_batch(n, batch);
+    if (rs != LBM_OK) return rs;
+    n->batch = batch;
+    const int64_t P = (int64_t)batch * n->p.H * n->p.W;
+    if (n->dtype == LBM_BF16)
+        k_pack_raw<__bf16><<<blocks(P), kEw, 0, n->st>>>(d_x, P, (__bf16*)buf(n, X0));
+    else
+        k_pack_raw<float><<<blocks(P), kEw, 0, n->st>>>(d_x, P, (float*)buf(n, X0));
+    forward(n);
+    NNCHK(n, hipMemcpyAsync(d_y, at<float>(n, n->p.o_out), 12 * (size_t)P, hipMemcpyDeviceToDevice, n->st));
+    return sync_check(n);
+}
+
+lbm_status lbm_nn_backward(lbm_nn* n, const float* d_gy) {
+    if (!n || !d_gy) return LBM_EINVAL;
+    if (n->batch < 1) {
+        nn_set_err(n->err, "backward needs a forward first");
+        return LBM_ESTATE;
+    }
+    const int64_t P = (int64_t)n->batch * n->p.H * n->p.W;
+    if (n->dtype == LBM_BF16)
+        k_pack_head_grad<__bf16><<<blocks(P), kEw, 0, n->st>>>(d_gy, P, (__bf16*)buf(n, G_HEAD));
+    else
+        k_pack_head_grad<float><<<blocks(P), kEw, 0, n->st>>>(d_gy, P, (float*)buf(n, G_HEAD));
+    backward(n);
+    return sync_check(n);
+}
+
+lbm_status lbm_nn_adam(lbm_nn* n, double lr, double beta1, double beta2, double eps) {
+    if (!n || !(lr > 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0)) {
+        if (n) nn_set_err(n->err, "Adam needs lr > 0, 0 <= beta < 1, eps > 0");
+        return LBM_EINVAL;
+    }
+    adam(n, lr, beta1, beta2, eps);
+    return sync_check(n);
+}
+
+static lbm_status train_or_eval(lbm_nn* n, const uint8_t* solid, const float* rho, const float* ux, const float* uy,
+                                const double* re, const double* gx, const double* tau, const int32_t* idx,
+                                int32_t batch, double lr, double* loss, bool train) {
+    if (!n || !solid || !rho || !ux || !uy || !re || !gx || !tau) return LBM_EINVAL;
+    lbm_status rs = check_batch(n, batch);
+    if (rs != LBM_OK) return rs;
+    if (train && !(lr > 0.0)) {
+        nn_set_err(n->err, "lr must be > 0");
+        return LBM_EINVAL;
+    }
+    n->batch = batch;
+    if (n->dtype == LBM_BF16) {
+        pack_sample_t<__bf16>(n, solid, rho, ux, uy, re, gx, tau, idx);
+        forward_t<__bf16>(n);
+        loss_t<__bf16>(n);
+        if (train) backward_t<__bf16>(n);
+    } else {
+        pack_sample_t<float>(n, solid, rho, ux, uy, re, gx, tau, idx);
+        forward_t<float>(n);
+        loss_t<float>(n);
+        if (train) backward_t<float>(n);
+    }
+    if (train) adam(n, lr, 0.9, 0.999, 1e-8);
+    rs = sync_check(n);
+    if (rs != LBM_OK) return rs;
+    if (loss) {
+        double v[2];
+        NNCHK(n, hipMemcpyAsync(v, at<double>(n, n->p.o_loss), 16, hipMemcpyDeviceToHost, n->st));
+        NNCHK(n, hipStreamSynchronize(n->st));
+        *loss = v[0];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_nn_train_step(lbm_nn* n, const uint8_t* d_solid, const float* d_rho, const float* d_ux,
+                             const float* d_uy, const double* d_re, const double* d_gx, const double* d_tau,
+                             const int32_t* d_idx, int32_t batch, double lr, double* loss) {
+    return train_or_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch, lr, loss, true);
+}
+
+lbm_status lbm_nn_eval(lbm_nn* n, const uint8_t* d_solid, const float* d_rho, const float* d_ux, const float* d_uy,
+                       const double* d_re, const double* d_gx, const double* d_tau, const int32_t* d_idx,
+                       int32_t batch, double* loss) {
+    return train_or_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch, 0.0, loss, false);
+}
+
+lbm_status lbm_nn_infer(lbm_nn* n, const uint8_t* d_solid, const double* d_re, const double* d_gx,
+                        const double* d_tau, int32_t batch, float* d_rho, float* d_ux, float* d_uy) {
+    if (!n || !d_solid || !d_re || !d_gx || !d_tau || !d_rho || !d_ux || !d_uy) return LBM_EINVAL;
+    lbm_status rs = check_batch(n, batch);
+    if (rs != LBM_OK) return rs;
+    n->batch = batch;
+    const Plan& p = n->p;
+    const int64_t P = (int64_t)batch * p.H * p.W;
+    if (n->dtype == LBM_BF16) {
+        pack_sample_t<__bf16>(n, d_solid, nullptr, nullptr, nullptr, d_re, d_gx, d_tau, nullptr);
+        forward_t<__bf16>(n);
+    } else {
+        pack_sample_t<float>(n, d_solid, nullptr, nullptr, nullptr, d_re, d_gx, d_tau, nullptr);
+        forward_t<float>(n);
+    }
+    k_unpack_fields<<<blocks(P), kEw, 0, n->st>>>(at<float>(n, p.o_out), d_solid, d_gx, d_tau, p.H, p.W, batch,
+                                                  n->rho_scale, d_rho, d_ux, d_uy);
+    return sync_check(n);
+}
+
+void lbm_nn_destroy(lbm_nn* n) {
+    if (!n) return;
+    (void)hipStreamSynchronize(n->st);
+    delete n;
+}
+
+const char* lbm_nn_last_error(const lbm_nn* n) { return n ? n->err : g_nn_err; }
+
+}  // extern "C"

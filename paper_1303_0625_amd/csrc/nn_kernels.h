@@ -1,0 +1,599 @@
+// nn_kernels.h -- HIP kernels of the learned warm-start network (gfx950).
+//
+// Network: 4-level U-Net on a channel lattice (mask, Re) -> (rho, u_x, u_y),
+// channels (c0, c1, c2, c3), 3x3 convolutions with bias and ReLU, 2x2 mean
+// pooling, nearest 2x upsampling, concatenated skips [up, skip]; x periodic,
+// y zero-padded (walls).  Activations are NHWC in the compute type T
+// (__bf16 with FP32 accumulation on the matrix cores, or float for an
+// all-FP32 mode); weights are FP32 masters repacked into T.
+//
+// Convolution as an implicit GEMM on MFMA: M = pixels (the flattened
+// (b, y, x) index in 32-pixel blocks), N = output channels (32-channel
+// blocks), K = 9 taps x input channels in chunks of 16.  Each lane of a
+// 32x32 block owns one pixel (A) or one output channel (B) and 8 consecutive
+// channels of the chunk, so every operand load is one 16-byte (BF16) or
+// 32-byte (FP32) vector.  The input gradient is the same kernel on weights
+// flipped in (ky, kx) and transposed to [c_in][tap][c_out]; the weight
+// gradient is a second GEMM with K = pixels, split over workgroups and
+// combined in a fixed order (no atomics: results are reproducible).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kConvWaves = 4;  // waves per convolution workgroup
+constexpr int kEw = 256;       // threads per elementwise workgroup
+
+__device__ inline float to_f(float v) { return v; }
+__device__ inline float to_f(__bf16 v) { return (float)v; }
+template <typename T>
+__device__ inline T from_f(float v);
+template <>
+__device__ inline float from_f<float>(float v) { return v; }
+template <>
+__device__ inline __bf16 from_f<__bf16>(float v) { return (__bf16)v; }  // round to nearest even
+
+// Eight consecutive elements of T at p (16- or 32-byte aligned), or zeros.
+template <typename T>
+struct Frag;
+template <>
+struct Frag<__bf16> {
+    bf16x8 v;
+    __device__ inline void load(const __bf16* p) { v = *reinterpret_cast<const bf16x8*>(p); }
+    __device__ inline void zero() {
+        for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.0f;
+    }
+    __device__ inline void set(int e, __bf16 x) { v[e] = x; }
+};
+template <>
+struct Frag<float> {
+    float v[8];
+    __device__ inline void load(const float* p) {
+        const float4 a = reinterpret_cast<const float4*>(p)[0];
+        const float4 b = reinterpret_cast<const float4*>(p)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    }
+    __device__ inline void zero() {
+        for (int e = 0; e < 8; ++e) v[e] = 0.0f;
+    }
+    __device__ inline void set(int e, float x) { v[e] = x; }
+};
+
+// acc += A(32 x 16) * B(16 x 32).  Lane l holds A[l % 32][8 (l / 32) + e] and
+// B[8 (l / 32) + e][l % 32], e = 0..7.  The FP32 form issues eight K = 2
+// steps pairing element e of the two lane halves, which is the same sum.
+__device__ inline void mma(f32x16& acc, const Frag<__bf16>& a, const Frag<__bf16>& b) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b.v, acc, 0, 0, 0);
+}
+__device__ inline void mma(f32x16& acc, const Frag<float>& a, const Frag<float>& b) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[e], b.v[e], acc, 0, 0, 0);
+}
+
+// Row m of accumulator register j in lane l of a 32x32 block (column l % 32).
+__device__ inline int acc_row(int j, int l) { return 8 * (j >> 2) + 4 * (l >> 5) + (j & 3); }
+
+// ------------------------------------------------------------------ convolution
+struct ConvArgs {
+    const void* in;        // T [P][in_cs], channels [0, cin) read
+    int in_cs, cin;        // cin: multiple of 16
+    const void* w;         // T [cout_pad][9][cin]
+    const float* bias;     // [cout_pad] or null
+    void* out;             // T (or float for the network output) [P][out_cs]
+    int out_cs, out_co;    // channel stride and offset of the stored channels
+    int cout;              // channels stored: [0, cout)
+    const void* mask;      // optional T [P][mask_cs]: out *= (mask[.][mask_co + n] > 0)
+    int mask_cs, mask_co;
+    int relu;
+    int P, H, W;           // P = B * H * W pixels of this level
+};
+
+// Workgroup: kConvWaves waves; wave w takes pixels
+// [(blockIdx.x * kConvWaves + w) * 32 MB, + 32 MB) and output channels
+// [blockIdx.y * 32 NB, + 32 NB).
+template <typename T, typename OT, int MB, int NB>
+__global__ __launch_bounds__(kConvWaves * 64) void k_conv(ConvArgs a) {
+    const int l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int pbase = (blockIdx.x * kConvWaves + wave) * 32 * MB;
+    const int nbase = blockIdx.y * 32 * NB;
+    const int kg = l >> 5;
+    const T* in = static_cast<const T*>(a.in);
+    const T* w = static_cast<const T*>(a.w);
+    const int HW = a.H * a.W;
+    int pb[MB], py[MB], px[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int p = pbase + 32 * i + (l & 31);
+        const int b = p / HW;
+        const int r = p - b * HW;
+        pb[i] = p < a.P ? b : -1;
+        py[i] = r / a.W;
+        px[i] = r - py[i] * a.W;
+    }
+    f32x16 acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+    const int wrow = 9 * a.cin;
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const T* src[MB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            const int yy = py[i] + dy;
+            int xx = px[i] + dx;
+            xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+            const bool ok = pb[i] >= 0 && yy >= 0 && yy < a.H;
+            src[i] = ok ? in + ((int64_t)(pb[i] * a.H + yy) * a.W + xx) * a.in_cs + 8 * kg : nullptr;
+        }
+        const T* wsrc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) wsrc[j] = w + (int64_t)(nbase + 32 * j + (l & 31)) * wrow + tap * a.cin + 8 * kg;
+        for (int c0 = 0; c0 < a.cin; c0 += 16) {
+            Frag<T> fa[MB], fb[NB];
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                if (src[i])
+                    fa[i].load(src[i] + c0);
+                else
+                    fa[i].zero();
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) fb[j].load(wsrc[j] + c0);
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) mma(acc[i][j], fa[i], fb[j]);
+        }
+    }
+    OT* out = static_cast<OT*>(a.out);
+    const T* mask = static_cast<const T*>(a.mask);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int n = nbase + 32 * j + (l & 31);
+        if (n >= a.cout) continue;
+        const float bv = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int p = pbase + 32 * i + acc_row(q, l);
+                if (p >= a.P) continue;
+                float v = acc[i][j][q] + bv;
+                if (a.relu) v = v > 0.0f ? v : 0.0f;
+                if (mask && !(to_f(mask[(int64_t)p * a.mask_cs + a.mask_co + n]) > 0.0f)) v = 0.0f;
+                out[(int64_t)p * a.out_cs + a.out_co + n] = from_f<OT>(v);
+            }
+    }
+}
+
+// ------------------------------------------------------------------ weight gradient
+// dW[co][tap][ci] = sum over pixels p of g[p][co] x(p shifted by tap)[ci].
+// Workgroup (tile, split): co block of 32 MB, ci block of 32 NB, one tap;
+// pixels [k0, k1) of the split in chunks of 16, chunk c to wave c % 4.  The
+// four waves are combined in LDS in wave order; the partial of the split goes
+// to part[split][co][tap][ci] (real channels only).
+struct WgradArgs {
+    const void* g;   // T [P][g_cs]; channels [0, cout_pad) readable
+    int g_cs;
+    const void* x;   // T [P][x_cs]; channels [0, cin) used
+    int x_cs;
+    int cout, cin;   // real channel counts
+    int co_blocks, ci_blocks;  // in units of 32 MB / 32 NB
+    int P, H, W;
+    int chunk_per_split;       // pixels per split (multiple of 64)
+    float* part;     // [splits][cout][9][cin]
+};
+
+template <typename T, int MB, int NB>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+    __shared__ float red[3][MB * NB * 16][64];
+    const int l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int kg = l >> 5;
+    int tile = blockIdx.x;
+    const int tap = tile % 9;
+    tile /= 9;
+    const int cib = tile % a.ci_blocks;
+    const int cob = tile / a.ci_blocks;
+    const int split = blockIdx.y;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const T* g = static_cast<const T*>(a.g);
+    const T* x = static_cast<const T*>(a.x);
+    const int k0 = split * a.chunk_per_split;
+    const int k1 = min(a.P, k0 + a.chunk_per_split);
+    f32x16 acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+    int co_l[MB], ci_l[NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) co_l[i] = (cob * MB + i) * 32 + (l & 31);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) ci_l[j] = (cib * NB + j) * 32 + (l & 31);
+    for (int c = k0 + 16 * wave; c < k1; c += 64) {
+        // the lane's 8 pixels c + 8 kg + e lie in one row (W is a multiple of 8)
+        const int p0 = c + 8 * kg;
+        Frag<T> fa[MB], fb[NB];
+        if (p0 < k1) {
+            const int row = p0 / a.W;  // b * H + y
+            const int x0 = p0 - row * a.W;
+            const int b = row / a.H;
+            const int yy = row - b * a.H + dy;
+            const bool yok = yy >= 0 && yy < a.H;
+            const int64_t srow = (int64_t)(b * a.H + yy) * a.W;
+#pragma unroll
+            for (int i = 0; i < MB; ++i)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) fa[i].set(e, g[(int64_t)(p0 + e) * a.g_cs + co_l[i]]);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const bool cok = ci_l[j] < a.cin;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    int xx = x0 + e + dx;
+                    xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+                    fb[j].set(e, (yok && cok) ? x[(srow + xx) * a.x_cs + ci_l[j]] : from_f<T>(0.0f));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < MB; ++i) fa[i].zero();
+#pragma unroll
+            for (int j = 0; j < NB; ++j) fb[j].zero();
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) mma(acc[i][j], fa[i], fb[j]);
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) red[wave - 1][(i * NB + j) * 16 + q][l] = acc[i][j][q];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+    const int64_t slab = (int64_t)a.cout * 9 * a.cin;
+    float* part = a.part + (int64_t)split * slab;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int r = (i * NB + j) * 16 + q;
+                const float v = ((acc[i][j][q] + red[0][r][l]) + red[1][r][l]) + red[2][r][l];
+                const int co = (cob * MB + i) * 32 + acc_row(q, l);
+                const int ci = ci_l[j];
+                if (co < a.cout && ci < a.cin) part[((int64_t)co * 9 + tap) * a.cin + ci] = v;
+            }
+}
+
+// grad[i] = sum over splits s (in order) of part[s][i], i < n.
+__global__ __launch_bounds__(kEw) void k_sum_splits(const float* __restrict__ part, int splits, int64_t n,
+                                                    float* __restrict__ grad) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (i >= n) return;
+    float v = 0.0f;
+    for (int s = 0; s < splits; ++s) v += part[(int64_t)s * n + i];
+    grad[i] = v;
+}
+
+// Bias gradient: db[co] = sum over pixels of g[p][co].  Stage 1: block b sums
+// pixels [b R, (b + 1) R) for every channel; stage 2 sums the blocks in order.
+__global__ __launch_bounds__(kEw) void k_bias_partial(const void* __restrict__ gv, int is_bf16, int g_cs,
+                                                      int cout, int P, int rows, float* __restrict__ part) {
+    const int p0 = blockIdx.x * rows;
+    const int p1 = min(P, p0 + rows);
+    for (int co = threadIdx.x; co < cout; co += kEw) {
+        float v = 0.0f;
+        for (int p = p0; p < p1; ++p) {
+            const int64_t k = (int64_t)p * g_cs + co;
+            v += is_bf16 ? (float)static_cast<const __bf16*>(gv)[k] : static_cast<const float*>(gv)[k];
+        }
+        part[(int64_t)blockIdx.x * cout + co] = v;
+    }
+}
+
+__global__ __launch_bounds__(kEw) void k_bias_final(const float* __restrict__ part, int nblk, int cout,
+                                                    float* __restrict__ db) {
+    const int co = blockIdx.x * kEw + threadIdx.x;
+    if (co >= cout) return;
+    float v = 0.0f;
+    for (int b = 0; b < nblk; ++b) v += part[(int64_t)b * cout + co];
+    db[co] = v;
+}
+
+// ------------------------------------------------------------------ pooling, upsampling
+// out[b][y][x][c] = mean of in[b][2y + i][2x + j][c] (level l -> l + 1).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_pool(const T* __restrict__ in, int in_cs, int in_co, int C,
+                                              T* __restrict__ out, int Ho, int Wo, int B) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    const int64_t n = (int64_t)B * Ho * Wo * C;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    const int64_t q = i / C;
+    const int xo = (int)(q % Wo);
+    const int64_t by = q / Wo;  // b * Ho + yo
+    const int Wi = 2 * Wo;
+    const int64_t r0 = (2 * by) * Wi + 2 * xo;  // (b * Hi + 2 yo) * Wi + 2 xo
+    float v = (to_f(in[r0 * in_cs + in_co + c]) + to_f(in[(r0 + 1) * in_cs + in_co + c])) +
+              (to_f(in[(r0 + Wi) * in_cs + in_co + c]) + to_f(in[(r0 + Wi + 1) * in_cs + in_co + c]));
+    out[q * C + c] = from_f<T>(0.25f * v);
+}
+
+// out[b][y][x][out_co + c] = in[b][y / 2][x / 2][c] (level l + 1 -> l).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_upsample(const T* __restrict__ in, int C, T* __restrict__ out,
+                                                  int out_cs, int out_co, int Ho, int Wo, int B) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    const int64_t n = (int64_t)B * Ho * Wo * C;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    const int64_t q = i / C;
+    const int xo = (int)(q % Wo);
+    const int64_t by = q / Wo;
+    const int64_t src = (by >> 1) * (Wo >> 1) + (xo >> 1);
+    out[q * out_cs + out_co + c] = in[src * C + c];
+}
+
+// Adjoint of the upsampling, then the ReLU mask of the lower-level activation:
+// out[q][c] = (sum over the 2x2 children of g[child][g_co + c]) * (act[q][c] > 0).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_upsample_back(const T* __restrict__ g, int g_cs, int g_co, int C,
+                                                       const T* __restrict__ act, T* __restrict__ out, int Hl,
+                                                       int Wl, int B) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    const int64_t n = (int64_t)B * Hl * Wl * C;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    const int64_t q = i / C;
+    const int xl = (int)(q % Wl);
+    const int64_t by = q / Wl;
+    const int Wh = 2 * Wl;
+    const int64_t r0 = (2 * by) * Wh + 2 * xl;
+    float v = (to_f(g[r0 * g_cs + g_co + c]) + to_f(g[(r0 + 1) * g_cs + g_co + c])) +
+              (to_f(g[(r0 + Wh) * g_cs + g_co + c]) + to_f(g[(r0 + Wh + 1) * g_cs + g_co + c]));
+    out[q * C + c] = from_f<T>(to_f(act[q * C + c]) > 0.0f ? v : 0.0f);
+}
+
+// Encoder skip: out[p][c] = (g_low[parent][c] / 4 + g_cat[p][skip_co + c]) *
+// (act[p][act_co + c] > 0), act the skip activation (inside the concat buffer).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_pool_back_skip(const T* __restrict__ g_low, const T* __restrict__ g_cat,
+                                                        int cat_cs, int skip_co, const T* __restrict__ act,
+                                                        int C, T* __restrict__ out, int H, int W, int B) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    const int64_t n = (int64_t)B * H * W * C;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    const int x = (int)(p % W);
+    const int64_t by = p / W;
+    const int64_t parent = (by >> 1) * (W >> 1) + (x >> 1);
+    const float v = 0.25f * to_f(g_low[parent * C + c]) + to_f(g_cat[p * cat_cs + skip_co + c]);
+    out[p * C + c] = from_f<T>(to_f(act[p * cat_cs + skip_co + c]) > 0.0f ? v : 0.0f);
+}
+
+// ------------------------------------------------------------------ data
+// Network input from a solid mask and Re: channel 0 = solid, 1 = Re / 100,
+// channels 2..15 zero.  idx (optional) selects samples of a larger set.
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_pack_input(const uint8_t* __restrict__ solid, const double* __restrict__ re,
+                                                    const int* __restrict__ idx, int HW, int B,
+                                                    T* __restrict__ x0) {
+    const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (p >= (int64_t)B * HW) return;
+    const int b = (int)(p / HW);
+    const int s = idx ? idx[b] : b;
+    const int64_t src = (int64_t)s * HW + (p - (int64_t)b * HW);
+    T* o = x0 + p * 16;
+    o[0] = from_f<T>(solid[src] ? 1.0f : 0.0f);
+    o[1] = from_f<T>((float)(re[s] / 100.0));
+    for (int c = 2; c < 16; ++c) o[c] = from_f<T>(0.0f);
+}
+
+// Raw input [P][2] (float) into the padded input tensor.
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_pack_raw(const float* __restrict__ xin, int64_t P, T* __restrict__ x0) {
+    const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (p >= P) return;
+    T* o = x0 + p * 16;
+    o[0] = from_f<T>(xin[2 * p]);
+    o[1] = from_f<T>(xin[2 * p + 1]);
+    for (int c = 2; c < 16; ++c) o[c] = from_f<T>(0.0f);
+}
+
+// Centre-line speed of the unobstructed channel of sample s, g H^2 / (8 nu),
+// nu = (tau - 1/2) / 3.
+__device__ inline double u_centre(double gx, double tau, int ny) {
+    const double nu = (tau - 0.5) / 3.0;
+    return gx * (double)ny * (double)ny / (8.0 * nu);
+}
+
+// Normalised target and fluid flag of the selected samples:
+// t = ((rho - 1) / (U_c s_rho), u_x / U_c, u_y / U_c).
+__global__ __launch_bounds__(kEw) void k_pack_target(const uint8_t* __restrict__ solid, const float* __restrict__ rho,
+                                                     const float* __restrict__ ux, const float* __restrict__ uy,
+                                                     const double* __restrict__ gx, const double* __restrict__ tau,
+                                                     const int* __restrict__ idx, int H, int W, int B,
+                                                     double rho_scale, float* __restrict__ tgt,
+                                                     uint8_t* __restrict__ fluid) {
+    const int HW = H * W;
+    const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (p >= (int64_t)B * HW) return;
+    const int b = (int)(p / HW);
+    const int s = idx ? idx[b] : b;
+    const int64_t src = (int64_t)s * HW + (p - (int64_t)b * HW);
+    const double uc = u_centre(gx[s], tau[s], H);
+    const bool fl = solid[src] == 0;
+    fluid[p] = fl ? 1 : 0;
+    tgt[3 * p + 0] = fl ? (float)(((double)rho[src] - 1.0) / (uc * rho_scale)) : 0.0f;
+    tgt[3 * p + 1] = fl ? (float)((double)ux[src] / uc) : 0.0f;
+    tgt[3 * p + 2] = fl ? (float)((double)uy[src] / uc) : 0.0f;
+}
+
+// Fields from the network output (inference): fluid nodes get
+// rho = 1 + y0 U_c s_rho, u = (y1, y2) U_c; solid nodes 0.
+__global__ __launch_bounds__(kEw) void k_unpack_fields(const float* __restrict__ y, const uint8_t* __restrict__ solid,
+                                                       const double* __restrict__ gx, const double* __restrict__ tau,
+                                                       int H, int W, int B, double rho_scale, float* __restrict__ rho,
+                                                       float* __restrict__ ux, float* __restrict__ uy) {
+    const int HW = H * W;
+    const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (p >= (int64_t)B * HW) return;
+    const int b = (int)(p / HW);
+    const double uc = u_centre(gx[b], tau[b], H);
+    const bool fl = solid[p] == 0;
+    rho[p] = fl ? (float)(1.0 + (double)y[3 * p] * uc * rho_scale) : 0.0f;
+    ux[p] = fl ? (float)((double)y[3 * p + 1] * uc) : 0.0f;
+    uy[p] = fl ? (float)((double)y[3 * p + 2] * uc) : 0.0f;
+}
+
+// ------------------------------------------------------------------ loss
+// Masked mean squared error over fluid nodes and 3 channels.  Stage 1: block
+// partial sums {sum (y - t)^2, fluid count}; stage 2 (one thread) sums the
+// blocks in order, then every node writes its gradient 2 (y - t) / (3 n_f)
+// into the padded head-gradient tensor (channels 3..31 zero).
+__global__ __launch_bounds__(kEw) void k_loss_partial(const float* __restrict__ y, const float* __restrict__ t,
+                                                      const uint8_t* __restrict__ fluid, int64_t P,
+                                                      double* __restrict__ part) {
+    __shared__ double s1[kEw], s2[kEw];
+    const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    double a = 0.0, c = 0.0;
+    if (p < P && fluid[p]) {
+        for (int k = 0; k < 3; ++k) {
+            const double d = (double)y[3 * p + k] - (double)t[3 * p + k];
+            a += d * d;
+        }
+        c = 1.0;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = kEw / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            s1[threadIdx.x] += s1[threadIdx.x + off];
+            s2[threadIdx.x] += s2[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+__global__ void k_loss_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a = 0.0, c = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        a += part[2 * b];
+        c += part[2 * b + 1];
+    }
+    out[0] = c > 0.0 ? a / (3.0 * c) : 0.0;
+    out[1] = c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_loss_grad(const float* __restrict__ y, const float* __restrict__ t,
+                                                   const uint8_t* __restrict__ fluid, int64_t P,
+                                                   const double* __restrict__ lossv, T* __restrict__ g_head) {
+    const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (p >= P) return;
+    const double nf = lossv[1];
+    const double sc = nf > 0.0 ? 2.0 / (3.0 * nf) : 0.0;
+    T* o = g_head + p * 32;
+    for (int k = 0; k < 3; ++k)
+        o[k] = from_f<T>(fluid[p] ? (float)(sc * ((double)y[3 * p + k] - (double)t[3 * p + k])) : 0.0f);
+    for (int k = 3; k < 32; ++k) o[k] = from_f<T>(0.0f);
+}
+
+// Raw output gradient [P][3] (float) into the padded head-gradient tensor.
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_pack_head_grad(const float* __restrict__ gy, int64_t P, T* __restrict__ g_head) {
+    const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (p >= P) return;
+    T* o = g_head + p * 32;
+    for (int k = 0; k < 3; ++k) o[k] = from_f<T>(gy[3 * p + k]);
+    for (int k = 3; k < 32; ++k) o[k] = from_f<T>(0.0f);
+}
+
+// ------------------------------------------------------------------ parameters
+struct LayerDev {
+    int64_t off;        // first weight in the master vector (bias follows the weights)
+    int cin, cout;      // real channel counts
+    int cin_pad, cout_pad;
+    int64_t wf_off;     // forward weights T [cout_pad][9][cin_pad]
+    int64_t wt_off;     // input-gradient weights T [cin_dg][9][cout_pad], flipped taps
+    int cin_dg;         // rows of the input-gradient weights (cin rounded up to 32)
+    int64_t b_off;      // padded bias [cout_pad]
+};
+
+// Master FP32 parameters -> forward weights, flipped/transposed weights and
+// padded biases of layer L (one thread per padded element of the largest).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_pack_weights(const float* __restrict__ master, LayerDev L,
+                                                      T* __restrict__ wf, T* __restrict__ wt,
+                                                      float* __restrict__ bias) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    const int64_t nf = (int64_t)L.cout_pad * 9 * L.cin_pad;
+    if (i < nf) {
+        const int ci = (int)(i % L.cin_pad);
+        const int64_t r = i / L.cin_pad;
+        const int tap = (int)(r % 9);
+        const int co = (int)(r / 9);
+        const float v = (co < L.cout && ci < L.cin) ? master[L.off + ((int64_t)co * 9 + tap) * L.cin + ci] : 0.0f;
+        wf[L.wf_off + i] = from_f<T>(v);
+    }
+    const int64_t nt = (int64_t)L.cin_dg * 9 * L.cout_pad;
+    if (i < nt) {
+        const int co = (int)(i % L.cout_pad);
+        const int64_t r = i / L.cout_pad;
+        const int tapf = (int)(r % 9);
+        const int ci = (int)(r / 9);
+        const int tap = 8 - tapf;  // (ky, kx) -> (2 - ky, 2 - kx)
+        const float v = (co < L.cout && ci < L.cin) ? master[L.off + ((int64_t)co * 9 + tap) * L.cin + ci] : 0.0f;
+        wt[L.wt_off + i] = from_f<T>(v);
+    }
+    if (i < L.cout_pad) bias[L.b_off + i] = i < L.cout ? master[L.off + (int64_t)L.cout * 9 * L.cin + i] : 0.0f;
+}
+
+// Adam (Kingma and Ba) on the FP32 master vector; t counts from 1.
+__global__ __launch_bounds__(kEw) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(kEw) void k_zero_f32(float* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+}  // namespace nn

@@ -34,6 +34,11 @@ class lbm_grid(ctypes.Structure):
                 ("wall_vy", ctypes.c_double)]
 
 
+class lbm_nn_config(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_int32), ("w", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("ch", ctypes.c_int32 * 4), ("rho_scale", ctypes.c_double)]
+
+
 class lbm_solid(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int32), ("moves", ctypes.c_int32), ("cx", ctypes.c_double),
                 ("cy", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
@@ -94,6 +99,22 @@ _SIG = {
     "lbm_batch_time": (_I64, [_VP]),
     "lbm_batch_destroy": (None, [_VP]),
     "lbm_batch_last_error": (ctypes.c_char_p, [_VP]),
+    "lbm_nn_workspace_bytes": (_I32, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm_nn_create": (_I32, [_VP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "lbm_nn_param_count": (_I64, [_VP]),
+    "lbm_nn_set_params": (_I32, [_VP, _VP]),
+    "lbm_nn_get_params": (_I32, [_VP, _VP]),
+    "lbm_nn_get_grads": (_I32, [_VP, _VP]),
+    "lbm_nn_forward": (_I32, [_VP, _VP, _I32, _VP]),
+    "lbm_nn_backward": (_I32, [_VP, _VP]),
+    "lbm_nn_adam": (_I32, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "lbm_nn_train_step": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double)]),
+    "lbm_nn_eval": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32,
+                           ctypes.POINTER(ctypes.c_double)]),
+    "lbm_nn_infer": (_I32, [_VP, _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP]),
+    "lbm_nn_destroy": (None, [_VP]),
+    "lbm_nn_last_error": (ctypes.c_char_p, [_VP]),
 }
 
 
@@ -316,6 +337,81 @@ def lbm_batch_destroy(b) -> None:
 
 def lbm_batch_last_error(b=None) -> str:
     m = load_library().lbm_batch_last_error(b)
+    return m.decode() if m else ""
+
+
+# ---- warm-start network ----------------------------------------------------
+def _ncheck(status, n=None):
+    if status != LBM_OK:
+        msg = load_library().lbm_nn_last_error(n)
+        raise LBMError(status, msg.decode() if msg else "")
+
+
+def lbm_nn_workspace_bytes(cfg: lbm_nn_config) -> int:
+    out = ctypes.c_size_t(0)
+    _ncheck(load_library().lbm_nn_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def lbm_nn_create(cfg: lbm_nn_config, d_workspace: int, nbytes: int, stream: int):
+    n = _VP()
+    _ncheck(load_library().lbm_nn_create(ctypes.byref(cfg), d_workspace, nbytes, stream, ctypes.byref(n)))
+    return n
+
+
+def lbm_nn_param_count(n) -> int:
+    return load_library().lbm_nn_param_count(n)
+
+
+def lbm_nn_set_params(n, d_params) -> None:
+    _ncheck(load_library().lbm_nn_set_params(n, d_params), n)
+
+
+def lbm_nn_get_params(n, d_out) -> None:
+    _ncheck(load_library().lbm_nn_get_params(n, d_out), n)
+
+
+def lbm_nn_get_grads(n, d_out) -> None:
+    _ncheck(load_library().lbm_nn_get_grads(n, d_out), n)
+
+
+def lbm_nn_forward(n, d_x, batch: int, d_y) -> None:
+    _ncheck(load_library().lbm_nn_forward(n, d_x, batch, d_y), n)
+
+
+def lbm_nn_backward(n, d_gy) -> None:
+    _ncheck(load_library().lbm_nn_backward(n, d_gy), n)
+
+
+def lbm_nn_adam(n, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+    _ncheck(load_library().lbm_nn_adam(n, lr, beta1, beta2, eps), n)
+
+
+def lbm_nn_train_step(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch: int, lr: float,
+                      want_loss: bool = False):
+    loss = ctypes.c_double(0.0)
+    _ncheck(load_library().lbm_nn_train_step(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch, lr,
+                                             ctypes.byref(loss) if want_loss else None), n)
+    return loss.value if want_loss else None
+
+
+def lbm_nn_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch: int) -> float:
+    loss = ctypes.c_double(0.0)
+    _ncheck(load_library().lbm_nn_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch,
+                                       ctypes.byref(loss)), n)
+    return loss.value
+
+
+def lbm_nn_infer(n, d_solid, d_re, d_gx, d_tau, batch: int, d_rho, d_ux, d_uy) -> None:
+    _ncheck(load_library().lbm_nn_infer(n, d_solid, d_re, d_gx, d_tau, batch, d_rho, d_ux, d_uy), n)
+
+
+def lbm_nn_destroy(n) -> None:
+    load_library().lbm_nn_destroy(n)
+
+
+def lbm_nn_last_error(n=None) -> str:
+    m = load_library().lbm_nn_last_error(n)
     return m.decode() if m else ""
 
 
@@ -552,3 +648,91 @@ class LatticeBatch:
         dt = LBM_F64 if rho.dtype == self.torch.float64 else LBM_F32
         rho, ux, uy = (a.contiguous() for a in (rho, ux, uy))
         lbm_batch_init_fields(self.b, case_id, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), dt)
+
+
+class WarmStartNet:
+    """The warm-start U-Net on the current device.  Tensors passed in are torch
+    CUDA tensors (contiguous, of the dtypes the header names)."""
+
+    def __init__(self, h, w, max_batch, dtype="bf16", ch=(32, 64, 128, 256), rho_scale=1.0, device="cuda",
+                 stream=None):
+        import torch
+
+        self.torch = torch
+        self.h, self.w, self.max_batch = int(h), int(w), int(max_batch)
+        self.cfg = lbm_nn_config()
+        self.cfg.h, self.cfg.w, self.cfg.max_batch = self.h, self.w, self.max_batch
+        self.cfg.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        for k in range(4):
+            self.cfg.ch[k] = int(ch[k])
+        self.cfg.rho_scale = float(rho_scale)
+        nbytes = lbm_nn_workspace_bytes(self.cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._destroy = load_library().lbm_nn_destroy
+        self.n = lbm_nn_create(self.cfg, self._ws_ptr, nbytes, self.stream.cuda_stream)
+        self.n_params = lbm_nn_param_count(self.n)
+
+    def __del__(self):
+        n = getattr(self, "n", None)
+        if n:
+            self._destroy(n)
+            self.n = None
+
+    def _f32(self, t):
+        return t.to(device=self.workspace.device, dtype=self.torch.float32).contiguous()
+
+    def set_params(self, params) -> None:
+        p = self._f32(self.torch.as_tensor(params))
+        assert p.numel() == self.n_params
+        lbm_nn_set_params(self.n, p.data_ptr())
+        self.stream.synchronize()
+
+    def params(self):
+        out = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.workspace.device)
+        lbm_nn_get_params(self.n, out.data_ptr())
+        return out
+
+    def grads(self):
+        out = self.torch.empty(self.n_params, dtype=self.torch.float32, device=self.workspace.device)
+        lbm_nn_get_grads(self.n, out.data_ptr())
+        return out
+
+    def forward(self, x):
+        """x [B][h][w][2] -> y [B][h][w][3] (float32)."""
+        x = self._f32(x)
+        y = self.torch.empty(x.shape[:3] + (3,), dtype=self.torch.float32, device=x.device)
+        lbm_nn_forward(self.n, x.data_ptr(), x.shape[0], y.data_ptr())
+        self._keep = x
+        return y
+
+    def backward(self, gy) -> None:
+        gy = self._f32(gy)
+        lbm_nn_backward(self.n, gy.data_ptr())
+        self._keep_g = gy
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+        lbm_nn_adam(self.n, lr, beta1, beta2, eps)
+
+    def train_step(self, data, idx, lr, want_loss=False):
+        """data: dict of device tensors solid, rho, ux, uy, re, gx, tau; idx int32 [B]."""
+        d = data
+        return lbm_nn_train_step(self.n, d["solid"].data_ptr(), d["rho"].data_ptr(), d["ux"].data_ptr(),
+                                 d["uy"].data_ptr(), d["re"].data_ptr(), d["gx"].data_ptr(), d["tau"].data_ptr(),
+                                 idx.data_ptr(), idx.numel(), lr, want_loss)
+
+    def eval(self, data, idx) -> float:
+        d = data
+        return lbm_nn_eval(self.n, d["solid"].data_ptr(), d["rho"].data_ptr(), d["ux"].data_ptr(),
+                           d["uy"].data_ptr(), d["re"].data_ptr(), d["gx"].data_ptr(), d["tau"].data_ptr(),
+                           idx.data_ptr(), idx.numel())
+
+    def infer(self, solid, re, gx, tau):
+        """solid u8 [B][h][w], re/gx/tau float64 [B] (device) -> rho, ux, uy [B][h][w] float32."""
+        B = solid.shape[0]
+        dev = self.workspace.device
+        outs = [self.torch.empty((B, self.h, self.w), dtype=self.torch.float32, device=dev) for _ in range(3)]
+        lbm_nn_infer(self.n, solid.data_ptr(), re.data_ptr(), gx.data_ptr(), tau.data_ptr(), B,
+                     *(o.data_ptr() for o in outs))
+        return outs

@@ -159,3 +159,29 @@ def test_param_count_of_the_warm_start_network():
                                             (128, 256), (256, 256), (384, 128), (128, 128), (192, 64),
                                             (64, 64), (96, 32), (32, 32), (32, 3)])
     assert n == expect == 1_947_427
+
+
+def test_bf16_rounding():
+    # 7 stored fraction bits: ulp(1) = 2^-7; halfway cases go to the even neighbour
+    cases = {1.0: 1.0, 1 + 2 ** -8: 1.0, 1 + 3 * 2 ** -8: 1 + 2 ** -6, 1 + 2 ** -8 + 2 ** -20: 1 + 2 ** -7,
+             -3.0: -3.0, 0.0: 0.0, 2.0 ** -130: 2.0 ** -130}
+    for x, want in cases.items():
+        assert co.bf16(np.array([x]))[0] == want, x
+    torch = pytest.importorskip("torch")
+    v = RNG.normal(size=10000) * 10.0 ** RNG.integers(-8, 8, size=10000)
+    ref = torch.from_numpy(v.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(co.bf16(v), ref)
+
+
+def test_storage_rounding_hook():
+    """q = identity reproduces the plain network; q = bf16 keeps every stored
+    tensor on the bfloat16 grid and moves the output by ~1e-2 at most."""
+    ch, p = _small_net()
+    x = RNG.normal(size=(1, 8, 16, 2))
+    y0, _ = co.forward(p, x, ch)
+    y1, t1 = co.forward(p, x, ch, q=lambda a: a)
+    assert np.array_equal(y0, y1)
+    yb, tb = co.forward(p, x, ch, q=co.bf16)
+    for k, inp, _ in tb:
+        assert np.array_equal(inp, co.bf16(inp)), k
+    assert 0 < np.abs(yb - y0).max() <= 5e-2 * np.abs(y0).max()

@@ -1,0 +1,204 @@
+"""Warm-start network on the GPU (lbm_nn_*) against the FP64 network oracle.
+
+Real channel widths (32, 64, 128, 256) on a 32 x 64 lattice (levels down to
+4 x 8, pixel counts that leave ragged workgroups), batch 2 of a maximum 3.
+Bars: FP32 mode within 1e-5 and BF16 mode within 2e-2 of the oracle, per
+tensor, relative to its largest magnitude (forward output, the gradient of
+every layer's weights and biases); Adam against the oracle's Adam; training
+reduces the loss; repeated calls are bit-identical.  In BF16 mode the oracle
+rounds every stored tensor to bfloat16 where the kernels store one, so both
+sides take the ReLU decisions on the same values (its arithmetic stays FP64).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cnn_oracle as co
+
+pytestmark = pytest.mark.gpu
+
+H, W, B, MAXB = 32, 64, 2, 3
+CH = (32, 64, 128, 256)
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lbm_mod(torch_mod):
+    from paper_1303_0625_amd import lbm
+
+    lbm.load_library()
+    return lbm
+
+
+def he_params(seed):
+    """He-normal weights (fan-in 9 c_in), small random biases."""
+    rng = np.random.default_rng(seed)
+    layers = []
+    for ci, o, _ in co.layer_shapes(CH):
+        Wt = rng.normal(size=(o, 3, 3, ci)) * np.sqrt(2.0 / (9 * ci))
+        b = rng.normal(size=o) * 0.05
+        layers.append((Wt, b))
+    return co.pack(layers)
+
+
+def inputs(seed):
+    rng = np.random.default_rng(seed)
+    x = np.zeros((B, H, W, 2))
+    yy, xx = np.mgrid[0:H, 0:W]
+    for b in range(B):
+        cx, cy, r = rng.uniform(10, W - 10), rng.uniform(8, H - 8), rng.uniform(3, 7)
+        x[b, :, :, 0] = ((xx - cx) ** 2 + (yy - cy) ** 2 <= r * r)
+        x[b, :, :, 1] = rng.uniform(0.01, 1.0)
+    return x
+
+
+def layer_slices():
+    out, k = [], 0
+    for ci, o, _ in co.layer_shapes(CH):
+        nw = o * 9 * ci
+        out.append((slice(k, k + nw), slice(k + nw, k + nw + o)))
+        k += nw + o
+    return out
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 2e-2)])
+def test_forward_backward_parity(torch_mod, lbm_mod, dtype, tol):
+    torch = torch_mod
+    p = he_params(7)
+    x = inputs(8)
+    gy = np.random.default_rng(9).normal(size=(B, H, W, 3))
+    _say(f"network {dtype}: oracle forward/backward")
+    q = co.bf16 if dtype == "bf16" else (lambda a: a)
+    y_ref, tape = co.forward(p, x, CH, q=q)
+    g_ref = co.backward(p, tape, gy, CH, q=q)
+    _say(f"network {dtype}: GPU")
+    net = lbm_mod.WarmStartNet(H, W, MAXB, dtype=dtype, ch=CH)
+    assert net.n_params == co.param_count(CH)
+    net.set_params(torch.from_numpy(p))
+    y = net.forward(torch.from_numpy(x)).cpu().numpy()
+    e_y = rel_max(y, y_ref)
+    net.backward(torch.from_numpy(gy))
+    g = net.grads().cpu().numpy()
+    worst = (0.0, None)
+    for k, (sw, sb) in enumerate(layer_slices()):
+        for name, s in (("w", sw), ("b", sb)):
+            e = rel_max(g[s], g_ref[s])
+            if e > worst[0]:
+                worst = (e, (k, name))
+    _say(f"{dtype}: output rel err {e_y:.3e}; worst gradient rel err {worst[0]:.3e} at layer {worst[1]}")
+    assert e_y <= tol
+    assert worst[0] <= tol
+    # bit-identical on a repeat
+    y2 = net.forward(torch.from_numpy(x)).cpu().numpy()
+    net.backward(torch.from_numpy(gy))
+    assert np.array_equal(y, y2)
+    assert np.array_equal(g, net.grads().cpu().numpy())
+
+
+def test_adam_matches_oracle(torch_mod, lbm_mod):
+    torch = torch_mod
+    p = he_params(11)
+    x = inputs(12)
+    gy = np.random.default_rng(13).normal(size=(B, H, W, 3))
+    net = lbm_mod.WarmStartNet(H, W, MAXB, dtype="f32", ch=CH)
+    net.set_params(torch.from_numpy(p))
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    q = p.copy()
+    for t in (1, 2, 3):
+        net.forward(torch.from_numpy(x))
+        net.backward(torch.from_numpy(gy))
+        g = net.grads().cpu().numpy().astype(np.float64)
+        q, m, v = co.adam(np.float32(q).astype(np.float64), g, m, v, t, 1e-3)
+        net.adam(1e-3)
+        got = net.params().cpu().numpy()
+        # FP32 master: one rounding of the update per step
+        assert np.abs(got - q).max() <= 1e-6 * max(np.abs(q).max(), 1.0), t
+
+
+def synthetic_set(torch, n, seed):
+    """Channel-like samples: a disc in a walled channel, a plane-Poiseuille
+    flow with a smooth wake (a fixed analytic map of (mask, Re)), so the
+    network has something learnable."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    solid = np.zeros((n, H, W), np.uint8)
+    rho = np.zeros((n, H, W), np.float32)
+    ux = np.zeros((n, H, W), np.float32)
+    uy = np.zeros((n, H, W), np.float32)
+    re = rng.uniform(1, 100, size=n)
+    tau = rng.uniform(0.55, 1.2, size=n)
+    gx = rng.uniform(1e-6, 1e-5, size=n)
+    for k in range(n):
+        cx, cy, r = rng.uniform(12, W - 12), rng.uniform(10, H - 10), rng.uniform(3, 6)
+        d2 = (xx - cx) ** 2 + (yy - cy) ** 2
+        solid[k] = d2 <= r * r
+        uc = co.u_scale(gx[k], tau[k], H)
+        prof = 4 * (yy + 0.5) * (H - 0.5 - yy) / (H * H)
+        wake = np.exp(-d2 / (4 * r * r) * (1 + re[k] / 100))
+        ux[k] = np.where(solid[k], 0, uc * prof * (1 - wake))
+        uy[k] = np.where(solid[k], 0, uc * 0.1 * (yy - cy) / r * wake)
+        rho[k] = np.where(solid[k], 0, 1 + 0.01 * uc * (xx - cx) / W)
+    dev = "cuda"
+    return {"solid": torch.from_numpy(solid).to(dev), "rho": torch.from_numpy(rho).to(dev),
+            "ux": torch.from_numpy(ux).to(dev), "uy": torch.from_numpy(uy).to(dev),
+            "re": torch.from_numpy(re).to(dev), "gx": torch.from_numpy(gx).to(dev),
+            "tau": torch.from_numpy(tau).to(dev)}
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_training_reduces_loss_and_infer_matches_oracle(torch_mod, lbm_mod, dtype):
+    torch = torch_mod
+    data = synthetic_set(torch, 12, 21)
+    net = lbm_mod.WarmStartNet(H, W, MAXB, dtype=dtype, ch=CH, rho_scale=0.05)
+    net.set_params(torch.from_numpy(he_params(22)))
+    all_idx = torch.arange(MAXB, dtype=torch.int32, device="cuda")
+    loss0 = net.eval(data, all_idx)
+    rng = np.random.default_rng(23)
+    for it in range(150):
+        idx = torch.from_numpy(rng.choice(12, size=MAXB, replace=False).astype(np.int32)).to("cuda")
+        net.train_step(data, idx, 1e-3)
+    loss1 = net.eval(data, all_idx)
+    _say(f"{dtype}: loss {loss0:.4e} -> {loss1:.4e} after 150 steps")
+    assert loss1 < 0.2 * loss0
+    # the loss the library reports equals the oracle's on its own output
+    p = net.params().cpu().numpy().astype(np.float64)
+    solid = data["solid"][:MAXB].cpu().numpy()
+    x = co.make_input(solid, data["re"][:MAXB].cpu().numpy())
+    uc = co.u_scale(data["gx"][:MAXB].cpu().numpy(), data["tau"][:MAXB].cpu().numpy(), H)
+    t = co.make_target(data["rho"][:MAXB].cpu().numpy(), data["ux"][:MAXB].cpu().numpy(),
+                       data["uy"][:MAXB].cpu().numpy(), uc, 0.05)
+    y_ref, _ = co.forward(p, x, CH, q=co.bf16 if dtype == "bf16" else (lambda a: a))
+    l_ref = co.masked_mse(y_ref, t, solid == 0)[0]
+    tol = 1e-5 if dtype == "f32" else 2e-2
+    # an output error dy moves the loss by at most ~2 sqrt(loss) |dy|
+    ymax = np.abs(y_ref).max()
+    assert abs(loss1 - l_ref) <= 2.0 * np.sqrt(l_ref) * tol * ymax + tol * l_ref
+    rho, ux, uy = net.infer(data["solid"][:MAXB].contiguous(), data["re"][:MAXB].contiguous(),
+                            data["gx"][:MAXB].contiguous(), data["tau"][:MAXB].contiguous())
+    r_ref, x_ref, v_ref = co.fields_from_output(y_ref, solid, uc, 0.05)
+    assert rel_max(ux.cpu().numpy(), x_ref) <= tol
+    assert rel_max(uy.cpu().numpy(), v_ref) <= tol
+    fl = solid == 0
+    # rho is written in FP32 next to 1: one unit in the last place on top
+    dr = np.abs(rho.cpu().numpy()[fl] - r_ref[fl]).max()
+    assert dr <= tol * np.abs(r_ref[fl] - 1.0).max() + 1.2e-7
+    assert (rho.cpu().numpy()[~fl] == 0).all()
