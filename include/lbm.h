@@ -155,6 +155,15 @@ lbm_status lbm_fields(lbm_ctx* ctx, void* d_rho, void* d_ux, void* d_uy, int32_t
 lbm_status lbm_init_fields(lbm_ctx* ctx, const void* d_rho, const void* d_ux, const void* d_uy,
                            int32_t in_dtype);
 
+/* Replace the state by the exact steady plane-Poiseuille flow of the
+ * unobstructed channel at every fluid node: f = f_eq(rho0, u_P(y) - g/2),
+ * collided once, with u_P(y) = g_x/(2 nu) (Y^2 - (y - y_c)^2) + s, Y = ny/2,
+ * y_c = (ny - 1)/2, s = g_x (4 (2 tau - 1)^2 - 3) / (4 (2 tau - 1)),
+ * nu = (tau - 1/2)/3 (BGK with Guo forcing between half-way walls; Eq. 2-3).
+ * A non-learned warm start.  Needs walls_y = 1 (LBM_ESTATE otherwise).
+ * Asynchronous. */
+lbm_status lbm_init_poiseuille(lbm_ctx* ctx);
+
 /* Post-collision populations f~_i(x, t) of the current state as absolute
  * values in double, [9][ny][nx] device memory; 0 at solid nodes.  Asynchronous. */
 lbm_status lbm_populations(lbm_ctx* ctx, double* d_out);
@@ -279,13 +288,18 @@ lbm_status lbm_batch_force(lbm_batch* b, int32_t case_id, int32_t solid_id, int3
 
 /* Density and Guo velocity of case case_id (at its retirement step if it has
  * retired) into device buffers of nx*ny elements (LBM_F64 or LBM_F32); 0 at
- * solid nodes.  Synchronises. */
+ * solid nodes.  d_owner (optional) receives the owner map as uint8.
+ * Synchronises. */
 lbm_status lbm_batch_fields(lbm_batch* b, int32_t case_id, void* d_rho, void* d_ux, void* d_uy,
-                            int32_t out_dtype);
+                            int32_t out_dtype, uint8_t* d_owner);
 
 /* Warm start of case case_id, as lbm_init_fields.  Synchronises. */
 lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t case_id, const void* d_rho, const void* d_ux,
                                  const void* d_uy, int32_t in_dtype);
+
+/* Warm start of case case_id by the exact plane-Poiseuille flow, as
+ * lbm_init_poiseuille.  Synchronises. */
+lbm_status lbm_batch_init_poiseuille(lbm_batch* b, int32_t case_id);
 
 /* Completed steps of the batch (cases advanced together). */
 int64_t lbm_batch_time(const lbm_batch* b);

@@ -315,6 +315,22 @@ void batch_init_case(lbm_batch* b, int c, hipStream_t st, const void* rho, const
                                                           (const float*)ux, (const float*)uy);
 }
 
+template <typename T>
+void batch_poiseuille_case(lbm_batch* b, int c, hipStream_t st) {
+    using C = typename Sto<T>::C;
+    const CaseDev& d = b->cd[c];
+    const int64_t nb = ((int64_t)d.sa.ny * d.sa.rowlen + kBlock - 1) / kBlock;
+    CollideParams<C> cp;
+    cp.rho0 = (C)d.cp64.rho0;
+    cp.omega = (C)d.cp64.omega;
+    cp.gx = (C)d.cp64.gx;
+    cp.gy = (C)d.cp64.gy;
+    cp.pref = (C)d.cp64.pref;
+    k_init_poiseuille<T><<<(unsigned)nb, kBlock, 0, st>>>(bws<T>(b, b->o_f) + d.f_off[b->t & 1],
+                                                         bws<uint8_t>(b, b->o_own) + d.own_off, d.sa, cp,
+                                                         b->grids[c].gx, b->taus[c]);
+}
+
 void batch_init_dispatch(lbm_batch* b, int c, hipStream_t st, const void* rho, const void* ux,
                          const void* uy, int in_dtype) {
     switch (b->dtype) {
@@ -677,7 +693,7 @@ lbm_status lbm_batch_force(lbm_batch* b, int32_t case_id, int32_t solid_id, int3
 }
 
 lbm_status lbm_batch_fields(lbm_batch* b, int32_t case_id, void* d_rho, void* d_ux, void* d_uy,
-                            int32_t out_dtype) {
+                            int32_t out_dtype, uint8_t* d_owner) {
     if (!b || case_id < 0 || case_id >= b->n) return LBM_EINVAL;
     if (out_dtype != LBM_F64 && out_dtype != LBM_F32) {
         set_err(b->err, "fields are written as LBM_F64 or LBM_F32");
@@ -699,11 +715,11 @@ lbm_status lbm_batch_fields(lbm_batch* b, int32_t case_id, void* d_rho, void* d_
     if (out_dtype == LBM_F64)                                                                             \
         k_fields<T, double><<<nb, kBlock, 0, st>>>(bws<T>(b, b->o_f) + d.f_off[p], own, d.sa, d.cp64.gx,    \
                                                    d.cp64.gy, (double*)d_rho, (double*)d_ux, (double*)d_uy, \
-                                                   nullptr, errf);                                        \
+                                                   d_owner, errf);                                        \
     else                                                                                                  \
         k_fields<T, float><<<nb, kBlock, 0, st>>>(bws<T>(b, b->o_f) + d.f_off[p], own, d.sa, d.cp64.gx,     \
                                                   d.cp64.gy, (float*)d_rho, (float*)d_ux, (float*)d_uy,   \
-                                                  nullptr, errf);
+                                                  d_owner, errf);
     switch (b->dtype) {
         case LBM_F64: BFIELDS_T(double) break;
         case LBM_F32: BFIELDS_T(float) break;
@@ -730,6 +746,29 @@ lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t case_id, const void* d_rh
     lbm_status rs = batch_join_user(b);
     if (rs != LBM_OK) return rs;
     batch_init_dispatch(b, case_id, b->run_stream, d_rho, d_ux, d_uy, in_dtype);
+    BCHK(b, hipGetLastError());
+    BCHK(b, hipStreamSynchronize(b->run_stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_init_poiseuille(lbm_batch* b, int32_t case_id) {
+    if (!b || case_id < 0 || case_id >= b->n) return LBM_EINVAL;
+    if (!b->grids[case_id].walls_y) {
+        set_err(b->err, "the Poiseuille start needs walls at y (walls_y = 1)");
+        return LBM_ESTATE;
+    }
+    if (b->conv_h[case_id]) {
+        set_err(b->err, "case %d has retired", case_id);
+        return LBM_ESTATE;
+    }
+    lbm_status rs = batch_join_user(b);
+    if (rs != LBM_OK) return rs;
+    switch (b->dtype) {
+        case LBM_F64: batch_poiseuille_case<double>(b, case_id, b->run_stream); break;
+        case LBM_F32: batch_poiseuille_case<float>(b, case_id, b->run_stream); break;
+        case LBM_F16: batch_poiseuille_case<_Float16>(b, case_id, b->run_stream); break;
+        default: batch_poiseuille_case<bf16_t>(b, case_id, b->run_stream); break;
+    }
     BCHK(b, hipGetLastError());
     BCHK(b, hipStreamSynchronize(b->run_stream));
     return LBM_OK;

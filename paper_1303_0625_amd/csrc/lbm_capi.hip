@@ -358,6 +358,14 @@ void enqueue_init(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
         c->g.u0y, rho, ux, uy);
 }
 
+template <typename T>
+void enqueue_init_poiseuille(lbm_ctx* c) {
+    using C = typename Sto<T>::C;
+    const int p = (int)(c->t & 1);
+    k_init_poiseuille<T><<<(unsigned)node_blocks(c), kBlock, 0, c->stream>>>(
+        wsp<T>(c, c->L.f[p]), own_ptr(c, p), step_args(c), collide_params<C>(c), c->g.gx, c->tau);
+}
+
 template <typename FT>
 void dispatch_init(lbm_ctx* c, const FT* rho, const FT* ux, const FT* uy) {
     switch (c->g.dtype) {
@@ -735,6 +743,22 @@ lbm_status lbm_init_fields(lbm_ctx* c, const void* d_rho, const void* d_ux, cons
     else {
         set_err(c->err, "fields are read as LBM_F64 or LBM_F32");
         return LBM_EINVAL;
+    }
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_init_poiseuille(lbm_ctx* c) {
+    if (!c) return LBM_EINVAL;
+    if (!c->g.walls_y) {
+        set_err(c->err, "the Poiseuille start needs walls at y (walls_y = 1)");
+        return LBM_ESTATE;
+    }
+    switch (c->g.dtype) {
+        case LBM_F64: enqueue_init_poiseuille<double>(c); break;
+        case LBM_F32: enqueue_init_poiseuille<float>(c); break;
+        case LBM_F16: enqueue_init_poiseuille<_Float16>(c); break;
+        default: enqueue_init_poiseuille<bf16_t>(c); break;
     }
     HIPCHK(c, hipGetLastError());
     return LBM_OK;

@@ -219,6 +219,37 @@ __global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_
     for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(d[i]);
 }
 
+// f = f_eq(rho0, u_P(y) - g/2), collided once, at every fluid node: the exact
+// steady plane-Poiseuille profile of BGK + Guo forcing between half-way walls,
+// u_P(y) = g_x / (2 nu) (Y^2 - (y - y_c)^2) + s, Y = ny/2, y_c = (ny - 1)/2,
+// s = g_x (4 (2 tau - 1)^2 - 3) / (4 (2 tau - 1)), nu = (tau - 1/2)/3 (the
+// start a solve reaches without bodies).  Solid nodes are zeroed.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_poiseuille(T* __restrict__ f, const uint8_t* __restrict__ own,
+                                                            StepArgs a, CollideParams<typename Sto<T>::C> cp,
+                                                            double gx, double tau) {
+    using C = typename Sto<T>::C;
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int y = (int)(idx / a.rowlen);
+    const int x = (int)(idx - (int64_t)y * a.rowlen);
+    if (y >= a.ny || x >= a.nx) return;
+    T* w0 = f + (int64_t)y * a.ystride + x;
+    if (own[(int64_t)y * a.opitch + x] != 0) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(C(0));
+        return;
+    }
+    const double nu = (tau - 0.5) / 3.0;
+    const double Y = 0.5 * a.ny, yc = 0.5 * (a.ny - 1), dy = y - yc;
+    const double slip = gx * (4.0 * (2.0 * tau - 1.0) * (2.0 * tau - 1.0) - 3.0) / (4.0 * (2.0 * tau - 1.0));
+    const double u = gx / (2.0 * nu) * (Y * Y - dy * dy) + slip;
+    C d[9];
+    feq_dev<C>((C)a.rho0, (C)a.rho0, (C)(u - 0.5 * gx), (C)(-0.5 * (double)cp.gy), d);
+    collide<C>(d, cp);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(d[i]);
+}
+
 // ------------------------------------------------------------------ fields
 // rho and the Guo velocity of the pre-collision state f(t), from the stored
 // post-collision populations: collision keeps mass and adds rho*g to the

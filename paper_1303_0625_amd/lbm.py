@@ -94,7 +94,9 @@ _SIG = {
     "lbm_batch_status": (_I32, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I64),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "lbm_batch_force": (_I32, [_VP, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_double)]),
-    "lbm_batch_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32]),
+    "lbm_batch_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32, _VP]),
+    "lbm_batch_init_poiseuille": (_I32, [_VP, _I32]),
+    "lbm_init_poiseuille": (_I32, [_VP]),
     "lbm_batch_init_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32]),
     "lbm_batch_time": (_I64, [_VP]),
     "lbm_batch_destroy": (None, [_VP]),
@@ -319,8 +321,16 @@ def lbm_batch_force(b, case_id: int, solid_id: int, scheme: int):
     return list(out)
 
 
-def lbm_batch_fields(b, case_id: int, d_rho, d_ux, d_uy, out_dtype: int) -> None:
-    _bcheck(load_library().lbm_batch_fields(b, case_id, d_rho, d_ux, d_uy, out_dtype), b)
+def lbm_batch_fields(b, case_id: int, d_rho, d_ux, d_uy, out_dtype: int, d_owner=None) -> None:
+    _bcheck(load_library().lbm_batch_fields(b, case_id, d_rho, d_ux, d_uy, out_dtype, d_owner), b)
+
+
+def lbm_batch_init_poiseuille(b, case_id: int) -> None:
+    _bcheck(load_library().lbm_batch_init_poiseuille(b, case_id), b)
+
+
+def lbm_init_poiseuille(ctx) -> None:
+    _check(load_library().lbm_init_poiseuille(ctx), ctx)
 
 
 def lbm_batch_init_fields(b, case_id: int, d_rho, d_ux, d_uy, in_dtype: int) -> None:
@@ -530,6 +540,9 @@ class Lattice:
         lbm_init_fields(self.ctx, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), dt)
         self._keep = (rho, ux, uy)
 
+    def init_poiseuille(self) -> None:
+        lbm_init_poiseuille(self.ctx)
+
     def populations(self):
         out = self.torch.empty((9, self.ny, self.nx), dtype=self.torch.float64,
                                device=self.workspace.device)
@@ -635,14 +648,20 @@ class LatticeBatch:
     def force(self, case_id: int, solid_id: int, scheme: int):
         return lbm_batch_force(self.b, case_id, solid_id, scheme)
 
-    def fields(self, case_id: int, out_dtype="f64"):
+    def fields(self, case_id: int, out_dtype="f64", owner=False):
+        """rho, ux, uy [ny][nx] (and the uint8 owner map when owner=True)."""
         c = self.cases[case_id]
         tdt = self.torch.float64 if out_dtype == "f64" else self.torch.float32
         shp = (c["ny"], c["nx"])
         dev = self.workspace.device
         rho, ux, uy = (self.torch.empty(shp, dtype=tdt, device=dev) for _ in range(3))
-        lbm_batch_fields(self.b, case_id, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), DTYPES[out_dtype])
-        return rho, ux, uy
+        own = self.torch.empty(shp, dtype=self.torch.uint8, device=dev) if owner else None
+        lbm_batch_fields(self.b, case_id, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), DTYPES[out_dtype],
+                         own.data_ptr() if owner else None)
+        return (rho, ux, uy, own) if owner else (rho, ux, uy)
+
+    def init_poiseuille(self, case_id: int) -> None:
+        lbm_batch_init_poiseuille(self.b, case_id)
 
     def init_fields(self, case_id: int, rho, ux, uy) -> None:
         dt = LBM_F64 if rho.dtype == self.torch.float64 else LBM_F32

@@ -1,0 +1,300 @@
+"""Learned warm start: training data from the batched solver, training of the
+U-Net through lbm_nn_*, and the comparison of cold, exact-Poiseuille and
+learned starts on held-out channels.
+
+Every arithmetic step runs in the library's HIP kernels (solver, network,
+normalisation, initialisation); this module orders the calls, draws the
+seeded parameter initialisation and minibatch order, and keeps the tallies.
+
+Command line (one GPU):
+    python -m paper_1303_0625_amd.warmstart --train 512 --held 64 --out DIR
+writes DIR/warmstart_weights.npz (parameters, rho_scale, channels, grid) and
+DIR/warmstart_results.json, printing progress lines as it goes.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import lbm
+
+CH = (32, 64, 128, 256)
+
+
+def _log(msg):
+    print(f"[warmstart] {msg}", flush=True)
+
+
+# --------------------------------------------------------------------- solving
+def solve(batch, tol, check, cap, chunk=20000, log=_log, drag_every_check=False, t0=None):
+    """Advance a LatticeBatch until every case retires (r < tol) or `cap`
+    steps.  With drag_every_check, one interval per call and the drag of every
+    case recorded after each check: returns (history [(wall_s, step, drags)],
+    wall seconds)."""
+    t0 = time.perf_counter() if t0 is None else t0
+    hist = []
+    last = time.perf_counter()
+    while batch.t < cap:
+        if drag_every_check:
+            done = batch.run(check, tol, check)
+            conv, _, _, drag = batch.status()
+            hist.append((time.perf_counter() - t0, batch.t, [d[0] for d in drag]))
+        else:
+            done = batch.run(min(chunk, cap - batch.t), tol, check)
+            conv = batch.status()[0]
+        if all(conv) or done == 0:
+            break
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            log(f"  step {batch.t}: {sum(conv)}/{len(conv)} converged")
+    return hist, time.perf_counter() - t0
+
+
+# --------------------------------------------------------------------- data
+def generate(cases, tol=1e-8, check=100, cap=2_000_000, log=_log):
+    """Solve every case to steady state (FP32, cold start) and gather the
+    training set on the device: solid u8, rho/ux/uy f32 [N][ny][nx], re/gx/tau
+    f64 [N]; plus per-case converged flags and steps."""
+    import torch
+
+    t0 = time.perf_counter()
+    batch = lbm.LatticeBatch(cases, dtype="f32")
+    batch.autotune(None)
+    solve(batch, tol, check, cap, log=log)
+    conv, steps, res, drag = batch.status()
+    n = len(cases)
+    ny, nx = cases[0]["ny"], cases[0]["nx"]
+    dev = batch.workspace.device
+    data = {"solid": torch.empty((n, ny, nx), dtype=torch.uint8, device=dev),
+            "rho": torch.empty((n, ny, nx), dtype=torch.float32, device=dev),
+            "ux": torch.empty((n, ny, nx), dtype=torch.float32, device=dev),
+            "uy": torch.empty((n, ny, nx), dtype=torch.float32, device=dev)}
+    for k in range(n):
+        rho, ux, uy, own = batch.fields(k, "f32", owner=True)
+        data["rho"][k], data["ux"][k], data["uy"][k] = rho, ux, uy
+        data["solid"][k] = own != 0
+    for key, vals in (("re", [c["Re"] for c in cases]), ("gx", [c["gx"] for c in cases]),
+                      ("tau", [c["tau"] for c in cases])):
+        data[key] = torch.tensor(vals, dtype=torch.float64, device=dev)
+    wall = time.perf_counter() - t0
+    nodes = sum(c["nx"] * c["ny"] for c in cases)
+    log(f"generated {n} cases in {wall:.1f} s: {sum(conv)} converged, steps max {max(steps)}, "
+        f"{nodes * float(np.mean(steps)) / 1e9:.2f} G node-steps")
+    del batch
+    torch.cuda.empty_cache()
+    return data, {"converged": conv, "steps": steps, "residual": res, "drag": drag, "wall_s": wall}
+
+
+def rho_scale_of(data):
+    """Root-mean-square of (rho - 1) / U_c over fluid nodes (the density
+    output's scale), U_c = g_x ny^2 / (8 nu)."""
+    import torch
+
+    nu = (data["tau"] - 0.5) / 3.0
+    ny = data["rho"].shape[1]
+    uc = (data["gx"] * ny * ny / (8.0 * nu)).to(torch.float64)[:, None, None]
+    fl = data["solid"] == 0
+    d = (data["rho"].double() - 1.0) / uc
+    return float(torch.sqrt((d[fl] ** 2).mean()).item())
+
+
+# --------------------------------------------------------------------- network
+def init_params(seed, ch=CH):
+    """He-normal weights (fan-in 9 c_in), zero biases, head scaled by 0.1."""
+    rng = np.random.default_rng(seed)
+    c0, c1, c2, c3 = ch
+    shapes = [(2, c0), (c0, c0), (c0, c1), (c1, c1), (c1, c2), (c2, c2), (c2, c3), (c3, c3),
+              (c3 + c2, c2), (c2, c2), (c2 + c1, c1), (c1, c1), (c1 + c0, c0), (c0, c0), (c0, 3)]
+    out = []
+    for k, (ci, co) in enumerate(shapes):
+        w = rng.normal(size=co * 9 * ci) * np.sqrt(2.0 / (9 * ci))
+        if k == len(shapes) - 1:
+            w *= 0.1
+        out += [w, np.zeros(co)]
+    return np.concatenate(out).astype(np.float32)
+
+
+def train(data, train_idx, val_idx, epochs=60, batch=8, lr=1e-3, lr_min=1e-5, seed=0, dtype="bf16",
+          rho_scale=1.0, log=_log):
+    """Adam with a cosine learning-rate decay; returns (net, history)."""
+    import torch
+
+    ny, nx = data["rho"].shape[1:]
+    net = lbm.WarmStartNet(ny, nx, batch, dtype=dtype, ch=CH, rho_scale=rho_scale)
+    net.set_params(torch.from_numpy(init_params(seed)))
+    rng = np.random.default_rng(seed + 1)
+    dev = data["rho"].device
+    steps_per_epoch = max(1, len(train_idx) // batch)
+    total = epochs * steps_per_epoch
+    hist = []
+    t0 = time.perf_counter()
+    it = 0
+
+    def eval_set(idx):
+        if len(idx) == 0:
+            return float("nan")
+        s = 0.0
+        for k in range(0, len(idx), batch):
+            part = torch.tensor(idx[k:k + batch], dtype=torch.int32, device=dev)
+            s += net.eval(data, part) * len(part)
+        return s / len(idx)
+
+    for ep in range(epochs):
+        order = rng.permutation(train_idx)
+        for k in range(steps_per_epoch):
+            frac = it / max(total - 1, 1)
+            cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * frac))
+            part = torch.tensor(order[k * batch:(k + 1) * batch], dtype=torch.int32, device=dev)
+            net.train_step(data, part, float(cur))
+            it += 1
+        if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
+            tr, va = eval_set(train_idx[:64]), eval_set(val_idx)
+            hist.append({"epoch": ep, "train_loss": tr, "val_loss": va, "wall_s": time.perf_counter() - t0})
+            log(f"epoch {ep}: train loss {tr:.4e}, held-out loss {va:.4e} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return net, {"history": hist, "wall_s": time.perf_counter() - t0, "steps": it, "batch": batch}
+
+
+def save_weights(path, net, rho_scale):
+    np.savez(path, params=net.params().cpu().numpy(), rho_scale=np.float64(rho_scale),
+             ch=np.asarray(CH, dtype=np.int32), h=np.int32(net.h), w=np.int32(net.w))
+
+
+def load_weights(path):
+    """(params float32, rho_scale, ch, h, w) from a weights file (no pickles)."""
+    with np.load(path, allow_pickle=False) as z:
+        return (z["params"].astype(np.float32), float(z["rho_scale"]), tuple(int(c) for c in z["ch"]),
+                int(z["h"]), int(z["w"]))
+
+
+# --------------------------------------------------------------------- evaluation
+def start_batch(cases, kind, net=None, dtype="f32"):
+    """A LatticeBatch of the cases started cold, from the exact Poiseuille
+    flow, or from the network's fields."""
+    import torch
+
+    b = lbm.LatticeBatch(cases, dtype=dtype)
+    if kind == "poiseuille":
+        for k in range(len(cases)):
+            b.init_poiseuille(k)
+    elif kind == "learned":
+        dev = b.workspace.device
+        for k0 in range(0, len(cases), net.max_batch):
+            part = cases[k0:k0 + net.max_batch]
+            solid = torch.stack([b.fields(k0 + j, "f32", owner=True)[3] for j in range(len(part))]) != 0
+            re = torch.tensor([c["Re"] for c in part], dtype=torch.float64, device=dev)
+            gx = torch.tensor([c["gx"] for c in part], dtype=torch.float64, device=dev)
+            tau = torch.tensor([c["tau"] for c in part], dtype=torch.float64, device=dev)
+            rho, ux, uy = net.infer(solid.to(torch.uint8).contiguous(), re, gx, tau)
+            for j in range(len(part)):
+                b.init_fields(k0 + j, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
+    return b
+
+
+def steady_time(hist, d_inf, rel=1e-4):
+    """Per case, the first (step, wall) after which |D - D_inf| <= rel |D_inf|
+    at every later check; None if never."""
+    n = len(d_inf)
+    out = [None] * n
+    for k in range(n):
+        ok_from = None
+        for wall, step, drags in hist:
+            good = abs(drags[k] - d_inf[k]) <= rel * abs(d_inf[k])
+            if good and ok_from is None:
+                ok_from = (step, wall)
+            elif not good:
+                ok_from = None
+        out[k] = ok_from
+    return out
+
+
+def evaluate(cases, net, tol=1e-8, check=100, cap=2_000_000, kinds=("cold", "poiseuille", "learned"), log=_log):
+    """Solve the held-out cases from each start; per start: steps to r < tol,
+    steps and wall time until every drag stays within 1e-4 of the cold run's
+    converged drag, and the drags at convergence."""
+    import torch
+
+    out = {}
+    for kind in kinds:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = start_batch(cases, kind, net)
+        hist, wall = solve(b, tol, check, cap, log=log, drag_every_check=True, t0=t0)
+        conv, steps, res, drag = b.status()
+        out[kind] = {"converged": conv, "steps": steps, "residual": res, "drag": [d[0] for d in drag],
+                     "wall_s": wall, "hist": hist}
+        log(f"{kind}: {sum(conv)}/{len(conv)} converged, mean steps {np.mean(steps):.0f}, wall {wall:.1f} s")
+        del b
+        torch.cuda.empty_cache()
+    # cases whose cold run reached steady state define D_inf; the others
+    # (vortex shedding, or the step cap) have no steady drag to reach
+    d_inf = out["cold"]["drag"]
+    steady = [k for k, c in enumerate(out["cold"]["converged"]) if c]
+    out["steady_cases"] = steady
+    for kind in kinds:
+        st = steady_time(out[kind]["hist"], d_inf)
+        out[kind]["drag_steady_step"] = [st[k][0] if st[k] else None for k in steady]
+        ok = [st[k] for k in steady if st[k]]
+        out[kind]["drag_steady_wall_s"] = max(s[1] for s in ok) if ok and len(ok) == len(steady) else None
+        out[kind]["drag_rel_err"] = [abs(out[kind]["drag"][k] - d_inf[k]) / abs(d_inf[k]) for k in steady]
+        del out[kind]["hist"]
+    return out
+
+
+# --------------------------------------------------------------------- command line
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=512)
+    ap.add_argument("--held", type=int, default=64)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--cap", type=int, default=2_000_000)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--dtype", default="bf16")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import lbm_cases as lc
+
+    lbm.load_library()
+    torch.cuda.set_device(0)
+    os.makedirs(a.out, exist_ok=True)
+    train_cases = lc.warmstart_channels(seed=5005, n_cases=a.train)
+    held_cases = lc.warmstart_channels(seed=5006, n_cases=a.held)
+    _log(f"training set: {a.train} channels; held-out: {a.held}")
+    data, gen = generate(train_cases, a.tol, 100, a.cap)
+    keep = [k for k in range(a.train) if gen["converged"][k]]
+    _log(f"{len(keep)} of {a.train} training cases converged (the rest are dropped)")
+    rs = rho_scale_of({k: (v[keep] if hasattr(v, "shape") and v.shape[0] == a.train else v)
+                       for k, v in data.items()})
+    _log(f"rho_scale {rs:.4e}")
+    n_val = max(1, len(keep) // 16)
+    val_idx, train_idx = np.array(keep[:n_val]), np.array(keep[n_val:])
+    net, tr = train(data, train_idx, val_idx, a.epochs, a.batch, a.lr, dtype=a.dtype, rho_scale=rs)
+    save_weights(os.path.join(a.out, "warmstart_weights.npz"), net, rs)
+    del data
+    torch.cuda.empty_cache()
+    ev = evaluate(held_cases, net, a.tol, 100, a.cap)
+    res = {"train_cases": a.train, "held_cases": a.held, "tol": a.tol, "cap": a.cap,
+           "generation": {k: gen[k] for k in ("converged", "steps", "wall_s")}, "rho_scale": rs,
+           "training": tr, "evaluation": ev}
+    with open(os.path.join(a.out, "warmstart_results.json"), "w") as fh:
+        json.dump(res, fh)
+    for kind in ("cold", "poiseuille", "learned"):
+        e = ev[kind]
+        err = max(e["drag_rel_err"]) if e["drag_rel_err"] else float("nan")
+        _log(f"{kind}: mean steps to r<{a.tol:g}: {np.mean(e['steps']):.0f}; all drags steady (1e-4) at "
+             f"{e['drag_steady_wall_s']} s; max drag rel err {err:.2e}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -249,3 +249,27 @@ def test_batch_rejects_bad_input(lbm_mod):
         batch.run(100, 1e-8, 1)
     with pytest.raises(lbm_mod.LBMError):
         batch.force(0, 5, 0)
+
+
+def test_poiseuille_start_is_the_steady_channel(lbm_mod):
+    """The exact plane-Poiseuille start is a fixed point of an empty walled
+    channel (FP64): fields equal the closed form and stay put; in a batch the
+    case retires at its first residual check."""
+    case = lc.make_case(64, 24, 0.8, walls_y=True, gx=5e-6, name="poiseuille_64x24")
+    nu, g, ny, tau = 0.1, 5e-6, 24, 0.8
+    y = np.arange(ny)
+    slip = g * (4 * (2 * tau - 1) ** 2 - 3) / (4 * (2 * tau - 1))
+    exact = g / (2 * nu) * ((ny / 2) ** 2 - (y - (ny - 1) / 2) ** 2) + slip
+    lat = lbm_mod.Lattice(case, dtype="f64", history_steps=4)
+    lat.init_poiseuille()
+    for steps in (0, 500):
+        lat.step(steps)
+        rho, ux, uy, _ = (_np(a) for a in lat.fields("f64"))
+        assert np.abs(ux - exact[:, None]).max() <= 1e-13 * exact.max(), steps
+        assert np.abs(uy).max() <= 1e-13 * exact.max() and np.abs(rho - 1).max() <= 1e-13
+    batch = lbm_mod.LatticeBatch([case, uneven_cases()[0]], dtype="f64")
+    batch.init_poiseuille(0)
+    batch.run(400, 1e-12, 100)
+    conv, steps, res, _ = batch.status()
+    assert conv[0] == 1 and steps[0] == 100 and conv[1] == 0
+    assert np.abs(_np(batch.fields(0, "f64")[1]) - exact[:, None]).max() <= 1e-13 * exact.max()
