@@ -379,14 +379,18 @@ lbm_status lbm_nn_adam(lbm_nn* nn, double lr, double beta1, double beta2, double
 
 /* Training step on the samples d_idx[0..batch) (NULL: 0..batch-1) of a data
  * set held in device memory: solid mask u8 [N][h][w], steady fields rho, u_x,
- * u_y FP32 [N][h][w], and per sample Re, g_x and tau (FP64 [N]).  The loss is
- * the mean over fluid nodes and the 3 outputs of the squared error of the
- * normalised output; then backward and Adam (beta 0.9, 0.999, eps 1e-8) with
- * learning rate lr.  *loss (optional, host) receives the loss before the
- * update and makes the call synchronise. */
+ * u_y FP32 [N][h][w], and per sample Re, g_x and tau (FP64 [N]).  d_aug
+ * (optional, int32 [batch]) transforms each drawn sample: bits 0..15 shift it
+ * periodically in x by that many nodes, bit 16 mirrors it about the channel
+ * centre line (u_y changes sign) -- both map a steady channel flow to the
+ * steady flow of the transformed geometry.  The loss is the mean over fluid
+ * nodes and the 3 outputs of the squared error of the normalised output; then
+ * backward and Adam (beta 0.9, 0.999, eps 1e-8) with learning rate lr.  *loss
+ * (optional, host) receives the loss before the update and makes the call
+ * synchronise. */
 lbm_status lbm_nn_train_step(lbm_nn* nn, const uint8_t* d_solid, const float* d_rho, const float* d_ux,
                              const float* d_uy, const double* d_re, const double* d_gx, const double* d_tau,
-                             const int32_t* d_idx, int32_t batch, double lr, double* loss);
+                             const int32_t* d_idx, const int32_t* d_aug, int32_t batch, double lr, double* loss);
 
 /* The loss of lbm_nn_train_step without the update (synchronises). */
 lbm_status lbm_nn_eval(lbm_nn* nn, const uint8_t* d_solid, const float* d_rho, const float* d_ux, const float* d_uy,

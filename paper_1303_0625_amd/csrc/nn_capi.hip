@@ -445,12 +445,12 @@ void loss_t(lbm_nn* n) {
 
 template <typename T>
 void pack_sample_t(lbm_nn* n, const uint8_t* solid, const float* rho, const float* ux, const float* uy,
-                   const double* re, const double* gx, const double* tau, const int* idx) {
+                   const double* re, const double* gx, const double* tau, const int* idx, const int* aug) {
     const Plan& p = n->p;
     const int64_t P = (int64_t)n->batch * p.H * p.W;
-    k_pack_input<T><<<blocks(P), kEw, 0, n->st>>>(solid, re, idx, p.H * p.W, n->batch, (T*)buf(n, X0));
+    k_pack_input<T><<<blocks(P), kEw, 0, n->st>>>(solid, re, idx, aug, p.H, p.W, n->batch, (T*)buf(n, X0));
     if (rho)
-        k_pack_target<<<blocks(P), kEw, 0, n->st>>>(solid, rho, ux, uy, gx, tau, idx, p.H, p.W, n->batch,
+        k_pack_target<<<blocks(P), kEw, 0, n->st>>>(solid, rho, ux, uy, gx, tau, idx, aug, p.H, p.W, n->batch,
                                                     n->rho_scale, at<float>(n, p.o_tgt), at<uint8_t>(n, p.o_fluid));
 }
 
@@ -596,7 +596,7 @@ lbm_status lbm_nn_adam(lbm_nn* n, double lr, double beta1, double beta2, double 
 
 static lbm_status train_or_eval(lbm_nn* n, const uint8_t* solid, const float* rho, const float* ux, const float* uy,
                                 const double* re, const double* gx, const double* tau, const int32_t* idx,
-                                int32_t batch, double lr, double* loss, bool train) {
+                                const int32_t* aug, int32_t batch, double lr, double* loss, bool train) {
     if (!n || !solid || !rho || !ux || !uy || !re || !gx || !tau) return LBM_EINVAL;
     lbm_status rs = check_batch(n, batch);
     if (rs != LBM_OK) return rs;
@@ -606,12 +606,12 @@ static lbm_status train_or_eval(lbm_nn* n, const uint8_t* solid, const float* rh
     }
     n->batch = batch;
     if (n->dtype == LBM_BF16) {
-        pack_sample_t<__bf16>(n, solid, rho, ux, uy, re, gx, tau, idx);
+        pack_sample_t<__bf16>(n, solid, rho, ux, uy, re, gx, tau, idx, aug);
         forward_t<__bf16>(n);
         loss_t<__bf16>(n);
         if (train) backward_t<__bf16>(n);
     } else {
-        pack_sample_t<float>(n, solid, rho, ux, uy, re, gx, tau, idx);
+        pack_sample_t<float>(n, solid, rho, ux, uy, re, gx, tau, idx, aug);
         forward_t<float>(n);
         loss_t<float>(n);
         if (train) backward_t<float>(n);
@@ -630,14 +630,14 @@ static lbm_status train_or_eval(lbm_nn* n, const uint8_t* solid, const float* rh
 
 lbm_status lbm_nn_train_step(lbm_nn* n, const uint8_t* d_solid, const float* d_rho, const float* d_ux,
                              const float* d_uy, const double* d_re, const double* d_gx, const double* d_tau,
-                             const int32_t* d_idx, int32_t batch, double lr, double* loss) {
-    return train_or_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch, lr, loss, true);
+                             const int32_t* d_idx, const int32_t* d_aug, int32_t batch, double lr, double* loss) {
+    return train_or_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, d_aug, batch, lr, loss, true);
 }
 
 lbm_status lbm_nn_eval(lbm_nn* n, const uint8_t* d_solid, const float* d_rho, const float* d_ux, const float* d_uy,
                        const double* d_re, const double* d_gx, const double* d_tau, const int32_t* d_idx,
                        int32_t batch, double* loss) {
-    return train_or_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch, 0.0, loss, false);
+    return train_or_eval(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, nullptr, batch, 0.0, loss, false);
 }
 
 lbm_status lbm_nn_infer(lbm_nn* n, const uint8_t* d_solid, const double* d_re, const double* d_gx,
@@ -649,10 +649,10 @@ lbm_status lbm_nn_infer(lbm_nn* n, const uint8_t* d_solid, const double* d_re, c
     const Plan& p = n->p;
     const int64_t P = (int64_t)batch * p.H * p.W;
     if (n->dtype == LBM_BF16) {
-        pack_sample_t<__bf16>(n, d_solid, nullptr, nullptr, nullptr, d_re, d_gx, d_tau, nullptr);
+        pack_sample_t<__bf16>(n, d_solid, nullptr, nullptr, nullptr, d_re, d_gx, d_tau, nullptr, nullptr);
         forward_t<__bf16>(n);
     } else {
-        pack_sample_t<float>(n, d_solid, nullptr, nullptr, nullptr, d_re, d_gx, d_tau, nullptr);
+        pack_sample_t<float>(n, d_solid, nullptr, nullptr, nullptr, d_re, d_gx, d_tau, nullptr, nullptr);
         forward_t<float>(n);
     }
     k_unpack_fields<<<blocks(P), kEw, 0, n->st>>>(at<float>(n, p.o_out), d_solid, d_gx, d_tau, p.H, p.W, batch,

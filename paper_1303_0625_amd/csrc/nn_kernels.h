@@ -394,17 +394,38 @@ __global__ __launch_bounds__(kEw) void k_pool_back_skip(const T* __restrict__ g_
 }
 
 // ------------------------------------------------------------------ data
+// Source node of output node (y, x) of sample b under the augmentation code
+// aug[b] (optional): bits 0..15 shift x periodically by that many nodes, bit
+// 16 mirrors y about the channel centre line (y -> H - 1 - y).  Both map a
+// steady channel flow onto the steady flow of the transformed geometry (u_y
+// changes sign under the mirror).
+__device__ inline int64_t aug_source(const int* aug, int b, int s, int y, int x, int H, int W, bool& flip) {
+    int shift = 0;
+    flip = false;
+    if (aug) {
+        shift = aug[b] & 0xFFFF;
+        flip = ((aug[b] >> 16) & 1) != 0;
+    }
+    const int ys = flip ? H - 1 - y : y;
+    int xs = x - shift;
+    xs = xs < 0 ? xs + W : xs;
+    return ((int64_t)s * H + ys) * W + xs;
+}
+
 // Network input from a solid mask and Re: channel 0 = solid, 1 = Re / 100,
 // channels 2..15 zero.  idx (optional) selects samples of a larger set.
 template <typename T>
 __global__ __launch_bounds__(kEw) void k_pack_input(const uint8_t* __restrict__ solid, const double* __restrict__ re,
-                                                    const int* __restrict__ idx, int HW, int B,
-                                                    T* __restrict__ x0) {
+                                                    const int* __restrict__ idx, const int* __restrict__ aug, int H,
+                                                    int W, int B, T* __restrict__ x0) {
+    const int HW = H * W;
     const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
     if (p >= (int64_t)B * HW) return;
     const int b = (int)(p / HW);
     const int s = idx ? idx[b] : b;
-    const int64_t src = (int64_t)s * HW + (p - (int64_t)b * HW);
+    const int r = (int)(p - (int64_t)b * HW);
+    bool flip;
+    const int64_t src = aug_source(aug, b, s, r / W, r % W, H, W, flip);
     T* o = x0 + p * 16;
     o[0] = from_f<T>(solid[src] ? 1.0f : 0.0f);
     o[1] = from_f<T>((float)(re[s] / 100.0));
@@ -434,21 +455,23 @@ __device__ inline double u_centre(double gx, double tau, int ny) {
 __global__ __launch_bounds__(kEw) void k_pack_target(const uint8_t* __restrict__ solid, const float* __restrict__ rho,
                                                      const float* __restrict__ ux, const float* __restrict__ uy,
                                                      const double* __restrict__ gx, const double* __restrict__ tau,
-                                                     const int* __restrict__ idx, int H, int W, int B,
-                                                     double rho_scale, float* __restrict__ tgt,
+                                                     const int* __restrict__ idx, const int* __restrict__ aug, int H,
+                                                     int W, int B, double rho_scale, float* __restrict__ tgt,
                                                      uint8_t* __restrict__ fluid) {
     const int HW = H * W;
     const int64_t p = (int64_t)blockIdx.x * kEw + threadIdx.x;
     if (p >= (int64_t)B * HW) return;
     const int b = (int)(p / HW);
     const int s = idx ? idx[b] : b;
-    const int64_t src = (int64_t)s * HW + (p - (int64_t)b * HW);
+    const int r = (int)(p - (int64_t)b * HW);
+    bool flip;
+    const int64_t src = aug_source(aug, b, s, r / W, r % W, H, W, flip);
     const double uc = u_centre(gx[s], tau[s], H);
     const bool fl = solid[src] == 0;
     fluid[p] = fl ? 1 : 0;
     tgt[3 * p + 0] = fl ? (float)(((double)rho[src] - 1.0) / (uc * rho_scale)) : 0.0f;
     tgt[3 * p + 1] = fl ? (float)((double)ux[src] / uc) : 0.0f;
-    tgt[3 * p + 2] = fl ? (float)((double)uy[src] / uc) : 0.0f;
+    tgt[3 * p + 2] = fl ? (float)((flip ? -1.0 : 1.0) * (double)uy[src] / uc) : 0.0f;
 }
 
 // Fields from the network output (inference): fluid nodes get

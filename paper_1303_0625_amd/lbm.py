@@ -110,7 +110,7 @@ _SIG = {
     "lbm_nn_forward": (_I32, [_VP, _VP, _I32, _VP]),
     "lbm_nn_backward": (_I32, [_VP, _VP]),
     "lbm_nn_adam": (_I32, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
-    "lbm_nn_train_step": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, ctypes.c_double,
+    "lbm_nn_train_step": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_double)]),
     "lbm_nn_eval": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32,
                            ctypes.POINTER(ctypes.c_double)]),
@@ -397,11 +397,11 @@ def lbm_nn_adam(n, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
     _ncheck(load_library().lbm_nn_adam(n, lr, beta1, beta2, eps), n)
 
 
-def lbm_nn_train_step(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch: int, lr: float,
+def lbm_nn_train_step(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, d_aug, batch: int, lr: float,
                       want_loss: bool = False):
     loss = ctypes.c_double(0.0)
-    _ncheck(load_library().lbm_nn_train_step(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, batch, lr,
-                                             ctypes.byref(loss) if want_loss else None), n)
+    _ncheck(load_library().lbm_nn_train_step(n, d_solid, d_rho, d_ux, d_uy, d_re, d_gx, d_tau, d_idx, d_aug, batch,
+                                             lr, ctypes.byref(loss) if want_loss else None), n)
     return loss.value if want_loss else None
 
 
@@ -734,12 +734,14 @@ class WarmStartNet:
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
         lbm_nn_adam(self.n, lr, beta1, beta2, eps)
 
-    def train_step(self, data, idx, lr, want_loss=False):
-        """data: dict of device tensors solid, rho, ux, uy, re, gx, tau; idx int32 [B]."""
+    def train_step(self, data, idx, lr, want_loss=False, aug=None):
+        """data: dict of device tensors solid, rho, ux, uy, re, gx, tau; idx
+        int32 [B]; aug (optional) int32 [B] augmentation codes."""
         d = data
         return lbm_nn_train_step(self.n, d["solid"].data_ptr(), d["rho"].data_ptr(), d["ux"].data_ptr(),
                                  d["uy"].data_ptr(), d["re"].data_ptr(), d["gx"].data_ptr(), d["tau"].data_ptr(),
-                                 idx.data_ptr(), idx.numel(), lr, want_loss)
+                                 idx.data_ptr(), aug.data_ptr() if aug is not None else None, idx.numel(), lr,
+                                 want_loss)
 
     def eval(self, data, idx) -> float:
         d = data

@@ -7,9 +7,14 @@ normalisation, initialisation); this module orders the calls, draws the
 seeded parameter initialisation and minibatch order, and keeps the tallies.
 
 Command line (one GPU):
-    python -m paper_1303_0625_amd.warmstart --train 512 --held 64 --out DIR
-writes DIR/warmstart_weights.npz (parameters, rho_scale, channels, grid) and
-DIR/warmstart_results.json, printing progress lines as it goes.
+    python -m paper_1303_0625_amd.warmstart train --train 512 --out DIR
+        solves 512 channels (seed 5005) to steady state, trains, and writes
+        DIR/warmstart_weights.npz (parameters, rho_scale, channels, grid) and
+        DIR/warmstart_train.json;
+    python -m paper_1303_0625_amd.warmstart eval --weights W --held 64 --out DIR
+        starts 64 held-out channels (seed 5006) cold, from the Poiseuille flow
+        and from the network, solves them, writes DIR/warmstart_eval.json.
+Both print progress lines as they go.
 """
 from __future__ import annotations
 
@@ -120,8 +125,9 @@ def init_params(seed, ch=CH):
 
 
 def train(data, train_idx, val_idx, epochs=60, batch=8, lr=1e-3, lr_min=1e-5, seed=0, dtype="bf16",
-          rho_scale=1.0, log=_log):
-    """Adam with a cosine learning-rate decay; returns (net, history)."""
+          rho_scale=1.0, augment=True, log=_log):
+    """Adam with a cosine learning-rate decay, each drawn sample shifted in x
+    and mirrored in y at random (augment); returns (net, history)."""
     import torch
 
     ny, nx = data["rho"].shape[1:]
@@ -150,7 +156,10 @@ def train(data, train_idx, val_idx, epochs=60, batch=8, lr=1e-3, lr_min=1e-5, se
             frac = it / max(total - 1, 1)
             cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * frac))
             part = torch.tensor(order[k * batch:(k + 1) * batch], dtype=torch.int32, device=dev)
-            net.train_step(data, part, float(cur))
+            # exact symmetries of the periodic walled channel: x shift, mirror in y
+            codes = rng.integers(0, nx, size=len(part)) | (rng.integers(0, 2, size=len(part)) << 16)
+            aug = torch.tensor(codes.astype(np.int32), device=dev) if augment else None
+            net.train_step(data, part, float(cur), aug=aug)
             it += 1
         if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
             tr, va = eval_set(train_idx[:64]), eval_set(val_idx)
@@ -247,17 +256,34 @@ def evaluate(cases, net, tol=1e-8, check=100, cap=2_000_000, kinds=("cold", "poi
 
 
 # --------------------------------------------------------------------- command line
+def load_net(path, max_batch=8, dtype="bf16"):
+    """A WarmStartNet with the weights of a weights file."""
+    import torch
+
+    params, rs, ch, h, w = load_weights(path)
+    net = lbm.WarmStartNet(h, w, max_batch, dtype=dtype, ch=ch, rho_scale=rs)
+    net.set_params(torch.from_numpy(params))
+    return net
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=512)
-    ap.add_argument("--held", type=int, default=64)
-    ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--cap", type=int, default=2_000_000)
-    ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--dtype", default="bf16")
-    ap.add_argument("--out", required=True)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train", help="generate steady fields with the solver, train, save the weights")
+    t.add_argument("--train", type=int, default=512)
+    t.add_argument("--tol", type=float, default=1e-8)
+    t.add_argument("--cap", type=int, default=2_000_000)
+    t.add_argument("--epochs", type=int, default=300)
+    t.add_argument("--batch", type=int, default=8)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--dtype", default="bf16")
+    t.add_argument("--out", required=True)
+    e = sub.add_parser("eval", help="cold, Poiseuille and learned starts on held-out channels")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--held", type=int, default=64)
+    e.add_argument("--tol", type=float, default=1e-8)
+    e.add_argument("--cap", type=int, default=2_000_000)
+    e.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     import torch
 
@@ -267,32 +293,37 @@ def main(argv=None) -> int:
     lbm.load_library()
     torch.cuda.set_device(0)
     os.makedirs(a.out, exist_ok=True)
-    train_cases = lc.warmstart_channels(seed=5005, n_cases=a.train)
-    held_cases = lc.warmstart_channels(seed=5006, n_cases=a.held)
-    _log(f"training set: {a.train} channels; held-out: {a.held}")
-    data, gen = generate(train_cases, a.tol, 100, a.cap)
-    keep = [k for k in range(a.train) if gen["converged"][k]]
-    _log(f"{len(keep)} of {a.train} training cases converged (the rest are dropped)")
-    rs = rho_scale_of({k: (v[keep] if hasattr(v, "shape") and v.shape[0] == a.train else v)
-                       for k, v in data.items()})
-    _log(f"rho_scale {rs:.4e}")
-    n_val = max(1, len(keep) // 16)
-    val_idx, train_idx = np.array(keep[:n_val]), np.array(keep[n_val:])
-    net, tr = train(data, train_idx, val_idx, a.epochs, a.batch, a.lr, dtype=a.dtype, rho_scale=rs)
-    save_weights(os.path.join(a.out, "warmstart_weights.npz"), net, rs)
-    del data
-    torch.cuda.empty_cache()
-    ev = evaluate(held_cases, net, a.tol, 100, a.cap)
-    res = {"train_cases": a.train, "held_cases": a.held, "tol": a.tol, "cap": a.cap,
-           "generation": {k: gen[k] for k in ("converged", "steps", "wall_s")}, "rho_scale": rs,
-           "training": tr, "evaluation": ev}
-    with open(os.path.join(a.out, "warmstart_results.json"), "w") as fh:
-        json.dump(res, fh)
+    if a.cmd == "train":
+        cases = lc.warmstart_channels(seed=5005, n_cases=a.train)
+        _log(f"training set: {a.train} channels (seed 5005)")
+        data, gen = generate(cases, a.tol, 100, a.cap)
+        keep = [k for k in range(a.train) if gen["converged"][k]]
+        _log(f"{len(keep)} of {a.train} training cases converged (the rest are dropped)")
+        sub_data = {k: (v[keep] if v.shape[0] == a.train else v) for k, v in data.items()}
+        rs = rho_scale_of(sub_data)
+        _log(f"rho_scale {rs:.4e}")
+        n_val = max(1, len(keep) // 16)
+        val_idx, train_idx = np.array(keep[:n_val]), np.array(keep[n_val:])
+        net, tr = train(data, train_idx, val_idx, a.epochs, a.batch, a.lr, dtype=a.dtype, rho_scale=rs)
+        save_weights(os.path.join(a.out, "warmstart_weights.npz"), net, rs)
+        res = {"train_cases": a.train, "tol": a.tol, "cap": a.cap, "rho_scale": rs,
+               "generation": {k: gen[k] for k in ("converged", "steps", "wall_s")},
+               "re": [c["Re"] for c in cases], "training": tr}
+        with open(os.path.join(a.out, "warmstart_train.json"), "w") as fh:
+            json.dump(res, fh)
+        return 0
+    held = lc.warmstart_channels(seed=5006, n_cases=a.held)
+    _log(f"held-out set: {a.held} channels (seed 5006)")
+    net = load_net(a.weights)
+    ev = evaluate(held, net, a.tol, 100, a.cap)
+    ev["re"] = [c["Re"] for c in held]
+    with open(os.path.join(a.out, "warmstart_eval.json"), "w") as fh:
+        json.dump(ev, fh)
     for kind in ("cold", "poiseuille", "learned"):
-        e = ev[kind]
-        err = max(e["drag_rel_err"]) if e["drag_rel_err"] else float("nan")
-        _log(f"{kind}: mean steps to r<{a.tol:g}: {np.mean(e['steps']):.0f}; all drags steady (1e-4) at "
-             f"{e['drag_steady_wall_s']} s; max drag rel err {err:.2e}")
+        r = ev[kind]
+        err = max(r["drag_rel_err"]) if r["drag_rel_err"] else float("nan")
+        _log(f"{kind}: mean steps to r<{a.tol:g}: {np.mean(r['steps']):.0f}; all drags steady (1e-4) at "
+             f"{r['drag_steady_wall_s']} s; max drag rel err {err:.2e}")
     return 0
 
 

@@ -228,3 +228,39 @@ def test_training_reduces_loss_and_infer_matches_oracle(torch_mod, lbm_mod, dtyp
         _say(f"bf16: inferred fields vs oracle output, relative L2 {e:.3e}")
         assert e <= tol
     assert (rho.cpu().numpy()[~fl] == 0).all()
+
+
+def test_augmentation_codes(torch_mod, lbm_mod):
+    """A drawn sample shifted in x (bits 0..15) or mirrored about the centre
+    line (bit 16, u_y negated) gives the loss of the same sample transformed
+    on the host and stored; equal up to the order of the loss sum."""
+    torch = torch_mod
+    base = synthetic_set(torch, 1, 31)
+    s0 = {k: v.cpu().numpy() for k, v in base.items()}
+
+    def mirror(a):
+        return a[:, ::-1, :].copy()
+
+    def roll(a):
+        return np.roll(a, 5, axis=2)
+
+    data = {"solid": np.concatenate([s0["solid"], mirror(s0["solid"]), roll(s0["solid"])]),
+            "rho": np.concatenate([s0["rho"], mirror(s0["rho"]), roll(s0["rho"])]),
+            "ux": np.concatenate([s0["ux"], mirror(s0["ux"]), roll(s0["ux"])]),
+            "uy": np.concatenate([s0["uy"], -mirror(s0["uy"]), roll(s0["uy"])])}
+    for k in ("re", "gx", "tau"):
+        data[k] = np.repeat(s0[k], 3)
+    data = {k: torch.from_numpy(np.ascontiguousarray(v)).to("cuda") for k, v in data.items()}
+    net = lbm_mod.WarmStartNet(H, W, 1, dtype="f32", ch=CH, rho_scale=0.05)
+    p = torch.from_numpy(he_params(32))
+
+    def loss(sample, code):
+        net.set_params(p)
+        idx = torch.tensor([sample], dtype=torch.int32, device="cuda")
+        aug = torch.tensor([code], dtype=torch.int32, device="cuda") if code is not None else None
+        return net.train_step(data, idx, 1e-9, want_loss=True, aug=aug)
+
+    assert loss(0, None) == loss(0, 0)
+    assert abs(loss(0, 1 << 16) - loss(1, None)) <= 1e-6 * loss(1, None)
+    assert abs(loss(0, 5) - loss(2, None)) <= 1e-6 * loss(2, None)
+    assert abs(loss(0, 5) - loss(0, None)) > 1e-4 * loss(0, None)  # the network is not shift-invariant by 5
