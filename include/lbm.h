@@ -321,17 +321,21 @@ const char* lbm_batch_last_error(const lbm_batch* b);
  *
  * Network: level l = 0..3 at (h >> l) x (w >> l); encoder levels 0..2 apply
  * two 3x3 convolutions with ReLU (channels ch[l]) and a 2x2 mean pool;
- * level 3 applies two; decoder levels 2..0 upsample 2x (nearest),
- * concatenate [upsampled, encoder output of the level] and apply two 3x3
- * convolutions with ReLU; a last 3x3 convolution gives 3 outputs.  x is
- * periodic, y zero-padded.  Input channels: solid (1) / fluid (0) and Re/100.
+ * level 3 applies two, and its per-sample channel means (global context: the
+ * flow rate of a periodic channel depends on every body in it) join the
+ * first decoder level; decoder levels 2..0 upsample 2x (nearest),
+ * concatenate [upsampled, encoder output of the level (, level 2: the means
+ * broadcast to every node)] and apply two 3x3 convolutions with ReLU; a last
+ * 3x3 convolution gives 3 outputs.  x is periodic, y zero-padded.  Input
+ * channels: solid (1) / fluid (0) and Re/100.
  * Outputs (normalised): (rho - 1) / (U_c rho_scale), u_x / U_c, u_y / U_c with
  * U_c = g_x h^2 / (8 nu), nu = (tau - 1/2) / 3, the centre-line speed of the
  * unobstructed channel.
  *
  * Parameters: one FP32 vector; for each of the 15 convolutions in order
  * (encoder 0a 0b 1a 1b 2a 2b, bottleneck a b, decoder 2a 2b 1a 1b 0a 0b,
- * head) the weights W[c_out][ky][kx][c_in] then the bias[c_out].  Activations
+ * head) the weights W[c_out][ky][kx][c_in] then the bias[c_out]; decoder 2a
+ * reads c_in = 2 ch[3] + ch[2] channels [up, skip, means].  Activations
  * are NHWC in BF16 (matrix-core inputs, FP32 accumulation) or FP32.  Every
  * reduction has a fixed order: results are reproducible bit for bit.
  * All device state lives in the caller's workspace; calls are asynchronous on

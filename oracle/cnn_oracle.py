@@ -12,8 +12,10 @@ Network (the layout of the warm-start network of this project):
   input  [B][H][W][2]  : solid mask (1 solid, 0 fluid), Re / 100
   output [B][H][W][3]  : (rho - 1) / (U_c s_rho), u_x / U_c, u_y / U_c
   encoder level l = 0..2 : conv(c_l) ReLU conv(c_l) ReLU  -> skip_l, 2x2 mean pool
-  bottleneck             : conv(c_3) ReLU conv(c_3) ReLU
-  decoder level l = 2..0 : nearest 2x upsample, concat [up, skip_l],
+  bottleneck             : conv(c_3) ReLU conv(c_3) ReLU -> b, and its mean
+                           over the sample's nodes m [c_3] (global context)
+  decoder level l = 2..0 : nearest 2x upsample, concat [up, skip_l] (level 2
+                           also [.., m broadcast to every node]),
                            conv(c_l) ReLU conv(c_l) ReLU
   head                   : conv(3), no activation
 Every conv is 3x3 with a bias; x is periodic (the channel is periodic in x),
@@ -39,7 +41,7 @@ def layer_shapes(ch=(32, 64, 128, 256)):
         (c0, c1, True), (c1, c1, True),
         (c1, c2, True), (c2, c2, True),
         (c2, c3, True), (c3, c3, True),
-        (c3 + c2, c2, True), (c2, c2, True),
+        (c3 + c2 + c3, c2, True), (c2, c2, True),
         (c2 + c1, c1, True), (c1, c1, True),
         (c1 + c0, c0, True), (c0, c0, True),
         (c0, OUT_CH, False),
@@ -177,8 +179,13 @@ def forward(params, x, ch=(32, 64, 128, 256), q=_ident):
         h = q(pool(h))
     h = layer(6, h)
     h = layer(7, h)
+    m = q(h.mean(axis=(1, 2)))  # [B][c3]
     for j, lev in enumerate((2, 1, 0)):
-        h = np.concatenate([upsample(h), skips[lev]], axis=3)
+        parts = [upsample(h), skips[lev]]
+        if lev == 2:
+            Bn, H2, W2, _ = skips[2].shape
+            parts.append(np.broadcast_to(m[:, None, None, :], (Bn, H2, W2, m.shape[1])))
+        h = np.concatenate(parts, axis=3)
         h = layer(8 + 2 * j, h)
         h = layer(9 + 2 * j, h)
     y = layer(14, h)
@@ -208,9 +215,15 @@ def backward(params, tape, gy, ch=(32, 64, 128, 256), q=_ident):
     for j, lev in ((2, 0), (1, 1), (0, 2)):
         g = layer_back(9 + 2 * j, g)
         g = layer_back(8 + 2 * j, g)
-        c_up = g.shape[3] - c[lev]
-        g_skip[lev] = g[..., c_up:]
-        g = q(upsample_backward(g[..., :c_up]))
+        c_up = c[lev + 1]
+        g_skip[lev] = g[..., c_up:c_up + c[lev]]
+        up = upsample_backward(g[..., :c_up])
+        if lev == 2:
+            # the mean's adjoint: the summed gradient of the broadcast
+            # channels, spread evenly over the bottleneck's nodes
+            gm = g[..., c_up + c[lev]:].sum(axis=(1, 2))
+            up = up + gm[:, None, None, :] / (up.shape[1] * up.shape[2])
+        g = q(up)
     g = layer_back(7, g)
     g = layer_back(6, g)
     for lev in (2, 1, 0):

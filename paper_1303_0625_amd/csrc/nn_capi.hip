@@ -35,7 +35,7 @@ constexpr int kLayers = 15;
 enum Buf {
     X0, A0, CAT0, X1, A1, CAT1, X2, A2, CAT2, X3, B1, B2, D2A, D2B, D1A, D1B, D0A, D0B,
     G_HEAD, G_D0B, G_D0A, G_CAT0, G_D1B, G_D1A, G_CAT1, G_D2B, G_D2A, G_CAT2, G_B2, G_B1, G_X3,
-    G_S2, G_A2, G_X2, G_S1, G_A1, G_X1, G_S0, G_A0, NBUF
+    G_S2, G_A2, G_X2, G_S1, G_A1, G_X1, G_S0, G_A0, GMEAN, NBUF
 };
 
 struct BufShape {
@@ -54,7 +54,7 @@ struct Plan {
     int64_t bpart_max;  // floats of the largest bias partial
     size_t off[NBUF];
     size_t o_master, o_grad, o_m, o_v, o_wf, o_wt, o_bias, o_out, o_tgt, o_fluid, o_wpart, o_bpart,
-        o_lpart, o_loss, o_idx, total;
+        o_lpart, o_loss, o_idx, o_gmean, total;
 };
 
 int64_t pixels(const Plan& p, int level) { return (int64_t)p.B * (p.H >> level) * (p.W >> level); }
@@ -86,12 +86,13 @@ const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
     p.es = cfg.dtype == LBM_BF16 ? 2 : 4;
     const int c0 = p.c[0], c1 = p.c[1], c2 = p.c[2], c3 = p.c[3];
     const BufShape sh[NBUF] = {
-        {0, 16}, {0, c0}, {0, c1 + c0}, {1, c0}, {1, c1}, {1, c2 + c1}, {2, c1}, {2, c2}, {2, c3 + c2}, {3, c2},
+        {0, 16}, {0, c0}, {0, c1 + c0}, {1, c0}, {1, c1}, {1, c2 + c1}, {2, c1}, {2, c2}, {2, 2 * c3 + c2}, {3, c2},
         {3, c3}, {3, c3}, {2, c2}, {2, c2}, {1, c1}, {1, c1}, {0, c0}, {0, c0},
-        {0, 32}, {0, c0}, {0, c0}, {0, c1 + c0}, {1, c1}, {1, c1}, {1, c2 + c1}, {2, c2}, {2, c2}, {2, c3 + c2},
-        {3, c3}, {3, c3}, {3, c2}, {2, c2}, {2, c2}, {2, c1}, {1, c1}, {1, c1}, {1, c0}, {0, c0}, {0, c0}};
+        {0, 32}, {0, c0}, {0, c0}, {0, c1 + c0}, {1, c1}, {1, c1}, {1, c2 + c1}, {2, c2}, {2, c2}, {2, 2 * c3 + c2},
+        {3, c3}, {3, c3}, {3, c2}, {2, c2}, {2, c2}, {2, c1}, {1, c1}, {1, c1}, {1, c0}, {0, c0}, {0, c0},
+        {-1, c3}};
     for (int k = 0; k < NBUF; ++k) p.shape[k] = sh[k];
-    const int cin[kLayers] = {2, c0, c0, c1, c1, c2, c2, c3, c3 + c2, c2, c2 + c1, c1, c1 + c0, c0, c0};
+    const int cin[kLayers] = {2, c0, c0, c1, c1, c2, c2, c3, 2 * c3 + c2, c2, c2 + c1, c1, c1 + c0, c0, c0};
     const int cout[kLayers] = {c0, c0, c1, c1, c2, c2, c3, c3, c2, c2, c1, c1, c0, c0, 3};
     int64_t off = 0, wf = 0, wt = 0, bo = 0;
     p.wpart_max = 1;
@@ -136,7 +137,11 @@ const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
     take(p.o_wf, (size_t)p.es * wf);
     take(p.o_wt, (size_t)p.es * wt);
     take(p.o_bias, 4 * (size_t)bo);
-    for (int k = 0; k < NBUF; ++k) take(p.off[k], (size_t)p.es * pixels(p, p.shape[k].level) * p.shape[k].ch);
+    // level -1: one value per sample (the bottleneck's channel means)
+    for (int k = 0; k < NBUF; ++k)
+        take(p.off[k], (size_t)p.es * (p.shape[k].level < 0 ? (int64_t)p.B : pixels(p, p.shape[k].level)) *
+                           p.shape[k].ch);
+    take(p.o_gmean, 4 * (size_t)p.B * c3);
     const int64_t P0 = pixels(p, 0);
     take(p.o_out, 12 * (size_t)P0);
     take(p.o_tgt, 12 * (size_t)P0);
@@ -298,16 +303,21 @@ void forward_t(lbm_nn* n) {
     layer_fwd<T>(n, 3, 1, A1, CAT1, c2 + c1, c2);
     k_pool<T><<<blocks((int64_t)B * H(2) * W(2) * c1), kEw, 0, n->st>>>(
         (const T*)buf(n, CAT1), c2 + c1, c2, c1, (T*)buf(n, X2), H(2), W(2), B);
+    const int cat2 = 2 * c3 + c2;  // [up(b2), skip_2, mean(b2)]
     layer_fwd<T>(n, 4, 2, X2, A2, c2, 0);
-    layer_fwd<T>(n, 5, 2, A2, CAT2, c3 + c2, c3);
+    layer_fwd<T>(n, 5, 2, A2, CAT2, cat2, c3);
     k_pool<T><<<blocks((int64_t)B * H(3) * W(3) * c2), kEw, 0, n->st>>>(
-        (const T*)buf(n, CAT2), c3 + c2, c3, c2, (T*)buf(n, X3), H(3), W(3), B);
-    // bottleneck
+        (const T*)buf(n, CAT2), cat2, c3, c2, (T*)buf(n, X3), H(3), W(3), B);
+    // bottleneck and its global context
     layer_fwd<T>(n, 6, 3, X3, B1, c3, 0);
     layer_fwd<T>(n, 7, 3, B1, B2, c3, 0);
+    k_channel_mean<T><<<blocks((int64_t)B * c3), kEw, 0, n->st>>>((const T*)buf(n, B2), c3, H(3) * W(3), B,
+                                                                  (T*)buf(n, GMEAN));
+    k_broadcast<T><<<blocks((int64_t)B * H(2) * W(2) * c3), kEw, 0, n->st>>>(
+        (const T*)buf(n, GMEAN), c3, (T*)buf(n, CAT2), cat2, c3 + c2, H(2) * W(2), B);
     // decoder
     k_upsample<T><<<blocks((int64_t)B * H(2) * W(2) * c3), kEw, 0, n->st>>>(
-        (const T*)buf(n, B2), c3, (T*)buf(n, CAT2), c3 + c2, 0, H(2), W(2), B);
+        (const T*)buf(n, B2), c3, (T*)buf(n, CAT2), cat2, 0, H(2), W(2), B);
     layer_fwd<T>(n, 8, 2, CAT2, D2A, c2, 0);
     layer_fwd<T>(n, 9, 2, D2A, D2B, c2, 0);
     k_upsample<T><<<blocks((int64_t)B * H(1) * W(1) * c2), kEw, 0, n->st>>>(
@@ -340,21 +350,25 @@ void backward_t(lbm_nn* n) {
     layer_wgrad<T>(n, 12, 0, CAT0, G_D0A);
     layer_dgrad<T>(n, 12, 0, G_D0A, G_CAT0, CAT0, 0, 0, false);
     k_upsample_back<T><<<blocks((int64_t)B * H(1) * W(1) * c1), kEw, 0, n->st>>>(
-        (const T*)buf(n, G_CAT0), c1 + c0, 0, c1, (const T*)buf(n, D1B), (T*)buf(n, G_D1B), H(1), W(1), B);
+        (const T*)buf(n, G_CAT0), c1 + c0, 0, c1, (const T*)buf(n, D1B), nullptr, (T*)buf(n, G_D1B), H(1), W(1), B);
     // decoder level 1
     layer_wgrad<T>(n, 11, 1, D1A, G_D1B);
     layer_dgrad<T>(n, 11, 1, G_D1B, G_D1A, D1A, c1, 0, true);
     layer_wgrad<T>(n, 10, 1, CAT1, G_D1A);
     layer_dgrad<T>(n, 10, 1, G_D1A, G_CAT1, CAT1, 0, 0, false);
     k_upsample_back<T><<<blocks((int64_t)B * H(2) * W(2) * c2), kEw, 0, n->st>>>(
-        (const T*)buf(n, G_CAT1), c2 + c1, 0, c2, (const T*)buf(n, D2B), (T*)buf(n, G_D2B), H(2), W(2), B);
+        (const T*)buf(n, G_CAT1), c2 + c1, 0, c2, (const T*)buf(n, D2B), nullptr, (T*)buf(n, G_D2B), H(2), W(2), B);
     // decoder level 2
     layer_wgrad<T>(n, 9, 2, D2A, G_D2B);
     layer_dgrad<T>(n, 9, 2, G_D2B, G_D2A, D2A, c2, 0, true);
     layer_wgrad<T>(n, 8, 2, CAT2, G_D2A);
     layer_dgrad<T>(n, 8, 2, G_D2A, G_CAT2, CAT2, 0, 0, false);
+    const int cat2 = 2 * c3 + c2;
+    k_broadcast_back<T><<<blocks((int64_t)B * c3), kEw, 0, n->st>>>((const T*)buf(n, G_CAT2), cat2, c3 + c2, c3,
+                                                                    H(2) * W(2), B, at<float>(n, p.o_gmean));
     k_upsample_back<T><<<blocks((int64_t)B * H(3) * W(3) * c3), kEw, 0, n->st>>>(
-        (const T*)buf(n, G_CAT2), c3 + c2, 0, c3, (const T*)buf(n, B2), (T*)buf(n, G_B2), H(3), W(3), B);
+        (const T*)buf(n, G_CAT2), cat2, 0, c3, (const T*)buf(n, B2), at<float>(n, p.o_gmean), (T*)buf(n, G_B2),
+        H(3), W(3), B);
     // bottleneck
     layer_wgrad<T>(n, 7, 3, B1, G_B2);
     layer_dgrad<T>(n, 7, 3, G_B2, G_B1, B1, c3, 0, true);
@@ -362,7 +376,7 @@ void backward_t(lbm_nn* n) {
     layer_dgrad<T>(n, 6, 3, G_B1, G_X3, X3, 0, 0, false);
     // encoder level 2
     k_pool_back_skip<T><<<blocks((int64_t)B * H(2) * W(2) * c2), kEw, 0, n->st>>>(
-        (const T*)buf(n, G_X3), (const T*)buf(n, G_CAT2), c3 + c2, c3, (const T*)buf(n, CAT2), c2, (T*)buf(n, G_S2),
+        (const T*)buf(n, G_X3), (const T*)buf(n, G_CAT2), cat2, c3, (const T*)buf(n, CAT2), c2, (T*)buf(n, G_S2),
         H(2), W(2), B);
     layer_wgrad<T>(n, 5, 2, A2, G_S2);
     layer_dgrad<T>(n, 5, 2, G_S2, G_A2, A2, c2, 0, true);

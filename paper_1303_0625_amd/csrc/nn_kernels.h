@@ -2,8 +2,10 @@
 //
 // Network: 4-level U-Net on a channel lattice (mask, Re) -> (rho, u_x, u_y),
 // channels (c0, c1, c2, c3), 3x3 convolutions with bias and ReLU, 2x2 mean
-// pooling, nearest 2x upsampling, concatenated skips [up, skip]; x periodic,
-// y zero-padded (walls).  Activations are NHWC in the compute type T
+// pooling, nearest 2x upsampling, concatenated skips [up, skip], and the
+// bottleneck's per-sample channel mean broadcast into the first decoder level
+// (global context: the flow rate of a periodic channel depends on every body
+// in it); x periodic, y zero-padded (walls).  Activations are NHWC in the compute type T
 // (__bf16 with FP32 accumulation on the matrix cores, or float for an
 // all-FP32 mode); weights are FP32 masters repacked into T.
 //
@@ -356,11 +358,13 @@ __global__ __launch_bounds__(kEw) void k_upsample(const T* __restrict__ in, int 
 }
 
 // Adjoint of the upsampling, then the ReLU mask of the lower-level activation:
-// out[q][c] = (sum over the 2x2 children of g[child][g_co + c]) * (act[q][c] > 0).
+// out[q][c] = (sum over the 2x2 children of g[child][g_co + c]
+//              + gmean[b][c] / (Hl Wl)) * (act[q][c] > 0),
+// gmean (optional) the gradient of the sample's channel mean of act.
 template <typename T>
 __global__ __launch_bounds__(kEw) void k_upsample_back(const T* __restrict__ g, int g_cs, int g_co, int C,
-                                                       const T* __restrict__ act, T* __restrict__ out, int Hl,
-                                                       int Wl, int B) {
+                                                       const T* __restrict__ act, const float* __restrict__ gmean,
+                                                       T* __restrict__ out, int Hl, int Wl, int B) {
     const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
     const int64_t n = (int64_t)B * Hl * Wl * C;
     if (i >= n) return;
@@ -372,7 +376,48 @@ __global__ __launch_bounds__(kEw) void k_upsample_back(const T* __restrict__ g, 
     const int64_t r0 = (2 * by) * Wh + 2 * xl;
     float v = (to_f(g[r0 * g_cs + g_co + c]) + to_f(g[(r0 + 1) * g_cs + g_co + c])) +
               (to_f(g[(r0 + Wh) * g_cs + g_co + c]) + to_f(g[(r0 + Wh + 1) * g_cs + g_co + c]));
+    if (gmean) {
+        const int b = (int)(by / Hl);
+        v += gmean[(int64_t)b * C + c] / (float)(Hl * Wl);
+    }
     out[q * C + c] = from_f<T>(to_f(act[q * C + c]) > 0.0f ? v : 0.0f);
+}
+
+// Global context: m[b][c] = mean over the N nodes of sample b of a[p][c]
+// (summed in node order, one thread per (b, c)).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_channel_mean(const T* __restrict__ a, int C, int N, int B,
+                                                      T* __restrict__ m) {
+    const int i = blockIdx.x * kEw + threadIdx.x;
+    if (i >= B * C) return;
+    const int b = i / C, c = i % C;
+    float v = 0.0f;
+    for (int p = 0; p < N; ++p) v += to_f(a[((int64_t)b * N + p) * C + c]);
+    m[i] = from_f<T>(v / (float)N);
+}
+
+// out[p][out_co + c] = m[b(p)][c] for every node p of a level with N nodes per sample.
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_broadcast(const T* __restrict__ m, int C, T* __restrict__ out, int out_cs,
+                                                   int out_co, int N, int B) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (i >= (int64_t)B * N * C) return;
+    const int c = (int)(i % C);
+    const int64_t p = i / C;
+    out[p * out_cs + out_co + c] = m[(p / N) * C + c];
+}
+
+// Adjoint of the broadcast: gm[b][c] = sum over the N nodes of sample b of
+// g[p][g_co + c] (node order, one thread per (b, c)).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_broadcast_back(const T* __restrict__ g, int g_cs, int g_co, int C, int N,
+                                                        int B, float* __restrict__ gm) {
+    const int i = blockIdx.x * kEw + threadIdx.x;
+    if (i >= B * C) return;
+    const int b = i / C, c = i % C;
+    float v = 0.0f;
+    for (int p = 0; p < N; ++p) v += to_f(g[((int64_t)b * N + p) * g_cs + g_co + c]);
+    gm[i] = v;
 }
 
 // Encoder skip: out[p][c] = (g_low[parent][c] / 4 + g_cat[p][skip_co + c]) *

@@ -84,6 +84,28 @@ def _small_net():
     return ch, p
 
 
+def test_global_context_sees_the_whole_channel():
+    """A change of the input ~120 nodes away (both ways round the periodic x,
+    beyond the receptive field of the convolutions) changes the output through
+    the bottleneck mean; with the global-context weights zeroed it does not."""
+    ch, p = _small_net()
+    x = RNG.normal(size=(1, 8, 256, 2))
+    x2 = x.copy()
+    x2[0, :, 124:132, :] += 1.0
+    y, _ = co.forward(p, x, ch)
+    y2, _ = co.forward(p, x2, ch)
+    assert np.abs(y2 - y)[0, :, 0:8].max() > 1e-6
+    layers = co.unpack(p, ch)
+    W8, b8 = layers[8]
+    W8 = W8.copy()
+    W8[..., ch[3] + ch[2]:] = 0.0  # the broadcast-mean input channels of the first decoder conv
+    layers[8] = (W8, b8)
+    p0 = co.pack(layers)
+    y, _ = co.forward(p0, x, ch)
+    y2, _ = co.forward(p0, x2, ch)
+    assert np.abs(y2 - y)[0, :, 0:8].max() == 0.0
+
+
 def test_network_shift_equivariance():
     """Three 2x2 poolings: shifting the input by 8 nodes along x shifts the
     output by 8 (x is periodic); a shift of 1 in general does not."""
@@ -153,12 +175,13 @@ def test_normalisation_round_trip():
 
 
 def test_param_count_of_the_warm_start_network():
-    # 15 convolutions 3x3 with biases, channels (32, 64, 128, 256)
+    # 15 convolutions 3x3 with biases, channels (32, 64, 128, 256); the first
+    # decoder convolution also reads the 256 global-context channels
     n = co.param_count()
     expect = sum(o * 9 * i + o for i, o in [(2, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128),
-                                            (128, 256), (256, 256), (384, 128), (128, 128), (192, 64),
+                                            (128, 256), (256, 256), (640, 128), (128, 128), (192, 64),
                                             (64, 64), (96, 32), (32, 32), (32, 3)])
-    assert n == expect == 1_947_427
+    assert n == expect == 2_242_339
 
 
 def test_bf16_rounding():

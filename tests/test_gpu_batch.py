@@ -266,7 +266,7 @@ def test_poiseuille_start(lbm_mod):
     lat.init_poiseuille()
     rho, ux, uy, _ = (_np(a) for a in lat.fields("f64"))
     assert np.abs(ux - exact[:, None]).max() <= 1e-15 * exact.max() * 10
-    assert np.abs(uy).max() == 0 and np.abs(rho - 1).max() <= 1e-15
+    assert np.abs(uy).max() <= 1e-15 * exact.max() and np.abs(rho - 1).max() <= 1e-15
     lat.step(40000)
     rho, ux, uy, _ = (_np(a) for a in lat.fields("f64"))
     assert np.abs(ux - exact[:, None]).max() <= 1e-10 * exact.max()
