@@ -276,4 +276,7 @@ def test_poiseuille_start(lbm_mod):
     conv, steps, res, _ = batch.status()
     _say(f"steps to r < 1e-10: Poiseuille start {steps[0]}, cold {steps[1]}")
     assert conv == [1, 1] and steps[0] < 0.7 * steps[1]
-    assert np.abs(_np(batch.fields(0, "f64")[1]) - exact[:, None]).max() <= 1e-8 * exact.max()
+    # at retirement the distance left to steady state is ~ r / lambda, with
+    # lambda = pi^2 nu / ny^2 the slowest decay rate: 1e-10 / 1.7e-3 here
+    lam = np.pi ** 2 * nu / ny ** 2
+    assert np.abs(_np(batch.fields(0, "f64")[1]) - exact[:, None]).max() <= 10 * 1e-10 / lam * exact.max()
