@@ -114,7 +114,7 @@ def init_params(seed, ch=CH):
     rng = np.random.default_rng(seed)
     c0, c1, c2, c3 = ch
     shapes = [(2, c0), (c0, c0), (c0, c1), (c1, c1), (c1, c2), (c2, c2), (c2, c3), (c3, c3),
-              (c3 + c2, c2), (c2, c2), (c2 + c1, c1), (c1, c1), (c1 + c0, c0), (c0, c0), (c0, 3)]
+              (2 * c3 + c2, c2), (c2, c2), (c2 + c1, c1), (c1, c1), (c1 + c0, c0), (c0, c0), (c0, 3)]
     out = []
     for k, (ci, co) in enumerate(shapes):
         w = rng.normal(size=co * 9 * ci) * np.sqrt(2.0 / (9 * ci))
