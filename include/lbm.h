@@ -407,6 +407,20 @@ lbm_status lbm_nn_eval(lbm_nn* nn, const uint8_t* d_solid, const float* d_rho, c
 lbm_status lbm_nn_infer(lbm_nn* nn, const uint8_t* d_solid, const double* d_re, const double* d_gx,
                         const double* d_tau, int32_t batch, float* d_rho, float* d_ux, float* d_uy);
 
+/* Make warm-start fields safe to start from, in place, for n_fields channels
+ * of nx x ny (nx even, both <= 2048): owner map u8 and rho, u_x, u_y FP32,
+ * [n_fields][ny][nx] device memory, fluid nodes only.  rho is shifted to mean
+ * rho0 (the mass of a cold start, so the steady drag, which balances g_x sum
+ * rho, is the same); u_x is scaled column by column to equal fluxes
+ * sum_y rho u_x (continuity), u_y shifted row by row to zero flux.  A lattice
+ * started at equilibrium from fields without this carries a staggered
+ * momentum sum_x (-1)^x rho u_x that changes sign every step and is never
+ * damped (it makes the force on a body alternate; a residual over an even
+ * interval does not see it).  Asynchronous on hip_stream; LBM_EINVAL on bad
+ * sizes. */
+lbm_status lbm_warm_project(int32_t nx, int32_t ny, int32_t n_fields, const uint8_t* d_owner, float* d_rho,
+                            float* d_ux, float* d_uy, double rho0, void* hip_stream);
+
 /* Release the network (not the caller's buffers).  NULL is ignored. */
 void lbm_nn_destroy(lbm_nn* nn);
 

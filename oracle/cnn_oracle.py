@@ -280,3 +280,22 @@ def fields_from_output(y, solid, uc, rho_scale):
     ux = np.where(fl, y[..., 1] * uc, 0.0)
     uy = np.where(fl, y[..., 2] * uc, 0.0)
     return rho, ux, uy
+
+
+def warm_project(solid, rho, ux, uy, rho0=1.0):
+    """Warm-start projection of fields [ny][nx] (fluid nodes only): rho
+    shifted to mean rho0; u_x of every column scaled so that its flux
+    sum_y rho u_x equals the mean column flux; u_y of every row shifted so that
+    its flux sum_x rho u_y is zero.  Returns new arrays."""
+    fl = np.asarray(solid) == 0
+    rho = np.where(fl, np.asarray(rho, dtype=np.float64), 0.0)
+    rho = np.where(fl, rho + (rho0 - rho[fl].mean()), 0.0)
+    ux = np.where(fl, np.asarray(ux, dtype=np.float64), 0.0)
+    uy = np.where(fl, np.asarray(uy, dtype=np.float64), 0.0)
+    J = (rho * ux).sum(axis=0)
+    scale = np.where(J != 0.0, J.mean() / np.where(J != 0.0, J, 1.0), 1.0)
+    ux = ux * scale[None, :]
+    K = (rho * uy).sum(axis=1)
+    R = rho.sum(axis=1)
+    uy = np.where(fl, uy - np.where(R > 0, K / np.where(R > 0, R, 1.0), 0.0)[:, None], 0.0)
+    return rho, ux, uy

@@ -674,6 +674,25 @@ lbm_status lbm_nn_infer(lbm_nn* n, const uint8_t* d_solid, const double* d_re, c
     return sync_check(n);
 }
 
+lbm_status lbm_warm_project(int32_t nx, int32_t ny, int32_t n_fields, const uint8_t* d_owner, float* d_rho,
+                            float* d_ux, float* d_uy, double rho0, void* hip_stream) {
+    if (nx < 2 || ny < 1 || nx > kProjMax || ny > kProjMax || (nx & 1) || n_fields < 1) {
+        nn_set_err(g_nn_err, "nx must be even and in [2, %d], ny in [1, %d], n_fields >= 1", kProjMax, kProjMax);
+        return LBM_EINVAL;
+    }
+    if (!d_owner || !d_rho || !d_ux || !d_uy || !(rho0 > 0.0)) {
+        nn_set_err(g_nn_err, "field pointers must not be NULL and rho0 must be > 0");
+        return LBM_EINVAL;
+    }
+    k_project<<<n_fields, kEw, 0, (hipStream_t)hip_stream>>>(d_owner, d_rho, d_ux, d_uy, nx, ny, rho0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        nn_set_err(g_nn_err, "projection launch failed: %s", hipGetErrorString(e));
+        return LBM_EDEVICE;
+    }
+    return LBM_OK;
+}
+
 void lbm_nn_destroy(lbm_nn* n) {
     if (!n) return;
     (void)hipStreamSynchronize(n->st);

@@ -536,6 +536,85 @@ __global__ __launch_bounds__(kEw) void k_unpack_fields(const float* __restrict__
     uy[p] = fl ? (float)((double)y[3 * p + 2] * uc) : 0.0f;
 }
 
+// ------------------------------------------------------------------ warm-start projection
+// Projection of a warm-start field of one channel (one workgroup per sample,
+// fluid nodes only): rho shifted so that the mean density is rho0 (the mass
+// of the cold start), u_x of column x scaled so that its flux
+// J(x) = sum_y rho u_x equals the mean flux over the columns, u_y of row y
+// shifted so that its flux K(y) = sum_x rho u_y is zero.  Equal column fluxes
+// (continuity) give zero staggered momentum sum_x (-1)^x J(x) for even nx,
+// zero row fluxes zero sum_y (-1)^y K(y): the start then excites no
+// period-2 staggered mode, which no relaxation would damp.  Sums in double,
+// in a fixed order.
+constexpr int kProjMax = 2048;  // largest nx and ny of a projected field (LDS: 52 KB)
+
+__global__ __launch_bounds__(kEw) void k_project(const uint8_t* __restrict__ own, float* __restrict__ rho,
+                                                 float* __restrict__ ux, float* __restrict__ uy, int nx, int ny,
+                                                 double rho0) {
+    __shared__ double colsum[kProjMax];
+    __shared__ double rowsum[kProjMax];
+    __shared__ double rowrho[kProjMax];
+    __shared__ double red[2][kEw];
+    const int64_t base = (int64_t)blockIdx.x * nx * ny;
+    const uint8_t* o = own + base;
+    float* r = rho + base;
+    float* u = ux + base;
+    float* v = uy + base;
+    // mass
+    double m = 0.0, nf = 0.0;
+    for (int64_t i = threadIdx.x; i < (int64_t)nx * ny; i += kEw)
+        if (o[i] == 0) {
+            m += (double)r[i];
+            nf += 1.0;
+        }
+    red[0][threadIdx.x] = m;
+    red[1][threadIdx.x] = nf;
+    __syncthreads();
+    for (int off = kEw / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    const double shift = red[1][0] > 0.0 ? rho0 - red[0][0] / red[1][0] : 0.0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < (int64_t)nx * ny; i += kEw)
+        if (o[i] == 0) r[i] = (float)((double)r[i] + shift);
+    __syncthreads();
+    // column fluxes of u_x, row fluxes of u_y
+    for (int x = threadIdx.x; x < nx; x += kEw) {
+        double j = 0.0;
+        for (int y = 0; y < ny; ++y) {
+            const int64_t i = (int64_t)y * nx + x;
+            if (o[i] == 0) j += (double)r[i] * (double)u[i];
+        }
+        colsum[x] = j;
+    }
+    for (int y = threadIdx.x; y < ny; y += kEw) {
+        double k = 0.0, rr = 0.0;
+        for (int x = 0; x < nx; ++x) {
+            const int64_t i = (int64_t)y * nx + x;
+            if (o[i] == 0) {
+                k += (double)r[i] * (double)v[i];
+                rr += (double)r[i];
+            }
+        }
+        rowsum[y] = k;
+        rowrho[y] = rr;
+    }
+    __syncthreads();
+    double jm = 0.0;
+    for (int x = 0; x < nx; ++x) jm += colsum[x];
+    jm /= (double)nx;
+    for (int64_t i = threadIdx.x; i < (int64_t)nx * ny; i += kEw) {
+        if (o[i] != 0) continue;
+        const int y = (int)(i / nx), x = (int)(i - (int64_t)y * nx);
+        if (colsum[x] != 0.0) u[i] = (float)((double)u[i] * (jm / colsum[x]));
+        if (rowrho[y] > 0.0) v[i] = (float)((double)v[i] - rowsum[y] / rowrho[y]);
+    }
+}
+
 // ------------------------------------------------------------------ loss
 // Masked mean squared error over fluid nodes and 3 channels.  Stage 1: block
 // partial sums {sum (y - t)^2, fluid count}; stage 2 (one thread) sums the

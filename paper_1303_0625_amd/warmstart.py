@@ -182,26 +182,38 @@ def load_weights(path):
 
 
 # --------------------------------------------------------------------- evaluation
-def start_batch(cases, kind, net=None, dtype="f32"):
+def start_batch(cases, kind, net=None, dtype="f32", project=True):
     """A LatticeBatch of the cases started cold, from the exact Poiseuille
-    flow, or from the network's fields."""
+    flow, or from the network's fields.  Warm-start fields are projected
+    (lbm_warm_project: the cold start's mass, equal column fluxes, zero row
+    fluxes) unless project=False, so that they excite no undamped staggered
+    momentum."""
     import torch
 
     b = lbm.LatticeBatch(cases, dtype=dtype)
-    if kind == "poiseuille":
-        for k in range(len(cases)):
-            b.init_poiseuille(k)
-    elif kind == "learned":
-        dev = b.workspace.device
-        for k0 in range(0, len(cases), net.max_batch):
-            part = cases[k0:k0 + net.max_batch]
-            solid = torch.stack([b.fields(k0 + j, "f32", owner=True)[3] for j in range(len(part))]) != 0
+    if kind == "cold":
+        return b
+    dev = b.workspace.device
+    step = net.max_batch if net is not None else 16
+    for k0 in range(0, len(cases), step):
+        part = cases[k0:k0 + step]
+        own = torch.stack([b.fields(k0 + j, "f32", owner=True)[3] for j in range(len(part))]).contiguous()
+        if kind == "poiseuille":
+            fields = []
+            for j in range(len(part)):
+                b.init_poiseuille(k0 + j)
+                fields.append(b.fields(k0 + j, "f32"))
+            rho, ux, uy = (torch.stack([f[i] for f in fields]).contiguous() for i in range(3))
+        else:
             re = torch.tensor([c["Re"] for c in part], dtype=torch.float64, device=dev)
             gx = torch.tensor([c["gx"] for c in part], dtype=torch.float64, device=dev)
             tau = torch.tensor([c["tau"] for c in part], dtype=torch.float64, device=dev)
-            rho, ux, uy = net.infer(solid.to(torch.uint8).contiguous(), re, gx, tau)
-            for j in range(len(part)):
-                b.init_fields(k0 + j, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
+            rho, ux, uy = net.infer((own != 0).to(torch.uint8).contiguous(), re, gx, tau)
+        if project:
+            lbm.warm_project(own, rho, ux, uy, rho0=float(part[0].get("rho0", 1.0)))
+        for j in range(len(part)):
+            b.init_fields(k0 + j, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
+    torch.cuda.synchronize()
     return b
 
 

@@ -264,3 +264,29 @@ def test_augmentation_codes(torch_mod, lbm_mod):
     assert abs(loss(0, 1 << 16) - loss(1, None)) <= 1e-6 * loss(1, None)
     assert abs(loss(0, 5) - loss(2, None)) <= 1e-6 * loss(2, None)
     assert abs(loss(0, 5) - loss(0, None)) > 1e-4 * loss(0, None)  # the network is not shift-invariant by 5
+
+
+def test_warm_project_matches_oracle(torch_mod, lbm_mod):
+    torch = torch_mod
+    rng = np.random.default_rng(41)
+    n, ny, nx = 3, 32, 64
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    solid = np.zeros((n, ny, nx), np.uint8)
+    for k in range(n):
+        solid[k][(xx - rng.uniform(10, 50)) ** 2 + (yy - rng.uniform(8, 24)) ** 2 <= rng.uniform(9, 36)] = 1
+    rho = (1 + 1e-3 * rng.normal(size=solid.shape)).astype(np.float32)
+    ux = (0.02 + 0.005 * rng.normal(size=solid.shape)).astype(np.float32)
+    uy = (0.003 * rng.normal(size=solid.shape)).astype(np.float32)
+    tens = [torch.from_numpy(a).to("cuda") for a in (solid, rho, ux, uy)]
+    lbm_mod.warm_project(*tens, rho0=1.0)
+    torch.cuda.synchronize()
+    for k in range(n):
+        r, u, v = co.warm_project(solid[k], rho[k], ux[k], uy[k], 1.0)
+        fl = solid[k] == 0
+        g = [t[k].cpu().numpy().astype(np.float64) for t in tens[1:]]
+        assert np.abs(g[0][fl] - r[fl]).max() <= 2e-7
+        assert np.abs(g[1][fl] - u[fl]).max() <= 1e-6 * np.abs(u).max()
+        assert np.abs(g[2][fl] - v[fl]).max() <= 1e-6 * np.abs(uy[k]).max()
+        # the staggered column flux of the projected field vanishes
+        J = (g[0] * g[1] * fl).sum(axis=0)
+        assert abs(((-1.0) ** np.arange(nx) * J).sum()) <= 1e-5 * np.abs(J).max()
