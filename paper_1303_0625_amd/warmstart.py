@@ -36,19 +36,19 @@ def _log(msg):
 
 
 # --------------------------------------------------------------------- solving
-def solve(batch, tol, check, cap, chunk=20000, log=_log, drag_every_check=False, t0=None):
+def solve(batch, tol, check, cap, chunk=20000, log=_log, record=False, t0=None, step0=0):
     """Advance a LatticeBatch until every case retires (r < tol) or `cap`
-    steps.  With drag_every_check, one interval per call and the drag of every
-    case recorded after each check: returns (history [(wall_s, step, drags)],
-    wall seconds)."""
+    steps.  With record, one check interval per call and after each check the
+    drag and residual of every case: returns (history
+    [(wall_s, step0 + step, drags, residuals)], wall seconds)."""
     t0 = time.perf_counter() if t0 is None else t0
     hist = []
     last = time.perf_counter()
     while batch.t < cap:
-        if drag_every_check:
+        if record:
             done = batch.run(check, tol, check)
-            conv, _, _, drag = batch.status()
-            hist.append((time.perf_counter() - t0, batch.t, [d[0] for d in drag]))
+            conv, _, res, drag = batch.status()
+            hist.append((time.perf_counter() - t0, step0 + batch.t, [d[0] for d in drag], list(res)))
         else:
             done = batch.run(min(chunk, cap - batch.t), tol, check)
             conv = batch.status()[0]
@@ -182,12 +182,13 @@ def load_weights(path):
 
 
 # --------------------------------------------------------------------- evaluation
-def start_batch(cases, kind, net=None, dtype="f32", project=True):
+def start_batch(cases, kind, net=None, dtype="f32", project=True, fields=None):
     """A LatticeBatch of the cases started cold, from the exact Poiseuille
-    flow, or from the network's fields.  Warm-start fields are projected
-    (lbm_warm_project: the cold start's mass, equal column fluxes, zero row
-    fluxes) unless project=False, so that they excite no undamped staggered
-    momentum."""
+    flow ("poiseuille"), from the network ("learned"), or from given fields
+    (rho, ux, uy [n][ny][nx] float32, "fields").  Warm-start fields are
+    projected (lbm_warm_project: the cold start's mass, equal column fluxes,
+    zero row fluxes) unless project=False, so that they excite no undamped
+    staggered momentum."""
     import torch
 
     b = lbm.LatticeBatch(cases, dtype=dtype)
@@ -199,11 +200,13 @@ def start_batch(cases, kind, net=None, dtype="f32", project=True):
         part = cases[k0:k0 + step]
         own = torch.stack([b.fields(k0 + j, "f32", owner=True)[3] for j in range(len(part))]).contiguous()
         if kind == "poiseuille":
-            fields = []
+            fl = []
             for j in range(len(part)):
                 b.init_poiseuille(k0 + j)
-                fields.append(b.fields(k0 + j, "f32"))
-            rho, ux, uy = (torch.stack([f[i] for f in fields]).contiguous() for i in range(3))
+                fl.append(b.fields(k0 + j, "f32"))
+            rho, ux, uy = (torch.stack([f[i] for f in fl]).contiguous() for i in range(3))
+        elif kind == "fields":
+            rho, ux, uy = (f[k0:k0 + len(part)].clone().contiguous() for f in fields)
         else:
             re = torch.tensor([c["Re"] for c in part], dtype=torch.float64, device=dev)
             gx = torch.tensor([c["gx"] for c in part], dtype=torch.float64, device=dev)
@@ -217,14 +220,30 @@ def start_batch(cases, kind, net=None, dtype="f32", project=True):
     return b
 
 
+def all_fields(b, n):
+    """rho, ux, uy [n][ny][nx] float32 of a batch's cases (at retirement)."""
+    import torch
+
+    fl = [b.fields(k, "f32") for k in range(n)]
+    return [torch.stack([f[i] for f in fl]).contiguous() for i in range(3)]
+
+
+def first_below(hist, k, tol):
+    """(step, wall) of the first check at which case k's residual is below tol."""
+    for wall, step, _, res in hist:
+        if 0 <= res[k] < tol:
+            return step, wall
+    return None
+
+
 def steady_time(hist, d_inf, rel=1e-4):
     """Per case, the first (step, wall) after which |D - D_inf| <= rel |D_inf|
     at every later check; None if never."""
-    n = len(d_inf)
-    out = [None] * n
-    for k in range(n):
+    out = [None] * len(d_inf)
+    for k in range(len(d_inf)):
         ok_from = None
-        for wall, step, drags in hist:
+        for rec in hist:
+            wall, step, drags = rec[0], rec[1], rec[2]
             good = abs(drags[k] - d_inf[k]) <= rel * abs(d_inf[k])
             if good and ok_from is None:
                 ok_from = (step, wall)
@@ -234,36 +253,68 @@ def steady_time(hist, d_inf, rel=1e-4):
     return out
 
 
-def evaluate(cases, net, tol=1e-8, check=100, cap=2_000_000, kinds=("cold", "poiseuille", "learned"), log=_log):
-    """Solve the held-out cases from each start; per start: steps to r < tol,
-    steps and wall time until every drag stays within 1e-4 of the cold run's
-    converged drag, and the drags at convergence."""
+def run_start(cases, kind, net, tol_ref, check, cap, switch_tol=1e-5, log=_log):
+    """One start solved to tol_ref with per-check records.  "learned_f16":
+    the learned start with FP16-offset storage until every case has r below
+    switch_tol, then FP32 from those (projected) fields."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if kind != "learned_f16":
+        b = start_batch(cases, kind, net)
+        hist, _ = solve(b, tol_ref, check, cap, log=log, record=True, t0=t0)
+        st = b.status()
+        del b
+        return hist, st, time.perf_counter() - t0, None
+    b16 = start_batch(cases, "learned", net, dtype="f16")
+    hist, _ = solve(b16, switch_tol, check, cap, log=log, record=True, t0=t0)
+    switch = b16.t
+    fields = all_fields(b16, len(cases))
+    del b16
+    b = start_batch(cases, "fields", fields=fields)
+    h2, _ = solve(b, tol_ref, check, cap - switch, log=log, record=True, t0=t0, step0=switch)
+    st = b.status()
+    del b
+    return hist + h2, st, time.perf_counter() - t0, switch
+
+
+def evaluate(cases, net, tol=1e-8, tol_ref=1e-11, check=100, cap=4_000_000,
+             kinds=("cold", "poiseuille", "learned", "learned_f16"), log=_log):
+    """Solve the held-out cases from each start to r < tol_ref.  The cold run
+    gives the steady drag D_inf of every case it brings below tol_ref (a
+    case retired at r carries an error ~ r / lambda, lambda the slowest decay
+    rate, so r < 1e-8 alone does not fix D_inf to 1e-4).  Per start: the step
+    (and wall time) of r < tol, and the step and wall time after which the drag
+    stays within 1e-4 of D_inf; per batch, the wall time until every such case
+    is steady."""
     import torch
 
     out = {}
     for kind in kinds:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        b = start_batch(cases, kind, net)
-        hist, wall = solve(b, tol, check, cap, log=log, drag_every_check=True, t0=t0)
-        conv, steps, res, drag = b.status()
-        out[kind] = {"converged": conv, "steps": steps, "residual": res, "drag": [d[0] for d in drag],
-                     "wall_s": wall, "hist": hist}
-        log(f"{kind}: {sum(conv)}/{len(conv)} converged, mean steps {np.mean(steps):.0f}, wall {wall:.1f} s")
-        del b
+        hist, st, wall, switch = run_start(cases, kind, net, tol_ref, check, cap, log=log)
+        conv, steps, res, drag = st
+        out[kind] = {"converged_ref": conv, "steps_ref": steps, "drag": [d[0] for d in drag], "wall_s": wall,
+                     "hist": hist}
+        if switch is not None:
+            out[kind]["switch_step"] = switch
+        log(f"{kind}: {sum(conv)}/{len(conv)} below {tol_ref:g}, wall {wall:.1f} s")
         torch.cuda.empty_cache()
-    # cases whose cold run reached steady state define D_inf; the others
-    # (vortex shedding, or the step cap) have no steady drag to reach
     d_inf = out["cold"]["drag"]
-    steady = [k for k, c in enumerate(out["cold"]["converged"]) if c]
+    steady = [k for k, c in enumerate(out["cold"]["converged_ref"]) if c]
     out["steady_cases"] = steady
+    out["d_inf"] = d_inf
     for kind in kinds:
-        st = steady_time(out[kind]["hist"], d_inf)
-        out[kind]["drag_steady_step"] = [st[k][0] if st[k] else None for k in steady]
-        ok = [st[k] for k in steady if st[k]]
-        out[kind]["drag_steady_wall_s"] = max(s[1] for s in ok) if ok and len(ok) == len(steady) else None
-        out[kind]["drag_rel_err"] = [abs(out[kind]["drag"][k] - d_inf[k]) / abs(d_inf[k]) for k in steady]
-        del out[kind]["hist"]
+        h = out[kind].pop("hist")
+        fb = [first_below(h, k, tol) for k in range(len(cases))]
+        out[kind]["steps_tol"] = [f[0] if f else None for f in fb]
+        out[kind]["wall_tol"] = [f[1] if f else None for f in fb]
+        sd = steady_time(h, d_inf)
+        out[kind]["drag_steady_step"] = [sd[k][0] if sd[k] else None for k in steady]
+        out[kind]["drag_steady_wall"] = [sd[k][1] if sd[k] else None for k in steady]
+        ok = [sd[k][1] for k in steady if sd[k]]
+        out[kind]["batch_drag_steady_wall_s"] = max(ok) if ok and len(ok) == len(steady) else None
+        out[kind]["drag_rel_err_end"] = [abs(out[kind]["drag"][k] - d_inf[k]) / abs(d_inf[k]) for k in steady]
     return out
 
 
@@ -294,7 +345,9 @@ def main(argv=None) -> int:
     e.add_argument("--weights", required=True)
     e.add_argument("--held", type=int, default=64)
     e.add_argument("--tol", type=float, default=1e-8)
-    e.add_argument("--cap", type=int, default=2_000_000)
+    e.add_argument("--tol-ref", type=float, default=1e-11)
+    e.add_argument("--cap", type=int, default=4_000_000)
+    e.add_argument("--kinds", default="cold,poiseuille,learned,learned_f16")
     e.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     import torch
@@ -330,15 +383,20 @@ def main(argv=None) -> int:
     held = lc.warmstart_channels(seed=5006, n_cases=a.held)
     _log(f"held-out set: {a.held} channels (seed 5006)")
     net = load_net(a.weights)
-    ev = evaluate(held, net, a.tol, 100, a.cap)
+    kinds = tuple(a.kinds.split(","))
+    ev = evaluate(held, net, a.tol, a.tol_ref, 100, a.cap, kinds=kinds)
     ev["re"] = [c["Re"] for c in held]
     with open(os.path.join(a.out, "warmstart_eval.json"), "w") as fh:
         json.dump(ev, fh)
-    for kind in ("cold", "poiseuille", "learned"):
+    steady = ev["steady_cases"]
+    _log(f"{len(steady)} of {a.held} held-out cases reach r < {a.tol_ref:g} from the cold start")
+    for kind in kinds:
         r = ev[kind]
-        err = max(r["drag_rel_err"]) if r["drag_rel_err"] else float("nan")
-        _log(f"{kind}: mean steps to r<{a.tol:g}: {np.mean(r['steps']):.0f}; all drags steady (1e-4) at "
-             f"{r['drag_steady_wall_s']} s; max drag rel err {err:.2e}")
+        ratio = [x / y for x, y in zip(r["drag_steady_step"], ev["cold"]["drag_steady_step"]) if x and y]
+        st = [x for x in r["drag_steady_step"] if x]
+        _log(f"{kind}: steady drag (1e-4) for {len(st)}/{len(steady)} cases, median steps {np.median(st):.0f}, "
+             f"median ratio to cold {np.median(ratio):.3f}; batch steady at {r['batch_drag_steady_wall_s']} s "
+             f"(total {r['wall_s']:.1f} s)")
     return 0
 
 
