@@ -297,6 +297,14 @@ lbm_status lbm_batch_fields(lbm_batch* b, int32_t case_id, void* d_rho, void* d_
 lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t case_id, const void* d_rho, const void* d_ux,
                                  const void* d_uy, int32_t in_dtype);
 
+/* Retire (active = 0) or reactivate (active = 1) case case_id by hand.  A
+ * retired case keeps its state and leaves the step launch; a reactivated case
+ * continues from its state (moved to the current step's buffer if needed)
+ * and its residual starts over.  With lbm_batch_init_fields after the
+ * reactivation, a case can be handed over from another batch (for instance
+ * from FP16 storage to FP32).  Synchronises. */
+lbm_status lbm_batch_set_active(lbm_batch* b, int32_t case_id, int32_t active);
+
 /* Warm start of case case_id by the exact plane-Poiseuille flow, as
  * lbm_init_poiseuille.  Synchronises. */
 lbm_status lbm_batch_init_poiseuille(lbm_batch* b, int32_t case_id);

@@ -838,6 +838,39 @@ lbm_status lbm_batch_autotune(lbm_batch* b, const char* cache_path) {
     return batch_reset(b);  // the timing steps advanced the state: start over
 }
 
+lbm_status lbm_batch_set_active(lbm_batch* b, int32_t case_id, int32_t active) {
+    if (!b || case_id < 0 || case_id >= b->n) return LBM_EINVAL;
+    lbm_status rs = batch_sync_flags(b);
+    if (rs != LBM_OK) return rs;
+    CaseResult rr;
+    BCHK(b, hipMemcpy(&rr, b->ws + b->o_res + sizeof(CaseResult) * case_id, sizeof(rr), hipMemcpyDeviceToHost));
+    if (active) {
+        if (!b->conv_h[case_id]) return LBM_OK;
+        const CaseDev& d = b->cd[case_id];
+        if ((rr.steps & 1) != (b->t & 1)) {  // the frozen state sits in the other buffer
+            const size_t bytes = (size_t)(d.f_off[1] - d.f_off[0]) * dtype_size(b->dtype);
+            const size_t es = dtype_size(b->dtype);
+            BCHK(b, hipMemcpyAsync(b->ws + b->o_f + es * d.f_off[b->t & 1], b->ws + b->o_f + es * d.f_off[rr.steps & 1],
+                                   bytes, hipMemcpyDeviceToDevice, b->run_stream));
+        }
+        rr.converged = 0;
+        rr.have_snap = 0;
+        rr.residual = -1.0;
+        b->conv_h[case_id] = 0;
+    } else {
+        if (b->conv_h[case_id]) return LBM_OK;
+        rr.converged = 1;
+        rr.steps = b->t;
+        b->conv_h[case_id] = 1;
+    }
+    BCHK(b, hipMemcpyAsync(b->ws + b->o_res + sizeof(CaseResult) * case_id, &rr, sizeof(rr), hipMemcpyHostToDevice,
+                           b->run_stream));
+    BCHK(b, hipMemcpyAsync(b->ws + b->o_conv, b->conv_h.data(), 4 * (size_t)b->n, hipMemcpyHostToDevice,
+                           b->run_stream));
+    BCHK(b, hipStreamSynchronize(b->run_stream));
+    return upload_tiles(b);
+}
+
 lbm_status lbm_batch_set_tiling(lbm_batch* b, int32_t waves, int32_t nontemporal) {
     if (!b) return LBM_EINVAL;
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8) {

@@ -96,6 +96,7 @@ _SIG = {
     "lbm_batch_force": (_I32, [_VP, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_double)]),
     "lbm_batch_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32, _VP]),
     "lbm_batch_init_poiseuille": (_I32, [_VP, _I32]),
+    "lbm_batch_set_active": (_I32, [_VP, _I32, _I32]),
     "lbm_init_poiseuille": (_I32, [_VP]),
     "lbm_batch_init_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32]),
     "lbm_batch_time": (_I64, [_VP]),
@@ -324,6 +325,10 @@ def lbm_batch_force(b, case_id: int, solid_id: int, scheme: int):
 
 def lbm_batch_fields(b, case_id: int, d_rho, d_ux, d_uy, out_dtype: int, d_owner=None) -> None:
     _bcheck(load_library().lbm_batch_fields(b, case_id, d_rho, d_ux, d_uy, out_dtype, d_owner), b)
+
+
+def lbm_batch_set_active(b, case_id: int, active: bool) -> None:
+    _bcheck(load_library().lbm_batch_set_active(b, case_id, int(bool(active))), b)
 
 
 def lbm_batch_init_poiseuille(b, case_id: int) -> None:
@@ -679,6 +684,9 @@ class LatticeBatch:
 
     def init_poiseuille(self, case_id: int) -> None:
         lbm_batch_init_poiseuille(self.b, case_id)
+
+    def set_active(self, case_id: int, active: bool) -> None:
+        lbm_batch_set_active(self.b, case_id, active)
 
     def init_fields(self, case_id: int, rho, ux, uy) -> None:
         dt = LBM_F64 if rho.dtype == self.torch.float64 else LBM_F32

@@ -228,11 +228,16 @@ def all_fields(b, n):
     return [torch.stack([f[i] for f in fl]).contiguous() for i in range(3)]
 
 
+def _step_of(step, k):
+    return step[k] if isinstance(step, (list, tuple)) else step
+
+
 def first_below(hist, k, tol):
-    """(step, wall) of the first check at which case k's residual is below tol."""
+    """(step, wall) of the first check at which case k's residual is below
+    tol (a record's step is the batch step or a per-case list)."""
     for wall, step, _, res in hist:
         if 0 <= res[k] < tol:
-            return step, wall
+            return _step_of(step, k), wall
     return None
 
 
@@ -246,75 +251,142 @@ def steady_time(hist, d_inf, rel=1e-4):
             wall, step, drags = rec[0], rec[1], rec[2]
             good = abs(drags[k] - d_inf[k]) <= rel * abs(d_inf[k])
             if good and ok_from is None:
-                ok_from = (step, wall)
+                ok_from = (_step_of(step, k), wall)
             elif not good:
                 ok_from = None
         out[k] = ok_from
     return out
 
 
-def run_start(cases, kind, net, tol_ref, check, cap, switch_tol=1e-5, log=_log):
-    """One start solved to tol_ref with per-check records.  "learned_f16":
-    the learned start with FP16-offset storage until every case has r below
-    switch_tol, then FP32 from those (projected) fields."""
+def run_mixed(cases, net, tol_stop, check, cap, switch_tol=1e-5, max_f16=None, log=_log):
+    """Learned start with FP16-offset storage; each case moves to FP32 storage
+    (its fields projected and re-initialised there) once its residual falls
+    below switch_tol, or after max_f16 steps.  Both batches advance one check
+    interval per round; returns (history with per-case drags and residuals,
+    per-case [converged, steps], wall seconds, per-case switch steps)."""
+    import torch
+
+    n = len(cases)
+    max_f16 = max_f16 if max_f16 is not None else cap // 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b16 = start_batch(cases, "learned", net, dtype="f16")
+    b32 = lbm.LatticeBatch(cases, dtype="f32")
+    for k in range(n):
+        b32.set_active(k, False)
+    in16 = [True] * n
+    steps = [0] * n
+    switch = [None] * n
+    done32 = [False] * n
+    hist = []
+    last = time.perf_counter()
+    drag = [0.0] * n
+    res = [-1.0] * n
+    while max(steps) < cap:
+        act16 = [k for k in range(n) if in16[k]]
+        if act16:
+            b16.run(check, switch_tol, check)
+            c16, _, r16, d16 = b16.status()
+            for k in act16:
+                steps[k] += check
+                drag[k], res[k] = d16[k][0], r16[k]
+            move = [k for k in act16 if c16[k] or steps[k] >= max_f16]
+            if move:
+                own = torch.stack([b16.fields(k, "f32", owner=True)[3] for k in move]).contiguous()
+                f = [b16.fields(k, "f32") for k in move]
+                rho, ux, uy = (torch.stack([x[i] for x in f]).contiguous() for i in range(3))
+                lbm.warm_project(own, rho, ux, uy, rho0=1.0)
+                for j, k in enumerate(move):
+                    b32.set_active(k, True)
+                    b32.init_fields(k, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
+                    b16.set_active(k, False)
+                    in16[k] = False
+                    switch[k] = steps[k]
+        act32 = [k for k in range(n) if not in16[k] and not done32[k]]
+        if act32:
+            b32.run(check, tol_stop, check)
+            c32, _, r32, d32 = b32.status()
+            for k in act32:
+                steps[k] += check
+                drag[k], res[k] = d32[k][0], r32[k]
+                if c32[k]:
+                    done32[k] = True
+        if not act16 and not act32:
+            break
+        hist.append((time.perf_counter() - t0, list(steps), list(drag), list(res)))
+        if time.perf_counter() - last > 20.0:
+            last = time.perf_counter()
+            log(f"  fp16 {sum(in16)} cases, fp32 done {sum(done32)}/{n}")
+    torch.cuda.synchronize()
+    return hist, done32, steps, time.perf_counter() - t0, switch
+
+
+def run_start(cases, kind, net, tol_stop, check, cap, log=_log):
+    """One start (cold, poiseuille, learned: FP32 storage) solved to tol_stop
+    with per-check records [(wall, step, drags, residuals)]; the step is the
+    batch step (every active case advances together)."""
     import torch
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    if kind != "learned_f16":
-        b = start_batch(cases, kind, net)
-        hist, _ = solve(b, tol_ref, check, cap, log=log, record=True, t0=t0)
-        st = b.status()
-        del b
-        return hist, st, time.perf_counter() - t0, None
-    b16 = start_batch(cases, "learned", net, dtype="f16")
-    hist, _ = solve(b16, switch_tol, check, cap, log=log, record=True, t0=t0)
-    switch = b16.t
-    fields = all_fields(b16, len(cases))
-    del b16
-    b = start_batch(cases, "fields", fields=fields)
-    h2, _ = solve(b, tol_ref, check, cap - switch, log=log, record=True, t0=t0, step0=switch)
+    b = start_batch(cases, kind, net)
+    hist, _ = solve(b, tol_stop, check, cap, log=log, record=True, t0=t0)
     st = b.status()
     del b
-    return hist + h2, st, time.perf_counter() - t0, switch
+    return hist, st, time.perf_counter() - t0
 
 
-def evaluate(cases, net, tol=1e-8, tol_ref=1e-11, check=100, cap=4_000_000,
-             kinds=("cold", "poiseuille", "learned", "learned_f16"), log=_log):
-    """Solve the held-out cases from each start to r < tol_ref.  The cold run
-    gives the steady drag D_inf of every case it brings below tol_ref (a
-    case retired at r carries an error ~ r / lambda, lambda the slowest decay
-    rate, so r < 1e-8 alone does not fix D_inf to 1e-4).  Per start: the step
-    (and wall time) of r < tol, and the step and wall time after which the drag
-    stays within 1e-4 of D_inf; per batch, the wall time until every such case
-    is steady."""
+def reference_drag(cases, tol_ref, check, cap, log=_log):
+    """Steady drag of every case from a cold start in FP64 storage solved to
+    r < tol_ref (a case retired at r still differs from its steady state by
+    ~ r / lambda, lambda the slowest decay rate: r < 1e-11 puts D_inf within
+    ~1e-5 for the slowest channels here).  Returns (D_inf, reached)."""
     import torch
 
-    out = {}
+    b = lbm.LatticeBatch(cases, dtype="f64")
+    solve(b, tol_ref, check, cap, log=log)
+    conv, _, _, drag = b.status()
+    del b
+    torch.cuda.empty_cache()
+    return [d[0] for d in drag], conv
+
+
+def evaluate(cases, net, tol=1e-8, tol_stop=1e-9, tol_ref=1e-11, check=100, cap=3_000_000,
+             kinds=("cold", "poiseuille", "learned", "learned_f16"), log=_log):
+    """Solve the held-out cases from each start (FP32 storage unless named)
+    to r < tol_stop with per-check records.  D_inf comes from an FP64 cold
+    run to r < tol_ref.  Per start: the step (and wall time) of r < tol, and
+    the step and wall time after which the drag stays within 1e-4 of D_inf;
+    per batch, the wall time until every case with a reference is steady."""
+    import torch
+
+    t0 = time.perf_counter()
+    d_inf, ref_ok = reference_drag(cases, tol_ref, check, cap, log=log)
+    steady = [k for k, c in enumerate(ref_ok) if c]
+    out = {"steady_cases": steady, "d_inf": d_inf, "reference_wall_s": time.perf_counter() - t0}
+    log(f"reference: {len(steady)}/{len(cases)} cases below {tol_ref:g} (FP64)")
     for kind in kinds:
-        hist, st, wall, switch = run_start(cases, kind, net, tol_ref, check, cap, log=log)
-        conv, steps, res, drag = st
-        out[kind] = {"converged_ref": conv, "steps_ref": steps, "drag": [d[0] for d in drag], "wall_s": wall,
-                     "hist": hist}
-        if switch is not None:
-            out[kind]["switch_step"] = switch
-        log(f"{kind}: {sum(conv)}/{len(conv)} below {tol_ref:g}, wall {wall:.1f} s")
-        torch.cuda.empty_cache()
-    d_inf = out["cold"]["drag"]
-    steady = [k for k, c in enumerate(out["cold"]["converged_ref"]) if c]
-    out["steady_cases"] = steady
-    out["d_inf"] = d_inf
-    for kind in kinds:
-        h = out[kind].pop("hist")
-        fb = [first_below(h, k, tol) for k in range(len(cases))]
-        out[kind]["steps_tol"] = [f[0] if f else None for f in fb]
-        out[kind]["wall_tol"] = [f[1] if f else None for f in fb]
-        sd = steady_time(h, d_inf)
-        out[kind]["drag_steady_step"] = [sd[k][0] if sd[k] else None for k in steady]
-        out[kind]["drag_steady_wall"] = [sd[k][1] if sd[k] else None for k in steady]
+        if kind == "learned_f16":
+            hist, conv, steps, wall, switch = run_mixed(cases, net, tol_stop, check, cap, log=log)
+            r = {"converged_stop": conv, "steps_stop": steps, "drag": hist[-1][2], "wall_s": wall,
+                 "switch_step": switch}
+        else:
+            hist, st, wall = run_start(cases, kind, net, tol_stop, check, cap, log=log)
+            conv, steps, res, drag = st
+            r = {"converged_stop": conv, "steps_stop": steps, "drag": [d[0] for d in drag], "wall_s": wall}
+        fb = [first_below(hist, k, tol) for k in range(len(cases))]
+        r["steps_tol"] = [f[0] if f else None for f in fb]
+        r["wall_tol"] = [f[1] if f else None for f in fb]
+        r["min_residual"] = [min((h[3][k] for h in hist if h[3][k] >= 0), default=None) for k in range(len(cases))]
+        sd = steady_time(hist, d_inf)
+        r["drag_steady_step"] = [sd[k][0] if sd[k] else None for k in steady]
+        r["drag_steady_wall"] = [sd[k][1] if sd[k] else None for k in steady]
         ok = [sd[k][1] for k in steady if sd[k]]
-        out[kind]["batch_drag_steady_wall_s"] = max(ok) if ok and len(ok) == len(steady) else None
-        out[kind]["drag_rel_err_end"] = [abs(out[kind]["drag"][k] - d_inf[k]) / abs(d_inf[k]) for k in steady]
+        r["batch_drag_steady_wall_s"] = max(ok) if ok and len(ok) == len(steady) else None
+        r["drag_rel_err_end"] = [abs(r["drag"][k] - d_inf[k]) / abs(d_inf[k]) for k in steady]
+        out[kind] = r
+        log(f"{kind}: {sum(conv)}/{len(conv)} below {tol_stop:g}, wall {wall:.1f} s")
+        torch.cuda.empty_cache()
     return out
 
 
@@ -345,8 +417,9 @@ def main(argv=None) -> int:
     e.add_argument("--weights", required=True)
     e.add_argument("--held", type=int, default=64)
     e.add_argument("--tol", type=float, default=1e-8)
+    e.add_argument("--tol-stop", type=float, default=1e-9)
     e.add_argument("--tol-ref", type=float, default=1e-11)
-    e.add_argument("--cap", type=int, default=4_000_000)
+    e.add_argument("--cap", type=int, default=3_000_000)
     e.add_argument("--kinds", default="cold,poiseuille,learned,learned_f16")
     e.add_argument("--out", required=True)
     a = ap.parse_args(argv)
@@ -384,12 +457,12 @@ def main(argv=None) -> int:
     _log(f"held-out set: {a.held} channels (seed 5006)")
     net = load_net(a.weights)
     kinds = tuple(a.kinds.split(","))
-    ev = evaluate(held, net, a.tol, a.tol_ref, 100, a.cap, kinds=kinds)
+    ev = evaluate(held, net, a.tol, a.tol_stop, a.tol_ref, 100, a.cap, kinds=kinds)
     ev["re"] = [c["Re"] for c in held]
     with open(os.path.join(a.out, "warmstart_eval.json"), "w") as fh:
         json.dump(ev, fh)
     steady = ev["steady_cases"]
-    _log(f"{len(steady)} of {a.held} held-out cases reach r < {a.tol_ref:g} from the cold start")
+    _log(f"{len(steady)} of {a.held} held-out cases reach r < {a.tol_ref:g} from an FP64 cold start")
     for kind in kinds:
         r = ev[kind]
         ratio = [x / y for x, y in zip(r["drag_steady_step"], ev["cold"]["drag_steady_step"]) if x and y]

@@ -280,3 +280,17 @@ def test_poiseuille_start(lbm_mod):
     # lambda = pi^2 nu / ny^2 the slowest decay rate: 1e-10 / 1.7e-3 here
     lam = np.pi ** 2 * nu / ny ** 2
     assert np.abs(_np(batch.fields(0, "f64")[1]) - exact[:, None]).max() <= 10 * 1e-10 / lam * exact.max()
+
+
+def test_set_active_retires_and_resumes_across_parity(lbm_mod):
+    case = uneven_cases()[0]
+    batch = lbm_mod.LatticeBatch([case, case], dtype="f64")
+    batch.step(10)
+    batch.set_active(1, False)
+    batch.step(7)  # odd: the retired case's state now sits in the other buffer
+    batch.set_active(1, True)
+    batch.step(5)
+    for k, steps in ((0, 22), (1, 15)):
+        (rho, ux, uy), _ = lone_state(lbm_mod, case, "f64", steps)
+        got = [_np(a) for a in batch.fields(k, "f64")]
+        assert np.array_equal(got[0], rho) and np.array_equal(got[1], ux) and np.array_equal(got[2], uy), k
