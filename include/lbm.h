@@ -417,7 +417,11 @@ lbm_status lbm_nn_infer(lbm_nn* nn, const uint8_t* d_solid, const double* d_re, 
 
 /* Make warm-start fields safe to start from, in place, for n_fields channels
  * of nx x ny (nx even, both <= 2048): owner map u8 and rho, u_x, u_y FP32,
- * [n_fields][ny][nx] device memory, fluid nodes only.  rho is shifted to mean
+ * [n_fields][ny][nx] device memory, fluid nodes only.  When the second set
+ * (rho2, u_x2, u_y2; all or none) is given, the fields are first replaced by
+ * the mean of the two sets: with the fields of two consecutive steps of a
+ * started lattice, the spurious modes that change sign every step (excited
+ * where a warm field meets a body) cancel.  Then rho is shifted to mean
  * rho0 (the mass of a cold start, so the steady drag, which balances g_x sum
  * rho, is the same); u_x is scaled column by column to equal fluxes
  * sum_y rho u_x (continuity), u_y shifted row by row to zero flux.  A lattice
@@ -427,7 +431,8 @@ lbm_status lbm_nn_infer(lbm_nn* nn, const uint8_t* d_solid, const double* d_re, 
  * interval does not see it).  Asynchronous on hip_stream; LBM_EINVAL on bad
  * sizes. */
 lbm_status lbm_warm_project(int32_t nx, int32_t ny, int32_t n_fields, const uint8_t* d_owner, float* d_rho,
-                            float* d_ux, float* d_uy, double rho0, void* hip_stream);
+                            float* d_ux, float* d_uy, const float* d_rho2, const float* d_ux2, const float* d_uy2,
+                            double rho0, void* hip_stream);
 
 /* Release the network (not the caller's buffers).  NULL is ignored. */
 void lbm_nn_destroy(lbm_nn* nn);

@@ -675,7 +675,8 @@ lbm_status lbm_nn_infer(lbm_nn* n, const uint8_t* d_solid, const double* d_re, c
 }
 
 lbm_status lbm_warm_project(int32_t nx, int32_t ny, int32_t n_fields, const uint8_t* d_owner, float* d_rho,
-                            float* d_ux, float* d_uy, double rho0, void* hip_stream) {
+                            float* d_ux, float* d_uy, const float* d_rho2, const float* d_ux2, const float* d_uy2,
+                            double rho0, void* hip_stream) {
     if (nx < 2 || ny < 1 || nx > kProjMax || ny > kProjMax || (nx & 1) || n_fields < 1) {
         nn_set_err(g_nn_err, "nx must be even and in [2, %d], ny in [1, %d], n_fields >= 1", kProjMax, kProjMax);
         return LBM_EINVAL;
@@ -684,7 +685,18 @@ lbm_status lbm_warm_project(int32_t nx, int32_t ny, int32_t n_fields, const uint
         nn_set_err(g_nn_err, "field pointers must not be NULL and rho0 must be > 0");
         return LBM_EINVAL;
     }
-    k_project<<<n_fields, kEw, 0, (hipStream_t)hip_stream>>>(d_owner, d_rho, d_ux, d_uy, nx, ny, rho0);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    if (d_rho2 || d_ux2 || d_uy2) {
+        if (!d_rho2 || !d_ux2 || !d_uy2) {
+            nn_set_err(g_nn_err, "the second field set needs all three of rho, u_x, u_y");
+            return LBM_EINVAL;
+        }
+        const int64_t n = (int64_t)n_fields * nx * ny;
+        k_average<<<blocks(n), kEw, 0, st>>>(d_rho, d_rho2, n);
+        k_average<<<blocks(n), kEw, 0, st>>>(d_ux, d_ux2, n);
+        k_average<<<blocks(n), kEw, 0, st>>>(d_uy, d_uy2, n);
+    }
+    k_project<<<n_fields, kEw, 0, st>>>(d_owner, d_rho, d_ux, d_uy, nx, ny, rho0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         nn_set_err(g_nn_err, "projection launch failed: %s", hipGetErrorString(e));

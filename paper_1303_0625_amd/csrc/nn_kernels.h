@@ -548,6 +548,13 @@ __global__ __launch_bounds__(kEw) void k_unpack_fields(const float* __restrict__
 // in a fixed order.
 constexpr int kProjMax = 2048;  // largest nx and ny of a projected field (LDS: 52 KB)
 
+// a = (a + b) / 2 elementwise (the mean of the fields of two consecutive
+// steps: modes that change sign every step cancel, slowly varying ones stay).
+__global__ __launch_bounds__(kEw) void k_average(float* __restrict__ a, const float* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (i < n) a[i] = 0.5f * (a[i] + b[i]);
+}
+
 __global__ __launch_bounds__(kEw) void k_project(const uint8_t* __restrict__ own, float* __restrict__ rho,
                                                  float* __restrict__ ux, float* __restrict__ uy, int nx, int ny,
                                                  double rho0) {

@@ -116,7 +116,7 @@ _SIG = {
     "lbm_nn_eval": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32,
                            ctypes.POINTER(ctypes.c_double)]),
     "lbm_nn_infer": (_I32, [_VP, _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP]),
-    "lbm_warm_project": (_I32, [_I32, _I32, _I32, _VP, _VP, _VP, _VP, ctypes.c_double, _VP]),
+    "lbm_warm_project": (_I32, [_I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP]),
     "lbm_nn_destroy": (None, [_VP]),
     "lbm_nn_last_error": (ctypes.c_char_p, [_VP]),
 }
@@ -422,19 +422,23 @@ def lbm_nn_infer(n, d_solid, d_re, d_gx, d_tau, batch: int, d_rho, d_ux, d_uy) -
     _ncheck(load_library().lbm_nn_infer(n, d_solid, d_re, d_gx, d_tau, batch, d_rho, d_ux, d_uy), n)
 
 
-def lbm_warm_project(nx: int, ny: int, n_fields: int, d_owner, d_rho, d_ux, d_uy, rho0: float, stream) -> None:
-    _ncheck(load_library().lbm_warm_project(nx, ny, n_fields, d_owner, d_rho, d_ux, d_uy, rho0, stream))
+def lbm_warm_project(nx: int, ny: int, n_fields: int, d_owner, d_rho, d_ux, d_uy, d_rho2, d_ux2, d_uy2,
+                     rho0: float, stream) -> None:
+    _ncheck(load_library().lbm_warm_project(nx, ny, n_fields, d_owner, d_rho, d_ux, d_uy, d_rho2, d_ux2, d_uy2,
+                                            rho0, stream))
 
 
-def warm_project(owner, rho, ux, uy, rho0=1.0):
+def warm_project(owner, rho, ux, uy, rho0=1.0, second=None):
     """In-place projection of warm-start fields (torch CUDA tensors
-    [n][ny][nx]: owner uint8, rho/ux/uy float32) on the current stream."""
+    [n][ny][nx]: owner uint8, rho/ux/uy float32) on the current stream;
+    second = (rho2, ux2, uy2) averages that set in first."""
     import torch
 
-    for t in (owner, rho, ux, uy):
+    for t in (owner, rho, ux, uy) + (tuple(second) if second else ()):
         assert t.is_contiguous() and t.is_cuda
     n, ny, nx = rho.shape
-    lbm_warm_project(nx, ny, n, owner.data_ptr(), rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), rho0,
+    p2 = [t.data_ptr() for t in second] if second else [None, None, None]
+    lbm_warm_project(nx, ny, n, owner.data_ptr(), rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), *p2, rho0,
                      torch.cuda.current_stream(rho.device).cuda_stream)
 
 

@@ -182,18 +182,42 @@ def load_weights(path):
 
 
 # --------------------------------------------------------------------- evaluation
-def start_batch(cases, kind, net=None, dtype="f32", project=True, fields=None):
+DESTAGGER_STEPS = 100
+
+
+def start_batch(cases, kind, net=None, dtype="f32", project=True, fields=None, destagger=DESTAGGER_STEPS):
     """A LatticeBatch of the cases started cold, from the exact Poiseuille
     flow ("poiseuille"), from the network ("learned"), or from given fields
     (rho, ux, uy [n][ny][nx] float32, "fields").  Warm-start fields are
     projected (lbm_warm_project: the cold start's mass, equal column fluxes,
     zero row fluxes) unless project=False, so that they excite no undamped
-    staggered momentum."""
+    staggered momentum.  With destagger = N > 0 the started batch runs N
+    steps, and is started again from the projected mean of its fields at
+    steps N and N + 1: a warm field meeting a body at rest excites staggered
+    modes (sign change every step, decay as slow as the slowest shear mode),
+    which that mean removes.  The batch's step counter then stands at N + 1."""
     import torch
 
     b = lbm.LatticeBatch(cases, dtype=dtype)
     if kind == "cold":
         return b
+    _init_warm(b, cases, kind, net, project, fields)
+    if destagger > 0:
+        b.step(destagger)
+        f1 = all_fields(b, len(cases))
+        b.step(1)
+        f2 = all_fields(b, len(cases))
+        own = torch.stack([b.fields(k, "f32", owner=True)[3] for k in range(len(cases))]).contiguous()
+        lbm.warm_project(own, *f1, rho0=float(cases[0].get("rho0", 1.0)), second=f2)
+        for k in range(len(cases)):
+            b.init_fields(k, f1[0][k].contiguous(), f1[1][k].contiguous(), f1[2][k].contiguous())
+    torch.cuda.synchronize()
+    return b
+
+
+def _init_warm(b, cases, kind, net, project, fields):
+    import torch
+
     dev = b.workspace.device
     step = net.max_batch if net is not None else 16
     for k0 in range(0, len(cases), step):
@@ -216,8 +240,6 @@ def start_batch(cases, kind, net=None, dtype="f32", project=True, fields=None):
             lbm.warm_project(own, rho, ux, uy, rho0=float(part[0].get("rho0", 1.0)))
         for j in range(len(part)):
             b.init_fields(k0 + j, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
-    torch.cuda.synchronize()
-    return b
 
 
 def all_fields(b, n):
@@ -275,7 +297,7 @@ def run_mixed(cases, net, tol_stop, check, cap, switch_tol=1e-5, max_f16=None, l
     for k in range(n):
         b32.set_active(k, False)
     in16 = [True] * n
-    steps = [0] * n
+    steps = [b16.t] * n  # the de-staggering steps
     switch = [None] * n
     done32 = [False] * n
     hist = []
