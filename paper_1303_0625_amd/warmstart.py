@@ -280,12 +280,14 @@ def steady_time(hist, d_inf, rel=1e-4):
     return out
 
 
-def run_mixed(cases, net, tol_stop, check, cap, switch_tol=1e-5, max_f16=None, log=_log):
-    """Learned start with FP16-offset storage; each case moves to FP32 storage
-    (its fields projected and re-initialised there) once its residual falls
-    below switch_tol, or after max_f16 steps.  Both batches advance one check
-    interval per round; returns (history with per-case drags and residuals,
-    per-case [converged, steps], wall seconds, per-case switch steps)."""
+def run_mixed(cases, net, tol_stop, check, cap, switch_tol=1e-5, switch_frac=0.9, max_f16=None, log=_log):
+    """Learned start with FP16-offset storage (half the bytes per step) until
+    switch_frac of the cases have r < switch_tol (or max_f16 steps), then every
+    case in FP32 storage, restarted from its FP16 fields through the same
+    de-staggering restart as a warm start.  Per-case step counts add the FP16
+    steps a case took (a case retired early waits, uncounted) and the FP32
+    steps.  Returns (history [(wall, per-case steps, drags, residuals)],
+    per-case converged, per-case steps, wall seconds, FP32 start step)."""
     import torch
 
     n = len(cases)
@@ -293,54 +295,24 @@ def run_mixed(cases, net, tol_stop, check, cap, switch_tol=1e-5, max_f16=None, l
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b16 = start_batch(cases, "learned", net, dtype="f16")
-    b32 = lbm.LatticeBatch(cases, dtype="f32")
-    for k in range(n):
-        b32.set_active(k, False)
-    in16 = [True] * n
-    steps = [b16.t] * n  # the de-staggering steps
-    switch = [None] * n
-    done32 = [False] * n
+    steps = [b16.t] * n
     hist = []
-    last = time.perf_counter()
-    drag = [0.0] * n
-    res = [-1.0] * n
-    while max(steps) < cap:
-        act16 = [k for k in range(n) if in16[k]]
-        if act16:
-            b16.run(check, switch_tol, check)
-            c16, _, r16, d16 = b16.status()
-            for k in act16:
-                steps[k] += check
-                drag[k], res[k] = d16[k][0], r16[k]
-            move = [k for k in act16 if c16[k] or steps[k] >= max_f16]
-            if move:
-                own = torch.stack([b16.fields(k, "f32", owner=True)[3] for k in move]).contiguous()
-                f = [b16.fields(k, "f32") for k in move]
-                rho, ux, uy = (torch.stack([x[i] for x in f]).contiguous() for i in range(3))
-                lbm.warm_project(own, rho, ux, uy, rho0=1.0)
-                for j, k in enumerate(move):
-                    b32.set_active(k, True)
-                    b32.init_fields(k, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
-                    b16.set_active(k, False)
-                    in16[k] = False
-                    switch[k] = steps[k]
-        act32 = [k for k in range(n) if not in16[k] and not done32[k]]
-        if act32:
-            b32.run(check, tol_stop, check)
-            c32, _, r32, d32 = b32.status()
-            for k in act32:
-                steps[k] += check
-                drag[k], res[k] = d32[k][0], r32[k]
-                if c32[k]:
-                    done32[k] = True
-        if not act16 and not act32:
+    while b16.t < max_f16:
+        b16.run(check, switch_tol, check)
+        conv, steps, res, drag = b16.status()  # steps: at retirement, or the current step
+        hist.append((time.perf_counter() - t0, list(steps), [d[0] for d in drag], list(res)))
+        if sum(conv) >= switch_frac * n:
             break
-        hist.append((time.perf_counter() - t0, list(steps), list(drag), list(res)))
-        if time.perf_counter() - last > 20.0:
-            last = time.perf_counter()
-            log(f"  fp16 {sum(in16)} cases, fp32 done {sum(done32)}/{n}")
-    torch.cuda.synchronize()
-    return hist, done32, steps, time.perf_counter() - t0, switch
+    fields = all_fields(b16, n)
+    del b16
+    b = start_batch(cases, "fields", fields=fields)  # de-staggering restart in FP32
+    base = list(steps)
+    h2, _ = solve(b, tol_stop, check, cap - max(steps), log=log, record=True, t0=t0)
+    for wall, t, drags, res in h2:
+        hist.append((wall, [base[k] + t for k in range(n)], drags, res))
+    conv, st, _, _ = b.status()
+    del b
+    return hist, conv, [base[k] + st[k] for k in range(n)], time.perf_counter() - t0, list(base)
 
 
 def run_start(cases, kind, net, tol_stop, check, cap, log=_log):
