@@ -12,8 +12,9 @@ kernel (the one-per-step launch whose update role moves 18 populations per
 fluid node, timed with HIP events attached to each dispatch on the library's
 stream), an additional HBM-bound measurement on a 4096 x 4096 periodic lattice
 (its A/B working set is 4.7x the 256 MB Infinity Cache), the batched solver on
-256 uneven channel/cylinder cases, and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+256 uneven channel/cylinder cases, the learned warm start (network throughput
+and time to steady drag against a plain cold start on held-out channels), and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -106,6 +107,42 @@ def run_batch(lc, pkg, torch, steps):
             "timing": "wall clock around graph replays, monitor included"}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_network(pkg):
+    """Training and inference throughput of the warm-start network (BF16
+    matrix-core convolutions) at 256 x 128, batch 8, in algorithmic FLOPs."""
+    from paper_1303_0625_amd import warmstart as ws
+
+    r = ws.network_throughput(batch=8, steps=40)
+    r["train_frac_of_bf16_peak"] = round(r["train_tflops"] / MFMA_BF16_PEAK_TFLOPS, 4)
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+
+
+def run_warm_start(lc, pkg, n_cases):
+    """Time to steady drag (within 1e-4 of an FP64 cold run solved to
+    r < 1e-11) of the first n_cases held-out channels (seed 5006): plain FP32
+    cold start vs the learned start with FP16 storage switching to FP32."""
+    import numpy as np
+
+    from paper_1303_0625_amd import warmstart as ws
+
+    held = lc.warmstart_channels(seed=5006, n_cases=n_cases)
+    net = ws.load_net(os.path.join(ROOT, "paper_1303_0625_amd", "weights", "warmstart_256x128.npz"))
+    ev = ws.evaluate(held, net, tol=1e-8, tol_stop=1e-9, tol_ref=1e-11, check=100, cap=3_000_000,
+                     kinds=("cold", "learned_f16"), log=lambda m: None)
+    cold, warm = ev["cold"], ev["learned_f16"]
+    ratio = [a / b for a, b in zip(warm["drag_steady_step"], cold["drag_steady_step"]) if a and b]
+    tc, tw = cold["batch_drag_steady_wall_s"], warm["batch_drag_steady_wall_s"]
+    return {"cases": n_cases, "cases_with_reference": len(ev["steady_cases"]),
+            "plain_fp32_cold_s": round(tc, 3) if tc else None,
+            "learned_fp16_mixed_s": round(tw, 3) if tw else None,
+            "speedup": round(tc / tw, 3) if tc and tw else None,
+            "median_step_ratio": round(float(np.median(ratio)), 3) if ratio else None,
+            "criterion": "drag within 1e-4 of an FP64 cold run at r < 1e-11, at every later check"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,8 +154,12 @@ def main() -> int:
     ap.add_argument("--no-hbm-case", action="store_true")
     ap.add_argument("--no-batch-case", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--warm-cases", type=int, default=16)
     ap.add_argument("--only-hbm-case", action="store_true",
                     help="run only the 4096 x 4096 measurement (profiling)")
+    ap.add_argument("--only-network", action="store_true",
+                    help="run only the warm-start network throughput (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -138,6 +179,9 @@ def main() -> int:
 
     case = lc.moving_cylinders()
     nx, ny = case["nx"], case["ny"]
+    if args.only_network:
+        print(json.dumps(run_network(pkg)), flush=True)
+        return 0
     if args.only_hbm_case:
         big = lc.periodic_cylinders()
         lat2, tms2, ums2, n2, nf2 = run_gpu(big, args.dtype, args.steps, args.warmup, torch, pkg)
@@ -182,6 +226,11 @@ def main() -> int:
 
     if not args.no_batch_case:
         extra["batched_uneven_256"] = run_batch(lc, pkg, torch, args.batch_steps)
+        torch.cuda.empty_cache()
+
+    if not args.no_warm_start:
+        extra["warm_start_network"] = run_network(pkg)
+        extra["warm_start_time_to_steady"] = run_warm_start(lc, pkg, args.warm_cases)
         torch.cuda.empty_cache()
 
     cpu = None

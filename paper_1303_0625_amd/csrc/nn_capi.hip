@@ -117,10 +117,10 @@ const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
         const int tiles = (L.cout_pad / (32 * mb)) * (L.cin_dg / (32 * nbk)) * 9;
         int splits, chunk;
         wgrad_split(p, level_in[k], tiles, splits, chunk);
-        p.wpart_max = std::max<int64_t>(p.wpart_max, (int64_t)splits * cout[k] * 9 * cin[k]);
-        const int64_t P = pixels(p, level_in[k]);
-        p.bpart_max = std::max<int64_t>(p.bpart_max, ((P + 255) / 256) * cout[k]);
+        p.wpart_max = std::max<int64_t>(p.wpart_max, (int64_t)splits * (cout[k] * 9 * cin[k] + cout[k]));
     }
+    // channel means of the bottleneck and their adjoint (per sample, c3 wide)
+    p.bpart_max = std::max<int64_t>(p.bpart_max, (int64_t)p.B * ((pixels(p, 2) / p.B + 255) / 256) * c3);
     p.n_params = off;
     p.wf_total = wf;
     p.wt_total = wt;
@@ -223,6 +223,18 @@ void conv(lbm_nn* n, int level, const void* in, int in_cs, int cin, const void* 
     }
 }
 
+constexpr int kColRows = 256;  // nodes per workgroup of a column sum
+
+// out[b][c] = scale * sum over the N nodes of segment b of a[.][co + c]
+// (c < C <= kEw), in a fixed order; float (fout) and/or T (tout) results.
+template <typename T>
+void colsum(lbm_nn* n, const void* a, int cs, int co, int C, int64_t N, int B, float scale, float* fout, T* tout) {
+    const int nblk = (int)((N + kColRows - 1) / kColRows);
+    float* part = at<float>(n, n->p.o_bpart);
+    k_colsum_partial<T><<<dim3(nblk, B), kEw, 0, n->st>>>((const T*)a, cs, co, C, N, kColRows, part);
+    k_colsum_final<T><<<blocks((int64_t)B * C), kEw, 0, n->st>>>(part, nblk, C, B, scale, fout, tout);
+}
+
 template <typename T>
 void layer_fwd(lbm_nn* n, int k, int level, Buf in, Buf out, int out_cs, int out_co) {
     const LayerDev& L = n->p.L[k];
@@ -277,14 +289,9 @@ void layer_wgrad(lbm_nn* n, int k, int level, Buf x, Buf g) {
         k_wgrad<T, 1, 2><<<gr, 256, 0, n->st>>>(a);
     else
         k_wgrad<T, 1, 1><<<gr, 256, 0, n->st>>>(a);
-    const int64_t nw = (int64_t)L.cout * 9 * L.cin;
-    k_sum_splits<<<blocks(nw), kEw, 0, n->st>>>(a.part, splits, nw, at<float>(n, p.o_grad) + L.off);
-    const int rows = 256;
-    const int nblk = (a.P + rows - 1) / rows;
-    k_bias_partial<<<nblk, kEw, 0, n->st>>>(a.g, n->dtype == LBM_BF16 ? 1 : 0, a.g_cs, L.cout, a.P, rows,
-                                            at<float>(n, p.o_bpart));
-    k_bias_final<<<blocks(L.cout), kEw, 0, n->st>>>(at<float>(n, p.o_bpart), nblk, L.cout,
-                                                   at<float>(n, p.o_grad) + L.off + nw);
+    // weights and bias are contiguous in the parameter vector and in each split's partial
+    const int64_t nwb = (int64_t)L.cout * 9 * L.cin + L.cout;
+    k_sum_splits<<<blocks(nwb), kEw, 0, n->st>>>(a.part, splits, nwb, at<float>(n, p.o_grad) + L.off);
 }
 
 template <typename T>
@@ -311,8 +318,8 @@ void forward_t(lbm_nn* n) {
     // bottleneck and its global context
     layer_fwd<T>(n, 6, 3, X3, B1, c3, 0);
     layer_fwd<T>(n, 7, 3, B1, B2, c3, 0);
-    k_channel_mean<T><<<blocks((int64_t)B * c3), kEw, 0, n->st>>>((const T*)buf(n, B2), c3, H(3) * W(3), B,
-                                                                  (T*)buf(n, GMEAN));
+    colsum<T>(n, buf(n, B2), c3, 0, c3, (int64_t)H(3) * W(3), B, 1.0f / (float)(H(3) * W(3)), nullptr,
+              (T*)buf(n, GMEAN));
     k_broadcast<T><<<blocks((int64_t)B * H(2) * W(2) * c3), kEw, 0, n->st>>>(
         (const T*)buf(n, GMEAN), c3, (T*)buf(n, CAT2), cat2, c3 + c2, H(2) * W(2), B);
     // decoder
@@ -364,8 +371,8 @@ void backward_t(lbm_nn* n) {
     layer_wgrad<T>(n, 8, 2, CAT2, G_D2A);
     layer_dgrad<T>(n, 8, 2, G_D2A, G_CAT2, CAT2, 0, 0, false);
     const int cat2 = 2 * c3 + c2;
-    k_broadcast_back<T><<<blocks((int64_t)B * c3), kEw, 0, n->st>>>((const T*)buf(n, G_CAT2), cat2, c3 + c2, c3,
-                                                                    H(2) * W(2), B, at<float>(n, p.o_gmean));
+    colsum<T>(n, buf(n, G_CAT2), cat2, c3 + c2, c3, (int64_t)H(2) * W(2), B, 1.0f, at<float>(n, p.o_gmean),
+              (T*)nullptr);
     k_upsample_back<T><<<blocks((int64_t)B * H(3) * W(3) * c3), kEw, 0, n->st>>>(
         (const T*)buf(n, G_CAT2), cat2, 0, c3, (const T*)buf(n, B2), at<float>(n, p.o_gmean), (T*)buf(n, G_B2),
         H(3), W(3), B);
@@ -452,7 +459,7 @@ void loss_t(lbm_nn* n) {
     const int nb = (int)blocks(P);
     k_loss_partial<<<nb, kEw, 0, n->st>>>(at<float>(n, p.o_out), at<float>(n, p.o_tgt), at<uint8_t>(n, p.o_fluid), P,
                                           at<double>(n, p.o_lpart));
-    k_loss_final<<<1, 64, 0, n->st>>>(at<double>(n, p.o_lpart), nb, at<double>(n, p.o_loss));
+    k_loss_final<<<1, kEw, 0, n->st>>>(at<double>(n, p.o_lpart), nb, at<double>(n, p.o_loss));
     k_loss_grad<T><<<nb, kEw, 0, n->st>>>(at<float>(n, p.o_out), at<float>(n, p.o_tgt), at<uint8_t>(n, p.o_fluid), P,
                                          at<double>(n, p.o_loss), (T*)buf(n, G_HEAD));
 }

@@ -184,7 +184,9 @@ __global__ __launch_bounds__(kConvWaves * 64) void k_conv(ConvArgs a) {
 // Workgroup (tile, split): co block of 32 MB, ci block of 32 NB, one tap;
 // pixels [k0, k1) of the split in chunks of 16, chunk c to wave c % 4.  The
 // four waves are combined in LDS in wave order; the partial of the split goes
-// to part[split][co][tap][ci] (real channels only).
+// to part[split][co][tap][ci] (real channels only).  The centre-tap tiles of
+// the first ci block also sum their g operand: the bias gradient
+// db[co] = sum over p of g[p][co], at part[split][cout * 9 * cin + co].
 struct WgradArgs {
     const void* g;   // T [P][g_cs]; channels [0, cout_pad) readable
     int g_cs;
@@ -194,12 +196,13 @@ struct WgradArgs {
     int co_blocks, ci_blocks;  // in units of 32 MB / 32 NB
     int P, H, W;
     int chunk_per_split;       // pixels per split (multiple of 64)
-    float* part;     // [splits][cout][9][cin]
+    float* part;     // [splits][cout * 9 * cin + cout]: weights, then the bias
 };
 
 template <typename T, int MB, int NB>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     __shared__ float red[3][MB * NB * 16][64];
+    __shared__ float bred[3][MB][64];
     const int l = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int kg = l >> 5;
@@ -221,6 +224,10 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+    const bool bias_tile = tap == 4 && cib == 0;
+    float bsum[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) bsum[i] = 0.0f;
     int co_l[MB], ci_l[NB];
 #pragma unroll
     for (int i = 0; i < MB; ++i) co_l[i] = (cob * MB + i) * 32 + (l & 31);
@@ -240,7 +247,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) fa[i].set(e, g[(int64_t)(p0 + e) * a.g_cs + co_l[i]]);
+                for (int e = 0; e < 8; ++e) {
+                    const T gv = g[(int64_t)(p0 + e) * a.g_cs + co_l[i]];
+                    fa[i].set(e, gv);
+                    if (bias_tile) bsum[i] += to_f(gv);
+                }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const bool cok = ci_l[j] < a.cin;
@@ -264,16 +275,28 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     }
     if (wave > 0) {
 #pragma unroll
-        for (int i = 0; i < MB; ++i)
+        for (int i = 0; i < MB; ++i) {
 #pragma unroll
             for (int j = 0; j < NB; ++j)
 #pragma unroll
                 for (int q = 0; q < 16; ++q) red[wave - 1][(i * NB + j) * 16 + q][l] = acc[i][j][q];
+            bred[wave - 1][i][l] = bsum[i];
+        }
     }
     __syncthreads();
     if (wave != 0) return;
-    const int64_t slab = (int64_t)a.cout * 9 * a.cin;
+    const int64_t nw = (int64_t)a.cout * 9 * a.cin;
+    const int64_t slab = nw + a.cout;
     float* part = a.part + (int64_t)split * slab;
+    if (bias_tile) {
+        // lanes l and l ^ 32 hold the two 8-pixel halves of the same channel
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+            float v = ((bsum[i] + bred[0][i][l]) + bred[1][i][l]) + bred[2][i][l];
+            v += __shfl_xor(v, 32, 64);
+            if (l < 32 && co_l[i] < a.cout) part[nw + co_l[i]] = v;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -298,29 +321,47 @@ __global__ __launch_bounds__(kEw) void k_sum_splits(const float* __restrict__ pa
     grad[i] = v;
 }
 
-// Bias gradient: db[co] = sum over pixels of g[p][co].  Stage 1: block b sums
-// pixels [b R, (b + 1) R) for every channel; stage 2 sums the blocks in order.
-__global__ __launch_bounds__(kEw) void k_bias_partial(const void* __restrict__ gv, int is_bf16, int g_cs,
-                                                      int cout, int P, int rows, float* __restrict__ part) {
-    const int p0 = blockIdx.x * rows;
-    const int p1 = min(P, p0 + rows);
-    for (int co = threadIdx.x; co < cout; co += kEw) {
-        float v = 0.0f;
-        for (int p = p0; p < p1; ++p) {
-            const int64_t k = (int64_t)p * g_cs + co;
-            v += is_bf16 ? (float)static_cast<const __bf16*>(gv)[k] : static_cast<const float*>(gv)[k];
-        }
-        part[(int64_t)blockIdx.x * cout + co] = v;
+// Column sums over nodes, two stages, fixed order (bias gradients, channel
+// means and their adjoints).  Segment b (blockIdx.y) is the node range
+// [b N, (b + 1) N) of a tensor a[.][cs] (channels [co, co + C)); workgroup x
+// takes nodes [x R, (x + 1) R) of the segment.  Thread t handles channel
+// t % C and node lane t / C of J = kEw / C lanes (C <= kEw); lanes are then
+// combined in lane order into part[b][x][c].
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_colsum_partial(const T* __restrict__ a, int cs, int co, int C, int64_t N,
+                                                        int R, float* __restrict__ part) {
+    __shared__ float red[kEw];
+    const int J = kEw / C;
+    const int t = threadIdx.x;
+    const int c = t % C, j = t / C;
+    const int64_t seg = blockIdx.y;
+    const int64_t p0 = (int64_t)blockIdx.x * R;
+    const int64_t p1 = p0 + R < N ? p0 + R : N;
+    float v = 0.0f;
+    if (j < J)
+        for (int64_t p = p0 + j; p < p1; p += J) v += to_f(a[(seg * N + p) * cs + co + c]);
+    red[t] = v;
+    __syncthreads();
+    if (t < C) {
+        float s = 0.0f;
+        for (int k = 0; k < J; ++k) s += red[k * C + t];
+        part[(seg * gridDim.x + blockIdx.x) * C + t] = s;
     }
 }
 
-__global__ __launch_bounds__(kEw) void k_bias_final(const float* __restrict__ part, int nblk, int cout,
-                                                    float* __restrict__ db) {
-    const int co = blockIdx.x * kEw + threadIdx.x;
-    if (co >= cout) return;
-    float v = 0.0f;
-    for (int b = 0; b < nblk; ++b) v += part[(int64_t)b * cout + co];
-    db[co] = v;
+// out[b][c] = scale * sum over the nblk partials of segment b (in order),
+// written as float (fout) or as T (tout).
+template <typename T>
+__global__ __launch_bounds__(kEw) void k_colsum_final(const float* __restrict__ part, int nblk, int C, int B,
+                                                      float scale, float* __restrict__ fout, T* __restrict__ tout) {
+    const int i = blockIdx.x * kEw + threadIdx.x;
+    if (i >= B * C) return;
+    const int b = i / C, c = i % C;
+    float s = 0.0f;
+    for (int k = 0; k < nblk; ++k) s += part[((int64_t)b * nblk + k) * C + c];
+    s *= scale;
+    if (fout) fout[i] = s;
+    if (tout) tout[i] = from_f<T>(s);
 }
 
 // ------------------------------------------------------------------ pooling, upsampling
@@ -383,19 +424,6 @@ __global__ __launch_bounds__(kEw) void k_upsample_back(const T* __restrict__ g, 
     out[q * C + c] = from_f<T>(to_f(act[q * C + c]) > 0.0f ? v : 0.0f);
 }
 
-// Global context: m[b][c] = mean over the N nodes of sample b of a[p][c]
-// (summed in node order, one thread per (b, c)).
-template <typename T>
-__global__ __launch_bounds__(kEw) void k_channel_mean(const T* __restrict__ a, int C, int N, int B,
-                                                      T* __restrict__ m) {
-    const int i = blockIdx.x * kEw + threadIdx.x;
-    if (i >= B * C) return;
-    const int b = i / C, c = i % C;
-    float v = 0.0f;
-    for (int p = 0; p < N; ++p) v += to_f(a[((int64_t)b * N + p) * C + c]);
-    m[i] = from_f<T>(v / (float)N);
-}
-
 // out[p][out_co + c] = m[b(p)][c] for every node p of a level with N nodes per sample.
 template <typename T>
 __global__ __launch_bounds__(kEw) void k_broadcast(const T* __restrict__ m, int C, T* __restrict__ out, int out_cs,
@@ -405,19 +433,6 @@ __global__ __launch_bounds__(kEw) void k_broadcast(const T* __restrict__ m, int 
     const int c = (int)(i % C);
     const int64_t p = i / C;
     out[p * out_cs + out_co + c] = m[(p / N) * C + c];
-}
-
-// Adjoint of the broadcast: gm[b][c] = sum over the N nodes of sample b of
-// g[p][g_co + c] (node order, one thread per (b, c)).
-template <typename T>
-__global__ __launch_bounds__(kEw) void k_broadcast_back(const T* __restrict__ g, int g_cs, int g_co, int C, int N,
-                                                        int B, float* __restrict__ gm) {
-    const int i = blockIdx.x * kEw + threadIdx.x;
-    if (i >= B * C) return;
-    const int b = i / C, c = i % C;
-    float v = 0.0f;
-    for (int p = 0; p < N; ++p) v += to_f(g[((int64_t)b * N + p) * g_cs + g_co + c]);
-    gm[i] = v;
 }
 
 // Encoder skip: out[p][c] = (g_low[parent][c] / 4 + g_cat[p][skip_co + c]) *
@@ -656,15 +671,30 @@ __global__ __launch_bounds__(kEw) void k_loss_partial(const float* __restrict__ 
     }
 }
 
-__global__ void k_loss_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One workgroup: thread t sums the partials [t K, (t + 1) K) in order, then a
+// fixed tree combines the threads.
+__global__ __launch_bounds__(kEw) void k_loss_final(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    __shared__ double s1[kEw], s2[kEw];
+    const int K = (nblk + kEw - 1) / kEw;
     double a = 0.0, c = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = threadIdx.x * K; b < (threadIdx.x + 1) * K && b < nblk; ++b) {
         a += part[2 * b];
         c += part[2 * b + 1];
     }
-    out[0] = c > 0.0 ? a / (3.0 * c) : 0.0;
-    out[1] = c;
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = kEw / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            s1[threadIdx.x] += s1[threadIdx.x + off];
+            s2[threadIdx.x] += s2[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s2[0] > 0.0 ? s1[0] / (3.0 * s2[0]) : 0.0;
+        out[1] = s2[0];
+    }
 }
 
 template <typename T>

@@ -384,6 +384,60 @@ def evaluate(cases, net, tol=1e-8, tol_stop=1e-9, tol_ref=1e-11, check=100, cap=
     return out
 
 
+# --------------------------------------------------------------------- throughput
+def network_flops(h, w, ch=CH):
+    """Algorithmic FLOPs of one sample through the network: forward (every 3x3
+    convolution at its level, real channel counts) and a training step
+    (forward, input gradients of layers 1..14, weight gradients)."""
+    c0, c1, c2, c3 = ch
+    layers = [(2, c0, 0), (c0, c0, 0), (c0, c1, 1), (c1, c1, 1), (c1, c2, 2), (c2, c2, 2), (c2, c3, 3),
+              (c3, c3, 3), (2 * c3 + c2, c2, 2), (c2, c2, 2), (c2 + c1, c1, 1), (c1, c1, 1), (c1 + c0, c0, 0),
+              (c0, c0, 0), (c0, 3, 0)]
+    fwd = [2 * 9 * ci * co * (h >> l) * (w >> l) for ci, co, l in layers]
+    return sum(fwd), sum(fwd) + sum(fwd[1:]) + sum(fwd)
+
+
+def network_throughput(h=128, w=256, batch=8, steps=40, dtype="bf16", seed=0):
+    """Training steps per second of the network on synthetic fields (the
+    arithmetic does not depend on the values), and inference time per batch.
+    Returns a dict with algorithmic TFLOP/s."""
+    import torch
+
+    dev = "cuda"
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    n = 4 * batch
+    data = {"solid": (torch.rand((n, h, w), generator=g) < 0.05).to(torch.uint8).to(dev),
+            "rho": (1 + 1e-3 * torch.randn((n, h, w), generator=g)).float().to(dev),
+            "ux": (0.02 * torch.rand((n, h, w), generator=g)).float().to(dev),
+            "uy": (0.002 * torch.randn((n, h, w), generator=g)).float().to(dev),
+            "re": (1 + 99 * torch.rand(n, generator=g)).double().to(dev),
+            "gx": torch.full((n,), 2e-6, dtype=torch.float64, device=dev),
+            "tau": torch.full((n,), 0.6, dtype=torch.float64, device=dev)}
+    net = lbm.WarmStartNet(h, w, batch, dtype=dtype, ch=CH, rho_scale=0.01)
+    net.set_params(torch.from_numpy(init_params(seed)))
+    idx = [torch.arange(k * batch, (k + 1) * batch, dtype=torch.int32, device=dev) for k in range(4)]
+    for k in range(3):
+        net.train_step(data, idx[k % 4], 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        net.train_step(data, idx[k % 4], 1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    solid, re, gx, tau = data["solid"][:batch].contiguous(), data["re"][:batch], data["gx"][:batch], data["tau"][:batch]
+    net.infer(solid, re, gx, tau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        net.infer(solid, re, gx, tau)
+    torch.cuda.synchronize()
+    di = (time.perf_counter() - t0) / steps
+    f_fwd, f_train = network_flops(h, w)
+    return {"batch": batch, "dtype": dtype, "train_step_ms": dt * 1e3, "infer_ms": di * 1e3,
+            "train_tflops": batch * f_train / dt / 1e12, "infer_tflops": batch * f_fwd / di / 1e12,
+            "gflop_per_sample_forward": f_fwd / 1e9, "gflop_per_sample_train": f_train / 1e9}
+
+
 # --------------------------------------------------------------------- command line
 def load_net(path, max_batch=8, dtype="bf16"):
     """A WarmStartNet with the weights of a weights file."""
