@@ -214,6 +214,37 @@ void conv(lbm_nn* n, int level, const void* in, int in_cs, int cin, const void* 
     a.H = p.H >> level;
     a.W = p.W >> level;
     a.P = (int)((int64_t)n->batch * a.H * a.W);
+    a.out_f32 = sizeof(OT) == 4 ? 1 : 0;
+    if (sizeof(T) == 2) {
+        // BF16: LDS-staged tiles (BM x BN).  The widest tile that divides the
+        // output channels and still gives >= 512 workgroups (two per CU),
+        // otherwise the tile with the most workgroups.
+        struct Shape { int bm, bn; };
+        const Shape shapes[5] = {{128, 128}, {128, 64}, {256, 32}, {64, 64}, {128, 32}};
+        int pick = -1, most = -1;
+        int64_t most_wg = -1;
+        for (int k = 0; k < 5; ++k) {
+            if (cout_pad % shapes[k].bn) continue;
+            const int64_t wg = (int64_t)blocks(a.P, shapes[k].bm) * (cout_pad / shapes[k].bn);
+            if (pick < 0 && wg >= 512) pick = k;
+            if (wg > most_wg) { most_wg = wg; most = k; }
+        }
+        if (pick < 0) pick = most;
+        const bool bk32 = cin % 32 == 0;
+        dim3 g(blocks(a.P, shapes[pick].bm), cout_pad / shapes[pick].bn);
+#define CONV_LDS_LAUNCH(MW, NW, WM, WN)                                                   \
+    if (bk32) k_conv_lds<MW, NW, WM, WN, 32><<<g, 256, 0, n->st>>>(a);                    \
+    else k_conv_lds<MW, NW, WM, WN, 16><<<g, 256, 0, n->st>>>(a);
+        switch (pick) {
+            case 0: CONV_LDS_LAUNCH(2, 2, 2, 2) break;
+            case 1: CONV_LDS_LAUNCH(2, 2, 2, 1) break;
+            case 2: CONV_LDS_LAUNCH(4, 1, 2, 1) break;
+            case 3: CONV_LDS_LAUNCH(2, 2, 1, 1) break;
+            default: CONV_LDS_LAUNCH(4, 1, 1, 1) break;
+        }
+#undef CONV_LDS_LAUNCH
+        return;
+    }
     if (cout_pad % 64 == 0) {
         dim3 g(blocks(a.P, 32 * 2 * kConvWaves), cout_pad / 64);
         k_conv<T, OT, 2, 2><<<g, kConvWaves * 64, 0, n->st>>>(a);

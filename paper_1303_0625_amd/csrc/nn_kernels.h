@@ -94,6 +94,7 @@ struct ConvArgs {
     int mask_cs, mask_co;
     int relu;
     int P, H, W;           // P = B * H * W pixels of this level
+    int out_f32;           // k_conv_lds: store the output as float (network head)
 };
 
 // Workgroup: kConvWaves waves; wave w takes pixels
@@ -175,6 +176,136 @@ __global__ __launch_bounds__(kConvWaves * 64) void k_conv(ConvArgs a) {
                 if (a.relu) v = v > 0.0f ? v : 0.0f;
                 if (mask && !(to_f(mask[(int64_t)p * a.mask_cs + a.mask_co + n]) > 0.0f)) v = 0.0f;
                 out[(int64_t)p * a.out_cs + a.out_co + n] = from_f<OT>(v);
+            }
+    }
+}
+
+// One 16-byte A segment of the BF16 convolution: 8 channels from c of node
+// (b, yy, xx) with x periodic, zero outside the walls or for b < 0.
+__device__ __forceinline__ uint4 conv_load_a(const __bf16* in, int b, int yy, int xx, int H, int W, int cs, int c) {
+    xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+    if (b >= 0 && yy >= 0 && yy < H) return *reinterpret_cast<const uint4*>(in + ((int64_t)(b * H + yy) * W + xx) * cs + c);
+    return make_uint4(0, 0, 0, 0);
+}
+
+// BF16 convolution with LDS-staged operands.  Workgroup tile: BM = 32 WM MW
+// pixels x BN = 32 WN NW output channels, four waves in an MW x NW grid, each
+// owning WM x WN MFMA blocks.  The K loop runs over stages of one tap x BK
+// input channels: the stage's A tile (BM pixels, shifted by the tap, zero
+// outside the walls) and B tile (BN weight rows) are read from global memory
+// into registers while the MFMAs of the previous stage run from LDS, then
+// written to the other of two LDS buffers (rows padded by 8 elements), with
+// one barrier per stage.  Same arguments and epilogue as k_conv.
+template <int MW, int NW, int WM, int WN, int BK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_conv_lds(ConvArgs a) {
+    static_assert(MW * NW == 4, "four waves");
+    constexpr int BM = 32 * WM * MW, BN = 32 * WN * NW;
+    constexpr int LDK = BK + 8;                 // padded LDS row (elements)
+    constexpr int SEG = BK / 8;                 // 16-byte segments per row
+    constexpr int A_SEGS = BM * SEG, B_SEGS = BN * SEG;
+    constexpr int A_PER = (A_SEGS + 255) / 256, B_PER = (B_SEGS + 255) / 256;
+    __shared__ __align__(16) __bf16 As[2][BM * LDK];
+    __shared__ __align__(16) __bf16 Bs[2][BN * LDK];
+    const int t = threadIdx.x;
+    const int l = t & 63, wave = t >> 6;
+    const int wm = wave % MW, wn = wave / MW;
+    const int kg = l >> 5;
+    const int pbase = blockIdx.x * BM;
+    const int nbase = blockIdx.y * BN;
+    const __bf16* in = static_cast<const __bf16*>(a.in);
+    const __bf16* w = static_cast<const __bf16*>(a.w);
+    const int HW = a.H * a.W;
+    // the A rows this thread loads, and their (b, y, x)
+    int ar[A_PER], as_[A_PER], ab[A_PER], ay[A_PER], ax[A_PER];
+#pragma unroll
+    for (int r = 0; r < A_PER; ++r) {
+        const int id = t + 256 * r;
+        ar[r] = id / SEG;
+        as_[r] = id % SEG;
+        const int p = pbase + ar[r];
+        const int b = p / HW, rem = p - b * HW;
+        ab[r] = (id < A_SEGS && p < a.P) ? b : -1;
+        ay[r] = rem / a.W;
+        ax[r] = rem - ay[r] * a.W;
+    }
+    int br[B_PER], bsg[B_PER];
+#pragma unroll
+    for (int r = 0; r < B_PER; ++r) {
+        const int id = t + 256 * r;
+        br[r] = id < B_SEGS ? id / SEG : -1;
+        bsg[r] = id % SEG;
+    }
+    const int kchunks = a.cin / BK;
+    const int nst = 9 * kchunks;
+    const int wrow = 9 * a.cin;
+    uint4 ra[A_PER], rb[B_PER];
+    f32x16 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+#define CONV_LDS_GLOAD(ST)                                                                                     \
+    {                                                                                                          \
+        const int tap_ = (ST) / kchunks, c0_ = ((ST) - tap_ * kchunks) * BK;                                    \
+        const int dy_ = tap_ / 3 - 1, dx_ = tap_ % 3 - 1;                                                      \
+        _Pragma("unroll") for (int r = 0; r < A_PER; ++r) ra[r] =                                                \
+            conv_load_a(in, ab[r], ay[r] + dy_, ax[r] + dx_, a.H, a.W, a.in_cs, c0_ + 8 * as_[r]);              \
+        _Pragma("unroll") for (int r = 0; r < B_PER; ++r) if (br[r] >= 0) rb[r] =                                \
+            *reinterpret_cast<const uint4*>(w + (int64_t)(nbase + br[r]) * wrow + tap_ * a.cin + c0_ + 8 * bsg[r]); \
+    }
+#define CONV_LDS_LSTORE(BUF)                                                                                   \
+    {                                                                                                          \
+        _Pragma("unroll") for (int r = 0; r < A_PER; ++r) if (t + 256 * r < A_SEGS)                              \
+            *reinterpret_cast<uint4*>(&As[BUF][ar[r] * LDK + 8 * as_[r]]) = ra[r];                              \
+        _Pragma("unroll") for (int r = 0; r < B_PER; ++r) if (br[r] >= 0)                                        \
+            *reinterpret_cast<uint4*>(&Bs[BUF][br[r] * LDK + 8 * bsg[r]]) = rb[r];                              \
+    }
+    CONV_LDS_GLOAD(0)
+    CONV_LDS_LSTORE(0)
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) CONV_LDS_GLOAD(st + 1)
+#pragma unroll
+        for (int kk = 0; kk < BK / 16; ++kk) {
+            Frag<__bf16> fa[WM], fb[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+                fa[i].v = *reinterpret_cast<const bf16x8*>(&As[buf][((wm * WM + i) * 32 + (l & 31)) * LDK + kk * 16 + 8 * kg]);
+#pragma unroll
+            for (int j = 0; j < WN; ++j)
+                fb[j].v = *reinterpret_cast<const bf16x8*>(&Bs[buf][((wn * WN + j) * 32 + (l & 31)) * LDK + kk * 16 + 8 * kg]);
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) mma(acc[i][j], fa[i], fb[j]);
+        }
+        if (st + 1 < nst) CONV_LDS_LSTORE(buf ^ 1)
+        __syncthreads();
+    }
+#undef CONV_LDS_GLOAD
+#undef CONV_LDS_LSTORE
+    const __bf16* mask = static_cast<const __bf16*>(a.mask);
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        const int n = nbase + (wn * WN + j) * 32 + (l & 31);
+        if (n >= a.cout) continue;
+        const float bv = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int p = pbase + (wm * WM + i) * 32 + acc_row(q, l);
+                if (p >= a.P) continue;
+                float v = acc[i][j][q] + bv;
+                if (a.relu) v = v > 0.0f ? v : 0.0f;
+                if (mask && !(to_f(mask[(int64_t)p * a.mask_cs + a.mask_co + n]) > 0.0f)) v = 0.0f;
+                if (a.out_f32)
+                    static_cast<float*>(a.out)[(int64_t)p * a.out_cs + a.out_co + n] = v;
+                else
+                    static_cast<__bf16*>(a.out)[(int64_t)p * a.out_cs + a.out_co + n] = (__bf16)v;
             }
     }
 }
