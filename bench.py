@@ -32,7 +32,7 @@ METRIC = "MLUPS and % HBM roofline; time-to-steady drag at 1e-4 (learned+mixed v
 BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
-def stored_traffic(workload: str, kernel: str = "k_fused"):
+def stored_traffic(workload: str, kernel: str = "k_fused", family: str = "lbm"):
     """HBM bytes per launch of a time-step kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size);
     None when absent or taken on other kernel sources."""
@@ -43,7 +43,7 @@ def stored_traffic(workload: str, kernel: str = "k_fused"):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_hash") != source_hash():
+    if rec.get("kernel_source_hash") != source_hash(family):
         return None
     return round(rec.get("hbm_bytes_per_launch"))
 

@@ -386,6 +386,21 @@ lbm_status lbm_nn_forward(lbm_nn* nn, const float* d_x, int32_t batch, float* d_
  * the last lbm_nn_forward; gy [batch][h][w][3] FP32 device memory. */
 lbm_status lbm_nn_backward(lbm_nn* nn, const float* d_gy);
 
+/* Weight and bias gradient of one layer alone, for inspection and tests of
+ * the weight-gradient kernels: dW[co][ky][kx][ci] = sum over pixels p of
+ * g[p][co] x[p + (ky - 1, kx - 1)][ci] (x periodic, y zero outside the
+ * image) and db[co] = sum over p of g[p][co], in FP32 accumulation.  x is
+ * the layer's input at its level, [batch][h_l][w_l][x_cs] in the network's
+ * compute type (channels [0, cin) used; x_cs >= cin, >= 16 for layer 0), g
+ * the pre-activation gradient [batch][h_l][w_l][g_cs] (channels [0, cout)
+ * used; g_cs >= cout rounded up to 32); both strides multiples of 8, both
+ * tensors 16-byte aligned device memory.  d_grad (device, FP32) receives
+ * cout * 9 * cin weights then cout biases, the layout of the layer in the
+ * parameter vector.  Layer levels: 0,0,1,1,2,2,3,3,2,2,1,1,0,0,0.  Leaves the
+ * network's own gradient and last batch untouched; synchronises. */
+lbm_status lbm_nn_layer_wgrad(lbm_nn* nn, int32_t layer, int32_t batch, const void* d_x, int32_t x_cs,
+                              const void* d_g, int32_t g_cs, float* d_grad);
+
 /* One Adam step (Kingma and Ba, bias-corrected) on the current gradient. */
 lbm_status lbm_nn_adam(lbm_nn* nn, double lr, double beta1, double beta2, double eps);
 

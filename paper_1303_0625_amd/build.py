@@ -21,14 +21,15 @@ FLAGS = [
 ]
 
 
-def source_hash() -> str:
-    """Short hash of the kernel sources (ties measurements to a kernel version)."""
+def source_hash(family: str = "lbm") -> str:
+    """Short hash of one kernel family's sources (ties a measurement to that
+    kernel version): "lbm" = the lattice solver files, "nn" = the network."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip")):
+        if f.startswith(family + "_") and f.endswith((".h", ".hip")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]

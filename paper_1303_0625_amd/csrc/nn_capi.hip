@@ -50,6 +50,7 @@ struct Plan {
     BufShape shape[NBUF];
     LayerDev L[kLayers];
     int64_t n_params, wf_total, wt_total, b_total;
+    int level[kLayers];  // level of each layer's input
     int64_t wpart_max;  // floats of the largest weight-gradient partial
     int64_t bpart_max;  // floats of the largest bias partial
     size_t off[NBUF];
@@ -69,6 +70,36 @@ void wgrad_split(const Plan& p, int level, int tiles, int& splits, int& chunk) {
 }
 
 int mb_of(int cout_pad) { return cout_pad % 64 == 0 ? 2 : 1; }
+
+// The nine-tap weight-gradient kernel takes BF16 levels whose row length is
+// a multiple of its tile.
+bool wgrad9_ok(const Plan& p, int level) { return p.es == 2 && ((p.W >> level) % kWgTile) == 0; }
+
+// Splits of the nine-tap kernel: the count that minimises a cost model of
+// the products (tiles per split times the per-tile time of one workgroup,
+// in rounds of 512 workgroups) plus the split partials written and read.
+// Rates are those measured for this kernel on MI355X: ~3 TFLOP/s per
+// workgroup of 6 waves (2.25 of 3), partial round trip ~5 TB/s.
+void wgrad9_split(int64_t ntiles, int pairs, int mb, int nb, int64_t nwb, int& splits, int& tps) {
+    const double tile_flop = 2.0 * kWgTile * (32.0 * mb) * (32.0 * nb) * 9.0;
+    const double rate = 3.0e12 * (nb == 2 ? 1.0 : 0.75);
+    double best = 1e300;
+    splits = 1;
+    tps = (int)ntiles;
+    const int smax = (int)std::min<int64_t>(ntiles, 1024);
+    for (int s = 1; s <= smax; ++s) {
+        const int64_t tp = (ntiles + s - 1) / s;
+        const int64_t sp = (ntiles + tp - 1) / tp;
+        const int64_t wgs = sp * pairs;
+        const double rounds = (double)((wgs + 511) / 512);
+        const double est = rounds * (double)tp * tile_flop / rate + 8.0 * (double)sp * (double)nwb / 5.0e12;
+        if (est < best - 1e-12) {
+            best = est;
+            splits = (int)sp;
+            tps = (int)tp;
+        }
+    }
+}
 
 const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
     if (cfg.h < 8 || cfg.h % 8 != 0) return "h must be a positive multiple of 8";
@@ -98,6 +129,7 @@ const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
     p.wpart_max = 1;
     p.bpart_max = 1;
     const int level_in[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+    for (int k = 0; k < kLayers; ++k) p.level[k] = level_in[k];
     for (int k = 0; k < kLayers; ++k) {
         LayerDev& L = p.L[k];
         L.off = off;
@@ -114,10 +146,18 @@ const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
         wt += (int64_t)L.cin_dg * 9 * L.cout_pad;
         bo += L.cout_pad;
         const int mb = mb_of(L.cout_pad), nbk = L.cin_dg % 64 == 0 ? 2 : 1;
-        const int tiles = (L.cout_pad / (32 * mb)) * (L.cin_dg / (32 * nbk)) * 9;
-        int splits, chunk;
-        wgrad_split(p, level_in[k], tiles, splits, chunk);
-        p.wpart_max = std::max<int64_t>(p.wpart_max, (int64_t)splits * (cout[k] * 9 * cin[k] + cout[k]));
+        const int pairs = (L.cout_pad / (32 * mb)) * (L.cin_dg / (32 * nbk));
+        const int64_t nwb = (int64_t)cout[k] * 9 * cin[k] + cout[k];
+        for (int b = 1; b <= p.B; ++b) {
+            Plan q = p;
+            q.B = b;
+            int splits, chunk;
+            if (wgrad9_ok(q, level_in[k]))
+                wgrad9_split(pixels(q, level_in[k]) / kWgTile, pairs, mb, nbk, nwb, splits, chunk);
+            else
+                wgrad_split(q, level_in[k], pairs * 9, splits, chunk);
+            p.wpart_max = std::max<int64_t>(p.wpart_max, (int64_t)splits * nwb);
+        }
     }
     // channel means of the bottleneck and their adjoint (per sample, c3 wide)
     p.bpart_max = std::max<int64_t>(p.bpart_max, (int64_t)p.B * ((pixels(p, 2) / p.B + 255) / 256) * c3);
@@ -284,17 +324,50 @@ void layer_dgrad(lbm_nn* n, int k, int level, Buf g_pre, Buf g_in, Buf act, int 
                act_co);
 }
 
-// Weight and bias gradient of layer k from its forward input x (at `level`)
-// and its pre-activation gradient g.
+// Weight and bias gradient of layer k from its forward input x (at `level`,
+// channel stride x_cs) and its pre-activation gradient g (stride g_cs), for
+// the batch of the last forward; the sum goes to out[cout * 9 * cin + cout].
 template <typename T>
-void layer_wgrad(lbm_nn* n, int k, int level, Buf x, Buf g) {
+void layer_wgrad_ptr(lbm_nn* n, int k, int level, const void* xp, int x_cs, const void* gp, int g_cs, float* out) {
     const Plan& p = n->p;
     const LayerDev& L = p.L[k];
+    const int64_t nwb = (int64_t)L.cout * 9 * L.cin + L.cout;  // weights and bias, contiguous
+    Plan q = p;
+    q.B = n->batch;
+    if (wgrad9_ok(q, level)) {
+        Wgrad9Args a;
+        a.g = static_cast<const __bf16*>(gp);
+        a.g_cs = g_cs;
+        a.x = static_cast<const __bf16*>(xp);
+        a.x_cs = x_cs;
+        a.cout = L.cout;
+        a.cin = L.cin;
+        a.H = p.H >> level;
+        a.W = p.W >> level;
+        const int mb = mb_of(L.cout_pad), nbk = L.cin_dg % 64 == 0 ? 2 : 1;
+        const int co_blocks = L.cout_pad / (32 * mb);
+        a.ci_blocks = L.cin_dg / (32 * nbk);
+        a.ntiles = (int)(pixels(q, level) / kWgTile);
+        int splits;
+        wgrad9_split(a.ntiles, co_blocks * a.ci_blocks, mb, nbk, nwb, splits, a.tps);
+        a.part = at<float>(n, p.o_wpart);
+        const dim3 gr(co_blocks * a.ci_blocks, splits);
+        if (mb == 2 && nbk == 2)
+            k_wgrad9<2, 2><<<gr, 192 * 2, 0, n->st>>>(a);
+        else if (mb == 2)
+            k_wgrad9<2, 1><<<gr, 192, 0, n->st>>>(a);
+        else if (nbk == 2)
+            k_wgrad9<1, 2><<<gr, 192 * 2, 0, n->st>>>(a);
+        else
+            k_wgrad9<1, 1><<<gr, 192, 0, n->st>>>(a);
+        k_sum_splits<<<blocks(nwb, kSumCols), kEw, 0, n->st>>>(a.part, splits, nwb, out);
+        return;
+    }
     WgradArgs a;
-    a.g = buf(n, g);
-    a.g_cs = p.shape[g].ch;
-    a.x = buf(n, x);
-    a.x_cs = p.shape[x].ch;
+    a.g = gp;
+    a.g_cs = g_cs;
+    a.x = xp;
+    a.x_cs = x_cs;
     a.cout = L.cout;
     a.cin = L.cin;
     a.H = p.H >> level;
@@ -305,9 +378,6 @@ void layer_wgrad(lbm_nn* n, int k, int level, Buf x, Buf g) {
     a.ci_blocks = L.cin_dg / (32 * nbk);
     const int tiles = a.co_blocks * a.ci_blocks * 9;
     int splits, chunk;
-    // split against the planned batch so the partial buffer always fits
-    Plan q = p;
-    q.B = n->batch;
     wgrad_split(q, level, tiles, splits, chunk);
     a.chunk_per_split = chunk;
     a.part = at<float>(n, p.o_wpart);
@@ -320,9 +390,14 @@ void layer_wgrad(lbm_nn* n, int k, int level, Buf x, Buf g) {
         k_wgrad<T, 1, 2><<<gr, 256, 0, n->st>>>(a);
     else
         k_wgrad<T, 1, 1><<<gr, 256, 0, n->st>>>(a);
-    // weights and bias are contiguous in the parameter vector and in each split's partial
-    const int64_t nwb = (int64_t)L.cout * 9 * L.cin + L.cout;
-    k_sum_splits<<<blocks(nwb), kEw, 0, n->st>>>(a.part, splits, nwb, at<float>(n, p.o_grad) + L.off);
+    k_sum_splits<<<blocks(nwb, kSumCols), kEw, 0, n->st>>>(a.part, splits, nwb, out);
+}
+
+template <typename T>
+void layer_wgrad(lbm_nn* n, int k, int level, Buf x, Buf g) {
+    const Plan& p = n->p;
+    layer_wgrad_ptr<T>(n, k, level, buf(n, x), p.shape[x].ch, buf(n, g), p.shape[g].ch,
+                       at<float>(n, p.o_grad) + p.L[k].off);
 }
 
 template <typename T>
@@ -634,6 +709,33 @@ lbm_status lbm_nn_backward(lbm_nn* n, const float* d_gy) {
     else
         k_pack_head_grad<float><<<blocks(P), kEw, 0, n->st>>>(d_gy, P, (float*)buf(n, G_HEAD));
     backward(n);
+    return sync_check(n);
+}
+
+lbm_status lbm_nn_layer_wgrad(lbm_nn* n, int32_t layer, int32_t batch, const void* d_x, int32_t x_cs,
+                              const void* d_g, int32_t g_cs, float* d_grad) {
+    if (!n || !d_x || !d_g || !d_grad) return LBM_EINVAL;
+    if (layer < 0 || layer >= kLayers) {
+        nn_set_err(n->err, "layer must be in [0, %d)", kLayers);
+        return LBM_EINVAL;
+    }
+    lbm_status rs = check_batch(n, batch);
+    if (rs != LBM_OK) return rs;
+    const LayerDev& L = n->p.L[layer];
+    const int xmin = layer == 0 ? 16 : L.cin;
+    if (x_cs < xmin || x_cs % 8 != 0 || g_cs < L.cout_pad || g_cs % 8 != 0 ||
+        ((uintptr_t)d_x | (uintptr_t)d_g) % 16 != 0) {
+        nn_set_err(n->err, "layer %d needs x_cs >= %d and g_cs >= %d, multiples of 8, 16-byte aligned tensors", layer,
+                   xmin, L.cout_pad);
+        return LBM_EINVAL;
+    }
+    const int last = n->batch;  // the batch of the last forward stays that of the network
+    n->batch = batch;
+    if (n->dtype == LBM_BF16)
+        layer_wgrad_ptr<__bf16>(n, layer, n->p.level[layer], d_x, x_cs, d_g, g_cs, d_grad);
+    else
+        layer_wgrad_ptr<float>(n, layer, n->p.level[layer], d_x, x_cs, d_g, g_cs, d_grad);
+    n->batch = last;
     return sync_check(n);
 }
 

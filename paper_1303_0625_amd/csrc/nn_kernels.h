@@ -442,14 +442,243 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
             }
 }
 
-// grad[i] = sum over splits s (in order) of part[s][i], i < n.
+// Weight gradient with all nine taps in one workgroup (BF16).  A tile is
+// kWgTile consecutive pixels of one image row (b, y, [x0, x0 + kWgTile)).
+// The workgroup stages, transposed to channel-major so that a lane's eight
+// consecutive pixels are one 16-byte LDS vector, the tile's g (its 32 MB
+// output channels) and x of rows y - 1, y, y + 1 over columns
+// [x0 - 4, x0 + kWgTile + 4) (x periodic, rows outside the image zero), its
+// 32 NB input channels.  Wave (j, r) takes input block j and row offset
+// dy = r - 1 for all three dx and all MB output blocks: the dx = -1 and +1
+// operands are the dx = 0 vector shifted by one pixel, with the neighbouring
+// pixel taken from the words before and after it, so the g operand and the
+// x vector are read once for three products.  Tiles [split * tps, + tps)
+// go through a double-buffered LDS stage (next tile's global loads in
+// registers during the products).  Partial sums go to part[split] as for
+// k_wgrad; the first input block of a split also sums g into the bias slot,
+// per channel group in pixel order, then over the groups in order.
+constexpr int kWgTile = 32;                // pixels per tile
+constexpr int kWgXPitch = kWgTile + 24;    // x row: halo 4 + 4 guard + tile + 4 + 12 (odd multiple of 16 B)
+constexpr int kWgGPitch = kWgTile + 8;     // g row (odd multiple of 16 B)
+constexpr int kWgGroups = kWgTile / 4 + 2; // 4-pixel column groups of an x row (with halos)
+
+struct Wgrad9Args {
+    const __bf16* g;  // [P][g_cs]; channels [0, cout_pad) readable
+    int g_cs;
+    const __bf16* x;  // [P][x_cs]; channels [0, cin) read, x_cs and the offset multiples of 8
+    int x_cs;
+    int cout, cin;    // real channel counts
+    int ci_blocks;    // input blocks of 32 NB channels
+    int H, W;         // level size; W a multiple of kWgTile
+    int ntiles;       // B * H * W / kWgTile
+    int tps;          // tiles per split
+    float* part;      // [splits][cout * 9 * cin + cout]
+};
+
+__device__ inline uint32_t lo_pair(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
+__device__ inline uint32_t hi_pair(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
+// bf16 elements (1..8) of the 9 consecutive ones (w0.lo .. w4.lo): a shift by one element
+__device__ inline uint32_t shift1(uint32_t a, uint32_t b) { return (a >> 16) | (b << 16); }
+
+template <int MB, int NB>
+__global__ __launch_bounds__(192 * NB) void k_wgrad9(Wgrad9Args a) {
+    constexpr int NT = 192 * NB;
+    constexpr int NG = (kWgTile / 4) * 4 * MB;   // g units: 4 pixels x 8 channels
+    constexpr int NX = 3 * kWgGroups * 4 * NB;   // x units
+    static_assert(NG + NX <= NT, "one staging unit per thread");
+    __shared__ __align__(16) __bf16 Xs[2][3][32 * NB][kWgXPitch];
+    __shared__ __align__(16) __bf16 Gs[2][32 * MB][kWgGPitch];
+    __shared__ float bred[kWgTile / 4][32 * MB];
+    const int t = threadIdx.x;
+    const int l = t & 63;
+    const int wave = t >> 6;
+    const int wj = wave / 3, wr = wave % 3;
+    const int cob = blockIdx.x / a.ci_blocks, cib = blockIdx.x % a.ci_blocks;
+    const int split = blockIdx.y;
+    const int nseg = a.W / kWgTile;
+    const int t0 = split * a.tps;
+    const int t1 = min(a.ntiles, t0 + a.tps);
+    const bool bias_wg = cib == 0;
+
+    // this thread's staging unit
+    const bool is_g = t < NG;
+    const bool is_x = !is_g && t < NG + NX;
+    int u_ch, u_grp, u_row;  // channel group (8 channels), pixel group, x row (0..2)
+    if (is_g) {
+        u_ch = t % (4 * MB);
+        u_grp = t / (4 * MB);
+        u_row = 0;
+    } else {
+        const int v = t - NG;
+        u_ch = v % (4 * NB);
+        u_grp = (v / (4 * NB)) % kWgGroups;
+        u_row = v / (4 * NB * kWgGroups);
+    }
+    const int gch = cob * 32 * MB + 8 * u_ch;             // g channel of the unit
+    const int xch = cib * 32 * NB + 8 * u_ch;             // x channel of the unit
+    const bool x_ok = is_x && xch < a.cin;                 // group holds real channels
+    float bsum[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) bsum[c] = 0.0f;
+    uint4 reg[4];
+
+    auto gload = [&](int tile) {
+        const int seg = tile % nseg;
+        const int row = tile / nseg;  // b * H + y
+        const int x0 = seg * kWgTile;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) reg[e] = make_uint4(0u, 0u, 0u, 0u);
+        if (is_g) {
+            const int64_t p = (int64_t)row * a.W + x0 + 4 * u_grp;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                reg[e] = *reinterpret_cast<const uint4*>(a.g + (p + e) * a.g_cs + gch);
+        } else if (x_ok) {
+            const int b = row / a.H;
+            const int yy = row - b * a.H + u_row - 1;
+            if (yy >= 0 && yy < a.H) {
+                int xx = x0 - 4 + 4 * u_grp;
+                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+                const int64_t p = ((int64_t)b * a.H + yy) * a.W + xx;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    reg[e] = *reinterpret_cast<const uint4*>(a.x + (p + e) * a.x_cs + xch);
+            }
+        }
+    };
+    auto lstore = [&](int buf) {
+        if (!is_g && !is_x) return;
+        const uint32_t w[4][4] = {{reg[0].x, reg[0].y, reg[0].z, reg[0].w},
+                                  {reg[1].x, reg[1].y, reg[1].z, reg[1].w},
+                                  {reg[2].x, reg[2].y, reg[2].z, reg[2].w},
+                                  {reg[3].x, reg[3].y, reg[3].z, reg[3].w}};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // channels 2k and 2k + 1 of the four pixels
+            const uint2 ev = make_uint2(lo_pair(w[0][k], w[1][k]), lo_pair(w[2][k], w[3][k]));
+            const uint2 od = make_uint2(hi_pair(w[0][k], w[1][k]), hi_pair(w[2][k], w[3][k]));
+            __bf16* d0;
+            __bf16* d1;
+            if (is_g) {
+                d0 = &Gs[buf][8 * u_ch + 2 * k][4 * u_grp];
+                d1 = &Gs[buf][8 * u_ch + 2 * k + 1][4 * u_grp];
+            } else {
+                d0 = &Xs[buf][u_row][8 * u_ch + 2 * k][4 + 4 * u_grp];
+                d1 = &Xs[buf][u_row][8 * u_ch + 2 * k + 1][4 + 4 * u_grp];
+            }
+            *reinterpret_cast<uint2*>(d0) = ev;
+            *reinterpret_cast<uint2*>(d1) = od;
+        }
+    };
+    auto bias_add = [&]() {
+        if (!(bias_wg && is_g)) return;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t w[4] = {reg[e].x, reg[e].y, reg[e].z, reg[e].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                bsum[2 * k] += __uint_as_float(w[k] << 16);
+                bsum[2 * k + 1] += __uint_as_float(w[k] & 0xffff0000u);
+            }
+        }
+    };
+
+    f32x16 acc[MB][3];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[i][d][q] = 0.0f;
+
+    gload(t0);
+    bias_add();
+    lstore(0);
+    __syncthreads();
+    for (int tile = t0; tile < t1; ++tile) {
+        const int buf = (tile - t0) & 1;
+        if (tile + 1 < t1) gload(tile + 1);
+#pragma unroll
+        for (int ks = 0; ks < kWgTile / 16; ++ks) {
+            const int k8 = 16 * ks + 8 * (l >> 5);
+            const __bf16* xr = &Xs[buf][wr][32 * wj + (l & 31)][8 + k8];
+            const uint4 mid = *reinterpret_cast<const uint4*>(xr);
+            const uint32_t prev = *reinterpret_cast<const uint32_t*>(xr - 2);
+            const uint32_t next = *reinterpret_cast<const uint32_t*>(xr + 8);
+            Frag<__bf16> fb[3];
+            // x at pixel p + dx for dx = -1, 0, +1
+            const uint4 bm = make_uint4(shift1(prev, mid.x), shift1(mid.x, mid.y), shift1(mid.y, mid.z),
+                                        shift1(mid.z, mid.w));
+            const uint4 bp = make_uint4(shift1(mid.x, mid.y), shift1(mid.y, mid.z), shift1(mid.z, mid.w),
+                                        shift1(mid.w, next));
+            fb[0].v = __builtin_bit_cast(bf16x8, bm);
+            fb[1].v = __builtin_bit_cast(bf16x8, mid);
+            fb[2].v = __builtin_bit_cast(bf16x8, bp);
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                Frag<__bf16> fa;
+                fa.v = *reinterpret_cast<const bf16x8*>(&Gs[buf][32 * i + (l & 31)][k8]);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) mma(acc[i][d], fa, fb[d]);
+            }
+        }
+        if (tile + 1 < t1) {
+            bias_add();
+            lstore(buf ^ 1);
+        }
+        __syncthreads();
+    }
+
+    const int64_t nw = (int64_t)a.cout * 9 * a.cin;
+    float* part = a.part + (int64_t)split * (nw + a.cout);
+    if (bias_wg) {
+        if (is_g) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) bred[u_grp][8 * u_ch + c] = bsum[c];
+        }
+        __syncthreads();
+        if (t < 32 * MB) {
+            float v = bred[0][t];
+#pragma unroll
+            for (int k = 1; k < kWgTile / 4; ++k) v += bred[k][t];
+            const int co = cob * 32 * MB + t;
+            if (co < a.cout) part[nw + co] = v;
+        }
+    }
+    const int ci = cib * 32 * NB + 32 * wj + (l & 31);
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int co = cob * 32 * MB + 32 * i + acc_row(q, l);
+                if (co < a.cout && ci < a.cin) part[((int64_t)co * 9 + 3 * wr + d) * a.cin + ci] = acc[i][d][q];
+            }
+}
+
+// grad[i] = sum over splits s of part[s][i], i < n.  Workgroup: 32 outputs
+// x 8 rows; row r sums the splits s = r, r + 8, ... in order, then the rows
+// are added in row order (a fixed order for a given split count).
+constexpr int kSumCols = 32, kSumRows = kEw / kSumCols;
 __global__ __launch_bounds__(kEw) void k_sum_splits(const float* __restrict__ part, int splits, int64_t n,
                                                     float* __restrict__ grad) {
-    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float red[kSumRows][kSumCols + 1];
+    const int c = threadIdx.x % kSumCols, r = threadIdx.x / kSumCols;
+    const int64_t i = (int64_t)blockIdx.x * kSumCols + c;
     float v = 0.0f;
-    for (int s = 0; s < splits; ++s) v += part[(int64_t)s * n + i];
-    grad[i] = v;
+    if (i < n) {
+#pragma unroll 4
+        for (int s = r; s < splits; s += kSumRows) v += part[(int64_t)s * n + i];
+    }
+    red[r][c] = v;
+    __syncthreads();
+    if (r == 0 && i < n) {
+        float t = red[0][c];
+#pragma unroll
+        for (int k = 1; k < kSumRows; ++k) t += red[k][c];
+        grad[i] = t;
+    }
 }
 
 // Column sums over nodes, two stages, fixed order (bias gradients, channel

@@ -110,6 +110,7 @@ _SIG = {
     "lbm_nn_get_grads": (_I32, [_VP, _VP]),
     "lbm_nn_forward": (_I32, [_VP, _VP, _I32, _VP]),
     "lbm_nn_backward": (_I32, [_VP, _VP]),
+    "lbm_nn_layer_wgrad": (_I32, [_VP, _I32, _I32, _VP, _I32, _VP, _I32, _VP]),
     "lbm_nn_adam": (_I32, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_nn_train_step": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_double)]),
@@ -397,6 +398,10 @@ def lbm_nn_forward(n, d_x, batch: int, d_y) -> None:
 
 def lbm_nn_backward(n, d_gy) -> None:
     _ncheck(load_library().lbm_nn_backward(n, d_gy), n)
+
+
+def lbm_nn_layer_wgrad(n, layer, batch, d_x, x_cs, d_g, g_cs, d_grad) -> None:
+    _ncheck(load_library().lbm_nn_layer_wgrad(n, layer, batch, d_x, x_cs, d_g, g_cs, d_grad), n)
 
 
 def lbm_nn_adam(n, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
@@ -721,6 +726,17 @@ class WarmStartNet:
         self._destroy = load_library().lbm_nn_destroy
         self.n = lbm_nn_create(self.cfg, self._ws_ptr, nbytes, self.stream.cuda_stream)
         self.n_params = lbm_nn_param_count(self.n)
+        self.ch = tuple(int(c) for c in ch)
+
+    # level of each layer's input (0: h x w, k: h / 2^k x w / 2^k)
+    LAYER_LEVELS = (0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0)
+
+    def layer_shapes(self):
+        """(c_out, c_in) of the 15 convolutions in parameter order."""
+        c0, c1, c2, c3 = self.ch
+        cin = (2, c0, c0, c1, c1, c2, c2, c3, 2 * c3 + c2, c2, c2 + c1, c1, c1 + c0, c0, c0)
+        cout = (c0, c0, c1, c1, c2, c2, c3, c3, c2, c2, c1, c1, c0, c0, 3)
+        return list(zip(cout, cin))
 
     def __del__(self):
         n = getattr(self, "n", None)
@@ -762,6 +778,18 @@ class WarmStartNet:
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
         lbm_nn_adam(self.n, lr, beta1, beta2, eps)
+
+    def layer_wgrad(self, layer, x, g):
+        """Weight and bias gradient of one layer from its input x
+        [B][h_l][w_l][x_cs] and pre-activation gradient g [B][h_l][w_l][g_cs]
+        (device tensors of the compute type) -> float32 [cout * 9 * cin + cout]."""
+        cout, cin = self.layer_shapes()[layer]
+        out = self.torch.empty(cout * 9 * cin + cout, dtype=self.torch.float32, device=x.device)
+        x = x.contiguous()
+        g = g.contiguous()
+        lbm_nn_layer_wgrad(self.n, layer, x.shape[0], x.data_ptr(), x.shape[-1], g.data_ptr(), g.shape[-1],
+                           out.data_ptr())
+        return out
 
     def train_step(self, data, idx, lr, want_loss=False, aug=None):
         """data: dict of device tensors solid, rho, ux, uy, re, gx, tau; idx

@@ -95,6 +95,7 @@ def main() -> None:
     t.add_argument("--workload", required=True)
     t.add_argument("--alg-bytes", type=float, required=True)
     t.add_argument("--commands", required=True)
+    t.add_argument("--family", default="lbm", help="kernel source family the hash covers (lbm or nn)")
     t.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
@@ -119,7 +120,7 @@ def main() -> None:
     traffic = fetch * 1024.0 * sf + write * 1024.0 * sw
     rec = {
         "kernel": a.kernel, "workload": a.workload, "grid": a.grid,
-        "kernel_source_hash": source_hash(),
+        "kernel_source_hash": source_hash(a.family), "source_family": a.family,
         "fetch_kib_per_launch": fetch, "write_kib_per_launch": write,
         "copy_fetch_kib": cfetch, "copy_write_kib": cwrite, "copy_bytes_each_way": copy_bytes,
         "scale_fetch": sf, "scale_write": sw,

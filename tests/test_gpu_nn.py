@@ -295,3 +295,45 @@ def test_warm_project_matches_oracle(torch_mod, lbm_mod):
         # the staggered column flux of the projected field vanishes
         J = (g[0] * g[1] * fl).sum(axis=0)
         assert abs(((-1.0) ** np.arange(nx) * J).sum()) <= 1e-5 * np.abs(J).max()
+
+
+def _layer_wgrad_case(torch, lbm, h, w, ch, batch, dtype, seed):
+    """Every layer's weight and bias gradient through lbm_nn_layer_wgrad on
+    random tensors of the compute type (padding channels filled with noise
+    that must not leak), against the oracle's conv_backward on the same
+    values in FP64.  The products of two stored values are exact in FP32, so
+    the only difference is the FP32 accumulation order: max-norm 2e-5."""
+    net = lbm.WarmStartNet(h, w, batch, dtype=dtype, ch=ch)
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for k, (cout, cin) in enumerate(net.layer_shapes()):
+        lv = net.LAYER_LEVELS[k]
+        hl, wl = h >> lv, w >> lv
+        x_cs = max(16, cin)
+        g_cs = (cout + 31) // 32 * 32
+        xt = torch.tensor(rng.normal(size=(batch, hl, wl, x_cs)), dtype=tdt, device="cuda")
+        gt = torch.tensor(rng.normal(size=(batch, hl, wl, g_cs)), dtype=tdt, device="cuda")
+        got = net.layer_wgrad(k, xt, gt).cpu().numpy().astype(np.float64)
+        x64 = xt.float().cpu().numpy().astype(np.float64)[..., :cin]
+        g64 = gt.float().cpu().numpy().astype(np.float64)[..., :cout]
+        _, dW, db = co.conv_backward(x64, np.zeros((cout, 3, 3, cin)), g64)
+        ref = np.concatenate([dW.reshape(-1), db])
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        _say(f"layer_wgrad {dtype} {h}x{w} batch {batch} layer {k} ({cout}x{cin}, level {lv}): {err:.2e}")
+        assert err < 2e-5, (k, err)
+        worst = max(worst, err)
+    return worst
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_layer_wgrad_exact_small(torch_mod, lbm_mod, dtype):
+    """32 x 64 lattice: levels 2 and 3 (rows of 16 and 8) take the per-tap
+    kernel, levels 0 and 1 the nine-tap kernel in BF16."""
+    _layer_wgrad_case(torch_mod, lbm_mod, H, W, CH, 3, dtype, 71)
+
+
+def test_layer_wgrad_exact_full(torch_mod, lbm_mod):
+    """The 256 x 128 training lattice at batch 3 (every level nine-tap in
+    BF16; split counts from the planner, ragged last splits)."""
+    _layer_wgrad_case(torch_mod, lbm_mod, 128, 256, CH, 3, "bf16", 72)
