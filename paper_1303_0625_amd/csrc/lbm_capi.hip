@@ -316,10 +316,10 @@ lbm_status enqueue_step(lbm_ctx* c) {
     sp.errflag = wsp<int>(c, c->L.err);
     RoleCounts rc;
     rc.n_force = c->L.nchunks;
-    rc.n_move = c->L.n_movers;
+    rc.n_move = 2 * c->L.n_movers;  // geometry and refill workgroup per body
     rc.n_lead = (rc.n_force + rc.n_move + 1 + 7) / 8 * 8;
     MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
-                9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes};
+                9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes, c->L.n_movers};
     StepArgs sa = step_args(c);
     ForceArgs fa = force_args(c);
     CollideParams<C> cp = collide_params<C>(c);

@@ -449,16 +449,21 @@ __global__ __launch_bounds__(kBlock) void k_links(const uint8_t* __restrict__ ow
 }
 
 // ------------------------------------------------------------------ movers
-// One workgroup per translating body s.  The body's swept range from t-1 to
-// t+1, widened by kBoxMargin nodes, is staged in LDS as two byte maps: ot
-// (owners of G_t) and on (the second owner map, which holds G_{t-1} on entry
-// and G_{t+1} on exit).  Virtual wall rows are marked kWallMark.  Translating
+// Two workgroups per translating body s, which run side by side: part 0
+// writes G_{t+1} into the second owner map and rebuilds the body's link
+// list, part 1 refills the newborn nodes.  Both stage the body's swept range
+// from t-1 to t+1, widened by kBoxMargin nodes, in LDS as two byte maps: ot
+// (owners of G_t) and on (the second owner map, G_{t-1} on entry, then
+// G_{t+1} as both parts rasterise the body at t+1 the same way).  Part 1 may
+// stage a node after part 0 has rewritten it; rasterising G_{t+1} over it
+// again gives the same value, so neither part depends on the other's
+// timing.  Virtual wall rows are marked kWallMark.  Translating
 // bodies keep a gap of at least kMoverGap nodes to each other, so no other
-// workgroup changes an owner that this one reads.
+// body's workgroups change an owner that these read.
 constexpr int kBoxMargin = 5;
 constexpr uint8_t kWallMark = 255;
 constexpr int kMoverGap = 8;
-constexpr int kNewbornBatch = 8;   // newborn nodes refilled together
+constexpr int kNewbornBatch = 4;   // newborn nodes refilled together
 constexpr int kNewbornMax = 128;   // newborn nodes of one body in one step
 
 struct MoveArgs {
@@ -467,6 +472,7 @@ struct MoveArgs {
     double rho0;
     int refill;     // 0 A1, 1 A2, 2 A3
     int box_bytes;  // capacity of each LDS byte map
+    int n_movers;   // translating bodies (mover workgroups: 2 n_movers)
 };
 
 __device__ inline void swept_box(const SolidDev& S, int64_t t, long& x0, long& x1, long& y0, long& y1) {
@@ -495,7 +501,8 @@ struct MoveShared {
     C nb_mom[kNewbornBatch][4];
 };
 
-// Mover role for body movers[m]; lds holds the two byte maps (2 * box_bytes).
+// Mover role m: part m / n_movers for body movers[m % n_movers]; lds holds
+// the two byte maps (2 * box_bytes).
 template <typename T>
 __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>& sm,
                                  const T* __restrict__ fin, T* __restrict__ fout,
@@ -509,7 +516,8 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
     using C = typename Sto<T>::C;
     uint8_t* ot = lds;
     uint8_t* on = lds + a.box_bytes;
-    const int s = movers[m];
+    const int part = m / a.n_movers;  // 0: G_{t+1} and links, 1: refill
+    const int s = movers[m - part * a.n_movers];
     if (threadIdx.x == 0) sm.body = sol[s];
     __syncthreads();
     const SolidDev& S = sm.body;
@@ -566,18 +574,20 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
         const uint8_t nv = solid_inside(S, Xn, Yn, xx, yy) ? (uint8_t)s : (v == s ? (uint8_t)0 : v);
         if (nv != v) {
             on[q] = nv;
-            int gx, gy;
-            gidx(q, gx, gy);
-            own_n[(int64_t)gy * a.opitch + gx] = nv;
+            if (part == 0) {
+                int gx, gy;
+                gidx(q, gx, gy);
+                own_n[(int64_t)gy * a.opitch + gx] = nv;
+            }
         }
-        if (ot[q] == s && nv == 0) {
+        if (part == 1 && ot[q] == s && nv == 0) {
             const int k = atomicAdd(&sm.nb_count, 1);
             if (k < kNewbornMax) sm.nb_list[k] = q;
         }
     }
     __syncthreads();
     // 3. link list of G_{t+1}, row-major (y, x, i) over the box interior
-    {
+    if (part == 0) {
         const int chunk = (N + kBlock - 1) / kBlock;
         const int q0 = threadIdx.x * chunk;
         const int q1 = q0 + chunk < N ? q0 + chunk : N;
@@ -611,6 +621,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
             seg_cnt_n[s] = total <= cap ? total : 0;
             if (total > cap) atomicOr(errflag, 1);
         }
+        return;
     }
     // 4. refill the newborn nodes in batches, then collide and store
     const int nborn = sm.nb_count;
