@@ -92,6 +92,18 @@ __device__ inline void st_stream(bf16_t* p, bf16_t v) {
     else p->bits = v.bits;
 }
 
+// Element idx of a row that starts at a wave-uniform base, with the byte
+// offset formed in 32 bits (rows are far below 4 GiB): the load or store
+// then takes the scalar base plus a 32-bit vector offset.
+template <typename T>
+__device__ inline const T* row_at(const T* base, uint32_t idx) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ inline T* row_at(T* base, uint32_t idx) {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T));
+}
+
 // One thread per node, each wave 64 consecutive nodes of one row.  The nine
 // pull loads of the interior case are issued together with the owner loads;
 // only when a source node is solid (or a wall row) are they replaced by the
@@ -137,29 +149,33 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
         ym = y == 0 ? a.ny - 1 : y - 1;
         yp = y == a.ny - 1 ? 0 : y + 1;
     }
+    // Row bases are wave-uniform (a wave covers 64 x of one row); the lane
+    // offsets are unsigned 32-bit, so every access is a scalar base plus a
+    // 32-bit vector offset (no per-lane 64-bit address arithmetic).
+    const uint32_t ux = (uint32_t)x, uxm = (uint32_t)xm, uxp = (uint32_t)xp;
     const uint8_t* om = own_t + (int64_t)ym * a.opitch;
     const uint8_t* o0 = own_t + (int64_t)y * a.opitch;
     const uint8_t* op = own_t + (int64_t)yp * a.opitch;
-    const uint32_t self = o0[x];
+    const uint32_t self = o0[ux];
     // owners of the sources x - e_i
-    const uint32_t s1 = o0[xm], s3 = o0[xp];
-    const uint32_t s2 = om[x], s5 = om[xm], s6 = om[xp];
-    const uint32_t s4 = op[x], s7 = op[xp], s8 = op[xm];
+    const uint32_t s1 = o0[uxm], s3 = o0[uxp];
+    const uint32_t s2 = om[ux], s5 = om[uxm], s6 = om[uxp];
+    const uint32_t s4 = op[ux], s7 = op[uxp], s8 = op[uxm];
 
     const int64_t P = a.istride;
     const T* r0 = fin + (int64_t)y * a.ystride;
     const T* rm = fin + (int64_t)ym * a.ystride;
     const T* rp = fin + (int64_t)yp * a.ystride;
     T raw[9];
-    raw[0] = ld_stream<NT>(r0 + x);
-    raw[1] = ld_stream<NT>(r0 + P + xm);
-    raw[2] = ld_stream<NT>(rm + 2 * P + x);
-    raw[3] = ld_stream<NT>(r0 + 3 * P + xp);
-    raw[4] = ld_stream<NT>(rp + 4 * P + x);
-    raw[5] = ld_stream<NT>(rm + 5 * P + xm);
-    raw[6] = ld_stream<NT>(rm + 6 * P + xp);
-    raw[7] = ld_stream<NT>(rp + 7 * P + xp);
-    raw[8] = ld_stream<NT>(rp + 8 * P + xm);
+    raw[0] = ld_stream<NT>(row_at(r0, ux));
+    raw[1] = ld_stream<NT>(row_at(r0 + P, uxm));
+    raw[2] = ld_stream<NT>(row_at(rm + 2 * P, ux));
+    raw[3] = ld_stream<NT>(row_at(r0 + 3 * P, uxp));
+    raw[4] = ld_stream<NT>(row_at(rp + 4 * P, ux));
+    raw[5] = ld_stream<NT>(row_at(rm + 5 * P, uxm));
+    raw[6] = ld_stream<NT>(row_at(rm + 6 * P, uxp));
+    raw[7] = ld_stream<NT>(row_at(rp + 7 * P, uxp));
+    raw[8] = ld_stream<NT>(row_at(rp + 8 * P, uxm));
     if (self) return;  // solid at t (a newborn node is refilled by the mover role)
     C d[9];
 #pragma unroll
@@ -175,15 +191,15 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
             const uint32_t sid = wall ? 0u : src[i];
             if (wall || sid != 0u) {
                 const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-                d[i] = Sto<T>::ld(r0[opp_(i) * P + x]) +
+                d[i] = Sto<T>::ld(*row_at(r0 + opp_(i) * P, ux)) +
                        C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
             }
         }
     }
     collide<C>(d, cp);
-    T* w0 = fout + (int64_t)y * a.ystride + x;
+    T* w0 = fout + (int64_t)y * a.ystride;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) st_stream<NT>(w0 + i * P, Sto<T>::st(d[i]));
+    for (int i = 0; i < 9; ++i) st_stream<NT>(row_at(w0 + i * P, ux), Sto<T>::st(d[i]));
 }
 
 // ------------------------------------------------------------------ init
@@ -517,11 +533,15 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
     uint8_t* ot = lds;
     uint8_t* on = lds + a.box_bytes;
     const int part = m / a.n_movers;  // 0: G_{t+1} and links, 1: refill
+    // uniform values, issued together (one dependent round trip for the
+    // body record, kept in LDS, and its link segment)
     const int s = movers[m - part * a.n_movers];
+    const int64_t t = tctr[parity];
     if (threadIdx.x == 0) sm.body = sol[s];
+    const int cap = seg_cap[s];
+    const int soff = seg_off[s];
     __syncthreads();
     const SolidDev& S = sm.body;
-    const int64_t t = tctr[parity];
     long x0, x1, y0, y1;
     swept_box(S, t, x0, x1, y0, y1);
     const int W = (int)(x1 - x0 + 1), H = (int)(y1 - y0 + 1), N = W * H;
@@ -537,8 +557,9 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
         return true;
     };
     if (threadIdx.x == 0) sm.nb_count = 0;
-    // 1. stage both owner maps; loads of a round are issued before any store
-    constexpr int R = 4;
+    // 1. stage the owner maps (part 0 needs only the second one); loads of
+    // a round are issued before any store
+    constexpr int R = 8;
     for (int q0 = 0; q0 < N; q0 += R * kBlock) {
         uint8_t vt[R], vn[R];
 #pragma unroll
@@ -548,7 +569,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
             vt[r] = vn[r] = kWallMark;
             if (q < N && gidx(q, gx, gy)) {
                 const int64_t o = (int64_t)gy * a.opitch + gx;
-                vt[r] = own_t[o];
+                if (part == 1) vt[r] = own_t[o];
                 vn[r] = own_n[o];
             }
         }
@@ -612,9 +633,8 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
         for (int q = q0; q < q1; ++q) cnt += links_at(q, nullptr, 0);
         int total;
         int off = block_exclusive_scan(cnt, sm.scan, total);
-        const int cap = seg_cap[s];
         if (total <= cap) {
-            uint32_t* L = links_n + seg_off[s];
+            uint32_t* L = links_n + soff;
             for (int q = q0; q < q1; ++q) off += links_at(q, L, off);
         }
         if (threadIdx.x == 0) {
