@@ -382,21 +382,29 @@ __global__ void k_wall_links(uint32_t* __restrict__ links, int nx, int ny) {
     }
 }
 
-// Block-wide exclusive scan of one int per thread (kBlock threads).
+// Block-wide exclusive scan of one int per thread (kBlock threads): an
+// inclusive scan inside each wavefront by shuffles, then the wave totals
+// through LDS (two barriers; sh needs kBlock / 64 ints).
 __device__ inline int block_exclusive_scan(int v, int* sh, int& total) {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        int t = tid >= off ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += t;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    total = sh[kBlock - 1];
-    int ex = sh[tid] - v;
+    if (lane == 63) sh[wave] = x;
     __syncthreads();
-    return ex;
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int tw = sh[w];
+        pre += w < wave ? tw : 0;
+        tot += tw;
+    }
+    total = tot;
+    __syncthreads();  // sh may be reused by the caller
+    return pre + x - v;
 }
 
 // Build the link list of solid s from owner map own over its bounding range
