@@ -89,6 +89,10 @@ def _load():
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, dp]
     lib.orc_refill_node.restype = ctypes.c_int
+    lib.orc_set_mrt.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.orc_collide_node_mrt.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp]
+    lib.orc_mrt_matrix.argtypes = [dp]
+    lib.orc_mrt_inverse.argtypes = [dp]
     _lib = lib
     return lib
 
@@ -122,6 +126,28 @@ def collide_node(f, tau: float, gx: float = 0.0, gy: float = 0.0) -> np.ndarray:
     return out
 
 
+def collide_node_mrt(f, s, gx: float = 0.0, gy: float = 0.0) -> np.ndarray:
+    """MRT collision of one node with the nine moment rates s (moments rho,
+    e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    out = np.zeros(9)
+    _load().orc_collide_node_mrt(_dp(f), _dp(s), gx, gy, _dp(out))
+    return out
+
+
+def mrt_matrix() -> np.ndarray:
+    out = np.zeros(81)
+    _load().orc_mrt_matrix(_dp(out))
+    return out.reshape(9, 9)
+
+
+def mrt_inverse() -> np.ndarray:
+    out = np.zeros(81)
+    _load().orc_mrt_inverse(_dp(out))
+    return out.reshape(9, 9)
+
+
 def refill_node(fpost: np.ndarray, oldfluid: np.ndarray, x: int, y: int, scheme: int,
                 walls_y: bool = False, rho0: float = 1.0, v=(0.0, 0.0)):
     """Refill of one newborn node; returns (f[9], number of participating links)."""
@@ -142,7 +168,7 @@ class OracleSim:
     """
 
     def __init__(self, nx, ny, tau, *, walls_y=False, rho0=1.0, gx=0.0, gy=0.0, u0=(0.0, 0.0),
-                 wall_v=(0.0, 0.0), refill=A1, rho_w_local=False, bodies=()):
+                 wall_v=(0.0, 0.0), refill=A1, rho_w_local=False, bodies=(), mrt=None):
         lib = _load()
         self.nx, self.ny = int(nx), int(ny)
         self.nb = len(bodies)
@@ -164,6 +190,9 @@ class OracleSim:
                                  wall_v[0], wall_v[1], int(refill), int(rho_w_local), self.nb, arr)
         if not self._h:
             raise ValueError("oracle rejected the configuration")
+        if mrt is not None:
+            # (s_e, s_eps, s_q); the shear rates are 1/tau
+            lib.orc_set_mrt(self._h, float(mrt[0]), float(mrt[1]), float(mrt[2]))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -8,7 +8,10 @@
  * One time step t -> t+1 on geometry G_t (Sec. II, Sec. III.A-B, Sec. IV.B):
  *   O1 moments       rho = sum f_i, rho*u = sum e_i f_i + rho*g/2
  *   O2 collision     Eq. 2 with the single-relaxation-time (BGK) operator,
- *                    Eq. 8 equilibrium and Guo's forcing term
+ *                    Eq. 8 equilibrium and Guo's forcing term; or, after
+ *                    orc_set_mrt, the multiple-relaxation-time operator of
+ *                    Sec. IV (relaxation in moment space with the diagonal
+ *                    matrix S) with the same equilibrium and forcing
  *   O3 link forces   Eq. 4 (CME) and Eq. 5 (GME) on every fluid-solid link,
  *                    summed per solid (Eq. 6) with torque (Eq. 7)
  *   O4 advection     Eq. 3; a population whose source node is solid is the
@@ -41,6 +44,8 @@ struct orc_sim {
     double tau, rho0, gx, gy;
     double wall_vx, wall_vy;
     int refill, rho_w_local;
+    int mrt;         /* 0: BGK; 1: MRT with rates s_rate */
+    double s_rate[9];
     int nb;
     orc_body* body;
     long t;
@@ -165,6 +170,99 @@ void orc_collide_node(const double f[9], double tau, double gx, double gy, doubl
         double src = pref * W[i] * (sx * rho * gx + sy * rho * gy);
         out[i] = f[i] - (f[i] - feq[i]) / tau + src;
     }
+}
+
+/* Moment basis of the D2Q9 multiple-relaxation-time model (Lallemand and
+ * Luo): rows rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy over the velocities
+ * of Sec. III.C. */
+static const double MRT_M[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1},
+};
+
+/* Inverse of MRT_M by Gauss-Jordan elimination with partial pivoting. */
+void orc_mrt_inverse(double inv[81]) {
+    double a[9][18];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 18; ++c) a[r][c] = c < 9 ? MRT_M[r][c] : (c - 9 == r ? 1.0 : 0.0);
+    for (int c = 0; c < 9; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 9; ++r)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        for (int k = 0; k < 18; ++k) {
+            double tmp = a[c][k];
+            a[c][k] = a[piv][k];
+            a[piv][k] = tmp;
+        }
+        double d = a[c][c];
+        for (int k = 0; k < 18; ++k) a[c][k] /= d;
+        for (int r = 0; r < 9; ++r) {
+            if (r == c) continue;
+            double m = a[r][c];
+            for (int k = 0; k < 18; ++k) a[r][k] -= m * a[c][k];
+        }
+    }
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) inv[r * 9 + c] = a[r][9 + c];
+}
+
+void orc_mrt_matrix(double out[81]) {
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) out[r * 9 + c] = MRT_M[r][c];
+}
+
+/* O1 + O2 with the MRT operator: m = M f, m* = m - S (m - M f_eq)
+ * + (I - S/2) M F, f* = M^-1 m*, where F_i = w_i [3 (e_i - u) + 9 (e_i.u) e_i]
+ * . rho g is Guo's forcing term without its BGK prefactor (the prefactor
+ * becomes I - S/2 in moment space) and s[k] is the rate of moment k. */
+void orc_collide_node_mrt(const double f[9], const double s[9], double gx, double gy, double out[9]) {
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        rho += f[i];
+        jx += EX[i] * f[i];
+        jy += EY[i] * f[i];
+    }
+    double ux = (jx + 0.5 * rho * gx) / rho;
+    double uy = (jy + 0.5 * rho * gy) / rho;
+    double feq[9], F[9];
+    orc_feq(rho, ux, uy, feq);
+    for (int i = 0; i < 9; ++i) {
+        double eu = EX[i] * ux + EY[i] * uy;
+        double sx = 3.0 * (EX[i] - ux) + 9.0 * eu * EX[i];
+        double sy = 3.0 * (EY[i] - uy) + 9.0 * eu * EY[i];
+        F[i] = W[i] * (sx * rho * gx + sy * rho * gy);
+    }
+    double m[9], meq[9], mF[9], ms[9];
+    for (int k = 0; k < 9; ++k) {
+        m[k] = meq[k] = mF[k] = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            m[k] += MRT_M[k][i] * f[i];
+            meq[k] += MRT_M[k][i] * feq[i];
+            mF[k] += MRT_M[k][i] * F[i];
+        }
+        ms[k] = m[k] - s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * s[k]) * mF[k];
+    }
+    double inv[81];
+    orc_mrt_inverse(inv);
+    for (int i = 0; i < 9; ++i) {
+        out[i] = 0.0;
+        for (int k = 0; k < 9; ++k) out[i] += inv[i * 9 + k] * ms[k];
+    }
+}
+
+void orc_set_mrt(orc_sim* sim, double s_e, double s_eps, double s_q) {
+    /* Sec. IV: S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 1/tau, 1/tau) */
+    const double nu = 1.0 / sim->tau;
+    const double r[9] = {0.0, s_e, s_eps, 0.0, s_q, 0.0, s_q, nu, nu};
+    for (int k = 0; k < 9; ++k) sim->s_rate[k] = r[k];
+    sim->mrt = 1;
 }
 
 void orc_link_force(int i, double a, double b, double vx, double vy, int scheme, double out[2]) {
@@ -317,7 +415,10 @@ static void one_step(orc_sim* s) {
             if (s->own[idx(s, x, y)] != 0) continue;
             double fl[9], out[9];
             for (int i = 0; i < 9; ++i) fl[i] = s->f[pidx(s, i, x, y)];
-            orc_collide_node(fl, s->tau, s->gx, s->gy, out);
+            if (s->mrt)
+                orc_collide_node_mrt(fl, s->s_rate, s->gx, s->gy, out);
+            else
+                orc_collide_node(fl, s->tau, s->gx, s->gy, out);
             for (int i = 0; i < 9; ++i) s->ft[pidx(s, i, x, y)] = out[i];
         }
 

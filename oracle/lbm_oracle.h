@@ -94,6 +94,19 @@ void orc_link_force(int i, double a, double b, double vx, double vy,
 void orc_collide_node(const double f[9], double tau, double gx, double gy,
                       double out[9]);
 
+/* Switch the collision to the multiple-relaxation-time operator of Sec. IV
+ * with S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 1/tau, 1/tau) over the moments
+ * (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy); same equilibrium (Eq. 8) and
+ * Guo forcing.  Applies from the next step on. */
+void orc_set_mrt(orc_sim* s, double s_e, double s_eps, double s_q);
+
+/* One MRT collision of one node with the nine moment rates s[9]. */
+void orc_collide_node_mrt(const double f[9], const double s[9], double gx, double gy, double out[9]);
+
+/* The moment matrix M (row-major 9 x 9) and its inverse (Gauss-Jordan). */
+void orc_mrt_matrix(double out[81]);
+void orc_mrt_inverse(double inv[81]);
+
 /* Newborn refill of node (x, y) from post-stream values fpost [9][ny][nx] of
  * the nodes marked old-fluid (oldfluid[y*nx+x] != 0).  Periodic wrap in x,
  * and in y unless walls_y.  When no direction participates, out = f_eq(rho0, v).

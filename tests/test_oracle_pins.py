@@ -455,3 +455,105 @@ def test_torque_sign_in_shear(oracle_mod):
             F = s.force(1, sch)
             assert F[0] > 0
             assert sign * F[2] > 0.05 * F[0]
+
+
+# ---------------------------------------------------------------- MRT (Sec. IV)
+# The multiple-relaxation-time operator the paper pairs with S = diag(0, 1.64,
+# 1.54, 0, 1.9, 0, 1.9, 1/tau, 1/tau).  Pinned against the moment-space facts
+# of the D2Q9 model (Lallemand and Luo), its BGK special case, conservation,
+# and the exact Poiseuille solution of two-rate schemes under half-way
+# bounce-back, which depends on the rates only through
+# Lambda = (1/s_nu - 1/2)(1/s_q - 1/2).
+PAPER_MRT = (1.64, 1.54, 1.9)
+
+
+def _mrt_rates(tau, s_e, s_eps, s_q):
+    return [0.0, s_e, s_eps, 0.0, s_q, 0.0, s_q, 1 / tau, 1 / tau]
+
+
+def test_mrt_basis(oracle_mod):
+    """The moment basis: rows orthogonal with squared norms (9, 36, 36, 6, 12,
+    6, 12, 4, 4); the rows rho, j_x, j_y are the mass and momentum sums; the
+    Gauss-Jordan inverse inverts it."""
+    M = oracle_mod.mrt_matrix()
+    G = M @ M.T
+    assert np.array_equal(np.diag(G), [9, 36, 36, 6, 12, 6, 12, 4, 4])
+    assert np.array_equal(G - np.diag(np.diag(G)), np.zeros((9, 9)))
+    assert np.array_equal(M[0], np.ones(9)) and np.array_equal(M[3], EX) and np.array_equal(M[5], EY)
+    assert np.abs(oracle_mod.mrt_inverse() @ M - np.eye(9)).max() < 1e-15
+
+
+def test_mrt_equilibrium_and_source_moments(oracle_mod):
+    """Moments of the Eq. 8 equilibrium and of Guo's source in this basis are
+    the textbook closed forms: m_eq = (rho, -2 rho + 3 rho u.u, rho - 3 rho u.u,
+    rho u_x, -rho u_x, rho u_y, -rho u_y, rho (u_x^2 - u_y^2), rho u_x u_y) and
+    M F = (0, 6 u.F, -6 u.F, F_x, -F_x, F_y, -F_y, 2 (u_x F_x - u_y F_y),
+    u_x F_y + u_y F_x).  The source is read off a collision with every rate 0
+    (f* = f + F)."""
+    M = oracle_mod.mrt_matrix()
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        rho = rng.uniform(0.8, 1.2)
+        u = rng.uniform(-0.1, 0.1, 2)
+        uu = u @ u
+        m = M @ oracle_mod.feq(rho, u[0], u[1])
+        want = [rho, -2 * rho + 3 * rho * uu, rho - 3 * rho * uu, rho * u[0], -rho * u[0], rho * u[1],
+                -rho * u[1], rho * (u[0] ** 2 - u[1] ** 2), rho * u[0] * u[1]]
+        assert np.abs(m - want).max() < 1e-15
+        g = rng.uniform(-1e-3, 1e-3, 2)
+        f = WT * rho * (1 + rng.normal(size=9) * 0.02)
+        r0, j = f.sum(), np.array([(EX * f).sum(), (EY * f).sum()])
+        uG = (j + 0.5 * r0 * g) / r0
+        F = r0 * g
+        src = oracle_mod.collide_node_mrt(f, np.zeros(9), g[0], g[1]) - f
+        mF = M @ src
+        want = [0, 6 * uG @ F, -6 * uG @ F, F[0], -F[0], F[1], -F[1], 2 * (uG[0] * F[0] - uG[1] * F[1]),
+                uG[0] * F[1] + uG[1] * F[0]]
+        assert np.abs(mF - want).max() < 1e-15
+
+
+def test_mrt_reduces_to_bgk(oracle_mod):
+    """With every moment relaxed at 1/tau the MRT operator is the BGK one."""
+    rng = np.random.default_rng(8)
+    for tau in (0.55, 0.6, 0.8, 1.3):
+        for _ in range(10):
+            f = WT * (1 + rng.normal(size=9) * 0.05)
+            g = rng.uniform(-1e-4, 1e-4, 2)
+            a = oracle_mod.collide_node(f, tau, g[0], g[1])
+            b = oracle_mod.collide_node_mrt(f, [1 / tau] * 9, g[0], g[1])
+            assert np.abs(a - b).max() < 5e-16
+
+
+def test_mrt_conserves_mass_and_adds_momentum_rho_g(oracle_mod):
+    """The paper's rates: mass unchanged, momentum changed by exactly rho g,
+    whatever the non-conserved moments relax to."""
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        f = WT * (1 + rng.normal(size=9) * 0.05)
+        g = rng.uniform(-1e-4, 1e-4, 2)
+        out = oracle_mod.collide_node_mrt(f, _mrt_rates(0.6, *PAPER_MRT), g[0], g[1])
+        rho = f.sum()
+        assert abs(out.sum() - rho) < 1e-15
+        assert abs((EX * out).sum() - (EX * f).sum() - rho * g[0]) < 1e-16
+        assert abs((EY * out).sum() - (EY * f).sum() - rho * g[1]) < 1e-16
+
+
+@pytest.mark.parametrize("tau,s_q,ny,steps", [(0.6, 1.9, 12, 20000), (0.8, 1.2, 16, 20000),
+                                                 (0.8, 1 / 1.125, 16, 20000)])
+def test_mrt_poiseuille_exact(oracle_mod, tau, s_q, ny, steps):
+    """Steady body-force-driven channel under half-way bounce-back with the
+    MRT operator: u(y) = g/(2 nu) (H^2/4 - (y - y_c)^2) + g (16 Lambda - 3)/(24 nu)
+    with Lambda = (tau - 1/2)(1/s_q - 1/2) (the BGK formula at s_q = 1/tau);
+    s_q = 1/1.125 at tau = 0.8 is Lambda = 3/16, where the walls sit exactly
+    half-way (no slip term).  The energy rates s_e, s_eps drop out."""
+    gx = 1e-6
+    sim = oracle_mod.OracleSim(4, ny, tau, walls_y=True, gx=gx, mrt=(PAPER_MRT[0], PAPER_MRT[1], s_q))
+    sim.step(steps)
+    rho, ux, uy, _ = sim.fields()
+    nu = (tau - 0.5) / 3
+    lam = (tau - 0.5) * (1 / s_q - 0.5)
+    y = np.arange(ny)
+    want = gx / (2 * nu) * ((ny / 2) ** 2 - (y - (ny - 1) / 2) ** 2) + gx * (16 * lam - 3) / (24 * nu)
+    assert np.abs(ux[:, 1] - want).max() < 2e-10 * want.max()
+    assert np.abs(uy).max() < 1e-14
+    assert np.abs(rho - 1).max() < 1e-9
