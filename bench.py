@@ -48,12 +48,12 @@ def stored_traffic(workload: str, kernel: str = "k_fused", family: str = "lbm"):
     return round(rec.get("hbm_bytes_per_launch"))
 
 
-def run_gpu(case, dtype, steps, warmup, torch, pkg):
+def run_gpu(case, dtype, steps, warmup, torch, pkg, mrt=None):
     """Warm up, time `steps` steps (whole-step throughput), then time another
     `steps` steps with HIP events attached to each time-step launch (kernel
     roofline).  The two passes are separate so that the event records do not
     perturb the throughput figure."""
-    lat = pkg.Lattice(case, dtype=dtype, history_steps=2 * steps + warmup + 1)
+    lat = pkg.Lattice(case, dtype=dtype, history_steps=2 * steps + warmup + 1, mrt=mrt)
     stream = lat.stream
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -153,6 +153,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hbm-case", action="store_true")
     ap.add_argument("--no-batch-case", action="store_true")
+    ap.add_argument("--no-mrt-case", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--warm-cases", type=int, default=16)
@@ -207,6 +208,22 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     extra = {}
+    if not args.no_mrt_case:
+        # the same workload with the MRT operator of Sec. IV (paper's rates)
+        mrt = pkg.lbm.PAPER_MRT_RATES
+        m_steps = min(args.steps, 2000)
+        lat3, tms3, ums3, n3, nf3 = run_gpu(case, args.dtype, m_steps, args.warmup, torch, pkg, mrt=mrt)
+        avg3 = ums3 / max(n3, 1) * 1e-3
+        ab3 = 18 * BYTES[args.dtype] * nf3
+        extra["mrt_" + wl] = {
+            "rates_e_eps_q": list(mrt),
+            "mlups": round(nx * ny * m_steps / (tms3 * 1e-3) / 1e6, 1),
+            "ms_per_step": round(tms3 / m_steps, 5),
+            "kernel_us": round(avg3 * 1e6, 3),
+            "achieved_GBs": round(ab3 / avg3 / 1e9, 1),
+            "frac": round(ab3 / avg3 / 1e9 / HBM_PEAK_GBS, 4)}
+        del lat3
+        torch.cuda.empty_cache()
     if not args.no_hbm_case:
         big = lc.periodic_cylinders()
         big_steps = 200

@@ -155,13 +155,29 @@ lbm_status lbm_fields(lbm_ctx* ctx, void* d_rho, void* d_ux, void* d_uy, int32_t
 lbm_status lbm_init_fields(lbm_ctx* ctx, const void* d_rho, const void* d_ux, const void* d_uy,
                            int32_t in_dtype);
 
+/* Collision operators. */
+typedef enum { LBM_BGK = 0, LBM_MRT = 1 } lbm_collision;
+
+/* Choose the collision operator (default LBM_BGK, Eq. 2 with the single
+ * relaxation time tau).  LBM_MRT is the multiple-relaxation-time operator the
+ * paper pairs with its simulations (Sec. IV): relaxation in the moment space
+ * (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) of the D2Q9 basis with
+ * S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 1/tau, 1/tau), the Eq. 8
+ * equilibrium and Guo's forcing ((I - S/2) in moment space); rates[3] =
+ * {s_e, s_eps, s_q}, each in (0, 2) (the paper: 1.64, 1.54, 1.9); ignored for
+ * BGK.  Only before the first step (LBM_ESTATE after): the state is reset to
+ * f_eq(rho0, u0) collided once with the chosen operator.  Force evaluation,
+ * bounce-back and refill are unchanged; the newborn refill collides with the
+ * chosen operator.  Asynchronous. */
+lbm_status lbm_set_collision(lbm_ctx* ctx, int32_t model, const double* rates);
+
 /* Replace the state by the exact steady plane-Poiseuille flow of the
  * unobstructed channel at every fluid node: f = f_eq(rho0, u_P(y) - g/2),
  * collided once, with u_P(y) = g_x/(2 nu) (Y^2 - (y - y_c)^2) + s, Y = ny/2,
- * y_c = (ny - 1)/2, s = g_x (4 (2 tau - 1)^2 - 3) / (4 (2 tau - 1)),
- * nu = (tau - 1/2)/3 (BGK with Guo forcing between half-way walls; Eq. 2-3).
- * A non-learned warm start.  Needs walls_y = 1 (LBM_ESTATE otherwise).
- * Asynchronous. */
+ * y_c = (ny - 1)/2, s = g_x (16 Lambda - 3) / (24 nu), nu = (tau - 1/2)/3,
+ * Lambda = (tau - 1/2)^2 for BGK and (tau - 1/2)(1/s_q - 1/2) for MRT (Guo
+ * forcing between half-way walls; Eq. 2-3).  A non-learned warm start.
+ * Needs walls_y = 1 (LBM_ESTATE otherwise).  Asynchronous. */
 lbm_status lbm_init_poiseuille(lbm_ctx* ctx);
 
 /* Post-collision populations f~_i(x, t) of the current state as absolute

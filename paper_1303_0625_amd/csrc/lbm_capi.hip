@@ -208,6 +208,8 @@ struct lbm_ctx {
     size_t ws_bytes;
     Layout L;
     int64_t t;
+    int mrt = 0;                        // collision operator: 0 BGK, 1 MRT
+    double mrt_s[3] = {0.0, 0.0, 0.0};  // MRT rates s_e, s_eps, s_q
     int64_t hist_first = 0;  // first step whose force record is held
     std::vector<int> seg_off, seg_cap;
     int64_t link_cap_total;
@@ -248,6 +250,10 @@ CollideParams<C> collide_params(const lbm_ctx* c) {
     p.gx = (C)c->g.gx;
     p.gy = (C)c->g.gy;
     p.pref = (C)(1.0 - 1.0 / (2.0 * c->tau));
+    p.mrt = c->mrt;
+    p.s_e = (C)c->mrt_s[0];
+    p.s_eps = (C)c->mrt_s[1];
+    p.s_q = (C)c->mrt_s[2];
     return p;
 }
 
@@ -327,7 +333,8 @@ lbm_status enqueue_step(lbm_ctx* c) {
     const size_t lds = c->L.n_movers > 0 ? 2 * (size_t)c->L.box_bytes : 0;
     // both population buffers larger than the Infinity Cache: stream them
     const bool nt = 2 * c->L.fbytes > kStreamBytes;
-    auto kern = nt ? k_fused<T, true> : k_fused<T, false>;
+    auto kern = c->mrt ? (nt ? k_fused<T, true, true> : k_fused<T, false, true>)
+                       : (nt ? k_fused<T, true, false> : k_fused<T, false, false>);
     const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
     if (timed) {
         hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), lds, c->stream, c->ev[c->ev_used],
@@ -744,6 +751,32 @@ lbm_status lbm_init_fields(lbm_ctx* c, const void* d_rho, const void* d_ux, cons
         set_err(c->err, "fields are read as LBM_F64 or LBM_F32");
         return LBM_EINVAL;
     }
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+lbm_status lbm_set_collision(lbm_ctx* c, int32_t model, const double* rates) {
+    if (!c) return LBM_EINVAL;
+    if (model != LBM_BGK && model != LBM_MRT) {
+        set_err(c->err, "model must be LBM_BGK or LBM_MRT");
+        return LBM_EINVAL;
+    }
+    if (model == LBM_MRT) {
+        if (!rates) return LBM_EINVAL;
+        for (int k = 0; k < 3; ++k)
+            if (!(rates[k] > 0.0 && rates[k] < 2.0)) {
+                set_err(c->err, "MRT rates must lie in (0, 2)");
+                return LBM_EINVAL;
+            }
+    }
+    if (c->t != 0) {
+        set_err(c->err, "the collision operator is chosen before the first step");
+        return LBM_ESTATE;
+    }
+    c->mrt = model == LBM_MRT ? 1 : 0;
+    for (int k = 0; k < 3; ++k) c->mrt_s[k] = c->mrt ? rates[k] : 0.0;
+    // the start state is f_eq(rho0, u0) collided once with the chosen operator
+    dispatch_init<double>(c, nullptr, nullptr, nullptr);
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
 }

@@ -89,6 +89,8 @@ struct Sto<bf16_t> {
 template <typename C>
 struct CollideParams {
     C rho0, omega, gx, gy, pref;  // pref = 1 - 1/(2 tau)
+    int mrt;                      // 1: multiple-relaxation-time operator (below)
+    C s_e, s_eps, s_q;            // its energy, energy-square and heat-flux rates
 };
 
 // Moments of one node: drho = sum d_i, rho = rho0 + drho, Guo velocity u.
@@ -154,6 +156,73 @@ __device__ inline void collide(C d[9], const CollideParams<C>& p) {
     pair(2, 4, m.uy, Fy, w_<C>(2));
     pair(5, 7, m.ux + m.uy, Fx + Fy, w_<C>(5));
     pair(6, 8, m.uy - m.ux, Fy - Fx, w_<C>(6));
+}
+
+// Multiple-relaxation-time collision (Sec. IV) on the deviations, over the
+// moments (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) of the D2Q9 basis
+// (Lallemand and Luo) with rates S = diag(0, s_e, s_eps, 0, s_q, 0, s_q,
+// omega, omega): m* = m - S (m - m_eq) + (I - S/2) M F.  In this basis the
+// Eq. 8 equilibrium has the moments
+//   (rho, -2 rho + 3 rho u.u, rho - 3 rho u.u, rho u_x, -rho u_x, rho u_y,
+//    -rho u_y, rho (u_x^2 - u_y^2), rho u_x u_y)
+// and Guo's source (F = rho g, u the Guo velocity)
+//   (0, 6 u.F, -6 u.F, F_x, -F_x, F_y, -F_y, 2 (u_x F_x - u_y F_y),
+//    u_x F_y + u_y F_x);
+// the rest-state part w rho0 of the deviations has moments rho0 (1, -2, 1, 0..)
+// and drops out of m - m_eq.  The rows of M are orthogonal with squared
+// norms (9, 36, 36, 6, 12, 6, 12, 4, 4), so M^-1 = M^T diag(1 / norms).
+template <typename C>
+__device__ inline void collide_mrt(C d[9], const CollideParams<C>& p) {
+    const Moments<C> mo = moments<C>(d, p);
+    const C drho = mo.drho, rho = mo.rho, ux = mo.ux, uy = mo.uy;
+    const C s14 = (d[1] + d[2]) + (d[3] + d[4]);
+    const C s58 = (d[5] + d[6]) + (d[7] + d[8]);
+    const C e = C(-4) * d[0] - s14 + C(2) * s58;
+    const C eps = C(4) * d[0] - C(2) * s14 + s58;
+    const C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    const C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    const C qx = C(-2) * (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+    const C qy = C(-2) * (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+    const C pxx = (d[1] - d[2]) + (d[3] - d[4]);
+    const C pxy = (d[5] - d[6]) + (d[7] - d[8]);
+    const C Fx = rho * p.gx, Fy = rho * p.gy;
+    const C uu = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
+    const C om = p.omega;
+    // relaxed moments (deviation form; rho and j: mass kept, momentum + F)
+    const C e1 = e - p.s_e * (e - (C(-2) * drho + C(3) * rho * uu)) + (C(1) - C(0.5) * p.s_e) * (C(6) * uF);
+    const C eps1 = eps - p.s_eps * (eps - (drho - C(3) * rho * uu)) - (C(1) - C(0.5) * p.s_eps) * (C(6) * uF);
+    const C jx1 = jx + Fx, jy1 = jy + Fy;
+    const C qx1 = qx - p.s_q * (qx + rho * ux) - (C(1) - C(0.5) * p.s_q) * Fx;
+    const C qy1 = qy - p.s_q * (qy + rho * uy) - (C(1) - C(0.5) * p.s_q) * Fy;
+    const C pxx1 = pxx - om * (pxx - rho * (ux * ux - uy * uy)) + (C(1) - C(0.5) * om) * (C(2) * (ux * Fx - uy * Fy));
+    const C pxy1 = pxy - om * (pxy - rho * ux * uy) + (C(1) - C(0.5) * om) * (ux * Fy + uy * Fx);
+    // back to populations
+    const C a = drho * C(1.0 / 9.0), b = e1 * C(1.0 / 36.0), c = eps1 * C(1.0 / 36.0);
+    const C jx6 = jx1 * C(1.0 / 6.0), jy6 = jy1 * C(1.0 / 6.0);
+    const C qx12 = qx1 * C(1.0 / 12.0), qy12 = qy1 * C(1.0 / 12.0);
+    const C p4 = pxx1 * C(0.25), s4 = pxy1 * C(0.25);
+    const C ax = a - b - C(2) * c;    // axis directions, even part
+    const C dg = a + C(2) * b + c;    // diagonal directions, even part
+    const C xo = jx6 - C(2) * qx12, yo = jy6 - C(2) * qy12;  // axis odd parts
+    const C xd = jx6 + qx12, yd = jy6 + qy12;                // diagonal odd parts
+    d[0] = a - C(4) * b + C(4) * c;
+    d[1] = ax + xo + p4;
+    d[3] = ax - xo + p4;
+    d[2] = ax + yo - p4;
+    d[4] = ax - yo - p4;
+    d[5] = dg + xd + yd + s4;
+    d[7] = dg - xd - yd + s4;
+    d[6] = dg - xd + yd - s4;
+    d[8] = dg + xd - yd - s4;
+}
+
+// The operator the parameters select (used off the streaming path).
+template <typename C>
+__device__ inline void collide_any(C d[9], const CollideParams<C>& p) {
+    if (p.mrt)
+        collide_mrt<C>(d, p);
+    else
+        collide<C>(d, p);
 }
 
 // Equilibrium deviation f_eq(rho, u) - w rho0 of Eq. 8, one direction.

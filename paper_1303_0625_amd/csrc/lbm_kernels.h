@@ -109,12 +109,12 @@ __device__ inline T* row_at(T* base, uint32_t idx) {
 // only when a source node is solid (or a wall row) are they replaced by the
 // per-direction bounce-back values.  bid/nblk: this workgroup's index among
 // the update workgroups (remapped so that each XCD walks a contiguous band).
-template <typename T, bool NT>
+template <typename T, bool NT, bool MRT = false>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
                                  const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp);
 
-template <typename T, bool NT>
+template <typename T, bool NT, bool MRT>
 __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restrict__ fin,
                                  T* __restrict__ fout, const uint8_t* __restrict__ own_t,
                                  const double* __restrict__ vtab, const StepArgs& a,
@@ -126,11 +126,12 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
     const int y = (int)(gw / wpr);
     const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
     if (y >= a.ny || x >= a.nx) return;
-    step_node<T, NT>(x, y, fin, fout, own_t, vtab, a, cp);
+    step_node<T, NT, MRT>(x, y, fin, fout, own_t, vtab, a, cp);
 }
 
-// The update of node (x, y): pull, bounce-back, collide, store.
-template <typename T, bool NT>
+// The update of node (x, y): pull, bounce-back, collide (BGK, or MRT when
+// MRT), store.
+template <typename T, bool NT, bool MRT>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
                                  const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp) {
@@ -196,7 +197,10 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
             }
         }
     }
-    collide<C>(d, cp);
+    if constexpr (MRT)
+        collide_mrt<C>(d, cp);
+    else
+        collide<C>(d, cp);
     T* w0 = fout + (int64_t)y * a.ystride;
 #pragma unroll
     for (int i = 0; i < 9; ++i) st_stream<NT>(row_at(w0 + i * P, ux), Sto<T>::st(d[i]));
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_
         int64_t n = (int64_t)y * a.nx + x;
         feq_dev<C>((C)rho[n], (C)a.rho0, (C)ux[n] - C(0.5) * cp.gx, (C)uy[n] - C(0.5) * cp.gy, d);
     }
-    collide<C>(d, cp);
+    collide_any<C>(d, cp);
 #pragma unroll
     for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(d[i]);
 }
@@ -238,8 +242,9 @@ __global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_
 // f = f_eq(rho0, u_P(y) - g/2), collided once, at every fluid node: the exact
 // steady plane-Poiseuille profile of BGK + Guo forcing between half-way walls,
 // u_P(y) = g_x / (2 nu) (Y^2 - (y - y_c)^2) + s, Y = ny/2, y_c = (ny - 1)/2,
-// s = g_x (4 (2 tau - 1)^2 - 3) / (4 (2 tau - 1)), nu = (tau - 1/2)/3 (the
-// start a solve reaches without bodies).  Solid nodes are zeroed.
+// s = g_x (16 Lambda - 3) / (24 nu), nu = (tau - 1/2)/3, Lambda = (tau - 1/2)^2
+// for BGK and (tau - 1/2)(1/s_q - 1/2) for the MRT operator (the start a
+// solve reaches without bodies).  Solid nodes are zeroed.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_poiseuille(T* __restrict__ f, const uint8_t* __restrict__ own,
                                                             StepArgs a, CollideParams<typename Sto<T>::C> cp,
@@ -257,11 +262,14 @@ __global__ __launch_bounds__(kBlock) void k_init_poiseuille(T* __restrict__ f, c
     }
     const double nu = (tau - 0.5) / 3.0;
     const double Y = 0.5 * a.ny, yc = 0.5 * (a.ny - 1), dy = y - yc;
-    const double slip = gx * (4.0 * (2.0 * tau - 1.0) * (2.0 * tau - 1.0) - 3.0) / (4.0 * (2.0 * tau - 1.0));
+    // wall slip of the two-rate solution: Lambda = (1/omega - 1/2)(1/s_q - 1/2),
+    // (tau - 1/2)^2 for BGK
+    const double lam = (tau - 0.5) * (cp.mrt ? 1.0 / (double)cp.s_q - 0.5 : tau - 0.5);
+    const double slip = gx * (16.0 * lam - 3.0) / (24.0 * nu);
     const double u = gx / (2.0 * nu) * (Y * Y - dy * dy) + slip;
     C d[9];
     feq_dev<C>((C)a.rho0, (C)a.rho0, (C)(u - 0.5 * gx), (C)(-0.5 * (double)cp.gy), d);
-    collide<C>(d, cp);
+    collide_any<C>(d, cp);
 #pragma unroll
     for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(d[i]);
 }
@@ -527,7 +535,7 @@ struct MoveShared {
 
 // Mover role m: part m / n_movers for body movers[m % n_movers]; lds holds
 // the two byte maps (2 * box_bytes).
-template <typename T>
+template <typename T, bool MRT>
 __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>& sm,
                                  const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, uint8_t* __restrict__ own_n,
@@ -727,6 +735,26 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
         }
         __syncthreads();
         // 4d. collide: moments per newborn node, then one direction per thread
+        // (MRT: the whole node in one thread, then the stores)
+        if constexpr (MRT) {
+            if (threadIdx.x < nbat) {
+                C dd[9];
+#pragma unroll
+                for (int j = 0; j < 9; ++j) dd[j] = sm.nb_new[threadIdx.x][j];
+                collide_mrt<C>(dd, cp);
+#pragma unroll
+                for (int j = 0; j < 9; ++j) sm.nb_new[threadIdx.x][j] = dd[j];
+            }
+            __syncthreads();
+            if (threadIdx.x < nbat * 9) {
+                const int bb = threadIdx.x / 9, j = threadIdx.x % 9;
+                int gx, gy;
+                gidx(sm.nb_list[base + bb], gx, gy);
+                fout[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx] = Sto<T>::st(sm.nb_new[bb][j]);
+            }
+            __syncthreads();
+            continue;
+        }
         if (threadIdx.x < nbat) {
             const Moments<C> mo = moments<C>(sm.nb_new[threadIdx.x], cp);
             sm.nb_mom[threadIdx.x][0] = mo.drho;
@@ -913,7 +941,7 @@ struct RoleCounts {
     int n_force, n_move, n_lead;
 };
 
-template <typename T, bool NT>
+template <typename T, bool NT, bool MRT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fused(
     StepPtrs<T> p, int parity, RoleCounts rc, StepArgs sa, MoveArgs ma, ForceArgs fa,
     CollideParams<typename Sto<T>::C> cp) {
@@ -929,7 +957,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
             force_role<T>(b, sh.f, p.fin, p.links_t, p.seg_cnt_t, p.seg_off, p.chunk_solid, p.chunk_start,
                           p.sol, p.partial + (size_t)(t & 1) * fa.nchunks * 6, t, fa);
         } else if (b < rc.n_force + rc.n_move) {
-            move_role<T>(b - rc.n_force, dyn_lds, sh.m, p.fin, p.fout, p.own_t, p.own_n, p.links_n,
+            move_role<T, MRT>(b - rc.n_force, dyn_lds, sh.m, p.fin, p.fout, p.own_t, p.own_n, p.links_n,
                          p.seg_cnt_n, p.seg_off, p.seg_cap, p.sol, p.vtab, p.movers, p.tctr, parity, ma,
                          cp, p.errflag);
         } else if (b == rc.n_force + rc.n_move) {
@@ -942,7 +970,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         }
         return;
     }
-    step_role<T, NT>((uint32_t)(b - rc.n_lead), gridDim.x - (uint32_t)rc.n_lead, p.fin, p.fout, p.own_t,
+    step_role<T, NT, MRT>((uint32_t)(b - rc.n_lead), gridDim.x - (uint32_t)rc.n_lead, p.fin, p.fout, p.own_t,
                      p.vtab, sa, cp);
 }
 

@@ -98,6 +98,7 @@ _SIG = {
     "lbm_batch_init_poiseuille": (_I32, [_VP, _I32]),
     "lbm_batch_set_active": (_I32, [_VP, _I32, _I32]),
     "lbm_init_poiseuille": (_I32, [_VP]),
+    "lbm_set_collision": (_I32, [_VP, _I32, _VP]),
     "lbm_batch_init_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32]),
     "lbm_batch_time": (_I64, [_VP]),
     "lbm_batch_destroy": (None, [_VP]),
@@ -336,6 +337,16 @@ def lbm_batch_init_poiseuille(b, case_id: int) -> None:
     _bcheck(load_library().lbm_batch_init_poiseuille(b, case_id), b)
 
 
+LBM_BGK, LBM_MRT = 0, 1
+# relaxation rates (s_e, s_eps, s_q) of the paper's MRT simulations (Sec. IV)
+PAPER_MRT_RATES = (1.64, 1.54, 1.9)
+
+
+def lbm_set_collision(ctx, model: int, rates=None) -> None:
+    arr = (ctypes.c_double * 3)(*(rates if rates is not None else (0.0, 0.0, 0.0)))
+    _check(load_library().lbm_set_collision(ctx, int(model), arr), ctx)
+
+
 def lbm_init_poiseuille(ctx) -> None:
     _check(load_library().lbm_init_poiseuille(ctx), ctx)
 
@@ -501,7 +512,8 @@ class Lattice:
     current stream at creation time.
     """
 
-    def __init__(self, case: dict, dtype="f64", history_steps=None, device="cuda", stream=None):
+    def __init__(self, case: dict, dtype="f64", history_steps=None, device="cuda", stream=None, mrt=None):
+        """mrt: None for the BGK operator, else the MRT rates (s_e, s_eps, s_q)."""
         import torch
 
         self.torch = torch
@@ -522,6 +534,8 @@ class Lattice:
         self._destroy = load_library().lbm_destroy  # usable at interpreter exit
         self.ctx = lbm_create(self.grid, float(case["tau"]), solids, self.history_steps,
                               self._ws_ptr, nbytes, self.stream.cuda_stream)
+        if mrt is not None:
+            lbm_set_collision(self.ctx, LBM_MRT, tuple(float(r) for r in mrt))
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)

@@ -13,10 +13,10 @@ from __future__ import annotations
 import numpy as np
 
 
-def oracle_sim(oracle, c):
+def oracle_sim(oracle, c, mrt=None):
     return oracle.OracleSim(c["nx"], c["ny"], c["tau"], walls_y=c["walls_y"], rho0=c["rho0"],
                             gx=c["gx"], gy=c["gy"], u0=c["u0"], wall_v=c["wall_v"],
-                            refill=c["refill"], bodies=c["bodies"])
+                            refill=c["refill"], bodies=c["bodies"], mrt=mrt)
 
 
 def rel_field_err(gpu, ref, mask):
