@@ -402,6 +402,17 @@ lbm_status lbm_nn_forward(lbm_nn* nn, const float* d_x, int32_t batch, float* d_
  * the last lbm_nn_forward; gy [batch][h][w][3] FP32 device memory. */
 lbm_status lbm_nn_backward(lbm_nn* nn, const float* d_gy);
 
+/* One convolution layer alone (layers 1..13), for inspection and tests of
+ * the convolution kernels: y = ReLU(conv3x3(x, W) + b) with the network's
+ * current parameters rounded to the compute type, x periodic, y zero
+ * outside the image.  x is the layer's input at its level,
+ * [batch][h_l][w_l][x_cs] in the compute type (channels [0, cin) used,
+ * x_cs >= cin), y receives [batch][h_l][w_l][y_cs] (channels [0, cout)
+ * written, y_cs >= cout); strides multiples of 8, tensors 16-byte aligned
+ * device memory.  Leaves the network's state untouched; synchronises. */
+lbm_status lbm_nn_layer_forward(lbm_nn* nn, int32_t layer, int32_t batch, const void* d_x, int32_t x_cs,
+                                void* d_y, int32_t y_cs);
+
 /* Weight and bias gradient of one layer alone, for inspection and tests of
  * the weight-gradient kernels: dW[co][ky][kx][ci] = sum over pixels p of
  * g[p][co] x[p + (ky - 1, kx - 1)][ci] (x periodic, y zero outside the

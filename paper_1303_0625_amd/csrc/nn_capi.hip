@@ -255,6 +255,19 @@ void conv(lbm_nn* n, int level, const void* in, int in_cs, int cin, const void* 
     a.W = p.W >> level;
     a.P = (int)((int64_t)n->batch * a.H * a.W);
     a.out_f32 = sizeof(OT) == 4 ? 1 : 0;
+    if (sizeof(T) == 2 && cin % 32 == 0 && a.H % kC9Rows == 0 && a.W % 32 == 0) {
+        // BF16 with the input tile held across the nine taps, when the
+        // launch still gives >= 256 workgroups
+        const int64_t tiles = (int64_t)n->batch * (a.H / kC9Rows) * (a.W / 32);
+        if (cout_pad % 64 == 0 && tiles * (cout_pad / 64) >= 512) {
+            k_conv9<2><<<dim3((unsigned)tiles, cout_pad / 64), 256, 0, n->st>>>(a);
+            return;
+        }
+        if (tiles * (cout_pad / 32) >= 256) {
+            k_conv9<1><<<dim3((unsigned)tiles, cout_pad / 32), 256, 0, n->st>>>(a);
+            return;
+        }
+    }
     if (sizeof(T) == 2) {
         // BF16: LDS-staged tiles (BM x BN).  The widest tile that divides the
         // output channels and still gives >= 512 workgroups (two per CU),
@@ -709,6 +722,38 @@ lbm_status lbm_nn_backward(lbm_nn* n, const float* d_gy) {
     else
         k_pack_head_grad<float><<<blocks(P), kEw, 0, n->st>>>(d_gy, P, (float*)buf(n, G_HEAD));
     backward(n);
+    return sync_check(n);
+}
+
+lbm_status lbm_nn_layer_forward(lbm_nn* n, int32_t layer, int32_t batch, const void* d_x, int32_t x_cs,
+                                void* d_y, int32_t y_cs) {
+    if (!n || !d_x || !d_y) return LBM_EINVAL;
+    if (layer < 1 || layer > kLayers - 2) {
+        nn_set_err(n->err, "layer must be in [1, %d]", kLayers - 2);
+        return LBM_EINVAL;
+    }
+    lbm_status rs = check_batch(n, batch);
+    if (rs != LBM_OK) return rs;
+    const LayerDev& L = n->p.L[layer];
+    if (x_cs < L.cin || x_cs % 8 != 0 || y_cs < L.cout || y_cs % 8 != 0 ||
+        ((uintptr_t)d_x | (uintptr_t)d_y) % 16 != 0) {
+        nn_set_err(n->err, "layer %d needs x_cs >= %d and y_cs >= %d, multiples of 8, 16-byte aligned tensors",
+                   layer, L.cin, L.cout);
+        return LBM_EINVAL;
+    }
+    const int last = n->batch;
+    n->batch = batch;
+    pack_weights(n);
+    const int lv = n->p.level[layer];
+    if (n->dtype == LBM_BF16)
+        conv<__bf16, __bf16>(n, lv, d_x, x_cs, L.cin_pad, at<__bf16>(n, n->p.o_wf) + L.wf_off,
+                             at<float>(n, n->p.o_bias) + L.b_off, d_y, y_cs, 0, L.cout, L.cout_pad, true, nullptr,
+                             0, 0);
+    else
+        conv<float, float>(n, lv, d_x, x_cs, L.cin_pad, at<float>(n, n->p.o_wf) + L.wf_off,
+                           at<float>(n, n->p.o_bias) + L.b_off, d_y, y_cs, 0, L.cout, L.cout_pad, true, nullptr, 0,
+                           0);
+    n->batch = last;
     return sync_check(n);
 }
 

@@ -310,6 +310,111 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
     }
 }
 
+// 3x3 convolution with the input tile held across the nine taps (BF16).  A
+// workgroup computes an output tile of kC9Rows rows x 32 pixels of one image
+// for 32 NB output channels; per 32-channel chunk of the input it stages in
+// LDS the tile's input with a one-pixel halo (rows y0 - 1 .. y0 + kC9Rows,
+// columns x0 - 1 .. x0 + 32, x periodic, rows outside the image zero) and
+// the chunk's weights of all nine taps, so each input value is read from
+// memory once per chunk instead of once per tap.  Wave w takes output rows
+// 2w and 2w + 1; the operand of tap (dy, dx) for output pixel (r, m) is the
+// staged pixel (r + 1 + dy, m + 1 + dx): 8 consecutive channels, one aligned
+// 16-byte LDS vector.  Same epilogue as k_conv_lds.  Needs H % kC9Rows == 0,
+// W % 32 == 0, cin % 32 == 0 and cout_pad % (32 NB) == 0.
+constexpr int kC9Rows = 8;
+constexpr int kC9Pitch = 40;  // LDS elements per staged pixel / weight row (32 + 8 pad)
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_conv9(ConvArgs a) {
+    constexpr int IR = kC9Rows + 2, IX = 34;         // staged input rows, pixels
+    constexpr int IN_UNITS = IR * IX * 4;            // 16-byte units (8 channels)
+    constexpr int W_UNITS = 32 * NB * 9 * 4;
+    __shared__ __align__(16) __bf16 Is[IR * IX * kC9Pitch];
+    __shared__ __align__(16) __bf16 Ws[32 * NB * 9 * kC9Pitch];
+    const int t = threadIdx.x;
+    const int l = t & 63, wave = t >> 6;
+    const int kg = l >> 5;
+    const int nseg = a.W / 32, nrow = a.H / kC9Rows;
+    int tile = blockIdx.x;
+    const int seg = tile % nseg;
+    tile /= nseg;
+    const int rb = tile % nrow;
+    const int b = tile / nrow;
+    const int x0 = seg * 32, y0 = rb * kC9Rows;
+    const int nbase = blockIdx.y * 32 * NB;
+    const __bf16* in = static_cast<const __bf16*>(a.in);
+    const __bf16* w = static_cast<const __bf16*>(a.w);
+    const int wrow = 9 * a.cin;
+    f32x16 acc[2][NB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        // stage the input tile and the weights of this chunk
+        for (int u = t; u < IN_UNITS; u += 256) {
+            const int cg = u & 3, px = (u >> 2) % IX, r = (u >> 2) / IX;
+            const int yy = y0 - 1 + r;
+            int xx = x0 - 1 + px;
+            xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (yy >= 0 && yy < a.H)
+                v = *reinterpret_cast<const uint4*>(in + ((int64_t)(b * a.H + yy) * a.W + xx) * a.in_cs + c0 + 8 * cg);
+            *reinterpret_cast<uint4*>(&Is[(r * IX + px) * kC9Pitch + 8 * cg]) = v;
+        }
+        for (int u = t; u < W_UNITS; u += 256) {
+            const int cg = u & 3, tap = (u >> 2) % 9, n = (u >> 2) / 9;
+            *reinterpret_cast<uint4*>(&Ws[(n * 9 + tap) * kC9Pitch + 8 * cg]) =
+                *reinterpret_cast<const uint4*>(w + (int64_t)(nbase + n) * wrow + tap * a.cin + c0 + 8 * cg);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                Frag<__bf16> fa[2], fb[NB];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const int r = 2 * wave + i + 1 + dy, px = (l & 31) + 1 + dx;
+                    fa[i].v = *reinterpret_cast<const bf16x8*>(&Is[(r * IX + px) * kC9Pitch + 16 * ks + 8 * kg]);
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    fb[j].v = *reinterpret_cast<const bf16x8*>(
+                        &Ws[((32 * j + (l & 31)) * 9 + tap) * kC9Pitch + 16 * ks + 8 * kg]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) mma(acc[i][j], fa[i], fb[j]);
+            }
+        }
+        __syncthreads();
+    }
+    const __bf16* mask = static_cast<const __bf16*>(a.mask);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int n = nbase + 32 * j + (l & 31);
+        if (n >= a.cout) continue;
+        const float bv = a.bias ? a.bias[n] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int p = (b * a.H + y0 + 2 * wave + i) * a.W + x0 + acc_row(q, l);
+                float v = acc[i][j][q] + bv;
+                if (a.relu) v = v > 0.0f ? v : 0.0f;
+                if (mask && !(to_f(mask[(int64_t)p * a.mask_cs + a.mask_co + n]) > 0.0f)) v = 0.0f;
+                if (a.out_f32)
+                    static_cast<float*>(a.out)[(int64_t)p * a.out_cs + a.out_co + n] = v;
+                else
+                    static_cast<__bf16*>(a.out)[(int64_t)p * a.out_cs + a.out_co + n] = (__bf16)v;
+            }
+    }
+}
+
 // ------------------------------------------------------------------ weight gradient
 // dW[co][tap][ci] = sum over pixels p of g[p][co] x(p shifted by tap)[ci].
 // Workgroup (tile, split): co block of 32 MB, ci block of 32 NB, one tap;

@@ -112,6 +112,7 @@ _SIG = {
     "lbm_nn_forward": (_I32, [_VP, _VP, _I32, _VP]),
     "lbm_nn_backward": (_I32, [_VP, _VP]),
     "lbm_nn_layer_wgrad": (_I32, [_VP, _I32, _I32, _VP, _I32, _VP, _I32, _VP]),
+    "lbm_nn_layer_forward": (_I32, [_VP, _I32, _I32, _VP, _I32, _VP, _I32]),
     "lbm_nn_adam": (_I32, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "lbm_nn_train_step": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I32, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_double)]),
@@ -409,6 +410,10 @@ def lbm_nn_forward(n, d_x, batch: int, d_y) -> None:
 
 def lbm_nn_backward(n, d_gy) -> None:
     _ncheck(load_library().lbm_nn_backward(n, d_gy), n)
+
+
+def lbm_nn_layer_forward(n, layer, batch, d_x, x_cs, d_y, y_cs) -> None:
+    _ncheck(load_library().lbm_nn_layer_forward(n, layer, batch, d_x, x_cs, d_y, y_cs), n)
 
 
 def lbm_nn_layer_wgrad(n, layer, batch, d_x, x_cs, d_g, g_cs, d_grad) -> None:
@@ -792,6 +797,15 @@ class WarmStartNet:
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
         lbm_nn_adam(self.n, lr, beta1, beta2, eps)
+
+    def layer_forward(self, layer, x):
+        """ReLU(conv(x) + b) of one layer (1..13) on x [B][h_l][w_l][x_cs]
+        (device tensor of the compute type) -> [B][h_l][w_l][cout]."""
+        cout, cin = self.layer_shapes()[layer]
+        x = x.contiguous()
+        y = self.torch.zeros(x.shape[:3] + (cout,), dtype=x.dtype, device=x.device)
+        lbm_nn_layer_forward(self.n, layer, x.shape[0], x.data_ptr(), x.shape[-1], y.data_ptr(), cout)
+        return y
 
     def layer_wgrad(self, layer, x, g):
         """Weight and bias gradient of one layer from its input x

@@ -337,3 +337,39 @@ def test_layer_wgrad_exact_full(torch_mod, lbm_mod):
     """The 256 x 128 training lattice at batch 3 (every level nine-tap in
     BF16; split counts from the planner, ragged last splits)."""
     _layer_wgrad_case(torch_mod, lbm_mod, 128, 256, CH, 3, "bf16", 72)
+
+
+def _layer_forward_case(torch, lbm, h, w, batch, seed):
+    """Layers 1..13 through lbm_nn_layer_forward on random BF16 inputs, against
+    ReLU(conv + b) of the oracle in FP64 on the same inputs and the weights
+    rounded to bfloat16.  The kernels add exact products in FP32 and round
+    the sum to bfloat16 once: |y - ref| <= 2^-8 |ref| + 1e-5 max |ref|."""
+    net = lbm.WarmStartNet(h, w, batch, dtype="bf16", ch=CH)
+    params = he_params(seed)
+    net.set_params(params)
+    layers = co.unpack(params, CH)
+    rng = np.random.default_rng(seed + 1)
+    for k in range(1, 14):
+        cout, cin = net.layer_shapes()[k]
+        lv = net.LAYER_LEVELS[k]
+        hl, wl = h >> lv, w >> lv
+        xt = torch.tensor(rng.normal(size=(batch, hl, wl, cin)), dtype=torch.bfloat16, device="cuda")
+        y = net.layer_forward(k, xt).float().cpu().numpy().astype(np.float64)
+        x64 = xt.float().cpu().numpy().astype(np.float64)
+        Wk, bk = layers[k]
+        ref = np.maximum(co.conv(x64, co.bf16(Wk), bk), 0.0)
+        excess = (np.abs(y - ref) - 2.0 ** -8 * np.abs(ref)).max() / np.abs(ref).max()
+        _say(f"layer_forward {h}x{w} batch {batch} layer {k} ({cout}x{cin}, level {lv}): excess {excess:.2e}")
+        assert excess <= 1e-5, (k, excess)
+
+
+def test_layer_forward_exact_full(torch_mod, lbm_mod):
+    """The 256 x 128 training lattice at batch 3 (levels 0-2 on the kernel that
+    holds the input tile across the taps, level 3 on the LDS-tiled GEMM)."""
+    _layer_forward_case(torch_mod, lbm_mod, 128, 256, 3, 81)
+
+
+def test_layer_forward_exact_small(torch_mod, lbm_mod):
+    """32 x 64 lattice: too few tiles for the tap-holding kernel, every layer
+    on the LDS-tiled GEMM."""
+    _layer_forward_case(torch_mod, lbm_mod, H, W, 2, 82)
