@@ -93,6 +93,11 @@ def _load():
     lib.orc_collide_node_mrt.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp]
     lib.orc_mrt_matrix.argtypes = [dp]
     lib.orc_mrt_inverse.argtypes = [dp]
+    lib.orc_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    lib.orc_set_free.restype = ctypes.c_int
+    lib.orc_set_gravity.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.orc_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+    lib.orc_body_state.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -199,6 +204,21 @@ class OracleSim:
         if h:
             self._lib.orc_destroy(h)
             self._h = None
+
+    def set_free(self, body: int, rho_s: float, omega0: float = 0.0) -> None:
+        """Body `body` (1-based disc) becomes a free particle of density rho_s."""
+        if self._lib.orc_set_free(self._h, int(body), float(rho_s), float(omega0)) != 0:
+            raise ValueError("oracle rejected the free body")
+
+    def set_gravity(self, G, scheme: int) -> None:
+        self._lib.orc_set_gravity(self._h, float(G[0]), float(G[1]), int(scheme))
+
+    def body_state(self, body: int) -> np.ndarray:
+        """{X, Y, V_x, V_y, Omega} of body `body` now."""
+        out = np.zeros(5)
+        if self._lib.orc_body_state(self._h, int(body), _dp(out)) != 0:
+            raise IndexError(body)
+        return out
 
     @property
     def t(self) -> int:

@@ -17,7 +17,9 @@
  *   O4 advection     Eq. 3; a population whose source node is solid is the
  *                    half-way bounce-back of the node's own opposite population
  *                    plus the moving-boundary term 6 w_i rho_w (e_i . v)
- *   O5 move bodies   positions at t+1, rasterise G_{t+1}
+ *   O5 move bodies   positions at t+1 (prescribed, or for free bodies the
+ *                    Newton-Euler update from the step's force and torque),
+ *                    rasterise G_{t+1}
  *   O6 covered nodes populations dropped
  *   O7 newborn nodes refilled by extrapolation along the participating links
  *                    (A1 second order, A2 linear, A3 neighbour value), averaged
@@ -46,6 +48,15 @@ struct orc_sim {
     int refill, rho_w_local;
     int mrt;         /* 0: BGK; 1: MRT with rates s_rate */
     double s_rate[9];
+    /* free bodies (Sec. IV): state at step t and the centre at t+1 */
+    struct orc_dyn {
+        int free_;
+        double X, Y, Vx, Vy, Om;   /* centre, velocity, angular velocity at t */
+        double Xn, Yn;             /* centre at t+1 (O5) */
+        double M, I, A;            /* mass, moment of inertia, area */
+    } * dyn;
+    double Gx, Gy;   /* gravity acting on free bodies (buoyancy-corrected) */
+    int dyn_scheme;  /* ORC_CME or ORC_GME force drives them */
     int nb;
     orc_body* body;
     long t;
@@ -97,6 +108,34 @@ static int inside(const orc_body* b, double X, double Y, long x, long y) {
     return fabs(dx) <= b->a && fabs(dy) <= b->b;
 }
 
+/* Centre of body k at step t (t = s->t or s->t + 1 for a free body). */
+static void body_center(const orc_sim* s, int k, long t, double* X, double* Y) {
+    const struct orc_dyn* d = &s->dyn[k];
+    if (d->free_) {
+        *X = t == s->t ? d->X : d->Xn;
+        *Y = t == s->t ? d->Y : d->Yn;
+    } else {
+        body_pos(&s->body[k], t, X, Y);
+    }
+}
+
+static double min_image(double d, int n);
+
+/* Velocity of body k's surface at the point (px, py) at step t: V + Omega
+ * z x (p - X), minimum image; a prescribed body translates rigidly. */
+static void wall_velocity(const orc_sim* s, int k, double px, double py, double* vx, double* vy) {
+    const struct orc_dyn* d = &s->dyn[k];
+    if (!d->free_) {
+        *vx = s->body[k].vx;
+        *vy = s->body[k].vy;
+        return;
+    }
+    double rx = min_image(px - d->X, s->nx);
+    double ry = s->walls_y ? (py - d->Y) : min_image(py - d->Y, s->ny);
+    *vx = d->Vx - d->Om * ry;
+    *vy = d->Vy + d->Om * rx;
+}
+
 /* Rasterise all bodies at step t into own (0 = fluid).  Every integer point
  * of each body's bounding range is tested and mapped to its periodic image. */
 static void rasterise(const orc_sim* s, long t, int* own) {
@@ -104,7 +143,7 @@ static void rasterise(const orc_sim* s, long t, int* own) {
     for (int k = 0; k < s->nb; ++k) {
         const orc_body* b = &s->body[k];
         double X, Y;
-        body_pos(b, t, &X, &Y);
+        body_center(s, k, t, &X, &Y);
         double hx = b->a;
         double hy = (b->kind == ORC_DISC) ? b->a : b->b;
         long x0 = (long)floor(X - hx) - 1, x1 = (long)ceil(X + hx) + 1;
@@ -345,6 +384,7 @@ orc_sim* orc_create(int nx, int ny, int walls_y, double tau, double rho0, double
     s->nb = n_bodies;
     s->body = (orc_body*)calloc((size_t)(n_bodies > 0 ? n_bodies : 1), sizeof(orc_body));
     for (int k = 0; k < n_bodies; ++k) s->body[k] = bodies[k];
+    s->dyn = (struct orc_dyn*)calloc((size_t)(n_bodies > 0 ? n_bodies : 1), sizeof(struct orc_dyn));
     size_t n = (size_t)nx * (size_t)ny;
     s->f = (double*)calloc(9 * n, sizeof(double));
     s->ft = (double*)calloc(9 * n, sizeof(double));
@@ -363,8 +403,46 @@ orc_sim* orc_create(int nx, int ny, int walls_y, double tau, double rho0, double
     return s;
 }
 
+int orc_set_free(orc_sim* s, int body, double rho_s, double omega0) {
+    if (body < 1 || body > s->nb || s->t != 0 || !(rho_s > 0.0)) return -1;
+    const orc_body* b = &s->body[body - 1];
+    if (b->kind != ORC_DISC) return -1;
+    struct orc_dyn* d = &s->dyn[body - 1];
+    const double pi = 3.14159265358979323846;
+    d->free_ = 1;
+    d->X = b->cx;
+    d->Y = b->cy;
+    d->Vx = b->vx;
+    d->Vy = b->vy;
+    d->Om = omega0;
+    d->A = pi * b->a * b->a;
+    d->M = rho_s * d->A;
+    d->I = 0.5 * d->M * b->a * b->a;
+    return 0;
+}
+
+void orc_set_gravity(orc_sim* s, double Gx, double Gy, int scheme) {
+    s->Gx = Gx;
+    s->Gy = Gy;
+    s->dyn_scheme = scheme == ORC_GME ? ORC_GME : ORC_CME;
+}
+
+int orc_body_state(const orc_sim* s, int body, double out[5]) {
+    if (body < 1 || body > s->nb) return -1;
+    double X, Y;
+    body_center(s, body - 1, s->t, &X, &Y);
+    const struct orc_dyn* d = &s->dyn[body - 1];
+    out[0] = X;
+    out[1] = Y;
+    out[2] = d->free_ ? d->Vx : s->body[body - 1].vx;
+    out[3] = d->free_ ? d->Vy : s->body[body - 1].vy;
+    out[4] = d->free_ ? d->Om : 0.0;
+    return 0;
+}
+
 void orc_destroy(orc_sim* s) {
     if (!s) return;
+    free(s->dyn);
     free(s->body);
     free(s->f);
     free(s->ft);
@@ -440,8 +518,8 @@ static void one_step(orc_sim* s) {
                 } else {
                     sid = s->own[idx(s, xb, yb)];
                     if (sid == 0) continue;
-                    vx = s->body[sid - 1].vx;
-                    vy = s->body[sid - 1].vy;
+                    /* boundary velocity at the link midpoint x_f + e_i/2 */
+                    wall_velocity(s, sid - 1, x + 0.5 * EX[i], y + 0.5 * EY[i], &vx, &vy);
                 }
                 double rho_w = s->rho0;
                 if (s->rho_w_local) {
@@ -458,7 +536,7 @@ static void one_step(orc_sim* s) {
                 double tc = 0.0, tg = 0.0;
                 if (sid > 0) {
                     double X, Y;
-                    body_pos(&s->body[sid - 1], t, &X, &Y);
+                    body_center(s, sid - 1, t, &X, &Y);
                     /* intersection point S at the link midpoint */
                     double rx = min_image(x + 0.5 * EX[i] - X, nx);
                     double ry = s->walls_y ? (y + 0.5 * EY[i] - Y) : min_image(y + 0.5 * EY[i] - Y, ny);
@@ -496,8 +574,8 @@ static void one_step(orc_sim* s) {
                         s->fn[pidx(s, i, x, y)] = s->ft[pidx(s, i, xs, ys)];
                         continue;
                     }
-                    vx = s->body[sid - 1].vx;
-                    vy = s->body[sid - 1].vy;
+                    /* boundary velocity at the link midpoint x - e_i/2 */
+                    wall_velocity(s, sid - 1, x - 0.5 * EX[i], y - 0.5 * EY[i], &vx, &vy);
                 }
                 double rho_w = s->rho0;
                 if (s->rho_w_local) {
@@ -509,7 +587,27 @@ static void one_step(orc_sim* s) {
             }
         }
 
-    /* O5: move bodies, rasterise G_{t+1}. */
+    /* O5: move bodies.  A free body: M dV/dt = F + (M - rho0 A) G,
+     * I dOmega/dt = T with the step's force and torque of the chosen scheme,
+     * explicit: V(t+1) = V(t) + (F + (M - rho0 A) G)/M, Omega(t+1) =
+     * Omega(t) + T/I, X(t+1) = X(t) + V(t+1).  Then rasterise G_{t+1}. */
+    double *nvx = NULL, *nvy = NULL, *nom = NULL;
+    if (s->nb > 0) {
+        nvx = (double*)calloc((size_t)s->nb * 3, sizeof(double));
+        nvy = nvx + s->nb;
+        nom = nvx + 2 * s->nb;
+    }
+    for (int k = 0; k < s->nb; ++k) {
+        struct orc_dyn* d = &s->dyn[k];
+        if (!d->free_) continue;
+        const double* hk = h + 6 * (k + 1) + 3 * s->dyn_scheme;
+        const double ext = d->M - s->rho0 * d->A;
+        nvx[k] = d->Vx + (hk[0] + ext * s->Gx) / d->M;
+        nvy[k] = d->Vy + (hk[1] + ext * s->Gy) / d->M;
+        nom[k] = d->Om + hk[2] / d->I;
+        d->Xn = d->X + nvx[k];
+        d->Yn = d->Y + nvy[k];
+    }
     rasterise(s, t + 1, s->own_next);
     for (long n = 0; n < (long)nx * ny; ++n)
         s->oldfluid[n] = (s->own[n] == 0 && s->own_next[n] == 0);
@@ -522,15 +620,34 @@ static void one_step(orc_sim* s) {
             if (s->own[n] == 0 && s->own_next[n] != 0) {
                 for (int i = 0; i < 9; ++i) s->fn[pidx(s, i, x, y)] = 0.0;
             } else if (s->own[n] != 0 && s->own_next[n] == 0) {
-                const orc_body* b = &s->body[s->own[n] - 1];
+                const int k = s->own[n] - 1;
+                const orc_body* b = &s->body[k];
+                double vx = b->vx, vy = b->vy;
+                if (s->dyn[k].free_) {
+                    /* the body's surface velocity at the node at t+1 */
+                    double rx = min_image(x - s->dyn[k].Xn, nx);
+                    double ry = s->walls_y ? (y - s->dyn[k].Yn) : min_image(y - s->dyn[k].Yn, ny);
+                    vx = nvx[k] - nom[k] * ry;
+                    vy = nvy[k] + nom[k] * rx;
+                }
                 double out[9];
-                orc_refill_node(nx, ny, s->walls_y, s->fn, s->oldfluid, x, y, s->refill, s->rho0,
-                                b->vx, b->vy, out);
+                orc_refill_node(nx, ny, s->walls_y, s->fn, s->oldfluid, x, y, s->refill, s->rho0, vx, vy,
+                                out);
                 for (int i = 0; i < 9; ++i) s->fn[pidx(s, i, x, y)] = out[i];
             }
         }
 
     /* O8 */
+    for (int k = 0; k < s->nb; ++k) {
+        struct orc_dyn* d = &s->dyn[k];
+        if (!d->free_) continue;
+        d->X = d->Xn;
+        d->Y = d->Yn;
+        d->Vx = nvx[k];
+        d->Vy = nvy[k];
+        d->Om = nom[k];
+    }
+    free(nvx);
     double* tmp = s->f;
     s->f = s->fn;
     s->fn = tmp;

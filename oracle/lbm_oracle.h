@@ -94,6 +94,24 @@ void orc_link_force(int i, double a, double b, double vx, double vy,
 void orc_collide_node(const double f[9], double tau, double gx, double gy,
                       double out[9]);
 
+/* Make disc `body` (1-based) a free body (Sec. IV: particles moving under
+ * gravity and the hydrodynamic force) before the first step: density rho_s,
+ * mass M = rho_s pi r^2, moment of inertia I = M r^2 / 2, initial velocity
+ * its (vx, vy), initial angular velocity omega0.  Each step, after the
+ * forces of step t (scheme of orc_set_gravity), V(t+1) = V(t) + (F +
+ * (M - rho0 pi r^2) G)/M, Omega(t+1) = Omega(t) + T/I, X(t+1) = X(t) +
+ * V(t+1); its surface moves at V + Omega z x (p - X) in bounce-back, in the
+ * force of every link (at the link midpoint) and in the refill fallback.
+ * Returns 0, or -1 (not a disc, t > 0, rho_s <= 0, bad index). */
+int orc_set_free(orc_sim* s, int body, double rho_s, double omega0);
+
+/* Gravity G on free bodies (buoyancy-corrected: (M - rho0 A) G) and the force
+ * scheme (ORC_CME / ORC_GME) that drives them. */
+void orc_set_gravity(orc_sim* s, double Gx, double Gy, int scheme);
+
+/* out = {X, Y, V_x, V_y, Omega} of body `body` at the current step. */
+int orc_body_state(const orc_sim* s, int body, double out[5]);
+
 /* Switch the collision to the multiple-relaxation-time operator of Sec. IV
  * with S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 1/tau, 1/tau) over the moments
  * (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy); same equilibrium (Eq. 8) and
