@@ -155,6 +155,30 @@ lbm_status lbm_fields(lbm_ctx* ctx, void* d_rho, void* d_ux, void* d_uy, int32_t
 lbm_status lbm_init_fields(lbm_ctx* ctx, const void* d_rho, const void* d_ux, const void* d_uy,
                            int32_t in_dtype);
 
+/* Free bodies (Sec. IV: particles moving under gravity and the hydrodynamic
+ * force).  Before the first step, make body solid_id a free rigid disc of
+ * density rho_s (it must be a disc created with moves = 1; its (vx, vy) is
+ * the initial velocity, omega0 the initial angular velocity): mass
+ * M = rho_s pi r^2, moment of inertia I = M r^2 / 2.  After the forces of
+ * step t (the scheme lbm_set_gravity names, GME by default): V(t+1) = V(t) +
+ * (F + (M - rho0 pi r^2) G)/M, Omega(t+1) = Omega(t) + T/I, X(t+1) = X(t) +
+ * V(t+1); its surface moves at V + Omega z x (p - X) in bounce-back, in the
+ * force of every link (p the link midpoint) and in the refill fallback.
+ * Free bodies add one small launch per step; their paths are not validated
+ * ahead: meeting a wall or another body, or moving more than half a node in
+ * a step, makes the next synchronising call return LBM_EGEOM.  Checkpoints
+ * (lbm_save / lbm_load) are refused while free bodies exist.  Synchronises. */
+lbm_status lbm_set_free_body(lbm_ctx* ctx, int32_t solid_id, double rho_s, double omega0);
+
+/* Gravity G = (gx, gy) on free bodies (buoyancy-corrected: the fluid carries
+ * no gravity) and the force scheme (LBM_CME / LBM_GME) that drives them. */
+lbm_status lbm_set_gravity(lbm_ctx* ctx, double gx, double gy, int32_t scheme);
+
+/* out = {X, Y, V_x, V_y, Omega} of body solid_id at the current step
+ * (prescribed bodies: their closed-form centre and velocity, Omega = 0).
+ * Synchronises. */
+lbm_status lbm_body_state(lbm_ctx* ctx, int32_t solid_id, double out[5]);
+
 /* Collision operators. */
 typedef enum { LBM_BGK = 0, LBM_MRT = 1 } lbm_collision;
 

@@ -258,7 +258,7 @@ void batch_monitor_tw(lbm_batch* b, hipStream_t st, int k_steps, double tol) {
     k_batch_force<T><<<(unsigned)b->chunks.size(), kBlock, 0, st>>>(
         bws<CaseDev>(b, b->o_cases), bws<BatchChunk>(b, b->o_chunks), bws<int>(b, b->o_conv),
         bws<T>(b, b->o_f), bws<uint32_t>(b, b->o_links), bws<int>(b, b->o_segcnt), bws<int>(b, b->o_segoff),
-        bws<SolidDev>(b, b->o_sol), bws<double>(b, b->o_fpart), p, b->t);
+        bws<SolidDev>(b, b->o_sol), bws<double>(b, b->o_vtab), bws<double>(b, b->o_fpart), p, b->t);
     if (b->n_tiles > 0)
         k_batch_monitor<T, W><<<b->n_tiles, W * 64, 0, st>>>(
             bws<CaseDev>(b, b->o_cases), bws<Tile>(b, b->o_tiles), bws<int>(b, b->o_conv), bws<T>(b, b->o_f),
@@ -295,7 +295,7 @@ void batch_init_case(lbm_batch* b, int c, hipStream_t st, const void* rho, const
     using C = typename Sto<T>::C;
     const CaseDev& d = b->cd[c];
     const int64_t nb = ((int64_t)d.sa.ny * d.sa.rowlen + kBlock - 1) / kBlock;
-    CollideParams<C> cp;
+    CollideParams<C> cp{};
     cp.rho0 = (C)d.cp64.rho0;
     cp.omega = (C)d.cp64.omega;
     cp.gx = (C)d.cp64.gx;
@@ -320,7 +320,7 @@ void batch_poiseuille_case(lbm_batch* b, int c, hipStream_t st) {
     using C = typename Sto<T>::C;
     const CaseDev& d = b->cd[c];
     const int64_t nb = ((int64_t)d.sa.ny * d.sa.rowlen + kBlock - 1) / kBlock;
-    CollideParams<C> cp;
+    CollideParams<C> cp{};
     cp.rho0 = (C)d.cp64.rho0;
     cp.omega = (C)d.cp64.omega;
     cp.gx = (C)d.cp64.gx;

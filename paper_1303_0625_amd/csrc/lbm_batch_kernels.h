@@ -65,7 +65,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_step(const CaseDev* __rest
     const int x = (w - y * cd.wpr) * 64 + (int)(threadIdx.x & 63);
     if (x >= cd.sa.nx) return;
     step_node<T, NT>(x, y, fbase + cd.f_off[parity], fbase + cd.f_off[parity ^ 1], obase + cd.own_off,
-                     vtab_all + 2 * cd.solid_base, cd.sa, case_cp<T>(cd));
+                     vtab_all + 2 * cd.solid_base, nullptr, cd.sa, case_cp<T>(cd));
 }
 
 // Force chunks of every active case at the current state (parity).
@@ -82,6 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const CaseDev* __restric
                                                         const int* __restrict__ seg_cnt,
                                                         const int* __restrict__ seg_off,
                                                         const SolidDev* __restrict__ sol_all,
+                                                        const double* __restrict__ vtab_all,
                                                         double* __restrict__ partial, int parity,
                                                         int64_t t) {
     __shared__ ForceShared fs;
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const CaseDev* __restric
     const int cs = ch.s, cstart = ch.start;
     force_role<T>(0, fs, fbase + cd.f_off[parity], links + cd.links_base, seg_cnt + cd.solid_base,
                   seg_off + cd.solid_base, &cs, &cstart, sol_all + cd.solid_base,
-                  partial + (size_t)blockIdx.x * 6, t, cd.fa);
+                  vtab_all + 2 * cd.solid_base, nullptr, partial + (size_t)blockIdx.x * 6, t, cd.fa);
 }
 
 // Per-tile sums of |u - u_snap|^2 and |u|^2 over fluid nodes; the snapshot is

@@ -48,10 +48,10 @@ size_t dtype_size(int dt) {
 struct Layout {
     int pitch, opitch;
     int64_t plane;
-    size_t f[2], own[2], links[2], seg_off, seg_cap, seg_cnt[2], rec_off, sol, vtab, movers, all,
-        chunk_solid, chunk_start, solid_chunk0, partial, hist, tctr, err, total;
+    size_t f[2], own[2], links[2], seg_off, seg_cap, seg_cnt[2], rec_off, sol, vtab, rtab, movers, frees, fdyn,
+        all, chunk_solid, chunk_start, solid_chunk0, partial, hist, tctr, err, total;
     int64_t link_total;
-    int n_movers;
+    int n_movers;  // bodies whose geometry moves (prescribed or free)
     int nchunks;
     int box_bytes;  // LDS byte map per translating body (mover role)
     size_t fbytes;  // bytes of one population buffer
@@ -124,8 +124,12 @@ bool make_layout(const lbm_grid& g, const lbm_solid* solids, int n, int64_t hist
     L.partial = off; off = align256(off + 2 * 48 * (size_t)nch);
     L.rec_off = off; off = align256(off + 4 * ns);
     L.sol = off; off = align256(off + sizeof(SolidDev) * ns);
-    L.vtab = off; off = align256(off + 16 * ns);
+    // per-solid velocity {vx, vy} and rotation {Omega, X, Y, free} tables, one per step parity
+    L.vtab = off; off = align256(off + 2 * 16 * ns);
+    L.rtab = off; off = align256(off + 2 * 8 * kRot * ns);
     L.movers = off; off = align256(off + 4 * (size_t)std::max(L.n_movers, 1));
+    L.frees = off; off = align256(off + 4 * (size_t)std::max(L.n_movers, 1));
+    L.fdyn = off; off = align256(off + sizeof(FreeDyn) * (size_t)std::max(L.n_movers, 1));
     L.all = off; off = align256(off + 4 * ns);
     L.hist = off; off = align256(off + 48 * ns * (size_t)hist_steps);
     L.tctr = off; off = align256(off + 16);
@@ -208,6 +212,10 @@ struct lbm_ctx {
     size_t ws_bytes;
     Layout L;
     int64_t t;
+    std::vector<int> movers_h, frees_h;  // prescribed and free translating bodies
+    std::vector<char> is_free;           // by solid id
+    double Gx = 0.0, Gy = 0.0;           // gravity on free bodies
+    int dyn_scheme = LBM_GME;            // force that drives them
     int mrt = 0;                        // collision operator: 0 BGK, 1 MRT
     double mrt_s[3] = {0.0, 0.0, 0.0};  // MRT rates s_e, s_eps, s_q
     int64_t hist_first = 0;  // first step whose force record is held
@@ -244,7 +252,7 @@ StepArgs step_args(const lbm_ctx* c) {
 
 template <typename C>
 CollideParams<C> collide_params(const lbm_ctx* c) {
-    CollideParams<C> p;
+    CollideParams<C> p{};
     p.rho0 = (C)c->g.rho0;
     p.omega = (C)(1.0 / c->tau);
     p.gx = (C)c->g.gx;
@@ -314,27 +322,36 @@ lbm_status enqueue_step(lbm_ctx* c) {
     sp.chunk_start = wsp<int>(c, c->L.chunk_start);
     sp.solid_chunk0 = wsp<int>(c, c->L.solid_chunk0);
     sp.sol = wsp<SolidDev>(c, c->L.sol);
-    sp.vtab = wsp<double>(c, c->L.vtab);
+    const int ns = c->n + 1;
+    sp.vtab = wsp<double>(c, c->L.vtab) + (size_t)p * 2 * ns;
+    sp.rtab = wsp<double>(c, c->L.rtab) + (size_t)p * kRot * ns;
     sp.movers = wsp<int>(c, c->L.movers);
     sp.partial = wsp<double>(c, c->L.partial);
     sp.hist = wsp<double>(c, c->L.hist);
     sp.tctr = wsp<int64_t>(c, c->L.tctr);
     sp.errflag = wsp<int>(c, c->L.err);
+    const int n_presc = (int)c->movers_h.size(), n_free = (int)c->frees_h.size();
     RoleCounts rc;
     rc.n_force = c->L.nchunks;
-    rc.n_move = 2 * c->L.n_movers;  // geometry and refill workgroup per body
+    rc.n_move = 2 * n_presc;  // geometry and refill workgroup per prescribed mover
     rc.n_lead = (rc.n_force + rc.n_move + 1 + 7) / 8 * 8;
     MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
-                9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes, c->L.n_movers};
+                9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes, n_presc};
     StepArgs sa = step_args(c);
     ForceArgs fa = force_args(c);
     CollideParams<C> cp = collide_params<C>(c);
     const dim3 grid((unsigned)(rc.n_lead + node_blocks(c)));
-    const size_t lds = c->L.n_movers > 0 ? 2 * (size_t)c->L.box_bytes : 0;
+    const size_t lds = n_presc > 0 ? 2 * (size_t)c->L.box_bytes : 0;
     // both population buffers larger than the Infinity Cache: stream them
     const bool nt = 2 * c->L.fbytes > kStreamBytes;
-    auto kern = c->mrt ? (nt ? k_fused<T, true, true> : k_fused<T, false, true>)
-                       : (nt ? k_fused<T, true, false> : k_fused<T, false, false>);
+    using KF = decltype(&k_fused<T, true, true, true>);
+    KF kern;
+    if (n_free > 0)
+        kern = c->mrt ? (nt ? k_fused<T, true, true, true> : k_fused<T, false, true, true>)
+                      : (nt ? k_fused<T, true, false, true> : k_fused<T, false, false, true>);
+    else
+        kern = c->mrt ? (nt ? k_fused<T, true, true, false> : k_fused<T, false, true, false>)
+                      : (nt ? k_fused<T, true, false, false> : k_fused<T, false, false, false>);
     const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
     if (timed) {
         hipExtLaunchKernelGGL(kern, grid, dim3(kBlock), lds, c->stream, c->ev[c->ev_used],
@@ -342,6 +359,27 @@ lbm_status enqueue_step(lbm_ctx* c) {
         c->ev_used += 2;
     } else {
         kern<<<grid, kBlock, lds, c->stream>>>(sp, p, rc, sa, ma, fa, cp);
+    }
+    if (n_free > 0) {
+        // free bodies: Newton-Euler step from this step's forces, then their
+        // G_{t+1}, links and refill (after the update: its partials are done)
+        StepPtrs<T> fp = sp;
+        fp.movers = wsp<int>(c, c->L.frees);
+        MoveArgs fm = ma;
+        fm.n_movers = n_free;
+        FreeArgs fr;
+        fr.dyn = wsp<FreeDyn>(c, c->L.fdyn);
+        fr.partial = sp.partial + (size_t)p * fa.nchunks * 6;
+        fr.solid_chunk0 = sp.solid_chunk0;
+        fr.rtab = sp.rtab;
+        fr.vtab_next = wsp<double>(c, c->L.vtab) + (size_t)(p ^ 1) * 2 * ns;
+        fr.rtab_next = wsp<double>(c, c->L.rtab) + (size_t)(p ^ 1) * kRot * ns;
+        fr.Gx = c->Gx;
+        fr.Gy = c->Gy;
+        fr.rho0 = c->g.rho0;
+        fr.scheme = c->dyn_scheme == LBM_CME ? 0 : 1;
+        auto kf = c->mrt ? k_free<T, true> : k_free<T, false>;
+        kf<<<2 * n_free, kBlock, 2 * (size_t)c->L.box_bytes, c->stream>>>(fp, p, fm, fr, cp);
     }
     c->t += 1;
     return LBM_OK;
@@ -389,7 +427,7 @@ const char* check_paths(const lbm_ctx* c, int64_t t0, int64_t t1, char* buf) {
     const auto& S = c->solids;
     const lbm_grid& g = c->g;
     for (int p = 0; p < c->n; ++p) {
-        if (!S[p].moves) continue;
+        if (!S[p].moves || c->is_free[p + 1]) continue;  // free bodies are checked on the device
         double hy = S[p].shape == LBM_DISC ? S[p].a : S[p].b;
         if (g.walls_y && S[p].vy != 0.0) {
             for (int64_t t : {t0, t1}) {
@@ -401,7 +439,7 @@ const char* check_paths(const lbm_ctx* c, int64_t t0, int64_t t1, char* buf) {
             }
         }
         for (int q = 0; q < c->n; ++q) {
-            if (q == p || (S[q].moves && q < p)) continue;
+            if (q == p || (S[q].moves && q < p) || c->is_free[q + 1]) continue;
             double rvx = S[p].vx - (S[q].moves ? S[q].vx : 0.0);
             double rvy = S[p].vy - (S[q].moves ? S[q].vy : 0.0);
             double rv = std::hypot(rvx, rvy);
@@ -435,6 +473,10 @@ lbm_status read_err(lbm_ctx* c) {
     if (e & 2) {
         set_err(c->err, "non-finite or non-positive density detected");
         return LBM_ENUMERIC;
+    }
+    if (e & 8) {
+        set_err(c->err, "a free body met a wall or another body, or moved more than half a node in a step");
+        return LBM_EGEOM;
     }
     return LBM_OK;
 }
@@ -567,6 +609,9 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = up(L.sol, sol.data(), sizeof(SolidDev) * ns);
     if (e == hipSuccess) e = up(L.vtab, vtab.data(), sizeof(double) * 2 * ns);
+    if (e == hipSuccess) e = up(L.vtab + sizeof(double) * 2 * ns, vtab.data(), sizeof(double) * 2 * ns);
+    std::vector<double> rtab((size_t)2 * kRot * ns, 0.0);
+    if (e == hipSuccess) e = up(L.rtab, rtab.data(), sizeof(double) * rtab.size());
     if (e == hipSuccess) e = up(L.seg_off, c->seg_off.data(), sizeof(int) * ns);
     if (e == hipSuccess) e = up(L.seg_cap, c->seg_cap.data(), sizeof(int) * ns);
     if (e == hipSuccess) e = up(L.seg_cnt[0], seg_cnt.data(), sizeof(int) * ns);
@@ -574,6 +619,8 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
     if (e == hipSuccess) e = up(L.chunk_start, chunk_start.data(), sizeof(int) * chunk_start.size());
     if (e == hipSuccess) e = up(L.solid_chunk0, solid_chunk0.data(), sizeof(int) * solid_chunk0.size());
     if (e == hipSuccess && !movers.empty()) e = up(L.movers, movers.data(), sizeof(int) * movers.size());
+    c->movers_h = movers;
+    c->is_free.assign(ns, 0);
     if (e == hipSuccess && !all.empty()) e = up(L.all, all.data(), sizeof(int) * all.size());
     // the uploads read pageable host vectors: finish them before they go away
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -781,6 +828,95 @@ lbm_status lbm_set_collision(lbm_ctx* c, int32_t model, const double* rates) {
     return LBM_OK;
 }
 
+lbm_status lbm_set_free_body(lbm_ctx* c, int32_t solid_id, double rho_s, double omega0) {
+    if (!c) return LBM_EINVAL;
+    if (c->t != 0) {
+        set_err(c->err, "free bodies are declared before the first step");
+        return LBM_ESTATE;
+    }
+    if (solid_id < 1 || solid_id > c->n || !(rho_s > 0.0) || !std::isfinite(omega0)) {
+        set_err(c->err, "solid_id must name a body and rho_s must be > 0");
+        return LBM_EINVAL;
+    }
+    const lbm_solid& b = c->solids[solid_id - 1];
+    if (b.shape != LBM_DISC || !b.moves) {
+        set_err(c->err, "a free body must be a disc created with moves = 1");
+        return LBM_EINVAL;
+    }
+    if (c->is_free[solid_id]) return LBM_OK;
+    // the body leaves the prescribed movers and joins the free ones
+    std::vector<int> presc;
+    for (int s : c->movers_h)
+        if (s != solid_id) presc.push_back(s);
+    std::vector<int> frees = c->frees_h;
+    frees.push_back(solid_id);
+    const double pi = 3.14159265358979323846;
+    FreeDyn d{};
+    for (int k = 0; k < 3; ++k) {
+        d.X[k] = b.cx;
+        d.Y[k] = b.cy;
+        d.Vx[k] = b.vx;
+        d.Vy[k] = b.vy;
+        d.Om[k] = omega0;
+    }
+    d.A = pi * b.a * b.a;
+    d.M = rho_s * d.A;
+    d.I = 0.5 * d.M * b.a * b.a;
+    d.s = solid_id;
+    const double rot[kRot] = {omega0, b.cx, b.cy, 1.0};
+    const int ns = c->n + 1;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (!presc.empty())
+        HIPCHK(c, hipMemcpy(c->ws + c->L.movers, presc.data(), sizeof(int) * presc.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.frees, frees.data(), sizeof(int) * frees.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.fdyn + sizeof(FreeDyn) * (frees.size() - 1), &d, sizeof(FreeDyn),
+                        hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k)
+        HIPCHK(c, hipMemcpy(c->ws + c->L.rtab + sizeof(double) * ((size_t)k * kRot * ns + (size_t)kRot * solid_id),
+                            rot, sizeof(rot), hipMemcpyHostToDevice));
+    c->movers_h = presc;
+    c->frees_h = frees;
+    c->is_free[solid_id] = 1;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_gravity(lbm_ctx* c, double gx, double gy, int32_t scheme) {
+    if (!c || !std::isfinite(gx) || !std::isfinite(gy) || (scheme != LBM_CME && scheme != LBM_GME))
+        return LBM_EINVAL;
+    c->Gx = gx;
+    c->Gy = gy;
+    c->dyn_scheme = scheme;
+    return LBM_OK;
+}
+
+lbm_status lbm_body_state(lbm_ctx* c, int32_t solid_id, double out[5]) {
+    if (!c || !out || solid_id < 1 || solid_id > c->n) return LBM_EINVAL;
+    lbm_status rs = read_err(c);
+    if (rs != LBM_OK) return rs;
+    const lbm_solid& b = c->solids[solid_id - 1];
+    if (c->is_free[solid_id]) {
+        size_t f = 0;
+        while (c->frees_h[f] != solid_id) ++f;
+        FreeDyn d;
+        HIPCHK(c, hipMemcpy(&d, c->ws + c->L.fdyn + sizeof(FreeDyn) * f, sizeof(FreeDyn), hipMemcpyDeviceToHost));
+        const int k = (int)(c->t % 3);
+        out[0] = d.X[k];
+        out[1] = d.Y[k];
+        out[2] = d.Vx[k];
+        out[3] = d.Vy[k];
+        out[4] = d.Om[k];
+        return LBM_OK;
+    }
+    const double tt = b.moves ? (double)c->t : 0.0;
+    out[0] = b.cx + tt * b.vx;
+    out[1] = b.cy + tt * b.vy;
+    out[2] = b.vx;
+    out[3] = b.vy;
+    out[4] = 0.0;
+    return LBM_OK;
+}
+
 lbm_status lbm_init_poiseuille(lbm_ctx* c) {
     if (!c) return LBM_EINVAL;
     if (!c->g.walls_y) {
@@ -842,11 +978,13 @@ lbm_status lbm_link_forces(lbm_ctx* c, double* d_out, int64_t max, int64_t* n) {
     const int* so = wsp<int>(c, c->L.seg_off);
     const int* ro = wsp<int>(c, c->L.rec_off);
     const SolidDev* sol = wsp<SolidDev>(c, c->L.sol);
+    const double* vt = wsp<double>(c, c->L.vtab) + (size_t)p * 2 * (c->n + 1);
+    const double* rt = wsp<double>(c, c->L.rtab) + (size_t)p * kRot * (c->n + 1);
     switch (c->g.dtype) {
-        case LBM_F64: k_link_records<double><<<ns, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
-        case LBM_F32: k_link_records<float><<<ns, kBlock, 0, c->stream>>>(wsp<float>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
-        case LBM_F16: k_link_records<_Float16><<<ns, kBlock, 0, c->stream>>>(wsp<_Float16>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
-        default: k_link_records<bf16_t><<<ns, kBlock, 0, c->stream>>>(wsp<bf16_t>(c, c->L.f[p]), links, sc, so, ro, sol, d_out, fa); break;
+        case LBM_F64: k_link_records<double><<<ns, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
+        case LBM_F32: k_link_records<float><<<ns, kBlock, 0, c->stream>>>(wsp<float>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
+        case LBM_F16: k_link_records<_Float16><<<ns, kBlock, 0, c->stream>>>(wsp<_Float16>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
+        default: k_link_records<bf16_t><<<ns, kBlock, 0, c->stream>>>(wsp<bf16_t>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -863,6 +1001,10 @@ lbm_status lbm_checkpoint_bytes(const lbm_ctx* c, size_t* bytes) {
 
 lbm_status lbm_save(lbm_ctx* c, void* d_dst, size_t bytes) {
     if (!c || !d_dst) return LBM_EINVAL;
+    if (!c->frees_h.empty()) {
+        set_err(c->err, "checkpoints do not hold the state of free bodies");
+        return LBM_ESTATE;
+    }
     size_t need;
     lbm_checkpoint_bytes(c, &need);
     if (bytes < need) {
@@ -890,6 +1032,10 @@ lbm_status lbm_save(lbm_ctx* c, void* d_dst, size_t bytes) {
 }
 
 lbm_status lbm_load(lbm_ctx* c, const void* d_src, size_t bytes) {
+    if (c && !c->frees_h.empty()) {
+        set_err(c->err, "checkpoints do not hold the state of free bodies");
+        return LBM_ESTATE;
+    }
     if (!c || !d_src) return LBM_EINVAL;
     size_t need;
     lbm_checkpoint_bytes(c, &need);

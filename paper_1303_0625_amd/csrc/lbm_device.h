@@ -255,6 +255,23 @@ struct SolidDev {
     int32_t moves;   // geometry translates
 };
 
+// Free discs (particles moving under gravity and the hydrodynamic force):
+// state at step t in slot t % 3 (the mover reads t - 1 and t while the next
+// step's values go to t + 1).
+struct FreeDyn {
+    double X[3], Y[3], Vx[3], Vy[3], Om[3];  // centre, velocity, angular velocity
+    double M, I, A;                          // mass, moment of inertia, area
+    int s;                                   // solid id
+    int pad;
+};
+
+// Per-solid rotation table, one per step parity: {Omega, X, Y, free} with the
+// centre of a free body at that step (Omega = 0 for every other solid).
+constexpr int kRot = 4;
+
+// Minimum-image difference on a periodic axis of length n.
+__device__ inline double min_image(double d, int n) { return d - (double)n * rint(d / (double)n); }
+
 // Centre of a solid at step t: X = x0 + t*vx with separately rounded product
 // and sum (contraction into a fused multiply-add is switched off here and in
 // solid_inside), so that the solid/fluid decision of every node is the one a

@@ -109,16 +109,17 @@ __device__ inline T* row_at(T* base, uint32_t idx) {
 // only when a source node is solid (or a wall row) are they replaced by the
 // per-direction bounce-back values.  bid/nblk: this workgroup's index among
 // the update workgroups (remapped so that each XCD walks a contiguous band).
-template <typename T, bool NT, bool MRT = false>
+template <typename T, bool NT, bool MRT = false, bool ROT = false>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
-                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp);
+                                 const double* __restrict__ rtab, const StepArgs& a,
+                                 const CollideParams<typename Sto<T>::C>& cp);
 
-template <typename T, bool NT, bool MRT>
+template <typename T, bool NT, bool MRT, bool ROT>
 __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restrict__ fin,
                                  T* __restrict__ fout, const uint8_t* __restrict__ own_t,
-                                 const double* __restrict__ vtab, const StepArgs& a,
-                                 const CollideParams<typename Sto<T>::C>& cp) {
+                                 const double* __restrict__ vtab, const double* __restrict__ rtab,
+                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp) {
     // row and column base are wave-uniform scalars
     const uint32_t b = xcd_remap(bid, nblk);
     const uint32_t wpr = (uint32_t)a.rowlen >> 6;
@@ -126,15 +127,17 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
     const int y = (int)(gw / wpr);
     const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
     if (y >= a.ny || x >= a.nx) return;
-    step_node<T, NT, MRT>(x, y, fin, fout, own_t, vtab, a, cp);
+    step_node<T, NT, MRT, ROT>(x, y, fin, fout, own_t, vtab, rtab, a, cp);
 }
 
 // The update of node (x, y): pull, bounce-back, collide (BGK, or MRT when
-// MRT), store.
-template <typename T, bool NT, bool MRT>
+// MRT), store.  ROT: some solid rotates (free bodies); its wall velocity at
+// the link midpoint x - e_i/2 is V + Omega z x (x - e_i/2 - X).
+template <typename T, bool NT, bool MRT, bool ROT>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
-                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp) {
+                                 const double* __restrict__ rtab, const StepArgs& a,
+                                 const CollideParams<typename Sto<T>::C>& cp) {
     using C = typename Sto<T>::C;
 
     const int xm = x == 0 ? a.nx - 1 : x - 1;
@@ -191,7 +194,17 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
             const bool wall = (ey_(i) == 1 && wall_lo) || (ey_(i) == -1 && wall_hi);
             const uint32_t sid = wall ? 0u : src[i];
             if (wall || sid != 0u) {
-                const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                if constexpr (ROT) {
+                    const double om = rtab[kRot * sid];
+                    if (om != 0.0) {
+                        const double rx = min_image((double)x - 0.5 * ex_(i) - rtab[kRot * sid + 1], a.nx);
+                        double ry = (double)y - 0.5 * ey_(i) - rtab[kRot * sid + 2];
+                        if (!a.walls) ry = min_image(ry, a.ny);
+                        vx = (C)((double)vtab[2 * sid] - om * ry);
+                        vy = (C)((double)vtab[2 * sid + 1] + om * rx);
+                    }
+                }
                 d[i] = Sto<T>::ld(*row_at(r0 + opp_(i) * P, ux)) +
                        C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
             }
@@ -507,10 +520,10 @@ struct MoveArgs {
     int n_movers;   // translating bodies (mover workgroups: 2 n_movers)
 };
 
-__device__ inline void swept_box(const SolidDev& S, int64_t t, long& x0, long& x1, long& y0, long& y1) {
-    double Xa, Ya, Xb, Yb;
-    solid_pos(S, t - 1, Xa, Ya);
-    solid_pos(S, t + 1, Xb, Yb);
+// Bounding range of the body centred at (Xa, Ya) (step t - 1) and at
+// (Xb, Yb) (step t + 1), widened by kBoxMargin.
+__device__ inline void swept_box(const SolidDev& S, double Xa, double Ya, double Xb, double Yb, long& x0, long& x1,
+                                 long& y0, long& y1) {
     long ax0, ax1, ay0, ay1, bx0, bx1, by0, by1;
     solid_range(S, Xa, Ya, kBoxMargin, ax0, ax1, ay0, ay1);
     solid_range(S, Xb, Yb, kBoxMargin, bx0, bx1, by0, by1);
@@ -519,6 +532,19 @@ __device__ inline void swept_box(const SolidDev& S, int64_t t, long& x0, long& x
     y0 = ay0 < by0 ? ay0 : by0;
     y1 = ay1 > by1 ? ay1 : by1;
 }
+
+// Free-body mover arguments (one launch after the step: the step's force
+// partials are complete).
+struct FreeArgs {
+    FreeDyn* dyn;               // [n_free], in the order of the mover list
+    const double* partial;      // step t's force partials [nchunks][6]
+    const int* solid_chunk0;    // chunk range of each solid
+    const double* rtab;         // rotation table of step t
+    double* vtab_next;          // velocity table of step t + 1
+    double* rtab_next;          // rotation table of step t + 1
+    double Gx, Gy, rho0;        // gravity on free bodies, reference density
+    int scheme;                 // force that drives them: 0 CME, 1 GME
+};
 
 template <typename T>
 struct MoveShared {
@@ -544,7 +570,8 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                                  const SolidDev* __restrict__ sol, const double* __restrict__ vtab,
                                  const int* __restrict__ movers, const int64_t* __restrict__ tctr,
                                  int parity, const MoveArgs& a,
-                                 const CollideParams<typename Sto<T>::C>& cp, int* __restrict__ errflag) {
+                                 const CollideParams<typename Sto<T>::C>& cp, int* __restrict__ errflag,
+                                 const FreeArgs* fr = nullptr) {
     using C = typename Sto<T>::C;
     uint8_t* ot = lds;
     uint8_t* on = lds + a.box_bytes;
@@ -558,8 +585,53 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
     const int soff = seg_off[s];
     __syncthreads();
     const SolidDev& S = sm.body;
+    // centres at t - 1 and t + 1; a free body first takes its Newton-Euler
+    // step from the force and torque of step t (summed in chunk order, as
+    // the force history is): V' = V + (F + (M - rho0 A) G)/M,
+    // Omega' = Omega + T/I, X' = X + V'
+    double Xa, Ya, Xn, Yn;
+    double Xt = 0.0, Yt = 0.0, Vnx = 0.0, Vny = 0.0, Omn = 0.0;
+    if (fr) {
+        FreeDyn& D = fr->dyn[m - part * a.n_movers];
+        const int k0 = (int)(t % 3), km = (int)((t + 2) % 3), kp = (int)((t + 1) % 3);
+        double F[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double v = 0.0;
+            for (int cc = fr->solid_chunk0[s]; cc < fr->solid_chunk0[s + 1]; ++cc)
+                v += fr->partial[cc * 6 + 3 * fr->scheme + q];
+            F[q] = v;
+        }
+        const double ext = D.M - fr->rho0 * D.A;
+        Vnx = D.Vx[k0] + (F[0] + ext * fr->Gx) / D.M;
+        Vny = D.Vy[k0] + (F[1] + ext * fr->Gy) / D.M;
+        Omn = D.Om[k0] + F[2] / D.I;
+        Xa = D.X[km];
+        Ya = D.Y[km];
+        Xt = D.X[k0];
+        Yt = D.Y[k0];
+        Xn = Xt + Vnx;
+        Yn = Yt + Vny;
+        if (part == 0 && threadIdx.x == 0) {
+            D.X[kp] = Xn;
+            D.Y[kp] = Yn;
+            D.Vx[kp] = Vnx;
+            D.Vy[kp] = Vny;
+            D.Om[kp] = Omn;
+            fr->vtab_next[2 * s] = Vnx;
+            fr->vtab_next[2 * s + 1] = Vny;
+            fr->rtab_next[kRot * s] = Omn;
+            fr->rtab_next[kRot * s + 1] = Xn;
+            fr->rtab_next[kRot * s + 2] = Yn;
+            fr->rtab_next[kRot * s + 3] = 1.0;
+            if (fabs(Vnx) + fabs(Vny) > 0.5) atomicOr(errflag, 8);  // outruns its swept box
+        }
+    } else {
+        solid_pos(S, t - 1, Xa, Ya);
+        solid_pos(S, t + 1, Xn, Yn);
+    }
     long x0, x1, y0, y1;
-    swept_box(S, t, x0, x1, y0, y1);
+    swept_box(S, Xa, Ya, Xn, Yn, x0, x1, y0, y1);
     const int W = (int)(x1 - x0 + 1), H = (int)(y1 - y0 + 1), N = W * H;
     if (N > a.box_bytes) {  // the host sizes the box for the largest mover
         if (threadIdx.x == 0) atomicOr(errflag, 4);
@@ -602,13 +674,14 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
     // 2. G_{t+1}: rasterise the body at t+1, clear what it left; collect the
     // newborn nodes (solid at t, fluid at t+1); their order in the list does
     // not affect any value
-    double Xn, Yn;
-    solid_pos(S, t + 1, Xn, Yn);
     for (int q = threadIdx.x; q < N; q += kBlock) {
-        if (on[q] == kWallMark) continue;
         const long yy = y0 + q / W, xx = x0 + q % W;
         const uint8_t v = on[q];
-        const uint8_t nv = solid_inside(S, Xn, Yn, xx, yy) ? (uint8_t)s : (v == s ? (uint8_t)0 : v);
+        const bool in = solid_inside(S, Xn, Yn, xx, yy);
+        // a free body has no validated path: flag it meeting a wall or body
+        if (fr && in && (v == kWallMark || (v != 0 && v != s))) atomicOr(errflag, 8);
+        if (v == kWallMark) continue;
+        const uint8_t nv = in ? (uint8_t)s : (v == s ? (uint8_t)0 : v);
         if (nv != v) {
             on[q] = nv;
             if (part == 0) {
@@ -702,7 +775,15 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
             C v;
             if (j != 0 && o != 0) {
                 const int sid = o == kWallMark ? 0 : o;
-                const C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                if (fr && sid == s) {  // spinning free body: velocity at the link midpoint, step t
+                    const double om = fr->rtab[kRot * s];
+                    const double rx = min_image((double)gx - 0.5 * ex_(j) - Xt, a.nx);
+                    double ry = (double)gy - 0.5 * ey_(j) - Yt;
+                    if (!a.walls) ry = min_image(ry, a.ny);
+                    vx = (C)(vtab[2 * s] - om * ry);
+                    vy = (C)(vtab[2 * s + 1] + om * rx);
+                }
                 v = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]) +
                     C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
             } else {
@@ -730,8 +811,19 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                 else
                     acc += v1;
             }
-            // no participant: equilibrium at the body velocity
-            sm.nb_new[bb][j] = np > 0 ? acc / C(np) : feq_one<C>(j, rho0, rho0, (C)S.vx, (C)S.vy);
+            // no participant: equilibrium at the body's velocity (a free body:
+            // its surface velocity at the node at t + 1)
+            C bvx = (C)S.vx, bvy = (C)S.vy;
+            if (fr) {
+                int nx_, ny_;
+                gidx(sm.nb_list[base + bb], nx_, ny_);
+                const double rx = min_image((double)nx_ - Xn, a.nx);
+                double ry = (double)ny_ - Yn;
+                if (!a.walls) ry = min_image(ry, a.ny);
+                bvx = (C)(Vnx - Omn * ry);
+                bvy = (C)(Vny + Omn * rx);
+            }
+            sm.nb_new[bb][j] = np > 0 ? acc / C(np) : feq_one<C>(j, rho0, rho0, bvx, bvy);
         }
         __syncthreads();
         // 4d. collide: moments per newborn node, then one direction per thread
@@ -817,7 +909,8 @@ __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ 
                                   const int* __restrict__ seg_cnt, const int* __restrict__ seg_off,
                                   const int* __restrict__ chunk_solid,
                                   const int* __restrict__ chunk_start,
-                                  const SolidDev* __restrict__ sol, double* __restrict__ partial,
+                                  const SolidDev* __restrict__ sol, const double* __restrict__ vt,
+                                  const double* __restrict__ rt, double* __restrict__ partial,
                                   int64_t t, const ForceArgs& a) {
     const int s = chunk_solid[c];
     const int start = chunk_start[c];
@@ -825,9 +918,17 @@ __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ 
     const int end = start + kForceChunk < n ? start + kForceChunk : n;
     const uint32_t* L = links + seg_off[s];
     const SolidDev S = sol[s];
+    // a free body's velocity, spin and centre come from the step's tables
+    const double om = rt ? rt[kRot * s] : 0.0;
+    const bool fr = rt && rt[kRot * s + 3] != 0.0;
     double X = 0.0, Y = 0.0;
-    if (s > 0) solid_pos(S, t, X, Y);
-    const double vx = S.vx, vy = S.vy;
+    if (fr) {
+        X = rt[kRot * s + 1];
+        Y = rt[kRot * s + 2];
+    } else if (s > 0) {
+        solid_pos(S, t, X, Y);
+    }
+    const double vbx = vt[2 * s], vby = vt[2 * s + 1];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int k = start + threadIdx.x; k < end; k += kBlock) {
         const uint32_t code = L[k];
@@ -846,6 +947,14 @@ __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ 
             case 7: ex = -1; ey = -1; w = 1.0 / 36.0; break;
             default: ex = 1; ey = -1; w = 1.0 / 36.0; break;
         }
+        // arm from the centre to the link midpoint x_f + e_i/2 (minimum image)
+        double rx = 0.0, ry = 0.0;
+        if (s > 0) {
+            rx = min_image(((double)x + 0.5 * ex) - X, a.nx);
+            ry = ((double)y + 0.5 * ey) - Y;
+            if (!a.walls) ry = min_image(ry, a.ny);
+        }
+        const double vx = vbx - om * ry, vy = vby + om * rx;
         const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
         const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
         // CME: e_i a - e_ibar b, e_ibar = -e_i
@@ -859,10 +968,6 @@ __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ 
         acc[3] += gfx;
         acc[4] += gfy;
         if (s > 0) {
-            double rx = ((double)x + 0.5 * ex) - X;
-            rx -= (double)a.nx * rint(rx / (double)a.nx);
-            double ry = ((double)y + 0.5 * ey) - Y;
-            if (!a.walls) ry -= (double)a.ny * rint(ry / (double)a.ny);
             acc[2] += rx * cfy - ry * cfx;
             acc[5] += rx * gfy - ry * gfx;
         }
@@ -930,6 +1035,7 @@ struct StepPtrs {
     const int* solid_chunk0;
     const SolidDev* sol;
     const double* vtab;
+    const double* rtab;  // rotation table of this step
     const int* movers;
     double* partial;  // [2][nchunks][6], by step parity
     double* hist;
@@ -941,7 +1047,7 @@ struct RoleCounts {
     int n_force, n_move, n_lead;
 };
 
-template <typename T, bool NT, bool MRT>
+template <typename T, bool NT, bool MRT, bool ROT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fused(
     StepPtrs<T> p, int parity, RoleCounts rc, StepArgs sa, MoveArgs ma, ForceArgs fa,
     CollideParams<typename Sto<T>::C> cp) {
@@ -955,7 +1061,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const int64_t t = p.tctr[parity];
         if (b < rc.n_force) {
             force_role<T>(b, sh.f, p.fin, p.links_t, p.seg_cnt_t, p.seg_off, p.chunk_solid, p.chunk_start,
-                          p.sol, p.partial + (size_t)(t & 1) * fa.nchunks * 6, t, fa);
+                          p.sol, p.vtab, p.rtab, p.partial + (size_t)(t & 1) * fa.nchunks * 6, t, fa);
         } else if (b < rc.n_force + rc.n_move) {
             move_role<T, MRT>(b - rc.n_force, dyn_lds, sh.m, p.fin, p.fout, p.own_t, p.own_n, p.links_n,
                          p.seg_cnt_n, p.seg_off, p.seg_cap, p.sol, p.vtab, p.movers, p.tctr, parity, ma,
@@ -970,8 +1076,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         }
         return;
     }
-    step_role<T, NT, MRT>((uint32_t)(b - rc.n_lead), gridDim.x - (uint32_t)rc.n_lead, p.fin, p.fout, p.own_t,
-                     p.vtab, sa, cp);
+    step_role<T, NT, MRT, ROT>((uint32_t)(b - rc.n_lead), gridDim.x - (uint32_t)rc.n_lead, p.fin, p.fout,
+                               p.own_t, p.vtab, p.rtab, sa, cp);
+}
+
+// Free bodies after the step: two workgroups per body (part 0: Newton-Euler
+// step, G_{t+1} and links; part 1: the same step and rasterisation, then the
+// newborn refill).  p.movers lists the free bodies.
+template <typename T, bool MRT>
+__global__ __launch_bounds__(kBlock) void k_free(StepPtrs<T> p, int parity, MoveArgs ma, FreeArgs fa,
+                                                 CollideParams<typename Sto<T>::C> cp) {
+    extern __shared__ __align__(16) uint8_t dyn_lds[];
+    __shared__ MoveShared<T> sm;
+    move_role<T, MRT>((int)blockIdx.x, dyn_lds, sm, p.fin, p.fout, p.own_t, p.own_n, p.links_n, p.seg_cnt_n,
+                      p.seg_off, p.seg_cap, p.sol, p.vtab, p.movers, p.tctr, parity, ma, cp, p.errflag, &fa);
 }
 
 // Per-link force records of the current state (test and inspection path).
@@ -982,11 +1100,13 @@ __global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f
                                                          const int* __restrict__ seg_off,
                                                          const int* __restrict__ rec_off,
                                                          const SolidDev* __restrict__ sol,
+                                                         const double* __restrict__ vt,
+                                                         const double* __restrict__ rt,
                                                          double* __restrict__ out, ForceArgs a) {
     const int s = blockIdx.x;
     const int n = seg_cnt[s];
     const uint32_t* L = links + seg_off[s];
-    const double vx = sol[s].vx, vy = sol[s].vy;
+    const double om = rt[kRot * s], cx = rt[kRot * s + 1], cy = rt[kRot * s + 2];
     for (int k = threadIdx.x; k < n; k += kBlock) {
         const uint32_t code = L[k];
         const int i = (int)(code & 15u);
@@ -994,6 +1114,14 @@ __global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f
         const int y = (int)(node / (uint32_t)a.nx);
         const int x = (int)(node - (uint32_t)y * (uint32_t)a.nx);
         const double ex = ex_(i), ey = ey_(i), w = w_<double>(i);
+        double vx = vt[2 * s], vy = vt[2 * s + 1];
+        if (om != 0.0) {  // surface velocity of a spinning free body at the link midpoint
+            const double rx = min_image(((double)x + 0.5 * ex) - cx, a.nx);
+            double ry = ((double)y + 0.5 * ey) - cy;
+            if (!a.walls) ry = min_image(ry, a.ny);
+            vx -= om * ry;
+            vy += om * rx;
+        }
         const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
         const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
         double* r = out + 8 * (int64_t)(rec_off[s] + k);

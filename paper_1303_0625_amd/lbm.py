@@ -99,6 +99,9 @@ _SIG = {
     "lbm_batch_set_active": (_I32, [_VP, _I32, _I32]),
     "lbm_init_poiseuille": (_I32, [_VP]),
     "lbm_set_collision": (_I32, [_VP, _I32, _VP]),
+    "lbm_set_free_body": (_I32, [_VP, _I32, ctypes.c_double, ctypes.c_double]),
+    "lbm_set_gravity": (_I32, [_VP, ctypes.c_double, ctypes.c_double, _I32]),
+    "lbm_body_state": (_I32, [_VP, _I32, _VP]),
     "lbm_batch_init_fields": (_I32, [_VP, _I32, _VP, _VP, _VP, _I32]),
     "lbm_batch_time": (_I64, [_VP]),
     "lbm_batch_destroy": (None, [_VP]),
@@ -348,6 +351,20 @@ def lbm_set_collision(ctx, model: int, rates=None) -> None:
     _check(load_library().lbm_set_collision(ctx, int(model), arr), ctx)
 
 
+def lbm_set_free_body(ctx, solid_id: int, rho_s: float, omega0: float = 0.0) -> None:
+    _check(load_library().lbm_set_free_body(ctx, int(solid_id), float(rho_s), float(omega0)), ctx)
+
+
+def lbm_set_gravity(ctx, gx: float, gy: float, scheme: int) -> None:
+    _check(load_library().lbm_set_gravity(ctx, float(gx), float(gy), int(scheme)), ctx)
+
+
+def lbm_body_state(ctx, solid_id: int):
+    out = (ctypes.c_double * 5)()
+    _check(load_library().lbm_body_state(ctx, int(solid_id), out), ctx)
+    return list(out)
+
+
 def lbm_init_poiseuille(ctx) -> None:
     _check(load_library().lbm_init_poiseuille(ctx), ctx)
 
@@ -592,6 +609,17 @@ class Lattice:
 
     def init_poiseuille(self) -> None:
         lbm_init_poiseuille(self.ctx)
+
+    def set_free(self, solid_id: int, rho_s: float, omega0: float = 0.0) -> None:
+        """Body solid_id (a disc created with moves=True) becomes a free particle."""
+        lbm_set_free_body(self.ctx, solid_id, rho_s, omega0)
+
+    def set_gravity(self, G, scheme: int = 1) -> None:
+        lbm_set_gravity(self.ctx, G[0], G[1], scheme)
+
+    def body_state(self, solid_id: int):
+        """[X, Y, V_x, V_y, Omega] of a body at the current step."""
+        return lbm_body_state(self.ctx, solid_id)
 
     def populations(self):
         out = self.torch.empty((9, self.ny, self.nx), dtype=self.torch.float64,
