@@ -107,6 +107,47 @@ def run_batch(lc, pkg, torch, steps):
             "timing": "wall clock around graph replays, monitor included"}
 
 
+def run_sedimentation(lc, pkg, torch, steps):
+    """Sec. IV.A in lattice units: a channel 120 wide (walls at y) and 1200
+    long (periodic in x), a free disc of diameter 30 (0.1 cm in a 0.4 cm
+    channel) and density 1.03, released 22.8 nodes (0.076 cm) from a wall,
+    tau = 0.6 (nu = 0.01 cm^2/s), gravity 980 cm/s^2 along the channel
+    = 4.03e-4 in lattice units.  Timed with GME driving the disc; then the
+    paper's frame test: fluid, disc and walls given an extra V = 0.01 along
+    the channel, and the trajectory relative to the channel (x - V t, y,
+    Omega) compared with the V = 0 run, for GME and for CME."""
+    nx, ny, r, rho_s, G = 1200, 120, 15.0, 1.03, 4.03e-4
+
+    def case(V):
+        body = lc.disc(100.0, 22.3, r, vx=V, moves=True)
+        return lc.make_case(nx, ny, 0.6, walls_y=True, u0=(V, 0.0), wall_v=(V, 0.0), bodies=[body],
+                            name=f"sediment_V{V}")
+
+    def run(V, scheme, timed=False):
+        lat = pkg.Lattice(case(V), dtype="f64", history_steps=steps + 1)
+        lat.set_free(1, rho_s)
+        lat.set_gravity((G, 0.0), scheme)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(steps)
+        lat.check()
+        dt = time.perf_counter() - t0
+        st = lat.body_state(1)
+        return st, dt
+
+    out = {"nx": nx, "ny": ny, "d": 2 * r, "rho_s": rho_s, "G": G, "tau": 0.6, "steps": steps, "dtype": "f64"}
+    for name, scheme in (("gme", 1), ("cme", 0)):
+        s0, dt0 = run(0.0, scheme)
+        s1, _ = run(0.01, scheme)
+        rel = [s1[0] - 0.01 * steps - s0[0], s1[1] - s0[1], s1[4] - s0[4]]
+        out[name] = {"state_V0": [round(v, 9) for v in s0],
+                     "frame_V0.01_minus_V0": {"x": rel[0], "y": rel[1], "omega": rel[2]}}
+        if scheme == 1:
+            out["ms_per_step"] = round(dt0 / steps * 1e3, 4)
+            out["mlups"] = round(nx * ny * steps / dt0 / 1e6, 1)
+    return out
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -154,6 +195,8 @@ def main() -> int:
     ap.add_argument("--no-hbm-case", action="store_true")
     ap.add_argument("--no-batch-case", action="store_true")
     ap.add_argument("--no-mrt-case", action="store_true")
+    ap.add_argument("--no-free-case", action="store_true")
+    ap.add_argument("--free-steps", type=int, default=4000)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--warm-cases", type=int, default=16)
@@ -223,6 +266,9 @@ def main() -> int:
             "achieved_GBs": round(ab3 / avg3 / 1e9, 1),
             "frac": round(ab3 / avg3 / 1e9 / HBM_PEAK_GBS, 4)}
         del lat3
+        torch.cuda.empty_cache()
+    if not args.no_free_case:
+        extra["free_sedimentation_1200x120"] = run_sedimentation(lc, pkg, torch, args.free_steps)
         torch.cuda.empty_cache()
     if not args.no_hbm_case:
         big = lc.periodic_cylinders()
