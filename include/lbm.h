@@ -395,7 +395,7 @@ typedef struct {
     int32_t h, w;      /* lattice rows (ny, multiple of 8) and columns (nx, multiple of 64) */
     int32_t max_batch; /* samples per call, >= 1 */
     int32_t dtype;     /* LBM_BF16 or LBM_F32 activations */
-    int32_t ch[4];     /* channels per level, multiples of 32 */
+    int32_t ch[4];     /* channels per level, multiples of 32 in [32, 1024]; ch[3] <= 256 */
     double rho_scale;  /* scale of the density output */
 } lbm_nn_config;
 

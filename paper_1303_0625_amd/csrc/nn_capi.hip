@@ -101,6 +101,12 @@ void wgrad9_split(int64_t ntiles, int pairs, int mb, int nb, int64_t nwb, int& s
     }
 }
 
+// Nodes per workgroup of a column sum: 8 per thread lane (kEw / C lanes per
+// channel), so a sum over few nodes with many channels still spreads over
+// many workgroups.
+constexpr int kColPerLane = 8;
+int col_rows(int C) { return kColPerLane * (kEw / C); }
+
 const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
     if (cfg.h < 8 || cfg.h % 8 != 0) return "h must be a positive multiple of 8";
     if (cfg.w < 64 || cfg.w % 64 != 0) return "w must be a positive multiple of 64";
@@ -108,6 +114,7 @@ const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
     if (cfg.dtype != LBM_BF16 && cfg.dtype != LBM_F32) return "dtype must be LBM_BF16 or LBM_F32";
     for (int k = 0; k < 4; ++k)
         if (cfg.ch[k] < 32 || cfg.ch[k] % 32 != 0 || cfg.ch[k] > 1024) return "channels must be multiples of 32 in [32, 1024]";
+    if (cfg.ch[3] > kEw) return "the bottleneck width ch[3] must be <= 256 (its channel means)";
     if (!(cfg.rho_scale > 0.0)) return "rho_scale must be > 0";
     if ((int64_t)cfg.max_batch * cfg.h * cfg.w >= (1LL << 31) / 32) return "max_batch * h * w too large";
     p.H = cfg.h;
@@ -160,7 +167,9 @@ const char* make_plan(const lbm_nn_config& cfg, Plan& p) {
         }
     }
     // channel means of the bottleneck and their adjoint (per sample, c3 wide)
-    p.bpart_max = std::max<int64_t>(p.bpart_max, (int64_t)p.B * ((pixels(p, 2) / p.B + 255) / 256) * c3);
+    // column sums over c3 channels of at most the level-2 nodes of a sample
+    p.bpart_max = std::max<int64_t>(
+        p.bpart_max, (int64_t)p.B * ((pixels(p, 2) / p.B + col_rows(c3) - 1) / col_rows(c3)) * c3);
     p.n_params = off;
     p.wf_total = wf;
     p.wt_total = wt;
@@ -307,15 +316,14 @@ void conv(lbm_nn* n, int level, const void* in, int in_cs, int cin, const void* 
     }
 }
 
-constexpr int kColRows = 256;  // nodes per workgroup of a column sum
-
 // out[b][c] = scale * sum over the N nodes of segment b of a[.][co + c]
 // (c < C <= kEw), in a fixed order; float (fout) and/or T (tout) results.
 template <typename T>
 void colsum(lbm_nn* n, const void* a, int cs, int co, int C, int64_t N, int B, float scale, float* fout, T* tout) {
-    const int nblk = (int)((N + kColRows - 1) / kColRows);
+    const int R = col_rows(C);
+    const int nblk = (int)((N + R - 1) / R);
     float* part = at<float>(n, n->p.o_bpart);
-    k_colsum_partial<T><<<dim3(nblk, B), kEw, 0, n->st>>>((const T*)a, cs, co, C, N, kColRows, part);
+    k_colsum_partial<T><<<dim3(nblk, B), kEw, 0, n->st>>>((const T*)a, cs, co, C, N, R, part);
     k_colsum_final<T><<<blocks((int64_t)B * C), kEw, 0, n->st>>>(part, nblk, C, B, scale, fout, tout);
 }
 
