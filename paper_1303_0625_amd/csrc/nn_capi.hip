@@ -324,7 +324,7 @@ void colsum(lbm_nn* n, const void* a, int cs, int co, int C, int64_t N, int B, f
     const int nblk = (int)((N + R - 1) / R);
     float* part = at<float>(n, n->p.o_bpart);
     k_colsum_partial<T><<<dim3(nblk, B), kEw, 0, n->st>>>((const T*)a, cs, co, C, N, R, part);
-    k_colsum_final<T><<<blocks((int64_t)B * C), kEw, 0, n->st>>>(part, nblk, C, B, scale, fout, tout);
+    k_colsum_final<T><<<blocks((int64_t)B * C, kSumCols), kEw, 0, n->st>>>(part, nblk, C, B, scale, fout, tout);
 }
 
 template <typename T>
@@ -431,34 +431,34 @@ void forward_t(lbm_nn* n) {
     // encoder
     layer_fwd<T>(n, 0, 0, X0, A0, c0, 0);
     layer_fwd<T>(n, 1, 0, A0, CAT0, c1 + c0, c1);
-    k_pool<T><<<blocks((int64_t)B * H(1) * W(1) * c0), kEw, 0, n->st>>>(
+    k_pool<T><<<blocks(((int64_t)B * H(1) * W(1) * c0) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, CAT0), c1 + c0, c1, c0, (T*)buf(n, X1), H(1), W(1), B);
     layer_fwd<T>(n, 2, 1, X1, A1, c1, 0);
     layer_fwd<T>(n, 3, 1, A1, CAT1, c2 + c1, c2);
-    k_pool<T><<<blocks((int64_t)B * H(2) * W(2) * c1), kEw, 0, n->st>>>(
+    k_pool<T><<<blocks(((int64_t)B * H(2) * W(2) * c1) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, CAT1), c2 + c1, c2, c1, (T*)buf(n, X2), H(2), W(2), B);
     const int cat2 = 2 * c3 + c2;  // [up(b2), skip_2, mean(b2)]
     layer_fwd<T>(n, 4, 2, X2, A2, c2, 0);
     layer_fwd<T>(n, 5, 2, A2, CAT2, cat2, c3);
-    k_pool<T><<<blocks((int64_t)B * H(3) * W(3) * c2), kEw, 0, n->st>>>(
+    k_pool<T><<<blocks(((int64_t)B * H(3) * W(3) * c2) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, CAT2), cat2, c3, c2, (T*)buf(n, X3), H(3), W(3), B);
     // bottleneck and its global context
     layer_fwd<T>(n, 6, 3, X3, B1, c3, 0);
     layer_fwd<T>(n, 7, 3, B1, B2, c3, 0);
     colsum<T>(n, buf(n, B2), c3, 0, c3, (int64_t)H(3) * W(3), B, 1.0f / (float)(H(3) * W(3)), nullptr,
               (T*)buf(n, GMEAN));
-    k_broadcast<T><<<blocks((int64_t)B * H(2) * W(2) * c3), kEw, 0, n->st>>>(
+    k_broadcast<T><<<blocks(((int64_t)B * H(2) * W(2) * c3) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, GMEAN), c3, (T*)buf(n, CAT2), cat2, c3 + c2, H(2) * W(2), B);
     // decoder
-    k_upsample<T><<<blocks((int64_t)B * H(2) * W(2) * c3), kEw, 0, n->st>>>(
+    k_upsample<T><<<blocks(((int64_t)B * H(2) * W(2) * c3) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, B2), c3, (T*)buf(n, CAT2), cat2, 0, H(2), W(2), B);
     layer_fwd<T>(n, 8, 2, CAT2, D2A, c2, 0);
     layer_fwd<T>(n, 9, 2, D2A, D2B, c2, 0);
-    k_upsample<T><<<blocks((int64_t)B * H(1) * W(1) * c2), kEw, 0, n->st>>>(
+    k_upsample<T><<<blocks(((int64_t)B * H(1) * W(1) * c2) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, D2B), c2, (T*)buf(n, CAT1), c2 + c1, 0, H(1), W(1), B);
     layer_fwd<T>(n, 10, 1, CAT1, D1A, c1, 0);
     layer_fwd<T>(n, 11, 1, D1A, D1B, c1, 0);
-    k_upsample<T><<<blocks((int64_t)B * H(0) * W(0) * c1), kEw, 0, n->st>>>(
+    k_upsample<T><<<blocks(((int64_t)B * H(0) * W(0) * c1) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, D1B), c1, (T*)buf(n, CAT0), c1 + c0, 0, H(0), W(0), B);
     layer_fwd<T>(n, 12, 0, CAT0, D0A, c0, 0);
     layer_fwd<T>(n, 13, 0, D0A, D0B, c0, 0);
@@ -483,14 +483,14 @@ void backward_t(lbm_nn* n) {
     layer_dgrad<T>(n, 13, 0, G_D0B, G_D0A, D0A, c0, 0, true);
     layer_wgrad<T>(n, 12, 0, CAT0, G_D0A);
     layer_dgrad<T>(n, 12, 0, G_D0A, G_CAT0, CAT0, 0, 0, false);
-    k_upsample_back<T><<<blocks((int64_t)B * H(1) * W(1) * c1), kEw, 0, n->st>>>(
+    k_upsample_back<T><<<blocks(((int64_t)B * H(1) * W(1) * c1) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, G_CAT0), c1 + c0, 0, c1, (const T*)buf(n, D1B), nullptr, (T*)buf(n, G_D1B), H(1), W(1), B);
     // decoder level 1
     layer_wgrad<T>(n, 11, 1, D1A, G_D1B);
     layer_dgrad<T>(n, 11, 1, G_D1B, G_D1A, D1A, c1, 0, true);
     layer_wgrad<T>(n, 10, 1, CAT1, G_D1A);
     layer_dgrad<T>(n, 10, 1, G_D1A, G_CAT1, CAT1, 0, 0, false);
-    k_upsample_back<T><<<blocks((int64_t)B * H(2) * W(2) * c2), kEw, 0, n->st>>>(
+    k_upsample_back<T><<<blocks(((int64_t)B * H(2) * W(2) * c2) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, G_CAT1), c2 + c1, 0, c2, (const T*)buf(n, D2B), nullptr, (T*)buf(n, G_D2B), H(2), W(2), B);
     // decoder level 2
     layer_wgrad<T>(n, 9, 2, D2A, G_D2B);
@@ -500,7 +500,7 @@ void backward_t(lbm_nn* n) {
     const int cat2 = 2 * c3 + c2;
     colsum<T>(n, buf(n, G_CAT2), cat2, c3 + c2, c3, (int64_t)H(2) * W(2), B, 1.0f, at<float>(n, p.o_gmean),
               (T*)nullptr);
-    k_upsample_back<T><<<blocks((int64_t)B * H(3) * W(3) * c3), kEw, 0, n->st>>>(
+    k_upsample_back<T><<<blocks(((int64_t)B * H(3) * W(3) * c3) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, G_CAT2), cat2, 0, c3, (const T*)buf(n, B2), at<float>(n, p.o_gmean), (T*)buf(n, G_B2),
         H(3), W(3), B);
     // bottleneck
@@ -509,7 +509,7 @@ void backward_t(lbm_nn* n) {
     layer_wgrad<T>(n, 6, 3, X3, G_B1);
     layer_dgrad<T>(n, 6, 3, G_B1, G_X3, X3, 0, 0, false);
     // encoder level 2
-    k_pool_back_skip<T><<<blocks((int64_t)B * H(2) * W(2) * c2), kEw, 0, n->st>>>(
+    k_pool_back_skip<T><<<blocks(((int64_t)B * H(2) * W(2) * c2) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, G_X3), (const T*)buf(n, G_CAT2), cat2, c3, (const T*)buf(n, CAT2), c2, (T*)buf(n, G_S2),
         H(2), W(2), B);
     layer_wgrad<T>(n, 5, 2, A2, G_S2);
@@ -517,7 +517,7 @@ void backward_t(lbm_nn* n) {
     layer_wgrad<T>(n, 4, 2, X2, G_A2);
     layer_dgrad<T>(n, 4, 2, G_A2, G_X2, X2, 0, 0, false);
     // encoder level 1
-    k_pool_back_skip<T><<<blocks((int64_t)B * H(1) * W(1) * c1), kEw, 0, n->st>>>(
+    k_pool_back_skip<T><<<blocks(((int64_t)B * H(1) * W(1) * c1) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, G_X2), (const T*)buf(n, G_CAT1), c2 + c1, c2, (const T*)buf(n, CAT1), c1, (T*)buf(n, G_S1),
         H(1), W(1), B);
     layer_wgrad<T>(n, 3, 1, A1, G_S1);
@@ -525,7 +525,7 @@ void backward_t(lbm_nn* n) {
     layer_wgrad<T>(n, 2, 1, X1, G_A1);
     layer_dgrad<T>(n, 2, 1, G_A1, G_X1, X1, 0, 0, false);
     // encoder level 0
-    k_pool_back_skip<T><<<blocks((int64_t)B * H(0) * W(0) * c0), kEw, 0, n->st>>>(
+    k_pool_back_skip<T><<<blocks(((int64_t)B * H(0) * W(0) * c0) / 8), kEw, 0, n->st>>>(
         (const T*)buf(n, G_X1), (const T*)buf(n, G_CAT0), c1 + c0, c1, (const T*)buf(n, CAT0), c0, (T*)buf(n, G_S0),
         H(0), W(0), B);
     layer_wgrad<T>(n, 1, 0, A0, G_S0);

@@ -814,38 +814,93 @@ __global__ __launch_bounds__(kEw) void k_colsum_partial(const T* __restrict__ a,
     }
 }
 
-// out[b][c] = scale * sum over the nblk partials of segment b (in order),
-// written as float (fout) or as T (tout).
+// out[b][c] = scale * sum over the nblk partials of segment b, written as
+// float (fout) or as T (tout).  Workgroup: 32 outputs x 8 rows; row r sums
+// the partials k = r, r + 8, ... in order, then the rows are added in order.
 template <typename T>
 __global__ __launch_bounds__(kEw) void k_colsum_final(const float* __restrict__ part, int nblk, int C, int B,
                                                       float scale, float* __restrict__ fout, T* __restrict__ tout) {
-    const int i = blockIdx.x * kEw + threadIdx.x;
-    if (i >= B * C) return;
-    const int b = i / C, c = i % C;
-    float s = 0.0f;
-    for (int k = 0; k < nblk; ++k) s += part[((int64_t)b * nblk + k) * C + c];
-    s *= scale;
-    if (fout) fout[i] = s;
-    if (tout) tout[i] = from_f<T>(s);
+    __shared__ float red[kSumRows][kSumCols + 1];
+    const int cc = threadIdx.x % kSumCols, r = threadIdx.x / kSumCols;
+    const int i = blockIdx.x * kSumCols + cc;
+    const bool ok = i < B * C;
+    const int b = ok ? i / C : 0, c = ok ? i % C : 0;
+    float v = 0.0f;
+    if (ok) {
+#pragma unroll 4
+        for (int k = r; k < nblk; k += kSumRows) v += part[((int64_t)b * nblk + k) * C + c];
+    }
+    red[r][cc] = v;
+    __syncthreads();
+    if (r == 0 && ok) {
+        float s = red[0][cc];
+#pragma unroll
+        for (int k = 1; k < kSumRows; ++k) s += red[k][cc];
+        s *= scale;
+        if (fout) fout[i] = s;
+        if (tout) tout[i] = from_f<T>(s);
+    }
 }
 
 // ------------------------------------------------------------------ pooling, upsampling
+// Every kernel here takes 8 consecutive channels per thread (one 16-byte
+// BF16 vector, two float4 in FP32 mode): channel counts, strides and offsets
+// are multiples of 8.  The arithmetic per element is the plain elementwise
+// one.
+template <typename T>
+__device__ inline void load8(const T* p, float f[8]);
+template <>
+__device__ inline void load8<__bf16>(const __bf16* p, float f[8]) {
+    const uint4 u = *reinterpret_cast<const uint4*>(p);
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = __uint_as_float(w[k] << 16);
+        f[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+}
+template <>
+__device__ inline void load8<float>(const float* p, float f[8]) {
+    const float4 a = reinterpret_cast<const float4*>(p)[0], b = reinterpret_cast<const float4*>(p)[1];
+    f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = a.w;
+    f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
+}
+template <typename T>
+__device__ inline void store8(T* p, const float f[8]);
+template <>
+__device__ inline void store8<__bf16>(__bf16* p, const float f[8]) {
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (__bf16)f[e];  // round to nearest even
+    *reinterpret_cast<bf16x8*>(p) = v;
+}
+template <>
+__device__ inline void store8<float>(float* p, const float f[8]) {
+    reinterpret_cast<float4*>(p)[0] = make_float4(f[0], f[1], f[2], f[3]);
+    reinterpret_cast<float4*>(p)[1] = make_float4(f[4], f[5], f[6], f[7]);
+}
+
 // out[b][y][x][c] = mean of in[b][2y + i][2x + j][c] (level l -> l + 1).
 template <typename T>
 __global__ __launch_bounds__(kEw) void k_pool(const T* __restrict__ in, int in_cs, int in_co, int C,
                                               T* __restrict__ out, int Ho, int Wo, int B) {
     const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
-    const int64_t n = (int64_t)B * Ho * Wo * C;
-    if (i >= n) return;
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
+    const int C8 = C / 8;
+    if (i >= (int64_t)B * Ho * Wo * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
     const int xo = (int)(q % Wo);
     const int64_t by = q / Wo;  // b * Ho + yo
     const int Wi = 2 * Wo;
     const int64_t r0 = (2 * by) * Wi + 2 * xo;  // (b * Hi + 2 yo) * Wi + 2 xo
-    float v = (to_f(in[r0 * in_cs + in_co + c]) + to_f(in[(r0 + 1) * in_cs + in_co + c])) +
-              (to_f(in[(r0 + Wi) * in_cs + in_co + c]) + to_f(in[(r0 + Wi + 1) * in_cs + in_co + c]));
-    out[q * C + c] = from_f<T>(0.25f * v);
+    float a[8], b1[8], c2[8], d[8], o[8];
+    load8(in + r0 * in_cs + in_co + c, a);
+    load8(in + (r0 + 1) * in_cs + in_co + c, b1);
+    load8(in + (r0 + Wi) * in_cs + in_co + c, c2);
+    load8(in + (r0 + Wi + 1) * in_cs + in_co + c, d);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = 0.25f * ((a[e] + b1[e]) + (c2[e] + d[e]));
+    store8(out + q * C + c, o);
 }
 
 // out[b][y][x][out_co + c] = in[b][y / 2][x / 2][c] (level l + 1 -> l).
@@ -853,14 +908,16 @@ template <typename T>
 __global__ __launch_bounds__(kEw) void k_upsample(const T* __restrict__ in, int C, T* __restrict__ out,
                                                   int out_cs, int out_co, int Ho, int Wo, int B) {
     const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
-    const int64_t n = (int64_t)B * Ho * Wo * C;
-    if (i >= n) return;
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
+    const int C8 = C / 8;
+    if (i >= (int64_t)B * Ho * Wo * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
     const int xo = (int)(q % Wo);
     const int64_t by = q / Wo;
     const int64_t src = (by >> 1) * (Wo >> 1) + (xo >> 1);
-    out[q * out_cs + out_co + c] = in[src * C + c];
+    float v[8];
+    load8(in + src * C + c, v);
+    store8(out + q * out_cs + out_co + c, v);
 }
 
 // Adjoint of the upsampling, then the ReLU mask of the lower-level activation:
@@ -872,21 +929,28 @@ __global__ __launch_bounds__(kEw) void k_upsample_back(const T* __restrict__ g, 
                                                        const T* __restrict__ act, const float* __restrict__ gmean,
                                                        T* __restrict__ out, int Hl, int Wl, int B) {
     const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
-    const int64_t n = (int64_t)B * Hl * Wl * C;
-    if (i >= n) return;
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
+    const int C8 = C / 8;
+    if (i >= (int64_t)B * Hl * Wl * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
     const int xl = (int)(q % Wl);
     const int64_t by = q / Wl;
     const int Wh = 2 * Wl;
     const int64_t r0 = (2 * by) * Wh + 2 * xl;
-    float v = (to_f(g[r0 * g_cs + g_co + c]) + to_f(g[(r0 + 1) * g_cs + g_co + c])) +
-              (to_f(g[(r0 + Wh) * g_cs + g_co + c]) + to_f(g[(r0 + Wh + 1) * g_cs + g_co + c]));
-    if (gmean) {
-        const int b = (int)(by / Hl);
-        v += gmean[(int64_t)b * C + c] / (float)(Hl * Wl);
+    float a[8], b1[8], c2[8], d[8], m[8], o[8];
+    load8(g + r0 * g_cs + g_co + c, a);
+    load8(g + (r0 + 1) * g_cs + g_co + c, b1);
+    load8(g + (r0 + Wh) * g_cs + g_co + c, c2);
+    load8(g + (r0 + Wh + 1) * g_cs + g_co + c, d);
+    load8(act + q * C + c, m);
+    const int b = (int)(by / Hl);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        float v = (a[e] + b1[e]) + (c2[e] + d[e]);
+        if (gmean) v += gmean[(int64_t)b * C + c + e] / (float)(Hl * Wl);
+        o[e] = m[e] > 0.0f ? v : 0.0f;
     }
-    out[q * C + c] = from_f<T>(to_f(act[q * C + c]) > 0.0f ? v : 0.0f);
+    store8(out + q * C + c, o);
 }
 
 // out[p][out_co + c] = m[b(p)][c] for every node p of a level with N nodes per sample.
@@ -894,10 +958,13 @@ template <typename T>
 __global__ __launch_bounds__(kEw) void k_broadcast(const T* __restrict__ m, int C, T* __restrict__ out, int out_cs,
                                                    int out_co, int N, int B) {
     const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
-    if (i >= (int64_t)B * N * C) return;
-    const int c = (int)(i % C);
-    const int64_t p = i / C;
-    out[p * out_cs + out_co + c] = m[(p / N) * C + c];
+    const int C8 = C / 8;
+    if (i >= (int64_t)B * N * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t p = i / C8;
+    float v[8];
+    load8(m + (p / N) * C + c, v);
+    store8(out + p * out_cs + out_co + c, v);
 }
 
 // Encoder skip: out[p][c] = (g_low[parent][c] / 4 + g_cat[p][skip_co + c]) *
@@ -907,15 +974,23 @@ __global__ __launch_bounds__(kEw) void k_pool_back_skip(const T* __restrict__ g_
                                                         int cat_cs, int skip_co, const T* __restrict__ act,
                                                         int C, T* __restrict__ out, int H, int W, int B) {
     const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
-    const int64_t n = (int64_t)B * H * W * C;
-    if (i >= n) return;
-    const int c = (int)(i % C);
-    const int64_t p = i / C;
+    const int C8 = C / 8;
+    if (i >= (int64_t)B * H * W * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t p = i / C8;
     const int x = (int)(p % W);
     const int64_t by = p / W;
     const int64_t parent = (by >> 1) * (W >> 1) + (x >> 1);
-    const float v = 0.25f * to_f(g_low[parent * C + c]) + to_f(g_cat[p * cat_cs + skip_co + c]);
-    out[p * C + c] = from_f<T>(to_f(act[p * cat_cs + skip_co + c]) > 0.0f ? v : 0.0f);
+    float lo[8], sk[8], ac[8], o[8];
+    load8(g_low + parent * C + c, lo);
+    load8(g_cat + p * cat_cs + skip_co + c, sk);
+    load8(act + p * cat_cs + skip_co + c, ac);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float v = 0.25f * lo[e] + sk[e];
+        o[e] = ac[e] > 0.0f ? v : 0.0f;
+    }
+    store8(out + p * C + c, o);
 }
 
 // ------------------------------------------------------------------ data
