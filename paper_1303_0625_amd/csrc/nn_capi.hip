@@ -267,13 +267,24 @@ void conv(lbm_nn* n, int level, const void* in, int in_cs, int cin, const void* 
     if (sizeof(T) == 2 && cin % 32 == 0 && a.H % kC9Rows == 0 && a.W % 32 == 0) {
         // BF16 with the input tile held across the nine taps, when the
         // launch still gives >= 256 workgroups
+        // (with <= 640 workgroups and several chunks the next chunk is
+        // prefetched into registers: fewer waves, but its loads overlap)
         const int64_t tiles = (int64_t)n->batch * (a.H / kC9Rows) * (a.W / 32);
+        const bool deep = cin >= 128;
         if (cout_pad % 64 == 0 && tiles * (cout_pad / 64) >= 512) {
-            k_conv9<2><<<dim3((unsigned)tiles, cout_pad / 64), 256, 0, n->st>>>(a);
+            const dim3 g((unsigned)tiles, cout_pad / 64);
+            if (deep && tiles * (cout_pad / 64) <= 640)
+                k_conv9<2, true><<<g, 256, 0, n->st>>>(a);
+            else
+                k_conv9<2, false><<<g, 256, 0, n->st>>>(a);
             return;
         }
         if (tiles * (cout_pad / 32) >= 256) {
-            k_conv9<1><<<dim3((unsigned)tiles, cout_pad / 32), 256, 0, n->st>>>(a);
+            const dim3 g((unsigned)tiles, cout_pad / 32);
+            if (deep && tiles * (cout_pad / 32) <= 640)
+                k_conv9<1, true><<<g, 256, 0, n->st>>>(a);
+            else
+                k_conv9<1, false><<<g, 256, 0, n->st>>>(a);
             return;
         }
     }

@@ -27,6 +27,7 @@ namespace nn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kConvWaves = 4;  // waves per convolution workgroup
 constexpr int kEw = 256;       // threads per elementwise workgroup
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 3))) voi
 constexpr int kC9Rows = 8;
 constexpr int kC9Pitch = 40;  // LDS elements per staged pixel / weight row (32 + 8 pad)
 
-template <int NB>
+template <int NB, bool PF>
 __global__ __launch_bounds__(256) void k_conv9(ConvArgs a) {
     constexpr int IR = kC9Rows + 2, IX = 34;         // staged input rows, pixels
     constexpr int IN_UNITS = IR * IX * 4;            // 16-byte units (8 channels)
@@ -352,47 +353,105 @@ __global__ __launch_bounds__(256) void k_conv9(ConvArgs a) {
         for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.0f;
-    for (int c0 = 0; c0 < a.cin; c0 += 32) {
-        // stage the input tile and the weights of this chunk
-        for (int u = t; u < IN_UNITS; u += 256) {
-            const int cg = u & 3, px = (u >> 2) % IX, r = (u >> 2) / IX;
-            const int yy = y0 - 1 + r;
-            int xx = x0 - 1 + px;
-            xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (yy >= 0 && yy < a.H)
-                v = *reinterpret_cast<const uint4*>(in + ((int64_t)(b * a.H + yy) * a.W + xx) * a.in_cs + c0 + 8 * cg);
-            *reinterpret_cast<uint4*>(&Is[(r * IX + px) * kC9Pitch + 8 * cg]) = v;
-        }
-        for (int u = t; u < W_UNITS; u += 256) {
-            const int cg = u & 3, tap = (u >> 2) % 9, n = (u >> 2) / 9;
-            *reinterpret_cast<uint4*>(&Ws[(n * 9 + tap) * kC9Pitch + 8 * cg]) =
-                *reinterpret_cast<const uint4*>(w + (int64_t)(nbase + n) * wrow + tap * a.cin + c0 + 8 * cg);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                Frag<__bf16> fa[2], fb[NB];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const int r = 2 * wave + i + 1 + dy, px = (l & 31) + 1 + dx;
-                    fa[i].v = *reinterpret_cast<const bf16x8*>(&Is[(r * IX + px) * kC9Pitch + 16 * ks + 8 * kg]);
-                }
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-                    fb[j].v = *reinterpret_cast<const bf16x8*>(
-                        &Ws[((32 * j + (l & 31)) * 9 + tap) * kC9Pitch + 16 * ks + 8 * kg]);
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < NB; ++j) mma(acc[i][j], fa[i], fb[j]);
-            }
-        }
-        __syncthreads();
+// the products of one staged chunk: nine taps x two K = 16 steps
+#define C9_PRODUCTS()                                                                                 \
+    _Pragma("unroll") for (int tap = 0; tap < 9; ++tap) {                                            \
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;                                                 \
+        _Pragma("unroll") for (int ks = 0; ks < 2; ++ks) {                                            \
+            Frag<__bf16> fa[2], fb[NB];                                                               \
+            _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                           \
+                const int r = 2 * wave + i + 1 + dy, px = (l & 31) + 1 + dx;                          \
+                fa[i].v = *reinterpret_cast<const bf16x8*>(&Is[(r * IX + px) * kC9Pitch + 16 * ks + 8 * kg]); \
+            }                                                                                         \
+            _Pragma("unroll") for (int j = 0; j < NB; ++j) fb[j].v = *reinterpret_cast<const bf16x8*>( \
+                &Ws[((32 * j + (l & 31)) * 9 + tap) * kC9Pitch + 16 * ks + 8 * kg]);                  \
+            _Pragma("unroll") for (int i = 0; i < 2; ++i)                                            \
+                _Pragma("unroll") for (int j = 0; j < NB; ++j) mma(acc[i][j], fa[i], fb[j]);          \
+        }                                                                                             \
     }
+    // PF: the next chunk's input and weights wait in registers while this
+    // chunk's products run (more registers; pays where few tiles share the
+    // chip); otherwise each chunk is loaded straight into LDS
+    if constexpr (!PF) {
+        for (int c0 = 0; c0 < a.cin; c0 += 32) {
+            for (int u = t; u < IN_UNITS; u += 256) {
+                const int cg = u & 3, px = (u >> 2) % IX, r = (u >> 2) / IX;
+                const int yy = y0 - 1 + r;
+                int xx = x0 - 1 + px;
+                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (yy >= 0 && yy < a.H)
+                    v = *reinterpret_cast<const uint4*>(in + ((int64_t)(b * a.H + yy) * a.W + xx) * a.in_cs + c0 + 8 * cg);
+                *reinterpret_cast<uint4*>(&Is[(r * IX + px) * kC9Pitch + 8 * cg]) = v;
+            }
+            for (int u = t; u < W_UNITS; u += 256) {
+                const int cg = u & 3, tap = (u >> 2) % 9, n = (u >> 2) / 9;
+                *reinterpret_cast<uint4*>(&Ws[(n * 9 + tap) * kC9Pitch + 8 * cg]) =
+                    *reinterpret_cast<const uint4*>(w + (int64_t)(nbase + n) * wrow + tap * a.cin + c0 + 8 * cg);
+            }
+            __syncthreads();
+            C9_PRODUCTS()
+            __syncthreads();
+        }
+    } else {
+    constexpr int IN_PER = (IN_UNITS + 255) / 256, W_PER = (W_UNITS + 255) / 256;
+    u32x4 rin[IN_PER], rw[W_PER];
+#define C9_GLOAD(C0)                                                                                             \
+    {                                                                                                            \
+        _Pragma("unroll") for (int k = 0; k < IN_PER; ++k) {                                                       \
+            const int u = t + 256 * k;                                                                           \
+            rin[k] = u32x4{0u, 0u, 0u, 0u};                                                                 \
+            if (u < IN_UNITS) {                                                                                  \
+                const int cg = u & 3, px = (u >> 2) % IX, r = (u >> 2) / IX;                                     \
+                const int yy = y0 - 1 + r;                                                                       \
+                int xx = x0 - 1 + px;                                                                            \
+                xx = xx < 0 ? xx + a.W : (xx >= a.W ? xx - a.W : xx);                                            \
+                if (yy >= 0 && yy < a.H)                                                                         \
+                    rin[k] = *reinterpret_cast<const u32x4*>(in + ((int64_t)(b * a.H + yy) * a.W + xx) * a.in_cs + \
+                                                             (C0) + 8 * cg);                                     \
+            }                                                                                                    \
+        }                                                                                                        \
+        _Pragma("unroll") for (int k = 0; k < W_PER; ++k) {                                                        \
+            const int u = t + 256 * k;                                                                           \
+            if (u < W_UNITS) {                                                                                   \
+                const int cg = u & 3, tap = (u >> 2) % 9, n = (u >> 2) / 9;                                      \
+                rw[k] = *reinterpret_cast<const u32x4*>(w + (int64_t)(nbase + n) * wrow + tap * a.cin + (C0) + 8 * cg); \
+            }                                                                                                    \
+        }                                                                                                        \
+    }
+#define C9_LSTORE()                                                                                              \
+    {                                                                                                            \
+        _Pragma("unroll") for (int k = 0; k < IN_PER; ++k) {                                                       \
+            const int u = t + 256 * k;                                                                           \
+            if (u < IN_UNITS) {                                                                                  \
+                const int cg = u & 3, px = (u >> 2) % IX, r = (u >> 2) / IX;                                     \
+                *reinterpret_cast<u32x4*>(&Is[(r * IX + px) * kC9Pitch + 8 * cg]) = rin[k];                      \
+            }                                                                                                    \
+        }                                                                                                        \
+        _Pragma("unroll") for (int k = 0; k < W_PER; ++k) {                                                        \
+            const int u = t + 256 * k;                                                                           \
+            if (u < W_UNITS) {                                                                                   \
+                const int cg = u & 3, tap = (u >> 2) % 9, n = (u >> 2) / 9;                                      \
+                *reinterpret_cast<u32x4*>(&Ws[(n * 9 + tap) * kC9Pitch + 8 * cg]) = rw[k];                       \
+            }                                                                                                    \
+        }                                                                                                        \
+    }
+    C9_GLOAD(0)
+    C9_LSTORE()
+    __syncthreads();
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        if (c0 + 32 < a.cin) C9_GLOAD(c0 + 32)
+        C9_PRODUCTS()
+        __syncthreads();
+        if (c0 + 32 < a.cin) {
+            C9_LSTORE()
+            __syncthreads();
+        }
+    }
+#undef C9_GLOAD
+#undef C9_LSTORE
+    }
+#undef C9_PRODUCTS
     const __bf16* mask = static_cast<const __bf16*>(a.mask);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
