@@ -98,6 +98,9 @@ def _load():
     lib.orc_set_gravity.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int]
     lib.orc_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     lib.orc_body_state.restype = ctypes.c_int
+    lib.orc_set_ibb.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.orc_link_q.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_int]
+    lib.orc_link_q.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -209,6 +212,13 @@ class OracleSim:
         """Body `body` (1-based disc) becomes a free particle of density rho_s."""
         if self._lib.orc_set_free(self._h, int(body), float(rho_s), float(omega0)) != 0:
             raise ValueError("oracle rejected the free body")
+
+    def set_ibb(self, on: bool = True) -> None:
+        """Interpolated bounce-back on body links."""
+        self._lib.orc_set_ibb(self._h, int(bool(on)))
+
+    def link_q(self, body: int, x: int, y: int, i: int) -> float:
+        return self._lib.orc_link_q(self._h, int(body), int(x), int(y), int(i))
 
     def set_gravity(self, G, scheme: int) -> None:
         self._lib.orc_set_gravity(self._h, float(G[0]), float(G[1]), int(scheme))

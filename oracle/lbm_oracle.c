@@ -16,7 +16,10 @@
  *                    summed per solid (Eq. 6) with torque (Eq. 7)
  *   O4 advection     Eq. 3; a population whose source node is solid is the
  *                    half-way bounce-back of the node's own opposite population
- *                    plus the moving-boundary term 6 w_i rho_w (e_i . v)
+ *                    plus the moving-boundary term 6 w_i rho_w (e_i . v); or,
+ *                    after orc_set_ibb, on body links the interpolated
+ *                    bounce-back of Sec. IV (linear in the fraction q of the
+ *                    link at which the surface lies)
  *   O5 move bodies   positions at t+1 (prescribed, or for free bodies the
  *                    Newton-Euler update from the step's force and torque),
  *                    rasterise G_{t+1}
@@ -56,6 +59,7 @@ struct orc_sim {
         double M, I, A;            /* mass, moment of inertia, area */
     } * dyn;
     double Gx, Gy;   /* gravity acting on free bodies (buoyancy-corrected) */
+    int ibb;         /* interpolated bounce-back on body links */
     int dyn_scheme;  /* ORC_CME or ORC_GME force drives them */
     int nb;
     orc_body* body;
@@ -134,6 +138,40 @@ static void wall_velocity(const orc_sim* s, int k, double px, double py, double*
     double ry = s->walls_y ? (py - d->Y) : min_image(py - d->Y, s->ny);
     *vx = d->Vx - d->Om * ry;
     *vy = d->Vy + d->Om * rx;
+}
+
+/* Fraction q in (0, 1] of the link from the fluid node (x, y) to (x, y) +
+ * (ex, ey) at which the surface of body k, centred at (X, Y), is crossed
+ * (the far end is inside the body, the near end outside).  Disc: the smaller
+ * root of |P + q e|^2 = r^2; box: the entry parameter of the ray into the
+ * slabs |dx| <= a, |dy| <= b.  Minimum image on periodic axes. */
+static double link_q_at(const orc_sim* s, int k, double X, double Y, long x, long y, int ex, int ey) {
+    const orc_body* b = &s->body[k];
+    double px = min_image((double)x - X, s->nx);
+    double py = s->walls_y ? ((double)y - Y) : min_image((double)y - Y, s->ny);
+    double q;
+    if (b->kind == ORC_DISC) {
+        double a2 = (double)(ex * ex + ey * ey);
+        double b2 = 2.0 * (px * ex + py * ey);
+        double c2 = px * px + py * py - b->a * b->a;
+        double disc = b2 * b2 - 4.0 * a2 * c2;
+        if (disc < 0.0) disc = 0.0;
+        q = (-b2 - sqrt(disc)) / (2.0 * a2);
+    } else {
+        double lo = -1e300;
+        const double p[2] = {px, py}, h[2] = {b->a, b->b};
+        const int e[2] = {ex, ey};
+        for (int d = 0; d < 2; ++d) {
+            if (e[d] == 0) continue;
+            double t1 = (-h[d] - p[d]) / e[d], t2 = (h[d] - p[d]) / e[d];
+            double tmin = t1 < t2 ? t1 : t2;
+            if (tmin > lo) lo = tmin;
+        }
+        q = lo;
+    }
+    if (q <= 0.0) q = 1e-12;
+    if (q > 1.0) q = 1.0;
+    return q;
 }
 
 /* Rasterise all bodies at step t into own (0 = fluid).  Every integer point
@@ -421,6 +459,15 @@ int orc_set_free(orc_sim* s, int body, double rho_s, double omega0) {
     return 0;
 }
 
+void orc_set_ibb(orc_sim* s, int on) { s->ibb = on ? 1 : 0; }
+
+double orc_link_q(const orc_sim* s, int body, long x, long y, int i) {
+    if (body < 1 || body > s->nb || i < 1 || i > 8) return -1.0;
+    double X, Y;
+    body_center(s, body - 1, s->t, &X, &Y);
+    return link_q_at(s, body - 1, X, Y, x, y, EX[i], EY[i]);
+}
+
 void orc_set_gravity(orc_sim* s, double Gx, double Gy, int scheme) {
     s->Gx = Gx;
     s->Gy = Gy;
@@ -518,8 +565,17 @@ static void one_step(orc_sim* s) {
                 } else {
                     sid = s->own[idx(s, xb, yb)];
                     if (sid == 0) continue;
-                    /* boundary velocity at the link midpoint x_f + e_i/2 */
-                    wall_velocity(s, sid - 1, x + 0.5 * EX[i], y + 0.5 * EY[i], &vx, &vy);
+                }
+                /* the link's surface point: the midpoint for half-way bounce-back,
+                 * x_f + q e_i for the interpolated one (body links) */
+                double q = 0.5;
+                if (sid > 0) {
+                    if (s->ibb) {
+                        double X, Y;
+                        body_center(s, sid - 1, t, &X, &Y);
+                        q = link_q_at(s, sid - 1, X, Y, x, y, EX[i], EY[i]);
+                    }
+                    wall_velocity(s, sid - 1, x + q * EX[i], y + q * EY[i], &vx, &vy);
                 }
                 double rho_w = s->rho0;
                 if (s->rho_w_local) {
@@ -528,8 +584,21 @@ static void one_step(orc_sim* s) {
                 }
                 double a = s->ft[pidx(s, i, x, y)];
                 /* population leaving the boundary node towards x_f: HWBB with
-                 * the moving-boundary term */
-                double b = a - 6.0 * W[i] * rho_w * (EX[i] * vx + EY[i] * vy);
+                 * the moving-boundary term, or the interpolated bounce-back
+                 * (the value O4 streams into x_f) */
+                const double m = 6.0 * W[i] * rho_w * (EX[i] * vx + EY[i] * vy);
+                double b = a - m;
+                if (q != 0.5) {
+                    int xq, yq;
+                    if (q < 0.5) {
+                        /* needs the fluid node behind x_f */
+                        if (!neighbour(s, x, y, i, -1, &xq, &yq) && s->own[idx(s, xq, yq)] == 0)
+                            b = 2.0 * q * a + (1.0 - 2.0 * q) * s->ft[pidx(s, i, xq, yq)] - m;
+                    } else {
+                        b = a / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->ft[pidx(s, OPP[i], x, y)] -
+                            m / (2.0 * q);
+                    }
+                }
                 double fc[2], fg[2];
                 orc_link_force(i, a, b, vx, vy, ORC_CME, fc);
                 orc_link_force(i, a, b, vx, vy, ORC_GME, fg);
@@ -537,9 +606,9 @@ static void one_step(orc_sim* s) {
                 if (sid > 0) {
                     double X, Y;
                     body_center(s, sid - 1, t, &X, &Y);
-                    /* intersection point S at the link midpoint */
-                    double rx = min_image(x + 0.5 * EX[i] - X, nx);
-                    double ry = s->walls_y ? (y + 0.5 * EY[i] - Y) : min_image(y + 0.5 * EY[i] - Y, ny);
+                    /* intersection point S of the link with the surface */
+                    double rx = min_image(x + q * EX[i] - X, nx);
+                    double ry = s->walls_y ? (y + q * EY[i] - Y) : min_image(y + q * EY[i] - Y, ny);
                     tc = rx * fc[1] - ry * fc[0];
                     tg = rx * fg[1] - ry * fg[0];
                 }
@@ -574,8 +643,34 @@ static void one_step(orc_sim* s) {
                         s->fn[pidx(s, i, x, y)] = s->ft[pidx(s, i, xs, ys)];
                         continue;
                     }
-                    /* boundary velocity at the link midpoint x - e_i/2 */
-                    wall_velocity(s, sid - 1, x - 0.5 * EX[i], y - 0.5 * EY[i], &vx, &vy);
+                    double q = 0.5;
+                    if (s->ibb) {
+                        double X, Y;
+                        body_center(s, sid - 1, t, &X, &Y);
+                        q = link_q_at(s, sid - 1, X, Y, x, y, -EX[i], -EY[i]);
+                    }
+                    /* boundary velocity at the surface point x - q e_i */
+                    wall_velocity(s, sid - 1, x - q * EX[i], y - q * EY[i], &vx, &vy);
+                    if (q != 0.5) {
+                        double rho_q = s->rho0;
+                        if (s->rho_w_local) {
+                            rho_q = 0.0;
+                            for (int j = 0; j < 9; ++j) rho_q += s->ft[pidx(s, j, x, y)];
+                        }
+                        const double m = 6.0 * W[i] * rho_q * (EX[i] * vx + EY[i] * vy);
+                        const double fo = s->ft[pidx(s, OPP[i], x, y)];
+                        double v = fo + m;  /* half-way when the node behind is not fluid */
+                        int xq, yq;
+                        if (q < 0.5) {
+                            if (!neighbour(s, x, y, i, +1, &xq, &yq) && s->own[idx(s, xq, yq)] == 0)
+                                v = 2.0 * q * fo + (1.0 - 2.0 * q) * s->ft[pidx(s, OPP[i], xq, yq)] + m;
+                        } else {
+                            v = fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->ft[pidx(s, i, x, y)] +
+                                m / (2.0 * q);
+                        }
+                        s->fn[pidx(s, i, x, y)] = v;
+                        continue;
+                    }
                 }
                 double rho_w = s->rho0;
                 if (s->rho_w_local) {

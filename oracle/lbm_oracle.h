@@ -105,6 +105,21 @@ void orc_collide_node(const double f[9], double tau, double gx, double gy,
  * Returns 0, or -1 (not a disc, t > 0, rho_s <= 0, bad index). */
 int orc_set_free(orc_sim* s, int body, double rho_s, double omega0);
 
+/* Interpolated bounce-back on body links (Sec. IV; linear in the fraction q
+ * of the link from the fluid node x_f to the surface): the population
+ * returning to x_f in direction ibar is
+ *   q < 1/2:  2q f~_i(x_f) + (1 - 2q) f~_i(x_f - e_i) + m_ibar
+ *             (half-way bounce-back when x_f - e_i is not fluid),
+ *   q >= 1/2: f~_i(x_f)/(2q) + (2q - 1)/(2q) f~_ibar(x_f) + m_ibar/(2q),
+ * m_ibar = 6 w_i rho_w (e_ibar . v) with the surface velocity v at x_f + q e_i;
+ * the link force (Eqs. 4-5) takes this population as the returning one and
+ * the torque arm ends at x_f + q e_i.  Wall rows keep half-way bounce-back. */
+void orc_set_ibb(orc_sim* s, int on);
+
+/* q of the link from fluid node (x, y) in direction i into body `body` at
+ * the current step (test access). */
+double orc_link_q(const orc_sim* s, int body, long x, long y, int i);
+
 /* Gravity G on free bodies (buoyancy-corrected: (M - rho0 A) G) and the force
  * scheme (ORC_CME / ORC_GME) that drives them. */
 void orc_set_gravity(orc_sim* s, double Gx, double Gy, int scheme);
