@@ -65,7 +65,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_step(const CaseDev* __rest
     const int x = (w - y * cd.wpr) * 64 + (int)(threadIdx.x & 63);
     if (x >= cd.sa.nx) return;
     step_node<T, NT>(x, y, fbase + cd.f_off[parity], fbase + cd.f_off[parity ^ 1], obase + cd.own_off,
-                     vtab_all + 2 * cd.solid_base, nullptr, cd.sa, case_cp<T>(cd));
+                     vtab_all + 2 * cd.solid_base, nullptr, nullptr, 0, cd.sa, case_cp<T>(cd));
 }
 
 // Force chunks of every active case at the current state (parity).
@@ -92,7 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_force(const CaseDev* __restric
     // force_role addresses the case's solids from its own base; chunk tables
     // are per case here, so pass one-element views
     const int cs = ch.s, cstart = ch.start;
-    force_role<T>(0, fs, fbase + cd.f_off[parity], links + cd.links_base, seg_cnt + cd.solid_base,
+    // (half-way bounce-back: the owner map is not consulted)
+    force_role<T, false>(0, fs, fbase + cd.f_off[parity], nullptr, links + cd.links_base, seg_cnt + cd.solid_base,
                   seg_off + cd.solid_base, &cs, &cstart, sol_all + cd.solid_base,
                   vtab_all + 2 * cd.solid_base, nullptr, partial + (size_t)blockIdx.x * 6, t, cd.fa);
 }

@@ -217,6 +217,7 @@ struct lbm_ctx {
     double Gx = 0.0, Gy = 0.0;           // gravity on free bodies
     int dyn_scheme = LBM_GME;            // force that drives them
     int mrt = 0;                        // collision operator: 0 BGK, 1 MRT
+    int ibb = 0;                        // interpolated bounce-back on body links
     double mrt_s[3] = {0.0, 0.0, 0.0};  // MRT rates s_e, s_eps, s_q
     int64_t hist_first = 0;  // first step whose force record is held
     std::vector<int> seg_off, seg_cap;
@@ -247,6 +248,7 @@ StepArgs step_args(const lbm_ctx* c) {
     a.ystride = 9 * (int64_t)c->L.pitch;
     a.walls = c->g.walls_y;
     a.rho0 = c->g.rho0;
+    a.ibb = c->ibb;
     return a;
 }
 
@@ -276,6 +278,8 @@ ForceArgs force_args(const lbm_ctx* c) {
     a.hist_cap = c->hist_cap;
     a.nsol = c->n + 1;
     a.nchunks = c->L.nchunks;
+    a.opitch = c->L.opitch;
+    a.ibb = c->ibb;
     return a;
 }
 
@@ -337,6 +341,7 @@ lbm_status enqueue_step(lbm_ctx* c) {
     rc.n_lead = (rc.n_force + rc.n_move + 1 + 7) / 8 * 8;
     MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
                 9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes, n_presc};
+    ma.ibb = c->ibb;
     StepArgs sa = step_args(c);
     ForceArgs fa = force_args(c);
     CollideParams<C> cp = collide_params<C>(c);
@@ -346,7 +351,8 @@ lbm_status enqueue_step(lbm_ctx* c) {
     const bool nt = 2 * c->L.fbytes > kStreamBytes;
     using KF = decltype(&k_fused<T, true, true, true>);
     KF kern;
-    if (n_free > 0)
+    // per-link surface geometry: spinning free bodies or interpolated bounce-back
+    if (n_free > 0 || c->ibb)
         kern = c->mrt ? (nt ? k_fused<T, true, true, true> : k_fused<T, false, true, true>)
                       : (nt ? k_fused<T, true, false, true> : k_fused<T, false, false, true>);
     else
@@ -802,6 +808,16 @@ lbm_status lbm_init_fields(lbm_ctx* c, const void* d_rho, const void* d_ux, cons
     return LBM_OK;
 }
 
+lbm_status lbm_set_boundary(lbm_ctx* c, int32_t rule) {
+    if (!c) return LBM_EINVAL;
+    if (rule != LBM_HALFWAY && rule != LBM_INTERPOLATED) {
+        set_err(c->err, "rule must be LBM_HALFWAY or LBM_INTERPOLATED");
+        return LBM_EINVAL;
+    }
+    c->ibb = rule == LBM_INTERPOLATED ? 1 : 0;
+    return LBM_OK;
+}
+
 lbm_status lbm_set_collision(lbm_ctx* c, int32_t model, const double* rates) {
     if (!c) return LBM_EINVAL;
     if (model != LBM_BGK && model != LBM_MRT) {
@@ -980,11 +996,12 @@ lbm_status lbm_link_forces(lbm_ctx* c, double* d_out, int64_t max, int64_t* n) {
     const SolidDev* sol = wsp<SolidDev>(c, c->L.sol);
     const double* vt = wsp<double>(c, c->L.vtab) + (size_t)p * 2 * (c->n + 1);
     const double* rt = wsp<double>(c, c->L.rtab) + (size_t)p * kRot * (c->n + 1);
+    const uint8_t* own = own_ptr(c, p);
     switch (c->g.dtype) {
-        case LBM_F64: k_link_records<double><<<ns, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
-        case LBM_F32: k_link_records<float><<<ns, kBlock, 0, c->stream>>>(wsp<float>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
-        case LBM_F16: k_link_records<_Float16><<<ns, kBlock, 0, c->stream>>>(wsp<_Float16>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
-        default: k_link_records<bf16_t><<<ns, kBlock, 0, c->stream>>>(wsp<bf16_t>(c, c->L.f[p]), links, sc, so, ro, sol, vt, rt, d_out, fa); break;
+        case LBM_F64: k_link_records<double><<<ns, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.f[p]), own, links, sc, so, ro, sol, vt, rt, d_out, c->t, fa); break;
+        case LBM_F32: k_link_records<float><<<ns, kBlock, 0, c->stream>>>(wsp<float>(c, c->L.f[p]), own, links, sc, so, ro, sol, vt, rt, d_out, c->t, fa); break;
+        case LBM_F16: k_link_records<_Float16><<<ns, kBlock, 0, c->stream>>>(wsp<_Float16>(c, c->L.f[p]), own, links, sc, so, ro, sol, vt, rt, d_out, c->t, fa); break;
+        default: k_link_records<bf16_t><<<ns, kBlock, 0, c->stream>>>(wsp<bf16_t>(c, c->L.f[p]), own, links, sc, so, ro, sol, vt, rt, d_out, c->t, fa); break;
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));

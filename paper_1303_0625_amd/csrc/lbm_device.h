@@ -300,6 +300,59 @@ __device__ inline bool solid_inside(const SolidDev& s, double X, double Y, long 
     return fabs(dx) <= s.a && fabs(dy) <= s.b;
 }
 
+// Centre of solid sid at step t: a free body's from the step's rotation
+// table {Omega, X, Y, free}, any other from its prescribed motion.
+__device__ inline void solid_centre(const SolidDev* __restrict__ sol, const double* __restrict__ rt, int sid,
+                                    int64_t t, double& X, double& Y) {
+    if (rt != nullptr && rt[kRot * sid + 3] != 0.0) {
+        X = rt[kRot * sid + 1];
+        Y = rt[kRot * sid + 2];
+    } else {
+        solid_pos(sol[sid], t, X, Y);
+    }
+}
+
+// Fraction q of the link from node (x, y) along (ex, ey) at which the link
+// enters solid S centred at (X, Y) (interpolated bounce-back, Sec. IV): the
+// node lies outside, (x + ex, y + ey) inside, so 0 < q <= 1.  Disc: the
+// nearer root of |P + q e| = r with P the node's offset from the centre
+// (half-coefficient form); box: the last of the two slab entries.  Offsets
+// take the minimum image on periodic axes; rounding is clamped into (0, 1].
+__device__ inline double link_fraction(const SolidDev& S, double X, double Y, int x, int y, int ex, int ey,
+                                       int nx, int ny, int walls) {
+    const double px = min_image((double)x - X, nx);
+    const double py = walls ? (double)y - Y : min_image((double)y - Y, ny);
+    double q;
+    if (S.shape == 0) {
+        const double e2 = (double)(ex * ex + ey * ey);
+        const double pe = px * ex + py * ey;
+        const double c = px * px + py * py - S.a * S.a;
+        const double disc = pe * pe - e2 * c;
+        q = (-pe - sqrt(disc > 0.0 ? disc : 0.0)) / e2;
+    } else {
+        q = -1.0e300;
+        if (ex != 0) q = fmax(q, fmin((-S.a - px) * ex, (S.a - px) * ex));
+        if (ey != 0) q = fmax(q, fmin((-S.b - py) * ey, (S.b - py) * ey));
+    }
+    if (q <= 0.0) q = 1.0e-12;
+    return q > 1.0 ? 1.0 : q;
+}
+
+// Population returned by interpolated bounce-back (linear in q) for the
+// direction whose link from the fluid node meets the surface at fraction q:
+//   q <  1/2:  2q fo + (1 - 2q) fb + m   (fb: the opposite population of the
+//              fluid node behind; half-way fo + m when there is none)
+//   q >= 1/2:  (fo + m)/(2q) + (1 - 1/(2q)) fi
+// fo: the node's own population towards the surface, fi: its own population
+// away from it, m: the moving-wall term.  q = 1/2 is half-way bounce-back.
+template <typename C>
+__device__ inline C ibb_value(double q, C fo, C fi, C fb, bool behind, C m) {
+    if (q == 0.5) return fo + m;
+    if (q < 0.5) return behind ? C(2.0 * q) * fo + C(1.0 - 2.0 * q) * fb + m : fo + m;
+    const double h = 0.5 / q;
+    return C(h) * (fo + m) + C(1.0 - h) * fi;
+}
+
 // Integer bounding range (with a margin) of solid s centred at (X, Y).
 __device__ inline void solid_range(const SolidDev& s, double X, double Y, int margin, long& x0,
                                    long& x1, long& y0, long& y1) {

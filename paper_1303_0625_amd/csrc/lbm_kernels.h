@@ -37,6 +37,7 @@ struct StepArgs {
     int64_t ystride;   // elements between rows y and y+1
     int walls;
     double rho0;
+    int ibb = 0;       // interpolated bounce-back on body links
 };
 
 // ------------------------------------------------------------------ pull
@@ -109,17 +110,18 @@ __device__ inline T* row_at(T* base, uint32_t idx) {
 // only when a source node is solid (or a wall row) are they replaced by the
 // per-direction bounce-back values.  bid/nblk: this workgroup's index among
 // the update workgroups (remapped so that each XCD walks a contiguous band).
-template <typename T, bool NT, bool MRT = false, bool ROT = false>
+template <typename T, bool NT, bool MRT = false, bool GEO = false>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
-                                 const double* __restrict__ rtab, const StepArgs& a,
-                                 const CollideParams<typename Sto<T>::C>& cp);
+                                 const double* __restrict__ rtab, const SolidDev* __restrict__ sol, int64_t t,
+                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp);
 
-template <typename T, bool NT, bool MRT, bool ROT>
+template <typename T, bool NT, bool MRT, bool GEO>
 __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restrict__ fin,
                                  T* __restrict__ fout, const uint8_t* __restrict__ own_t,
                                  const double* __restrict__ vtab, const double* __restrict__ rtab,
-                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp) {
+                                 const SolidDev* __restrict__ sol, int64_t t, const StepArgs& a,
+                                 const CollideParams<typename Sto<T>::C>& cp) {
     // row and column base are wave-uniform scalars
     const uint32_t b = xcd_remap(bid, nblk);
     const uint32_t wpr = (uint32_t)a.rowlen >> 6;
@@ -127,17 +129,20 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
     const int y = (int)(gw / wpr);
     const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
     if (y >= a.ny || x >= a.nx) return;
-    step_node<T, NT, MRT, ROT>(x, y, fin, fout, own_t, vtab, rtab, a, cp);
+    step_node<T, NT, MRT, GEO>(x, y, fin, fout, own_t, vtab, rtab, sol, t, a, cp);
 }
 
 // The update of node (x, y): pull, bounce-back, collide (BGK, or MRT when
-// MRT), store.  ROT: some solid rotates (free bodies); its wall velocity at
-// the link midpoint x - e_i/2 is V + Omega z x (x - e_i/2 - X).
-template <typename T, bool NT, bool MRT, bool ROT>
+// MRT), store.  GEO: body links take their surface geometry into account:
+// the surface point of the link into solid sid is x - q e_i (q = 1/2, or the
+// link fraction under interpolated bounce-back), where a spinning free body
+// moves at V + Omega z x (x - q e_i - X); t is the step (centres of moving
+// bodies).
+template <typename T, bool NT, bool MRT, bool GEO>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
-                                 const double* __restrict__ rtab, const StepArgs& a,
-                                 const CollideParams<typename Sto<T>::C>& cp) {
+                                 const double* __restrict__ rtab, const SolidDev* __restrict__ sol, int64_t t,
+                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp) {
     using C = typename Sto<T>::C;
 
     const int xm = x == 0 ? a.nx - 1 : x - 1;
@@ -195,14 +200,38 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
             const uint32_t sid = wall ? 0u : src[i];
             if (wall || sid != 0u) {
                 C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-                if constexpr (ROT) {
-                    const double om = rtab[kRot * sid];
-                    if (om != 0.0) {
-                        const double rx = min_image((double)x - 0.5 * ex_(i) - rtab[kRot * sid + 1], a.nx);
-                        double ry = (double)y - 0.5 * ey_(i) - rtab[kRot * sid + 2];
-                        if (!a.walls) ry = min_image(ry, a.ny);
-                        vx = (C)((double)vtab[2 * sid] - om * ry);
-                        vy = (C)((double)vtab[2 * sid + 1] + om * rx);
+                if constexpr (GEO) {
+                    if (sid != 0u) {
+                        double X, Y;
+                        solid_centre(sol, rtab, (int)sid, t, X, Y);
+                        const double q = a.ibb ? link_fraction(sol[sid], X, Y, x, y, -ex_(i), -ey_(i), a.nx,
+                                                               a.ny, a.walls)
+                                               : 0.5;
+                        const double om = rtab[kRot * sid];
+                        if (om != 0.0) {
+                            const double rx = min_image((double)x - q * ex_(i) - X, a.nx);
+                            double ry = (double)y - q * ey_(i) - Y;
+                            if (!a.walls) ry = min_image(ry, a.ny);
+                            vx = (C)((double)vtab[2 * sid] - om * ry);
+                            vy = (C)((double)vtab[2 * sid + 1] + om * rx);
+                        }
+                        const C m = C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
+                        const C fo = Sto<T>::ld(*row_at(r0 + opp_(i) * P, ux));
+                        if (q == 0.5) {
+                            d[i] = fo + m;
+                        } else {
+                            // the node behind, x + e_i, is the source of the
+                            // opposite direction o; when it is fluid, d[o]
+                            // still holds the value streamed from it (only
+                            // directions with a solid or wall source are
+                            // replaced)
+                            const int o = opp_(i);
+                            const bool owall = (ey_(o) == 1 && wall_lo) || (ey_(o) == -1 && wall_hi);
+                            const bool behind = !owall && src[o] == 0u;
+                            const C fi = q > 0.5 ? Sto<T>::ld(*row_at(r0 + i * P, ux)) : C(0);
+                            d[i] = ibb_value<C>(q, fo, fi, d[o], behind, m);
+                        }
+                        continue;
                     }
                 }
                 d[i] = Sto<T>::ld(*row_at(r0 + opp_(i) * P, ux)) +
@@ -518,6 +547,7 @@ struct MoveArgs {
     int refill;     // 0 A1, 1 A2, 2 A3
     int box_bytes;  // capacity of each LDS byte map
     int n_movers;   // translating bodies (mover workgroups: 2 n_movers)
+    int ibb = 0;    // interpolated bounce-back on body links
 };
 
 // Bounding range of the body centred at (Xa, Ya) (step t - 1) and at
@@ -560,16 +590,17 @@ struct MoveShared {
 };
 
 // Mover role m: part m / n_movers for body movers[m % n_movers]; lds holds
-// the two byte maps (2 * box_bytes).
-template <typename T, bool MRT>
+// the two byte maps (2 * box_bytes).  GEO: link geometry in the refill
+// stencil (spinning free bodies, interpolated bounce-back).
+template <typename T, bool MRT, bool GEO>
 __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>& sm,
                                  const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, uint8_t* __restrict__ own_n,
                                  uint32_t* __restrict__ links_n, int* __restrict__ seg_cnt_n,
                                  const int* __restrict__ seg_off, const int* __restrict__ seg_cap,
                                  const SolidDev* __restrict__ sol, const double* __restrict__ vtab,
-                                 const int* __restrict__ movers, const int64_t* __restrict__ tctr,
-                                 int parity, const MoveArgs& a,
+                                 const double* __restrict__ rt, const int* __restrict__ movers,
+                                 const int64_t* __restrict__ tctr, int parity, const MoveArgs& a,
                                  const CollideParams<typename Sto<T>::C>& cp, int* __restrict__ errflag,
                                  const FreeArgs* fr = nullptr) {
     using C = typename Sto<T>::C;
@@ -776,16 +807,39 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
             if (j != 0 && o != 0) {
                 const int sid = o == kWallMark ? 0 : o;
                 C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-                if (fr && sid == s) {  // spinning free body: velocity at the link midpoint, step t
-                    const double om = fr->rtab[kRot * s];
-                    const double rx = min_image((double)gx - 0.5 * ex_(j) - Xt, a.nx);
-                    double ry = (double)gy - 0.5 * ey_(j) - Yt;
-                    if (!a.walls) ry = min_image(ry, a.ny);
-                    vx = (C)(vtab[2 * s] - om * ry);
-                    vy = (C)(vtab[2 * s + 1] + om * rx);
+                // surface point gx - q e_j of a body link (q = 1/2 unless
+                // interpolated), step t; a spinning free body moves there at
+                // V + Omega z x (point - centre)
+                double q = 0.5;
+                if (GEO && sid != 0 && (a.ibb || fr)) {
+                    double X = Xt, Y = Yt;
+                    if (!(fr && sid == s)) solid_centre(sol, rt, sid, t, X, Y);
+                    if (a.ibb) q = link_fraction(sol[sid], X, Y, gx, gy, -ex_(j), -ey_(j), a.nx, a.ny, a.walls);
+                    const double om = rt[kRot * sid];
+                    if (om != 0.0) {
+                        const double rx = min_image((double)gx - q * ex_(j) - X, a.nx);
+                        double ry = (double)gy - q * ey_(j) - Y;
+                        if (!a.walls) ry = min_image(ry, a.ny);
+                        vx = (C)(vtab[2 * sid] - om * ry);
+                        vy = (C)(vtab[2 * sid + 1] + om * rx);
+                    }
                 }
-                v = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]) +
-                    C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
+                const C fo = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]);
+                const C mw = C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
+                if (q == 0.5) {
+                    v = fo + mw;
+                } else {
+                    // the node behind, gx + e_j (in the box: at most 4 nodes
+                    // from the newborn node, like the sources)
+                    const int qb = qm + (ey_(j) * W + ex_(j));
+                    const bool behind = ot[qb] == 0;
+                    C fb = C(0), fi = C(0);
+                    int bx, by;
+                    if (behind && q < 0.5 && gidx(qb, bx, by))
+                        fb = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)by * a.ystride + bx]);
+                    if (q > 0.5) fi = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx]);
+                    v = ibb_value<C>(q, fo, fi, fb, behind, mw);
+                }
             } else {
                 int sx, sy;
                 gidx(qs, sx, sy);
@@ -881,7 +935,62 @@ struct ForceArgs {
     int64_t hist_cap;
     int nsol;     // bodies + 1
     int nchunks;  // force workgroups
+    int opitch = 0;  // bytes per owner-map row
+    int ibb = 0;     // interpolated bounce-back on body links
 };
+
+// One fluid-solid link (x_f, i) of solid s, in FP64 on full populations:
+// a = f~_i(x_f) leaves towards the surface, b is the population that
+// returns to x_f (the value the update streams there): half-way
+// bounce-back a - m, or under interpolated bounce-back the rule of
+// ibb_value with q the link fraction; (rx, ry) is the arm from the centre to
+// the surface point x_f + q e_i and (vx, vy) the surface velocity there.
+struct LinkEval {
+    double av, bv, vx, vy, rx, ry;
+};
+
+template <typename T, bool GEO>
+__device__ inline LinkEval eval_link(const T* __restrict__ f, const uint8_t* __restrict__ own_t,
+                                     const SolidDev& S, double X, double Y, double vbx, double vby, double om,
+                                     int s, int x, int y, int i, const ForceArgs& a) {
+    const double ex = ex_(i), ey = ey_(i), w = w_<double>(i);
+    double q = 0.5;
+    if constexpr (GEO)
+        if (a.ibb && s > 0) q = link_fraction(S, X, Y, x, y, ex_(i), ey_(i), a.nx, a.ny, a.walls);
+    LinkEval L;
+    L.rx = 0.0;
+    L.ry = 0.0;
+    if (s > 0) {
+        L.rx = min_image(((double)x + q * ex) - X, a.nx);
+        L.ry = ((double)y + q * ey) - Y;
+        if (!a.walls) L.ry = min_image(L.ry, a.ny);
+    }
+    L.vx = vbx - om * L.ry;
+    L.vy = vby + om * L.rx;
+    L.av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
+    const double m = 6.0 * w * a.rho0 * (ex * L.vx + ey * L.vy);
+    L.bv = L.av - m;
+    if constexpr (!GEO) return L;
+    if (q < 0.5) {
+        // the fluid node behind, x_f - e_i (half-way when it is solid or a wall)
+        int xb = x - ex_(i), yb = y - ey_(i);
+        xb = xb < 0 ? xb + a.nx : (xb >= a.nx ? xb - a.nx : xb);
+        bool ok = true;
+        if (a.walls)
+            ok = yb >= 0 && yb < a.ny;
+        else
+            yb = yb < 0 ? yb + a.ny : (yb >= a.ny ? yb - a.ny : yb);
+        if (ok && own_t[(int64_t)yb * a.opitch + xb] == 0) {
+            const double fb = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)yb * a.ystride + xb]);
+            L.bv = 2.0 * q * L.av + (1.0 - 2.0 * q) * fb - m;
+        }
+    } else if (q > 0.5) {
+        const double fo = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)opp_(i) * a.istride + (int64_t)y * a.ystride + x]);
+        const double h = 0.5 / q;
+        L.bv = h * (L.av - m) + (1.0 - h) * fo;
+    }
+    return L;
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -891,10 +1000,11 @@ __device__ inline double wave_sum(double v) {
 
 // Chunked link forces.  Workgroup c takes links [start, start + kForceChunk)
 // of solid chunk_solid[c].  Per link (x_f, i) with a = f~_i(x_f) and the
-// bounced population b = a - 6 w_i rho0 (e_i . v):
+// returning population b of eval_link (half-way: b = a - 6 w_i rho0 (e_i . v)):
 //   CME (Eq. 4) F = e_i a - e_ibar b
 //   GME (Eq. 5) F = (e_i - v) a - (e_ibar - v) b
-//   T_z (Eq. 7) = (x_s - R) x F with x_s = x_f + e_i/2, R the body centre.
+//   T_z (Eq. 7) = (x_s - R) x F with x_s = x_f + q e_i (q = 1/2 for half-way
+//   bounce-back), R the body centre.
 // Each thread sums a fixed strided subset, the wave and workgroup combine in
 // a fixed tree into partial[c].  The per-solid totals are formed later, in
 // chunk order, by finalize_forces (in the next launch), so no workgroup
@@ -903,9 +1013,10 @@ struct ForceShared {
     double red[kBlock / 64][6];
 };
 
-template <typename T>
+// GEO: interpolated bounce-back may be on (a.ibb).
+template <typename T, bool GEO>
 __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ f,
-                                  const uint32_t* __restrict__ links,
+                                  const uint8_t* __restrict__ own_t, const uint32_t* __restrict__ links,
                                   const int* __restrict__ seg_cnt, const int* __restrict__ seg_off,
                                   const int* __restrict__ chunk_solid,
                                   const int* __restrict__ chunk_start,
@@ -936,27 +1047,9 @@ __device__ inline void force_role(int c, ForceShared& fs, const T* __restrict__ 
         const uint32_t node = code >> 4;
         const int y = (int)(node / (uint32_t)a.nx);
         const int x = (int)(node - (uint32_t)y * (uint32_t)a.nx);
-        double ex = 0, ey = 0, w = 0;
-        switch (i) {  // direction table of Sec. III.C
-            case 1: ex = 1; ey = 0; w = 1.0 / 9.0; break;
-            case 2: ex = 0; ey = 1; w = 1.0 / 9.0; break;
-            case 3: ex = -1; ey = 0; w = 1.0 / 9.0; break;
-            case 4: ex = 0; ey = -1; w = 1.0 / 9.0; break;
-            case 5: ex = 1; ey = 1; w = 1.0 / 36.0; break;
-            case 6: ex = -1; ey = 1; w = 1.0 / 36.0; break;
-            case 7: ex = -1; ey = -1; w = 1.0 / 36.0; break;
-            default: ex = 1; ey = -1; w = 1.0 / 36.0; break;
-        }
-        // arm from the centre to the link midpoint x_f + e_i/2 (minimum image)
-        double rx = 0.0, ry = 0.0;
-        if (s > 0) {
-            rx = min_image(((double)x + 0.5 * ex) - X, a.nx);
-            ry = ((double)y + 0.5 * ey) - Y;
-            if (!a.walls) ry = min_image(ry, a.ny);
-        }
-        const double vx = vbx - om * ry, vy = vby + om * rx;
-        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
-        const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
+        const double ex = ex_(i), ey = ey_(i);
+        const LinkEval le = eval_link<T, GEO>(f, own_t, S, X, Y, vbx, vby, om, s, x, y, i, a);
+        const double av = le.av, bv = le.bv, vx = le.vx, vy = le.vy, rx = le.rx, ry = le.ry;
         // CME: e_i a - e_ibar b, e_ibar = -e_i
         const double cfx = ex * av + ex * bv;
         const double cfy = ey * av + ey * bv;
@@ -1047,7 +1140,7 @@ struct RoleCounts {
     int n_force, n_move, n_lead;
 };
 
-template <typename T, bool NT, bool MRT, bool ROT>
+template <typename T, bool NT, bool MRT, bool GEO>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fused(
     StepPtrs<T> p, int parity, RoleCounts rc, StepArgs sa, MoveArgs ma, ForceArgs fa,
     CollideParams<typename Sto<T>::C> cp) {
@@ -1060,12 +1153,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     if (b < rc.n_lead) {
         const int64_t t = p.tctr[parity];
         if (b < rc.n_force) {
-            force_role<T>(b, sh.f, p.fin, p.links_t, p.seg_cnt_t, p.seg_off, p.chunk_solid, p.chunk_start,
+            force_role<T, GEO>(b, sh.f, p.fin, p.own_t, p.links_t, p.seg_cnt_t, p.seg_off, p.chunk_solid, p.chunk_start,
                           p.sol, p.vtab, p.rtab, p.partial + (size_t)(t & 1) * fa.nchunks * 6, t, fa);
         } else if (b < rc.n_force + rc.n_move) {
-            move_role<T, MRT>(b - rc.n_force, dyn_lds, sh.m, p.fin, p.fout, p.own_t, p.own_n, p.links_n,
-                         p.seg_cnt_n, p.seg_off, p.seg_cap, p.sol, p.vtab, p.movers, p.tctr, parity, ma,
-                         cp, p.errflag);
+            move_role<T, MRT, GEO>(b - rc.n_force, dyn_lds, sh.m, p.fin, p.fout, p.own_t, p.own_n, p.links_n,
+                         p.seg_cnt_n, p.seg_off, p.seg_cap, p.sol, p.vtab, p.rtab, p.movers, p.tctr, parity,
+                         ma, cp, p.errflag);
         } else if (b == rc.n_force + rc.n_move) {
             // previous step's totals (its partials are complete: the
             // previous launch has ended); then advance the step counter
@@ -1076,8 +1169,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         }
         return;
     }
-    step_role<T, NT, MRT, ROT>((uint32_t)(b - rc.n_lead), gridDim.x - (uint32_t)rc.n_lead, p.fin, p.fout,
-                               p.own_t, p.vtab, p.rtab, sa, cp);
+    const int64_t t = GEO ? p.tctr[parity] : 0;
+    step_role<T, NT, MRT, GEO>((uint32_t)(b - rc.n_lead), gridDim.x - (uint32_t)rc.n_lead, p.fin, p.fout,
+                               p.own_t, p.vtab, p.rtab, p.sol, t, sa, cp);
 }
 
 // Free bodies after the step: two workgroups per body (part 0: Newton-Euler
@@ -1088,13 +1182,15 @@ __global__ __launch_bounds__(kBlock) void k_free(StepPtrs<T> p, int parity, Move
                                                  CollideParams<typename Sto<T>::C> cp) {
     extern __shared__ __align__(16) uint8_t dyn_lds[];
     __shared__ MoveShared<T> sm;
-    move_role<T, MRT>((int)blockIdx.x, dyn_lds, sm, p.fin, p.fout, p.own_t, p.own_n, p.links_n, p.seg_cnt_n,
-                      p.seg_off, p.seg_cap, p.sol, p.vtab, p.movers, p.tctr, parity, ma, cp, p.errflag, &fa);
+    move_role<T, MRT, true>((int)blockIdx.x, dyn_lds, sm, p.fin, p.fout, p.own_t, p.own_n, p.links_n, p.seg_cnt_n,
+                      p.seg_off, p.seg_cap, p.sol, p.vtab, p.rtab, p.movers, p.tctr, parity, ma, cp, p.errflag,
+                      &fa);
 }
 
 // Per-link force records of the current state (test and inspection path).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f,
+                                                         const uint8_t* __restrict__ own_t,
                                                          const uint32_t* __restrict__ links,
                                                          const int* __restrict__ seg_cnt,
                                                          const int* __restrict__ seg_off,
@@ -1102,28 +1198,23 @@ __global__ __launch_bounds__(kBlock) void k_link_records(const T* __restrict__ f
                                                          const SolidDev* __restrict__ sol,
                                                          const double* __restrict__ vt,
                                                          const double* __restrict__ rt,
-                                                         double* __restrict__ out, ForceArgs a) {
+                                                         double* __restrict__ out, int64_t t, ForceArgs a) {
     const int s = blockIdx.x;
     const int n = seg_cnt[s];
-    const uint32_t* L = links + seg_off[s];
-    const double om = rt[kRot * s], cx = rt[kRot * s + 1], cy = rt[kRot * s + 2];
+    const uint32_t* Lk = links + seg_off[s];
+    const double om = rt[kRot * s];
+    double X = 0.0, Y = 0.0;
+    if (s > 0) solid_centre(sol, rt, s, t, X, Y);
+    const SolidDev S = sol[s];
     for (int k = threadIdx.x; k < n; k += kBlock) {
-        const uint32_t code = L[k];
+        const uint32_t code = Lk[k];
         const int i = (int)(code & 15u);
         const uint32_t node = code >> 4;
         const int y = (int)(node / (uint32_t)a.nx);
         const int x = (int)(node - (uint32_t)y * (uint32_t)a.nx);
-        const double ex = ex_(i), ey = ey_(i), w = w_<double>(i);
-        double vx = vt[2 * s], vy = vt[2 * s + 1];
-        if (om != 0.0) {  // surface velocity of a spinning free body at the link midpoint
-            const double rx = min_image(((double)x + 0.5 * ex) - cx, a.nx);
-            double ry = ((double)y + 0.5 * ey) - cy;
-            if (!a.walls) ry = min_image(ry, a.ny);
-            vx -= om * ry;
-            vy += om * rx;
-        }
-        const double av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
-        const double bv = av - 6.0 * w * a.rho0 * (ex * vx + ey * vy);
+        const double ex = ex_(i), ey = ey_(i);
+        const LinkEval le = eval_link<T, true>(f, own_t, S, X, Y, vt[2 * s], vt[2 * s + 1], om, s, x, y, i, a);
+        const double av = le.av, bv = le.bv, vx = le.vx, vy = le.vy;
         double* r = out + 8 * (int64_t)(rec_off[s] + k);
         r[0] = x;
         r[1] = y;

@@ -99,6 +99,7 @@ _SIG = {
     "lbm_batch_set_active": (_I32, [_VP, _I32, _I32]),
     "lbm_init_poiseuille": (_I32, [_VP]),
     "lbm_set_collision": (_I32, [_VP, _I32, _VP]),
+    "lbm_set_boundary": (_I32, [_VP, _I32]),
     "lbm_set_free_body": (_I32, [_VP, _I32, ctypes.c_double, ctypes.c_double]),
     "lbm_set_gravity": (_I32, [_VP, ctypes.c_double, ctypes.c_double, _I32]),
     "lbm_body_state": (_I32, [_VP, _I32, _VP]),
@@ -342,6 +343,11 @@ def lbm_batch_init_poiseuille(b, case_id: int) -> None:
 
 
 LBM_BGK, LBM_MRT = 0, 1
+LBM_HALFWAY, LBM_INTERPOLATED = 0, 1
+
+
+def lbm_set_boundary(ctx, rule: int) -> None:
+    _check(load_library().lbm_set_boundary(ctx, int(rule)), ctx)
 # relaxation rates (s_e, s_eps, s_q) of the paper's MRT simulations (Sec. IV)
 PAPER_MRT_RATES = (1.64, 1.54, 1.9)
 
@@ -616,6 +622,10 @@ class Lattice:
 
     def set_gravity(self, G, scheme: int = 1) -> None:
         lbm_set_gravity(self.ctx, G[0], G[1], scheme)
+
+    def set_boundary(self, interpolated: bool = True) -> None:
+        """Interpolated (True) or half-way (False) bounce-back on body links."""
+        lbm_set_boundary(self.ctx, LBM_INTERPOLATED if interpolated else LBM_HALFWAY)
 
     def body_state(self, solid_id: int):
         """[X, Y, V_x, V_y, Omega] of a body at the current step."""

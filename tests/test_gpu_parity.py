@@ -39,10 +39,13 @@ def lbm_mod(torch_mod):
     return pkg
 
 
-def run_pair(oracle_mod, lbm_mod, case, steps, dtype="f64", chunks=1, mrt=None):
-    _say(f"{case['name']} {case['nx']}x{case['ny']} steps={steps} dtype={dtype} mrt={mrt}")
+def run_pair(oracle_mod, lbm_mod, case, steps, dtype="f64", chunks=1, mrt=None, ibb=False):
+    _say(f"{case['name']} {case['nx']}x{case['ny']} steps={steps} dtype={dtype} mrt={mrt} ibb={ibb}")
     lat = lbm_mod.Lattice(case, dtype=dtype, history_steps=max(steps, 1), mrt=mrt)
     osim = oracle_sim(oracle_mod, case, mrt=mrt)
+    if ibb:
+        lat.set_boundary(True)
+        osim.set_ibb(True)
     per = steps // chunks
     for _ in range(chunks):
         lat.step(per)
@@ -286,11 +289,15 @@ def test_mrt_poiseuille_gpu_and_collision_choice(lbm_mod):
 
 
 # --------------------------------------------------------------- free bodies (Sec. IV)
-def run_free_pair(oracle_mod, lbm_mod, case, steps, free, G, scheme, dtype="f64", chunks=2):
+def run_free_pair(oracle_mod, lbm_mod, case, steps, free, G, scheme, dtype="f64", chunks=2, ibb=False):
     """free: list of (solid_id, rho_s, omega0)."""
-    _say(f"{case['name']} {case['nx']}x{case['ny']} steps={steps} dtype={dtype} free={free} G={G} scheme={scheme}")
+    _say(f"{case['name']} {case['nx']}x{case['ny']} steps={steps} dtype={dtype} free={free} G={G} "
+         f"scheme={scheme} ibb={ibb}")
     lat = lbm_mod.Lattice(case, dtype=dtype, history_steps=max(steps, 1))
     osim = oracle_sim(oracle_mod, case)
+    if ibb:
+        lat.set_boundary(True)
+        osim.set_ibb(True)
     for sid, rho_s, om0 in free:
         lat.set_free(sid, rho_s, om0)
         osim.set_free(sid, rho_s, om0)
@@ -358,3 +365,120 @@ def test_free_body_api_guards(lbm_mod):
         lat.save()                  # checkpoints hold no free-body state
     st = lat.body_state(1)
     assert abs(st[0] - 30.3) < 1e-6 and abs(st[4]) < 1e-12
+
+
+# --------------------------------------------------------------- interpolated bounce-back (Sec. IV)
+def _ibb_bodies():
+    # off-grid centres, radii and faces: link fractions spread over (0, 1]
+    return [lc.disc(40.37, 30.81, 6.43), lc.box(90.62, 22.29, 5.71, 4.18, vx=0.01, vy=-0.005),
+            lc.disc(100.1, 47.6, 4.55, vx=-0.02)]
+
+
+def test_ibb_fixed_bodies_f64(oracle_mod, lbm_mod):
+    """Driven 128x64 channel, a disc and a box with off-grid surfaces (one
+    sliding), a third disc with a surface velocity: interpolated bounce-back,
+    3000 steps, FP64 fields within 1e-12 and forces within 1e-10."""
+    c = lc.make_case(128, 64, 0.7, walls_y=True, gx=2e-6, bodies=_ibb_bodies(), name="ibb_fixed")
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 3000, chunks=3, ibb=True)
+    compare_fields(lat, osim, 1e-12)
+    compare_forces(lat, osim, c, 1e-10)
+    # the rule is really on: the half-way run differs
+    hw = oracle_sim(oracle_mod, c)
+    hw.step(3000)
+    assert np.abs(hw.fields()[1] - osim.fields()[1]).max() > 1e-6
+
+
+def test_ibb_link_records(oracle_mod, lbm_mod):
+    """Per-link records (returning population, surface point, wall velocity)
+    of the interpolated rule match the oracle's link by link."""
+    c = lc.make_case(128, 64, 0.7, walls_y=True, gx=2e-5, bodies=_ibb_bodies(), name="ibb_links")
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 40, ibb=True)
+    rec = lat.link_forces().cpu().numpy()
+    osim.step(1)  # oracle records of step 40 = links of the GPU's current state
+    orec = osim.links()
+    key = lambda r: (r[:, 3] * 1e9 + r[:, 1] * 1e5 + r[:, 0] * 10 + r[:, 2])
+    rec = rec[np.argsort(key(rec))]
+    orec = orec[np.argsort(key(orec))]
+    assert rec.shape == orec.shape
+    np.testing.assert_array_equal(rec[:, :4], orec[:, :4])
+    err = np.abs(rec[:, 4:] - orec[:, 4:]).max()
+    _say(f"ibb link record max abs err {err:.3e} over {len(rec)} links")
+    assert err <= 1e-14
+
+
+def test_ibb_moving_bodies_f64(oracle_mod, lbm_mod):
+    """Translating discs with newborn refill (A1, A2, A3) under interpolated
+    bounce-back: the refill stencil streams with the same rule."""
+    bodies = [lc.disc(60.3, 30.2, 9.1, vx=0.043, moves=True),
+              lc.disc(180.7, 95.6, 7.4, vx=-0.031, vy=0.004, moves=True),
+              lc.box(130.2, 64.5, 6.3, 5.8),
+              lc.disc(30.5, 100.1, 6.6, vx=0.01)]
+    for refill in (0, 1, 2):
+        c = lc.make_case(256, 128, 0.7, walls_y=True, gx=2e-6, refill=refill, bodies=bodies,
+                         name=f"ibb_movers_refill{refill}")
+        steps = 1500 if refill == 0 else 400
+        lat, osim = run_pair(oracle_mod, lbm_mod, c, steps, chunks=3, ibb=True)
+        compare_fields(lat, osim, 1e-12)
+        compare_forces(lat, osim, c, 1e-10)
+
+
+def test_ibb_free_bodies_f64(oracle_mod, lbm_mod):
+    """Free discs under interpolated bounce-back: a sedimenting disc driven by
+    GME beside a fixed one, and a spinning disc (surface velocity and torque
+    arm at the true surface point)."""
+    bodies = [lc.disc(30.3, 15.2, 5.0, moves=True), lc.disc(70.5, 26.4, 4.0)]
+    c = lc.make_case(96, 40, 0.7, walls_y=True, bodies=bodies, name="ibb_sediment")
+    lat, osim = run_free_pair(oracle_mod, lbm_mod, c, 1000, [(1, 1.4, 0.0)], (2e-4, 0.0), 1, ibb=True)
+    compare_fields(lat, osim, 1e-12)
+    compare_forces(lat, osim, c, 1e-10)
+    compare_bodies(lat, osim, [1], 1e-9)
+    bodies = [lc.disc(40.6, 12.1, 6.0, vx=0.002, moves=True)]
+    c = lc.make_case(80, 48, 0.8, walls_y=True, bodies=bodies, refill=1, name="ibb_spinning")
+    lat, osim = run_free_pair(oracle_mod, lbm_mod, c, 600, [(1, 1.2, 3e-3)], (0.0, 5e-5), 0, ibb=True)
+    compare_fields(lat, osim, 1e-12)
+    compare_forces(lat, osim, c, 1e-10)
+    compare_bodies(lat, osim, [1], 1e-9)
+
+
+def test_ibb_mrt_translating_f64(oracle_mod, lbm_mod):
+    """MRT with interpolated bounce-back, cylinder translating with refill."""
+    c = lc.channel_cylinder("translating", steps=1500, r=5.3)
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, c["steps"], chunks=3, mrt=(1.64, 1.54, 1.9), ibb=True)
+    compare_fields(lat, osim, 1e-12)
+    compare_forces(lat, osim, c, 1e-10)
+
+
+def test_ibb_halfway_faces(lbm_mod):
+    """A box with half-integer faces has q = 1/2 on every link, where the
+    interpolated rule is half-way bounce-back: the two GPU runs agree to
+    rounding (they run differently compiled kernel variants, whose
+    floating-point contraction may differ; the oracle pins the reduction bit
+    for bit)."""
+    body = lc.box(60.5, 20.5, 8.0, 6.0, vx=0.02, vy=-0.01)
+    c = lc.make_case(128, 48, 0.7, walls_y=True, gx=2e-5, bodies=[body], name="ibb_halfway")
+    a = lbm_mod.Lattice(c, dtype="f64", history_steps=200)
+    b = lbm_mod.Lattice(c, dtype="f64", history_steps=200)
+    b.set_boundary(True)
+    a.step(200)
+    b.step(200)
+    fa, fb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+    ha, hb = a.force_history().cpu().numpy(), b.force_history().cpu().numpy()
+    df = np.abs(fa - fb).max()
+    dh = np.abs(ha - hb).max() / np.abs(ha).max()
+    _say(f"ibb(q=1/2) vs half-way: populations max abs diff {df:.3e}, forces rel {dh:.3e}")
+    assert df <= 1e-15 and dh <= 1e-13
+    with pytest.raises(lbm_mod.lbm.LBMError):
+        lbm_mod.lbm.lbm_set_boundary(a.ctx, 7)
+
+
+def test_ibb_f32_drag(oracle_mod, lbm_mod):
+    """FP32 offset storage with interpolated bounce-back: drag within 1e-5 of
+    the FP64 oracle."""
+    c = lc.channel_cylinder("rest", steps=3000, r=5.3)
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, c["steps"], dtype="f32", ibb=True)
+    h = lat.force_history().cpu().numpy()
+    oh = oracle_history(osim, 1)
+    for comp in (0, 3):
+        rel = np.abs(h[100:, 1, comp] - oh[100:, 1, comp]).max() / np.abs(oh[100:, 1, comp]).max()
+        _say(f"ibb f32 drag history rel err comp{comp} = {rel:.3e}")
+        assert rel <= 1e-5
