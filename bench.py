@@ -48,12 +48,14 @@ def stored_traffic(workload: str, kernel: str = "k_fused", family: str = "lbm"):
     return round(rec.get("hbm_bytes_per_launch"))
 
 
-def run_gpu(case, dtype, steps, warmup, torch, pkg, mrt=None):
+def run_gpu(case, dtype, steps, warmup, torch, pkg, mrt=None, ibb=False):
     """Warm up, time `steps` steps (whole-step throughput), then time another
     `steps` steps with HIP events attached to each time-step launch (kernel
     roofline).  The two passes are separate so that the event records do not
     perturb the throughput figure."""
     lat = pkg.Lattice(case, dtype=dtype, history_steps=2 * steps + warmup + 1, mrt=mrt)
+    if ibb:
+        lat.set_boundary(True)
     stream = lat.stream
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -115,7 +117,8 @@ def run_sedimentation(lc, pkg, torch, steps):
     = 4.03e-4 in lattice units.  Timed with GME driving the disc; then the
     paper's frame test: fluid, disc and walls given an extra V = 0.01 along
     the channel, and the trajectory relative to the channel (x - V t, y,
-    Omega) compared with the V = 0 run, for GME and for CME."""
+    Omega) compared with the V = 0 run, for GME and for CME, with half-way
+    and with interpolated bounce-back (the rule the paper runs with)."""
     nx, ny, r, rho_s, G = 1200, 120, 15.0, 1.03, 4.03e-4
 
     def case(V):
@@ -123,8 +126,10 @@ def run_sedimentation(lc, pkg, torch, steps):
         return lc.make_case(nx, ny, 0.6, walls_y=True, u0=(V, 0.0), wall_v=(V, 0.0), bodies=[body],
                             name=f"sediment_V{V}")
 
-    def run(V, scheme, timed=False):
+    def run(V, scheme, ibb=False):
         lat = pkg.Lattice(case(V), dtype="f64", history_steps=steps + 1)
+        if ibb:
+            lat.set_boundary(True)
         lat.set_free(1, rho_s)
         lat.set_gravity((G, 0.0), scheme)
         torch.cuda.synchronize()
@@ -136,15 +141,19 @@ def run_sedimentation(lc, pkg, torch, steps):
         return st, dt
 
     out = {"nx": nx, "ny": ny, "d": 2 * r, "rho_s": rho_s, "G": G, "tau": 0.6, "steps": steps, "dtype": "f64"}
-    for name, scheme in (("gme", 1), ("cme", 0)):
-        s0, dt0 = run(0.0, scheme)
-        s1, _ = run(0.01, scheme)
-        rel = [s1[0] - 0.01 * steps - s0[0], s1[1] - s0[1], s1[4] - s0[4]]
-        out[name] = {"state_V0": [round(v, 9) for v in s0],
-                     "frame_V0.01_minus_V0": {"x": rel[0], "y": rel[1], "omega": rel[2]}}
-        if scheme == 1:
-            out["ms_per_step"] = round(dt0 / steps * 1e3, 4)
-            out["mlups"] = round(nx * ny * steps / dt0 / 1e6, 1)
+    for ibb in (False, True):
+        dst = out
+        if ibb:
+            dst = out["interpolated_bounce_back"] = {}
+        for name, scheme in (("gme", 1), ("cme", 0)):
+            s0, dt0 = run(0.0, scheme, ibb)
+            s1, _ = run(0.01, scheme, ibb)
+            rel = [s1[0] - 0.01 * steps - s0[0], s1[1] - s0[1], s1[4] - s0[4]]
+            dst[name] = {"state_V0": [round(v, 9) for v in s0],
+                         "frame_V0.01_minus_V0": {"x": rel[0], "y": rel[1], "omega": rel[2]}}
+            if scheme == 1:
+                dst["ms_per_step"] = round(dt0 / steps * 1e3, 4)
+                dst["mlups"] = round(nx * ny * steps / dt0 / 1e6, 1)
     return out
 
 
@@ -196,6 +205,7 @@ def main() -> int:
     ap.add_argument("--no-batch-case", action="store_true")
     ap.add_argument("--no-mrt-case", action="store_true")
     ap.add_argument("--no-free-case", action="store_true")
+    ap.add_argument("--no-ibb-case", action="store_true")
     ap.add_argument("--free-steps", type=int, default=4000)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-warm-start", action="store_true")
@@ -266,6 +276,20 @@ def main() -> int:
             "achieved_GBs": round(ab3 / avg3 / 1e9, 1),
             "frac": round(ab3 / avg3 / 1e9 / HBM_PEAK_GBS, 4)}
         del lat3
+        torch.cuda.empty_cache()
+    if not args.no_ibb_case:
+        # the same workload with interpolated bounce-back on the cylinders
+        i_steps = min(args.steps, 2000)
+        lat4, tms4, ums4, n4, nf4 = run_gpu(case, args.dtype, i_steps, args.warmup, torch, pkg, ibb=True)
+        avg4 = ums4 / max(n4, 1) * 1e-3
+        ab4 = 18 * BYTES[args.dtype] * nf4
+        extra["ibb_" + wl] = {
+            "mlups": round(nx * ny * i_steps / (tms4 * 1e-3) / 1e6, 1),
+            "ms_per_step": round(tms4 / i_steps, 5),
+            "kernel_us": round(avg4 * 1e6, 3),
+            "achieved_GBs": round(ab4 / avg4 / 1e9, 1),
+            "frac": round(ab4 / avg4 / 1e9 / HBM_PEAK_GBS, 4)}
+        del lat4
         torch.cuda.empty_cache()
     if not args.no_free_case:
         extra["free_sedimentation_1200x120"] = run_sedimentation(lc, pkg, torch, args.free_steps)

@@ -338,7 +338,8 @@ lbm_status enqueue_step(lbm_ctx* c) {
     RoleCounts rc;
     rc.n_force = c->L.nchunks;
     rc.n_move = 2 * n_presc;  // geometry and refill workgroup per prescribed mover
-    rc.n_lead = (rc.n_force + rc.n_move + 1 + 7) / 8 * 8;
+    rc.n_bnd = c->ibb ? 2 * c->L.nchunks : 0;  // boundary role: two per link chunk
+    rc.n_lead = (rc.n_force + rc.n_move + 1 + rc.n_bnd + 7) / 8 * 8;
     MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
                 9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes, n_presc};
     ma.ibb = c->ibb;

@@ -110,11 +110,21 @@ __device__ inline T* row_at(T* base, uint32_t idx) {
 // only when a source node is solid (or a wall row) are they replaced by the
 // per-direction bounce-back values.  bid/nblk: this workgroup's index among
 // the update workgroups (remapped so that each XCD walks a contiguous band).
-template <typename T, bool NT, bool MRT = false, bool GEO = false>
+// The body whose link list a boundary workgroup walks: its record, centre
+// and spin at the step, loaded once per workgroup (a node's links into
+// another body look that one up).
+struct BndSolid {
+    SolidDev S;
+    double X, Y, om;
+    int s;
+};
+
+template <typename T, bool NT, bool MRT = false, bool GEO = false, bool BND = false>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
                                  const double* __restrict__ rtab, const SolidDev* __restrict__ sol, int64_t t,
-                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp);
+                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp,
+                                 const BndSolid* bs = nullptr);
 
 template <typename T, bool NT, bool MRT, bool GEO>
 __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restrict__ fin,
@@ -133,16 +143,18 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
 }
 
 // The update of node (x, y): pull, bounce-back, collide (BGK, or MRT when
-// MRT), store.  GEO: body links take their surface geometry into account:
-// the surface point of the link into solid sid is x - q e_i (q = 1/2, or the
-// link fraction under interpolated bounce-back), where a spinning free body
-// moves at V + Omega z x (x - q e_i - X); t is the step (centres of moving
-// bodies).
-template <typename T, bool NT, bool MRT, bool GEO>
+// MRT), store.  GEO: body links take their surface geometry into account: a
+// spinning free body moves at V + Omega z x (p - X) at the surface point p
+// of the link.  Under interpolated bounce-back (a.ibb) the nodes next to a
+// body are left to the boundary role (BND = true), which updates them with
+// the rule of ibb_value and p = x - q e_i; otherwise p is the link midpoint.
+// t is the step (centres of moving bodies).
+template <typename T, bool NT, bool MRT, bool GEO, bool BND>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
                                  const double* __restrict__ rtab, const SolidDev* __restrict__ sol, int64_t t,
-                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp) {
+                                 const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp,
+                                 const BndSolid* bs) {
     using C = typename Sto<T>::C;
 
     const int xm = x == 0 ? a.nx - 1 : x - 1;
@@ -185,7 +197,16 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
     raw[6] = ld_stream<NT>(row_at(rm + 6 * P, uxp));
     raw[7] = ld_stream<NT>(row_at(rp + 7 * P, uxp));
     raw[8] = ld_stream<NT>(row_at(rp + 8 * P, uxm));
+    // boundary role: the node's own populations, which the interpolated rule
+    // takes, are loaded with the streamed ones
+    T own9[9];
+    if constexpr (BND) {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) own9[i] = ld_stream<NT>(row_at(r0 + i * P, ux));
+    }
     if (self) return;  // solid at t (a newborn node is refilled by the mover role)
+    if constexpr (GEO && !BND)
+        if (a.ibb && (s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0) return;  // boundary role
     C d[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
@@ -200,14 +221,28 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
             const uint32_t sid = wall ? 0u : src[i];
             if (wall || sid != 0u) {
                 C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-                if constexpr (GEO) {
+                if constexpr (GEO && !BND) {
+                    const double om = rtab[kRot * sid];
+                    if (om != 0.0) {
+                        const double rx = min_image((double)x - 0.5 * ex_(i) - rtab[kRot * sid + 1], a.nx);
+                        double ry = (double)y - 0.5 * ey_(i) - rtab[kRot * sid + 2];
+                        if (!a.walls) ry = min_image(ry, a.ny);
+                        vx = (C)((double)vtab[2 * sid] - om * ry);
+                        vy = (C)((double)vtab[2 * sid + 1] + om * rx);
+                    }
+                }
+                if constexpr (BND) {
                     if (sid != 0u) {
-                        double X, Y;
-                        solid_centre(sol, rtab, (int)sid, t, X, Y);
-                        const double q = a.ibb ? link_fraction(sol[sid], X, Y, x, y, -ex_(i), -ey_(i), a.nx,
-                                                               a.ny, a.walls)
+                        double X = bs->X, Y = bs->Y, om = bs->om;
+                        const SolidDev* B = &bs->S;
+                        if ((int)sid != bs->s) {
+                            solid_centre(sol, rtab, (int)sid, t, X, Y);
+                            om = rtab[kRot * sid];
+                            B = &sol[sid];
+                        }
+                        const double q = a.ibb ? link_fraction(*B, X, Y, x, y, -ex_(i), -ey_(i), a.nx, a.ny,
+                                                               a.walls)
                                                : 0.5;
-                        const double om = rtab[kRot * sid];
                         if (om != 0.0) {
                             const double rx = min_image((double)x - q * ex_(i) - X, a.nx);
                             double ry = (double)y - q * ey_(i) - Y;
@@ -216,21 +251,14 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
                             vy = (C)((double)vtab[2 * sid + 1] + om * rx);
                         }
                         const C m = C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
-                        const C fo = Sto<T>::ld(*row_at(r0 + opp_(i) * P, ux));
-                        if (q == 0.5) {
-                            d[i] = fo + m;
-                        } else {
-                            // the node behind, x + e_i, is the source of the
-                            // opposite direction o; when it is fluid, d[o]
-                            // still holds the value streamed from it (only
-                            // directions with a solid or wall source are
-                            // replaced)
-                            const int o = opp_(i);
-                            const bool owall = (ey_(o) == 1 && wall_lo) || (ey_(o) == -1 && wall_hi);
-                            const bool behind = !owall && src[o] == 0u;
-                            const C fi = q > 0.5 ? Sto<T>::ld(*row_at(r0 + i * P, ux)) : C(0);
-                            d[i] = ibb_value<C>(q, fo, fi, d[o], behind, m);
-                        }
+                        // the node behind, x + e_i, is the source of the
+                        // opposite direction o; when it is fluid, d[o] still
+                        // holds the value streamed from it (only directions
+                        // with a solid or wall source are replaced)
+                        const int o = opp_(i);
+                        const bool owall = (ey_(o) == 1 && wall_lo) || (ey_(o) == -1 && wall_hi);
+                        const bool behind = !owall && src[o] == 0u;
+                        d[i] = ibb_value<C>(q, Sto<T>::ld(own9[o]), Sto<T>::ld(own9[i]), d[o], behind, m);
                         continue;
                     }
                 }
@@ -659,6 +687,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
         }
     } else {
         solid_pos(S, t - 1, Xa, Ya);
+        solid_pos(S, t, Xt, Yt);
         solid_pos(S, t + 1, Xn, Yn);
     }
     long x0, x1, y0, y1;
@@ -810,11 +839,33 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                 // surface point gx - q e_j of a body link (q = 1/2 unless
                 // interpolated), step t; a spinning free body moves there at
                 // V + Omega z x (point - centre)
+                const C fo = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]);
                 double q = 0.5;
+                C fi = C(0), fb = C(0);
+                bool behind = false;
                 if (GEO && sid != 0 && (a.ibb || fr)) {
+                    if (a.ibb) {
+                        // populations the rule may take, loaded before q is
+                        // known: the node's own one away from the surface and
+                        // the opposite one of the node behind, gx + e_j (in
+                        // the box: at most 4 nodes from the newborn node, like
+                        // the sources)
+                        fi = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx]);
+                        const int qb = qm + (ey_(j) * W + ex_(j));
+                        int bx, by;
+                        behind = ot[qb] == 0 && gidx(qb, bx, by);
+                        if (behind)
+                            fb = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)by * a.ystride + bx]);
+                    }
+                    // this body's record and centre are at hand; another
+                    // body's come from the tables
                     double X = Xt, Y = Yt;
-                    if (!(fr && sid == s)) solid_centre(sol, rt, sid, t, X, Y);
-                    if (a.ibb) q = link_fraction(sol[sid], X, Y, gx, gy, -ex_(j), -ey_(j), a.nx, a.ny, a.walls);
+                    const SolidDev* B = &S;
+                    if (sid != s) {
+                        solid_centre(sol, rt, sid, t, X, Y);
+                        B = &sol[sid];
+                    }
+                    if (a.ibb) q = link_fraction(*B, X, Y, gx, gy, -ex_(j), -ey_(j), a.nx, a.ny, a.walls);
                     const double om = rt[kRot * sid];
                     if (om != 0.0) {
                         const double rx = min_image((double)gx - q * ex_(j) - X, a.nx);
@@ -824,22 +875,8 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                         vy = (C)(vtab[2 * sid + 1] + om * rx);
                     }
                 }
-                const C fo = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]);
                 const C mw = C(6) * w_<C>(j) * rho0 * (C(ex_(j)) * vx + C(ey_(j)) * vy);
-                if (q == 0.5) {
-                    v = fo + mw;
-                } else {
-                    // the node behind, gx + e_j (in the box: at most 4 nodes
-                    // from the newborn node, like the sources)
-                    const int qb = qm + (ey_(j) * W + ex_(j));
-                    const bool behind = ot[qb] == 0;
-                    C fb = C(0), fi = C(0);
-                    int bx, by;
-                    if (behind && q < 0.5 && gidx(qb, bx, by))
-                        fb = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)by * a.ystride + bx]);
-                    if (q > 0.5) fi = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx]);
-                    v = ibb_value<C>(q, fo, fi, fb, behind, mw);
-                }
+                v = q == 0.5 ? fo + mw : ibb_value<C>(q, fo, fi, fb, behind, mw);
             } else {
                 int sx, sy;
                 gidx(qs, sx, sy);
@@ -1108,7 +1145,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 // One launch per time step: workgroups [0, n_force) are force chunks,
 // [n_force, n_force + n_move) are translating bodies, workgroup
 // n_force + n_move finalizes the previous step's forces and advances the step
-// counter, and from n_lead (a multiple of 8, so that update workgroup j sits
+// counter, the next n_bnd update the nodes next to bodies under interpolated
+// bounce-back, and from n_lead (a multiple of 8, so that update workgroup j sits
 // on XCD j % 8) on the fused update.  The roles read only step-t data and write disjoint outputs, so
 // the small latency-bound roles run alongside the bandwidth-bound update.
 template <typename T>
@@ -1138,10 +1176,43 @@ struct StepPtrs {
 
 struct RoleCounts {
     int n_force, n_move, n_lead;
+    int n_bnd = 0;  // boundary workgroups (interpolated bounce-back, two per force chunk)
 };
 
+// Boundary role (interpolated bounce-back): workgroup c takes the links of
+// force chunk c; each fluid node next to a body is updated once per link
+// list it appears in, by the thread holding its first link there (a node's
+// links are contiguous; a node next to two bodies is updated twice with
+// identical results).  Wall-only nodes stay with the update role.
+template <typename T, bool MRT>
+__device__ inline void boundary_role(int wg, const StepPtrs<T>& p, int64_t t, const StepArgs& a,
+                                     const CollideParams<typename Sto<T>::C>& cp) {
+    // two workgroups per force chunk: one link per thread
+    static_assert(kForceChunk == 2 * kBlock, "a force chunk is two workgroups of links");
+    const int c = wg >> 1;
+    const int s = p.chunk_solid[c];
+    if (s == 0) return;
+    const int k = p.chunk_start[c] + (wg & 1) * kBlock + (int)threadIdx.x;
+    BndSolid bs;
+    bs.S = p.sol[s];
+    bs.s = s;
+    solid_centre(p.sol, p.rtab, s, t, bs.X, bs.Y);
+    bs.om = p.rtab[kRot * s];
+    const uint32_t* L = p.links_t + p.seg_off[s];
+    if (k >= p.seg_cnt_t[s]) return;
+    const uint32_t node = L[k] >> 4;
+    if (k > 0 && (L[k - 1] >> 4) == node) return;
+    const int y = (int)(node / (uint32_t)a.nx);
+    const int x = (int)(node - (uint32_t)y * (uint32_t)a.nx);
+    step_node<T, false, MRT, true, true>(x, y, p.fin, p.fout, p.own_t, p.vtab, p.rtab, p.sol, t, a, cp, &bs);
+}
+
+// Register budget: 64 VGPRs (8 waves per SIMD) keep the bandwidth-bound
+// update at full occupancy; the geometry variant allows 128 (4 waves), since
+// its boundary and refill roles would otherwise spill, and spill traffic
+// lengthens their dependent chains under the update's saturated HBM.
 template <typename T, bool NT, bool MRT, bool GEO>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_fused(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GEO ? 4 : 8, 8))) void k_fused(
     StepPtrs<T> p, int parity, RoleCounts rc, StepArgs sa, MoveArgs ma, ForceArgs fa,
     CollideParams<typename Sto<T>::C> cp) {
     extern __shared__ __align__(16) uint8_t dyn_lds[];
@@ -1166,6 +1237,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 finalize_forces(p.partial + (size_t)((t - 1) & 1) * fa.nchunks * 6, p.solid_chunk0, p.hist,
                                 t - 1, fa);
             if (threadIdx.x == 0) p.tctr[parity ^ 1] = t + 1;
+        } else if constexpr (GEO) {
+            const int c = b - (rc.n_force + rc.n_move + 1);
+            if (c < rc.n_bnd) boundary_role<T, MRT>(c, p, t, sa, cp);
         }
         return;
     }
