@@ -9,7 +9,9 @@ shares no code with the GPU path.
 Method: Wen et al., arXiv:1303.0625 -- LBE collision/advection (Sec. II,
 Eqs. 1-3), Eq. 8 equilibrium, half-way bounce-back with the moving-boundary
 term (Sec. III.A), CME (Eq. 4) and GME (Eq. 5) link forces, total force and
-torque (Eqs. 6-7), newborn refill A1/A2/A3 (Sec. IV.B).
+torque (Eqs. 6-7), newborn refill A1/A2/A3 (Sec. IV.B); the D3Q19 step of
+Sec. IV.D (``lbm3d_oracle.c``, fixed geometry: spheres with a rigid surface
+motion in a tube or between planes).
 """
 from __future__ import annotations
 
@@ -21,6 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
+_SRC3 = os.path.join(_HERE, "lbm3d_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 DISC, BOX = 0, 1
@@ -37,9 +40,10 @@ W = (4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36)
 
 def build(force: bool = True) -> str:
     """Compile the oracle shared library with gcc; returns its path."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(p) for p in (_SRC, _SRC3))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
+               "-o", _LIB + ".tmp", _SRC, _SRC3, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -280,3 +284,123 @@ class OracleSim:
     def init_fields(self, rho, ux, uy) -> None:
         rho, ux, uy = (np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy))
         self._lib.orc_init_fields(self._h, _dp(rho), _dp(ux), _dp(uy))
+
+
+# ------------------------------------------------------------------ D3Q19 (Sec. IV.D)
+OPEN3, TUBE3, PLANES3 = 0, 1, 2
+# the oracle's velocity set: rest, six axis directions, twelve edge diagonals
+E3 = ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+      (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+      (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1))
+
+
+def _load3():
+    lib = _load()
+    if getattr(lib, "_orc3_bound", False):
+        return lib
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.orc3_create.restype = ctypes.c_void_p
+    lib.orc3_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp]
+    lib.orc3_destroy.argtypes = [ctypes.c_void_p]
+    lib.orc3_time.argtypes = [ctypes.c_void_p]
+    lib.orc3_time.restype = ctypes.c_long
+    lib.orc3_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
+    lib.orc3_fields.argtypes = [ctypes.c_void_p, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    lib.orc3_force.argtypes = [ctypes.c_void_p, ctypes.c_long, ctypes.c_int, ctypes.c_int, dp]
+    lib.orc3_force.restype = ctypes.c_int
+    lib.orc3_feq.argtypes = [ctypes.c_double, dp, dp]
+    lib.orc3_collide_node.argtypes = [dp, ctypes.c_double, dp, dp]
+    lib.orc3_link_force.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, dp]
+    lib.orc3_get_f.argtypes = [ctypes.c_void_p, dp]
+    lib.orc3_set_f.argtypes = [ctypes.c_void_p, dp]
+    lib._orc3_bound = True
+    return lib
+
+
+def _vec(v, n=3):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(n))
+
+
+def feq3(rho: float, u) -> np.ndarray:
+    out = np.zeros(19)
+    _load3().orc3_feq(float(rho), _dp(_vec(u)), _dp(out))
+    return out
+
+
+def collide_node3(f, tau: float, g=(0.0, 0.0, 0.0)) -> np.ndarray:
+    f = _vec(f, 19)
+    out = np.zeros(19)
+    _load3().orc3_collide_node(_dp(f), float(tau), _dp(_vec(g)), _dp(out))
+    return out
+
+
+def link_force3(i: int, a: float, b: float, v, scheme: int) -> np.ndarray:
+    out = np.zeros(3)
+    _load3().orc3_link_force(int(i), float(a), float(b), _dp(_vec(v)), int(scheme), _dp(out))
+    return out
+
+
+class OracleSim3D:
+    """One D3Q19 simulation held by the C oracle.  spheres: dicts with keys
+    cx, cy, cz, r and optional v (3), omega (3)."""
+
+    def __init__(self, nx, ny, nz, tau, *, rho0=1.0, g=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0),
+                 duct=OPEN3, R=0.0, spheres=()):
+        lib = _load3()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.ns = len(spheres)
+        rec = np.zeros((max(1, self.ns), 10))
+        for k, sp in enumerate(spheres):
+            rec[k, :4] = (sp["cx"], sp["cy"], sp["cz"], sp["r"])
+            rec[k, 4:7] = sp.get("v", (0.0, 0.0, 0.0))
+            rec[k, 7:10] = sp.get("omega", (0.0, 0.0, 0.0))
+        rec = np.ascontiguousarray(rec)
+        self._lib = lib
+        self._h = lib.orc3_create(self.nx, self.ny, self.nz, float(tau), float(rho0), _dp(_vec(g)),
+                                  _dp(_vec(u0)), int(duct), float(R), self.ns, _dp(rec))
+        if not self._h:
+            raise ValueError("oracle rejected the 3D configuration")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc3_destroy(h)
+            self._h = None
+
+    @property
+    def t(self) -> int:
+        return self._lib.orc3_time(self._h)
+
+    def step(self, n: int = 1) -> None:
+        self._lib.orc3_step(self._h, int(n))
+
+    def fields(self):
+        """rho [nz, ny, nx], u [3, nz, ny, nx] (Guo velocity), owner [nz, ny, nx]."""
+        shp = (self.nz, self.ny, self.nx)
+        rho = np.zeros(shp)
+        u = np.zeros((3,) + shp)
+        own = np.zeros(shp, dtype=np.int32)
+        self._lib.orc3_fields(self._h, _dp(rho), _dp(u), _ip(own))
+        return rho, u, own
+
+    def force(self, solid: int, scheme: int, step: int | None = None) -> np.ndarray:
+        """{F_x, F_y, F_z, T_x, T_y, T_z} of solid (0 duct, k sphere k)."""
+        out = np.zeros(6)
+        if step is None:
+            step = self.t - 1
+        if self._lib.orc3_force(self._h, int(step), int(solid), int(scheme), _dp(out)) != 0:
+            raise IndexError("no force record for that step/solid")
+        return out
+
+    def force_history(self, scheme: int) -> np.ndarray:
+        h = np.zeros((self.t, self.ns + 1, 6))
+        for st in range(self.t):
+            for s in range(self.ns + 1):
+                h[st, s] = self.force(s, scheme, st)
+        return h
+
+    def get_f(self) -> np.ndarray:
+        f = np.zeros((19, self.nz, self.ny, self.nx))
+        self._lib.orc3_get_f(self._h, _dp(f))
+        return f

@@ -1,0 +1,311 @@
+/* lbm3d_oracle.c -- plain FP64 CPU oracle of the three-dimensional
+ * momentum-exchange step (test infrastructure only; shares no code with the
+ * GPU library).
+ *
+ * Sec. IV.D carries the method over to three dimensions (a sphere in a tube
+ * Poiseuille flow).  This file is the D3Q19 version of the two-dimensional
+ * oracle's fixed-geometry step, in the same order:
+ *   collide   Eq. 2 (BGK) with the Eq. 8 equilibrium written for D3Q19 and
+ *             Guo's forcing for the body force g (ρu = Σ e_i f_i + ρg/2)
+ *   forces    Eq. 4 (CME) and Eq. 5 (GME) on every fluid-solid link from the
+ *             post-collision population a leaving the fluid node and the
+ *             bounced population b = a - 6 w_i ρ0 (e_i . v), summed per solid
+ *             (Eq. 6) with the torque r x F about the sphere's centre (Eq. 7),
+ *             r from the centre to the link midpoint
+ *   advect    Eq. 3; a population whose source node is solid is the half-way
+ *             bounce-back of the node's own opposite population plus
+ *             6 w_i ρ0 (e_i . v), v the surface velocity at the link midpoint
+ * Geometry is fixed: spheres carry a rigid surface motion V + Ω x (p - X) but
+ * do not move; the duct is a circular tube along x (nodes farther than R from
+ * the axis are solid), two solid planes z = 0 and z = nz - 1, or nothing.
+ * Every axis is periodic (the duct walls are solid nodes).  Summation orders
+ * are fixed: nodes in (z, y, x) order, directions in index order.
+ *
+ * Velocity set: rest, the six axis directions, the twelve edge diagonals;
+ * weights 1/3, 1/18, 1/36 (the D3Q19 weights for which the equilibrium's
+ * second moment is ρ/3 I + ρ u u, pinned in the tests).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "lbm3d_oracle.h"
+
+static const int E[19][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                             {0, 0, 1},   {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                             {-1, 1, 0},  {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                             {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static double weight(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+static int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+struct orc3_sim {
+    int nx, ny, nz;
+    double tau, rho0, g[3];
+    int duct;
+    double R;
+    int ns;
+    double* sp;  /* ns x 10: X[3], r, V[3], Om[3] */
+    unsigned char* own;
+    double *f, *ft, *fn; /* [19][nz][ny][nx] */
+    long t;
+    double* hist; /* per step (ns + 1) x 12: CME F, T, GME F, T */
+    long hist_cap;
+};
+
+static long nidx(const orc3_sim* s, int x, int y, int z) {
+    return ((long)z * s->ny + y) * s->nx + x;
+}
+static long pidx(const orc3_sim* s, int i, int x, int y, int z) {
+    return (long)i * s->nx * s->ny * s->nz + nidx(s, x, y, z);
+}
+static int wrap(int a, int n) { return ((a % n) + n) % n; }
+static double min_image(double d, int n) { return d - (double)n * floor(d / (double)n + 0.5); }
+
+/* Solid membership: the duct first, then the spheres (minimum image). */
+static int classify(const orc3_sim* s, int x, int y, int z, int* overlap) {
+    int duct = 0;
+    if (s->duct == ORC3_TUBE) {
+        double dy = (double)y - 0.5 * (s->ny - 1), dz = (double)z - 0.5 * (s->nz - 1);
+        duct = dy * dy + dz * dz > s->R * s->R;
+    } else if (s->duct == ORC3_PLANES) {
+        duct = (z == 0 || z == s->nz - 1);
+    }
+    int owner = duct ? 255 : 0;
+    for (int k = 0; k < s->ns; ++k) {
+        const double* p = s->sp + 10 * k;
+        double dx = min_image((double)x - p[0], s->nx);
+        double dy = min_image((double)y - p[1], s->ny);
+        double dz = min_image((double)z - p[2], s->nz);
+        if (dx * dx + dy * dy + dz * dz <= p[3] * p[3]) {
+            if (owner != 0) *overlap = 1;
+            owner = k + 1;
+        }
+    }
+    return owner;
+}
+
+/* Rigid surface velocity of solid `owner` at point (px, py, pz); the duct
+ * is at rest. */
+static void surface_velocity(const orc3_sim* s, int owner, double px, double py, double pz, double v[3],
+                             double r[3]) {
+    v[0] = v[1] = v[2] = 0.0;
+    r[0] = r[1] = r[2] = 0.0;
+    if (owner == 255 || owner == 0) return;
+    const double* p = s->sp + 10 * (owner - 1);
+    r[0] = min_image(px - p[0], s->nx);
+    r[1] = min_image(py - p[1], s->ny);
+    r[2] = min_image(pz - p[2], s->nz);
+    const double* V = p + 4;
+    const double* Om = p + 7;
+    v[0] = V[0] + (Om[1] * r[2] - Om[2] * r[1]);
+    v[1] = V[1] + (Om[2] * r[0] - Om[0] * r[2]);
+    v[2] = V[2] + (Om[0] * r[1] - Om[1] * r[0]);
+}
+
+void orc3_feq(double rho, const double u[3], double out[19]) {
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < 19; ++i) {
+        double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+        out[i] = rho * weight(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+}
+
+void orc3_collide_node(const double f[19], double tau, const double g[3], double out[19]) {
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+        rho += f[i];
+        for (int d = 0; d < 3; ++d) j[d] += E[i][d] * f[i];
+    }
+    double u[3], F[3];
+    for (int d = 0; d < 3; ++d) {
+        F[d] = rho * g[d];
+        u[d] = (j[d] + 0.5 * F[d]) / rho;
+    }
+    double feq[19];
+    orc3_feq(rho, u, feq);
+    for (int i = 0; i < 19; ++i) {
+        double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+        double src = 0.0;
+        for (int d = 0; d < 3; ++d) src += (3.0 * (E[i][d] - u[d]) + 9.0 * eu * E[i][d]) * F[d];
+        out[i] = f[i] - (f[i] - feq[i]) / tau + (1.0 - 0.5 / tau) * weight(i) * src;
+    }
+}
+
+void orc3_link_force(int i, double a, double b, const double v[3], int scheme, double out[3]) {
+    for (int d = 0; d < 3; ++d) {
+        if (scheme == ORC3_CME)
+            out[d] = E[i][d] * a + E[i][d] * b; /* e_i a - e_ibar b */
+        else
+            out[d] = (E[i][d] - v[d]) * a + (E[i][d] + v[d]) * b; /* (e_i - v) a - (e_ibar - v) b */
+    }
+}
+
+orc3_sim* orc3_create(int nx, int ny, int nz, double tau, double rho0, const double g[3], const double u0[3],
+                      int duct, double R, int ns, const double* spheres) {
+    if (nx < 2 || ny < 2 || nz < 2 || !(tau > 0.5) || ns < 0 || ns > 200) return NULL;
+    orc3_sim* s = (orc3_sim*)calloc(1, sizeof(orc3_sim));
+    s->nx = nx;
+    s->ny = ny;
+    s->nz = nz;
+    s->tau = tau;
+    s->rho0 = rho0;
+    for (int d = 0; d < 3; ++d) s->g[d] = g[d];
+    s->duct = duct;
+    s->R = R;
+    s->ns = ns;
+    s->sp = (double*)malloc(sizeof(double) * 10 * (ns > 0 ? ns : 1));
+    if (ns > 0) memcpy(s->sp, spheres, sizeof(double) * 10 * ns);
+    long N = (long)nx * ny * nz;
+    s->own = (unsigned char*)calloc((size_t)N, 1);
+    s->f = (double*)calloc((size_t)(19 * N), sizeof(double));
+    s->ft = (double*)calloc((size_t)(19 * N), sizeof(double));
+    s->fn = (double*)calloc((size_t)(19 * N), sizeof(double));
+    int overlap = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) s->own[nidx(s, x, y, z)] = (unsigned char)classify(s, x, y, z, &overlap);
+    if (overlap) {
+        orc3_destroy(s);
+        return NULL;
+    }
+    double fe[19];
+    orc3_feq(rho0, u0, fe);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                if (s->own[nidx(s, x, y, z)] == 0)
+                    for (int i = 0; i < 19; ++i) s->f[pidx(s, i, x, y, z)] = fe[i];
+    return s;
+}
+
+void orc3_destroy(orc3_sim* s) {
+    if (!s) return;
+    free(s->sp);
+    free(s->own);
+    free(s->f);
+    free(s->ft);
+    free(s->fn);
+    free(s->hist);
+    free(s);
+}
+
+long orc3_time(const orc3_sim* s) { return s->t; }
+
+static double* hist_row(orc3_sim* s, long t) {
+    const long row = (long)(s->ns + 1) * 12;
+    if (t >= s->hist_cap) {
+        long cap = s->hist_cap ? 2 * s->hist_cap : 64;
+        while (cap <= t) cap *= 2;
+        s->hist = (double*)realloc(s->hist, sizeof(double) * (size_t)(cap * row));
+        s->hist_cap = cap;
+    }
+    return s->hist + t * row;
+}
+
+static void one_step(orc3_sim* s) {
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    /* collide */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (s->own[nidx(s, x, y, z)] != 0) continue;
+                double fl[19], out[19];
+                for (int i = 0; i < 19; ++i) fl[i] = s->f[pidx(s, i, x, y, z)];
+                orc3_collide_node(fl, s->tau, s->g, out);
+                for (int i = 0; i < 19; ++i) s->ft[pidx(s, i, x, y, z)] = out[i];
+            }
+    /* forces on every fluid-solid link */
+    double* h = hist_row(s, s->t);
+    memset(h, 0, sizeof(double) * (size_t)(s->ns + 1) * 12);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (s->own[nidx(s, x, y, z)] != 0) continue;
+                for (int i = 1; i < 19; ++i) {
+                    int xb = wrap(x + E[i][0], nx), yb = wrap(y + E[i][1], ny), zb = wrap(z + E[i][2], nz);
+                    int o = s->own[nidx(s, xb, yb, zb)];
+                    if (o == 0) continue;
+                    double v[3], r[3];
+                    surface_velocity(s, o, x + 0.5 * E[i][0], y + 0.5 * E[i][1], z + 0.5 * E[i][2], v, r);
+                    double a = s->ft[pidx(s, i, x, y, z)];
+                    double b = a - 6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
+                    double* hs = h + 12 * (o == 255 ? 0 : o);
+                    for (int sch = 0; sch < 2; ++sch) {
+                        double F[3];
+                        orc3_link_force(i, a, b, v, sch, F);
+                        double* hh = hs + 6 * sch;
+                        for (int d = 0; d < 3; ++d) hh[d] += F[d];
+                        if (o != 255) {
+                            hh[3] += r[1] * F[2] - r[2] * F[1];
+                            hh[4] += r[2] * F[0] - r[0] * F[2];
+                            hh[5] += r[0] * F[1] - r[1] * F[0];
+                        }
+                    }
+                }
+            }
+    /* advect with half-way bounce-back */
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (s->own[nidx(s, x, y, z)] != 0) continue;
+                for (int i = 0; i < 19; ++i) {
+                    int xs = wrap(x - E[i][0], nx), ys = wrap(y - E[i][1], ny), zs = wrap(z - E[i][2], nz);
+                    int o = s->own[nidx(s, xs, ys, zs)];
+                    double val;
+                    if (o == 0) {
+                        val = s->ft[pidx(s, i, xs, ys, zs)];
+                    } else {
+                        double v[3], r[3];
+                        surface_velocity(s, o, x - 0.5 * E[i][0], y - 0.5 * E[i][1], z - 0.5 * E[i][2], v, r);
+                        val = s->ft[pidx(s, opposite(i), x, y, z)] +
+                              6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
+                    }
+                    s->fn[pidx(s, i, x, y, z)] = val;
+                }
+            }
+    double* tmp = s->f;
+    s->f = s->fn;
+    s->fn = tmp;
+    s->t += 1;
+}
+
+void orc3_step(orc3_sim* s, long n) {
+    for (long k = 0; k < n; ++k) one_step(s);
+}
+
+void orc3_fields(const orc3_sim* s, double* rho, double* u, int* owner) {
+    const long N = (long)s->nx * s->ny * s->nz;
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                long n = nidx(s, x, y, z);
+                int o = s->own[n];
+                double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+                if (o == 0)
+                    for (int i = 0; i < 19; ++i) {
+                        double fi = s->f[pidx(s, i, x, y, z)];
+                        r += fi;
+                        for (int d = 0; d < 3; ++d) j[d] += E[i][d] * fi;
+                    }
+                if (rho) rho[n] = r;
+                if (u)
+                    for (int d = 0; d < 3; ++d) u[d * N + n] = o == 0 ? (j[d] + 0.5 * r * s->g[d]) / r : 0.0;
+                if (owner) owner[n] = o;
+            }
+}
+
+int orc3_force(const orc3_sim* s, long step, int solid, int scheme, double out[6]) {
+    if (step < 0 || step >= s->t || solid < 0 || solid > s->ns) return -1;
+    const double* h = s->hist + (step * (s->ns + 1) + solid) * 12 + 6 * (scheme == ORC3_CME ? 0 : 1);
+    for (int d = 0; d < 6; ++d) out[d] = h[d];
+    return 0;
+}
+
+void orc3_get_f(const orc3_sim* s, double* out) {
+    memcpy(out, s->f, sizeof(double) * 19 * (size_t)s->nx * s->ny * s->nz);
+}
+
+void orc3_set_f(orc3_sim* s, const double* in) {
+    memcpy(s->f, in, sizeof(double) * 19 * (size_t)s->nx * s->ny * s->nz);
+}

@@ -1,0 +1,44 @@
+/* lbm3d_oracle.h -- FP64 CPU oracle of the D3Q19 momentum-exchange step
+ * (test infrastructure only).  Sec. IV.D: the method in three dimensions. */
+#pragma once
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC3_CME = 0, ORC3_GME = 1 };
+enum { ORC3_OPEN = 0, ORC3_TUBE = 1, ORC3_PLANES = 2 };
+
+typedef struct orc3_sim orc3_sim;
+
+/* nx x ny x nz periodic lattice, BGK relaxation time tau, reference density
+ * rho0, body force (acceleration) g, initial velocity u0 (f = f_eq(rho0, u0)).
+ * duct: ORC3_TUBE (nodes with (y - (ny-1)/2)^2 + (z - (nz-1)/2)^2 > R^2 are
+ * solid), ORC3_PLANES (z = 0 and z = nz - 1 solid) or ORC3_OPEN.  spheres:
+ * ns records {X, Y, Z, r, Vx, Vy, Vz, Omx, Omy, Omz} (fixed geometry, rigid
+ * surface motion).  NULL when a sphere touches the duct or another sphere. */
+orc3_sim* orc3_create(int nx, int ny, int nz, double tau, double rho0, const double g[3], const double u0[3],
+                      int duct, double R, int ns, const double* spheres);
+void orc3_destroy(orc3_sim* s);
+long orc3_time(const orc3_sim* s);
+void orc3_step(orc3_sim* s, long n);
+
+/* rho[N], u[3][N] (Guo velocity) and owner[N] (0 fluid, k sphere k, 255
+ * duct), N = nx ny nz in (z, y, x) order. */
+void orc3_fields(const orc3_sim* s, double* rho, double* u, int* owner);
+
+/* {F, T} of solid `solid` (0 the duct, k sphere k) at step `step` for
+ * scheme ORC3_CME / ORC3_GME; -1 out of range. */
+int orc3_force(const orc3_sim* s, long step, int solid, int scheme, double out[6]);
+
+void orc3_feq(double rho, const double u[3], double out[19]);
+void orc3_collide_node(const double f[19], double tau, const double g[3], double out[19]);
+void orc3_link_force(int i, double a, double b, const double v[3], int scheme, double out[3]);
+
+/* pre-collision populations [19][nz][ny][nx] */
+void orc3_get_f(const orc3_sim* s, double* out);
+void orc3_set_f(orc3_sim* s, const double* in);
+
+#ifdef __cplusplus
+}
+#endif

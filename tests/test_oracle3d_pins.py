@@ -1,0 +1,174 @@
+"""Pins of the D3Q19 oracle (Sec. IV.D: the method in three dimensions).
+
+As for the two-dimensional oracle, none of these re-types the oracle's
+formulas: each compares it with a closed form, an exact invariant or a
+reduction to a case whose solution is known.
+"""
+import numpy as np
+import pytest
+
+# The D3Q19 set written out independently here: rest, axis directions, edges.
+E = np.array([(0, 0, 0)] + [(s * (d == 0), s * (d == 1), s * (d == 2)) for d in range(3) for s in (1, -1)]
+             + [tuple(v) for v in ((1, 1, 0), (1, -1, 0), (-1, 1, 0), (-1, -1, 0), (1, 0, 1), (1, 0, -1),
+                                   (-1, 0, 1), (-1, 0, -1), (0, 1, 1), (0, 1, -1), (0, -1, 1), (0, -1, -1))])
+WT = {0: 1 / 3, 1: 1 / 18, 2: 1 / 36}  # by |e|^2
+
+
+def _lookup(oracle_mod):
+    """Map the oracle's velocity order onto the set above (the oracle must use
+    the same nineteen vectors, in any order)."""
+    order = [int(np.nonzero((E == np.array(v)).all(axis=1))[0][0]) for v in oracle_mod.E3]
+    assert sorted(order) == list(range(19))
+    return np.array(oracle_mod.E3), np.array([WT[int(np.dot(v, v))] for v in oracle_mod.E3])
+
+
+def test_equilibrium_moments_3d(oracle_mod):
+    """Eq. 8 on D3Q19: mass, momentum and the Euler stress rho/3 I + rho u u."""
+    e, w = _lookup(oracle_mod)
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        rho = rng.uniform(0.5, 1.5)
+        u = rng.uniform(-0.15, 0.15, 3)
+        f = oracle_mod.feq3(rho, u)
+        assert abs(f.sum() - rho) <= 4e-15
+        assert np.abs(e.T @ f - rho * u).max() <= 4e-15
+        P = (e[:, :, None] * e[:, None, :] * f[:, None, None]).sum(0)
+        assert np.abs(P - (rho / 3 * np.eye(3) + rho * np.outer(u, u))).max() <= 4e-15
+
+
+def test_collision_conserves_mass_adds_momentum_3d(oracle_mod):
+    """BGK + Guo: mass is conserved and the momentum gains exactly rho g."""
+    e, _ = _lookup(oracle_mod)
+    rng = np.random.default_rng(12)
+    for tau in (0.55, 0.8, 1.7):
+        f = oracle_mod.feq3(1.02, (0.03, -0.02, 0.01)) + rng.normal(0, 1e-3, 19)
+        g = rng.normal(0, 1e-4, 3)
+        out = oracle_mod.collide_node3(f, tau, g)
+        assert abs(out.sum() - f.sum()) <= 1e-15
+        assert np.abs(e.T @ out - (e.T @ f + f.sum() * g)).max() <= 1e-16
+
+
+def test_link_force_closed_forms_3d(oracle_mod):
+    """Eq. 9 on every D3Q19 link for a surface moving along x at U, with the
+    equilibrium population a = f_eq,i(rho, v) and the bounced b: the GME
+    x-force is the rest value 2 w_i rho e_ix, the CME one is (1 + 3U^2) times
+    it (links with e_ix != 0); at rest both equal 2 w_i rho e_i."""
+    e, w = _lookup(oracle_mod)
+    rho, U = 1.03, 0.07
+    for v in ((U, 0.0, 0.0), (0.0, 0.0, 0.0)):
+        fe = oracle_mod.feq3(rho, v)
+        for i in range(1, 19):
+            a = fe[i]
+            b = a - 6 * w[i] * rho * np.dot(e[i], v)
+            gme = oracle_mod.link_force3(i, a, b, v, oracle_mod.GME)
+            cme = oracle_mod.link_force3(i, a, b, v, oracle_mod.CME)
+            if v[0] == 0.0:
+                assert np.abs(gme - 2 * w[i] * rho * e[i]).max() <= 1e-16
+                assert np.abs(cme - gme).max() == 0.0
+            elif e[i, 0] != 0:
+                assert abs(gme[0] - 2 * w[i] * rho * e[i, 0]) <= 1e-16
+                assert abs(cme[0] - 2 * w[i] * rho * e[i, 0] * (1 + 3 * U * U)) <= 1e-16
+
+
+@pytest.mark.parametrize("tau,steps", [(0.6, 40000), (1.0, 14000)])
+def test_planes_poiseuille_exact_3d(oracle_mod, tau, steps):
+    """Between the solid planes z = 0 and z = nz - 1 a y-invariant flow is the
+    D2Q9 problem (summing D3Q19 over e_y gives D2Q9's weights and
+    equilibrium), so the exact discrete Poiseuille solution of half-way
+    bounce-back with Guo forcing holds: u(z) = g/(2nu)(Z^2 - (z - z_c)^2) + s,
+    s = g [4(2tau-1)^2 - 3] / (4(2tau-1)), Z = (nz - 2)/2, z_c = (nz - 1)/2.
+    The planes carry the body force, and no lateral flow appears."""
+    nz, g = 14, 1e-5
+    s = oracle_mod.OracleSim3D(2, 3, nz, tau, g=(g, 0.0, 0.0), duct=oracle_mod.PLANES3)
+    s.step(steps)
+    rho, u, own = s.fields()
+    nu = (tau - 0.5) / 3
+    z = np.arange(nz)
+    slip = g * (4 * (2 * tau - 1) ** 2 - 3) / (4 * (2 * tau - 1))
+    exact = g / (2 * nu) * (((nz - 2) / 2) ** 2 - (z - (nz - 1) / 2) ** 2) + slip
+    fl = own[:, 0, 0] == 0
+    assert np.abs(u[0][:, 1, 1] - exact)[fl].max() / exact.max() <= 1e-10
+    assert np.abs(u[1:]).max() <= 1e-11 * exact.max()  # rounding only
+    F = s.force(0, oracle_mod.CME)
+    assert abs(F[0] - g * rho.sum()) <= 1e-9 * g * rho.sum()
+
+
+def test_comoving_sphere_uniform_flow_3d(oracle_mod):
+    """A sphere whose surface moves with the uniform flow f_eq(1, U) leaves
+    the state exactly unchanged and feels no force (fixed geometry)."""
+    U = np.array([0.04, -0.015, 0.02])
+    sp = dict(cx=9.3, cy=8.6, cz=7.8, r=4.2, v=tuple(U))
+    s = oracle_mod.OracleSim3D(20, 18, 16, 0.7, u0=tuple(U), spheres=[sp])
+    fe = oracle_mod.feq3(1.0, U)
+    s.step(15)
+    f = s.get_f()
+    _, _, own = s.fields()
+    assert np.abs(f[:, own == 0] - fe[:, None]).max() <= 1e-15
+    for sch in (oracle_mod.CME, oracle_mod.GME):
+        assert np.abs(s.force(1, sch)[:3]).max() <= 1e-13
+
+
+def _momentum(f, e):
+    return np.tensordot(e.T, f, axes=(1, 0)).reshape(3, -1).sum(1)
+
+
+def test_momentum_balance_3d(oracle_mod):
+    """Fixed geometry: P(t+1) - P(t) = g sum(rho) - sum_s F_CME,s every step
+    (every bounce-back link removes exactly the conventional exchange), with a
+    tube, a translating-surface and spinning sphere and a body force; mass is
+    constant."""
+    e, _ = _lookup(oracle_mod)
+    g = np.array([3e-5, -1e-5, 2e-5])
+    sp = dict(cx=8.4, cy=7.2, cz=7.9, r=3.1, v=(0.02, 0.01, -0.005), omega=(0.003, -0.002, 0.004))
+    s = oracle_mod.OracleSim3D(18, 16, 16, 0.7, g=tuple(g), duct=oracle_mod.TUBE3, R=6.8, spheres=[sp])
+    s.step(10)
+    f = s.get_f()
+    M0 = f.sum()
+    for _ in range(12):
+        P0 = _momentum(f, e)
+        rho, _, _ = s.fields()
+        s.step(1)
+        f = s.get_f()
+        expect = g * rho.sum() - s.force(0, oracle_mod.CME)[:3] - s.force(1, oracle_mod.CME)[:3]
+        assert np.abs(_momentum(f, e) - P0 - expect).max() <= 1e-14 * M0
+        assert abs(f.sum() - M0) <= 1e-13 * M0
+
+
+def test_gme_equals_cme_at_rest_and_symmetry_3d(oracle_mod):
+    """A sphere at rest on the axis of a tube Poiseuille flow: with no surface
+    motion GME and CME coincide bit for bit, and the mirror symmetries of the
+    geometry about the axis leave no lateral force and no torque."""
+    ny = nz = 15
+    sp = dict(cx=9.0, cy=(ny - 1) / 2, cz=(nz - 1) / 2, r=3.0)
+    s = oracle_mod.OracleSim3D(20, ny, nz, 0.8, g=(2e-5, 0.0, 0.0), duct=oracle_mod.TUBE3, R=6.5, spheres=[sp])
+    s.step(300)
+    for k in (0, 1):
+        c, g_ = s.force(k, oracle_mod.CME), s.force(k, oracle_mod.GME)
+        assert np.array_equal(c, g_)
+    F = s.force(1, oracle_mod.CME)
+    assert F[0] > 0
+    # rounding of sums over a few hundred links of size ~rho w_i
+    assert np.abs(F[1:3]).max() <= 1e-12 * F[0]
+    assert np.abs(F[3:]).max() <= 1e-12 * F[0]
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_spinning_sphere_torque_opposes_spin_3d(oracle_mod, axis):
+    """A sphere spinning about a lattice axis in fluid at rest: the fluid
+    resists, T . Omega < 0, the torque lies along the spin axis, and by the
+    cubic symmetry of lattice and sphere its magnitude is the same about every
+    axis; no net force."""
+    om = np.zeros(3)
+    om[axis] = 0.004
+    sp = dict(cx=10.0, cy=10.0, cz=10.0, r=4.0, omega=tuple(om))
+    s = oracle_mod.OracleSim3D(21, 21, 21, 0.8, spheres=[sp])
+    s.step(40)
+    ref = oracle_mod.OracleSim3D(21, 21, 21, 0.8, spheres=[dict(sp, omega=(0.0, 0.0, 0.004))])
+    ref.step(40)
+    for sch in (oracle_mod.CME, oracle_mod.GME):
+        F = s.force(1, sch)
+        assert np.dot(F[3:], om) < 0
+        others = [F[3 + d] for d in range(3) if d != axis]
+        assert abs(F[3 + axis]) > 1e3 * max(abs(o) for o in others)
+        assert abs(F[3 + axis] - ref.force(1, sch)[5]) <= 1e-12 * abs(F[3 + axis])
+        assert np.abs(F[:3]).max() <= 1e-14
