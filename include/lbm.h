@@ -527,6 +527,97 @@ void lbm_nn_destroy(lbm_nn* nn);
  * lbm_nn_create / lbm_nn_workspace_bytes in this thread. */
 const char* lbm_nn_last_error(const lbm_nn* nn);
 
+/* ------------------------------------------------------------------------
+ * Three dimensions (Sec. IV.D): the D3Q19 step with the same boundary and
+ * force evaluation, fixed geometry.
+ *
+ * Velocity set: rest, the six axis directions and the twelve edge diagonals,
+ * weights 1/3, 1/18, 1/36.  Every axis is periodic.  The duct is a circular
+ * tube along x (nodes with (y - (ny-1)/2)^2 + (z - (nz-1)/2)^2 > R^2 are
+ * solid), the two planes z = 0 and z = nz - 1, or nothing; spheres are solid
+ * where (minimum-image) |p - X|^2 <= r^2, each product and sum rounded
+ * separately, and their surfaces move rigidly at V + omega x (p - X) without
+ * the geometry moving.  One step: the CME (Eq. 4) and GME (Eq. 5) forces of
+ * every fluid-solid link from the post-collision populations with the torque
+ * (Eq. 7) about each sphere's centre at the link midpoint, summed per solid
+ * in a fixed order (Eq. 6); pull streaming with half-way bounce-back plus
+ * 6 w_i rho0 (e_i . v) (v at the link midpoint); BGK collision (Eq. 2) with
+ * the Eq. 8 equilibrium and Guo forcing for the body force g.  Storage:
+ * LBM_F64 or LBM_F32 deviations f_i - w_i rho0, arithmetic in FP64.  The
+ * caller owns the device workspace and the stream; nothing is allocated on
+ * the device by the library.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm3d_ctx lbm3d_ctx; /* opaque; lbm3d_create / lbm3d_destroy */
+
+typedef enum { LBM3D_OPEN = 0, LBM3D_TUBE = 1, LBM3D_PLANES = 2 } lbm3d_duct;
+
+typedef struct {
+    int32_t nx, ny, nz;   /* lattice size, each >= 4, nx ny nz < 2^27 */
+    int32_t dtype;        /* LBM_F64 or LBM_F32 */
+    int32_t duct;         /* lbm3d_duct */
+    int32_t reserved;     /* must be 0 */
+    double R;             /* tube radius (LBM3D_TUBE), >= 2 */
+    double tau;           /* BGK relaxation time, > 1/2 */
+    double rho0;          /* reference and initial density */
+    double g[3];          /* body-force acceleration (force density rho g) */
+    double u0[3];         /* initial populations f_eq(rho0, u0), collided once */
+} lbm3d_grid;
+
+typedef struct {
+    double X[3];          /* centre */
+    double r;             /* radius, >= 1 */
+    double V[3];          /* surface translation velocity, |V| < 0.3 */
+    double omega[3];      /* surface angular velocity */
+} lbm3d_sphere;
+
+/* Workspace size for a 3D lattice (validates as lbm3d_create does). */
+lbm_status lbm3d_workspace_bytes(const lbm3d_grid* grid, const lbm3d_sphere* spheres, int32_t n_spheres,
+                                 int64_t history_steps, size_t* bytes);
+
+/* Validate, build the owner map and link lists on the host, lay out the
+ * caller's 256-byte aligned device workspace of `bytes` bytes and initialise
+ * the populations; history_steps force records are kept (a ring).  LBM_EGEOM
+ * when a sphere overlaps the duct or another sphere.  Synchronises. */
+lbm_status lbm3d_create(const lbm3d_grid* grid, const lbm3d_sphere* spheres, int32_t n_spheres,
+                        int64_t history_steps, void* d_workspace, size_t bytes, void* hip_stream,
+                        lbm3d_ctx** out);
+
+/* Enqueue n time steps (one launch each, plus one for the last step's force
+ * totals).  Asynchronous. */
+lbm_status lbm3d_step(lbm3d_ctx* ctx, int64_t n);
+
+/* Completed time steps. */
+int64_t lbm3d_time(const lbm3d_ctx* ctx);
+
+/* out = {F_x, F_y, F_z, T_x, T_y, T_z} of solid `solid` (0 the duct, k the
+ * k-th sphere) for scheme LBM_CME / LBM_GME at step `step` (-1: the last
+ * completed step).  Synchronises. */
+lbm_status lbm3d_force(lbm3d_ctx* ctx, int32_t solid, int32_t scheme, int64_t step, double out[6]);
+
+/* Copy the force records of steps [first, first + count) to device memory
+ * d_out, [count][n_spheres + 1][12] doubles: CME {F, T}, then GME {F, T}.
+ * Asynchronous. */
+lbm_status lbm3d_force_history(lbm3d_ctx* ctx, int64_t first, int64_t count, double* d_out);
+
+/* Device outputs, (z, y, x) order, each optional (NULL skips it): d_rho[N],
+ * d_u[3][N] (Guo velocity (sum e_i f_i + rho g/2)/rho of the pre-collision
+ * state), d_owner[N] (0 fluid, k sphere k, 255 duct), N = nx ny nz; zeros at
+ * solid nodes.  Asynchronous. */
+lbm_status lbm3d_fields(lbm3d_ctx* ctx, double* d_rho, double* d_u, int32_t* d_owner);
+
+/* Number of fluid-solid links. */
+int64_t lbm3d_link_count(const lbm3d_ctx* ctx);
+
+/* Per-launch step timing with HIP events (as lbm_profile / lbm_profile_read). */
+lbm_status lbm3d_profile(lbm3d_ctx* ctx, int32_t enable);
+lbm_status lbm3d_profile_read(lbm3d_ctx* ctx, double* step_ms, int64_t* launches);
+
+void lbm3d_destroy(lbm3d_ctx* ctx);
+
+/* Message of the last failure on this context, or of the last failed
+ * lbm3d_create / lbm3d_workspace_bytes in this thread when ctx is NULL. */
+const char* lbm3d_last_error(const lbm3d_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

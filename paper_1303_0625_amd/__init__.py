@@ -7,4 +7,4 @@ The arithmetic lives in HIP kernels behind the C ABI of include/lbm.h
 (liblbm.so); ``paper_1303_0625_amd.lbm`` is its ctypes binding.
 """
 from . import lbm  # noqa: F401
-from .lbm import Lattice, LatticeBatch, WarmStartNet  # noqa: F401
+from .lbm import Lattice, Lattice3D, LatticeBatch, WarmStartNet  # noqa: F401

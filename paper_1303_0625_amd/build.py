@@ -11,7 +11,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbm_capi.hip"), os.path.join(HERE, "csrc", "nn_capi.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "lbm_capi.hip"), os.path.join(HERE, "csrc", "nn_capi.hip"),
+           os.path.join(HERE, "csrc", "lbm3d_capi.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

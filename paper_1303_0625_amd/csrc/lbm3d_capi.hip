@@ -1,0 +1,497 @@
+// lbm3d_capi.hip -- host side of the three-dimensional entry points
+// (lbm3d_* in include/lbm.h): validation, the geometry and link lists (fixed
+// geometry: built once on the host), workspace layout inside the caller's
+// device buffer, and the per-step launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm3d_kernels.h"
+
+using namespace lbm3;
+
+namespace {
+
+thread_local char g_err3[512] = "";
+
+void set_err3(char* buf, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+}
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr size_t kStreamBytes3 = 256ull << 20;  // Infinity Cache: stream above it
+
+struct Layout3 {
+    size_t f[2], own, links, seg_off, seg_cnt, chunk_solid, chunk_start, solid_chunk0, sol, partial, hist, tctr, total;
+    int pitch;
+    int nchunks;
+    int64_t nlinks;
+};
+
+}  // namespace
+
+struct lbm3d_ctx {
+    lbm3d_grid g;
+    int ns = 0;
+    int64_t hist_cap = 0;
+    int64_t t = 0;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    Layout3 L{};
+    char err[512] = "";
+    std::vector<double> sol;  // host copy of the solid table
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    double prof_ms = 0.0;
+    int64_t prof_n = 0;
+};
+
+namespace {
+
+lbm_status fail3(lbm3d_ctx* c, hipError_t e, const char* what) {
+    set_err3(c ? c->err : g_err3, "%s: %s", what, hipGetErrorString(e));
+    return LBM_EDEVICE;
+}
+
+#define HIPCHK3(ctx, call)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return fail3(ctx, e_, #call); \
+    } while (0)
+
+// Minimum-image difference on a periodic axis (ties go to +n/2).
+double mimg(double d, int n) { return d - (double)n * std::floor(d / (double)n + 0.5); }
+
+// Owner of node (x, y, z): the duct, then the spheres; every product and sum
+// rounded separately (no contraction), so that a node on a surface is
+// classified as a plain IEEE double evaluation does.  overlap: a node claimed
+// twice.
+#pragma clang fp contract(off)
+int owner_of(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, int x, int y, int z, bool& overlap) {
+    int o = 0;
+    if (g.duct == LBM3D_TUBE) {
+        const double dy = (double)y - 0.5 * (g.ny - 1), dz = (double)z - 0.5 * (g.nz - 1);
+        const double r2 = dy * dy + dz * dz;
+        if (r2 > g.R * g.R) o = kDuct;
+    } else if (g.duct == LBM3D_PLANES) {
+        if (z == 0 || z == g.nz - 1) o = kDuct;
+    }
+    for (int k = 0; k < ns; ++k) {
+        const double dx = mimg((double)x - sp[k].X[0], g.nx);
+        const double dy = mimg((double)y - sp[k].X[1], g.ny);
+        const double dz = mimg((double)z - sp[k].X[2], g.nz);
+        double d2 = dx * dx;
+        d2 = d2 + dy * dy;
+        d2 = d2 + dz * dz;
+        if (d2 <= sp[k].r * sp[k].r) {
+            if (o != 0) overlap = true;
+            o = k + 1;
+        }
+    }
+    return o;
+}
+
+const char* validate(const lbm3d_grid* g, const lbm3d_sphere* sp, int ns) {
+    if (!g) return "grid is NULL";
+    if (g->nx < 4 || g->ny < 4 || g->nz < 4) return "nx, ny, nz must be >= 4";
+    if ((int64_t)g->nx * g->ny * g->nz >= (1ll << 27)) return "at most 2^27 nodes (link codes)";
+    if (g->dtype != LBM_F64 && g->dtype != LBM_F32) return "dtype must be LBM_F64 or LBM_F32";
+    if (!(g->tau > 0.5)) return "tau must exceed 1/2";
+    if (!(g->rho0 > 0.0)) return "rho0 must be positive";
+    if (g->duct != LBM3D_OPEN && g->duct != LBM3D_TUBE && g->duct != LBM3D_PLANES) return "unknown duct";
+    if (g->duct == LBM3D_TUBE && !(g->R >= 2.0)) return "tube radius must be >= 2";
+    if (ns < 0 || ns > 200) return "0..200 spheres";
+    if (ns > 0 && !sp) return "spheres is NULL";
+    for (int k = 0; k < ns; ++k) {
+        if (!(sp[k].r >= 1.0)) return "sphere radius must be >= 1";
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) s += sp[k].V[d] * sp[k].V[d];
+        if (!(std::sqrt(s) < 0.3)) return "sphere surface speed must be below 0.3";
+    }
+    return nullptr;
+}
+
+// Geometry and link lists on the host; returns an error message or nullptr.
+const char* build_geometry(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, int pitch,
+                           std::vector<uint8_t>& own, std::vector<std::vector<uint32_t>>& seg) {
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    own.assign((size_t)ny * nz * pitch, 0);
+    bool overlap = false;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                own[((size_t)z * ny + y) * pitch + x] = (uint8_t)owner_of(g, sp, ns, x, y, z, overlap);
+    if (overlap) return "a sphere overlaps the duct or another sphere";
+    static const int E[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                                 {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                 {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                 {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    seg.assign(ns + 1, {});
+    size_t nfluid = 0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                if (own[((size_t)z * ny + y) * pitch + x] != 0) continue;
+                ++nfluid;
+                const uint32_t node = (uint32_t)(((int64_t)z * ny + y) * nx + x);
+                for (int i = 1; i < 19; ++i) {
+                    const int xb = (x + E[i][0] + nx) % nx, yb = (y + E[i][1] + ny) % ny,
+                              zb = (z + E[i][2] + nz) % nz;
+                    const uint8_t o = own[((size_t)zb * ny + yb) * pitch + xb];
+                    if (o == 0) continue;
+                    seg[o == kDuct ? 0 : o].push_back(node << 5 | (uint32_t)i);
+                }
+            }
+    if (nfluid == 0) return "no fluid node";
+    return nullptr;
+}
+
+Layout3 make_layout(const lbm3d_grid& g, int ns, int pitch, const std::vector<std::vector<uint32_t>>& seg,
+                    int64_t hist_cap) {
+    Layout3 L{};
+    L.pitch = pitch;
+    const size_t es = g.dtype == LBM_F64 ? 8 : 4;
+    const size_t fbytes = (size_t)19 * g.ny * g.nz * pitch * es;
+    size_t off = 0;
+    L.f[0] = off;
+    off = al256(off + fbytes);
+    // second buffer skewed by 1 MiB off a power-of-two distance
+    off = al256(off + (1u << 20));
+    L.f[1] = off;
+    off = al256(off + fbytes);
+    L.own = off;
+    off = al256(off + (size_t)g.ny * g.nz * pitch);
+    int64_t nl = 0;
+    int nch = 0;
+    for (auto& s : seg) {
+        nl += (int64_t)s.size();
+        nch += std::max<int>(1, (int)((s.size() + kChunk - 1) / kChunk));
+    }
+    L.nlinks = nl;
+    L.nchunks = nch;
+    L.links = off;
+    off = al256(off + 4 * (size_t)std::max<int64_t>(nl, 1));
+    L.seg_off = off;
+    off = al256(off + 4 * (size_t)(ns + 1));
+    L.seg_cnt = off;
+    off = al256(off + 4 * (size_t)(ns + 1));
+    L.chunk_solid = off;
+    off = al256(off + 4 * (size_t)nch);
+    L.chunk_start = off;
+    off = al256(off + 4 * (size_t)nch);
+    L.solid_chunk0 = off;
+    off = al256(off + 4 * (size_t)(ns + 2));
+    L.sol = off;
+    off = al256(off + 8 * (size_t)kSolidRow * (ns + 1));
+    L.partial = off;
+    off = al256(off + 8 * (size_t)2 * nch * 12);
+    L.hist = off;
+    off = al256(off + 8 * (size_t)hist_cap * (ns + 1) * 12);
+    L.tctr = off;
+    off = al256(off + 16);
+    L.total = off;
+    return L;
+}
+
+template <typename P>
+P* at(lbm3d_ctx* c, size_t off) {
+    return reinterpret_cast<P*>(c->ws + off);
+}
+
+Args args3(const lbm3d_ctx* c) {
+    Args a{};
+    a.nx = c->g.nx;
+    a.ny = c->g.ny;
+    a.nz = c->g.nz;
+    a.pitch = c->L.pitch;
+    a.ns = c->ns;
+    a.rho0 = c->g.rho0;
+    a.tau = c->g.tau;
+    for (int d = 0; d < 3; ++d) a.g[d] = c->g.g[d];
+    a.nchunks = c->L.nchunks;
+    a.hist_cap = c->hist_cap;
+    return a;
+}
+
+int pitch_for(int nx) { return (nx + 63) / 64 * 64; }
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm3d_workspace_bytes(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_t n_spheres,
+                                 int64_t history_steps, size_t* bytes) {
+    if (!bytes) {
+        set_err3(g_err3, "bytes is NULL");
+        return LBM_EINVAL;
+    }
+    if (const char* why = validate(g, spheres, n_spheres)) {
+        set_err3(g_err3, "%s", why);
+        return LBM_EINVAL;
+    }
+    if (history_steps < 1) {
+        set_err3(g_err3, "history_steps must be >= 1");
+        return LBM_EINVAL;
+    }
+    std::vector<uint8_t> own;
+    std::vector<std::vector<uint32_t>> seg;
+    const int pitch = pitch_for(g->nx);
+    if (const char* why = build_geometry(*g, spheres, n_spheres, pitch, own, seg)) {
+        set_err3(g_err3, "%s", why);
+        return LBM_EGEOM;
+    }
+    *bytes = make_layout(*g, n_spheres, pitch, seg, history_steps).total;
+    return LBM_OK;
+}
+
+lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_t n_spheres,
+                        int64_t history_steps, void* d_workspace, size_t bytes, void* hip_stream,
+                        lbm3d_ctx** out) {
+    if (!out) {
+        set_err3(g_err3, "out is NULL");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    if (const char* why = validate(g, spheres, n_spheres)) {
+        set_err3(g_err3, "%s", why);
+        return LBM_EINVAL;
+    }
+    if (history_steps < 1) {
+        set_err3(g_err3, "history_steps must be >= 1");
+        return LBM_EINVAL;
+    }
+    if (!d_workspace || ((uintptr_t)d_workspace & 255u) != 0) {
+        set_err3(g_err3, "workspace must be a non-NULL 256-byte aligned device pointer");
+        return LBM_EINVAL;
+    }
+    const int pitch = pitch_for(g->nx);
+    std::vector<uint8_t> own;
+    std::vector<std::vector<uint32_t>> seg;
+    if (const char* why = build_geometry(*g, spheres, n_spheres, pitch, own, seg)) {
+        set_err3(g_err3, "%s", why);
+        return LBM_EGEOM;
+    }
+    Layout3 L = make_layout(*g, n_spheres, pitch, seg, history_steps);
+    if (bytes < L.total) {
+        set_err3(g_err3, "workspace holds %zu bytes, %zu needed", bytes, L.total);
+        return LBM_ESIZE;
+    }
+    lbm3d_ctx* c = new (std::nothrow) lbm3d_ctx;
+    if (!c) return LBM_EINVAL;
+    c->g = *g;
+    c->ns = n_spheres;
+    c->hist_cap = history_steps;
+    c->ws = (char*)d_workspace;
+    c->stream = (hipStream_t)hip_stream;
+    c->L = L;
+    // tables
+    std::vector<uint32_t> links;
+    std::vector<int> seg_off(n_spheres + 1), seg_cnt(n_spheres + 1), chunk_solid, chunk_start,
+        solid_chunk0(n_spheres + 2);
+    for (int s = 0; s <= n_spheres; ++s) {
+        seg_off[s] = (int)links.size();
+        seg_cnt[s] = (int)seg[s].size();
+        links.insert(links.end(), seg[s].begin(), seg[s].end());
+        solid_chunk0[s] = (int)chunk_solid.size();
+        const int nchk = std::max<int>(1, (int)((seg[s].size() + kChunk - 1) / kChunk));
+        for (int k = 0; k < nchk; ++k) {
+            chunk_solid.push_back(s);
+            chunk_start.push_back(k * kChunk);
+        }
+    }
+    solid_chunk0[n_spheres + 1] = (int)chunk_solid.size();
+    c->sol.assign((size_t)kSolidRow * (n_spheres + 1), 0.0);
+    for (int k = 0; k < n_spheres; ++k) {
+        double* r = c->sol.data() + kSolidRow * (k + 1);
+        for (int d = 0; d < 3; ++d) {
+            r[d] = spheres[k].X[d];
+            r[4 + d] = spheres[k].V[d];
+            r[7 + d] = spheres[k].omega[d];
+        }
+        r[3] = spheres[k].r;
+    }
+    hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
+    auto up = [&](size_t off, const void* src, size_t n) {
+        if (e == hipSuccess && n > 0) e = hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, c->stream);
+    };
+    up(L.own, own.data(), own.size());
+    up(L.links, links.data(), 4 * links.size());
+    up(L.seg_off, seg_off.data(), 4 * seg_off.size());
+    up(L.seg_cnt, seg_cnt.data(), 4 * seg_cnt.size());
+    up(L.chunk_solid, chunk_solid.data(), 4 * chunk_solid.size());
+    up(L.chunk_start, chunk_start.data(), 4 * chunk_start.size());
+    up(L.solid_chunk0, solid_chunk0.data(), 4 * solid_chunk0.size());
+    up(L.sol, c->sol.data(), 8 * c->sol.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        set_err3(g_err3, "hipMemcpyAsync: %s", hipGetErrorString(e));
+        delete c;
+        return LBM_EDEVICE;
+    }
+    const Args a = args3(c);
+    const int64_t N = (int64_t)g->ny * g->nz * pitch;
+    const unsigned nb = (unsigned)((N + kBlock - 1) / kBlock);
+    if (g->dtype == LBM_F64)
+        k3_init<double><<<nb, kBlock, 0, c->stream>>>(at<double>(c, L.f[0]), at<uint8_t>(c, L.own), a, g->u0[0],
+                                                      g->u0[1], g->u0[2]);
+    else
+        k3_init<float><<<nb, kBlock, 0, c->stream>>>(at<float>(c, L.f[0]), at<uint8_t>(c, L.own), a, g->u0[0],
+                                                     g->u0[1], g->u0[2]);
+    k3_set_counters<<<1, 1, 0, c->stream>>>(at<int64_t>(c, L.tctr), 0);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        set_err3(g_err3, "init: %s", hipGetErrorString(e));
+        delete c;
+        return LBM_EDEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
+    if (!c || n < 0) return LBM_EINVAL;
+    if (n == 0) return LBM_OK;
+    const Args a = args3(c);
+    const int n_lead = (c->L.nchunks + 1 + 7) / 8 * 8;
+    const int64_t lines = (int64_t)c->g.ny * c->g.nz;
+    const int64_t waves = lines * (c->L.pitch / 64);
+    const unsigned grid = (unsigned)(n_lead + (waves + kBlock / 64 - 1) / (kBlock / 64));
+    const size_t es = c->g.dtype == LBM_F64 ? 8 : 4;
+    const bool nt = 2 * (size_t)19 * lines * c->L.pitch * es > kStreamBytes3;
+    Ptrs p{};
+    p.own = at<uint8_t>(c, c->L.own);
+    p.links = at<uint32_t>(c, c->L.links);
+    p.seg_off = at<int>(c, c->L.seg_off);
+    p.seg_cnt = at<int>(c, c->L.seg_cnt);
+    p.chunk_solid = at<int>(c, c->L.chunk_solid);
+    p.chunk_start = at<int>(c, c->L.chunk_start);
+    p.solid_chunk0 = at<int>(c, c->L.solid_chunk0);
+    p.sol = at<double>(c, c->L.sol);
+    p.partial = at<double>(c, c->L.partial);
+    p.hist = at<double>(c, c->L.hist);
+    p.tctr = at<int64_t>(c, c->L.tctr);
+    for (int64_t k = 0; k < n; ++k) {
+        const int par = (int)(c->t & 1);
+        p.fin = c->ws + c->L.f[par];
+        p.fout = c->ws + c->L.f[par ^ 1];
+        const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
+        if (timed) HIPCHK3(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+        if (c->g.dtype == LBM_F64) {
+            if (nt)
+                k3_step<double, true><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
+            else
+                k3_step<double, false><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
+        } else {
+            if (nt)
+                k3_step<float, true><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
+            else
+                k3_step<float, false><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
+        }
+        if (timed) {
+            HIPCHK3(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+            c->ev_used += 2;
+        }
+        c->t += 1;
+    }
+    k3_finalize<<<1, kBlock, 0, c->stream>>>(p.partial, p.solid_chunk0, p.hist, p.tctr, (int)(c->t & 1), a);
+    HIPCHK3(c, hipGetLastError());
+    return LBM_OK;
+}
+
+int64_t lbm3d_time(const lbm3d_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm3d_force(lbm3d_ctx* c, int32_t solid, int32_t scheme, int64_t step, double out[6]) {
+    if (!c || !out || solid < 0 || solid > c->ns || (scheme != LBM_CME && scheme != LBM_GME)) return LBM_EINVAL;
+    if (step < 0) step = c->t - 1;
+    if (step < 0 || step >= c->t || step < c->t - c->hist_cap) {
+        set_err3(c->err, "no force record for step %lld", (long long)step);
+        return LBM_ESTATE;
+    }
+    const size_t off =
+        c->L.hist + 8 * (((size_t)(step % c->hist_cap) * (c->ns + 1) + solid) * 12 + 6 * (size_t)scheme);
+    HIPCHK3(c, hipMemcpyAsync(out, c->ws + off, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK3(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm3d_force_history(lbm3d_ctx* c, int64_t first, int64_t count, double* d_out) {
+    if (!c || !d_out || first < 0 || count < 0) return LBM_EINVAL;
+    if (first + count > c->t || first < c->t - c->hist_cap) {
+        set_err3(c->err, "steps [%lld, %lld) are not in the history", (long long)first, (long long)(first + count));
+        return LBM_ESTATE;
+    }
+    const size_t row = 8 * (size_t)(c->ns + 1) * 12;
+    for (int64_t k = 0; k < count; ++k) {
+        const size_t src = c->L.hist + row * (size_t)((first + k) % c->hist_cap);
+        HIPCHK3(c, hipMemcpyAsync((char*)d_out + row * (size_t)k, c->ws + src, row, hipMemcpyDeviceToDevice,
+                                  c->stream));
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm3d_fields(lbm3d_ctx* c, double* d_rho, double* d_u, int32_t* d_owner) {
+    if (!c) return LBM_EINVAL;
+    const Args a = args3(c);
+    const int64_t N = (int64_t)c->g.nx * c->g.ny * c->g.nz;
+    const unsigned nb = (unsigned)((N + kBlock - 1) / kBlock);
+    const int par = (int)(c->t & 1);
+    const uint8_t* own = at<uint8_t>(c, c->L.own);
+    if (c->g.dtype == LBM_F64)
+        k3_fields<double><<<nb, kBlock, 0, c->stream>>>(at<double>(c, c->L.f[par]), own, a, d_rho, d_u, d_owner);
+    else
+        k3_fields<float><<<nb, kBlock, 0, c->stream>>>(at<float>(c, c->L.f[par]), own, a, d_rho, d_u, d_owner);
+    HIPCHK3(c, hipGetLastError());
+    return LBM_OK;
+}
+
+int64_t lbm3d_link_count(const lbm3d_ctx* c) { return c ? c->L.nlinks : -1; }
+
+lbm_status lbm3d_profile(lbm3d_ctx* c, int32_t enable) {
+    if (!c) return LBM_EINVAL;
+    c->prof = enable != 0;
+    c->ev_used = 0;
+    c->prof_ms = 0.0;
+    c->prof_n = 0;
+    if (c->prof && c->ev.empty()) {
+        c->ev.resize(2 * 16384);
+        for (auto& ev : c->ev) HIPCHK3(c, hipEventCreate(&ev));
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm3d_profile_read(lbm3d_ctx* c, double* step_ms, int64_t* launches) {
+    if (!c || !step_ms || !launches) return LBM_EINVAL;
+    HIPCHK3(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK3(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+        c->prof_ms += ms;
+        c->prof_n += 1;
+    }
+    c->ev_used = 0;
+    *step_ms = c->prof_ms;
+    *launches = c->prof_n;
+    return LBM_OK;
+}
+
+void lbm3d_destroy(lbm3d_ctx* c) {
+    if (!c) return;
+    for (auto& ev : c->ev) (void)hipEventDestroy(ev);
+    delete c;
+}
+
+const char* lbm3d_last_error(const lbm3d_ctx* c) { return c ? c->err : g_err3; }
+
+}  // extern "C"

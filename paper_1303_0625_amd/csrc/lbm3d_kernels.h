@@ -1,0 +1,341 @@
+// lbm3d_kernels.h -- HIP kernels of the three-dimensional (D3Q19) momentum-
+// exchange step, Sec. IV.D: fixed geometry (a duct of solid nodes and
+// spheres whose surfaces move rigidly), half-way bounce-back with the
+// moving-boundary term, BGK collision with Guo forcing, and per-link CME
+// (Eq. 4) / GME (Eq. 5) forces with torque about each sphere's centre
+// (Eqs. 6-7).
+//
+// State: post-collision deviations d~_i = f~_i - w_i rho0 of every fluid
+// node, layout [z][y][19][pitch] (the nineteen population rows of one (y, z)
+// line are contiguous), two ping-pong buffers by step parity.  One launch per
+// step: force workgroups (512 links each, fixed-order partials), one
+// finalizer workgroup (previous step's totals in chunk order, then the step
+// counter), and from n_lead on the update workgroups (one thread per node, a
+// wave = 64 consecutive x of one line).
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbm3 {
+
+using lbm::Sto;
+
+constexpr int kBlock = 256;
+constexpr int kChunk = 512;  // links per force workgroup
+constexpr int kQ = 19;
+constexpr uint8_t kDuct = 255;  // owner value of duct nodes (force slot 0)
+
+// Velocity set: rest, the axis directions (+x, -x, +y, -y, +z, -z), the
+// twelve edge diagonals in opposite pairs; opposite of i is i + 1 for odd
+// i, i - 1 for even i > 0.
+__device__ constexpr int kE[kQ][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                                      {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                      {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                      {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+__device__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__device__ constexpr double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+struct Args {
+    int nx, ny, nz;
+    int pitch;        // elements per population row (multiple of 64)
+    int ns;           // spheres (solid slots: 0 duct, 1..ns spheres)
+    double rho0, tau;
+    double g[3];      // body force (acceleration)
+    int nchunks;      // force workgroups
+    int64_t hist_cap;
+};
+
+// Solid table row: X, Y, Z, r, V (3), Omega (3), pad (2); row 0 is the duct.
+constexpr int kSolidRow = 12;
+
+__device__ inline double min_image3(double d, int n) { return d - (double)n * floor(d / (double)n + 0.5); }
+
+// Rigid surface velocity of solid slot s at point p (duct at rest), and the
+// arm from the centre.
+__device__ inline void surface_vel(const double* __restrict__ sol, int s, double px, double py, double pz,
+                                   const Args& a, double v[3], double r[3]) {
+    if (s == 0) {
+        v[0] = v[1] = v[2] = 0.0;
+        r[0] = r[1] = r[2] = 0.0;
+        return;
+    }
+    const double* S = sol + kSolidRow * s;
+    r[0] = min_image3(px - S[0], a.nx);
+    r[1] = min_image3(py - S[1], a.ny);
+    r[2] = min_image3(pz - S[2], a.nz);
+    v[0] = S[4] + (S[8] * r[2] - S[9] * r[1]);
+    v[1] = S[5] + (S[9] * r[0] - S[7] * r[2]);
+    v[2] = S[6] + (S[7] * r[1] - S[8] * r[0]);
+}
+
+__device__ inline int wrap3(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// BGK + Guo on deviations, in FP64: rho = rho0 + sum d, momentum sum e d
+// (the weights' first moment vanishes), u = (j + rho g/2)/rho.
+__device__ inline void collide3(double d[kQ], const Args& a) {
+    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        drho += d[i];
+        jx += kE[i][0] * d[i];
+        jy += kE[i][1] * d[i];
+        jz += kE[i][2] * d[i];
+    }
+    const double rho = a.rho0 + drho;
+    const double Fx = rho * a.g[0], Fy = rho * a.g[1], Fz = rho * a.g[2];
+    const double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double om = 1.0 / a.tau, cs = 1.0 - 0.5 / a.tau;
+    const double uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const double eu = kE[i][0] * ux + kE[i][1] * uy + kE[i][2] * uz;
+        const double eF = kE[i][0] * Fx + kE[i][1] * Fy + kE[i][2] * Fz;
+        // equilibrium deviation: w (rho - rho0) + w rho (3 eu + 4.5 eu^2 - 1.5 u^2)
+        const double deq = w3(i) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        // Guo source: w [3 (e - u) + 9 (e . u) e] . F
+        const double src = w3(i) * (3.0 * (eF - uF) + 9.0 * eu * eF);
+        d[i] = d[i] - om * (d[i] - deq) + cs * src;
+    }
+}
+
+struct Ptrs {
+    const void* fin;
+    void* fout;
+    const uint8_t* own;
+    const uint32_t* links;    // per link: node << 5 | i
+    const int* seg_off;       // per solid slot
+    const int* seg_cnt;
+    const int* chunk_solid;
+    const int* chunk_start;
+    const int* solid_chunk0;  // [ns + 2]
+    const double* sol;        // [ns + 1][kSolidRow]
+    double* partial;          // [2][nchunks][12]
+    double* hist;             // [hist_cap][ns + 1][12]
+    int64_t* tctr;
+};
+
+// Per link (x_f, i) of solid s: a = f~_i(x_f), b = a - 6 w_i rho0 (e_i . v)
+// with v at the link midpoint; CME F = e_i (a + b), GME F = (e_i - v) a +
+// (e_i + v) b; torque r x F about the sphere's centre.
+template <typename T>
+__device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ partial, const Args& a,
+                                   double (*red)[12]) {
+    const T* f = (const T*)p.fin;
+    const int s = p.chunk_solid[c];
+    const int start = p.chunk_start[c];
+    const int n = p.seg_cnt[s];
+    const int end = start + kChunk < n ? start + kChunk : n;
+    const uint32_t* L = p.links + p.seg_off[s];
+    double acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+    for (int k = start + (int)threadIdx.x; k < end; k += kBlock) {
+        const uint32_t code = L[k];
+        const int i = (int)(code & 31u);
+        const uint32_t node = code >> 5;
+        const int x = (int)(node % (uint32_t)a.nx);
+        const uint32_t line = node / (uint32_t)a.nx;  // z * ny + y
+        const int y = (int)(line % (uint32_t)a.ny);
+        const int z = (int)(line / (uint32_t)a.ny);
+        const double ex = kE[i][0], ey = kE[i][1], ez = kE[i][2], w = w3(i);
+        double v[3], r[3];
+        surface_vel(p.sol, s, x + 0.5 * ex, y + 0.5 * ey, z + 0.5 * ez, a, v, r);
+        const double av =
+            w * a.rho0 + (double)Sto<T>::ld(f[((int64_t)line * kQ + i) * a.pitch + x]);
+        const double bv = av - 6.0 * w * a.rho0 * (ex * v[0] + ey * v[1] + ez * v[2]);
+        const double e[3] = {ex, ey, ez};
+        double Fc[3], Fg[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            Fc[d] = e[d] * av + e[d] * bv;
+            Fg[d] = (e[d] - v[d]) * av + (e[d] + v[d]) * bv;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            acc[d] += Fc[d];
+            acc[6 + d] += Fg[d];
+        }
+        if (s > 0) {
+            acc[3] += r[1] * Fc[2] - r[2] * Fc[1];
+            acc[4] += r[2] * Fc[0] - r[0] * Fc[2];
+            acc[5] += r[0] * Fc[1] - r[1] * Fc[0];
+            acc[9] += r[1] * Fg[2] - r[2] * Fg[1];
+            acc[10] += r[2] * Fg[0] - r[0] * Fg[2];
+            acc[11] += r[0] * Fg[1] - r[1] * Fg[0];
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int q = threadIdx.x;
+        partial[c * 12 + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    }
+}
+
+// Totals of step `step` per solid from its chunk partials, in chunk order.
+__device__ inline void finalize3(const double* __restrict__ partial, const int* __restrict__ solid_chunk0,
+                                 double* __restrict__ hist, int64_t step, const Args& a) {
+    const int64_t slot = step % a.hist_cap;
+    const int nsol = a.ns + 1;
+    for (int r = threadIdx.x; r < nsol * 12; r += kBlock) {
+        const int s = r / 12, q = r % 12;
+        double v = 0.0;
+        for (int cc = solid_chunk0[s]; cc < solid_chunk0[s + 1]; ++cc) v += partial[cc * 12 + q];
+        hist[(slot * nsol + s) * 12 + q] = v;
+    }
+}
+
+// Update of node (x, line): pull the nineteen populations (all loads issued
+// before any is used), replace those whose source is solid by the half-way
+// bounce-back of the node's own opposite population plus 6 w_i rho0
+// (e_i . v), v the surface velocity at x - e_i/2; collide; store.
+template <typename T, bool NT>
+__device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a) {
+    const T* fin = (const T*)p.fin;
+    T* fout = (T*)p.fout;
+    const int64_t line = (int64_t)z * a.ny + y;
+    const uint8_t self = p.own[line * a.pitch + x];
+    T raw[kQ];
+    uint8_t src[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int xs = wrap3(x - kE[i][0], a.nx), ys = wrap3(y - kE[i][1], a.ny), zs = wrap3(z - kE[i][2], a.nz);
+        const int64_t ls = (int64_t)zs * a.ny + ys;
+        src[i] = p.own[ls * a.pitch + xs];
+        const T* ptr = fin + (ls * kQ + i) * a.pitch + xs;
+        if constexpr (NT)
+            raw[i] = __builtin_nontemporal_load(ptr);
+        else
+            raw[i] = *ptr;
+    }
+    if (self) return;
+    double d[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) d[i] = (double)Sto<T>::ld(raw[i]);
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) any |= src[i];
+    if (any) {
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) {
+            if (src[i] == 0) continue;
+            const int s = src[i] == kDuct ? 0 : (int)src[i];
+            double v[3], r[3];
+            surface_vel(p.sol, s, x - 0.5 * kE[i][0], y - 0.5 * kE[i][1], z - 0.5 * kE[i][2], a, v, r);
+            d[i] = (double)Sto<T>::ld(fin[(line * kQ + opp3(i)) * a.pitch + x]) +
+                   6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
+        }
+    }
+    collide3(d, a);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        T* ptr = fout + (line * kQ + i) * a.pitch + x;
+        const T val = Sto<T>::st(d[i]);
+        if constexpr (NT)
+            __builtin_nontemporal_store(val, ptr);
+        else
+            *ptr = val;
+    }
+}
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead, Args a) {
+    __shared__ double red[kBlock / 64][12];
+    const int b = (int)blockIdx.x;
+    if (b < n_lead) {
+        const int64_t t = p.tctr[parity];
+        if (b < a.nchunks) {
+            force_role3<T>(b, p, p.partial + (size_t)(t & 1) * a.nchunks * 12, a, red);
+        } else if (b == a.nchunks) {
+            if (t >= 1)
+                finalize3(p.partial + (size_t)((t - 1) & 1) * a.nchunks * 12, p.solid_chunk0, p.hist, t - 1, a);
+            if (threadIdx.x == 0) p.tctr[parity ^ 1] = t + 1;
+        }
+        return;
+    }
+    const uint32_t wpr = (uint32_t)a.pitch >> 6;
+    const uint32_t gw = (uint32_t)(b - n_lead) * (kBlock / 64) + (uint32_t)(threadIdx.x >> 6);
+    const uint32_t line = gw / wpr;
+    const int x = (int)((gw - line * wpr) << 6) + (int)(threadIdx.x & 63);
+    if (line >= (uint32_t)(a.ny * a.nz) || x >= a.nx) return;
+    update3<T, NT>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a);
+}
+
+// Totals of the last step tctr[parity] - 1 after a run of steps.
+__global__ __launch_bounds__(kBlock) void k3_finalize(const double* __restrict__ partial2,
+                                                      const int* __restrict__ solid_chunk0,
+                                                      double* __restrict__ hist, const int64_t* __restrict__ tctr,
+                                                      int parity, Args a) {
+    const int64_t t = tctr[parity];
+    if (t < 1) return;
+    finalize3(partial2 + (size_t)((t - 1) & 1) * a.nchunks * 12, solid_chunk0, hist, t - 1, a);
+}
+
+// f = f_eq(rho0, u0) at every fluid node, collided once; solid nodes zero.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k3_init(T* __restrict__ f, const uint8_t* __restrict__ own, Args a,
+                                                  double u0x, double u0y, double u0z) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t N = (int64_t)a.ny * a.nz * a.pitch;
+    if (n >= N) return;
+    const int x = (int)(n % a.pitch);
+    const int64_t line = n / a.pitch;
+    if (x >= a.nx) return;
+    double d[kQ];
+    const bool fluid = own[line * a.pitch + x] == 0;
+    const double uu = u0x * u0x + u0y * u0y + u0z * u0z;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const double eu = kE[i][0] * u0x + kE[i][1] * u0y + kE[i][2] * u0z;
+        d[i] = w3(i) * a.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+    if (fluid) collide3(d, a);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) f[(line * kQ + i) * a.pitch + x] = Sto<T>::st(fluid ? d[i] : 0.0);
+}
+
+// rho, Guo velocity (from the post-collision state: u = (sum e f~ - rho g/2)/rho)
+// and owner per node, in (z, y, x) order; zeros at solid nodes.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k3_fields(const T* __restrict__ f, const uint8_t* __restrict__ own,
+                                                    Args a, double* __restrict__ rho_out,
+                                                    double* __restrict__ u_out, int32_t* __restrict__ own_out) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t N = (int64_t)a.nx * a.ny * a.nz;
+    if (n >= N) return;
+    const int x = (int)(n % a.nx);
+    const int64_t line = n / a.nx;
+    const uint8_t o = own[line * a.pitch + x];
+    double r = 0.0, u[3] = {0.0, 0.0, 0.0};
+    if (o == 0) {
+        double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < kQ; ++i) {
+            const double d = (double)Sto<T>::ld(f[(line * kQ + i) * a.pitch + x]);
+            drho += d;
+            for (int c = 0; c < 3; ++c) j[c] += kE[i][c] * d;
+        }
+        r = a.rho0 + drho;
+        for (int c = 0; c < 3; ++c) u[c] = (j[c] - 0.5 * r * a.g[c]) / r;
+    }
+    if (rho_out) rho_out[n] = r;
+    if (u_out)
+        for (int c = 0; c < 3; ++c) u_out[c * N + n] = u[c];
+    if (own_out) own_out[n] = o;
+}
+
+__global__ void k3_set_counters(int64_t* tctr, int64_t t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        tctr[0] = t;
+        tctr[1] = t;
+    }
+}
+
+}  // namespace lbm3

@@ -56,6 +56,18 @@ _lib = None
 _VP = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
+class lbm3d_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("duct", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("R", ctypes.c_double), ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("g", ctypes.c_double * 3), ("u0", ctypes.c_double * 3)]
+
+
+class lbm3d_sphere(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_double * 3), ("r", ctypes.c_double), ("V", ctypes.c_double * 3),
+                ("omega", ctypes.c_double * 3)]
+
+
 _SIG = {
     "lbm_abi_version": (_I32, []),
     "lbm_workspace_bytes": (_I32, [ctypes.POINTER(lbm_grid), ctypes.POINTER(lbm_solid), _I32, _I64,
@@ -126,6 +138,20 @@ _SIG = {
     "lbm_warm_project": (_I32, [_I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP]),
     "lbm_nn_destroy": (None, [_VP]),
     "lbm_nn_last_error": (ctypes.c_char_p, [_VP]),
+    "lbm3d_workspace_bytes": (_I32, [ctypes.POINTER(lbm3d_grid), ctypes.POINTER(lbm3d_sphere), _I32, _I64,
+                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "lbm3d_create": (_I32, [ctypes.POINTER(lbm3d_grid), ctypes.POINTER(lbm3d_sphere), _I32, _I64, _VP,
+                            ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "lbm3d_step": (_I32, [_VP, _I64]),
+    "lbm3d_time": (_I64, [_VP]),
+    "lbm3d_force": (_I32, [_VP, _I32, _I32, _I64, ctypes.POINTER(ctypes.c_double)]),
+    "lbm3d_force_history": (_I32, [_VP, _I64, _I64, _VP]),
+    "lbm3d_fields": (_I32, [_VP, _VP, _VP, _VP]),
+    "lbm3d_link_count": (_I64, [_VP]),
+    "lbm3d_profile": (_I32, [_VP, _I32]),
+    "lbm3d_profile_read": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "lbm3d_destroy": (None, [_VP]),
+    "lbm3d_last_error": (ctypes.c_char_p, [_VP]),
 }
 
 
@@ -880,3 +906,142 @@ class WarmStartNet:
         lbm_nn_infer(self.n, solid.data_ptr(), re.data_ptr(), gx.data_ptr(), tau.data_ptr(), B,
                      *(o.data_ptr() for o in outs))
         return outs
+
+
+# ---- three dimensions (Sec. IV.D) -------------------------------------------
+LBM3D_OPEN, LBM3D_TUBE, LBM3D_PLANES = 0, 1, 2
+
+
+def _check3(status, ctx=None):
+    if status != LBM_OK:
+        msg = load_library().lbm3d_last_error(ctx)
+        raise LBMError(status, msg.decode() if msg else "")
+
+
+def make_grid3(case: dict, dtype="f64") -> lbm3d_grid:
+    g = lbm3d_grid()
+    g.nx, g.ny, g.nz = int(case["nx"]), int(case["ny"]), int(case["nz"])
+    g.dtype = {"f64": LBM_F64, "f32": LBM_F32}[dtype]
+    g.duct = int(case.get("duct", LBM3D_OPEN))
+    g.R = float(case.get("R", 0.0))
+    g.tau = float(case["tau"])
+    g.rho0 = float(case.get("rho0", 1.0))
+    for d in range(3):
+        g.g[d] = float(case.get("g", (0.0, 0.0, 0.0))[d])
+        g.u0[d] = float(case.get("u0", (0.0, 0.0, 0.0))[d])
+    return g
+
+
+def _spheres(spheres):
+    n = len(spheres)
+    arr = (lbm3d_sphere * max(1, n))()
+    for k, sp in enumerate(spheres):
+        arr[k].X[:] = [float(sp["cx"]), float(sp["cy"]), float(sp["cz"])]
+        arr[k].r = float(sp["r"])
+        arr[k].V[:] = [float(v) for v in sp.get("v", (0.0, 0.0, 0.0))]
+        arr[k].omega[:] = [float(v) for v in sp.get("omega", (0.0, 0.0, 0.0))]
+    return arr, n
+
+
+def lbm3d_workspace_bytes(grid, spheres, history_steps: int) -> int:
+    arr, n = _spheres(spheres)
+    out = ctypes.c_size_t()
+    _check3(load_library().lbm3d_workspace_bytes(ctypes.byref(grid), arr, n, int(history_steps),
+                                                 ctypes.byref(out)))
+    return out.value
+
+
+def lbm3d_create(grid, spheres, history_steps: int, d_workspace: int, nbytes: int, stream: int):
+    arr, n = _spheres(spheres)
+    ctx = ctypes.c_void_p()
+    _check3(load_library().lbm3d_create(ctypes.byref(grid), arr, n, int(history_steps), d_workspace, nbytes,
+                                        stream, ctypes.byref(ctx)))
+    return ctx
+
+
+def lbm3d_step(ctx, n: int) -> None:
+    _check3(load_library().lbm3d_step(ctx, int(n)), ctx)
+
+
+def lbm3d_force(ctx, solid: int, scheme: int, step: int = -1):
+    out = (ctypes.c_double * 6)()
+    _check3(load_library().lbm3d_force(ctx, int(solid), int(scheme), int(step), out), ctx)
+    return list(out)
+
+
+class Lattice3D:
+    """One D3Q19 lattice on the current device (workspace: a torch uint8
+    tensor; kernels on torch's current stream).  case keys: nx, ny, nz, tau,
+    duct, R, rho0, g, u0, spheres (dicts cx, cy, cz, r, v, omega)."""
+
+    def __init__(self, case: dict, dtype="f64", history_steps=1024, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.case = case
+        self.nx, self.ny, self.nz = case["nx"], case["ny"], case["nz"]
+        self.spheres = list(case.get("spheres", ()))
+        self.ns = len(self.spheres)
+        self.grid = make_grid3(case, dtype)
+        self.history_steps = int(history_steps)
+        nbytes = lbm3d_workspace_bytes(self.grid, self.spheres, self.history_steps)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._destroy = load_library().lbm3d_destroy
+        self.ctx = lbm3d_create(self.grid, self.spheres, self.history_steps, self._ws_ptr, nbytes,
+                                self.stream.cuda_stream)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                self.stream.synchronize()
+            except Exception:
+                pass
+            self._destroy(ctx)
+            self.ctx = None
+
+    @property
+    def t(self) -> int:
+        return load_library().lbm3d_time(self.ctx)
+
+    def step(self, n: int = 1) -> None:
+        lbm3d_step(self.ctx, n)
+
+    def force(self, solid: int, scheme: int, step: int = -1):
+        return lbm3d_force(self.ctx, solid, scheme, step)
+
+    def force_history(self):
+        """[t][ns + 1][12] (CME F, T, GME F, T) of the steps still in the ring."""
+        t = self.t
+        first = max(0, t - self.history_steps)
+        out = self.torch.empty((t - first, self.ns + 1, 12), dtype=self.torch.float64, device=self.workspace.device)
+        if t > first:
+            _check3(load_library().lbm3d_force_history(self.ctx, first, t - first, out.data_ptr()), self.ctx)
+        self.stream.synchronize()
+        return out
+
+    def fields(self):
+        """rho [nz, ny, nx], u [3, nz, ny, nx], owner [nz, ny, nx] (device tensors)."""
+        T = self.torch
+        shp = (self.nz, self.ny, self.nx)
+        dev = self.workspace.device
+        rho = T.empty(shp, dtype=T.float64, device=dev)
+        u = T.empty((3,) + shp, dtype=T.float64, device=dev)
+        own = T.empty(shp, dtype=T.int32, device=dev)
+        _check3(load_library().lbm3d_fields(self.ctx, rho.data_ptr(), u.data_ptr(), own.data_ptr()), self.ctx)
+        self.stream.synchronize()
+        return rho, u, own
+
+    def link_count(self) -> int:
+        return load_library().lbm3d_link_count(self.ctx)
+
+    def profile(self, enable: bool) -> None:
+        _check3(load_library().lbm3d_profile(self.ctx, int(bool(enable))), self.ctx)
+
+    def profile_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check3(load_library().lbm3d_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n)), self.ctx)
+        return ms.value, n.value

@@ -26,7 +26,7 @@ def L():
 def header_functions():
     src = open(os.path.join(ROOT, "include", "lbm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lbm(?:3d)?_[a-z_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported(L):

@@ -1,0 +1,163 @@
+"""GPU parity of the three-dimensional (D3Q19) step (Sec. IV.D) through the C
+ABI against the FP64 oracle on the same inputs.
+
+Bars as in two dimensions: FP64 storage within 1e-12 relative on fields and
+1e-10 on forces (relative to each solid's largest force or torque
+component); FP32 storage within 1e-5 relative on drag.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lbm_mod(torch_mod):
+    import paper_1303_0625_amd as pkg
+
+    pkg.lbm.load_library()
+    return pkg
+
+
+def _oracle(oracle_mod, c):
+    return oracle_mod.OracleSim3D(c["nx"], c["ny"], c["nz"], c["tau"], g=c.get("g", (0.0, 0.0, 0.0)),
+                                  u0=c.get("u0", (0.0, 0.0, 0.0)), duct=c.get("duct", 0), R=c.get("R", 0.0),
+                                  spheres=c.get("spheres", ()))
+
+
+def run_pair(oracle_mod, lbm_mod, c, steps, dtype="f64", chunks=2):
+    _say(f"{c['name']} {c['nx']}x{c['ny']}x{c['nz']} steps={steps} dtype={dtype}")
+    lat = lbm_mod.Lattice3D(c, dtype=dtype, history_steps=steps)
+    osim = _oracle(oracle_mod, c)
+    for _ in range(chunks):
+        lat.step(steps // chunks)
+        osim.step(steps // chunks)
+    return lat, osim
+
+
+def field_err(lat, osim):
+    rho, u, own = (a.cpu().numpy() for a in lat.fields())
+    orho, ou, oown = osim.fields()
+    assert np.array_equal(own, oown)
+    fl = own == 0
+    er = np.abs(rho - orho)[fl].max() / orho[fl].max()
+    scale = np.abs(ou[:, fl]).max()
+    eu = np.abs(u[:, fl] - ou[:, fl]).max() / max(scale, 1e-300)
+    _say(f"field rel err rho={er:.3e} u={eu:.3e} (max |u| {scale:.3e})")
+    return er, eu
+
+
+def force_err(lat, osim):
+    h = lat.force_history().cpu().numpy()
+    oh = np.concatenate([osim.force_history(0), osim.force_history(1)], axis=2)
+    assert h.shape == oh.shape, (h.shape, oh.shape)
+    worst = 0.0
+    for s in range(h.shape[1]):
+        for blk in (slice(0, 3), slice(3, 6), slice(6, 9), slice(9, 12)):
+            scale = np.abs(oh[:, s, blk]).max()
+            if scale == 0.0:
+                assert np.abs(h[:, s, blk]).max() <= 1e-14
+                continue
+            worst = max(worst, np.abs(h[:, s, blk] - oh[:, s, blk]).max() / scale)
+    _say(f"force rel err (history max, per solid and block) = {worst:.3e}")
+    return worst
+
+
+def test_tube_sphere_moving_surface_f64(oracle_mod, lbm_mod):
+    """Tube (R = 10.3) with a body force along it and an off-axis sphere whose
+    surface translates and spins: FP64 fields and per-step CME/GME force and
+    torque of tube and sphere."""
+    c = dict(name="tube_sphere", nx=40, ny=24, nz=24, tau=0.7, duct=1, R=10.3, g=(2e-5, 0.0, 0.0),
+             spheres=[dict(cx=17.4, cy=13.1, cz=10.6, r=4.3, v=(0.01, -0.004, 0.002),
+                           omega=(0.002, 0.001, -0.003))])
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 600)
+    er, eu = field_err(lat, osim)
+    assert er <= 1e-12 and eu <= 1e-12
+    assert force_err(lat, osim) <= 1e-10
+
+
+def test_two_spheres_open_box_f64(oracle_mod, lbm_mod):
+    """Periodic box, oblique body force, two spheres (one across the periodic
+    x boundary), initial flow."""
+    c = dict(name="two_spheres", nx=36, ny=28, nz=20, tau=0.8, g=(1e-5, 5e-6, -3e-6), u0=(0.02, 0.0, 0.01),
+             spheres=[dict(cx=1.2, cy=9.4, cz=10.3, r=3.6, omega=(0.0, 0.003, 0.0)),
+                      dict(cx=20.7, cy=19.2, cz=8.9, r=4.1, v=(-0.01, 0.0, 0.0))])
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 400)
+    er, eu = field_err(lat, osim)
+    assert er <= 1e-12 and eu <= 1e-12
+    assert force_err(lat, osim) <= 1e-10
+
+
+def test_planes_poiseuille_gpu(lbm_mod):
+    """The exact discrete Poiseuille profile between the planes z = 0 and
+    z = nz - 1 (D3Q19 reduces to D2Q9 for y-invariant flow), on the GPU."""
+    nz, g, tau = 14, 1e-5, 0.8
+    c = dict(nx=8, ny=6, nz=nz, tau=tau, duct=2, g=(g, 0.0, 0.0))
+    lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=16)
+    lat.step(30000)
+    rho, u, own = (a.cpu().numpy() for a in lat.fields())
+    nu = (tau - 0.5) / 3
+    z = np.arange(nz)
+    slip = g * (4 * (2 * tau - 1) ** 2 - 3) / (4 * (2 * tau - 1))
+    exact = g / (2 * nu) * (((nz - 2) / 2) ** 2 - (z - (nz - 1) / 2) ** 2) + slip
+    fl = own[:, 0, 0] == 0
+    err = np.abs(u[0][:, 2, 3] - exact)[fl].max() / exact.max()
+    _say(f"planes Poiseuille rel err {err:.3e}")
+    assert err <= 1e-10
+    F = lat.force(0, 0)
+    assert abs(F[0] - g * rho.sum()) <= 1e-9 * g * rho.sum()
+
+
+def test_comoving_sphere_uniform_flow_gpu(lbm_mod):
+    """Uniform f_eq(1, U) around a sphere whose surface moves at U stays
+    uniform, with no force on the sphere."""
+    U = (0.04, -0.015, 0.02)
+    c = dict(nx=20, ny=18, nz=16, tau=0.7, u0=U, spheres=[dict(cx=9.3, cy=8.6, cz=7.8, r=4.2, v=U)])
+    lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=32)
+    lat.step(20)
+    rho, u, own = (a.cpu().numpy() for a in lat.fields())
+    fl = own == 0
+    assert np.abs(rho[fl] - 1.0).max() <= 1e-14
+    for d in range(3):
+        assert np.abs(u[d][fl] - U[d]).max() <= 1e-15
+    for sch in (0, 1):
+        assert np.abs(np.array(lat.force(1, sch))[:3]).max() <= 1e-13
+
+
+def test_tube_sphere_f32_drag(oracle_mod, lbm_mod):
+    """FP32 storage (FP64 arithmetic): the sphere's drag within 1e-5 of the
+    FP64 oracle over the history."""
+    c = dict(name="tube_sphere_f32", nx=40, ny=24, nz=24, tau=0.6, duct=1, R=10.3, g=(2e-5, 0.0, 0.0),
+             spheres=[dict(cx=17.4, cy=13.1, cz=10.6, r=4.3)])
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 1200, dtype="f32")
+    h = lat.force_history().cpu().numpy()
+    for sch, off in ((0, 0), (1, 6)):
+        oh = osim.force_history(sch)
+        rel = np.abs(h[100:, 1, off] - oh[100:, 1, 0]).max() / np.abs(oh[100:, 1, 0]).max()
+        _say(f"f32 drag history rel err scheme {sch} = {rel:.3e}")
+        assert rel <= 1e-5
+
+
+def test_rejects_overlap_and_bad_args(lbm_mod):
+    L = lbm_mod.lbm
+    bad = dict(nx=20, ny=20, nz=20, tau=0.7, duct=1, R=6.0, spheres=[dict(cx=10, cy=14.0, cz=9.5, r=3.0)])
+    with pytest.raises(L.LBMError):
+        lbm_mod.Lattice3D(bad)
+    with pytest.raises(L.LBMError):
+        lbm_mod.Lattice3D(dict(nx=20, ny=20, nz=20, tau=0.5))
