@@ -157,6 +157,48 @@ def run_sedimentation(lc, pkg, torch, steps):
     return out
 
 
+def run_3d(pkg, torch, steps):
+    """Sec. IV.D in lattice units: a tube of radius 0.2/0.061 x 5.9 = 19.34
+    nodes and length 150, a sphere of radius 5.9 released at r*/R = 0.21, the
+    pressure drop 1.825e-5 over the tube applied as the equivalent body force
+    1.825e-5/150 along it, tau = 0.6, FP32 storage (fixed geometry; the
+    sphere at rest).  Then a larger tube (768 x 192 x 192, R = 94, the same
+    sphere scaled by 16) for the kernel's bandwidth: 19 populations read and
+    written per fluid node, 152 B in FP32."""
+    out = {}
+    for name, nx, n, R, r in (("tube_150x42x42", 150, 42, 19.34, 5.9), ("tube_768x192x192", 768, 192, 94.0, 28.7)):
+        cy = (n - 1) / 2
+        case = dict(nx=nx, ny=n, nz=n, tau=0.6, duct=pkg.lbm.LBM3D_TUBE, R=R, g=(1.825e-5 / 150, 0.0, 0.0),
+                    spheres=[dict(cx=nx / 4, cy=cy + 0.21 * R, cz=cy, r=r)])
+        k = steps if nx == 150 else max(20, steps // 10)
+        lat = pkg.Lattice3D(case, dtype="f32", history_steps=2 * k + 21)
+        lat.step(20)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(k)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        lat.profile(True)
+        lat.step(k)
+        kms, kn = lat.profile_read()
+        lat.profile(False)
+        _, _, own = lat.fields()
+        nf = int((own == 0).sum().item())
+        nodes = nx * n * n
+        kus = kms / max(kn, 1) * 1e3
+        out[name] = {"mlups": round(nodes * k / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms / k, 5),
+                     "kernel_us": round(kus, 2), "fluid_nodes": nf, "links": lat.link_count(),
+                     "achieved_GBs": round(152 * nf / (kus * 1e-6) / 1e9, 1),
+                     "frac": round(152 * nf / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "drag_gme": lat.force(1, 1)[0]}
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -206,6 +248,7 @@ def main() -> int:
     ap.add_argument("--no-mrt-case", action="store_true")
     ap.add_argument("--no-free-case", action="store_true")
     ap.add_argument("--no-ibb-case", action="store_true")
+    ap.add_argument("--no-3d-case", action="store_true")
     ap.add_argument("--free-steps", type=int, default=4000)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-warm-start", action="store_true")
@@ -294,6 +337,8 @@ def main() -> int:
     if not args.no_free_case:
         extra["free_sedimentation_1200x120"] = run_sedimentation(lc, pkg, torch, args.free_steps)
         torch.cuda.empty_cache()
+    if not args.no_3d_case:
+        extra["three_d"] = run_3d(pkg, torch, 2000)
     if not args.no_hbm_case:
         big = lc.periodic_cylinders()
         big_steps = 200

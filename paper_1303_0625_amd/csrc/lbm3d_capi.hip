@@ -364,7 +364,8 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
     if (!c || n < 0) return LBM_EINVAL;
     if (n == 0) return LBM_OK;
     const Args a = args3(c);
-    const int n_lead = (c->L.nchunks + 1 + 7) / 8 * 8;
+    const int n_fin = (c->ns + 1) * 12;  // one finalizer workgroup per (solid, component)
+    const int n_lead = (c->L.nchunks + n_fin + 7) / 8 * 8;
     const int64_t lines = (int64_t)c->g.ny * c->g.nz;
     const int64_t waves = lines * (c->L.pitch / 64);
     const unsigned grid = (unsigned)(n_lead + (waves + kBlock / 64 - 1) / (kBlock / 64));
@@ -405,7 +406,8 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
         }
         c->t += 1;
     }
-    k3_finalize<<<1, kBlock, 0, c->stream>>>(p.partial, p.solid_chunk0, p.hist, p.tctr, (int)(c->t & 1), a);
+    k3_finalize<<<(unsigned)n_fin, kBlock, 0, c->stream>>>(p.partial, p.solid_chunk0, p.hist, p.tctr,
+                                                           (int)(c->t & 1), a);
     HIPCHK3(c, hipGetLastError());
     return LBM_OK;
 }

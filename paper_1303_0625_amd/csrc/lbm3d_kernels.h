@@ -9,7 +9,8 @@
 // node, layout [z][y][19][pitch] (the nineteen population rows of one (y, z)
 // line are contiguous), two ping-pong buffers by step parity.  One launch per
 // step: force workgroups (512 links each, fixed-order partials), one
-// finalizer workgroup (previous step's totals in chunk order, then the step
+// finalizer workgroup per (solid, force or torque component) forming the
+// previous step's totals in a fixed order (the first also advances the step
 // counter), and from n_lead on the update workgroups (one thread per node, a
 // wave = 64 consecutive x of one line).
 #pragma once
@@ -180,37 +181,54 @@ __device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ pa
     }
 }
 
-// Totals of step `step` per solid from its chunk partials, in chunk order.
+// Total of component q of solid s at step `step` from the chunk partials
+// (one workgroup per (s, q)): thread j sums chunks j, j + 256, ... in order,
+// then a fixed shuffle tree per wave and the four waves in order, so the
+// result does not depend on scheduling.
 __device__ inline void finalize3(const double* __restrict__ partial, const int* __restrict__ solid_chunk0,
-                                 double* __restrict__ hist, int64_t step, const Args& a) {
-    const int64_t slot = step % a.hist_cap;
-    const int nsol = a.ns + 1;
-    for (int r = threadIdx.x; r < nsol * 12; r += kBlock) {
-        const int s = r / 12, q = r % 12;
-        double v = 0.0;
-        for (int cc = solid_chunk0[s]; cc < solid_chunk0[s + 1]; ++cc) v += partial[cc * 12 + q];
-        hist[(slot * nsol + s) * 12 + q] = v;
-    }
+                                 double* __restrict__ hist, int64_t step, int pair, const Args& a,
+                                 double* red) {
+    const int s = pair / 12, q = pair % 12;
+    const int c0 = solid_chunk0[s], c1 = solid_chunk0[s + 1];
+    double v = 0.0;
+    for (int cc = c0 + (int)threadIdx.x; cc < c1; cc += kBlock) v += partial[cc * 12 + q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        hist[((step % a.hist_cap) * (a.ns + 1) + s) * 12 + q] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Update of node (x, line): pull the nineteen populations (all loads issued
 // before any is used), replace those whose source is solid by the half-way
 // bounce-back of the node's own opposite population plus 6 w_i rho0
 // (e_i . v), v the surface velocity at x - e_i/2; collide; store.
+// A wave covers 64 consecutive x of one line, so y and z (and every source
+// line) are wave-uniform: each access is a scalar line base plus a 32-bit
+// lane offset (x - 1, x or x + 1, wrapped).
+template <typename T>
+__device__ inline const T* at3(const T* base, uint32_t idx) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+
 template <typename T, bool NT>
 __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a) {
     const T* fin = (const T*)p.fin;
     T* fout = (T*)p.fout;
     const int64_t line = (int64_t)z * a.ny + y;
-    const uint8_t self = p.own[line * a.pitch + x];
+    const uint32_t ux = (uint32_t)x;
+    const uint32_t uxm = (uint32_t)(x == 0 ? a.nx - 1 : x - 1), uxp = (uint32_t)(x == a.nx - 1 ? 0 : x + 1);
+    const uint8_t self = *at3(p.own + line * a.pitch, ux);
     T raw[kQ];
     uint8_t src[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        const int xs = wrap3(x - kE[i][0], a.nx), ys = wrap3(y - kE[i][1], a.ny), zs = wrap3(z - kE[i][2], a.nz);
+        const uint32_t xs = kE[i][0] == 1 ? uxm : (kE[i][0] == -1 ? uxp : ux);
+        const int ys = wrap3(y - kE[i][1], a.ny), zs = wrap3(z - kE[i][2], a.nz);
         const int64_t ls = (int64_t)zs * a.ny + ys;
-        src[i] = p.own[ls * a.pitch + xs];
-        const T* ptr = fin + (ls * kQ + i) * a.pitch + xs;
+        src[i] = *at3(p.own + ls * a.pitch, xs);
+        const T* ptr = at3(fin + (ls * kQ + i) * a.pitch, xs);
         if constexpr (NT)
             raw[i] = __builtin_nontemporal_load(ptr);
         else
@@ -230,14 +248,14 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
             const int s = src[i] == kDuct ? 0 : (int)src[i];
             double v[3], r[3];
             surface_vel(p.sol, s, x - 0.5 * kE[i][0], y - 0.5 * kE[i][1], z - 0.5 * kE[i][2], a, v, r);
-            d[i] = (double)Sto<T>::ld(fin[(line * kQ + opp3(i)) * a.pitch + x]) +
+            d[i] = (double)Sto<T>::ld(*at3(fin + (line * kQ + opp3(i)) * a.pitch, ux)) +
                    6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
         }
     }
     collide3(d, a);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        T* ptr = fout + (line * kQ + i) * a.pitch + x;
+        T* ptr = const_cast<T*>(at3(fout + (line * kQ + i) * a.pitch, ux));
         const T val = Sto<T>::st(d[i]);
         if constexpr (NT)
             __builtin_nontemporal_store(val, ptr);
@@ -246,6 +264,9 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
     }
 }
 
+// Workgroups [0, nchunks) force chunks, the next (ns + 1) * 12 the previous
+// step's totals (the first also advances the step counter), update
+// workgroups from n_lead (a multiple of 8) on.
 template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead, Args a) {
     __shared__ double red[kBlock / 64][12];
@@ -254,29 +275,35 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
         const int64_t t = p.tctr[parity];
         if (b < a.nchunks) {
             force_role3<T>(b, p, p.partial + (size_t)(t & 1) * a.nchunks * 12, a, red);
-        } else if (b == a.nchunks) {
+        } else if (b < a.nchunks + (a.ns + 1) * 12) {
+            const int pair = b - a.nchunks;
             if (t >= 1)
-                finalize3(p.partial + (size_t)((t - 1) & 1) * a.nchunks * 12, p.solid_chunk0, p.hist, t - 1, a);
-            if (threadIdx.x == 0) p.tctr[parity ^ 1] = t + 1;
+                finalize3(p.partial + (size_t)((t - 1) & 1) * a.nchunks * 12, p.solid_chunk0, p.hist, t - 1, pair,
+                          a, &red[0][0]);
+            if (pair == 0 && threadIdx.x == 0) p.tctr[parity ^ 1] = t + 1;
         }
         return;
     }
     const uint32_t wpr = (uint32_t)a.pitch >> 6;
-    const uint32_t gw = (uint32_t)(b - n_lead) * (kBlock / 64) + (uint32_t)(threadIdx.x >> 6);
+    const uint32_t gw = (uint32_t)(b - n_lead) * (kBlock / 64) +
+                        (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t line = gw / wpr;
     const int x = (int)((gw - line * wpr) << 6) + (int)(threadIdx.x & 63);
     if (line >= (uint32_t)(a.ny * a.nz) || x >= a.nx) return;
     update3<T, NT>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a);
 }
 
-// Totals of the last step tctr[parity] - 1 after a run of steps.
+// Totals of the last step tctr[parity] - 1 after a run of steps, one
+// workgroup per (solid, component).
 __global__ __launch_bounds__(kBlock) void k3_finalize(const double* __restrict__ partial2,
                                                       const int* __restrict__ solid_chunk0,
                                                       double* __restrict__ hist, const int64_t* __restrict__ tctr,
                                                       int parity, Args a) {
+    __shared__ double red[kBlock / 64];
     const int64_t t = tctr[parity];
     if (t < 1) return;
-    finalize3(partial2 + (size_t)((t - 1) & 1) * a.nchunks * 12, solid_chunk0, hist, t - 1, a);
+    finalize3(partial2 + (size_t)((t - 1) & 1) * a.nchunks * 12, solid_chunk0, hist, t - 1, (int)blockIdx.x, a,
+              red);
 }
 
 // f = f_eq(rho0, u0) at every fluid node, collided once; solid nodes zero.
