@@ -7,6 +7,9 @@
 * 256 x 256 periodic crop around one cylinder: FP16 and BF16 offset storage
   against the FP64 oracle over 5000 steps (drag within 1e-3, final step and
   the relative L2 error of Eq. 11 over the history).
+* The same 2048 x 1024 workload with interpolated bounce-back (FP64 against
+  the oracle, FP32 against FP64), and the three-dimensional tube of the
+  benchmark (FP64 and FP32 against the oracle).
 """
 import sys
 
@@ -120,3 +123,95 @@ def test_periodic_crop_reduced_precision_levels(oracle_mod, pkg, dtype):
 def test_periodic_crop_reduced_precision_target(oracle_mod, pkg, dtype):
     final, hist = _crop_errors(oracle_mod, pkg, dtype)
     assert final <= 1e-3 and hist <= 1e-3
+
+
+def test_moving_cylinders_fullsize_ibb(oracle_mod, pkg):
+    """The benchmark's interpolated-bounce-back leg at full size: FP64 GPU
+    against the oracle over a short run (every field, every force), then the
+    FP32 launch configuration the benchmark times against the FP64 GPU path
+    over 2000 steps (drag within 1e-5 as above)."""
+    c = lc.moving_cylinders()
+    steps = 30
+    _say(f"{c['name']} interpolated bounce-back f64 vs oracle, {steps} steps")
+    lat = pkg.Lattice(c, dtype="f64", history_steps=steps)
+    lat.set_boundary(True)
+    lat.step(steps)
+    o = oracle_sim(oracle_mod, c)
+    o.set_ibb(True)
+    o.step(steps)
+    e = field_errors([a.cpu().numpy() for a in lat.fields("f64")], o.fields())
+    _say(f"field rel err rho={e[0]:.3e} u={e[1]:.3e}")
+    assert max(e) <= 1e-12
+    h = lat.force_history().cpu().numpy()
+    oh = oracle_history(o, len(c["bodies"]))
+    norm, rel, where = force_errors(h, oh, c, 1e-10, link_load(o, len(c["bodies"])))
+    _say(f"force rel err {rel:.3e}; normalised {norm:.3f} at {where}")
+    assert norm <= 1.0
+    del lat
+    steps = 2000
+    ref = pkg.Lattice(c, dtype="f64", history_steps=steps)
+    ref.set_boundary(True)
+    ref.step(steps)
+    lat = pkg.Lattice(c, dtype="f32", history_steps=steps)
+    lat.set_boundary(True)
+    lat.step(steps)
+    h = lat.force_history().cpu().numpy()
+    hr = ref.force_history().cpu().numpy()
+    med = np.median(np.abs(hr[-1, 1:, 0]))
+    worst = 0.0
+    for s in range(1, len(c["bodies"]) + 1):
+        for comp in (0, 3):
+            scale = max(abs(hr[-1, s, comp]), med)
+            worst = max(worst, abs(h[-1, s, comp] - hr[-1, s, comp]) / scale)
+    _say(f"ibb f32 final drag rel err (worst cylinder) {worst:.3e}")
+    assert worst <= 1e-5
+
+
+def test_tube_3d_fullsize(oracle_mod, pkg):
+    """The benchmark's three-dimensional workload (the paper's tube, 150 x 42
+    x 42, sphere r = 5.9 at r*/R = 0.21): FP64 GPU against the oracle (fields
+    and forces) and the FP32 launch configuration the benchmark times against
+    the oracle's drag, over 100 steps."""
+    n, R, r = 42, 19.34, 5.9
+    cy = (n - 1) / 2
+    c = dict(nx=150, ny=n, nz=n, tau=0.6, duct=1, R=R, g=(1.825e-5 / 150, 0.0, 0.0),
+             spheres=[dict(cx=37.5, cy=cy + 0.21 * R, cz=cy, r=r)])
+    steps = 100
+    _say(f"tube 150x42x42 f64/f32 vs oracle, {steps} steps")
+    o = oracle_mod.OracleSim3D(c["nx"], n, n, c["tau"], g=c["g"], duct=1, R=R, spheres=c["spheres"])
+    o.step(steps)
+    oh = np.concatenate([o.force_history(0), o.force_history(1)], axis=2)
+    lat = pkg.Lattice3D(c, dtype="f64", history_steps=steps)
+    lat.step(steps)
+    rho, u, own = (a.cpu().numpy() for a in lat.fields())
+    orho, ou, oown = o.fields()
+    assert np.array_equal(own, oown)
+    fl = own == 0
+    # The driving force of this workload is tiny (g = 1.2e-7): after 100 steps
+    # |u| ~ 1e-5 and the sphere's drag is ~1e-4 of a single link's exchange,
+    # so the bars come from the arithmetic (R21): velocity within 64 eps
+    # absolute (the oracle sums full populations of size <= 1/3), forces
+    # within 1e-10 relative plus 16 eps times the summed link magnitudes
+    # (about 2 rho w_i <= 1/9 per link; re-ordered sums).
+    eps = np.finfo(np.float64).eps
+    er = np.abs(rho - orho)[fl].max() / orho[fl].max()
+    du = np.abs(u[:, fl] - ou[:, fl]).max()
+    h = lat.force_history().cpu().numpy()
+    slack = 16 * eps * lat.link_count() / 9
+    worst = 0.0
+    for s in (0, 1):
+        for b in (0, 3, 6, 9):
+            scale = np.abs(oh[:, s, b:b + 3]).max()
+            err = np.abs(h[:, s, b:b + 3] - oh[:, s, b:b + 3]).max()
+            worst = max(worst, err / (1e-10 * scale + slack))
+    _say(f"f64 rel err rho {er:.3e}; |du| {du:.3e} (max |u| {np.abs(ou[:, fl]).max():.3e}); "
+         f"force error / bar {worst:.3f}")
+    assert er <= 1e-12 and du <= 64 * eps and worst <= 1.0
+    del lat
+    lat = pkg.Lattice3D(c, dtype="f32", history_steps=steps)
+    lat.step(steps)
+    h = lat.force_history().cpu().numpy()
+    for col in (0, 6):
+        rel = np.abs(h[20:, 1, col] - oh[20:, 1, col]).max() / np.abs(oh[20:, 1, col]).max()
+        _say(f"f32 drag rel err col {col}: {rel:.3e} (drag {oh[-1, 1, col]:.3e})")
+        assert rel <= 1e-5
