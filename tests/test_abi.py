@@ -99,3 +99,35 @@ def test_batch_workspace_validation(L):
     assert "dtype" in str(e.value)
     with pytest.raises(L.LBMError):
         L.lbm_batch_workspace_bytes([], [], [])
+
+
+def test_3d_validation(L):
+    """lbm3d_workspace_bytes validates on the host (no device needed)."""
+    tube = dict(nx=24, ny=20, nz=20, tau=0.7, duct=L.LBM3D_TUBE, R=8.0,
+                spheres=[dict(cx=10.0, cy=9.5, cz=9.5, r=3.0)])
+
+    def bytes_for(case, dtype="f64", hist=16):
+        return L.lbm3d_workspace_bytes(L.make_grid3(case, dtype), case.get("spheres", ()), hist)
+
+    n16 = bytes_for(tube)
+    assert n16 > 2 * 19 * 20 * 20 * 64 * 8
+    assert bytes_for(tube, hist=1000) > n16
+    assert bytes_for(tube, "f32") < n16
+    E = L.LBMError
+    with pytest.raises(E):
+        bytes_for(dict(tube, tau=0.5))
+    g = L.make_grid3(tube)
+    g.dtype = L.LBM_F16
+    with pytest.raises(E):
+        L.lbm3d_workspace_bytes(g, tube["spheres"], 16)
+    with pytest.raises(E):  # the sphere reaches the tube wall
+        bytes_for(dict(tube, spheres=[dict(cx=10.0, cy=15.5, cz=9.5, r=3.0)]))
+    assert "sphere" in L.load_library().lbm3d_last_error(None).decode()
+    with pytest.raises(E):  # two spheres overlap
+        bytes_for(dict(tube, spheres=[dict(cx=10.0, cy=9.5, cz=9.5, r=2.5), dict(cx=13.0, cy=9.5, cz=9.5, r=2.5)]))
+    with pytest.raises(E):  # link codes hold 2^27 nodes
+        bytes_for(dict(nx=1024, ny=512, nz=256, tau=0.7))
+    with pytest.raises(E):  # surface speed
+        bytes_for(dict(tube, spheres=[dict(cx=10.0, cy=9.5, cz=9.5, r=3.0, v=(0.3, 0.0, 0.0))]))
+    with pytest.raises(E):
+        bytes_for(dict(tube, R=1.0))

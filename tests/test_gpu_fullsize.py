@@ -215,3 +215,28 @@ def test_tube_3d_fullsize(oracle_mod, pkg):
         rel = np.abs(h[20:, 1, col] - oh[20:, 1, col]).max() / np.abs(oh[20:, 1, col]).max()
         _say(f"f32 drag rel err col {col}: {rel:.3e} (drag {oh[-1, 1, col]:.3e})")
         assert rel <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_periodic_crop_reduced_precision_ibb(oracle_mod, pkg, dtype, cache={}):
+    """FP16/BF16 offset storage with interpolated bounce-back on the periodic
+    crop: the same regression levels as with half-way bounce-back (the
+    interpolated rule computes in the storage's arithmetic type, FP32)."""
+    c = lc.periodic_crop()
+    steps = c["steps"]
+    _say(f"{c['name']} {dtype} interpolated bounce-back vs oracle, {steps} steps")
+    lat = pkg.Lattice(c, dtype=dtype, history_steps=steps)
+    lat.set_boundary(True)
+    lat.step(steps)
+    if "oracle" not in cache:
+        o = oracle_sim(oracle_mod, c)
+        o.set_ibb(True)
+        o.step(steps)
+        cache["oracle"] = oracle_history(o, 1)
+    oh = cache["oracle"]
+    h = lat.force_history().cpu().numpy()
+    final = abs(h[-1, 1, 3] - oh[-1, 1, 3]) / abs(oh[-1, 1, 3])
+    hist = rel_l2(h[:, 1, 3], oh[:, 1, 3])
+    _say(f"ibb {dtype}: GME drag rel err final {final:.3e}, Eq. 11 history {hist:.3e}")
+    lf, lh = LEVELS[dtype]
+    assert final <= lf and hist <= lh
