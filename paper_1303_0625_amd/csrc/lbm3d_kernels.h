@@ -88,15 +88,26 @@ __device__ inline void collide3(double d[kQ], const Args& a) {
     const double uu = ux * ux + uy * uy + uz * uz;
     const double om = 1.0 / a.tau, cs = 1.0 - 0.5 / a.tau;
     const double uF = ux * Fx + uy * Fy + uz * Fz;
+    // equilibrium deviation w (rho - rho0) + w rho (3 eu + 4.5 eu^2 - 1.5 u^2)
+    // and Guo source w [3 (e - u) + 9 (e . u) e] . F, split into the parts
+    // even and odd in e_i, so that each opposite pair (i, i + 1) shares one
+    // evaluation
+    {
+        const double deq0 = w3(0) * (drho - rho * 1.5 * uu);
+        const double src0 = w3(0) * (-3.0 * uF);
+        d[0] = d[0] - om * (d[0] - deq0) + cs * src0;
+    }
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
+    for (int i = 1; i < kQ; i += 2) {
+        const double w = w3(i);
         const double eu = kE[i][0] * ux + kE[i][1] * uy + kE[i][2] * uz;
         const double eF = kE[i][0] * Fx + kE[i][1] * Fy + kE[i][2] * Fz;
-        // equilibrium deviation: w (rho - rho0) + w rho (3 eu + 4.5 eu^2 - 1.5 u^2)
-        const double deq = w3(i) * (drho + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
-        // Guo source: w [3 (e - u) + 9 (e . u) e] . F
-        const double src = w3(i) * (3.0 * (eF - uF) + 9.0 * eu * eF);
-        d[i] = d[i] - om * (d[i] - deq) + cs * src;
+        const double ev = w * (drho + rho * (4.5 * eu * eu - 1.5 * uu));
+        const double od = w * (3.0 * rho * eu);
+        const double sev = w * (9.0 * eu * eF - 3.0 * uF);
+        const double sod = w * (3.0 * eF);
+        d[i] = d[i] - om * (d[i] - (ev + od)) + cs * (sev + sod);
+        d[i + 1] = d[i + 1] - om * (d[i + 1] - (ev - od)) + cs * (sev - sod);
     }
 }
 
