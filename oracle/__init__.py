@@ -314,6 +314,13 @@ def _load3():
     lib.orc3_link_force.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, dp]
     lib.orc3_get_f.argtypes = [ctypes.c_void_p, dp]
     lib.orc3_set_f.argtypes = [ctypes.c_void_p, dp]
+    lib.orc3_set_moving.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc3_set_moving.restype = ctypes.c_int
+    lib.orc3_error.argtypes = [ctypes.c_void_p]
+    lib.orc3_error.restype = ctypes.c_int
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    lib.orc3_refill_node.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, u8p, u8p, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
     lib._orc3_bound = True
     return lib
 
@@ -339,6 +346,21 @@ def link_force3(i: int, a: float, b: float, v, scheme: int) -> np.ndarray:
     out = np.zeros(3)
     _load3().orc3_link_force(int(i), float(a), float(b), _dp(_vec(v)), int(scheme), _dp(out))
     return out
+
+
+def refill_node3(fn, own_t, own_n, x, y, z, scheme):
+    """Refill of a newborn node from post-advection values fn [19, nz, ny, nx]
+    and the owner maps of steps t and t + 1; (values, participant count)."""
+    fn = np.ascontiguousarray(fn, dtype=np.float64)
+    ot = np.ascontiguousarray(own_t, dtype=np.uint8)
+    on = np.ascontiguousarray(own_n, dtype=np.uint8)
+    _, nz, ny, nx = fn.shape
+    out = np.zeros(19)
+    npart = ctypes.c_int()
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    _load3().orc3_refill_node(nx, ny, nz, _dp(fn), ot.ctypes.data_as(u8p), on.ctypes.data_as(u8p), int(x), int(y),
+                              int(z), int(scheme), ctypes.byref(npart), _dp(out))
+    return out, npart.value
 
 
 class OracleSim3D:
@@ -367,6 +389,15 @@ class OracleSim3D:
         if h:
             self._lib.orc3_destroy(h)
             self._h = None
+
+    def set_moving(self, sphere: int, moving: bool = True, refill: int = 0) -> None:
+        """Sphere `sphere` (1-based) translates at its v; refill A1/A2/A3 (0/1/2)."""
+        if self._lib.orc3_set_moving(self._h, int(sphere), int(bool(moving)), int(refill)) != 0:
+            raise ValueError("oracle rejected the moving sphere")
+
+    @property
+    def error(self) -> int:
+        return self._lib.orc3_error(self._h)
 
     @property
     def t(self) -> int:

@@ -15,9 +15,18 @@
  *   advect    Eq. 3; a population whose source node is solid is the half-way
  *             bounce-back of the node's own opposite population plus
  *             6 w_i ρ0 (e_i . v), v the surface velocity at the link midpoint
- * Geometry is fixed: spheres carry a rigid surface motion V + Ω x (p - X) but
- * do not move; the duct is a circular tube along x (nodes farther than R from
- * the axis are solid), two solid planes z = 0 and z = nz - 1, or nothing.
+ * Spheres carry a rigid surface motion V + Ω x (p - X); a sphere marked
+ * moving also translates, X(t) = X0 + t V (product and sum rounded
+ * separately), and after advection the geometry of step t + 1 is rasterised:
+ * nodes it covers leave the fluid, newborn nodes (solid at t, fluid at t + 1)
+ * are refilled from the post-advection values of old-fluid neighbours along
+ * every participating direction k (A1: 3 f(x+e_k) - 3 f(x+2e_k) + f(x+3e_k),
+ * A2: 2 f(x+e_k) - f(x+2e_k), A3: f(x+e_k), falling back A1 -> A2 -> A3 where
+ * the farther nodes are not old fluid), averaged over the participants, or
+ * f_eq(rho0, v) at the node's surface velocity when none participates
+ * (Sec. IV.B written for D3Q19).  The duct is a circular tube along x (nodes
+ * farther than R from the axis are solid), two solid planes z = 0 and
+ * z = nz - 1, or nothing.
  * Every axis is periodic (the duct walls are solid nodes).  Summation orders
  * are fixed: nodes in (z, y, x) order, directions in index order.
  *
@@ -46,7 +55,11 @@ struct orc3_sim {
     double R;
     int ns;
     double* sp;  /* ns x 10: X[3], r, V[3], Om[3] */
+    int* moving; /* per sphere: translates at V */
+    int refill;  /* ORC3_A1 / A2 / A3 */
+    int err;     /* geometry error met while stepping */
     unsigned char* own;
+    unsigned char* own_n;
     double *f, *ft, *fn; /* [19][nz][ny][nx] */
     long t;
     double* hist; /* per step (ns + 1) x 12: CME F, T, GME F, T */
@@ -60,10 +73,17 @@ static long pidx(const orc3_sim* s, int i, int x, int y, int z) {
     return (long)i * s->nx * s->ny * s->nz + nidx(s, x, y, z);
 }
 static int wrap(int a, int n) { return ((a % n) + n) % n; }
+
+/* Centre of sphere k at step t. */
+static void centre(const orc3_sim* s, int k, long t, double X[3]) {
+    const double* p = s->sp + 10 * k;
+    for (int d = 0; d < 3; ++d) X[d] = s->moving[k] ? p[d] + (double)t * p[4 + d] : p[d];
+}
 static double min_image(double d, int n) { return d - (double)n * floor(d / (double)n + 0.5); }
 
-/* Solid membership: the duct first, then the spheres (minimum image). */
-static int classify(const orc3_sim* s, int x, int y, int z, int* overlap) {
+/* Solid membership at step t: the duct first, then the spheres (minimum
+ * image). */
+static int classify(const orc3_sim* s, int x, int y, int z, long t, int* overlap) {
     int duct = 0;
     if (s->duct == ORC3_TUBE) {
         double dy = (double)y - 0.5 * (s->ny - 1), dz = (double)z - 0.5 * (s->nz - 1);
@@ -74,9 +94,11 @@ static int classify(const orc3_sim* s, int x, int y, int z, int* overlap) {
     int owner = duct ? 255 : 0;
     for (int k = 0; k < s->ns; ++k) {
         const double* p = s->sp + 10 * k;
-        double dx = min_image((double)x - p[0], s->nx);
-        double dy = min_image((double)y - p[1], s->ny);
-        double dz = min_image((double)z - p[2], s->nz);
+        double X[3];
+        centre(s, k, t, X);
+        double dx = min_image((double)x - X[0], s->nx);
+        double dy = min_image((double)y - X[1], s->ny);
+        double dz = min_image((double)z - X[2], s->nz);
         if (dx * dx + dy * dy + dz * dz <= p[3] * p[3]) {
             if (owner != 0) *overlap = 1;
             owner = k + 1;
@@ -85,17 +107,19 @@ static int classify(const orc3_sim* s, int x, int y, int z, int* overlap) {
     return owner;
 }
 
-/* Rigid surface velocity of solid `owner` at point (px, py, pz); the duct
- * is at rest. */
-static void surface_velocity(const orc3_sim* s, int owner, double px, double py, double pz, double v[3],
+/* Rigid surface velocity of solid `owner` at point (px, py, pz) at step t;
+ * the duct is at rest. */
+static void surface_velocity(const orc3_sim* s, int owner, long t, double px, double py, double pz, double v[3],
                              double r[3]) {
     v[0] = v[1] = v[2] = 0.0;
     r[0] = r[1] = r[2] = 0.0;
     if (owner == 255 || owner == 0) return;
     const double* p = s->sp + 10 * (owner - 1);
-    r[0] = min_image(px - p[0], s->nx);
-    r[1] = min_image(py - p[1], s->ny);
-    r[2] = min_image(pz - p[2], s->nz);
+    double X[3];
+    centre(s, owner - 1, t, X);
+    r[0] = min_image(px - X[0], s->nx);
+    r[1] = min_image(py - X[1], s->ny);
+    r[2] = min_image(pz - X[2], s->nz);
     const double* V = p + 4;
     const double* Om = p + 7;
     v[0] = V[0] + (Om[1] * r[2] - Om[2] * r[1]);
@@ -156,15 +180,17 @@ orc3_sim* orc3_create(int nx, int ny, int nz, double tau, double rho0, const dou
     s->ns = ns;
     s->sp = (double*)malloc(sizeof(double) * 10 * (ns > 0 ? ns : 1));
     if (ns > 0) memcpy(s->sp, spheres, sizeof(double) * 10 * ns);
+    s->moving = (int*)calloc((size_t)(ns > 0 ? ns : 1), sizeof(int));
     long N = (long)nx * ny * nz;
     s->own = (unsigned char*)calloc((size_t)N, 1);
+    s->own_n = (unsigned char*)calloc((size_t)N, 1);
     s->f = (double*)calloc((size_t)(19 * N), sizeof(double));
     s->ft = (double*)calloc((size_t)(19 * N), sizeof(double));
     s->fn = (double*)calloc((size_t)(19 * N), sizeof(double));
     int overlap = 0;
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
-            for (int x = 0; x < nx; ++x) s->own[nidx(s, x, y, z)] = (unsigned char)classify(s, x, y, z, &overlap);
+            for (int x = 0; x < nx; ++x) s->own[nidx(s, x, y, z)] = (unsigned char)classify(s, x, y, z, 0, &overlap);
     if (overlap) {
         orc3_destroy(s);
         return NULL;
@@ -182,7 +208,9 @@ orc3_sim* orc3_create(int nx, int ny, int nz, double tau, double rho0, const dou
 void orc3_destroy(orc3_sim* s) {
     if (!s) return;
     free(s->sp);
+    free(s->moving);
     free(s->own);
+    free(s->own_n);
     free(s->f);
     free(s->ft);
     free(s->fn);
@@ -201,6 +229,42 @@ static double* hist_row(orc3_sim* s, long t) {
         s->hist_cap = cap;
     }
     return s->hist + t * row;
+}
+
+/* Refill of newborn node (x, y, z) from post-advection values fn
+ * [19][nz][ny][nx]: the average over participating directions k (x + e_k old
+ * fluid: fluid in own_t and own_n) of A1/A2/A3 along k, the scheme falling
+ * back A1 -> A2 -> A3 where x + 2e_k or x + 3e_k is not old fluid.  *np
+ * receives the participant count (out is untouched when it is zero). */
+void orc3_refill_node(int nx, int ny, int nz, const double* fn, const unsigned char* own_t,
+                      const unsigned char* own_n, int x, int y, int z, int scheme0, int* np_out, double out[19]) {
+    const long N = (long)nx * ny * nz;
+    double acc[19] = {0.0};
+    int np = 0;
+    for (int k = 1; k < 19; ++k) {
+        long q[4] = {0, 0, 0, 0};
+        int old[4] = {0, 0, 0, 0};
+        for (int m = 1; m <= 3; ++m) {
+            q[m] = ((long)wrap(z + m * E[k][2], nz) * ny + wrap(y + m * E[k][1], ny)) * nx + wrap(x + m * E[k][0], nx);
+            old[m] = own_t[q[m]] == 0 && own_n[q[m]] == 0;
+            if (!old[m]) break;
+        }
+        if (!old[1]) continue;
+        int scheme = scheme0;
+        if (scheme == ORC3_A1 && !(old[2] && old[3])) scheme = ORC3_A2;
+        if (scheme == ORC3_A2 && !old[2]) scheme = ORC3_A3;
+        ++np;
+        for (int j = 0; j < 19; ++j) {
+            const double f1 = fn[(long)j * N + q[1]];
+            double v = f1;
+            if (scheme == ORC3_A2) v = 2.0 * f1 - fn[(long)j * N + q[2]];
+            if (scheme == ORC3_A1) v = 3.0 * f1 - 3.0 * fn[(long)j * N + q[2]] + fn[(long)j * N + q[3]];
+            acc[j] += v;
+        }
+    }
+    *np_out = np;
+    if (np > 0)
+        for (int j = 0; j < 19; ++j) out[j] = acc[j] / np;
 }
 
 static void one_step(orc3_sim* s) {
@@ -227,7 +291,7 @@ static void one_step(orc3_sim* s) {
                     int o = s->own[nidx(s, xb, yb, zb)];
                     if (o == 0) continue;
                     double v[3], r[3];
-                    surface_velocity(s, o, x + 0.5 * E[i][0], y + 0.5 * E[i][1], z + 0.5 * E[i][2], v, r);
+                    surface_velocity(s, o, s->t, x + 0.5 * E[i][0], y + 0.5 * E[i][1], z + 0.5 * E[i][2], v, r);
                     double a = s->ft[pidx(s, i, x, y, z)];
                     double b = a - 6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
                     double* hs = h + 12 * (o == 255 ? 0 : o);
@@ -257,18 +321,60 @@ static void one_step(orc3_sim* s) {
                         val = s->ft[pidx(s, i, xs, ys, zs)];
                     } else {
                         double v[3], r[3];
-                        surface_velocity(s, o, x - 0.5 * E[i][0], y - 0.5 * E[i][1], z - 0.5 * E[i][2], v, r);
+                        surface_velocity(s, o, s->t, x - 0.5 * E[i][0], y - 0.5 * E[i][1], z - 0.5 * E[i][2], v,
+                                         r);
                         val = s->ft[pidx(s, opposite(i), x, y, z)] +
                               6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
                     }
                     s->fn[pidx(s, i, x, y, z)] = val;
                 }
             }
+    /* moving spheres: geometry of step t + 1, newborn refill */
+    int any_moving = 0;
+    for (int k = 0; k < s->ns; ++k) any_moving |= s->moving[k];
+    if (any_moving) {
+        int overlap = 0;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x)
+                    s->own_n[nidx(s, x, y, z)] = (unsigned char)classify(s, x, y, z, s->t + 1, &overlap);
+        if (overlap) s->err = 1;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const long n = nidx(s, x, y, z);
+                    if (s->own[n] == 0 || s->own_n[n] != 0) continue; /* not newborn */
+                    double acc[19];
+                    int np = 0;
+                    orc3_refill_node(nx, ny, nz, s->fn, s->own, s->own_n, x, y, z, s->refill, &np, acc);
+                    double out[19];
+                    if (np > 0) {
+                        for (int j = 0; j < 19; ++j) out[j] = acc[j];
+                    } else {
+                        double v[3], r[3];
+                        surface_velocity(s, s->own[n], s->t + 1, x, y, z, v, r);
+                        orc3_feq(s->rho0, v, out);
+                    }
+                    for (int j = 0; j < 19; ++j) s->fn[pidx(s, j, x, y, z)] = out[j];
+                }
+        unsigned char* t2 = s->own;
+        s->own = s->own_n;
+        s->own_n = t2;
+    }
     double* tmp = s->f;
     s->f = s->fn;
     s->fn = tmp;
     s->t += 1;
 }
+
+int orc3_set_moving(orc3_sim* s, int sphere, int moving, int refill) {
+    if (sphere < 1 || sphere > s->ns || refill < ORC3_A1 || refill > ORC3_A3 || s->t != 0) return -1;
+    s->moving[sphere - 1] = moving ? 1 : 0;
+    s->refill = refill;
+    return 0;
+}
+
+int orc3_error(const orc3_sim* s) { return s->err; }
 
 void orc3_step(orc3_sim* s, long n) {
     for (long k = 0; k < n; ++k) one_step(s);

@@ -8,6 +8,7 @@ extern "C" {
 
 enum { ORC3_CME = 0, ORC3_GME = 1 };
 enum { ORC3_OPEN = 0, ORC3_TUBE = 1, ORC3_PLANES = 2 };
+enum { ORC3_A1 = 0, ORC3_A2 = 1, ORC3_A3 = 2 };
 
 typedef struct orc3_sim orc3_sim;
 
@@ -34,6 +35,15 @@ int orc3_force(const orc3_sim* s, long step, int solid, int scheme, double out[6
 void orc3_feq(double rho, const double u[3], double out[19]);
 void orc3_collide_node(const double f[19], double tau, const double g[3], double out[19]);
 void orc3_link_force(int i, double a, double b, const double v[3], int scheme, double out[3]);
+
+/* Sphere `sphere` (1-based) translates at its V from step 0 on (before the
+ * first step only); refill: the newborn scheme for all moving spheres.
+ * -1 when rejected. */
+int orc3_set_moving(orc3_sim* s, int sphere, int moving, int refill);
+void orc3_refill_node(int nx, int ny, int nz, const double* fn, const unsigned char* own_t,
+                      const unsigned char* own_n, int x, int y, int z, int scheme, int* np, double out[19]);
+/* Non-zero when a moving sphere met the duct or another sphere. */
+int orc3_error(const orc3_sim* s);
 
 /* pre-collision populations [19][nz][ny][nx] */
 void orc3_get_f(const orc3_sim* s, double* out);

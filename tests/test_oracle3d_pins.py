@@ -172,3 +172,116 @@ def test_spinning_sphere_torque_opposes_spin_3d(oracle_mod, axis):
         assert abs(F[3 + axis]) > 1e3 * max(abs(o) for o in others)
         assert abs(F[3 + axis] - ref.force(1, sch)[5]) <= 1e-12 * abs(F[3 + axis])
         assert np.abs(F[:3]).max() <= 1e-14
+
+
+# ---------------------------------------------------------------- translating spheres (Sec. IV.B in 3D)
+def _poly_field(deg, rng, n=9):
+    """Post-advection values f_j = polynomial of degree deg in (x, y, z)."""
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    fn = np.zeros((19, n, n, n))
+    exact = np.zeros(19)
+    c = n // 2
+    for j in range(19):
+        a = rng.normal(size=10)
+        terms = [np.ones_like(x, dtype=float), x, y, z, x * x, y * y, z * z, x * y, y * z, x * z]
+        p = sum(a[t] * terms[t] for t in range([1, 4, 10][deg]))
+        fn[j] = p
+        exact[j] = p[c, c, c]
+    return fn, exact
+
+
+@pytest.mark.parametrize("scheme,exact_deg,miss_deg", [(0, 2, None), (1, 1, 2), (2, 1, 2)])
+def test_refill_polynomial_exactness_3d(oracle_mod, scheme, exact_deg, miss_deg):
+    """A1 reproduces quadratic fields along every link and A2 linear ones; A3
+    copies the first neighbour, which with all 18 directions taking part is
+    exact for linear fields too (the odd terms cancel in the average); A2 and
+    A3 miss quadratic fields.  With participants on one side only, A3 misses a
+    linear field."""
+    rng = np.random.default_rng(21)
+    n = 9
+    own_t = np.zeros((n, n, n), np.uint8)
+    own_t[4, 4, 4] = 1
+    own_n = np.zeros((n, n, n), np.uint8)
+    for deg in range(3):
+        fn, exact = _poly_field(deg, rng)
+        out, npart = oracle_mod.refill_node3(fn, own_t, own_n, 4, 4, 4, scheme)
+        assert npart == 18
+        err = np.abs(out - exact).max()
+        if deg <= exact_deg:
+            assert err <= 1e-12 * np.abs(fn).max()
+        elif deg == miss_deg:
+            assert err > 1e-3
+    if scheme == 2:
+        one_sided = own_t.copy()
+        one_sided[:, :, :4] = 1  # every node with x < 4 solid at t
+        fn, exact = _poly_field(1, rng)
+        out, npart = oracle_mod.refill_node3(fn, one_sided, own_n, 4, 4, 4, scheme)
+        assert npart == 13  # the directions with e_x = 1 (5) and e_x = 0 (8)
+        assert np.abs(out - exact).max() > 1e-3
+
+
+def test_refill_participants_and_fallback_3d(oracle_mod):
+    """Participants are the directions whose first neighbour is old fluid;
+    where the second or third neighbour is not, A1 falls back to A2 or A3
+    (a linear field is still reproduced exactly, a quadratic one is not)."""
+    n = 9
+    rng = np.random.default_rng(22)
+    own_t = np.zeros((n, n, n), np.uint8)
+    own_t[4, 4, 4] = 1
+    own_t[4, 4, 5] = 1          # +x neighbour solid at t: direction +x does not take part
+    own_n = np.zeros((n, n, n), np.uint8)
+    own_n[4, 4, 6] = 2          # x + 2 e_x... irrelevant (+x excluded); block -x at distance 3
+    own_n[4, 4, 1] = 2          # -x: x - 3 e_x covered at t+1 -> A1 falls back to A2 along -x
+    fn, exact = _poly_field(1, rng)
+    out, npart = oracle_mod.refill_node3(fn, own_t, own_n, 4, 4, 4, 0)
+    assert npart == 17
+    assert np.abs(out - exact).max() <= 1e-12 * np.abs(fn).max()
+    fn2, exact2 = _poly_field(2, rng)
+    out2, _ = oracle_mod.refill_node3(fn2, own_t, own_n, 4, 4, 4, 0)
+    assert np.abs(out2 - exact2).max() > 1e-6  # the -x direction used A2
+    own_t[4, 4, 4] = 1
+    own_t[:, :, :] = 1
+    own_t[4, 4, 4] = 1
+    _, npart = oracle_mod.refill_node3(fn, own_t, own_n, 4, 4, 4, 0)
+    assert npart == 0
+
+
+@pytest.mark.parametrize("refill", [0, 1, 2])
+def test_translating_sphere_comoving_flow_3d(oracle_mod, refill):
+    """A sphere translating with the uniform flow f_eq(1, U) across several
+    nodes (covered and newborn nodes every few steps) leaves the state exactly
+    uniform, with no force, for each refill scheme."""
+    U = (0.05, -0.02, 0.03)
+    sp = dict(cx=9.3, cy=8.6, cz=7.8, r=3.7, v=U)
+    s = oracle_mod.OracleSim3D(22, 18, 16, 0.7, u0=U, spheres=[sp])
+    s.set_moving(1, True, refill)
+    fe = oracle_mod.feq3(1.0, U)
+    _, _, own0 = s.fields()
+    for _ in range(6):
+        s.step(10)
+        f = s.get_f()
+        _, _, own = s.fields()
+        assert np.abs(f[:, own == 0] - fe[:, None]).max() <= 1e-14  # rounding of f ~ 1/3
+        assert np.abs(s.force(1, oracle_mod.GME)[:3]).max() <= 1e-13
+    assert s.error == 0
+    # the geometry of step 60 is the sphere centred at X0 + 60 U (raster
+    # written out here: minimum image, |p - X|^2 <= r^2)
+    nz, ny, nx = own.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X = [sp["cx"] + 60 * U[0], sp["cy"] + 60 * U[1], sp["cz"] + 60 * U[2]]
+
+    def mi(d, n):
+        return d - n * np.floor(d / n + 0.5)
+
+    dx, dy, dz = mi(x - X[0], nx), mi(y - X[1], ny), mi(z - X[2], nz)
+    expect = (dx * dx + dy * dy) + dz * dz <= sp["r"] ** 2
+    assert np.array_equal(own == 1, expect)
+
+
+def test_translating_sphere_meets_tube_3d(oracle_mod):
+    """A sphere driven into the tube wall is reported."""
+    sp = dict(cx=10.0, cy=10.5, cz=10.5, r=3.0, v=(0.0, 0.2, 0.0))
+    s = oracle_mod.OracleSim3D(20, 22, 22, 0.7, duct=oracle_mod.TUBE3, R=9.0, spheres=[sp])
+    s.set_moving(1, True, 0)
+    s.step(40)
+    assert s.error != 0
