@@ -536,8 +536,16 @@ const char* lbm_nn_last_error(const lbm_nn* nn);
  * tube along x (nodes with (y - (ny-1)/2)^2 + (z - (nz-1)/2)^2 > R^2 are
  * solid), the two planes z = 0 and z = nz - 1, or nothing; spheres are solid
  * where (minimum-image) |p - X|^2 <= r^2, each product and sum rounded
- * separately, and their surfaces move rigidly at V + omega x (p - X) without
- * the geometry moving.  One step: the CME (Eq. 4) and GME (Eq. 5) forces of
+ * separately, and their surfaces move rigidly at V + omega x (p - X); a
+ * sphere with moves = 1 also translates, X(t) = X + t V (product and sum
+ * rounded separately): after each step the geometry of the next one is
+ * rasterised and its newborn nodes are refilled as in two dimensions (A1, A2
+ * or A3 of grid->refill along every D3Q19 link whose neighbour stays fluid,
+ * averaged, then collided; the surface-velocity equilibrium when none does).
+ * A moving sphere must keep 2 nodes from the duct and from every other sphere
+ * (lbm3d_step returns LBM_EGEOM before launching otherwise), and its scan box
+ * of 2 ceil(r) + 5 nodes must fit the lattice.  One step: the CME (Eq. 4) and
+ * GME (Eq. 5) forces of
  * every fluid-solid link from the post-collision populations with the torque
  * (Eq. 7) about each sphere's centre at the link midpoint, summed per solid
  * in a fixed order (Eq. 6); pull streaming with half-way bounce-back plus
@@ -555,7 +563,7 @@ typedef struct {
     int32_t nx, ny, nz;   /* lattice size, each >= 4, nx ny nz < 2^27 */
     int32_t dtype;        /* LBM_F64 or LBM_F32 */
     int32_t duct;         /* lbm3d_duct */
-    int32_t reserved;     /* must be 0 */
+    int32_t refill;       /* lbm_refill for the newborn nodes of moving spheres */
     double R;             /* tube radius (LBM3D_TUBE), >= 2 */
     double tau;           /* BGK relaxation time, > 1/2 */
     double rho0;          /* reference and initial density */
@@ -564,10 +572,12 @@ typedef struct {
 } lbm3d_grid;
 
 typedef struct {
-    double X[3];          /* centre */
+    double X[3];          /* centre at t = 0 */
     double r;             /* radius, >= 1 */
     double V[3];          /* surface translation velocity, |V| < 0.3 */
     double omega[3];      /* surface angular velocity */
+    int32_t moves;        /* 1: the sphere translates, X(t) = X + t V */
+    int32_t pad;          /* must be 0 */
 } lbm3d_sphere;
 
 /* Workspace size for a 3D lattice (validates as lbm3d_create does). */

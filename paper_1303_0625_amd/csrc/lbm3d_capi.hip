@@ -32,11 +32,18 @@ size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 constexpr size_t kStreamBytes3 = 256ull << 20;  // Infinity Cache: stream above it
 
 struct Layout3 {
-    size_t f[2], own, links, seg_off, seg_cnt, chunk_solid, chunk_start, solid_chunk0, sol, partial, hist, tctr, total;
+    size_t f[2], own[2], links, seg_off, seg_cnt, chunk_solid, chunk_start, solid_chunk0, sol, partial, hist, tctr,
+        movers, total;
     int pitch;
     int nchunks;
     int64_t nlinks;
+    int box;      // scan-box edge of the moving spheres (0: none moves)
+    int nmovers;
 };
+
+// Scan-box edge of a moving sphere of radius r: the nodes from
+// floor(X - r) - 2 on, far enough to hold every fluid node next to it.
+int box_edge(double r) { return 2 * (int)std::ceil(r) + 5; }
 
 }  // namespace
 
@@ -103,6 +110,7 @@ int owner_of(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, int x, int y, 
 }
 
 const char* validate(const lbm3d_grid* g, const lbm3d_sphere* sp, int ns) {
+    if (g && (g->refill < 0 || g->refill > 2)) return "refill must be LBM_REFILL_A1, A2 or A3";
     if (!g) return "grid is NULL";
     if (g->nx < 4 || g->ny < 4 || g->nz < 4) return "nx, ny, nz must be >= 4";
     if ((int64_t)g->nx * g->ny * g->nz >= (1ll << 27)) return "at most 2^27 nodes (link codes)";
@@ -118,6 +126,10 @@ const char* validate(const lbm3d_grid* g, const lbm3d_sphere* sp, int ns) {
         double s = 0.0;
         for (int d = 0; d < 3; ++d) s += sp[k].V[d] * sp[k].V[d];
         if (!(std::sqrt(s) < 0.3)) return "sphere surface speed must be below 0.3";
+        if (sp[k].moves) {
+            const int b = box_edge(sp[k].r);
+            if (b > g->nx || b > g->ny || b > g->nz) return "a moving sphere's box (2 ceil(r) + 5) exceeds the lattice";
+        }
     }
     return nullptr;
 }
@@ -150,6 +162,7 @@ const char* build_geometry(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, 
                               zb = (z + E[i][2] + nz) % nz;
                     const uint8_t o = own[((size_t)zb * ny + yb) * pitch + xb];
                     if (o == 0) continue;
+                    if (o != kDuct && sp[o - 1].moves) continue;  // found by the box scan each step
                     seg[o == kDuct ? 0 : o].push_back(node << 5 | (uint32_t)i);
                 }
             }
@@ -157,10 +170,15 @@ const char* build_geometry(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, 
     return nullptr;
 }
 
-Layout3 make_layout(const lbm3d_grid& g, int ns, int pitch, const std::vector<std::vector<uint32_t>>& seg,
-                    int64_t hist_cap) {
+Layout3 make_layout(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, int pitch,
+                    const std::vector<std::vector<uint32_t>>& seg, int64_t hist_cap) {
     Layout3 L{};
     L.pitch = pitch;
+    for (int k = 0; k < ns; ++k)
+        if (sp[k].moves) {
+            L.box = std::max(L.box, box_edge(sp[k].r));
+            ++L.nmovers;
+        }
     const size_t es = g.dtype == LBM_F64 ? 8 : 4;
     const size_t fbytes = (size_t)19 * g.ny * g.nz * pitch * es;
     size_t off = 0;
@@ -170,13 +188,17 @@ Layout3 make_layout(const lbm3d_grid& g, int ns, int pitch, const std::vector<st
     off = al256(off + (1u << 20));
     L.f[1] = off;
     off = al256(off + fbytes);
-    L.own = off;
-    off = al256(off + (size_t)g.ny * g.nz * pitch);
+    for (int k = 0; k < 2; ++k) {
+        L.own[k] = off;
+        off = al256(off + (size_t)g.ny * g.nz * pitch);
+    }
     int64_t nl = 0;
     int nch = 0;
-    for (auto& s : seg) {
-        nl += (int64_t)s.size();
-        nch += std::max<int>(1, (int)((s.size() + kChunk - 1) / kChunk));
+    const int64_t box3 = (int64_t)L.box * L.box * L.box;
+    for (size_t s = 0; s < seg.size(); ++s) {
+        nl += (int64_t)seg[s].size();
+        const bool mv = s > 0 && sp[s - 1].moves;
+        nch += mv ? (int)((box3 + kChunk - 1) / kChunk) : std::max<int>(1, (int)((seg[s].size() + kChunk - 1) / kChunk));
     }
     L.nlinks = nl;
     L.nchunks = nch;
@@ -200,6 +222,8 @@ Layout3 make_layout(const lbm3d_grid& g, int ns, int pitch, const std::vector<st
     off = al256(off + 8 * (size_t)hist_cap * (ns + 1) * 12);
     L.tctr = off;
     off = al256(off + 16);
+    L.movers = off;
+    off = al256(off + 4 * (size_t)std::max(L.nmovers, 1));
     L.total = off;
     return L;
 }
@@ -221,6 +245,10 @@ Args args3(const lbm3d_ctx* c) {
     for (int d = 0; d < 3; ++d) a.g[d] = c->g.g[d];
     a.nchunks = c->L.nchunks;
     a.hist_cap = c->hist_cap;
+    a.duct = c->g.duct;
+    a.R = c->g.R;
+    a.box = c->L.box;
+    a.refill = c->g.refill;
     return a;
 }
 
@@ -251,7 +279,7 @@ lbm_status lbm3d_workspace_bytes(const lbm3d_grid* g, const lbm3d_sphere* sphere
         set_err3(g_err3, "%s", why);
         return LBM_EGEOM;
     }
-    *bytes = make_layout(*g, n_spheres, pitch, seg, history_steps).total;
+    *bytes = make_layout(*g, spheres, n_spheres, pitch, seg, history_steps).total;
     return LBM_OK;
 }
 
@@ -282,7 +310,7 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
         set_err3(g_err3, "%s", why);
         return LBM_EGEOM;
     }
-    Layout3 L = make_layout(*g, n_spheres, pitch, seg, history_steps);
+    Layout3 L = make_layout(*g, spheres, n_spheres, pitch, seg, history_steps);
     if (bytes < L.total) {
         set_err3(g_err3, "workspace holds %zu bytes, %zu needed", bytes, L.total);
         return LBM_ESIZE;
@@ -298,13 +326,17 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
     // tables
     std::vector<uint32_t> links;
     std::vector<int> seg_off(n_spheres + 1), seg_cnt(n_spheres + 1), chunk_solid, chunk_start,
-        solid_chunk0(n_spheres + 2);
+        solid_chunk0(n_spheres + 2), movers;
+    const int64_t box3 = (int64_t)L.box * L.box * L.box;
     for (int s = 0; s <= n_spheres; ++s) {
         seg_off[s] = (int)links.size();
         seg_cnt[s] = (int)seg[s].size();
         links.insert(links.end(), seg[s].begin(), seg[s].end());
         solid_chunk0[s] = (int)chunk_solid.size();
-        const int nchk = std::max<int>(1, (int)((seg[s].size() + kChunk - 1) / kChunk));
+        const bool mv = s > 0 && spheres[s - 1].moves;
+        if (mv) movers.push_back(s);
+        const int nchk = mv ? (int)((box3 + kChunk - 1) / kChunk)
+                            : std::max<int>(1, (int)((seg[s].size() + kChunk - 1) / kChunk));
         for (int k = 0; k < nchk; ++k) {
             chunk_solid.push_back(s);
             chunk_start.push_back(k * kChunk);
@@ -320,12 +352,15 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
             r[7 + d] = spheres[k].omega[d];
         }
         r[3] = spheres[k].r;
+        r[10] = spheres[k].moves ? 1.0 : 0.0;
     }
     hipError_t e = hipMemsetAsync(c->ws, 0, L.total, c->stream);
     auto up = [&](size_t off, const void* src, size_t n) {
         if (e == hipSuccess && n > 0) e = hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, c->stream);
     };
-    up(L.own, own.data(), own.size());
+    up(L.own[0], own.data(), own.size());
+    up(L.own[1], own.data(), own.size());
+    up(L.movers, movers.data(), 4 * movers.size());
     up(L.links, links.data(), 4 * links.size());
     up(L.seg_off, seg_off.data(), 4 * seg_off.size());
     up(L.seg_cnt, seg_cnt.data(), 4 * seg_cnt.size());
@@ -343,10 +378,10 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
     const int64_t N = (int64_t)g->ny * g->nz * pitch;
     const unsigned nb = (unsigned)((N + kBlock - 1) / kBlock);
     if (g->dtype == LBM_F64)
-        k3_init<double><<<nb, kBlock, 0, c->stream>>>(at<double>(c, L.f[0]), at<uint8_t>(c, L.own), a, g->u0[0],
-                                                      g->u0[1], g->u0[2]);
+        k3_init<double><<<nb, kBlock, 0, c->stream>>>(at<double>(c, L.f[0]), at<uint8_t>(c, L.own[0]), a,
+                                                      g->u0[0], g->u0[1], g->u0[2]);
     else
-        k3_init<float><<<nb, kBlock, 0, c->stream>>>(at<float>(c, L.f[0]), at<uint8_t>(c, L.own), a, g->u0[0],
+        k3_init<float><<<nb, kBlock, 0, c->stream>>>(at<float>(c, L.f[0]), at<uint8_t>(c, L.own[0]), a, g->u0[0],
                                                      g->u0[1], g->u0[2]);
     k3_set_counters<<<1, 1, 0, c->stream>>>(at<int64_t>(c, L.tctr), 0);
     e = hipGetLastError();
@@ -360,9 +395,53 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
     return LBM_OK;
 }
 
+// Moving spheres over steps [t0, t1]: each keeps 2 nodes from the duct and
+// from every other sphere (so the other solids' link lists stay valid).
+static const char* check_paths3(const lbm3d_ctx* c, int64_t t0, int64_t t1) {
+    const int ns = c->ns;
+    auto centre_at = [&](int k, int64_t t, double X[3]) {
+        const double* S = c->sol.data() + kSolidRow * (k + 1);
+        for (int d = 0; d < 3; ++d) X[d] = S[10] != 0.0 ? S[d] + (double)t * S[4 + d] : S[d];
+    };
+    for (int k = 0; k < ns; ++k) {
+        const double* S = c->sol.data() + kSolidRow * (k + 1);
+        if (S[10] == 0.0) continue;
+        const double r = S[3];
+        for (int64_t t = t0; t <= t1; ++t) {
+            double X[3];
+            centre_at(k, t, X);
+            if (c->g.duct == LBM3D_TUBE) {
+                const double dy = X[1] - 0.5 * (c->g.ny - 1), dz = X[2] - 0.5 * (c->g.nz - 1);
+                if (std::sqrt(dy * dy + dz * dz) + r > c->g.R - 2.0) return "a moving sphere comes within 2 nodes of the tube";
+            } else if (c->g.duct == LBM3D_PLANES) {
+                if (X[2] - r < 2.0 || X[2] + r > c->g.nz - 3.0) return "a moving sphere comes within 2 nodes of a plane";
+            }
+            for (int j = 0; j < ns; ++j) {
+                if (j == k) continue;
+                double Y[3];
+                centre_at(j, t, Y);
+                double d2 = 0.0;
+                const int n3[3] = {c->g.nx, c->g.ny, c->g.nz};
+                for (int d = 0; d < 3; ++d) {
+                    const double dd = mimg(X[d] - Y[d], n3[d]);
+                    d2 += dd * dd;
+                }
+                const double rj = c->sol[kSolidRow * (j + 1) + 3];
+                if (std::sqrt(d2) < r + rj + 2.0) return "a moving sphere comes within 2 nodes of another sphere";
+            }
+        }
+    }
+    return nullptr;
+}
+
 lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
     if (!c || n < 0) return LBM_EINVAL;
     if (n == 0) return LBM_OK;
+    if (c->L.nmovers > 0)
+        if (const char* why = check_paths3(c, c->t, c->t + n + 1)) {
+            set_err3(c->err, "%s", why);
+            return LBM_EGEOM;
+        }
     const Args a = args3(c);
     const int n_fin = (c->ns + 1) * 12;  // one finalizer workgroup per (solid, component)
     const int n_lead = (c->L.nchunks + n_fin + 7) / 8 * 8;
@@ -372,7 +451,6 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
     const size_t es = c->g.dtype == LBM_F64 ? 8 : 4;
     const bool nt = 2 * (size_t)19 * lines * c->L.pitch * es > kStreamBytes3;
     Ptrs p{};
-    p.own = at<uint8_t>(c, c->L.own);
     p.links = at<uint32_t>(c, c->L.links);
     p.seg_off = at<int>(c, c->L.seg_off);
     p.seg_cnt = at<int>(c, c->L.seg_cnt);
@@ -387,6 +465,7 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
         const int par = (int)(c->t & 1);
         p.fin = c->ws + c->L.f[par];
         p.fout = c->ws + c->L.f[par ^ 1];
+        p.own = at<uint8_t>(c, c->L.own[par]);
         const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
         if (timed) HIPCHK3(c, hipEventRecord(c->ev[c->ev_used], c->stream));
         if (c->g.dtype == LBM_F64) {
@@ -399,6 +478,19 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
                 k3_step<float, true><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
             else
                 k3_step<float, false><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
+        }
+        if (c->L.nmovers > 0) {
+            // geometry of step t + 1, then the newborn refill into the step's output
+            uint8_t* own_n = at<uint8_t>(c, c->L.own[par ^ 1]);
+            const int64_t N = (int64_t)c->g.nx * c->g.ny * c->g.nz;
+            k3_raster<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(p.sol, own_n, c->t + 1, a);
+            const int cpm = (int)(((int64_t)c->L.box * c->L.box * c->L.box + kBlock - 1) / kBlock);
+            const unsigned nrb = (unsigned)(cpm * c->L.nmovers);
+            const int* mv = at<int>(c, c->L.movers);
+            if (c->g.dtype == LBM_F64)
+                k3_refill<double><<<nrb, kBlock, 0, c->stream>>>(p, own_n, mv, cpm, c->t, a);
+            else
+                k3_refill<float><<<nrb, kBlock, 0, c->stream>>>(p, own_n, mv, cpm, c->t, a);
         }
         if (timed) {
             HIPCHK3(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
@@ -449,7 +541,7 @@ lbm_status lbm3d_fields(lbm3d_ctx* c, double* d_rho, double* d_u, int32_t* d_own
     const int64_t N = (int64_t)c->g.nx * c->g.ny * c->g.nz;
     const unsigned nb = (unsigned)((N + kBlock - 1) / kBlock);
     const int par = (int)(c->t & 1);
-    const uint8_t* own = at<uint8_t>(c, c->L.own);
+    const uint8_t* own = at<uint8_t>(c, c->L.own[par]);
     if (c->g.dtype == LBM_F64)
         k3_fields<double><<<nb, kBlock, 0, c->stream>>>(at<double>(c, c->L.f[par]), own, a, d_rho, d_u, d_owner);
     else

@@ -44,26 +44,42 @@ struct Args {
     double g[3];      // body force (acceleration)
     int nchunks;      // force workgroups
     int64_t hist_cap;
+    int duct;         // 0 open, 1 tube, 2 planes
+    double R;         // tube radius
+    int box;          // edge of a moving sphere's scan box (nodes)
+    int refill;       // 0 A1, 1 A2, 2 A3
 };
 
-// Solid table row: X, Y, Z, r, V (3), Omega (3), pad (2); row 0 is the duct.
+// Solid table row: X0, Y0, Z0, r, V (3), Omega (3), moves, pad; row 0 is the
+// duct.
 constexpr int kSolidRow = 12;
+
+// Centre of sphere slot s at step t (a moving sphere: X0 + t V, product and
+// sum rounded separately).
+__device__ inline void centre3(const double* __restrict__ sol, int s, int64_t t, double X[3]) {
+#pragma clang fp contract(off)
+    const double* S = sol + kSolidRow * s;
+    const bool mv = S[10] != 0.0;
+    for (int d = 0; d < 3; ++d) X[d] = mv ? S[d] + (double)t * S[4 + d] : S[d];
+}
 
 __device__ inline double min_image3(double d, int n) { return d - (double)n * floor(d / (double)n + 0.5); }
 
-// Rigid surface velocity of solid slot s at point p (duct at rest), and the
-// arm from the centre.
-__device__ inline void surface_vel(const double* __restrict__ sol, int s, double px, double py, double pz,
-                                   const Args& a, double v[3], double r[3]) {
+// Rigid surface velocity of solid slot s at point p at step t (duct at
+// rest), and the arm from the centre.
+__device__ inline void surface_vel(const double* __restrict__ sol, int s, int64_t t, double px, double py,
+                                   double pz, const Args& a, double v[3], double r[3]) {
     if (s == 0) {
         v[0] = v[1] = v[2] = 0.0;
         r[0] = r[1] = r[2] = 0.0;
         return;
     }
     const double* S = sol + kSolidRow * s;
-    r[0] = min_image3(px - S[0], a.nx);
-    r[1] = min_image3(py - S[1], a.ny);
-    r[2] = min_image3(pz - S[2], a.nz);
+    double X[3];
+    centre3(sol, s, t, X);
+    r[0] = min_image3(px - X[0], a.nx);
+    r[1] = min_image3(py - X[1], a.ny);
+    r[2] = min_image3(pz - X[2], a.nz);
     v[0] = S[4] + (S[8] * r[2] - S[9] * r[1]);
     v[1] = S[5] + (S[9] * r[0] - S[7] * r[2]);
     v[2] = S[6] + (S[7] * r[1] - S[8] * r[0]);
@@ -132,27 +148,57 @@ struct Ptrs {
 // (e_i + v) b; torque r x F about the sphere's centre.
 template <typename T>
 __device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ partial, const Args& a,
-                                   double (*red)[12]) {
+                                   double (*red)[12], int64_t t) {
     const T* f = (const T*)p.fin;
     const int s = p.chunk_solid[c];
     const int start = p.chunk_start[c];
-    const int n = p.seg_cnt[s];
+    // a moving sphere's links are found by scanning its box at step t (one
+    // node and its 18 directions per thread); other solids walk their list
+    const bool box = s > 0 && p.sol[kSolidRow * s + 10] != 0.0;
+    int bx0 = 0, by0 = 0, bz0 = 0;
+    if (box) {
+        double X[3];
+        centre3(p.sol, s, t, X);
+        const double r0 = p.sol[kSolidRow * s + 3];
+        bx0 = (int)floor(X[0] - r0) - 2;
+        by0 = (int)floor(X[1] - r0) - 2;
+        bz0 = (int)floor(X[2] - r0) - 2;
+    }
+    const int n = box ? a.box * a.box * a.box : p.seg_cnt[s];
     const int end = start + kChunk < n ? start + kChunk : n;
     const uint32_t* L = p.links + p.seg_off[s];
     double acc[12];
 #pragma unroll
     for (int q = 0; q < 12; ++q) acc[q] = 0.0;
     for (int k = start + (int)threadIdx.x; k < end; k += kBlock) {
-        const uint32_t code = L[k];
-        const int i = (int)(code & 31u);
-        const uint32_t node = code >> 5;
-        const int x = (int)(node % (uint32_t)a.nx);
-        const uint32_t line = node / (uint32_t)a.nx;  // z * ny + y
-        const int y = (int)(line % (uint32_t)a.ny);
-        const int z = (int)(line / (uint32_t)a.ny);
+        int x, y, z, i0, i1;
+        if (box) {
+            const int bx = k % a.box, by = (k / a.box) % a.box, bz = k / (a.box * a.box);
+            x = ((bx0 + bx) % a.nx + a.nx) % a.nx;
+            y = ((by0 + by) % a.ny + a.ny) % a.ny;
+            z = ((bz0 + bz) % a.nz + a.nz) % a.nz;
+            if (p.own[((int64_t)z * a.ny + y) * a.pitch + x] != 0) continue;
+            i0 = 1;
+            i1 = kQ;
+        } else {
+            const uint32_t code = L[k];
+            const uint32_t node = code >> 5;
+            x = (int)(node % (uint32_t)a.nx);
+            const uint32_t ln = node / (uint32_t)a.nx;  // z * ny + y
+            y = (int)(ln % (uint32_t)a.ny);
+            z = (int)(ln / (uint32_t)a.ny);
+            i0 = (int)(code & 31u);
+            i1 = i0 + 1;
+        }
+        const int64_t line = (int64_t)z * a.ny + y;
+        for (int i = i0; i < i1; ++i) {
+        if (box) {
+            const int xb = wrap3(x + kE[i][0], a.nx), yb = wrap3(y + kE[i][1], a.ny), zb = wrap3(z + kE[i][2], a.nz);
+            if (p.own[((int64_t)zb * a.ny + yb) * a.pitch + xb] != s) continue;
+        }
         const double ex = kE[i][0], ey = kE[i][1], ez = kE[i][2], w = w3(i);
         double v[3], r[3];
-        surface_vel(p.sol, s, x + 0.5 * ex, y + 0.5 * ey, z + 0.5 * ez, a, v, r);
+        surface_vel(p.sol, s, t, x + 0.5 * ex, y + 0.5 * ey, z + 0.5 * ez, a, v, r);
         const double av =
             w * a.rho0 + (double)Sto<T>::ld(f[((int64_t)line * kQ + i) * a.pitch + x]);
         const double bv = av - 6.0 * w * a.rho0 * (ex * v[0] + ey * v[1] + ez * v[2]);
@@ -175,6 +221,7 @@ __device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ pa
             acc[9] += r[1] * Fg[2] - r[2] * Fg[1];
             acc[10] += r[2] * Fg[0] - r[0] * Fg[2];
             acc[11] += r[0] * Fg[1] - r[1] * Fg[0];
+        }
         }
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -224,7 +271,7 @@ __device__ inline const T* at3(const T* base, uint32_t idx) {
 }
 
 template <typename T, bool NT>
-__device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a) {
+__device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a, int64_t t) {
     const T* fin = (const T*)p.fin;
     T* fout = (T*)p.fout;
     const int64_t line = (int64_t)z * a.ny + y;
@@ -258,7 +305,7 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
             if (src[i] == 0) continue;
             const int s = src[i] == kDuct ? 0 : (int)src[i];
             double v[3], r[3];
-            surface_vel(p.sol, s, x - 0.5 * kE[i][0], y - 0.5 * kE[i][1], z - 0.5 * kE[i][2], a, v, r);
+            surface_vel(p.sol, s, t, x - 0.5 * kE[i][0], y - 0.5 * kE[i][1], z - 0.5 * kE[i][2], a, v, r);
             d[i] = (double)Sto<T>::ld(*at3(fin + (line * kQ + opp3(i)) * a.pitch, ux)) +
                    6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
         }
@@ -285,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
     if (b < n_lead) {
         const int64_t t = p.tctr[parity];
         if (b < a.nchunks) {
-            force_role3<T>(b, p, p.partial + (size_t)(t & 1) * a.nchunks * 12, a, red);
+            force_role3<T>(b, p, p.partial + (size_t)(t & 1) * a.nchunks * 12, a, red, t);
         } else if (b < a.nchunks + (a.ns + 1) * 12) {
             const int pair = b - a.nchunks;
             if (t >= 1)
@@ -301,7 +348,134 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
     const uint32_t line = gw / wpr;
     const int x = (int)((gw - line * wpr) << 6) + (int)(threadIdx.x & 63);
     if (line >= (uint32_t)(a.ny * a.nz) || x >= a.nx) return;
-    update3<T, NT>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a);
+    update3<T, NT>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a, p.tctr[parity]);
+}
+
+// Owner of node (x, y, z) at step t: the duct, then the spheres (minimum
+// image, separately rounded products and sums, ties solid).
+__device__ inline uint8_t owner3(const double* __restrict__ sol, int x, int y, int z, int64_t t, const Args& a) {
+#pragma clang fp contract(off)
+    uint8_t o = 0;
+    if (a.duct == 1) {
+        const double dy = (double)y - 0.5 * (a.ny - 1), dz = (double)z - 0.5 * (a.nz - 1);
+        if (dy * dy + dz * dz > a.R * a.R) o = kDuct;
+    } else if (a.duct == 2) {
+        if (z == 0 || z == a.nz - 1) o = kDuct;
+    }
+    for (int k = 1; k <= a.ns; ++k) {
+        double X[3];
+        centre3(sol, k, t, X);
+        const double dx = min_image3((double)x - X[0], a.nx), dy = min_image3((double)y - X[1], a.ny),
+                     dz = min_image3((double)z - X[2], a.nz);
+        double d2 = dx * dx;
+        d2 = d2 + dy * dy;
+        d2 = d2 + dz * dz;
+        const double r = sol[kSolidRow * k + 3];
+        if (d2 <= r * r) o = (uint8_t)k;
+    }
+    return o;
+}
+
+// Geometry of step t + 1 (moving spheres): the owner of every node.
+__global__ __launch_bounds__(kBlock) void k3_raster(const double* __restrict__ sol, uint8_t* __restrict__ own_n,
+                                                    int64_t t1, Args a) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= (int64_t)a.nx * a.ny * a.nz) return;
+    const int x = (int)(n % a.nx);
+    const int64_t line = n / a.nx;
+    own_n[line * a.pitch + x] = owner3(sol, x, (int)(line % a.ny), (int)(line / a.ny), t1, a);
+}
+
+// Post-advection deviation of direction j at node (x, y, z) from step t's
+// post-collision populations: streamed from x - e_j, or the half-way
+// bounce-back with the moving-wall term when that node is solid at t.
+template <typename T>
+__device__ inline double pull3(const T* __restrict__ fin, const uint8_t* __restrict__ own_t,
+                               const double* __restrict__ sol, int x, int y, int z, int j, int64_t t, const Args& a) {
+    const int xs = wrap3(x - kE[j][0], a.nx), ys = wrap3(y - kE[j][1], a.ny), zs = wrap3(z - kE[j][2], a.nz);
+    const int64_t ls = (int64_t)zs * a.ny + ys;
+    const uint8_t o = own_t[ls * a.pitch + xs];
+    if (o == 0) return (double)Sto<T>::ld(fin[(ls * kQ + j) * a.pitch + xs]);
+    double v[3], r[3];
+    surface_vel(sol, o == kDuct ? 0 : (int)o, t, x - 0.5 * kE[j][0], y - 0.5 * kE[j][1], z - 0.5 * kE[j][2], a, v, r);
+    const int64_t line = (int64_t)z * a.ny + y;
+    return (double)Sto<T>::ld(fin[(line * kQ + opp3(j)) * a.pitch + x]) +
+           6.0 * w3(j) * a.rho0 * (kE[j][0] * v[0] + kE[j][1] * v[1] + kE[j][2] * v[2]);
+}
+
+// Newborn refill (moving sphere `s`, one box node per thread, box around its
+// centre at t + 1): a node solid at t and fluid at t + 1 takes the average
+// over participating directions k (x + e_k old fluid: fluid at t and t + 1)
+// of A1/A2/A3 along k of the post-advection values (falling back A1 -> A2 ->
+// A3), or the equilibrium at its surface velocity when none takes part; then
+// it is collided and stored with the step's output.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k3_refill(Ptrs p, const uint8_t* __restrict__ own_n, const int* __restrict__ movers,
+                                                    int chunks_per_mover, int64_t t, Args a) {
+    const int m = (int)blockIdx.x / chunks_per_mover;
+    const int k0 = ((int)blockIdx.x % chunks_per_mover) * kBlock + (int)threadIdx.x;
+    if (k0 >= a.box * a.box * a.box) return;
+    const int s = movers[m];
+    double X[3];
+    centre3(p.sol, s, t + 1, X);
+    const double r0 = p.sol[kSolidRow * s + 3];
+    const int x = (((int)floor(X[0] - r0) - 2 + k0 % a.box) % a.nx + a.nx) % a.nx;
+    const int y = (((int)floor(X[1] - r0) - 2 + (k0 / a.box) % a.box) % a.ny + a.ny) % a.ny;
+    const int z = (((int)floor(X[2] - r0) - 2 + k0 / (a.box * a.box)) % a.nz + a.nz) % a.nz;
+    const int64_t line = (int64_t)z * a.ny + y;
+    if (p.own[line * a.pitch + x] != s || own_n[line * a.pitch + x] != 0) return;
+    const T* fin = (const T*)p.fin;
+    double acc[kQ];
+#pragma unroll
+    for (int j = 0; j < kQ; ++j) acc[j] = 0.0;
+    int np = 0;
+    for (int k = 1; k < kQ; ++k) {
+        int qx[4], qy[4], qz[4];
+        bool old[4] = {false, false, false, false};
+        for (int mm = 1; mm <= 3; ++mm) {
+            qx[mm] = wrap3(x + mm * kE[k][0], a.nx);
+            qy[mm] = wrap3(y + mm * kE[k][1], a.ny);
+            qz[mm] = wrap3(z + mm * kE[k][2], a.nz);
+            // x + m e_k for m <= 3 stays within one period (n >= 4)
+            const int64_t q = ((int64_t)qz[mm] * a.ny + qy[mm]) * a.pitch + qx[mm];
+            old[mm] = p.own[q] == 0 && own_n[q] == 0;
+            if (!old[mm]) break;
+        }
+        if (!old[1]) continue;
+        int scheme = a.refill;
+        if (scheme == 0 && !(old[2] && old[3])) scheme = 1;
+        if (scheme == 1 && !old[2]) scheme = 2;
+        ++np;
+        for (int j = 0; j < kQ; ++j) {
+            const double f1 = pull3<T>(fin, p.own, p.sol, qx[1], qy[1], qz[1], j, t, a);
+            double v = f1;
+            if (scheme <= 1) {
+                const double f2 = pull3<T>(fin, p.own, p.sol, qx[2], qy[2], qz[2], j, t, a);
+                if (scheme == 1) {
+                    v = 2.0 * f1 - f2;
+                } else {
+                    const double f3 = pull3<T>(fin, p.own, p.sol, qx[3], qy[3], qz[3], j, t, a);
+                    v = 3.0 * f1 - 3.0 * f2 + f3;
+                }
+            }
+            acc[j] += v;
+        }
+    }
+    double d[kQ];
+    if (np > 0) {
+        for (int j = 0; j < kQ; ++j) d[j] = acc[j] / np;
+    } else {
+        double v[3], r[3];
+        surface_vel(p.sol, s, t + 1, x, y, z, a, v, r);
+        const double uu = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        for (int j = 0; j < kQ; ++j) {
+            const double eu = kE[j][0] * v[0] + kE[j][1] * v[1] + kE[j][2] * v[2];
+            d[j] = w3(j) * a.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        }
+    }
+    collide3(d, a);
+    T* fout = (T*)p.fout;
+    for (int j = 0; j < kQ; ++j) fout[(line * kQ + j) * a.pitch + x] = Sto<T>::st(d[j]);
 }
 
 // Totals of the last step tctr[parity] - 1 after a run of steps, one

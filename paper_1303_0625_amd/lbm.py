@@ -58,14 +58,14 @@ _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
 class lbm3d_grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("duct", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("duct", ctypes.c_int32), ("refill", ctypes.c_int32),
                 ("R", ctypes.c_double), ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("u0", ctypes.c_double * 3)]
 
 
 class lbm3d_sphere(ctypes.Structure):
     _fields_ = [("X", ctypes.c_double * 3), ("r", ctypes.c_double), ("V", ctypes.c_double * 3),
-                ("omega", ctypes.c_double * 3)]
+                ("omega", ctypes.c_double * 3), ("moves", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _SIG = {
@@ -924,6 +924,7 @@ def make_grid3(case: dict, dtype="f64") -> lbm3d_grid:
     g.dtype = {"f64": LBM_F64, "f32": LBM_F32}[dtype]
     g.duct = int(case.get("duct", LBM3D_OPEN))
     g.R = float(case.get("R", 0.0))
+    g.refill = int(case.get("refill", 0))
     g.tau = float(case["tau"])
     g.rho0 = float(case.get("rho0", 1.0))
     for d in range(3):
@@ -940,6 +941,7 @@ def _spheres(spheres):
         arr[k].r = float(sp["r"])
         arr[k].V[:] = [float(v) for v in sp.get("v", (0.0, 0.0, 0.0))]
         arr[k].omega[:] = [float(v) for v in sp.get("omega", (0.0, 0.0, 0.0))]
+        arr[k].moves = int(bool(sp.get("moves", False)))
     return arr, n
 
 
@@ -972,7 +974,8 @@ def lbm3d_force(ctx, solid: int, scheme: int, step: int = -1):
 class Lattice3D:
     """One D3Q19 lattice on the current device (workspace: a torch uint8
     tensor; kernels on torch's current stream).  case keys: nx, ny, nz, tau,
-    duct, R, rho0, g, u0, spheres (dicts cx, cy, cz, r, v, omega)."""
+    duct, R, rho0, g, u0, refill, spheres (dicts cx, cy, cz, r, v, omega,
+    moves)."""
 
     def __init__(self, case: dict, dtype="f64", history_steps=1024, device="cuda", stream=None):
         import torch

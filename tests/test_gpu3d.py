@@ -45,6 +45,9 @@ def run_pair(oracle_mod, lbm_mod, c, steps, dtype="f64", chunks=2):
     _say(f"{c['name']} {c['nx']}x{c['ny']}x{c['nz']} steps={steps} dtype={dtype}")
     lat = lbm_mod.Lattice3D(c, dtype=dtype, history_steps=steps)
     osim = _oracle(oracle_mod, c)
+    for k, sp in enumerate(c.get("spheres", ())):
+        if sp.get("moves"):
+            osim.set_moving(k + 1, True, c.get("refill", 0))
     for _ in range(chunks):
         lat.step(steps // chunks)
         osim.step(steps // chunks)
@@ -161,3 +164,48 @@ def test_rejects_overlap_and_bad_args(lbm_mod):
         lbm_mod.Lattice3D(bad)
     with pytest.raises(L.LBMError):
         lbm_mod.Lattice3D(dict(nx=20, ny=20, nz=20, tau=0.5))
+
+
+# --------------------------------------------------------------- translating spheres
+@pytest.mark.parametrize("refill,steps", [(0, 300), (1, 200), (2, 200)])
+def test_translating_sphere_f64(oracle_mod, lbm_mod, refill, steps):
+    """A spinning sphere translating obliquely through a tube Poiseuille flow
+    (covered and newborn nodes every few steps), refill A1/A2/A3: FP64
+    fields and per-step forces and torques against the oracle."""
+    c = dict(name=f"moving_sphere_refill{refill}", nx=40, ny=24, nz=24, tau=0.7, duct=1, R=10.3,
+             g=(2e-5, 0.0, 0.0), refill=refill,
+             spheres=[dict(cx=13.1, cy=13.1, cz=10.6, r=4.3, v=(0.04, 0.004, -0.003), omega=(0.0, 0.002, 0.001),
+                           moves=True)])
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, steps)
+    assert osim.error == 0
+    er, eu = field_err(lat, osim)
+    assert er <= 1e-12 and eu <= 1e-12
+    assert force_err(lat, osim) <= 1e-10
+
+
+def test_translating_sphere_comoving_gpu(lbm_mod):
+    """A sphere translating with the uniform flow f_eq(1, U) across several
+    nodes leaves the state uniform and feels no force."""
+    U = (0.05, -0.02, 0.03)
+    c = dict(nx=22, ny=18, nz=16, tau=0.7, u0=U, spheres=[dict(cx=9.3, cy=8.6, cz=7.8, r=3.7, v=U, moves=True)])
+    lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=64)
+    lat.step(60)
+    rho, u, own = (a.cpu().numpy() for a in lat.fields())
+    fl = own == 0
+    assert np.abs(rho[fl] - 1.0).max() <= 1e-13
+    for d in range(3):
+        assert np.abs(u[d][fl] - U[d]).max() <= 1e-14
+    assert np.abs(np.array(lat.force(1, 1))[:3]).max() <= 1e-13
+    assert int((own == 1).sum()) > 0
+
+
+def test_translating_sphere_path_check(lbm_mod):
+    """A moving sphere that would come within 2 nodes of the tube is refused
+    before any step is launched."""
+    c = dict(nx=20, ny=22, nz=22, tau=0.7, duct=1, R=9.0,
+             spheres=[dict(cx=10.0, cy=10.5, cz=10.5, r=3.0, v=(0.0, 0.2, 0.0), moves=True)])
+    lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=8)
+    lat.step(5)
+    with pytest.raises(lbm_mod.lbm.LBMError):
+        lat.step(40)
+    assert lat.t == 5
