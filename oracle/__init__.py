@@ -318,6 +318,11 @@ def _load3():
     lib.orc3_set_moving.restype = ctypes.c_int
     lib.orc3_error.argtypes = [ctypes.c_void_p]
     lib.orc3_error.restype = ctypes.c_int
+    lib.orc3_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, dp]
+    lib.orc3_set_free.restype = ctypes.c_int
+    lib.orc3_set_gravity.argtypes = [ctypes.c_void_p, dp, ctypes.c_int]
+    lib.orc3_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
+    lib.orc3_body_state.restype = ctypes.c_int
     u8p = ctypes.POINTER(ctypes.c_uint8)
     lib.orc3_refill_node.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, u8p, u8p, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
@@ -394,6 +399,21 @@ class OracleSim3D:
         """Sphere `sphere` (1-based) translates at its v; refill A1/A2/A3 (0/1/2)."""
         if self._lib.orc3_set_moving(self._h, int(sphere), int(bool(moving)), int(refill)) != 0:
             raise ValueError("oracle rejected the moving sphere")
+
+    def set_free(self, sphere: int, rho_s: float, omega0=(0.0, 0.0, 0.0)) -> None:
+        """Sphere `sphere` (set moving first) becomes free with density rho_s."""
+        if self._lib.orc3_set_free(self._h, int(sphere), float(rho_s), _dp(_vec(omega0))) != 0:
+            raise ValueError("oracle rejected the free sphere")
+
+    def set_gravity(self, G, scheme: int) -> None:
+        self._lib.orc3_set_gravity(self._h, _dp(_vec(G)), int(scheme))
+
+    def body_state(self, sphere: int) -> np.ndarray:
+        """{X (3), V (3), Omega (3)} of sphere `sphere` now."""
+        out = np.zeros(9)
+        if self._lib.orc3_body_state(self._h, int(sphere), _dp(out)) != 0:
+            raise IndexError(sphere)
+        return out
 
     @property
     def error(self) -> int:

@@ -24,7 +24,12 @@
  * A2: 2 f(x+e_k) - f(x+2e_k), A3: f(x+e_k), falling back A1 -> A2 -> A3 where
  * the farther nodes are not old fluid), averaged over the participants, or
  * f_eq(rho0, v) at the node's surface velocity when none participates
- * (Sec. IV.B written for D3Q19).  The duct is a circular tube along x (nodes
+ * (Sec. IV.B written for D3Q19).  A free sphere (density rho_s, mass
+ * M = rho_s 4/3 pi r^3, moment of inertia 2/5 M r^2) takes, after the forces
+ * of step t, the explicit Newton-Euler step of the two-dimensional free
+ * discs: V' = V + (F + (M - rho0 Vol) G)/M, Omega' = Omega + T/I,
+ * X' = X + V', with the chosen scheme's F and T; its surface then moves at
+ * V + Omega x (p - X) with the state of the step.  The duct is a circular tube along x (nodes
  * farther than R from the axis are solid), two solid planes z = 0 and
  * z = nz - 1, or nothing.
  * Every axis is periodic (the duct walls are solid nodes).  Summation orders
@@ -34,6 +39,7 @@
  * weights 1/3, 1/18, 1/36 (the D3Q19 weights for which the equilibrium's
  * second moment is ρ/3 I + ρ u u, pinned in the tests).
  */
+#define _DEFAULT_SOURCE
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -56,6 +62,12 @@ struct orc3_sim {
     int ns;
     double* sp;  /* ns x 10: X[3], r, V[3], Om[3] */
     int* moving; /* per sphere: translates at V */
+    int* free_;  /* per sphere: Newton-Euler motion */
+    double* dyn; /* per sphere: X, V, Om at the current step, then X', V', Om' (18) */
+    double* mass; /* per sphere: M, I, volume */
+    double G[3];
+    int dyn_scheme;
+    int advanced; /* dyn holds step t + 1 in its second half */
     int refill;  /* ORC3_A1 / A2 / A3 */
     int err;     /* geometry error met while stepping */
     unsigned char* own;
@@ -74,10 +86,32 @@ static long pidx(const orc3_sim* s, int i, int x, int y, int z) {
 }
 static int wrap(int a, int n) { return ((a % n) + n) % n; }
 
-/* Centre of sphere k at step t. */
+/* Centre of sphere k at step t (a free sphere: its state at step t, or at
+ * t + 1 once the step's dynamics are done). */
 static void centre(const orc3_sim* s, int k, long t, double X[3]) {
     const double* p = s->sp + 10 * k;
+    if (s->free_[k]) {
+        const double* D = s->dyn + 18 * k + ((s->advanced && t == s->t + 1) ? 9 : 0);
+        for (int d = 0; d < 3; ++d) X[d] = D[d];
+        return;
+    }
     for (int d = 0; d < 3; ++d) X[d] = s->moving[k] ? p[d] + (double)t * p[4 + d] : p[d];
+}
+
+/* Translation and spin of sphere k at step t. */
+static void motion(const orc3_sim* s, int k, long t, double V[3], double Om[3]) {
+    const double* p = s->sp + 10 * k;
+    const double* src = p + 4;
+    const double* som = p + 7;
+    if (s->free_[k]) {
+        const double* D = s->dyn + 18 * k + ((s->advanced && t == s->t + 1) ? 9 : 0);
+        src = D + 3;
+        som = D + 6;
+    }
+    for (int d = 0; d < 3; ++d) {
+        V[d] = src[d];
+        Om[d] = som[d];
+    }
 }
 static double min_image(double d, int n) { return d - (double)n * floor(d / (double)n + 0.5); }
 
@@ -114,14 +148,12 @@ static void surface_velocity(const orc3_sim* s, int owner, long t, double px, do
     v[0] = v[1] = v[2] = 0.0;
     r[0] = r[1] = r[2] = 0.0;
     if (owner == 255 || owner == 0) return;
-    const double* p = s->sp + 10 * (owner - 1);
-    double X[3];
+    double X[3], V[3], Om[3];
     centre(s, owner - 1, t, X);
+    motion(s, owner - 1, t, V, Om);
     r[0] = min_image(px - X[0], s->nx);
     r[1] = min_image(py - X[1], s->ny);
     r[2] = min_image(pz - X[2], s->nz);
-    const double* V = p + 4;
-    const double* Om = p + 7;
     v[0] = V[0] + (Om[1] * r[2] - Om[2] * r[1]);
     v[1] = V[1] + (Om[2] * r[0] - Om[0] * r[2]);
     v[2] = V[2] + (Om[0] * r[1] - Om[1] * r[0]);
@@ -181,6 +213,10 @@ orc3_sim* orc3_create(int nx, int ny, int nz, double tau, double rho0, const dou
     s->sp = (double*)malloc(sizeof(double) * 10 * (ns > 0 ? ns : 1));
     if (ns > 0) memcpy(s->sp, spheres, sizeof(double) * 10 * ns);
     s->moving = (int*)calloc((size_t)(ns > 0 ? ns : 1), sizeof(int));
+    s->free_ = (int*)calloc((size_t)(ns > 0 ? ns : 1), sizeof(int));
+    s->dyn = (double*)calloc((size_t)18 * (ns > 0 ? ns : 1), sizeof(double));
+    s->mass = (double*)calloc((size_t)3 * (ns > 0 ? ns : 1), sizeof(double));
+    s->dyn_scheme = ORC3_GME;
     long N = (long)nx * ny * nz;
     s->own = (unsigned char*)calloc((size_t)N, 1);
     s->own_n = (unsigned char*)calloc((size_t)N, 1);
@@ -209,6 +245,9 @@ void orc3_destroy(orc3_sim* s) {
     if (!s) return;
     free(s->sp);
     free(s->moving);
+    free(s->free_);
+    free(s->dyn);
+    free(s->mass);
     free(s->own);
     free(s->own_n);
     free(s->f);
@@ -329,6 +368,20 @@ static void one_step(orc3_sim* s) {
                     s->fn[pidx(s, i, x, y, z)] = val;
                 }
             }
+    /* free spheres: Newton-Euler step from this step's force and torque */
+    for (int k = 0; k < s->ns; ++k) {
+        if (!s->free_[k]) continue;
+        const double* hk = h + 12 * (k + 1) + 6 * s->dyn_scheme;
+        double* D = s->dyn + 18 * k;
+        const double M = s->mass[3 * k], I = s->mass[3 * k + 1], Vol = s->mass[3 * k + 2];
+        const double ext = M - s->rho0 * Vol;
+        for (int d = 0; d < 3; ++d) {
+            D[12 + d] = D[3 + d] + (hk[d] + ext * s->G[d]) / M;
+            D[15 + d] = D[6 + d] + hk[3 + d] / I;
+            D[9 + d] = D[d] + D[12 + d];
+        }
+    }
+    s->advanced = 1;
     /* moving spheres: geometry of step t + 1, newborn refill */
     int any_moving = 0;
     for (int k = 0; k < s->ns; ++k) any_moving |= s->moving[k];
@@ -361,10 +414,50 @@ static void one_step(orc3_sim* s) {
         s->own = s->own_n;
         s->own_n = t2;
     }
+    for (int k = 0; k < s->ns; ++k)
+        if (s->free_[k])
+            for (int d = 0; d < 9; ++d) s->dyn[18 * k + d] = s->dyn[18 * k + 9 + d];
+    s->advanced = 0;
     double* tmp = s->f;
     s->f = s->fn;
     s->fn = tmp;
     s->t += 1;
+}
+
+int orc3_set_free(orc3_sim* s, int sphere, double rho_s, const double omega0[3]) {
+    if (sphere < 1 || sphere > s->ns || !(rho_s > 0.0) || s->t != 0 || !s->moving[sphere - 1]) return -1;
+    const int k = sphere - 1;
+    const double* p = s->sp + 10 * k;
+    const double r = p[3];
+    const double vol = 4.0 / 3.0 * M_PI * r * r * r;
+    s->free_[k] = 1;
+    s->mass[3 * k] = rho_s * vol;
+    s->mass[3 * k + 1] = 0.4 * rho_s * vol * r * r;
+    s->mass[3 * k + 2] = vol;
+    for (int d = 0; d < 3; ++d) {
+        s->dyn[18 * k + d] = p[d];
+        s->dyn[18 * k + 3 + d] = p[4 + d];
+        s->dyn[18 * k + 6 + d] = omega0[d];
+    }
+    return 0;
+}
+
+void orc3_set_gravity(orc3_sim* s, const double G[3], int scheme) {
+    for (int d = 0; d < 3; ++d) s->G[d] = G[d];
+    s->dyn_scheme = scheme == ORC3_CME ? ORC3_CME : ORC3_GME;
+}
+
+int orc3_body_state(const orc3_sim* s, int sphere, double out[9]) {
+    if (sphere < 1 || sphere > s->ns) return -1;
+    double X[3], V[3], Om[3];
+    centre(s, sphere - 1, s->t, X);
+    motion(s, sphere - 1, s->t, V, Om);
+    for (int d = 0; d < 3; ++d) {
+        out[d] = X[d];
+        out[3 + d] = V[d];
+        out[6 + d] = Om[d];
+    }
+    return 0;
 }
 
 int orc3_set_moving(orc3_sim* s, int sphere, int moving, int refill) {

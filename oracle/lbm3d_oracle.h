@@ -42,6 +42,13 @@ void orc3_link_force(int i, double a, double b, const double v[3], int scheme, d
 int orc3_set_moving(orc3_sim* s, int sphere, int moving, int refill);
 void orc3_refill_node(int nx, int ny, int nz, const double* fn, const unsigned char* own_t,
                       const unsigned char* own_n, int x, int y, int z, int scheme, int* np, double out[19]);
+/* Sphere `sphere` (created moving) becomes free: density rho_s, initial spin
+ * omega0, initial velocity its V (before the first step only). */
+int orc3_set_free(orc3_sim* s, int sphere, double rho_s, const double omega0[3]);
+/* Gravity on free spheres (buoyancy-corrected) and the scheme that drives them. */
+void orc3_set_gravity(orc3_sim* s, const double G[3], int scheme);
+/* {X, V, Omega} of sphere `sphere` at the current step. */
+int orc3_body_state(const orc3_sim* s, int sphere, double out[9]);
 /* Non-zero when a moving sphere met the duct or another sphere. */
 int orc3_error(const orc3_sim* s);
 

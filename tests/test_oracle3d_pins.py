@@ -285,3 +285,61 @@ def test_translating_sphere_meets_tube_3d(oracle_mod):
     s.set_moving(1, True, 0)
     s.step(40)
     assert s.error != 0
+
+
+# ---------------------------------------------------------------- free spheres
+def _fluid_momentum3(s, e):
+    return _momentum(s.get_f(), e)
+
+
+def test_free_sphere_at_rest_3d(oracle_mod):
+    """A heavy free sphere at rest in fluid at rest without gravity stays at
+    rest: every link force cancels."""
+    s = oracle_mod.OracleSim3D(20, 20, 20, 0.7, spheres=[dict(cx=9.7, cy=10.2, cz=9.4, r=4.1)])
+    s.set_moving(1, True, 0)
+    s.set_free(1, 1.5)
+    s.step(30)
+    st = s.body_state(1)
+    assert np.abs(st[3:]).max() <= 1e-15
+    assert np.abs(st[:3] - (9.7, 10.2, 9.4)).max() <= 1e-15
+
+
+def test_free_sphere_momentum_balance_3d(oracle_mod):
+    """Periodic box, a free sphere (density 1.5) under gravity G with the CME
+    force: P_fluid(t) + M V(t) = P_fluid(0) + M V(0) + t (M - rho0 Vol) G
+    while the sphere covers the same nodes."""
+    e, _ = _lookup(oracle_mod)
+    r, rho_s, G = 4.3, 1.5, np.array([2e-6, -1e-6, 1.5e-6])
+    s = oracle_mod.OracleSim3D(22, 20, 18, 0.7, spheres=[dict(cx=10.3, cy=9.6, cz=8.7, r=r)])
+    s.set_moving(1, True, 0)
+    s.set_free(1, rho_s)
+    s.set_gravity(G, oracle_mod.CME)
+    vol = 4 / 3 * np.pi * r ** 3
+    M = rho_s * vol
+    P0 = _fluid_momentum3(s, e)
+    _, _, own0 = s.fields()
+    for t in (40, 80, 120):
+        s.step(40)
+        _, _, own = s.fields()
+        assert np.array_equal(own, own0)
+        st = s.body_state(1)
+        bal = _fluid_momentum3(s, e) + M * st[3:6] - P0 - t * (M - vol) * G
+        assert np.abs(bal).max() < 1e-12
+        assert np.linalg.norm(st[3:6]) > 1e-6
+
+
+def test_free_sphere_spin_down_3d(oracle_mod):
+    """A free sphere spinning about a lattice axis in fluid at rest slows
+    down: the spin decays monotonically, stays on its axis, and the centre
+    does not move."""
+    s = oracle_mod.OracleSim3D(21, 21, 21, 0.8, spheres=[dict(cx=10.0, cy=10.0, cz=10.0, r=4.0)])
+    s.set_moving(1, True, 0)
+    s.set_free(1, 1.2, (0.0, 0.004, 0.0))
+    prev = 0.004
+    for _ in range(4):
+        s.step(25)
+        st = s.body_state(1)
+        assert 0 < st[7] < prev
+        prev = st[7]
+        assert abs(st[6]) <= 1e-15 and abs(st[8]) <= 1e-15
+        assert np.abs(st[:3] - 10.0).max() <= 1e-13
