@@ -615,8 +615,32 @@ lbm_status lbm3d_force_history(lbm3d_ctx* ctx, int64_t first, int64_t count, dou
  * solid nodes.  Asynchronous. */
 lbm_status lbm3d_fields(lbm3d_ctx* ctx, double* d_rho, double* d_u, int32_t* d_owner);
 
-/* Number of fluid-solid links. */
+/* Number of fluid-solid links of the fixed solids (a moving sphere's links
+ * are found by a scan of its box each step). */
 int64_t lbm3d_link_count(const lbm3d_ctx* ctx);
+
+/* Sphere `sphere` (1-based, created with moves = 1) becomes free: density
+ * rho_s (mass M = rho_s 4/3 pi r^3, moment of inertia 2/5 M r^2), initial
+ * velocity its V, initial spin omega0.  After each step the scheme chosen by
+ * lbm3d_set_gravity (default LBM_GME) drives it explicitly:
+ * V' = V + (F + (M - rho0 Vol) G)/M, Omega' = Omega + T/I, X' = X + V'.
+ * Its path is not validated ahead: coming within 2 nodes of the duct or of
+ * another sphere, or moving more than half a node in a step, makes
+ * lbm3d_status_check return LBM_EGEOM.  Before the first step only
+ * (LBM_ESTATE after).  Synchronises. */
+lbm_status lbm3d_set_free(lbm3d_ctx* ctx, int32_t sphere, double rho_s, const double omega0[3]);
+
+/* Gravity G on free spheres (buoyancy-corrected: the fluid carries none) and
+ * the force scheme (LBM_CME / LBM_GME) that drives them. */
+lbm_status lbm3d_set_gravity(lbm3d_ctx* ctx, const double G[3], int32_t scheme);
+
+/* out = {X, V, Omega} (three components each) of sphere `sphere` at the
+ * current step.  Synchronises. */
+lbm_status lbm3d_body_state(lbm3d_ctx* ctx, int32_t sphere, double out[9]);
+
+/* LBM_EGEOM if a free sphere met the duct or another sphere (see
+ * lbm3d_set_free), else LBM_OK.  Synchronises. */
+lbm_status lbm3d_status_check(lbm3d_ctx* ctx);
 
 /* Per-launch step timing with HIP events (as lbm_profile / lbm_profile_read). */
 lbm_status lbm3d_profile(lbm3d_ctx* ctx, int32_t enable);

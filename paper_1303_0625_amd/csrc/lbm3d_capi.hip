@@ -32,8 +32,8 @@ size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 constexpr size_t kStreamBytes3 = 256ull << 20;  // Infinity Cache: stream above it
 
 struct Layout3 {
-    size_t f[2], own[2], links, seg_off, seg_cnt, chunk_solid, chunk_start, solid_chunk0, sol, partial, hist, tctr,
-        movers, total;
+    size_t f[2], own[2], links, seg_off, seg_cnt, chunk_solid, chunk_start, solid_chunk0, sol[2], partial, hist,
+        tctr, movers, mass, err, total;
     int pitch;
     int nchunks;
     int64_t nlinks;
@@ -56,7 +56,10 @@ struct lbm3d_ctx {
     hipStream_t stream = nullptr;
     Layout3 L{};
     char err[512] = "";
-    std::vector<double> sol;  // host copy of the solid table
+    std::vector<double> sol;  // host copy of the solid table (initial state)
+    int nfree = 0;
+    double G[3] = {0.0, 0.0, 0.0};
+    int dyn_scheme = LBM_GME;
     bool prof = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
@@ -214,8 +217,14 @@ Layout3 make_layout(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, int pit
     off = al256(off + 4 * (size_t)nch);
     L.solid_chunk0 = off;
     off = al256(off + 4 * (size_t)(ns + 2));
-    L.sol = off;
-    off = al256(off + 8 * (size_t)kSolidRow * (ns + 1));
+    for (int k = 0; k < 2; ++k) {
+        L.sol[k] = off;
+        off = al256(off + 8 * (size_t)kSolidRow * (ns + 1));
+    }
+    L.mass = off;
+    off = al256(off + 8 * (size_t)4 * (ns + 1));
+    L.err = off;
+    off = al256(off + 16);
     L.partial = off;
     off = al256(off + 8 * (size_t)2 * nch * 12);
     L.hist = off;
@@ -367,7 +376,8 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
     up(L.chunk_solid, chunk_solid.data(), 4 * chunk_solid.size());
     up(L.chunk_start, chunk_start.data(), 4 * chunk_start.size());
     up(L.solid_chunk0, solid_chunk0.data(), 4 * solid_chunk0.size());
-    up(L.sol, c->sol.data(), 8 * c->sol.size());
+    up(L.sol[0], c->sol.data(), 8 * c->sol.size());
+    up(L.sol[1], c->sol.data(), 8 * c->sol.size());
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         set_err3(g_err3, "hipMemcpyAsync: %s", hipGetErrorString(e));
@@ -405,7 +415,7 @@ static const char* check_paths3(const lbm3d_ctx* c, int64_t t0, int64_t t1) {
     };
     for (int k = 0; k < ns; ++k) {
         const double* S = c->sol.data() + kSolidRow * (k + 1);
-        if (S[10] == 0.0) continue;
+        if (S[10] == 0.0 || S[11] != 0.0) continue;  // fixed, or free (checked on the device)
         const double r = S[3];
         for (int64_t t = t0; t <= t1; ++t) {
             double X[3];
@@ -417,7 +427,7 @@ static const char* check_paths3(const lbm3d_ctx* c, int64_t t0, int64_t t1) {
                 if (X[2] - r < 2.0 || X[2] + r > c->g.nz - 3.0) return "a moving sphere comes within 2 nodes of a plane";
             }
             for (int j = 0; j < ns; ++j) {
-                if (j == k) continue;
+                if (j == k || c->sol[kSolidRow * (j + 1) + 11] != 0.0) continue;
                 double Y[3];
                 centre_at(j, t, Y);
                 double d2 = 0.0;
@@ -457,7 +467,7 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
     p.chunk_solid = at<int>(c, c->L.chunk_solid);
     p.chunk_start = at<int>(c, c->L.chunk_start);
     p.solid_chunk0 = at<int>(c, c->L.solid_chunk0);
-    p.sol = at<double>(c, c->L.sol);
+
     p.partial = at<double>(c, c->L.partial);
     p.hist = at<double>(c, c->L.hist);
     p.tctr = at<int64_t>(c, c->L.tctr);
@@ -466,6 +476,7 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
         p.fin = c->ws + c->L.f[par];
         p.fout = c->ws + c->L.f[par ^ 1];
         p.own = at<uint8_t>(c, c->L.own[par]);
+        p.sol = at<double>(c, c->L.sol[par]);
         const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
         if (timed) HIPCHK3(c, hipEventRecord(c->ev[c->ev_used], c->stream));
         if (c->g.dtype == LBM_F64) {
@@ -479,18 +490,32 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
             else
                 k3_step<float, false><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
         }
+        double* sol_n = at<double>(c, c->L.sol[par ^ 1]);
+        if (c->nfree > 0) {
+            // free spheres: Newton-Euler step from this step's forces
+            FreeArgs3 fa{};
+            fa.sol_t = p.sol;
+            fa.sol_n = sol_n;
+            fa.mass = at<double>(c, c->L.mass);
+            fa.partial = p.partial + (size_t)(c->t & 1) * c->L.nchunks * 12;
+            fa.solid_chunk0 = p.solid_chunk0;
+            fa.err = at<int>(c, c->L.err);
+            for (int d = 0; d < 3; ++d) fa.G[d] = c->G[d];
+            fa.scheme = c->dyn_scheme == LBM_CME ? 0 : 1;
+            k3_free<<<1, kBlock, 0, c->stream>>>(fa, c->t, a);
+        }
         if (c->L.nmovers > 0) {
             // geometry of step t + 1, then the newborn refill into the step's output
             uint8_t* own_n = at<uint8_t>(c, c->L.own[par ^ 1]);
             const int64_t N = (int64_t)c->g.nx * c->g.ny * c->g.nz;
-            k3_raster<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(p.sol, own_n, c->t + 1, a);
+            k3_raster<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(sol_n, own_n, c->t + 1, a);
             const int cpm = (int)(((int64_t)c->L.box * c->L.box * c->L.box + kBlock - 1) / kBlock);
             const unsigned nrb = (unsigned)(cpm * c->L.nmovers);
             const int* mv = at<int>(c, c->L.movers);
             if (c->g.dtype == LBM_F64)
-                k3_refill<double><<<nrb, kBlock, 0, c->stream>>>(p, own_n, mv, cpm, c->t, a);
+                k3_refill<double><<<nrb, kBlock, 0, c->stream>>>(p, sol_n, own_n, mv, cpm, c->t, a);
             else
-                k3_refill<float><<<nrb, kBlock, 0, c->stream>>>(p, own_n, mv, cpm, c->t, a);
+                k3_refill<float><<<nrb, kBlock, 0, c->stream>>>(p, sol_n, own_n, mv, cpm, c->t, a);
         }
         if (timed) {
             HIPCHK3(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
@@ -551,6 +576,71 @@ lbm_status lbm3d_fields(lbm3d_ctx* c, double* d_rho, double* d_u, int32_t* d_own
 }
 
 int64_t lbm3d_link_count(const lbm3d_ctx* c) { return c ? c->L.nlinks : -1; }
+
+lbm_status lbm3d_set_free(lbm3d_ctx* c, int32_t sphere, double rho_s, const double omega0[3]) {
+    if (!c || !omega0) return LBM_EINVAL;
+    if (sphere < 1 || sphere > c->ns || !(rho_s > 0.0)) {
+        set_err3(c->err, "sphere must be 1..n_spheres and rho_s positive");
+        return LBM_EINVAL;
+    }
+    double* S = c->sol.data() + kSolidRow * sphere;
+    if (S[10] == 0.0) {
+        set_err3(c->err, "a free sphere must be created with moves = 1");
+        return LBM_EINVAL;
+    }
+    if (c->t != 0) {
+        set_err3(c->err, "free spheres are set before the first step");
+        return LBM_ESTATE;
+    }
+    const double r = S[3];
+    const double vol = 4.0 / 3.0 * M_PI * r * r * r;
+    const double mass[4] = {rho_s * vol, 0.4 * rho_s * vol * r * r, vol, 0.0};
+    if (S[11] == 0.0) c->nfree += 1;
+    S[11] = 1.0;
+    for (int d = 0; d < 3; ++d) S[7 + d] = omega0[d];
+    for (int k = 0; k < 2; ++k)
+        HIPCHK3(c, hipMemcpyAsync(c->ws + c->L.sol[k] + 8 * (size_t)kSolidRow * sphere, S, 8 * kSolidRow,
+                                  hipMemcpyHostToDevice, c->stream));
+    HIPCHK3(c, hipMemcpyAsync(c->ws + c->L.mass + 8 * (size_t)4 * sphere, mass, sizeof(mass), hipMemcpyHostToDevice,
+                              c->stream));
+    HIPCHK3(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm3d_set_gravity(lbm3d_ctx* c, const double G[3], int32_t scheme) {
+    if (!c || !G || (scheme != LBM_CME && scheme != LBM_GME)) return LBM_EINVAL;
+    for (int d = 0; d < 3; ++d) c->G[d] = G[d];
+    c->dyn_scheme = scheme;
+    return LBM_OK;
+}
+
+lbm_status lbm3d_body_state(lbm3d_ctx* c, int32_t sphere, double out[9]) {
+    if (!c || !out || sphere < 1 || sphere > c->ns) return LBM_EINVAL;
+    double row[kSolidRow];
+    HIPCHK3(c, hipMemcpyAsync(row, c->ws + c->L.sol[c->t & 1] + 8 * (size_t)kSolidRow * sphere, sizeof(row),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK3(c, hipStreamSynchronize(c->stream));
+    const bool translating = row[10] != 0.0 && row[11] == 0.0;
+    for (int d = 0; d < 3; ++d) {
+        out[d] = translating ? row[d] + (double)c->t * row[4 + d] : row[d];
+        out[3 + d] = row[4 + d];
+        out[6 + d] = row[7 + d];
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm3d_status_check(lbm3d_ctx* c) {
+    if (!c) return LBM_EINVAL;
+    int e = 0;
+    HIPCHK3(c, hipMemcpyAsync(&e, c->ws + c->L.err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK3(c, hipStreamSynchronize(c->stream));
+    if (e != 0) {
+        set_err3(c->err, "a free sphere came within 2 nodes of the duct or another sphere, or moved more than half a "
+                         "node in a step");
+        return LBM_EGEOM;
+    }
+    return LBM_OK;
+}
 
 lbm_status lbm3d_profile(lbm3d_ctx* c, int32_t enable) {
     if (!c) return LBM_EINVAL;

@@ -50,16 +50,18 @@ struct Args {
     int refill;       // 0 A1, 1 A2, 2 A3
 };
 
-// Solid table row: X0, Y0, Z0, r, V (3), Omega (3), moves, pad; row 0 is the
-// duct.
+// Solid table row: X, r, V (3), Omega (3), moves, free; row 0 is the duct.
+// One table per step parity: a free sphere's row holds its centre, velocity
+// and spin at that step (written by the free-sphere update), every other
+// row its initial centre and prescribed motion.
 constexpr int kSolidRow = 12;
 
-// Centre of sphere slot s at step t (a moving sphere: X0 + t V, product and
-// sum rounded separately).
+// Centre of sphere slot s at step t (a translating sphere: X0 + t V,
+// product and sum rounded separately; a free sphere: the table's centre).
 __device__ inline void centre3(const double* __restrict__ sol, int s, int64_t t, double X[3]) {
 #pragma clang fp contract(off)
     const double* S = sol + kSolidRow * s;
-    const bool mv = S[10] != 0.0;
+    const bool mv = S[10] != 0.0 && S[11] == 0.0;
     for (int d = 0; d < 3; ++d) X[d] = mv ? S[d] + (double)t * S[4 + d] : S[d];
 }
 
@@ -410,14 +412,15 @@ __device__ inline double pull3(const T* __restrict__ fin, const uint8_t* __restr
 // A3), or the equilibrium at its surface velocity when none takes part; then
 // it is collided and stored with the step's output.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k3_refill(Ptrs p, const uint8_t* __restrict__ own_n, const int* __restrict__ movers,
+__global__ __launch_bounds__(kBlock) void k3_refill(Ptrs p, const double* __restrict__ sol_n,
+                                                    const uint8_t* __restrict__ own_n, const int* __restrict__ movers,
                                                     int chunks_per_mover, int64_t t, Args a) {
     const int m = (int)blockIdx.x / chunks_per_mover;
     const int k0 = ((int)blockIdx.x % chunks_per_mover) * kBlock + (int)threadIdx.x;
     if (k0 >= a.box * a.box * a.box) return;
     const int s = movers[m];
     double X[3];
-    centre3(p.sol, s, t + 1, X);
+    centre3(sol_n, s, t + 1, X);
     const double r0 = p.sol[kSolidRow * s + 3];
     const int x = (((int)floor(X[0] - r0) - 2 + k0 % a.box) % a.nx + a.nx) % a.nx;
     const int y = (((int)floor(X[1] - r0) - 2 + (k0 / a.box) % a.box) % a.ny + a.ny) % a.ny;
@@ -466,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k3_refill(Ptrs p, const uint8_t* __res
         for (int j = 0; j < kQ; ++j) d[j] = acc[j] / np;
     } else {
         double v[3], r[3];
-        surface_vel(p.sol, s, t + 1, x, y, z, a, v, r);
+        surface_vel(sol_n, s, t + 1, x, y, z, a, v, r);
         const double uu = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         for (int j = 0; j < kQ; ++j) {
             const double eu = kE[j][0] * v[0] + kE[j][1] * v[1] + kE[j][2] * v[2];
@@ -489,6 +492,71 @@ __global__ __launch_bounds__(kBlock) void k3_finalize(const double* __restrict__
     if (t < 1) return;
     finalize3(partial2 + (size_t)((t - 1) & 1) * a.nchunks * 12, solid_chunk0, hist, t - 1, (int)blockIdx.x, a,
               red);
+}
+
+// Free spheres after step t (one thread per solid slot): the step's force
+// and torque of the chosen scheme, summed over the sphere's chunks in order,
+// drive the explicit Newton-Euler step V' = V + (F + (M - rho0 Vol) G)/M,
+// Omega' = Omega + T/I, X' = X + V' into the next parity's table; every
+// other row is copied.  A free sphere that comes within 2 nodes of the duct
+// or another sphere, or moves more than half a node, sets bit 1 of err.
+struct FreeArgs3 {
+    const double* sol_t;
+    double* sol_n;
+    const double* mass;       // [ns + 1][4]: M, I, Vol
+    const double* partial;    // step t's chunk partials
+    const int* solid_chunk0;
+    int* err;
+    double G[3];
+    int scheme;               // 0 CME, 1 GME
+};
+
+__global__ __launch_bounds__(kBlock) void k3_free(FreeArgs3 fa, int64_t t, Args a) {
+    const int s = (int)threadIdx.x;
+    if (s > a.ns) return;
+    const double* S = fa.sol_t + kSolidRow * s;
+    double* N = fa.sol_n + kSolidRow * s;
+    if (s == 0 || S[11] == 0.0) {
+        for (int q = 0; q < kSolidRow; ++q) N[q] = S[q];
+        return;
+    }
+    double F[6];
+    for (int q = 0; q < 6; ++q) {
+        double v = 0.0;
+        for (int cc = fa.solid_chunk0[s]; cc < fa.solid_chunk0[s + 1]; ++cc) v += fa.partial[cc * 12 + 6 * fa.scheme + q];
+        F[q] = v;
+    }
+    const double M = fa.mass[4 * s], I = fa.mass[4 * s + 1], Vol = fa.mass[4 * s + 2];
+    const double ext = M - a.rho0 * Vol;
+    for (int q = 0; q < kSolidRow; ++q) N[q] = S[q];
+    double speed2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        N[4 + d] = S[4 + d] + (F[d] + ext * fa.G[d]) / M;
+        N[7 + d] = S[7 + d] + F[3 + d] / I;
+        N[d] = S[d] + N[4 + d];
+        speed2 += N[4 + d] * N[4 + d];
+    }
+    bool bad = speed2 > 0.25;
+    const double r = S[3];
+    if (a.duct == 1) {
+        const double dy = N[1] - 0.5 * (a.ny - 1), dz = N[2] - 0.5 * (a.nz - 1);
+        bad |= sqrt(dy * dy + dz * dz) + r > a.R - 2.0;
+    } else if (a.duct == 2) {
+        bad |= N[2] - r < 2.0 || N[2] + r > a.nz - 3.0;
+    }
+    for (int j = 1; j <= a.ns; ++j) {
+        if (j == s) continue;
+        double Y[3];
+        centre3(fa.sol_t, j, t, Y);  // the other sphere at step t (good to a node)
+        double d2 = 0.0;
+        const int n3[3] = {a.nx, a.ny, a.nz};
+        for (int d = 0; d < 3; ++d) {
+            const double dd = min_image3(N[d] - Y[d], n3[d]);
+            d2 += dd * dd;
+        }
+        bad |= sqrt(d2) < r + fa.sol_t[kSolidRow * j + 3] + 2.0;
+    }
+    if (bad) atomicOr(fa.err, 1);
 }
 
 // f = f_eq(rho0, u0) at every fluid node, collided once; solid nodes zero.

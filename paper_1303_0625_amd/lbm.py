@@ -148,6 +148,10 @@ _SIG = {
     "lbm3d_force_history": (_I32, [_VP, _I64, _I64, _VP]),
     "lbm3d_fields": (_I32, [_VP, _VP, _VP, _VP]),
     "lbm3d_link_count": (_I64, [_VP]),
+    "lbm3d_set_free": (_I32, [_VP, _I32, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "lbm3d_set_gravity": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), _I32]),
+    "lbm3d_body_state": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_double)]),
+    "lbm3d_status_check": (_I32, [_VP]),
     "lbm3d_profile": (_I32, [_VP, _I32]),
     "lbm3d_profile_read": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "lbm3d_destroy": (None, [_VP]),
@@ -1039,6 +1043,24 @@ class Lattice3D:
 
     def link_count(self) -> int:
         return load_library().lbm3d_link_count(self.ctx)
+
+    def set_free(self, sphere: int, rho_s: float, omega0=(0.0, 0.0, 0.0)) -> None:
+        """Sphere `sphere` (created with moves=True) becomes a free particle."""
+        om = (ctypes.c_double * 3)(*[float(v) for v in omega0])
+        _check3(load_library().lbm3d_set_free(self.ctx, int(sphere), float(rho_s), om), self.ctx)
+
+    def set_gravity(self, G, scheme: int = 1) -> None:
+        g = (ctypes.c_double * 3)(*[float(v) for v in G])
+        _check3(load_library().lbm3d_set_gravity(self.ctx, g, int(scheme)), self.ctx)
+
+    def body_state(self, sphere: int):
+        """[X (3), V (3), Omega (3)] of a sphere at the current step."""
+        out = (ctypes.c_double * 9)()
+        _check3(load_library().lbm3d_body_state(self.ctx, int(sphere), out), self.ctx)
+        return list(out)
+
+    def check(self) -> None:
+        _check3(load_library().lbm3d_status_check(self.ctx), self.ctx)
 
     def profile(self, enable: bool) -> None:
         _check3(load_library().lbm3d_profile(self.ctx, int(bool(enable))), self.ctx)

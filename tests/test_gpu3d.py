@@ -209,3 +209,82 @@ def test_translating_sphere_path_check(lbm_mod):
     with pytest.raises(lbm_mod.lbm.LBMError):
         lat.step(40)
     assert lat.t == 5
+
+
+# --------------------------------------------------------------- free spheres
+def _free_pair(oracle_mod, lbm_mod, c, steps, free, G, scheme):
+    lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=steps)
+    osim = _oracle(oracle_mod, c)
+    for sid, rho_s, om in free:
+        osim.set_moving(sid, True, c.get("refill", 0))
+        osim.set_free(sid, rho_s, om)
+        lat.set_free(sid, rho_s, om)
+    osim.set_gravity(G, scheme)
+    lat.set_gravity(G, scheme)
+    _say(f"{c['name']} free={free} G={G} scheme={scheme} steps={steps}")
+    for _ in range(2):
+        lat.step(steps // 2)
+        osim.step(steps // 2)
+    lat.check()
+    assert osim.error == 0
+    return lat, osim
+
+
+def _compare_bodies(lat, osim, sid, tol):
+    g = np.array(lat.body_state(sid))
+    o = osim.body_state(sid)
+    dx = np.abs(g[:3] - o[:3]).max()
+    dv = np.abs(g[3:6] - o[3:6]).max() / max(np.abs(o[3:6]).max(), 1e-12)
+    dw = np.abs(g[6:] - o[6:]).max() / max(np.abs(o[6:]).max(), 1e-12)
+    _say(f"sphere {sid}: X {o[:3]} |V| {np.linalg.norm(o[3:6]):.3e} |Om| {np.linalg.norm(o[6:]):.3e}; "
+         f"|dX| {dx:.2e} rel dV {dv:.2e} rel dOm {dw:.2e}")
+    assert dx <= tol and dv <= tol and dw <= tol
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_free_sphere_sedimentation_f64(oracle_mod, lbm_mod, scheme):
+    """A heavy sphere falling along a tube, off the axis, CME or GME driving
+    it: FP64 fields, forces and the sphere's state against the oracle after it
+    has moved across nodes and turned."""
+    c = dict(name=f"free_sphere_s{scheme}", nx=40, ny=24, nz=24, tau=0.7, duct=1, R=10.3, refill=0,
+             spheres=[dict(cx=12.2, cy=13.1, cz=10.6, r=4.0, moves=True)])
+    lat, osim = _free_pair(oracle_mod, lbm_mod, c, 400, [(1, 1.4, (0.0, 0.0, 0.0))], (4e-4, 0.0, 0.0), scheme)
+    er, eu = field_err(lat, osim)
+    assert er <= 1e-12 and eu <= 1e-12
+    assert force_err(lat, osim) <= 1e-10
+    _compare_bodies(lat, osim, 1, 1e-9)
+    st = osim.body_state(1)
+    assert st[0] - 12.2 > 1.0 and np.abs(st[6:]).max() > 0  # it has fallen and turns
+
+
+def test_free_sphere_carried_by_tube_flow_f64(oracle_mod, lbm_mod):
+    """A spinning sphere (density 1.5, no gravity) released off the axis of a
+    tube Poiseuille flow and carried along by it: FP64 parity with the oracle,
+    refill A2.  (At density 1 the explicit coupling oscillates with period 2,
+    the known limit of explicit momentum exchange for neutrally buoyant
+    particles.)"""
+    c = dict(name="carried_sphere", nx=40, ny=24, nz=24, tau=0.6, duct=1, R=10.3, refill=1, g=(3e-5, 0.0, 0.0),
+             spheres=[dict(cx=10.0, cy=13.4, cz=11.5, r=3.6, moves=True)])
+    lat, osim = _free_pair(oracle_mod, lbm_mod, c, 400, [(1, 1.5, (0.0, 0.0, 0.001))], (0.0, 0.0, 0.0), 1)
+    er, eu = field_err(lat, osim)
+    assert er <= 1e-12 and eu <= 1e-12
+    assert force_err(lat, osim) <= 1e-10
+    _compare_bodies(lat, osim, 1, 1e-9)
+
+
+def test_free_sphere_api_guards(lbm_mod):
+    L = lbm_mod.lbm
+    c = dict(nx=24, ny=20, nz=20, tau=0.7, spheres=[dict(cx=10.0, cy=9.5, cz=9.5, r=3.0, moves=True),
+                                                     dict(cx=20.0, cy=9.5, cz=9.5, r=2.0)])
+    lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=8)
+    with pytest.raises(L.LBMError):
+        lat.set_free(2, 1.2)  # not created moving
+    with pytest.raises(L.LBMError):
+        lat.set_free(1, -1.0)
+    lat.set_free(1, 1.2)
+    lat.step(2)
+    with pytest.raises(L.LBMError):
+        lat.set_free(1, 1.3)  # after the first step
+    lat.check()
+    st = lat.body_state(1)
+    assert abs(st[0] - 10.0) < 1e-6
