@@ -321,6 +321,7 @@ def _load3():
     lib.orc3_set_free.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, dp]
     lib.orc3_set_free.restype = ctypes.c_int
     lib.orc3_set_gravity.argtypes = [ctypes.c_void_p, dp, ctypes.c_int]
+    lib.orc3_set_force_average.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc3_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     lib.orc3_body_state.restype = ctypes.c_int
     u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -407,6 +408,10 @@ class OracleSim3D:
 
     def set_gravity(self, G, scheme: int) -> None:
         self._lib.orc3_set_gravity(self._h, _dp(_vec(G)), int(scheme))
+
+    def set_force_average(self, on: bool = True) -> None:
+        """Free spheres take the mean force of the last two steps."""
+        self._lib.orc3_set_force_average(self._h, int(bool(on)))
 
     def body_state(self, sphere: int) -> np.ndarray:
         """{X (3), V (3), Omega (3)} of sphere `sphere` now."""

@@ -67,6 +67,7 @@ struct orc3_sim {
     double* mass; /* per sphere: M, I, volume */
     double G[3];
     int dyn_scheme;
+    int force_avg; /* drive free spheres with the mean force of steps t - 1 and t */
     int advanced; /* dyn holds step t + 1 in its second half */
     int refill;  /* ORC3_A1 / A2 / A3 */
     int err;     /* geometry error met while stepping */
@@ -372,6 +373,12 @@ static void one_step(orc3_sim* s) {
     for (int k = 0; k < s->ns; ++k) {
         if (!s->free_[k]) continue;
         const double* hk = h + 12 * (k + 1) + 6 * s->dyn_scheme;
+        double havg[6];
+        if (s->force_avg && s->t >= 1) {
+            const double* hp = s->hist + ((s->t - 1) * (s->ns + 1) + (k + 1)) * 12 + 6 * s->dyn_scheme;
+            for (int q = 0; q < 6; ++q) havg[q] = 0.5 * (hk[q] + hp[q]);
+            hk = havg;
+        }
         double* D = s->dyn + 18 * k;
         const double M = s->mass[3 * k], I = s->mass[3 * k + 1], Vol = s->mass[3 * k + 2];
         const double ext = M - s->rho0 * Vol;
@@ -441,6 +448,8 @@ int orc3_set_free(orc3_sim* s, int sphere, double rho_s, const double omega0[3])
     }
     return 0;
 }
+
+void orc3_set_force_average(orc3_sim* s, int on) { s->force_avg = on ? 1 : 0; }
 
 void orc3_set_gravity(orc3_sim* s, const double G[3], int scheme) {
     for (int d = 0; d < 3; ++d) s->G[d] = G[d];

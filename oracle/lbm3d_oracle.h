@@ -45,6 +45,9 @@ void orc3_refill_node(int nx, int ny, int nz, const double* fn, const unsigned c
 /* Sphere `sphere` (created moving) becomes free: density rho_s, initial spin
  * omega0, initial velocity its V (before the first step only). */
 int orc3_set_free(orc3_sim* s, int sphere, double rho_s, const double omega0[3]);
+/* Drive free spheres with the mean of the forces and torques of steps t - 1
+ * and t (step 0: its own), the two-step average of particle suspensions. */
+void orc3_set_force_average(orc3_sim* s, int on);
 /* Gravity on free spheres (buoyancy-corrected) and the scheme that drives them. */
 void orc3_set_gravity(orc3_sim* s, const double G[3], int scheme);
 /* {X, V, Omega} of sphere `sphere` at the current step. */

@@ -343,3 +343,38 @@ def test_free_sphere_spin_down_3d(oracle_mod):
         prev = st[7]
         assert abs(st[6]) <= 1e-15 and abs(st[8]) <= 1e-15
         assert np.abs(st[:3] - 10.0).max() <= 1e-13
+
+
+def test_free_sphere_force_average_3d(oracle_mod):
+    """With the two-step force average the sphere gains sum_s (F_s + F_{s-1})/2
+    (F_{-1} = F_0): fluid plus sphere momentum then balances to
+    (F_0 - F_{T-1})/2 exactly; and a neutrally buoyant sphere carried by
+    tube flow, which the plain explicit update throws off, moves smoothly."""
+    e, _ = _lookup(oracle_mod)
+    r, rho_s, G = 4.3, 1.5, np.array([2e-6, -1e-6, 1.5e-6])
+    s = oracle_mod.OracleSim3D(22, 20, 18, 0.7, spheres=[dict(cx=10.3, cy=9.6, cz=8.7, r=r)])
+    s.set_moving(1, True, 0)
+    s.set_free(1, rho_s)
+    s.set_gravity(G, oracle_mod.CME)
+    s.set_force_average(True)
+    vol = 4 / 3 * np.pi * r ** 3
+    M = rho_s * vol
+    P0 = _fluid_momentum3(s, e)
+    T = 60
+    s.step(T)
+    F0, Fl = s.force(1, oracle_mod.CME, 0)[:3], s.force(1, oracle_mod.CME, T - 1)[:3]
+    st = s.body_state(1)
+    bal = _fluid_momentum3(s, e) + M * st[3:6] - P0 - T * (M - vol) * G - 0.5 * (F0 - Fl)
+    assert np.abs(bal).max() < 1e-12
+    n = oracle_mod.OracleSim3D(40, 24, 24, 0.6, g=(3e-5, 0, 0), duct=oracle_mod.TUBE3, R=10.3,
+                               spheres=[dict(cx=10.0, cy=13.4, cz=11.5, r=3.6)])
+    n.set_moving(1, True, 1)
+    n.set_free(1, 1.0)
+    n.set_force_average(True)
+    vx = []
+    for _ in range(200):
+        n.step(1)
+        vx.append(n.body_state(1)[3])
+    vx = np.array(vx)
+    assert n.error == 0
+    assert 0 < vx[-1] < 0.02 and np.abs(np.diff(vx[-100:])).max() < 1e-4
