@@ -634,6 +634,12 @@ lbm_status lbm3d_set_free(lbm3d_ctx* ctx, int32_t sphere, double rho_s, const do
  * the force scheme (LBM_CME / LBM_GME) that drives them. */
 lbm_status lbm3d_set_gravity(lbm3d_ctx* ctx, const double G[3], int32_t scheme);
 
+/* enable != 0: free spheres are driven by the mean of the forces and torques
+ * of steps t - 1 and t (step 0: its own), the two-step average used for
+ * suspended particles; it keeps spheres near neutral buoyancy (rho_s ~ rho0)
+ * stable, where the plain explicit update oscillates and diverges. */
+lbm_status lbm3d_set_force_average(lbm3d_ctx* ctx, int32_t enable);
+
 /* out = {X, V, Omega} (three components each) of sphere `sphere` at the
  * current step.  Synchronises. */
 lbm_status lbm3d_body_state(lbm3d_ctx* ctx, int32_t sphere, double out[9]);

@@ -60,6 +60,7 @@ struct lbm3d_ctx {
     int nfree = 0;
     double G[3] = {0.0, 0.0, 0.0};
     int dyn_scheme = LBM_GME;
+    int force_avg = 0;
     bool prof = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
@@ -498,6 +499,9 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
             fa.sol_n = sol_n;
             fa.mass = at<double>(c, c->L.mass);
             fa.partial = p.partial + (size_t)(c->t & 1) * c->L.nchunks * 12;
+            // step t - 1's partials are intact until step t + 1 writes them
+            fa.partial_prev = (c->force_avg && c->t >= 1) ? p.partial + (size_t)((c->t - 1) & 1) * c->L.nchunks * 12
+                                                           : nullptr;
             fa.solid_chunk0 = p.solid_chunk0;
             fa.err = at<int>(c, c->L.err);
             for (int d = 0; d < 3; ++d) fa.G[d] = c->G[d];
@@ -611,6 +615,12 @@ lbm_status lbm3d_set_gravity(lbm3d_ctx* c, const double G[3], int32_t scheme) {
     if (!c || !G || (scheme != LBM_CME && scheme != LBM_GME)) return LBM_EINVAL;
     for (int d = 0; d < 3; ++d) c->G[d] = G[d];
     c->dyn_scheme = scheme;
+    return LBM_OK;
+}
+
+lbm_status lbm3d_set_force_average(lbm3d_ctx* c, int32_t enable) {
+    if (!c) return LBM_EINVAL;
+    c->force_avg = enable != 0;
     return LBM_OK;
 }
 

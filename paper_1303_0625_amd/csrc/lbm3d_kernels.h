@@ -505,6 +505,7 @@ struct FreeArgs3 {
     double* sol_n;
     const double* mass;       // [ns + 1][4]: M, I, Vol
     const double* partial;    // step t's chunk partials
+    const double* partial_prev;  // step t - 1's (force average), or nullptr
     const int* solid_chunk0;
     int* err;
     double G[3];
@@ -520,10 +521,17 @@ __global__ __launch_bounds__(kBlock) void k3_free(FreeArgs3 fa, int64_t t, Args 
         for (int q = 0; q < kSolidRow; ++q) N[q] = S[q];
         return;
     }
+    // with the two-step average: the mean of the totals of steps t - 1 and t
     double F[6];
     for (int q = 0; q < 6; ++q) {
         double v = 0.0;
         for (int cc = fa.solid_chunk0[s]; cc < fa.solid_chunk0[s + 1]; ++cc) v += fa.partial[cc * 12 + 6 * fa.scheme + q];
+        if (fa.partial_prev) {
+            double w = 0.0;
+            for (int cc = fa.solid_chunk0[s]; cc < fa.solid_chunk0[s + 1]; ++cc)
+                w += fa.partial_prev[cc * 12 + 6 * fa.scheme + q];
+            v = 0.5 * (v + w);
+        }
         F[q] = v;
     }
     const double M = fa.mass[4 * s], I = fa.mass[4 * s + 1], Vol = fa.mass[4 * s + 2];

@@ -212,9 +212,12 @@ def test_translating_sphere_path_check(lbm_mod):
 
 
 # --------------------------------------------------------------- free spheres
-def _free_pair(oracle_mod, lbm_mod, c, steps, free, G, scheme):
+def _free_pair(oracle_mod, lbm_mod, c, steps, free, G, scheme, average=False):
     lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=steps)
     osim = _oracle(oracle_mod, c)
+    if average:
+        lat.set_force_average(True)
+        osim.set_force_average(True)
     for sid, rho_s, om in free:
         osim.set_moving(sid, True, c.get("refill", 0))
         osim.set_free(sid, rho_s, om)
@@ -288,3 +291,18 @@ def test_free_sphere_api_guards(lbm_mod):
     lat.check()
     st = lat.body_state(1)
     assert abs(st[0] - 10.0) < 1e-6
+
+
+def test_neutral_sphere_force_average_f64(oracle_mod, lbm_mod):
+    """A neutrally buoyant sphere released off the axis of a tube Poiseuille
+    flow with the two-step force average (the Sec. IV.D setting, small): FP64
+    parity with the oracle while it is carried along."""
+    c = dict(name="neutral_sphere_avg", nx=40, ny=24, nz=24, tau=0.6, duct=1, R=10.3, refill=0,
+             g=(3e-5, 0.0, 0.0), spheres=[dict(cx=10.0, cy=13.4, cz=11.5, r=3.6, moves=True)])
+    lat, osim = _free_pair(oracle_mod, lbm_mod, c, 400, [(1, 1.0, (0.0, 0.0, 0.0))], (0.0, 0.0, 0.0), 1,
+                           average=True)
+    er, eu = field_err(lat, osim)
+    assert er <= 1e-12 and eu <= 1e-12
+    assert force_err(lat, osim) <= 1e-10
+    _compare_bodies(lat, osim, 1, 1e-9)
+    assert osim.body_state(1)[0] > 11.0  # carried downstream
