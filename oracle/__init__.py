@@ -322,6 +322,8 @@ def _load3():
     lib.orc3_set_free.restype = ctypes.c_int
     lib.orc3_set_gravity.argtypes = [ctypes.c_void_p, dp, ctypes.c_int]
     lib.orc3_set_force_average.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.orc3_set_pressure.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    lib.orc3_set_pressure.restype = ctypes.c_int
     lib.orc3_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     lib.orc3_body_state.restype = ctypes.c_int
     u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -408,6 +410,11 @@ class OracleSim3D:
 
     def set_gravity(self, G, scheme: int) -> None:
         self._lib.orc3_set_gravity(self._h, _dp(_vec(G)), int(scheme))
+
+    def set_pressure(self, rho_in: float, rho_out: float) -> None:
+        """Pressure inlet (x = 0) and outlet (x = nx - 1) densities."""
+        if self._lib.orc3_set_pressure(self._h, float(rho_in), float(rho_out)) != 0:
+            raise ValueError("oracle rejected the pressure boundary")
 
     def set_force_average(self, on: bool = True) -> None:
         """Free spheres take the mean force of the last two steps."""

@@ -68,6 +68,8 @@ struct orc3_sim {
     double G[3];
     int dyn_scheme;
     int force_avg; /* drive free spheres with the mean force of steps t - 1 and t */
+    int pressure;  /* inlet x = 0 at rho_in, outlet x = nx - 1 at rho_out */
+    double rho_in, rho_out;
     int advanced; /* dyn holds step t + 1 in its second half */
     int refill;  /* ORC3_A1 / A2 / A3 */
     int err;     /* geometry error met while stepping */
@@ -319,6 +321,30 @@ static void one_step(orc3_sim* s) {
                 orc3_collide_node(fl, s->tau, s->g, out);
                 for (int i = 0; i < 19; ++i) s->ft[pidx(s, i, x, y, z)] = out[i];
             }
+    /* pressure inlet and outlet (non-equilibrium extrapolation): the
+     * post-collision populations of the planes x = 0 and x = nx - 1 become
+     * f_eq(rho_b, u) + (f~ - f_eq(rho, u)) of the fluid node next to them,
+     * rho and u its density and momentum over density */
+    if (s->pressure)
+        for (int side = 0; side < 2; ++side) {
+            const int xb = side == 0 ? 0 : nx - 1, xf = side == 0 ? 1 : nx - 2;
+            const double rb = side == 0 ? s->rho_in : s->rho_out;
+            for (int z = 0; z < nz; ++z)
+                for (int y = 0; y < ny; ++y) {
+                    if (s->own[nidx(s, xb, y, z)] != 0 || s->own[nidx(s, xf, y, z)] != 0) continue;
+                    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+                    for (int i = 0; i < 19; ++i) {
+                        const double fi = s->ft[pidx(s, i, xf, y, z)];
+                        r += fi;
+                        for (int d = 0; d < 3; ++d) j[d] += E[i][d] * fi;
+                    }
+                    const double u[3] = {j[0] / r, j[1] / r, j[2] / r};
+                    double eb[19], ef[19];
+                    orc3_feq(rb, u, eb);
+                    orc3_feq(r, u, ef);
+                    for (int i = 0; i < 19; ++i) s->ft[pidx(s, i, xb, y, z)] = eb[i] + (s->ft[pidx(s, i, xf, y, z)] - ef[i]);
+                }
+        }
     /* forces on every fluid-solid link */
     double* h = hist_row(s, s->t);
     memset(h, 0, sizeof(double) * (size_t)(s->ns + 1) * 12);
@@ -450,6 +476,16 @@ int orc3_set_free(orc3_sim* s, int sphere, double rho_s, const double omega0[3])
 }
 
 void orc3_set_force_average(orc3_sim* s, int on) { s->force_avg = on ? 1 : 0; }
+
+int orc3_set_pressure(orc3_sim* s, double rho_in, double rho_out) {
+    for (int k = 0; k < s->ns; ++k)
+        if (s->moving[k]) return -1;
+    if (!(rho_in > 0.0) || !(rho_out > 0.0) || s->t != 0) return -1;
+    s->pressure = 1;
+    s->rho_in = rho_in;
+    s->rho_out = rho_out;
+    return 0;
+}
 
 void orc3_set_gravity(orc3_sim* s, const double G[3], int scheme) {
     for (int d = 0; d < 3; ++d) s->G[d] = G[d];

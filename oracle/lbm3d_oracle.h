@@ -48,6 +48,10 @@ int orc3_set_free(orc3_sim* s, int sphere, double rho_s, const double omega0[3])
 /* Drive free spheres with the mean of the forces and torques of steps t - 1
  * and t (step 0: its own), the two-step average of particle suspensions. */
 void orc3_set_force_average(orc3_sim* s, int on);
+/* Pressure inlet x = 0 (density rho_in) and outlet x = nx - 1 (rho_out) by
+ * non-equilibrium extrapolation of the post-collision populations from the
+ * neighbouring plane; no moving spheres; before the first step. */
+int orc3_set_pressure(orc3_sim* s, double rho_in, double rho_out);
 /* Gravity on free spheres (buoyancy-corrected) and the scheme that drives them. */
 void orc3_set_gravity(orc3_sim* s, const double G[3], int scheme);
 /* {X, V, Omega} of sphere `sphere` at the current step. */

@@ -378,3 +378,32 @@ def test_free_sphere_force_average_3d(oracle_mod):
     vx = np.array(vx)
     assert n.error == 0
     assert 0 < vx[-1] < 0.02 and np.abs(np.diff(vx[-100:])).max() < 1e-4
+
+
+def test_pressure_driven_planes_poiseuille_3d(oracle_mod):
+    """Pressure inlet and outlet (non-equilibrium extrapolation) between the
+    planes z = 0 and z = nz - 1: at steady state the mass flux is the same
+    through every cross-section, and the profile is the exact discrete
+    Poiseuille profile for the local pressure gradient (rho/3)' (up to the
+    fluid's compressibility, O(drho))."""
+    nx, ny, nz, tau, drho = 24, 3, 12, 1.0, 4e-4
+    s = oracle_mod.OracleSim3D(nx, ny, nz, tau, duct=oracle_mod.PLANES3)
+    s.set_pressure(1 + drho / 2, 1 - drho / 2)
+    s.step(6000)
+    rho, u, own = s.fields()
+    flux = (rho * u[0])[:, 1, :].sum(0)
+    assert np.ptp(flux[1:-1]) <= 1e-9 * abs(flux.mean())
+    x, nu = nx // 2, (tau - 0.5) / 3
+    rm = rho[1:-1, 1, :].mean(0)
+    g = -(rm[x + 4] - rm[x - 4]) / 8 / 3 / rm[x]
+    z = np.arange(nz)
+    exact = g / (2 * nu) * (((nz - 2) / 2) ** 2 - (z - (nz - 1) / 2) ** 2) + \
+        g * (4 * (2 * tau - 1) ** 2 - 3) / (4 * (2 * tau - 1))
+    prof = u[0][:, 1, x]
+    assert g > 0 and np.abs(prof - exact)[1:-1].max() <= 1e-4 * exact.max()
+    # (the boundary planes' streamed state is replaced after each collision)
+    assert np.abs(u[2][:, :, 1:-1]).max() <= 1e-5 * exact.max()  # entrance effects only
+    with pytest.raises(ValueError):  # not with moving spheres
+        m = oracle_mod.OracleSim3D(20, 20, 20, 0.7, spheres=[dict(cx=10.0, cy=10.0, cz=10.0, r=3.0)])
+        m.set_moving(1, True, 0)
+        m.set_pressure(1.001, 0.999)
