@@ -634,6 +634,15 @@ lbm_status lbm3d_set_free(lbm3d_ctx* ctx, int32_t sphere, double rho_s, const do
  * the force scheme (LBM_CME / LBM_GME) that drives them. */
 lbm_status lbm3d_set_gravity(lbm3d_ctx* ctx, const double G[3], int32_t scheme);
 
+/* Pressure-driven duct (Sec. IV.D): the planes x = 0 and x = nx - 1 become a
+ * pressure inlet (density rho_in) and outlet (rho_out) by non-equilibrium
+ * extrapolation: after each step's collision their populations are
+ * f_eq(rho_b, u) + (f~ - f_eq(rho, u)) of the neighbouring plane's node
+ * (rho and u its density and momentum over density), replacing what the
+ * periodic x axis streamed there.  Fixed spheres only (LBM_EINVAL with
+ * moving ones); before the first step (LBM_ESTATE after).  Asynchronous. */
+lbm_status lbm3d_set_pressure(lbm3d_ctx* ctx, double rho_in, double rho_out);
+
 /* enable != 0: free spheres are driven by the mean of the forces and torques
  * of steps t - 1 and t (step 0: its own), the two-step average used for
  * suspended particles; it keeps spheres near neutral buoyancy (rho_s ~ rho0)

@@ -61,6 +61,8 @@ struct lbm3d_ctx {
     double G[3] = {0.0, 0.0, 0.0};
     int dyn_scheme = LBM_GME;
     int force_avg = 0;
+    int pressure = 0;
+    double rho_in = 1.0, rho_out = 1.0;
     bool prof = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
@@ -491,6 +493,14 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
             else
                 k3_step<float, false><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
         }
+        if (c->pressure) {
+            const unsigned npb = (unsigned)((2 * (int64_t)c->g.ny * c->g.nz + kBlock - 1) / kBlock);
+            const uint8_t* own_t = at<uint8_t>(c, c->L.own[par]);
+            if (c->g.dtype == LBM_F64)
+                k3_pressure<double><<<npb, kBlock, 0, c->stream>>>((double*)p.fout, own_t, a, c->rho_in, c->rho_out);
+            else
+                k3_pressure<float><<<npb, kBlock, 0, c->stream>>>((float*)p.fout, own_t, a, c->rho_in, c->rho_out);
+        }
         double* sol_n = at<double>(c, c->L.sol[par ^ 1]);
         if (c->nfree > 0) {
             // free spheres: Newton-Euler step from this step's forces
@@ -615,6 +625,32 @@ lbm_status lbm3d_set_gravity(lbm3d_ctx* c, const double G[3], int32_t scheme) {
     if (!c || !G || (scheme != LBM_CME && scheme != LBM_GME)) return LBM_EINVAL;
     for (int d = 0; d < 3; ++d) c->G[d] = G[d];
     c->dyn_scheme = scheme;
+    return LBM_OK;
+}
+
+lbm_status lbm3d_set_pressure(lbm3d_ctx* c, double rho_in, double rho_out) {
+    if (!c || !(rho_in > 0.0) || !(rho_out > 0.0)) return LBM_EINVAL;
+    if (c->L.nmovers > 0) {
+        set_err3(c->err, "pressure boundaries are for fixed spheres only");
+        return LBM_EINVAL;
+    }
+    if (c->t != 0) {
+        set_err3(c->err, "pressure boundaries are set before the first step");
+        return LBM_ESTATE;
+    }
+    c->pressure = 1;
+    c->rho_in = rho_in;
+    c->rho_out = rho_out;
+    // the initial post-collision state takes the boundary values too
+    const Args a = args3(c);
+    const unsigned npb = (unsigned)((2 * (int64_t)c->g.ny * c->g.nz + kBlock - 1) / kBlock);
+    if (c->g.dtype == LBM_F64)
+        k3_pressure<double><<<npb, kBlock, 0, c->stream>>>(at<double>(c, c->L.f[0]), at<uint8_t>(c, c->L.own[0]), a,
+                                                           rho_in, rho_out);
+    else
+        k3_pressure<float><<<npb, kBlock, 0, c->stream>>>(at<float>(c, c->L.f[0]), at<uint8_t>(c, c->L.own[0]), a,
+                                                          rho_in, rho_out);
+    HIPCHK3(c, hipGetLastError());
     return LBM_OK;
 }
 

@@ -567,6 +567,39 @@ __global__ __launch_bounds__(kBlock) void k3_free(FreeArgs3 fa, int64_t t, Args 
     if (bad) atomicOr(fa.err, 1);
 }
 
+// Pressure inlet (x = 0, density rho_in) and outlet (x = nx - 1, rho_out)
+// by non-equilibrium extrapolation, on the post-collision state: the plane
+// takes f_eq(rho_b, u) + (f~ - f_eq(rho, u)) of its fluid neighbour (rho, u:
+// the neighbour's density and momentum over density), i.e. in deviations
+// d_b = d + w_i (rho_b - rho)(1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2).  One
+// thread per (line, side); the periodic pull into these planes is replaced.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k3_pressure(T* __restrict__ f, const uint8_t* __restrict__ own, Args a,
+                                                      double rho_in, double rho_out) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t lines = (int64_t)a.ny * a.nz;
+    if (k >= 2 * lines) return;
+    const int side = (int)(k / lines);
+    const int64_t line = k % lines;
+    const int xb = side == 0 ? 0 : a.nx - 1, xf = side == 0 ? 1 : a.nx - 2;
+    if (own[line * a.pitch + xb] != 0 || own[line * a.pitch + xf] != 0) return;
+    double d[kQ];
+    double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < kQ; ++i) {
+        d[i] = (double)Sto<T>::ld(f[(line * kQ + i) * a.pitch + xf]);
+        drho += d[i];
+        for (int c = 0; c < 3; ++c) j[c] += kE[i][c] * d[i];
+    }
+    const double rho = a.rho0 + drho;
+    const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double dr = (side == 0 ? rho_in : rho_out) - rho;
+    for (int i = 0; i < kQ; ++i) {
+        const double eu = kE[i][0] * u[0] + kE[i][1] * u[1] + kE[i][2] * u[2];
+        f[(line * kQ + i) * a.pitch + xb] = Sto<T>::st(d[i] + w3(i) * dr * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+    }
+}
+
 // f = f_eq(rho0, u0) at every fluid node, collided once; solid nodes zero.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k3_init(T* __restrict__ f, const uint8_t* __restrict__ own, Args a,
