@@ -323,6 +323,9 @@ def _load3():
     lib.orc3_set_gravity.argtypes = [ctypes.c_void_p, dp, ctypes.c_int]
     lib.orc3_set_force_average.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc3_set_pressure.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]
+    lib.orc3_set_ibb.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.orc3_link_q.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc3_link_q.restype = ctypes.c_double
     lib.orc3_set_pressure.restype = ctypes.c_int
     lib.orc3_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     lib.orc3_body_state.restype = ctypes.c_int
@@ -410,6 +413,13 @@ class OracleSim3D:
 
     def set_gravity(self, G, scheme: int) -> None:
         self._lib.orc3_set_gravity(self._h, _dp(_vec(G)), int(scheme))
+
+    def set_ibb(self, on: bool = True) -> None:
+        """Interpolated bounce-back on sphere links."""
+        self._lib.orc3_set_ibb(self._h, int(bool(on)))
+
+    def link_q(self, sphere: int, x: int, y: int, z: int, i: int) -> float:
+        return self._lib.orc3_link_q(self._h, int(sphere), int(x), int(y), int(z), int(i))
 
     def set_pressure(self, rho_in: float, rho_out: float) -> None:
         """Pressure inlet (x = 0) and outlet (x = nx - 1) densities."""

@@ -69,6 +69,7 @@ struct orc3_sim {
     int dyn_scheme;
     int force_avg; /* drive free spheres with the mean force of steps t - 1 and t */
     int pressure;  /* inlet x = 0 at rho_in, outlet x = nx - 1 at rho_out */
+    int ibb;       /* interpolated bounce-back on sphere links */
     double rho_in, rho_out;
     int advanced; /* dyn holds step t + 1 in its second half */
     int refill;  /* ORC3_A1 / A2 / A3 */
@@ -161,6 +162,35 @@ static void surface_velocity(const orc3_sim* s, int owner, long t, double px, do
     v[1] = V[1] + (Om[2] * r[0] - Om[0] * r[2]);
     v[2] = V[2] + (Om[0] * r[1] - Om[1] * r[0]);
 }
+
+/* Fraction q in (0, 1] of the link from fluid node (x, y, z) along e into
+ * sphere k at step t: the nearer root of |P + q e|^2 = r^2, P the node's
+ * minimum-image offset from the centre. */
+static double sphere_q(const orc3_sim* s, int k, long t, int x, int y, int z, const int e[3]) {
+    double X[3];
+    centre(s, k, t, X);
+    const double P[3] = {min_image((double)x - X[0], s->nx), min_image((double)y - X[1], s->ny),
+                         min_image((double)z - X[2], s->nz)};
+    const double r = s->sp[10 * k + 3];
+    double a2 = 0.0, b2 = 0.0, c2 = -r * r;
+    for (int d = 0; d < 3; ++d) {
+        a2 += (double)(e[d] * e[d]);
+        b2 += 2.0 * P[d] * e[d];
+        c2 += P[d] * P[d];
+    }
+    double disc = b2 * b2 - 4.0 * a2 * c2;
+    if (disc < 0.0) disc = 0.0;
+    double q = (-b2 - sqrt(disc)) / (2.0 * a2);
+    if (q <= 0.0) q = 1e-12;
+    return q > 1.0 ? 1.0 : q;
+}
+
+double orc3_link_q(const orc3_sim* s, int sphere, int x, int y, int z, int i) {
+    if (sphere < 1 || sphere > s->ns || i < 1 || i > 18) return -1.0;
+    return sphere_q(s, sphere - 1, s->t, x, y, z, E[i]);
+}
+
+void orc3_set_ibb(orc3_sim* s, int on) { s->ibb = on ? 1 : 0; }
 
 void orc3_feq(double rho, const double u[3], double out[19]) {
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -356,10 +386,22 @@ static void one_step(orc3_sim* s) {
                     int xb = wrap(x + E[i][0], nx), yb = wrap(y + E[i][1], ny), zb = wrap(z + E[i][2], nz);
                     int o = s->own[nidx(s, xb, yb, zb)];
                     if (o == 0) continue;
+                    /* surface point x_f + q e_i: q = 1/2 (half-way), or the link
+                     * fraction into a sphere under interpolated bounce-back */
+                    const double q = (s->ibb && o != 255) ? sphere_q(s, o - 1, s->t, x, y, z, E[i]) : 0.5;
                     double v[3], r[3];
-                    surface_velocity(s, o, s->t, x + 0.5 * E[i][0], y + 0.5 * E[i][1], z + 0.5 * E[i][2], v, r);
+                    surface_velocity(s, o, s->t, x + q * E[i][0], y + q * E[i][1], z + q * E[i][2], v, r);
                     double a = s->ft[pidx(s, i, x, y, z)];
-                    double b = a - 6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
+                    const double m = 6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
+                    double b = a - m;
+                    if (q < 0.5) {
+                        const int xq = wrap(x - E[i][0], nx), yq = wrap(y - E[i][1], ny), zq = wrap(z - E[i][2], nz);
+                        if (s->own[nidx(s, xq, yq, zq)] == 0)
+                            b = 2.0 * q * a + (1.0 - 2.0 * q) * s->ft[pidx(s, i, xq, yq, zq)] - m;
+                    } else if (q > 0.5) {
+                        b = a / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->ft[pidx(s, opposite(i), x, y, z)] -
+                            m / (2.0 * q);
+                    }
                     double* hs = h + 12 * (o == 255 ? 0 : o);
                     for (int sch = 0; sch < 2; ++sch) {
                         double F[3];
@@ -386,11 +428,21 @@ static void one_step(orc3_sim* s) {
                     if (o == 0) {
                         val = s->ft[pidx(s, i, xs, ys, zs)];
                     } else {
+                        int me[3] = {-E[i][0], -E[i][1], -E[i][2]};
+                        const double q = (s->ibb && o != 255) ? sphere_q(s, o - 1, s->t, x, y, z, me) : 0.5;
                         double v[3], r[3];
-                        surface_velocity(s, o, s->t, x - 0.5 * E[i][0], y - 0.5 * E[i][1], z - 0.5 * E[i][2], v,
-                                         r);
-                        val = s->ft[pidx(s, opposite(i), x, y, z)] +
-                              6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
+                        surface_velocity(s, o, s->t, x - q * E[i][0], y - q * E[i][1], z - q * E[i][2], v, r);
+                        const double m = 6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);
+                        const double fo = s->ft[pidx(s, opposite(i), x, y, z)];
+                        val = fo + m;
+                        if (q < 0.5) {
+                            const int xq = wrap(x + E[i][0], nx), yq = wrap(y + E[i][1], ny), zq = wrap(z + E[i][2], nz);
+                            if (s->own[nidx(s, xq, yq, zq)] == 0)
+                                val = 2.0 * q * fo + (1.0 - 2.0 * q) * s->ft[pidx(s, opposite(i), xq, yq, zq)] + m;
+                        } else if (q > 0.5) {
+                            val = fo / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->ft[pidx(s, i, x, y, z)] +
+                                  m / (2.0 * q);
+                        }
                     }
                     s->fn[pidx(s, i, x, y, z)] = val;
                 }
