@@ -62,6 +62,7 @@ struct lbm3d_ctx {
     int dyn_scheme = LBM_GME;
     int force_avg = 0;
     int pressure = 0;
+    int ibb = 0;
     double rho_in = 1.0, rho_out = 1.0;
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -261,6 +262,7 @@ Args args3(const lbm3d_ctx* c) {
     a.R = c->g.R;
     a.box = c->L.box;
     a.refill = c->g.refill;
+    a.ibb = c->ibb;
     return a;
 }
 
@@ -482,16 +484,16 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
         p.sol = at<double>(c, c->L.sol[par]);
         const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
         if (timed) HIPCHK3(c, hipEventRecord(c->ev[c->ev_used], c->stream));
-        if (c->g.dtype == LBM_F64) {
-            if (nt)
-                k3_step<double, true><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
+        {
+            using K = decltype(&k3_step<double, true, true>);
+            void (*kern)(Ptrs, int, int, Args) = nullptr;
+            if (c->g.dtype == LBM_F64)
+                kern = c->ibb ? (nt ? (K)k3_step<double, true, true> : (K)k3_step<double, false, true>)
+                              : (nt ? (K)k3_step<double, true, false> : (K)k3_step<double, false, false>);
             else
-                k3_step<double, false><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
-        } else {
-            if (nt)
-                k3_step<float, true><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
-            else
-                k3_step<float, false><<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
+                kern = c->ibb ? (nt ? (K)k3_step<float, true, true> : (K)k3_step<float, false, true>)
+                              : (nt ? (K)k3_step<float, true, false> : (K)k3_step<float, false, false>);
+            kern<<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
         }
         if (c->pressure) {
             const unsigned npb = (unsigned)((2 * (int64_t)c->g.ny * c->g.nz + kBlock - 1) / kBlock);
@@ -625,6 +627,16 @@ lbm_status lbm3d_set_gravity(lbm3d_ctx* c, const double G[3], int32_t scheme) {
     if (!c || !G || (scheme != LBM_CME && scheme != LBM_GME)) return LBM_EINVAL;
     for (int d = 0; d < 3; ++d) c->G[d] = G[d];
     c->dyn_scheme = scheme;
+    return LBM_OK;
+}
+
+lbm_status lbm3d_set_boundary(lbm3d_ctx* c, int32_t rule) {
+    if (!c) return LBM_EINVAL;
+    if (rule != LBM_HALFWAY && rule != LBM_INTERPOLATED) {
+        set_err3(c->err, "rule must be LBM_HALFWAY or LBM_INTERPOLATED");
+        return LBM_EINVAL;
+    }
+    c->ibb = rule == LBM_INTERPOLATED ? 1 : 0;
     return LBM_OK;
 }
 

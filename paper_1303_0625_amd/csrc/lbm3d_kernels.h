@@ -48,6 +48,7 @@ struct Args {
     double R;         // tube radius
     int box;          // edge of a moving sphere's scan box (nodes)
     int refill;       // 0 A1, 1 A2, 2 A3
+    int ibb;          // interpolated bounce-back on sphere links
 };
 
 // Solid table row: X, r, V (3), Omega (3), moves, free; row 0 is the duct.
@@ -88,6 +89,25 @@ __device__ inline void surface_vel(const double* __restrict__ sol, int s, int64_
 }
 
 __device__ inline int wrap3(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Fraction q in (0, 1] of the link from node (x, y, z) along e into sphere
+// slot s at step t: the nearer root of |P + q e| = r with P the node's
+// minimum-image offset from the centre (half-coefficient form), clamped.
+__device__ inline double sphere_q3(const double* __restrict__ sol, int s, int64_t t, int x, int y, int z, int ex,
+                                   int ey, int ez, const Args& a) {
+    double X[3];
+    centre3(sol, s, t, X);
+    const double px = min_image3((double)x - X[0], a.nx), py = min_image3((double)y - X[1], a.ny),
+                 pz = min_image3((double)z - X[2], a.nz);
+    const double r = sol[kSolidRow * s + 3];
+    const double e2 = (double)(ex * ex + ey * ey + ez * ez);
+    const double pe = px * ex + py * ey + pz * ez;
+    const double c = px * px + py * py + pz * pz - r * r;
+    const double disc = pe * pe - e2 * c;
+    double q = (-pe - sqrt(disc > 0.0 ? disc : 0.0)) / e2;
+    if (q <= 0.0) q = 1.0e-12;
+    return q > 1.0 ? 1.0 : q;
+}
 
 // BGK + Guo on deviations, in FP64: rho = rho0 + sum d, momentum sum e d
 // (the weights' first moment vanishes), u = (j + rho g/2)/rho.
@@ -199,11 +219,24 @@ __device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ pa
             if (p.own[((int64_t)zb * a.ny + yb) * a.pitch + xb] != s) continue;
         }
         const double ex = kE[i][0], ey = kE[i][1], ez = kE[i][2], w = w3(i);
+        // surface point x_f + q e_i (q = 1/2 unless interpolated on a sphere)
+        const double q = (a.ibb && s > 0) ? sphere_q3(p.sol, s, t, x, y, z, kE[i][0], kE[i][1], kE[i][2], a) : 0.5;
         double v[3], r[3];
-        surface_vel(p.sol, s, t, x + 0.5 * ex, y + 0.5 * ey, z + 0.5 * ez, a, v, r);
+        surface_vel(p.sol, s, t, x + q * ex, y + q * ey, z + q * ez, a, v, r);
         const double av =
             w * a.rho0 + (double)Sto<T>::ld(f[((int64_t)line * kQ + i) * a.pitch + x]);
-        const double bv = av - 6.0 * w * a.rho0 * (ex * v[0] + ey * v[1] + ez * v[2]);
+        const double m = 6.0 * w * a.rho0 * (ex * v[0] + ey * v[1] + ez * v[2]);
+        double bv = av - m;
+        if (q < 0.5) {  // the returning population of the interpolated rule
+            const int xq = wrap3(x - kE[i][0], a.nx), yq = wrap3(y - kE[i][1], a.ny), zq = wrap3(z - kE[i][2], a.nz);
+            const int64_t lq = (int64_t)zq * a.ny + yq;
+            if (p.own[lq * a.pitch + xq] == 0)
+                bv = 2.0 * q * av + (1.0 - 2.0 * q) * (w * a.rho0 + (double)Sto<T>::ld(f[(lq * kQ + i) * a.pitch + xq])) - m;
+        } else if (q > 0.5) {
+            const double fo = w * a.rho0 + (double)Sto<T>::ld(f[((int64_t)line * kQ + opp3(i)) * a.pitch + x]);
+            const double h = 0.5 / q;
+            bv = h * (av - m) + (1.0 - h) * fo;
+        }
         const double e[3] = {ex, ey, ez};
         double Fc[3], Fg[3];
 #pragma unroll
@@ -272,7 +305,7 @@ __device__ inline const T* at3(const T* base, uint32_t idx) {
     return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, bool IBB>
 __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a, int64_t t) {
     const T* fin = (const T*)p.fin;
     T* fout = (T*)p.fout;
@@ -306,6 +339,22 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
         for (int i = 1; i < kQ; ++i) {
             if (src[i] == 0) continue;
             const int s = src[i] == kDuct ? 0 : (int)src[i];
+            if constexpr (IBB) {
+                if (s > 0) {
+                    // interpolated bounce-back: surface point x - q e_i; the
+                    // node behind, x + e_i, is the source of o = opp(i), so
+                    // d[o] still holds its value when it is fluid
+                    const double q = sphere_q3(p.sol, s, t, x, y, z, -kE[i][0], -kE[i][1], -kE[i][2], a);
+                    double v[3], r[3];
+                    surface_vel(p.sol, s, t, x - q * kE[i][0], y - q * kE[i][1], z - q * kE[i][2], a, v, r);
+                    const double m = 6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
+                    const int o = opp3(i);
+                    const double fo = (double)Sto<T>::ld(*at3(fin + (line * kQ + o) * a.pitch, ux));
+                    const double fi = (double)Sto<T>::ld(*at3(fin + (line * kQ + i) * a.pitch, ux));
+                    d[i] = lbm::ibb_value<double>(q, fo, fi, d[o], src[o] == 0, m);
+                    continue;
+                }
+            }
             double v[3], r[3];
             surface_vel(p.sol, s, t, x - 0.5 * kE[i][0], y - 0.5 * kE[i][1], z - 0.5 * kE[i][2], a, v, r);
             d[i] = (double)Sto<T>::ld(*at3(fin + (line * kQ + opp3(i)) * a.pitch, ux)) +
@@ -327,7 +376,7 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
 // Workgroups [0, nchunks) force chunks, the next (ns + 1) * 12 the previous
 // step's totals (the first also advances the step counter), update
 // workgroups from n_lead (a multiple of 8) on.
-template <typename T, bool NT>
+template <typename T, bool NT, bool IBB>
 __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead, Args a) {
     __shared__ double red[kBlock / 64][12];
     const int b = (int)blockIdx.x;
@@ -350,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
     const uint32_t line = gw / wpr;
     const int x = (int)((gw - line * wpr) << 6) + (int)(threadIdx.x & 63);
     if (line >= (uint32_t)(a.ny * a.nz) || x >= a.nx) return;
-    update3<T, NT>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a, p.tctr[parity]);
+    update3<T, NT, IBB>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a, p.tctr[parity]);
 }
 
 // Owner of node (x, y, z) at step t: the duct, then the spheres (minimum
@@ -398,9 +447,22 @@ __device__ inline double pull3(const T* __restrict__ fin, const uint8_t* __restr
     const int64_t ls = (int64_t)zs * a.ny + ys;
     const uint8_t o = own_t[ls * a.pitch + xs];
     if (o == 0) return (double)Sto<T>::ld(fin[(ls * kQ + j) * a.pitch + xs]);
+    const int64_t line = (int64_t)z * a.ny + y;
+    if (a.ibb && o != kDuct) {
+        const double q = sphere_q3(sol, (int)o, t, x, y, z, -kE[j][0], -kE[j][1], -kE[j][2], a);
+        double v[3], r[3];
+        surface_vel(sol, (int)o, t, x - q * kE[j][0], y - q * kE[j][1], z - q * kE[j][2], a, v, r);
+        const double m = 6.0 * w3(j) * a.rho0 * (kE[j][0] * v[0] + kE[j][1] * v[1] + kE[j][2] * v[2]);
+        const double fo = (double)Sto<T>::ld(fin[(line * kQ + opp3(j)) * a.pitch + x]);
+        const double fi = (double)Sto<T>::ld(fin[(line * kQ + j) * a.pitch + x]);
+        const int xb = wrap3(x + kE[j][0], a.nx), yb = wrap3(y + kE[j][1], a.ny), zb = wrap3(z + kE[j][2], a.nz);
+        const int64_t lb = (int64_t)zb * a.ny + yb;
+        const bool behind = own_t[lb * a.pitch + xb] == 0;
+        const double fb = behind ? (double)Sto<T>::ld(fin[(lb * kQ + opp3(j)) * a.pitch + xb]) : 0.0;
+        return lbm::ibb_value<double>(q, fo, fi, fb, behind, m);
+    }
     double v[3], r[3];
     surface_vel(sol, o == kDuct ? 0 : (int)o, t, x - 0.5 * kE[j][0], y - 0.5 * kE[j][1], z - 0.5 * kE[j][2], a, v, r);
-    const int64_t line = (int64_t)z * a.ny + y;
     return (double)Sto<T>::ld(fin[(line * kQ + opp3(j)) * a.pitch + x]) +
            6.0 * w3(j) * a.rho0 * (kE[j][0] * v[0] + kE[j][1] * v[1] + kE[j][2] * v[2]);
 }

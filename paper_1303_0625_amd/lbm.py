@@ -153,6 +153,7 @@ _SIG = {
     "lbm3d_body_state": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_double)]),
     "lbm3d_set_force_average": (_I32, [_VP, _I32]),
     "lbm3d_set_pressure": (_I32, [_VP, ctypes.c_double, ctypes.c_double]),
+    "lbm3d_set_boundary": (_I32, [_VP, _I32]),
     "lbm3d_status_check": (_I32, [_VP]),
     "lbm3d_profile": (_I32, [_VP, _I32]),
     "lbm3d_profile_read": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
@@ -1054,6 +1055,11 @@ class Lattice3D:
     def set_gravity(self, G, scheme: int = 1) -> None:
         g = (ctypes.c_double * 3)(*[float(v) for v in G])
         _check3(load_library().lbm3d_set_gravity(self.ctx, g, int(scheme)), self.ctx)
+
+    def set_boundary(self, interpolated: bool = True) -> None:
+        """Interpolated (True) or half-way (False) bounce-back on sphere links."""
+        _check3(load_library().lbm3d_set_boundary(self.ctx, LBM_INTERPOLATED if interpolated else LBM_HALFWAY),
+                self.ctx)
 
     def set_pressure(self, rho_in: float, rho_out: float) -> None:
         """Pressure inlet (x = 0) and outlet (x = nx - 1) densities."""
