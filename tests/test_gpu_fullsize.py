@@ -169,8 +169,9 @@ def test_moving_cylinders_fullsize_ibb(oracle_mod, pkg):
 
 def test_tube_3d_fullsize(oracle_mod, pkg):
     """The benchmark's three-dimensional workload (the paper's tube, 150 x 42
-    x 42, sphere r = 5.9 at r*/R = 0.21, pressure inlet and outlet 3 x
-    1.825e-5 apart in density): FP64 GPU against the oracle (fields on the
+    x 42, sphere r = 5.9 at r*/R = 0.21 with interpolated bounce-back,
+    pressure inlet and outlet 3 x 1.825e-5 apart in density): FP64 GPU
+    against the oracle (fields on the
     interior planes, forces) and the FP32 launch configuration the benchmark
     times against the oracle's drag, over 100 steps."""
     n, R, r = 42, 19.34, 5.9
@@ -181,10 +182,12 @@ def test_tube_3d_fullsize(oracle_mod, pkg):
     _say(f"tube 150x42x42 f64/f32 vs oracle, {steps} steps")
     o = oracle_mod.OracleSim3D(c["nx"], n, n, c["tau"], duct=1, R=R, spheres=c["spheres"])
     o.set_pressure(rin, rout)
+    o.set_ibb(True)
     o.step(steps)
     oh = np.concatenate([o.force_history(0), o.force_history(1)], axis=2)
     lat = pkg.Lattice3D(c, dtype="f64", history_steps=steps)
     lat.set_pressure(rin, rout)
+    lat.set_boundary(True)
     lat.step(steps)
     rho, u, own = (a.cpu().numpy() for a in lat.fields())
     orho, ou, oown = o.fields()
@@ -215,6 +218,7 @@ def test_tube_3d_fullsize(oracle_mod, pkg):
     del lat
     lat = pkg.Lattice3D(c, dtype="f32", history_steps=steps)
     lat.set_pressure(rin, rout)
+    lat.set_boundary(True)
     lat.step(steps)
     h = lat.force_history().cpu().numpy()
     for col in (0, 6):
