@@ -326,6 +326,8 @@ def _load3():
     lib.orc3_set_ibb.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc3_link_q.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.orc3_link_q.restype = ctypes.c_double
+    lib.orc3_tube_q.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.orc3_tube_q.restype = ctypes.c_double
     lib.orc3_set_pressure.restype = ctypes.c_int
     lib.orc3_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     lib.orc3_body_state.restype = ctypes.c_int
@@ -420,6 +422,9 @@ class OracleSim3D:
 
     def link_q(self, sphere: int, x: int, y: int, z: int, i: int) -> float:
         return self._lib.orc3_link_q(self._h, int(sphere), int(x), int(y), int(z), int(i))
+
+    def tube_q(self, y: int, z: int, i: int) -> float:
+        return self._lib.orc3_tube_q(self._h, int(y), int(z), int(i))
 
     def set_pressure(self, rho_in: float, rho_out: float) -> None:
         """Pressure inlet (x = 0) and outlet (x = nx - 1) densities."""

@@ -185,6 +185,33 @@ static double sphere_q(const orc3_sim* s, int k, long t, int x, int y, int z, co
     return q > 1.0 ? 1.0 : q;
 }
 
+/* Fraction q in (0, 1] of the link from fluid node (x, y, z) along e to the
+ * tube wall: the larger root of |P + q e|^2 = R^2 in the (y, z) plane, P the
+ * node's offset from the axis (the node lies inside, its neighbour outside). */
+static double tube_q(const orc3_sim* s, int y, int z, const int e[3]) {
+    const double py = (double)y - 0.5 * (s->ny - 1), pz = (double)z - 0.5 * (s->nz - 1);
+    const double a2 = (double)(e[1] * e[1] + e[2] * e[2]);
+    const double b2 = 2.0 * (py * e[1] + pz * e[2]);
+    const double c2 = py * py + pz * pz - s->R * s->R;
+    double disc = b2 * b2 - 4.0 * a2 * c2;
+    if (disc < 0.0) disc = 0.0;
+    double q = (-b2 + sqrt(disc)) / (2.0 * a2);
+    if (q <= 0.0) q = 1e-12;
+    return q > 1.0 ? 1.0 : q;
+}
+
+/* Link fraction of a fluid-solid link (half-way for the planes). */
+static double link_q3(const orc3_sim* s, int o, long t, int x, int y, int z, const int e[3]) {
+    if (!s->ibb) return 0.5;
+    if (o != 255) return sphere_q(s, o - 1, t, x, y, z, e);
+    return s->duct == ORC3_TUBE ? tube_q(s, y, z, e) : 0.5;
+}
+
+double orc3_tube_q(const orc3_sim* s, int y, int z, int i) {
+    if (i < 1 || i > 18 || (E[i][1] == 0 && E[i][2] == 0)) return -1.0;
+    return tube_q(s, y, z, E[i]);
+}
+
 double orc3_link_q(const orc3_sim* s, int sphere, int x, int y, int z, int i) {
     if (sphere < 1 || sphere > s->ns || i < 1 || i > 18) return -1.0;
     return sphere_q(s, sphere - 1, s->t, x, y, z, E[i]);
@@ -388,7 +415,7 @@ static void one_step(orc3_sim* s) {
                     if (o == 0) continue;
                     /* surface point x_f + q e_i: q = 1/2 (half-way), or the link
                      * fraction into a sphere under interpolated bounce-back */
-                    const double q = (s->ibb && o != 255) ? sphere_q(s, o - 1, s->t, x, y, z, E[i]) : 0.5;
+                    const double q = link_q3(s, o, s->t, x, y, z, E[i]);
                     double v[3], r[3];
                     surface_velocity(s, o, s->t, x + q * E[i][0], y + q * E[i][1], z + q * E[i][2], v, r);
                     double a = s->ft[pidx(s, i, x, y, z)];
@@ -429,7 +456,7 @@ static void one_step(orc3_sim* s) {
                         val = s->ft[pidx(s, i, xs, ys, zs)];
                     } else {
                         int me[3] = {-E[i][0], -E[i][1], -E[i][2]};
-                        const double q = (s->ibb && o != 255) ? sphere_q(s, o - 1, s->t, x, y, z, me) : 0.5;
+                        const double q = link_q3(s, o, s->t, x, y, z, me);
                         double v[3], r[3];
                         surface_velocity(s, o, s->t, x - q * E[i][0], y - q * E[i][1], z - q * E[i][2], v, r);
                         const double m = 6.0 * weight(i) * s->rho0 * (E[i][0] * v[0] + E[i][1] * v[1] + E[i][2] * v[2]);

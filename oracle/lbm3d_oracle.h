@@ -49,11 +49,13 @@ int orc3_set_free(orc3_sim* s, int sphere, double rho_s, const double omega0[3])
  * and t (step 0: its own), the two-step average of particle suspensions. */
 void orc3_set_force_average(orc3_sim* s, int on);
 /* Interpolated bounce-back (linear in the link fraction q, as in two
- * dimensions) on sphere links; duct links stay half-way. */
+ * dimensions) on sphere and tube links; the planes stay half-way. */
 void orc3_set_ibb(orc3_sim* s, int on);
 /* q of the link from node (x, y, z) along direction i into sphere `sphere`
  * at the current step. */
 double orc3_link_q(const orc3_sim* s, int sphere, int x, int y, int z, int i);
+/* q of the link from node (., y, z) along direction i to the tube wall. */
+double orc3_tube_q(const orc3_sim* s, int y, int z, int i);
 /* Pressure inlet x = 0 (density rho_in) and outlet x = nx - 1 (rho_out) by
  * non-equilibrium extrapolation of the post-collision populations from the
  * neighbouring plane; no moving spheres; before the first step. */

@@ -480,3 +480,61 @@ def test_ibb_momentum_balance_3d(oracle_mod):
         f = s.get_f()
         expect = g * rho.sum() - s.force(0, oracle_mod.CME)[:3] - s.force(1, oracle_mod.CME)[:3]
         assert np.abs(_momentum(f, e) - P0 - expect).max() <= 1e-14 * M0
+
+
+def test_ibb_tube_link_fraction_3d(oracle_mod):
+    """q of every link from the fluid to the tube wall is where the segment
+    leaves the cylinder, found by bisection."""
+    ny = nz = 21
+    R = 8.3
+    s = oracle_mod.OracleSim3D(6, ny, nz, 0.7, duct=oracle_mod.TUBE3, R=R)
+    _, _, own = s.fields()
+    e, _ = _lookup(oracle_mod)
+    c = (ny - 1) / 2
+    count = 0
+    for z in range(nz):
+        for y in range(ny):
+            if own[z, y, 0]:
+                continue
+            for i in range(1, 19):
+                if e[i, 1] == 0 and e[i, 2] == 0:
+                    continue
+                yb, zb = y + e[i, 1], z + e[i, 2]
+                if own[zb, yb, 0] != 255:
+                    continue
+                lo, hi = 0.0, 1.0
+                for _ in range(60):
+                    mid = 0.5 * (lo + hi)
+                    py, pz = y + mid * e[i, 1] - c, z + mid * e[i, 2] - c
+                    if py * py + pz * pz > R * R:
+                        hi = mid
+                    else:
+                        lo = mid
+                assert abs(s.tube_q(y, z, i) - hi) <= 1e-12
+                count += 1
+    assert count > 50
+
+
+def test_ibb_tube_momentum_balance_and_comoving_3d(oracle_mod):
+    """Interpolated bounce-back on tube and sphere: the momentum balance holds
+    every step, and a tube at rest with fluid at rest stays at rest."""
+    e, _ = _lookup(oracle_mod)
+    g = np.array([3e-5, -1e-5, 2e-5])
+    sp = dict(cx=8.4, cy=7.2, cz=7.9, r=3.1, v=(0.02, 0.01, -0.005), omega=(0.003, -0.002, 0.004))
+    s = oracle_mod.OracleSim3D(18, 16, 16, 0.7, g=tuple(g), duct=oracle_mod.TUBE3, R=6.8, spheres=[sp])
+    s.set_ibb(True)
+    s.step(10)
+    f = s.get_f()
+    M0 = f.sum()
+    for _ in range(8):
+        P0 = _momentum(f, e)
+        rho, _, _ = s.fields()
+        s.step(1)
+        f = s.get_f()
+        expect = g * rho.sum() - s.force(0, oracle_mod.CME)[:3] - s.force(1, oracle_mod.CME)[:3]
+        assert np.abs(_momentum(f, e) - P0 - expect).max() <= 1e-14 * M0
+    r = oracle_mod.OracleSim3D(10, 17, 17, 0.7, duct=oracle_mod.TUBE3, R=7.3)
+    r.set_ibb(True)
+    r.step(20)
+    _, u, own = r.fields()
+    assert np.abs(u[:, own == 0]).max() <= 1e-15
