@@ -634,10 +634,11 @@ lbm_status lbm3d_set_free(lbm3d_ctx* ctx, int32_t sphere, double rho_s, const do
  * the force scheme (LBM_CME / LBM_GME) that drives them. */
 lbm_status lbm3d_set_gravity(lbm3d_ctx* ctx, const double G[3], int32_t scheme);
 
-/* Bounce-back rule on sphere links (LBM_HALFWAY default, or
- * LBM_INTERPOLATED: the rule of lbm_set_boundary, with q the nearer root of
- * the ray-sphere intersection; duct links stay half-way).  Takes effect from
- * the next step.  LBM_EINVAL for another rule. */
+/* Bounce-back rule on curved walls (LBM_HALFWAY default, or
+ * LBM_INTERPOLATED: the rule of lbm_set_boundary on sphere and tube links,
+ * q the nearer root of the ray-sphere intersection or the ray's exit from
+ * the tube's circle; the planes stay half-way).  Takes effect from the next
+ * step.  LBM_EINVAL for another rule. */
 lbm_status lbm3d_set_boundary(lbm3d_ctx* ctx, int32_t rule);
 
 /* Pressure-driven duct (Sec. IV.D): the planes x = 0 and x = nx - 1 become a

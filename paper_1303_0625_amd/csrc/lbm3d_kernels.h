@@ -90,6 +90,20 @@ __device__ inline void surface_vel(const double* __restrict__ sol, int s, int64_
 
 __device__ inline int wrap3(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
+// Fraction q in (0, 1] of the link from fluid node (., y, z) along e to the
+// tube wall: the larger root of |P + q e| = R in the (y, z) plane (the node
+// inside, its neighbour outside), P the node's offset from the axis.
+__device__ inline double tube_q3(int y, int z, int ey, int ez, const Args& a) {
+    const double py = (double)y - 0.5 * (a.ny - 1), pz = (double)z - 0.5 * (a.nz - 1);
+    const double e2 = (double)(ey * ey + ez * ez);
+    const double pe = py * ey + pz * ez;
+    const double c = py * py + pz * pz - a.R * a.R;
+    const double disc = pe * pe - e2 * c;
+    double q = (-pe + sqrt(disc > 0.0 ? disc : 0.0)) / e2;
+    if (q <= 0.0) q = 1.0e-12;
+    return q > 1.0 ? 1.0 : q;
+}
+
 // Fraction q in (0, 1] of the link from node (x, y, z) along e into sphere
 // slot s at step t: the nearer root of |P + q e| = r with P the node's
 // minimum-image offset from the centre (half-coefficient form), clamped.
@@ -220,7 +234,9 @@ __device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ pa
         }
         const double ex = kE[i][0], ey = kE[i][1], ez = kE[i][2], w = w3(i);
         // surface point x_f + q e_i (q = 1/2 unless interpolated on a sphere)
-        const double q = (a.ibb && s > 0) ? sphere_q3(p.sol, s, t, x, y, z, kE[i][0], kE[i][1], kE[i][2], a) : 0.5;
+        double q = 0.5;
+        if (a.ibb && s > 0) q = sphere_q3(p.sol, s, t, x, y, z, kE[i][0], kE[i][1], kE[i][2], a);
+        if (a.ibb && s == 0 && a.duct == 1) q = tube_q3(y, z, kE[i][1], kE[i][2], a);
         double v[3], r[3];
         surface_vel(p.sol, s, t, x + q * ex, y + q * ey, z + q * ez, a, v, r);
         const double av =
@@ -340,11 +356,12 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
             if (src[i] == 0) continue;
             const int s = src[i] == kDuct ? 0 : (int)src[i];
             if constexpr (IBB) {
-                if (s > 0) {
-                    // interpolated bounce-back: surface point x - q e_i; the
-                    // node behind, x + e_i, is the source of o = opp(i), so
-                    // d[o] still holds its value when it is fluid
-                    const double q = sphere_q3(p.sol, s, t, x, y, z, -kE[i][0], -kE[i][1], -kE[i][2], a);
+                if (s > 0 || a.duct == 1) {
+                    // interpolated bounce-back (spheres and tube): surface
+                    // point x - q e_i; the node behind, x + e_i, is the source
+                    // of o = opp(i), so d[o] still holds its value when fluid
+                    const double q = s > 0 ? sphere_q3(p.sol, s, t, x, y, z, -kE[i][0], -kE[i][1], -kE[i][2], a)
+                                           : tube_q3(y, z, -kE[i][1], -kE[i][2], a);
                     double v[3], r[3];
                     surface_vel(p.sol, s, t, x - q * kE[i][0], y - q * kE[i][1], z - q * kE[i][2], a, v, r);
                     const double m = 6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
@@ -448,10 +465,12 @@ __device__ inline double pull3(const T* __restrict__ fin, const uint8_t* __restr
     const uint8_t o = own_t[ls * a.pitch + xs];
     if (o == 0) return (double)Sto<T>::ld(fin[(ls * kQ + j) * a.pitch + xs]);
     const int64_t line = (int64_t)z * a.ny + y;
-    if (a.ibb && o != kDuct) {
-        const double q = sphere_q3(sol, (int)o, t, x, y, z, -kE[j][0], -kE[j][1], -kE[j][2], a);
+    if (a.ibb && (o != kDuct || a.duct == 1)) {
+        const int so = o == kDuct ? 0 : (int)o;
+        const double q = so > 0 ? sphere_q3(sol, so, t, x, y, z, -kE[j][0], -kE[j][1], -kE[j][2], a)
+                                : tube_q3(y, z, -kE[j][1], -kE[j][2], a);
         double v[3], r[3];
-        surface_vel(sol, (int)o, t, x - q * kE[j][0], y - q * kE[j][1], z - q * kE[j][2], a, v, r);
+        surface_vel(sol, so, t, x - q * kE[j][0], y - q * kE[j][1], z - q * kE[j][2], a, v, r);
         const double m = 6.0 * w3(j) * a.rho0 * (kE[j][0] * v[0] + kE[j][1] * v[1] + kE[j][2] * v[2]);
         const double fo = (double)Sto<T>::ld(fin[(line * kQ + opp3(j)) * a.pitch + x]);
         const double fi = (double)Sto<T>::ld(fin[(line * kQ + j) * a.pitch + x]);
