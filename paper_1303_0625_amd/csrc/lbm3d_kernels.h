@@ -182,7 +182,9 @@ struct Ptrs {
 // Per link (x_f, i) of solid s: a = f~_i(x_f), b = a - 6 w_i rho0 (e_i . v)
 // with v at the link midpoint; CME F = e_i (a + b), GME F = (e_i - v) a +
 // (e_i + v) b; torque r x F about the sphere's centre.
-template <typename T>
+// IBB: interpolated bounce-back may be on (a.ibb); without it the link code
+// (and the kernel's registers) stay those of half-way bounce-back.
+template <typename T, bool IBB>
 __device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ partial, const Args& a,
                                    double (*red)[12], int64_t t) {
     const T* f = (const T*)p.fin;
@@ -235,20 +237,22 @@ __device__ inline void force_role3(int c, const Ptrs& p, double* __restrict__ pa
         const double ex = kE[i][0], ey = kE[i][1], ez = kE[i][2], w = w3(i);
         // surface point x_f + q e_i (q = 1/2 unless interpolated on a sphere)
         double q = 0.5;
-        if (a.ibb && s > 0) q = sphere_q3(p.sol, s, t, x, y, z, kE[i][0], kE[i][1], kE[i][2], a);
-        if (a.ibb && s == 0 && a.duct == 1) q = tube_q3(y, z, kE[i][1], kE[i][2], a);
+        if constexpr (IBB) {
+            if (a.ibb && s > 0) q = sphere_q3(p.sol, s, t, x, y, z, kE[i][0], kE[i][1], kE[i][2], a);
+            if (a.ibb && s == 0 && a.duct == 1) q = tube_q3(y, z, kE[i][1], kE[i][2], a);
+        }
         double v[3], r[3];
         surface_vel(p.sol, s, t, x + q * ex, y + q * ey, z + q * ez, a, v, r);
         const double av =
             w * a.rho0 + (double)Sto<T>::ld(f[((int64_t)line * kQ + i) * a.pitch + x]);
         const double m = 6.0 * w * a.rho0 * (ex * v[0] + ey * v[1] + ez * v[2]);
         double bv = av - m;
-        if (q < 0.5) {  // the returning population of the interpolated rule
+        if (IBB && q < 0.5) {  // the returning population of the interpolated rule
             const int xq = wrap3(x - kE[i][0], a.nx), yq = wrap3(y - kE[i][1], a.ny), zq = wrap3(z - kE[i][2], a.nz);
             const int64_t lq = (int64_t)zq * a.ny + yq;
             if (p.own[lq * a.pitch + xq] == 0)
                 bv = 2.0 * q * av + (1.0 - 2.0 * q) * (w * a.rho0 + (double)Sto<T>::ld(f[(lq * kQ + i) * a.pitch + xq])) - m;
-        } else if (q > 0.5) {
+        } else if (IBB && q > 0.5) {
             const double fo = w * a.rho0 + (double)Sto<T>::ld(f[((int64_t)line * kQ + opp3(i)) * a.pitch + x]);
             const double h = 0.5 / q;
             bv = h * (av - m) + (1.0 - h) * fo;
@@ -400,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
     if (b < n_lead) {
         const int64_t t = p.tctr[parity];
         if (b < a.nchunks) {
-            force_role3<T>(b, p, p.partial + (size_t)(t & 1) * a.nchunks * 12, a, red, t);
+            force_role3<T, IBB>(b, p, p.partial + (size_t)(t & 1) * a.nchunks * 12, a, red, t);
         } else if (b < a.nchunks + (a.ns + 1) * 12) {
             const int pair = b - a.nchunks;
             if (t >= 1)
