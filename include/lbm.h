@@ -529,7 +529,7 @@ const char* lbm_nn_last_error(const lbm_nn* nn);
 
 /* ------------------------------------------------------------------------
  * Three dimensions (Sec. IV.D): the D3Q19 step with the same boundary and
- * force evaluation, fixed geometry.
+ * force evaluation, for fixed, translating and free spheres in a duct.
  *
  * Velocity set: rest, the six axis directions and the twelve edge diagonals,
  * weights 1/3, 1/18, 1/36.  Every axis is periodic.  The duct is a circular
@@ -547,9 +547,11 @@ const char* lbm_nn_last_error(const lbm_nn* nn);
  * of 2 ceil(r) + 5 nodes must fit the lattice.  One step: the CME (Eq. 4) and
  * GME (Eq. 5) forces of
  * every fluid-solid link from the post-collision populations with the torque
- * (Eq. 7) about each sphere's centre at the link midpoint, summed per solid
- * in a fixed order (Eq. 6); pull streaming with half-way bounce-back plus
- * 6 w_i rho0 (e_i . v) (v at the link midpoint); BGK collision (Eq. 2) with
+ * (Eq. 7) about each sphere's centre at the link's surface point (the
+ * midpoint, or x_f + q e_i under lbm3d_set_boundary), summed per solid in a
+ * fixed order (Eq. 6); pull streaming with half-way (or interpolated)
+ * bounce-back plus 6 w_i rho0 (e_i . v) (v at the surface point); BGK
+ * collision (Eq. 2) with
  * the Eq. 8 equilibrium and Guo forcing for the body force g.  Storage:
  * LBM_F64 or LBM_F32 deviations f_i - w_i rho0, arithmetic in FP64.  The
  * caller owns the device workspace and the stream; nothing is allocated on

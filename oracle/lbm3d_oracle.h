@@ -16,8 +16,9 @@ typedef struct orc3_sim orc3_sim;
  * rho0, body force (acceleration) g, initial velocity u0 (f = f_eq(rho0, u0)).
  * duct: ORC3_TUBE (nodes with (y - (ny-1)/2)^2 + (z - (nz-1)/2)^2 > R^2 are
  * solid), ORC3_PLANES (z = 0 and z = nz - 1 solid) or ORC3_OPEN.  spheres:
- * ns records {X, Y, Z, r, Vx, Vy, Vz, Omx, Omy, Omz} (fixed geometry, rigid
- * surface motion).  NULL when a sphere touches the duct or another sphere. */
+ * ns records {X, Y, Z, r, Vx, Vy, Vz, Omx, Omy, Omz} (rigid surface motion;
+ * fixed unless orc3_set_moving / orc3_set_free).  NULL when a sphere touches
+ * the duct or another sphere. */
 orc3_sim* orc3_create(int nx, int ny, int nz, double tau, double rho0, const double g[3], const double u0[3],
                       int duct, double R, int ns, const double* spheres);
 void orc3_destroy(orc3_sim* s);

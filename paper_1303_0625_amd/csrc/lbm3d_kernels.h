@@ -1,9 +1,9 @@
 // lbm3d_kernels.h -- HIP kernels of the three-dimensional (D3Q19) momentum-
-// exchange step, Sec. IV.D: fixed geometry (a duct of solid nodes and
-// spheres whose surfaces move rigidly), half-way bounce-back with the
-// moving-boundary term, BGK collision with Guo forcing, and per-link CME
-// (Eq. 4) / GME (Eq. 5) forces with torque about each sphere's centre
-// (Eqs. 6-7).
+// exchange step, Sec. IV.D: a duct of solid nodes and spheres whose surfaces
+// move rigidly (fixed, translating with newborn refill, or free), half-way
+// or interpolated bounce-back with the moving-boundary term, BGK collision
+// with Guo forcing, per-link CME (Eq. 4) / GME (Eq. 5) forces with torque
+// about each sphere's centre (Eqs. 6-7), and pressure inlet/outlet planes.
 //
 // State: post-collision deviations d~_i = f~_i - w_i rho0 of every fluid
 // node, layout [z][y][19][pitch] (the nineteen population rows of one (y, z)
