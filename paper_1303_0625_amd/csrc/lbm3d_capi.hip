@@ -263,10 +263,20 @@ Args args3(const lbm3d_ctx* c) {
     a.box = c->L.box;
     a.refill = c->g.refill;
     a.ibb = c->ibb;
+    a.rho_in = c->rho_in;
+    a.rho_out = c->rho_out;
     return a;
 }
 
 int pitch_for(int nx) { return (nx + 63) / 64 * 64; }
+
+using StepKernel = void (*)(Ptrs, int, int, Args);
+
+template <typename T, bool NT>
+StepKernel step_kernel(bool ibb, bool pressure) {
+    if (ibb) return pressure ? k3_step<T, NT, true, true> : k3_step<T, NT, true, false>;
+    return pressure ? k3_step<T, NT, false, true> : k3_step<T, NT, false, false>;
+}
 
 }  // namespace
 
@@ -485,23 +495,12 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
         const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
         if (timed) HIPCHK3(c, hipEventRecord(c->ev[c->ev_used], c->stream));
         {
-            using K = decltype(&k3_step<double, true, true>);
-            void (*kern)(Ptrs, int, int, Args) = nullptr;
-            if (c->g.dtype == LBM_F64)
-                kern = c->ibb ? (nt ? (K)k3_step<double, true, true> : (K)k3_step<double, false, true>)
-                              : (nt ? (K)k3_step<double, true, false> : (K)k3_step<double, false, false>);
-            else
-                kern = c->ibb ? (nt ? (K)k3_step<float, true, true> : (K)k3_step<float, false, true>)
-                              : (nt ? (K)k3_step<float, true, false> : (K)k3_step<float, false, false>);
+            // the pressure planes, when set, are part of the step launch
+            const bool ibb = c->ibb != 0, pr = c->pressure != 0;
+            const StepKernel kern = c->g.dtype == LBM_F64
+                                        ? (nt ? step_kernel<double, true>(ibb, pr) : step_kernel<double, false>(ibb, pr))
+                                        : (nt ? step_kernel<float, true>(ibb, pr) : step_kernel<float, false>(ibb, pr));
             kern<<<grid, kBlock, 0, c->stream>>>(p, par, n_lead, a);
-        }
-        if (c->pressure) {
-            const unsigned npb = (unsigned)((2 * (int64_t)c->g.ny * c->g.nz + kBlock - 1) / kBlock);
-            const uint8_t* own_t = at<uint8_t>(c, c->L.own[par]);
-            if (c->g.dtype == LBM_F64)
-                k3_pressure<double><<<npb, kBlock, 0, c->stream>>>((double*)p.fout, own_t, a, c->rho_in, c->rho_out);
-            else
-                k3_pressure<float><<<npb, kBlock, 0, c->stream>>>((float*)p.fout, own_t, a, c->rho_in, c->rho_out);
         }
         double* sol_n = at<double>(c, c->L.sol[par ^ 1]);
         if (c->nfree > 0) {

@@ -49,6 +49,7 @@ struct Args {
     int box;          // edge of a moving sphere's scan box (nodes)
     int refill;       // 0 A1, 1 A2, 2 A3
     int ibb;          // interpolated bounce-back on sphere links
+    double rho_in, rho_out;  // pressure planes x = 0 and x = nx - 1
 };
 
 // Solid table row: X, r, V (3), Omega (3), moves, free; row 0 is the duct.
@@ -325,11 +326,25 @@ __device__ inline const T* at3(const T* base, uint32_t idx) {
     return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
 }
 
-template <typename T, bool NT, bool IBB>
-__device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a, int64_t t) {
+// PR: pressure planes.  A node of the plane x = 0 (x = nx - 1) whose inner
+// neighbour x = 1 (nx - 2) is fluid too computes that neighbour's update
+// itself and stores it moved to the plane's density by non-equilibrium
+// extrapolation (Guo, Zheng and Shi 2002), the boundary condition applied to
+// the post-collision state in the same launch.
+template <typename T, bool NT, bool IBB, bool PR>
+__device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& a, int64_t t) {
     const T* fin = (const T*)p.fin;
     T* fout = (T*)p.fout;
     const int64_t line = (int64_t)z * a.ny + y;
+    int x = xo;
+    bool plane = false;
+    if constexpr (PR) {
+        if (xo == 0 || xo == a.nx - 1) {
+            const int xf = xo == 0 ? 1 : a.nx - 2;
+            plane = *at3(p.own + line * a.pitch, (uint32_t)xo) == 0 && *at3(p.own + line * a.pitch, (uint32_t)xf) == 0;
+            if (plane) x = xf;
+        }
+    }
     const uint32_t ux = (uint32_t)x;
     const uint32_t uxm = (uint32_t)(x == 0 ? a.nx - 1 : x - 1), uxp = (uint32_t)(x == a.nx - 1 ? 0 : x + 1);
     const uint8_t self = *at3(p.own + line * a.pitch, ux);
@@ -383,9 +398,33 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
         }
     }
     collide3(d, a);
+    if constexpr (PR) {
+        if (plane) {
+            // the neighbour's stored post-collision state, moments and shift
+            double drho = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                d[i] = (double)Sto<T>::ld(Sto<T>::st(d[i]));
+                drho += d[i];
+                j[0] += kE[i][0] * d[i];
+                j[1] += kE[i][1] * d[i];
+                j[2] += kE[i][2] * d[i];
+            }
+            const double rho = a.rho0 + drho;
+            const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+            const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            const double dr = (xo == 0 ? a.rho_in : a.rho_out) - rho;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const double eu = kE[i][0] * u[0] + kE[i][1] * u[1] + kE[i][2] * u[2];
+                d[i] += w3(i) * dr * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+            }
+        }
+    }
+    const uint32_t uxo = (uint32_t)xo;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        T* ptr = const_cast<T*>(at3(fout + (line * kQ + i) * a.pitch, ux));
+        T* ptr = const_cast<T*>(at3(fout + (line * kQ + i) * a.pitch, uxo));
         const T val = Sto<T>::st(d[i]);
         if constexpr (NT)
             __builtin_nontemporal_store(val, ptr);
@@ -397,7 +436,7 @@ __device__ inline void update3(int x, int y, int z, const Ptrs& p, const Args& a
 // Workgroups [0, nchunks) force chunks, the next (ns + 1) * 12 the previous
 // step's totals (the first also advances the step counter), update
 // workgroups from n_lead (a multiple of 8) on.
-template <typename T, bool NT, bool IBB>
+template <typename T, bool NT, bool IBB, bool PR>
 __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead, Args a) {
     __shared__ double red[kBlock / 64][12];
     const int b = (int)blockIdx.x;
@@ -420,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
     const uint32_t line = gw / wpr;
     const int x = (int)((gw - line * wpr) << 6) + (int)(threadIdx.x & 63);
     if (line >= (uint32_t)(a.ny * a.nz) || x >= a.nx) return;
-    update3<T, NT, IBB>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a, p.tctr[parity]);
+    update3<T, NT, IBB, PR>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a, p.tctr[parity]);
 }
 
 // Owner of node (x, y, z) at step t: the duct, then the spheres (minimum
@@ -657,7 +696,8 @@ __global__ __launch_bounds__(kBlock) void k3_free(FreeArgs3 fa, int64_t t, Args 
 // takes f_eq(rho_b, u) + (f~ - f_eq(rho, u)) of its fluid neighbour (rho, u:
 // the neighbour's density and momentum over density), i.e. in deviations
 // d_b = d + w_i (rho_b - rho)(1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2).  One
-// thread per (line, side); the periodic pull into these planes is replaced.
+// thread per (line, side); applied to the initial state when the planes are
+// set (every step applies the same rule inside the update, PR).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k3_pressure(T* __restrict__ f, const uint8_t* __restrict__ own, Args a,
                                                       double rho_in, double rho_out) {
