@@ -346,6 +346,43 @@ def test_pressure_driven_tube_f64(oracle_mod, lbm_mod):
         m.set_pressure(1.0002, 0.9998)
 
 
+@pytest.mark.parametrize("ibb", [False, True])
+def test_pressure_planes_next_to_spheres_f64(oracle_mod, lbm_mod, ibb):
+    """Pressure planes with a sphere against each: on lines where the node
+    next to a plane is solid the plane node keeps its own update (the
+    extrapolation needs a fluid neighbour), elsewhere the plane takes its
+    neighbour's extrapolated state.  FP64 fields (interior and the plane nodes
+    with a solid neighbour) and per-step forces and torques, half-way and
+    interpolated bounce-back."""
+    c = dict(name="pressure_planes_spheres", nx=40, ny=24, nz=24, tau=0.7, duct=1, R=10.3,
+             spheres=[dict(cx=3.8, cy=13.1, cz=10.6, r=3.0), dict(cx=35.2, cy=10.4, cz=12.3, r=3.0)])
+    steps = 300
+    lat = lbm_mod.Lattice3D(c, dtype="f64", history_steps=steps)
+    osim = _oracle(oracle_mod, c)
+    if ibb:
+        lat.set_boundary(True)
+        osim.set_ibb(True)
+    lat.set_pressure(1.0003, 0.9997)
+    osim.set_pressure(1.0003, 0.9997)
+    _say(f"{c['name']} steps={steps} ibb={ibb}")
+    lat.step(steps)
+    osim.step(steps)
+    rho, u, own = (a.cpu().numpy() for a in lat.fields())
+    orho, ou, oown = osim.fields()
+    assert np.array_equal(own, oown)
+    kept_in = (own[:, :, 0] == 0) & (own[:, :, 1] != 0)
+    kept_out = (own[:, :, -1] == 0) & (own[:, :, -2] != 0)
+    assert kept_in.sum() >= 3 and kept_out.sum() >= 3  # the case this test is for
+    fl = own == 0
+    fl[:, :, 0] = kept_in
+    fl[:, :, -1] = kept_out
+    er = np.abs(rho - orho)[fl].max() / orho[fl].max()
+    eu = np.abs(u[:, fl] - ou[:, fl]).max() / np.abs(ou[:, fl]).max()
+    _say(f"field rel err rho={er:.3e} u={eu:.3e}")
+    assert er <= 1e-12 and eu <= 1e-11
+    assert force_err(lat, osim) <= 1e-10
+
+
 # --------------------------------------------------------------- interpolated bounce-back in 3D
 def test_ibb_tube_sphere_f64(oracle_mod, lbm_mod):
     """Interpolated bounce-back on a spinning, off-axis sphere in a tube flow
