@@ -24,7 +24,8 @@ FLAGS = [
 
 def source_hash(family: str = "lbm") -> str:
     """Short hash of one kernel family's sources (ties a measurement to that
-    kernel version): "lbm" = the lattice solver files, "nn" = the network."""
+    kernel version): "lbm" = the two-dimensional solver files, "lbm3d" = the
+    D3Q19 files, "nn" = the network."""
     import hashlib
 
     h = hashlib.sha256()

@@ -95,7 +95,7 @@ def main() -> None:
     t.add_argument("--workload", required=True)
     t.add_argument("--alg-bytes", type=float, required=True)
     t.add_argument("--commands", required=True)
-    t.add_argument("--family", default="lbm", help="kernel source family the hash covers (lbm or nn)")
+    t.add_argument("--family", default="lbm", help="kernel source family the hash covers (lbm, lbm3d or nn)")
     t.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
