@@ -472,7 +472,9 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
     const int n_lead = (c->L.nchunks + n_fin + 7) / 8 * 8;
     const int64_t lines = (int64_t)c->g.ny * c->g.nz;
     const int64_t waves = lines * (c->L.pitch / 64);
-    const unsigned grid = (unsigned)(n_lead + (waves + kBlock / 64 - 1) / (kBlock / 64));
+    const int64_t K = ((int64_t)c->g.ny * (c->L.pitch / 64) + kBlock / 64 - 1) / (kBlock / 64);
+    const int64_t n_upd = ((waves + kBlock / 64 - 1) / (kBlock / 64) + 8 * K - 1) / (8 * K) * (8 * K);
+    const unsigned grid = (unsigned)(n_lead + n_upd);
     const size_t es = c->g.dtype == LBM_F64 ? 8 : 4;
     const bool nt = 2 * (size_t)19 * lines * c->L.pitch * es > kStreamBytes3;
     Ptrs p{};

@@ -454,8 +454,14 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
         return;
     }
     const uint32_t wpr = (uint32_t)a.pitch >> 6;
-    const uint32_t gw = (uint32_t)(b - n_lead) * (kBlock / 64) +
-                        (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // XCD-aware order: workgroup b runs on XCD b % 8 (n_lead and the number
+    // of update workgroups are multiples of 8 K); the eight XCDs take eight
+    // consecutive z-planes (K workgroups each) at a time, so the lines y +- 1
+    // a node pulls from are in the XCD's own L2
+    const uint32_t K = ((uint32_t)a.ny * wpr + (kBlock / 64) - 1) / (kBlock / 64);
+    const uint32_t u = (uint32_t)(b - n_lead);
+    const uint32_t ub = (u / (8u * K)) * (8u * K) + (u & 7u) * K + (u >> 3) % K;
+    const uint32_t gw = ub * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t line = gw / wpr;
     const int x = (int)((gw - line * wpr) << 6) + (int)(threadIdx.x & 63);
     if (line >= (uint32_t)(a.ny * a.nz) || x >= a.nx) return;
