@@ -648,7 +648,8 @@ lbm_status lbm3d_set_boundary(lbm3d_ctx* ctx, int32_t rule);
  * extrapolation: after each step's collision their populations are
  * f_eq(rho_b, u) + (f~ - f_eq(rho, u)) of the neighbouring plane's node
  * (rho and u its density and momentum over density), replacing what the
- * periodic x axis streamed there.  Fixed spheres only (LBM_EINVAL with
+ * periodic x axis streamed there; a plane node whose neighbour is solid keeps
+ * its ordinary update.  Fixed spheres only (LBM_EINVAL with
  * moving ones); before the first step (LBM_ESTATE after).  Asynchronous. */
 lbm_status lbm3d_set_pressure(lbm3d_ctx* ctx, double rho_in, double rho_out);
 
