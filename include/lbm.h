@@ -594,9 +594,10 @@ lbm_status lbm3d_create(const lbm3d_grid* grid, const lbm3d_sphere* spheres, int
                         int64_t history_steps, void* d_workspace, size_t bytes, void* hip_stream,
                         lbm3d_ctx** out);
 
-/* Enqueue n time steps (one launch each, pressure planes included; moving
- * spheres add their Newton-Euler, owner-map and refill launches; plus one
- * launch for the last step's force totals).  Asynchronous. */
+/* Enqueue n time steps (one launch each, pressure planes included; free
+ * spheres add a Newton-Euler launch, moving spheres an owner-map and a
+ * refill launch; plus one launch for the last step's force totals).
+ * Asynchronous. */
 lbm_status lbm3d_step(lbm3d_ctx* ctx, int64_t n);
 
 /* Completed time steps. */
