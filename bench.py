@@ -264,6 +264,9 @@ def main() -> int:
                     help="run only the 4096 x 4096 measurement (profiling)")
     ap.add_argument("--only-network", action="store_true",
                     help="run only the warm-start network throughput (profiling)")
+    ap.add_argument("--only-copy", type=int, default=0, metavar="MIB",
+                    help="run only a plain device copy of MIB MiB, three times (the known-size "
+                         "reference that scales the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -281,6 +284,16 @@ def main() -> int:
         return 1
     torch.cuda.set_device(0)
 
+    if args.only_copy:
+        n = args.only_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.only_copy, "repeats": 3}), flush=True)
+        return 0
     case = lc.moving_cylinders()
     nx, ny = case["nx"], case["ny"]
     if args.only_network:

@@ -141,8 +141,10 @@ lbm_status lbm_force(lbm_ctx* ctx, int32_t solid_id, int32_t scheme, double out[
  * The steps must still be held by the history ring.  Asynchronous. */
 lbm_status lbm_force_history(lbm_ctx* ctx, int64_t first, int64_t count, double* d_out);
 
-/* Density and Guo velocity of the current state into device buffers of
- * nx*ny elements of type out_dtype (LBM_F64 or LBM_F32); 0 at solid nodes.
+/* Density and Guo velocity of the current state (the mass and momentum
+ * densities of Sec. II, rho = sum f_i and rho u = sum e_i f_i + rho g / 2 with
+ * the body-force half step) into device buffers of nx*ny elements of type
+ * out_dtype (LBM_F64 or LBM_F32); 0 at solid nodes.
  * d_owner (optional) receives the owner map as uint8 (0 = fluid, else body
  * id).  Any output pointer may be NULL.  Latches LBM_ENUMERIC if a fluid node
  * has a non-finite or non-positive density.  Asynchronous. */
@@ -270,8 +272,8 @@ const char* lbm_last_error(const lbm_ctx* ctx);
  * case advanced alone bit for bit).  Every check interval of k steps a
  * monitor evaluates on the device, per case:
  *   - the residual r = ||u_t - u_{t-k}||_2 / (k ||u_t||_2) over fluid nodes,
- *     u the Guo velocity (steady-state criterion; the paper runs its steady
- *     cases to convergence, Sec. V, Eq. 11 defines the drag coefficient);
+ *     u the Guo velocity (a steady-state criterion the paper does not state;
+ *     the momentum density it is built from is the one of Sec. II);
  *   - CME and GME force and torque on every solid (Eqs. 4-7), summed in a
  *     fixed order (deterministic);
  * and retires a case once r < tol: its state freezes and its tiles leave the

@@ -1,7 +1,8 @@
 """Build step of the gfx950 library (hipcc, in-tree).
 
 Produces ``paper_1303_0625_amd/liblbm.so`` from ``csrc/``.  Every HIP source is
-compiled for gfx950 only, with packed-FP32 instruction selection disabled.
+compiled for gfx950 only, with packed-FP32 instruction selection disabled; the
+translation units compile in parallel and are linked into one shared library.
 """
 from __future__ import annotations
 
@@ -14,9 +15,10 @@ LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = [os.path.join(HERE, "csrc", "lbm_capi.hip"), os.path.join(HERE, "csrc", "nn_capi.hip"),
            os.path.join(HERE, "csrc", "lbm3d_capi.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+OBJDIR = os.path.join(HERE, "_build")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
 ]
@@ -37,18 +39,39 @@ def source_hash(family: str = "lbm") -> str:
     return h.hexdigest()[:16]
 
 
+def _clean(text: str) -> str:
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+
+
 def build_library(verbose: bool = False) -> str:
-    """Compile liblbm.so (always recompiles)."""
+    """Compile liblbm.so (always recompiles every translation unit)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.basename(src).replace(".hip", ".o"))
+        cmd = [HIPCC, *FLAGS, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                            text=True)))
+        objs.append(obj)
+    failed = []
+    for cmd, p in procs:
+        out, _ = p.communicate()
+        out = _clean(out)
+        if p.returncode != 0:
+            failed.append(f"{' '.join(cmd)}\n{out}")
+        elif verbose and out.strip():
+            print(out)
+    if failed:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(failed))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{out}")
-    if verbose and out.strip():
-        print(out)
+        raise RuntimeError(f"hipcc link failed ({r.returncode}):\n{_clean(r.stdout + r.stderr)}")
     os.replace(tmp, LIB)
     return LIB
 
