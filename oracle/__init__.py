@@ -331,6 +331,9 @@ def _load3():
     lib.orc3_set_pressure.restype = ctypes.c_int
     lib.orc3_body_state.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
     lib.orc3_body_state.restype = ctypes.c_int
+    lib.orc3_record_links.argtypes = [ctypes.c_void_p, ctypes.c_long]
+    lib.orc3_links.argtypes = [ctypes.c_void_p, dp, ctypes.c_long]
+    lib.orc3_links.restype = ctypes.c_long
     u8p = ctypes.POINTER(ctypes.c_uint8)
     lib.orc3_refill_node.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, u8p, u8p, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
@@ -425,6 +428,19 @@ class OracleSim3D:
 
     def tube_q(self, y: int, z: int, i: int) -> float:
         return self._lib.orc3_tube_q(self._h, int(y), int(z), int(i))
+
+    def record_links(self, cap: int) -> None:
+        """Keep per-link records (at most cap links per step) from now on."""
+        self._lib.orc3_record_links(self._h, int(cap))
+        self._rec_cap = int(cap)
+
+    def links(self) -> np.ndarray:
+        """Link records of the last step: [n][11] = x, y, z, i, solid (0 the
+        duct), CME force (3), GME force (3)."""
+        cap = getattr(self, "_rec_cap", 0)
+        out = np.zeros((max(cap, 1), 11))
+        n = self._lib.orc3_links(self._h, _dp(out), cap)
+        return out[:n]
 
     def set_pressure(self, rho_in: float, rho_out: float) -> None:
         """Pressure inlet (x = 0) and outlet (x = nx - 1) densities."""

@@ -80,6 +80,8 @@ struct orc3_sim {
     long t;
     double* hist; /* per step (ns + 1) x 12: CME F, T, GME F, T */
     long hist_cap;
+    double* rec;  /* link records of the last step (x, y, z, i, solid, CME F, GME F), or NULL */
+    long rec_n, rec_cap;
 };
 
 static long nidx(const orc3_sim* s, int x, int y, int z) {
@@ -303,6 +305,7 @@ orc3_sim* orc3_create(int nx, int ny, int nz, double tau, double rho0, const dou
 
 void orc3_destroy(orc3_sim* s) {
     if (!s) return;
+    free(s->rec);
     free(s->sp);
     free(s->moving);
     free(s->free_);
@@ -405,6 +408,7 @@ static void one_step(orc3_sim* s) {
     /* forces on every fluid-solid link */
     double* h = hist_row(s, s->t);
     memset(h, 0, sizeof(double) * (size_t)(s->ns + 1) * 12);
+    s->rec_n = 0;
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -430,9 +434,20 @@ static void one_step(orc3_sim* s) {
                             m / (2.0 * q);
                     }
                     double* hs = h + 12 * (o == 255 ? 0 : o);
+                    double* rr = NULL;
+                    if (s->rec && s->rec_n < s->rec_cap) {
+                        rr = s->rec + 11 * s->rec_n++;
+                        rr[0] = x;
+                        rr[1] = y;
+                        rr[2] = z;
+                        rr[3] = i;
+                        rr[4] = o == 255 ? 0 : o;
+                    }
                     for (int sch = 0; sch < 2; ++sch) {
                         double F[3];
                         orc3_link_force(i, a, b, v, sch, F);
+                        if (rr)
+                            for (int d = 0; d < 3; ++d) rr[5 + 3 * sch + d] = F[d];
                         double* hh = hs + 6 * sch;
                         for (int d = 0; d < 3; ++d) hh[d] += F[d];
                         if (o != 255) {
@@ -631,4 +646,20 @@ void orc3_get_f(const orc3_sim* s, double* out) {
 
 void orc3_set_f(orc3_sim* s, const double* in) {
     memcpy(s->f, in, sizeof(double) * 19 * (size_t)s->nx * s->ny * s->nz);
+}
+
+/* Keep the per-link records of each step (up to cap links) from now on. */
+void orc3_record_links(orc3_sim* s, long cap) {
+    free(s->rec);
+    s->rec = cap > 0 ? (double*)calloc((size_t)cap * 11, sizeof(double)) : NULL;
+    s->rec_cap = cap > 0 ? cap : 0;
+    s->rec_n = 0;
+}
+
+/* Link records of the last step, 11 doubles each: x, y, z, i, solid (0 the
+ * duct), CME force (3), GME force (3); returns the count copied. */
+long orc3_links(const orc3_sim* s, double* out, long max) {
+    const long n = s->rec_n < max ? s->rec_n : max;
+    if (n > 0) memcpy(out, s->rec, sizeof(double) * 11 * (size_t)n);
+    return n;
 }

@@ -68,6 +68,12 @@ int orc3_body_state(const orc3_sim* s, int sphere, double out[9]);
 /* Non-zero when a moving sphere met the duct or another sphere. */
 int orc3_error(const orc3_sim* s);
 
+/* Keep per-link records of each step (at most cap links; 0 turns them off),
+ * and copy those of the last step: 11 doubles per link, {x, y, z, i, solid
+ * (0 the duct), CME force (3), GME force (3)}; returns the count. */
+void orc3_record_links(orc3_sim* s, long cap);
+long orc3_links(const orc3_sim* s, double* out, long max);
+
 /* pre-collision populations [19][nz][ny][nx] */
 void orc3_get_f(const orc3_sim* s, double* out);
 void orc3_set_f(orc3_sim* s, const double* in);

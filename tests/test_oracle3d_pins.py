@@ -538,3 +538,61 @@ def test_ibb_tube_momentum_balance_and_comoving_3d(oracle_mod):
     r.step(20)
     _, u, own = r.fields()
     assert np.abs(u[:, own == 0]).max() <= 1e-15
+
+
+def test_ibb_surface_point_arm_and_velocity_3d(oracle_mod):
+    """Under the interpolated rule a link's force acts at the point where the
+    link meets the sphere: found here by bisection on the geometry, that point
+    p gives (i) the torque of Eq. 7 as the sum of (p - X) x F over the link
+    records, for CME and GME, and (ii) the surface velocity of the GME
+    correction: F_GME - F_CME = -(a - b) v(p) is parallel to
+    v(p) = V + Omega x (p - X) on every link.  The sphere spins about a tilted
+    axis and translates in a driven flow, so the link forces are far from
+    parallel to e_i and the point off the link midpoint changes both."""
+    e, _ = _lookup(oracle_mod)
+    n = (18, 16, 16)
+    X = np.array([8.4, 7.2, 7.9])
+    r = 3.3
+    V = np.array([0.004, -0.002, 0.001])
+    Om = np.array([0.004, -0.003, 0.005])
+    s = oracle_mod.OracleSim3D(*n, 0.7, g=(2e-5, 1e-5, -1e-5),
+                               spheres=[dict(cx=X[0], cy=X[1], cz=X[2], r=r, v=tuple(V), omega=tuple(Om))])
+    s.set_ibb(True)
+    s.step(30)
+    s.record_links(20000)
+    s.step(1)
+    rec = s.links()
+    rec = rec[rec[:, 4] == 1]
+    assert len(rec) > 200
+    T = np.zeros((2, 3))
+    worst_par = 0.0
+    off_mid = 0
+    for x, y, z, i, _, cx, cy, cz, gx, gy, gz in rec:
+        i = int(i)
+        lo, hi = 0.0, 1.0
+        for _ in range(60):
+            mid = 0.5 * (lo + hi)
+            p = np.array([x, y, z]) + mid * e[i] - X
+            p = p - np.array(n) * np.floor(p / np.array(n) + 0.5)
+            if p @ p <= r * r:
+                hi = mid
+            else:
+                lo = mid
+        q = hi
+        off_mid += abs(q - 0.5) > 0.05
+        arm = np.array([x, y, z]) + q * e[i] - X
+        arm = arm - np.array(n) * np.floor(arm / np.array(n) + 0.5)
+        assert abs(np.sqrt(arm @ arm) - r) <= 1e-9  # on the surface
+        Fc, Fg = np.array([cx, cy, cz]), np.array([gx, gy, gz])
+        T[0] += np.cross(arm, Fc)
+        T[1] += np.cross(arm, Fg)
+        v = V + np.cross(Om, arm)
+        d = Fg - Fc
+        # relative to the link's force (d is a small difference of two
+        # forces, rounded at their scale)
+        worst_par = max(worst_par, np.linalg.norm(np.cross(d, v)) / (np.linalg.norm(Fc) * np.linalg.norm(v)))
+    assert off_mid > len(rec) // 4
+    assert worst_par <= 1e-13
+    for k, sch in enumerate((oracle_mod.CME, oracle_mod.GME)):
+        Ts = s.force(1, sch)[3:]
+        assert np.abs(Ts - T[k]).max() <= 1e-15 + 1e-12 * np.abs(T[k]).max()
