@@ -1,20 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the D2Q9 momentum-exchange hot path on one MI355X.
 
-Workload: the FP32 2048 x 1024 channel with 32 seeded cylinders (radii
-U(6, 12)), 16 fixed and 16 translating at |v| in [0.01, 0.05] with A1 refill
-of newborn nodes, tau = 0.6, CME and GME force and torque of every cylinder
-every step.  A "step" is one full time step of the hot path (forces, body
-motion, link rebuild, fused advection + bounce-back + collision, refill).
+Headline workload: the 4096 x 4096 periodic lattice with 64 seeded fixed
+cylinders (radii U(8, 16), seed 3003), tau = 0.6, body force 1e-5, plain FP32
+storage, CME and GME force and torque of every cylinder every step.  Its two
+population buffers (1.2 GB) are 4.7x the 256 MB Infinity Cache, so the step
+streams from HBM.  A "step" is one full time step of the hot path (forces and
+the fused advection + bounce-back + collision, one launch).
 
-Prints one JSON line: MLUPS over all nodes, the roofline of the dominant
-kernel (the one-per-step launch whose update role moves 18 populations per
-fluid node, timed with HIP events attached to each dispatch on the library's
-stream), an additional HBM-bound measurement on a 4096 x 4096 periodic lattice
-(its A/B working set is 4.7x the 256 MB Infinity Cache), the batched solver on
-256 uneven channel/cylinder cases, the learned warm start (network throughput
-and time to steady drag against a plain cold start on held-out channels), and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: MLUPS over all nodes (events around the timed steps),
+the roofline of the one-per-step launch whose update role moves 18
+populations per fluid node (timed with HIP events attached to each dispatch on
+the library's stream), and in "extra": the same lattice with FP16 and BF16
+offset storage, the 2048 x 1024 channel with 32 cylinders (16 translating;
+Infinity-Cache resident) with BGK, MRT and interpolated bounce-back, free-disc
+sedimentation, the three-dimensional tube, the batched solver on 256 uneven
+channel/cylinder cases, the learned warm start (network throughput and time
+to steady drag against a plain cold start on held-out channels); and the FP64
+CPU oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -107,6 +110,33 @@ def run_batch(lc, pkg, torch, steps):
             "traffic_per_step": traffic, "alg_bytes_per_step": 72 * n_fluid,
             "check_every": 100, "converged": int(sum(conv)), "max_residual": max(res),
             "timing": "wall clock around graph replays, monitor included"}
+
+
+def run_batch_converge(lc, pkg, torch, cap, chunk=50_000):
+    """The 256 uneven cases from a cold start, FP32, to r < 1e-8 (checks every
+    100 steps, graph-replayed intervals, autotuned tiling), at most `cap`
+    steps: converged fraction, steps at retirement per case, wall time.  A
+    progress line per chunk of steps."""
+    cases = lc.uneven_channels()
+    b = pkg.LatticeBatch(cases, dtype="f32")
+    b.autotune(None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while b.t < cap:
+        done = b.run(min(chunk, cap - b.t), 1e-8, 100)
+        conv = b.status()[0]
+        print(f"# step {b.t}: {sum(conv)}/{len(conv)} converged, {time.perf_counter() - t0:.0f} s", flush=True)
+        if all(conv) or done == 0:
+            break
+    wall = time.perf_counter() - t0
+    conv, steps, res, _ = b.status()
+    re = [c["Re"] for c in cases]
+    nodes = [c["nx"] * c["ny"] for c in cases]
+    return {"cases": len(cases), "cap": cap, "converged": int(sum(conv)),
+            "converged_fraction": round(sum(conv) / len(conv), 4), "wall_s": round(wall, 1),
+            "steps": [int(s) if c else None for s, c in zip(steps, conv)],
+            "residual_at_end": [float(r) for r in res], "Re": re, "nodes": nodes,
+            "criterion": "r = ||u_t - u_{t-100}|| / (100 ||u_t||) < 1e-8 over fluid nodes"}
 
 
 def run_sedimentation(lc, pkg, torch, steps):
@@ -242,15 +272,51 @@ def run_warm_start(lc, pkg, n_cases):
             "criterion": "drag within 1e-4 of an FP64 cold run at r < 1e-11, at every later check"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(case, steps):
+    """The FP64 oracle on a bounded sample of the headline workload: `steps`
+    steps of the same lattice, on all host cores (its OpenMP build: the
+    per-node collision and advection split over OMP_NUM_THREADS threads, the
+    force sum serial), and for reference on one core."""
+    import oracle
+
+    def timed(omp):
+        o = oracle.OracleSim(case["nx"], case["ny"], case["tau"], gx=case["gx"], bodies=case["bodies"],
+                             omp=omp)
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(steps)
+        return time.perf_counter() - t0
+
+    nodes = case["nx"] * case["ny"]
+    dt_all = timed(True)
+    dt_one = timed(False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(nodes * steps / dt_all / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} steps of the same 4096x4096 workload, FP64 ({dt_all:.1f} s on {threads} threads)",
+            "single_thread_mlups": round(nodes * steps / dt_one / 1e6, 3), "cpu_model": cpu_model()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--dtype", default="f32", choices=list(BYTES))
-    ap.add_argument("--cpu-sample-steps", type=int, default=60)
+    ap.add_argument("--cpu-sample-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-hbm-case", action="store_true")
+    ap.add_argument("--no-reduced-case", action="store_true")
+    ap.add_argument("--no-channel-case", action="store_true")
     ap.add_argument("--no-batch-case", action="store_true")
     ap.add_argument("--no-mrt-case", action="store_true")
     ap.add_argument("--no-free-case", action="store_true")
@@ -264,6 +330,9 @@ def main() -> int:
                     help="run only the 4096 x 4096 measurement (profiling)")
     ap.add_argument("--only-network", action="store_true",
                     help="run only the warm-start network throughput (profiling)")
+    ap.add_argument("--only-c4", type=int, default=0, metavar="CAP",
+                    help="run only the 256 uneven channel/cylinder cases (FP32, cold start) to r < 1e-8, "
+                         "at most CAP steps; prints progress and the converged fraction and steps per case")
     ap.add_argument("--only-copy", type=int, default=0, metavar="MIB",
                     help="run only a plain device copy of MIB MiB, three times (the known-size "
                          "reference that scales the HBM traffic counters)")
@@ -294,46 +363,83 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_mib": args.only_copy, "repeats": 3}), flush=True)
         return 0
-    case = lc.moving_cylinders()
-    nx, ny = case["nx"], case["ny"]
     if args.only_network:
         print(json.dumps(run_network(pkg)), flush=True)
         return 0
+    if args.only_c4:
+        print(json.dumps(run_batch_converge(lc, pkg, torch, args.only_c4)), flush=True)
+        return 0
+    big = lc.periodic_cylinders()
     if args.only_hbm_case:
-        big = lc.periodic_cylinders()
         lat2, tms2, ums2, n2, nf2 = run_gpu(big, args.dtype, args.steps, args.warmup, torch, pkg)
         avg2 = ums2 / max(n2, 1) * 1e-3
         print(json.dumps({"periodic_4096x4096_kernel_us": round(avg2 * 1e6, 2),
+                          "ms_per_step": round(tms2 / args.steps, 5),
                           "alg_bytes_per_launch": 18 * BYTES[args.dtype] * nf2,
                           "achieved_GBs": round(18 * BYTES[args.dtype] * nf2 / avg2 / 1e9, 1)}), flush=True)
         return 0
-    lat, total_ms, upd_ms, n_upd, n_fluid = run_gpu(case, args.dtype, args.steps, args.warmup,
-                                                    torch, pkg)
+
+    # headline: the HBM-resident 4096 x 4096 lattice, plain FP32 storage
+    nx, ny = big["nx"], big["ny"]
+    lat, total_ms, upd_ms, n_upd, n_fluid = run_gpu(big, args.dtype, args.steps, args.warmup, torch, pkg)
     ms_per_step = total_ms / args.steps
     mlups = nx * ny * args.steps / (total_ms * 1e-3) / 1e6
     upd_avg_s = (upd_ms / max(n_upd, 1)) * 1e-3
     alg_bytes = 18 * BYTES[args.dtype] * n_fluid
     achieved = alg_bytes / upd_avg_s / 1e9
-    wl = "moving_cylinders_2048x1024"
+    wl = "periodic_4096x4096"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(wl),
-                "kernel": "k_fused (one launch per step: force, mover and fused-update roles)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic(wl) if args.dtype == "f32" else None,
+                "kernel": "k_fused (one launch per step: force and fused-update roles)",
                 "kernel_us": round(upd_avg_s * 1e6, 3), "alg_bytes_per_launch": alg_bytes,
                 "alg_bytes_per_fluid_node": 18 * BYTES[args.dtype]}
     del lat
     torch.cuda.empty_cache()
 
     extra = {}
+    if not args.no_reduced_case:
+        # the same lattice with 16-bit offset storage (FP32 collision, nodes
+        # next to a cylinder kept in FP32)
+        for dt in ("f16", "bf16"):
+            r_steps = min(args.steps, 1000)
+            latr, tmsr, umsr, nr, nfr = run_gpu(big, dt, r_steps, min(args.warmup, 50), torch, pkg)
+            avgr = umsr / max(nr, 1) * 1e-3
+            abr = 18 * BYTES[dt] * nfr
+            extra[f"{wl}_{dt}"] = {
+                "mlups": round(nx * ny * r_steps / (tmsr * 1e-3) / 1e6, 1),
+                "ms_per_step": round(tmsr / r_steps, 5), "kernel_us": round(avgr * 1e6, 2),
+                "achieved_GBs": round(abr / avgr / 1e9, 1), "frac": round(abr / avgr / 1e9 / HBM_PEAK_GBS, 4),
+                "alg_bytes_per_fluid_node": 18 * BYTES[dt]}
+            del latr
+            torch.cuda.empty_cache()
+    case = lc.moving_cylinders()
+    cwl = "moving_cylinders_2048x1024"
+    cnx, cny = case["nx"], case["ny"]
+    if not args.no_channel_case:
+        # 2048 x 1024 channel, 32 cylinders (16 translating with refill): its
+        # FP32 A/B buffers (151 MB) stay in the 256 MB Infinity Cache, so this
+        # is not an HBM figure
+        c_steps = min(args.steps, 2000)
+        latc, tmsc, umsc, nc, nfc = run_gpu(case, "f32", c_steps, args.warmup, torch, pkg)
+        avgc = umsc / max(nc, 1) * 1e-3
+        abc = 72 * nfc
+        extra[cwl] = {"mlups": round(cnx * cny * c_steps / (tmsc * 1e-3) / 1e6, 1),
+                      "ms_per_step": round(tmsc / c_steps, 5), "kernel_us": round(avgc * 1e6, 3),
+                      "achieved_GBs": round(abc / avgc / 1e9, 1), "frac": round(abc / avgc / 1e9 / HBM_PEAK_GBS, 4),
+                      "traffic": stored_traffic(cwl), "residency": "Infinity Cache (151 MB A/B working set)"}
+        del latc
+        torch.cuda.empty_cache()
     if not args.no_mrt_case:
-        # the same workload with the MRT operator of Sec. IV (paper's rates)
+        # the channel workload with the MRT operator of Sec. IV (paper's rates)
         mrt = pkg.lbm.PAPER_MRT_RATES
         m_steps = min(args.steps, 2000)
-        lat3, tms3, ums3, n3, nf3 = run_gpu(case, args.dtype, m_steps, args.warmup, torch, pkg, mrt=mrt)
+        lat3, tms3, ums3, n3, nf3 = run_gpu(case, "f32", m_steps, args.warmup, torch, pkg, mrt=mrt)
         avg3 = ums3 / max(n3, 1) * 1e-3
-        ab3 = 18 * BYTES[args.dtype] * nf3
-        extra["mrt_" + wl] = {
+        ab3 = 72 * nf3
+        extra["mrt_" + cwl] = {
             "rates_e_eps_q": list(mrt),
-            "mlups": round(nx * ny * m_steps / (tms3 * 1e-3) / 1e6, 1),
+            "mlups": round(cnx * cny * m_steps / (tms3 * 1e-3) / 1e6, 1),
             "ms_per_step": round(tms3 / m_steps, 5),
             "kernel_us": round(avg3 * 1e6, 3),
             "achieved_GBs": round(ab3 / avg3 / 1e9, 1),
@@ -341,13 +447,13 @@ def main() -> int:
         del lat3
         torch.cuda.empty_cache()
     if not args.no_ibb_case:
-        # the same workload with interpolated bounce-back on the cylinders
+        # the channel workload with interpolated bounce-back on the cylinders
         i_steps = min(args.steps, 2000)
-        lat4, tms4, ums4, n4, nf4 = run_gpu(case, args.dtype, i_steps, args.warmup, torch, pkg, ibb=True)
+        lat4, tms4, ums4, n4, nf4 = run_gpu(case, "f32", i_steps, args.warmup, torch, pkg, ibb=True)
         avg4 = ums4 / max(n4, 1) * 1e-3
-        ab4 = 18 * BYTES[args.dtype] * nf4
-        extra["ibb_" + wl] = {
-            "mlups": round(nx * ny * i_steps / (tms4 * 1e-3) / 1e6, 1),
+        ab4 = 72 * nf4
+        extra["ibb_" + cwl] = {
+            "mlups": round(cnx * cny * i_steps / (tms4 * 1e-3) / 1e6, 1),
             "ms_per_step": round(tms4 / i_steps, 5),
             "kernel_us": round(avg4 * 1e6, 3),
             "achieved_GBs": round(ab4 / avg4 / 1e9, 1),
@@ -359,22 +465,6 @@ def main() -> int:
         torch.cuda.empty_cache()
     if not args.no_3d_case:
         extra["three_d"] = run_3d(pkg, torch, 2000)
-    if not args.no_hbm_case:
-        big = lc.periodic_cylinders()
-        big_steps = 200
-        lat2, tms2, ums2, n2, nf2 = run_gpu(big, args.dtype, big_steps, 20, torch, pkg)
-        avg2 = ums2 / max(n2, 1) * 1e-3
-        ab2 = 18 * BYTES[args.dtype] * nf2
-        extra["periodic_4096x4096"] = {
-            "mlups": round(big["nx"] * big["ny"] * big_steps / (tms2 * 1e-3) / 1e6, 1),
-            "ms_per_step": round(tms2 / big_steps, 4),
-            "kernel_us": round(avg2 * 1e6, 2),
-            "achieved_GBs": round(ab2 / avg2 / 1e9, 1),
-            "frac": round(ab2 / avg2 / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic("periodic_4096x4096"),
-            "cylinders": len(big["bodies"]), "fixed_geometry": True}
-        del lat2
-        torch.cuda.empty_cache()
 
     if not args.no_batch_case:
         extra["batched_uneven_256"] = run_batch(lc, pkg, torch, args.batch_steps)
@@ -387,27 +477,16 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-
-        o = oracle.OracleSim(nx, ny, case["tau"], walls_y=True, refill=case["refill"],
-                             bodies=case["bodies"])
-        o.step(2)
-        t0 = time.perf_counter()
-        o.step(args.cpu_sample_steps)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(nx * ny * args.cpu_sample_steps / dt / 1e6, 3), "unit": "MLUPS",
-               "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_sample_steps} steps of the same 2048x1024 workload, FP64, "
-                         f"single thread ({dt:.1f} s)"}
+        cpu = run_cpu_baseline(big, args.cpu_sample_steps)
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"{wl}: 32 cylinders r~U(6,12) seed 2002, 16 translating "
-                               "|v|~U(0.01,0.05) with A1 refill, tau 0.6, CME+GME force/torque "
-                               "every step", "nx": nx, "ny": ny, "fluid_nodes": n_fluid},
+        "config": {"workload": f"{wl}: periodic lattice, 64 fixed cylinders r~U(8,16) seed 3003, "
+                               "tau 0.6, body force 1e-5, CME+GME force/torque of every cylinder every step",
+                   "nx": nx, "ny": ny, "fluid_nodes": n_fluid},
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(out), flush=True)

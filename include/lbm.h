@@ -355,7 +355,11 @@ lbm_status lbm_batch_force(lbm_batch* b, int32_t case_id, int32_t solid_id, int3
 lbm_status lbm_batch_fields(lbm_batch* b, int32_t case_id, void* d_rho, void* d_ux, void* d_uy,
                             int32_t out_dtype, uint8_t* d_owner);
 
-/* Warm start of case case_id, as lbm_init_fields.  Synchronises. */
+/* Warm start of case case_id, as lbm_init_fields; with all three field
+ * pointers NULL, the cold start the batch was created with (f_eq(rho0, u0)
+ * collided once: the fallback of a warm start that fails lbm_warm_check or
+ * diverges).  The case's residual starts over (the next check records its
+ * snapshot only).  Synchronises. */
 lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t case_id, const void* d_rho, const void* d_ux,
                                  const void* d_uy, int32_t in_dtype);
 
@@ -521,6 +525,17 @@ lbm_status lbm_nn_infer(lbm_nn* nn, const uint8_t* d_solid, const double* d_re, 
 lbm_status lbm_warm_project(int32_t nx, int32_t ny, int32_t n_fields, const uint8_t* d_owner, float* d_rho,
                             float* d_ux, float* d_uy, const float* d_rho2, const float* d_ux2, const float* d_uy2,
                             double rho0, void* hip_stream);
+
+/* Start check of warm-start fields (the learned start falls back to the cold
+ * start of a channel whose fields fail it): for each of n_fields channels of
+ * nx x ny, d_ok[k] (int32 device [n_fields]) = 1 when every fluid node (owner
+ * 0) has a finite density in (0, 2 rho0) and a finite velocity of magnitude
+ * <= u_max, else 0.  Inputs as for lbm_warm_project, not modified.  The
+ * density and momentum it bounds are those of Sec. II.  Asynchronous on
+ * hip_stream; LBM_EINVAL on bad sizes, NULL pointers or rho0, u_max <= 0. */
+lbm_status lbm_warm_check(int32_t nx, int32_t ny, int32_t n_fields, const uint8_t* d_owner, const float* d_rho,
+                          const float* d_ux, const float* d_uy, double rho0, double u_max, int32_t* d_ok,
+                          void* hip_stream);
 
 /* Release the network (not the caller's buffers).  NULL is ignored. */
 void lbm_nn_destroy(lbm_nn* nn);

@@ -25,6 +25,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _SRC3 = os.path.join(_HERE, "lbm3d_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
+# The same sources built with OpenMP: the per-node collision and advection
+# loops split over threads, every result identical (used to time the oracle on
+# all of a host's cores; the tests use the single-threaded build).
+_LIB_OMP = os.path.join(_HERE, "liblbm_oracle_omp.so")
 
 DISC, BOX = 0, 1
 CME, GME = 0, 1
@@ -39,13 +43,15 @@ W = (4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle shared library with gcc; returns its path."""
+    """Compile the oracle shared library with gcc (and its multi-threaded
+    timing build from the same sources); returns the path of the first."""
     newest = max(os.path.getmtime(p) for p in (_SRC, _SRC3))
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
-               "-o", _LIB + ".tmp", _SRC, _SRC3, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < newest:
+            cmd = ["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared", *extra,
+                   "-o", lib + ".tmp", _SRC, _SRC3, "-lm"]
+            subprocess.check_call(cmd)
+            os.replace(lib + ".tmp", lib)
     return _LIB
 
 
@@ -57,14 +63,25 @@ class _Body(ctypes.Structure):
 
 
 _lib = None
+_lib_omp = None
 
 
-def _load():
-    global _lib
+def _load(omp: bool = False):
+    """The oracle library; omp: its multi-threaded timing build."""
+    global _lib, _lib_omp
+    if omp:
+        if _lib_omp is None:
+            build(force=False)
+            _lib_omp = _bind(ctypes.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is not None:
         return _lib
     build(force=False)
-    lib = ctypes.CDLL(_LIB)
+    _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _bind(lib):
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
     lib.orc_create.restype = ctypes.c_void_p
@@ -105,7 +122,6 @@ def _load():
     lib.orc_set_ibb.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.orc_link_q.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_long, ctypes.c_int]
     lib.orc_link_q.restype = ctypes.c_double
-    _lib = lib
     return lib
 
 
@@ -176,12 +192,13 @@ class OracleSim:
     """One D2Q9 simulation held by the C oracle.
 
     ``bodies`` is a sequence of dicts with keys kind ('disc'|'box' or 0|1),
-    cx, cy, r (or hx), hy, vx, vy, moves.
+    cx, cy, r (or hx), hy, vx, vy, moves.  ``omp``: run on the multi-threaded
+    build (OMP_NUM_THREADS threads; the same results).
     """
 
     def __init__(self, nx, ny, tau, *, walls_y=False, rho0=1.0, gx=0.0, gy=0.0, u0=(0.0, 0.0),
-                 wall_v=(0.0, 0.0), refill=A1, rho_w_local=False, bodies=(), mrt=None):
-        lib = _load()
+                 wall_v=(0.0, 0.0), refill=A1, rho_w_local=False, bodies=(), mrt=None, omp=False):
+        lib = _load(omp)
         self.nx, self.ny = int(nx), int(ny)
         self.nb = len(bodies)
         arr = (_Body * max(1, self.nb))()

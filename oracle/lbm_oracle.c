@@ -534,7 +534,9 @@ static void one_step(orc_sim* s) {
     const int nx = s->nx, ny = s->ny;
     const long t = s->t;
 
-    /* O1-O2: collide every fluid node of G_t. */
+    /* O1-O2: collide every fluid node of G_t (nodes are independent: the
+     * multi-threaded timing build splits the rows over threads). */
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (s->own[idx(s, x, y)] != 0) continue;
@@ -627,6 +629,7 @@ static void one_step(orc_sim* s) {
 
     /* O4: advection (Eq. 3) with half-way bounce-back on G_t. */
     memset(s->fn, 0, sizeof(double) * 9 * (size_t)nx * (size_t)ny);
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (s->own[idx(s, x, y)] != 0) continue;

@@ -26,8 +26,8 @@ struct lbm_batch {
     int max_nsol = 1;
     int n_tiles_max = 0;
     // layout (byte offsets)
-    size_t o_cases, o_tiles, o_conv, o_f, o_own, o_snap, o_links, o_segcnt, o_segoff, o_segcap, o_sol, o_vtab,
-        o_chunks, o_fpart, o_mpart, o_res, o_forces, o_tdev, o_tfirst, o_tcount, o_list, o_err;
+    size_t o_cases, o_tiles, o_conv, o_f, o_side, o_own, o_snap, o_links, o_segcnt, o_segoff, o_segcap, o_sol,
+        o_vtab, o_chunks, o_fpart, o_mpart, o_res, o_forces, o_tdev, o_tfirst, o_tcount, o_list, o_err;
     // current tiling
     int waves = 4;
     int nt = 1;
@@ -68,8 +68,8 @@ struct BatchLayout {
     std::vector<int> seg_off, seg_cap, solid_base;
     int max_nsol;
     int n_tiles_max;
-    size_t o_cases, o_tiles, o_conv, o_f, o_own, o_snap, o_links, o_segcnt, o_segoff, o_segcap, o_sol, o_vtab,
-        o_chunks, o_fpart, o_mpart, o_res, o_forces, o_tdev, o_tfirst, o_tcount, o_list, o_err;
+    size_t o_cases, o_tiles, o_conv, o_f, o_side, o_own, o_snap, o_links, o_segcnt, o_segoff, o_segcap, o_sol,
+        o_vtab, o_chunks, o_fpart, o_mpart, o_res, o_forces, o_tdev, o_tfirst, o_tcount, o_list, o_err;
 };
 
 const char* batch_layout(const lbm_grid* grids, const double* taus, const lbm_solid* solids,
@@ -77,7 +77,7 @@ const char* batch_layout(const lbm_grid* grids, const double* taus, const lbm_so
     if (n < 1) return "n_cases must be >= 1";
     if (!grids || !taus || !n_solids) return "grids, taus and n_solids must not be NULL";
     const size_t es = dtype_size(grids[0].dtype);
-    int64_t elem_off = 0, own_off = 0, snap_off = 0;
+    int64_t elem_off = 0, own_off = 0, snap_off = 0, side_el = 0;
     int links = 0, sbase = 0;
     B.max_nsol = 1;
     B.n_tiles_max = 0;
@@ -116,10 +116,26 @@ const char* batch_layout(const lbm_grid* grids, const double* taus, const lbm_so
         d.fa.nsol = n_solids[c] + 1;
         d.fa.nchunks = 0;
         const int64_t fel = 9 * (int64_t)g.ny * pitch;
-        elem_off = (elem_off + 63) / 64 * 64;  // 256-byte aligned rows for every storage size
+        elem_off = (elem_off + 127) / 128 * 128;  // 256-byte aligned rows for every storage size
         d.f_off[0] = elem_off;
-        d.f_off[1] = elem_off + (fel + 63) / 64 * 64;
-        elem_off = d.f_off[1] + fel;
+        d.sa.nseg = pitch >> kRefShift;
+        d.fa.nseg = d.sa.nseg;
+        if (es == 2) {
+            // 16-bit storage: each buffer has its reference table right after
+            // it; the two buffers sit at least one FP32 side array apart, so
+            // that side arrays at one common distance from them do not overlap
+            const int64_t ref_el = (fel + 127) / 128 * 128;               // byte offset 2 ref_el
+            const int64_t rb_el = (int64_t)g.ny * d.sa.nseg * kSeg * 2;   // reference table (floats)
+            d.sa.ref_off = 2 * ref_el;
+            d.fa.ref_off = d.sa.ref_off;
+            d.f_off[1] = elem_off + (std::max(2 * fel, ref_el + rb_el) + 127) / 128 * 128;
+            elem_off = d.f_off[1] + ref_el + rb_el;
+            d.sa.side_off = side_el;  // element offset in the side region for now
+            side_el += 2 * (d.f_off[1] - d.f_off[0]);
+        } else {
+            d.f_off[1] = elem_off + (fel + 63) / 64 * 64;
+            elem_off = d.f_off[1] + fel;
+        }
         d.own_off = own_off;
         own_off += (int64_t)g.ny * pitch;
         d.snap_off = snap_off;
@@ -156,6 +172,13 @@ const char* batch_layout(const lbm_grid* grids, const double* taus, const lbm_so
     take(B.o_tiles, sizeof(Tile) * B.n_tiles_max);
     take(B.o_conv, 4 * (size_t)n);
     take(B.o_f, es * (size_t)elem_off);
+    take(B.o_side, es * (size_t)side_el);
+    if (es == 2)
+        for (auto& d : B.cd) {
+            // bytes from a case's population buffer to its FP32 side array
+            d.sa.side_off = (int64_t)B.o_side + 2 * d.sa.side_off - (int64_t)(B.o_f + 2 * (size_t)d.f_off[0]);
+            d.fa.side_off = d.sa.side_off;
+        }
     take(B.o_own, (size_t)own_off);
     take(B.o_snap, 8 * (size_t)snap_off);
     take(B.o_links, 4 * (size_t)links);
@@ -460,7 +483,7 @@ lbm_status lbm_batch_create(const lbm_grid* grids, const double* taus, const lbm
     b->chunks = B.chunks;
     b->max_nsol = B.max_nsol;
     b->n_tiles_max = B.n_tiles_max;
-    b->o_cases = B.o_cases; b->o_tiles = B.o_tiles; b->o_conv = B.o_conv; b->o_f = B.o_f;
+    b->o_cases = B.o_cases; b->o_tiles = B.o_tiles; b->o_conv = B.o_conv; b->o_f = B.o_f; b->o_side = B.o_side;
     b->o_own = B.o_own; b->o_snap = B.o_snap; b->o_links = B.o_links; b->o_segcnt = B.o_segcnt;
     b->o_segoff = B.o_segoff; b->o_segcap = B.o_segcap; b->o_sol = B.o_sol; b->o_vtab = B.o_vtab; b->o_chunks = B.o_chunks;
     b->o_fpart = B.o_fpart; b->o_mpart = B.o_mpart; b->o_res = B.o_res; b->o_forces = B.o_forces;
@@ -470,7 +493,7 @@ lbm_status lbm_batch_create(const lbm_grid* grids, const double* taus, const lbm
     b->err[0] = 0;
     // the working set decides the streaming mode of the update
     size_t fb = 0;
-    for (const auto& d : b->cd) fb += (size_t)(d.f_off[1] - d.f_off[0]) * dtype_size(b->dtype) * 2;
+    for (const auto& d : b->cd) fb += (size_t)(9 * (int64_t)d.sa.ny * d.sa.rowlen) * dtype_size(b->dtype) * 2;
     b->nt = fb > kStreamBytes ? 1 : 0;
     hipError_t e = hipStreamCreateWithFlags(&b->run_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -734,8 +757,13 @@ lbm_status lbm_batch_fields(lbm_batch* b, int32_t case_id, void* d_rho, void* d_
 
 lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t case_id, const void* d_rho, const void* d_ux,
                                  const void* d_uy, int32_t in_dtype) {
-    if (!b || case_id < 0 || case_id >= b->n || !d_rho || !d_ux || !d_uy) return LBM_EINVAL;
-    if (in_dtype != LBM_F64 && in_dtype != LBM_F32) {
+    if (!b || case_id < 0 || case_id >= b->n) return LBM_EINVAL;
+    const bool cold = !d_rho && !d_ux && !d_uy;
+    if (!cold && (!d_rho || !d_ux || !d_uy)) {
+        set_err(b->err, "give all three fields, or none for the cold start");
+        return LBM_EINVAL;
+    }
+    if (!cold && in_dtype != LBM_F64 && in_dtype != LBM_F32) {
         set_err(b->err, "fields are read as LBM_F64 or LBM_F32");
         return LBM_EINVAL;
     }
@@ -747,6 +775,14 @@ lbm_status lbm_batch_init_fields(lbm_batch* b, int32_t case_id, const void* d_rh
     if (rs != LBM_OK) return rs;
     batch_init_dispatch(b, case_id, b->run_stream, d_rho, d_ux, d_uy, in_dtype);
     BCHK(b, hipGetLastError());
+    // the residual starts over: the next check records a snapshot only
+    CaseResult rr;
+    char* rp = b->ws + b->o_res + sizeof(CaseResult) * case_id;
+    BCHK(b, hipMemcpyAsync(&rr, rp, sizeof(rr), hipMemcpyDeviceToHost, b->run_stream));
+    BCHK(b, hipStreamSynchronize(b->run_stream));
+    rr.have_snap = 0;
+    rr.residual = -1.0;
+    BCHK(b, hipMemcpyAsync(rp, &rr, sizeof(rr), hipMemcpyHostToDevice, b->run_stream));
     BCHK(b, hipStreamSynchronize(b->run_stream));
     return LBM_OK;
 }
@@ -848,10 +884,18 @@ lbm_status lbm_batch_set_active(lbm_batch* b, int32_t case_id, int32_t active) {
         if (!b->conv_h[case_id]) return LBM_OK;
         const CaseDev& d = b->cd[case_id];
         if ((rr.steps & 1) != (b->t & 1)) {  // the frozen state sits in the other buffer
-            const size_t bytes = (size_t)(d.f_off[1] - d.f_off[0]) * dtype_size(b->dtype);
             const size_t es = dtype_size(b->dtype);
-            BCHK(b, hipMemcpyAsync(b->ws + b->o_f + es * d.f_off[b->t & 1], b->ws + b->o_f + es * d.f_off[rr.steps & 1],
-                                   bytes, hipMemcpyDeviceToDevice, b->run_stream));
+            const size_t bytes = (size_t)(9 * (int64_t)d.sa.ny * d.sa.rowlen) * es;
+            char* dst = b->ws + b->o_f + es * d.f_off[b->t & 1];
+            const char* src = b->ws + b->o_f + es * d.f_off[rr.steps & 1];
+            BCHK(b, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, b->run_stream));
+            if (es == 2) {  // and the FP32 side array and the reference table
+                BCHK(b, hipMemcpyAsync(dst + d.sa.side_off, src + d.sa.side_off, 2 * bytes, hipMemcpyDeviceToDevice,
+                                       b->run_stream));
+                const size_t rb = (size_t)d.sa.ny * d.sa.nseg * kSeg * 4;
+                BCHK(b, hipMemcpyAsync(dst + d.sa.ref_off, src + d.sa.ref_off, rb, hipMemcpyDeviceToDevice,
+                                       b->run_stream));
+            }
         }
         rr.converged = 0;
         rr.have_snap = 0;

@@ -63,9 +63,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_step(const CaseDev* __rest
     if (w >= cd.nwaves) return;
     const int y = w / cd.wpr;
     const int x = (w - y * cd.wpr) * 64 + (int)(threadIdx.x & 63);
-    if (x >= cd.sa.nx) return;
+    if constexpr (!Sto<T>::kSplit) {
+        if (x >= cd.sa.nx) return;
+    }
     step_node<T, NT>(x, y, fbase + cd.f_off[parity], fbase + cd.f_off[parity ^ 1], obase + cd.own_off,
-                     vtab_all + 2 * cd.solid_base, nullptr, nullptr, 0, cd.sa, case_cp<T>(cd));
+                     vtab_all + 2 * cd.solid_base, nullptr, nullptr, 0, cd.sa, case_cp<T>(cd), nullptr, x < cd.sa.nx);
 }
 
 // Force chunks of every active case at the current state (parity).
@@ -119,10 +121,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_monitor(const CaseDev* __r
             const int y = w / cd.wpr;
             const int x = (w - y * cd.wpr) * 64 + (int)(threadIdx.x & 63);
             if (x < cd.sa.nx && obase[cd.own_off + (int64_t)y * cd.sa.opitch + x] == 0) {
-                const T* f = fbase + cd.f_off[parity] + (int64_t)y * cd.sa.ystride + x;
+                const T* f = fbase + cd.f_off[parity];
                 double d[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) d[i] = (double)Sto<T>::ld(f[i * cd.sa.istride]);
+                for (int i = 0; i < 9; ++i) d[i] = (double)pop_at(f, cd.sa, i, x, y);
                 const double drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
                 const double r = cd.sa.rho0 + drho;
                 const double jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
@@ -181,7 +183,10 @@ __global__ void k_batch_finalize(const CaseDev* __restrict__ cases, const int* _
         dd += mon_partial[2 * (size_t)b];
         uu += mon_partial[2 * (size_t)b + 1];
     }
-    const double r = uu > 0.0 ? sqrt(dd) / ((double)k_steps * sqrt(uu)) : (dd > 0.0 ? 1.0 : 0.0);
+    // a state that is not finite (a diverged start) reports NaN and never retires
+    const double r = !(isfinite(dd) && isfinite(uu))
+                         ? __builtin_nan("")
+                         : (uu > 0.0 ? sqrt(dd) / ((double)k_steps * sqrt(uu)) : (dd > 0.0 ? 1.0 : 0.0));
     double* fc = forces + (size_t)c * max_nsol * 6;
     for (int q = 0; q < cd.nsol * 6; ++q) fc[q] = 0.0;
     // chunks of a case are listed solid by solid: chunk order is summation order

@@ -17,6 +17,7 @@
 
 using namespace lbm;
 
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -33,6 +34,8 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // Working sets above this use nontemporal loads/stores in the update kernel
 // (MI355X has a 256 MB Infinity Cache).
 constexpr size_t kStreamBytes = 256ull << 20;
+// Steps per captured graph of lbm_step (even: a block keeps its parity).
+constexpr int kGraphSteps = 32;
 
 size_t dtype_size(int dt) {
     switch (dt) {
@@ -55,6 +58,12 @@ struct Layout {
     int nchunks;
     int box_bytes;  // LDS byte map per translating body (mover role)
     size_t fbytes;  // bytes of one population buffer
+    size_t pbytes;  // bytes of its populations proper
+    // 16-bit storage: bytes from a buffer to its FP32 side array and to its
+    // reference table, their sizes, and reference segments per row
+    int64_t side_off, ref_off;
+    size_t sbytes, rbytes;
+    int nseg;
 };
 
 // Conservative link capacity of one body: every fluid node adjacent to a
@@ -75,15 +84,34 @@ bool make_layout(const lbm_grid& g, const lbm_solid* solids, int n, int64_t hist
     L.plane = (int64_t)g.ny * L.pitch;  // elements per population (all rows)
     size_t off = 0;
     const size_t fbytes = 9 * (size_t)L.plane * es;
+    L.pbytes = fbytes;
     L.fbytes = fbytes;
+    L.side_off = 0;
     // The second buffer starts off a large power-of-two distance from the
     // first: reads of row y and writes of row y then fall on different HBM
     // channels (measured on 4096 x 4096: 231.6 us with no offset, 208.4 us
     // with 3 MiB or more).
     const size_t skew = std::min<size_t>(4u << 20, align256(fbytes / 8));
-    for (int k = 0; k < 2; ++k) {
-        L.f[k] = off;
-        off = align256(off + fbytes) + (k == 0 ? skew : 0);
+    L.ref_off = 0;
+    L.sbytes = L.rbytes = 0;
+    L.nseg = L.pitch >> kRefShift;
+    if (es == 2) {
+        // 16-bit storage: each buffer has its reference table right after it
+        // and a float array (nodes next to a solid) at the same distance
+        // side_off; the buffers sit one float array apart so that the two
+        // float arrays do not overlap
+        L.sbytes = 9 * (size_t)L.plane * 4;
+        L.rbytes = (size_t)g.ny * L.nseg * kSeg * 4;
+        L.ref_off = (int64_t)align256(fbytes);
+        L.f[0] = 0;
+        L.f[1] = align256(std::max(L.sbytes, (size_t)L.ref_off + L.rbytes)) + skew;
+        L.side_off = (int64_t)align256(L.f[1] + (size_t)L.ref_off + L.rbytes);
+        off = align256(L.f[1] + (size_t)L.side_off + L.sbytes);
+    } else {
+        for (int k = 0; k < 2; ++k) {
+            L.f[k] = off;
+            off = align256(off + fbytes) + (k == 0 ? skew : 0);
+        }
     }
     L.n_movers = 0;
     for (int k = 0; k < n; ++k) L.n_movers += solids[k].moves ? 1 : 0;
@@ -223,6 +251,14 @@ struct lbm_ctx {
     std::vector<int> seg_off, seg_cap;
     int64_t link_cap_total;
     char err[512];
+    // blocks of kGraphSteps steps replayed as HIP graphs, one per start
+    // parity (every kernel argument is fixed by the parity; the step counter
+    // lives on the device), captured on a stream of the context's own
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // the force totals of the last step are summed when first read (every
+    // earlier step's are summed by the launch after it)
+    bool fin_pending = false;
     // instrumentation: event pairs around the lattice-update kernel
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -249,6 +285,9 @@ StepArgs step_args(const lbm_ctx* c) {
     a.walls = c->g.walls_y;
     a.rho0 = c->g.rho0;
     a.ibb = c->ibb;
+    a.side_off = c->L.side_off;
+    a.ref_off = c->L.ref_off;
+    a.nseg = c->L.nseg;
     return a;
 }
 
@@ -280,6 +319,9 @@ ForceArgs force_args(const lbm_ctx* c) {
     a.nchunks = c->L.nchunks;
     a.opitch = c->L.opitch;
     a.ibb = c->ibb;
+    a.side_off = c->L.side_off;
+    a.ref_off = c->L.ref_off;
+    a.nseg = c->L.nseg;
     return a;
 }
 
@@ -343,13 +385,16 @@ lbm_status enqueue_step(lbm_ctx* c) {
     MoveArgs ma{c->g.nx, c->g.ny, c->L.opitch, c->g.walls_y, (int64_t)c->L.pitch,
                 9 * (int64_t)c->L.pitch, c->g.rho0, c->g.refill, c->L.box_bytes, n_presc};
     ma.ibb = c->ibb;
+    ma.side_off = c->L.side_off;
+    ma.ref_off = c->L.ref_off;
+    ma.nseg = c->L.nseg;
     StepArgs sa = step_args(c);
     ForceArgs fa = force_args(c);
     CollideParams<C> cp = collide_params<C>(c);
     const dim3 grid((unsigned)(rc.n_lead + node_blocks(c)));
     const size_t lds = n_presc > 0 ? 2 * (size_t)c->L.box_bytes : 0;
     // both population buffers larger than the Infinity Cache: stream them
-    const bool nt = 2 * c->L.fbytes > kStreamBytes;
+    const bool nt = 2 * c->L.pbytes > kStreamBytes;
     using KF = decltype(&k_fused<T, true, true, true>);
     KF kern;
     // per-link surface geometry: spinning free bodies or interpolated bounce-back
@@ -486,6 +531,54 @@ lbm_status read_err(lbm_ctx* c) {
         return LBM_EGEOM;
     }
     return LBM_OK;
+}
+
+// Forget the captured step graphs (a setter changed what the launches take).
+void drop_graphs(lbm_ctx* c) {
+    for (auto& g : c->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Capture kGraphSteps steps starting at parity p into c->gexec[p].
+lbm_status capture_block(lbm_ctx* c, int p) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    const int64_t tsave = c->t;
+    c->t = p;  // only the parity of t enters the launches
+    c->stream = c->cap_stream;
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+    lbm_status rs = LBM_OK;
+    if (e == hipSuccess)
+        for (int k = 0; k < kGraphSteps && rs == LBM_OK; ++k) rs = dispatch_step(c);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(c->cap_stream, &g) : e;
+    c->stream = user;
+    c->t = tsave;
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+    if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+    if (rs != LBM_OK) {
+        (void)hipGraphDestroy(g);
+        return rs;
+    }
+    e = hipGraphInstantiate(&c->gexec[p], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec[p] = nullptr;
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    return LBM_OK;
+}
+
+// Sum the last step's force totals if a reader needs them.
+void finalize_pending(lbm_ctx* c) {
+    if (!c->fin_pending) return;
+    k_finalize<<<1, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.partial), wsp<int>(c, c->L.solid_chunk0),
+                                            wsp<double>(c, c->L.hist), wsp<int64_t>(c, c->L.tctr),
+                                            (int)(c->t & 1), force_args(c));
+    c->fin_pending = false;
 }
 
 }  // namespace
@@ -697,14 +790,24 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
             return LBM_EGEOM;
         }
     }
-    for (int64_t k = 0; k < n; ++k) {
+    c->fin_pending = false;  // the first launch sums the previous step's totals
+    int64_t k = 0;
+    // whole blocks as graph replays (not while timing single launches)
+    while (!c->prof && n - k >= kGraphSteps) {
+        const int p = (int)(c->t & 1);
+        if (!c->gexec[p]) {
+            lbm_status rs = capture_block(c, p);
+            if (rs != LBM_OK) return rs;
+        }
+        HIPCHK(c, hipGraphLaunch(c->gexec[p], c->stream));
+        c->t += kGraphSteps;
+        k += kGraphSteps;
+    }
+    for (; k < n; ++k) {
         lbm_status s = dispatch_step(c);
         if (s != LBM_OK) return s;
     }
-    // totals of the last step (every earlier step was finalized by the launch after it)
-    k_finalize<<<1, kBlock, 0, c->stream>>>(wsp<double>(c, c->L.partial), wsp<int>(c, c->L.solid_chunk0),
-                                            wsp<double>(c, c->L.hist), wsp<int64_t>(c, c->L.tctr),
-                                            (int)(c->t & 1), force_args(c));
+    c->fin_pending = true;
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
 }
@@ -725,6 +828,7 @@ lbm_status lbm_force(lbm_ctx* c, int32_t solid_id, int32_t scheme, double out[3]
         set_err(c->err, "no step has been taken yet (since create or load)");
         return LBM_ESTATE;
     }
+    finalize_pending(c);
     double rec[6];
     const int64_t slot = (c->t - 1) % c->hist_cap;
     const double* src = wsp<double>(c, c->L.hist) + (slot * (c->n + 1) + solid_id) * 6;
@@ -745,6 +849,7 @@ lbm_status lbm_force_history(lbm_ctx* c, int64_t first, int64_t count, double* d
                 (long long)first, (long long)(first + count), (long long)c->t, (long long)c->hist_cap);
         return LBM_EINVAL;
     }
+    finalize_pending(c);
     const size_t row = (size_t)(c->n + 1) * 6 * sizeof(double);
     const char* base = c->ws + c->L.hist;
     int64_t k = 0;
@@ -816,6 +921,7 @@ lbm_status lbm_set_boundary(lbm_ctx* c, int32_t rule) {
         return LBM_EINVAL;
     }
     c->ibb = rule == LBM_INTERPOLATED ? 1 : 0;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -839,6 +945,7 @@ lbm_status lbm_set_collision(lbm_ctx* c, int32_t model, const double* rates) {
     }
     c->mrt = model == LBM_MRT ? 1 : 0;
     for (int k = 0; k < 3; ++k) c->mrt_s[k] = c->mrt ? rates[k] : 0.0;
+    drop_graphs(c);
     // the start state is f_eq(rho0, u0) collided once with the chosen operator
     dispatch_init<double>(c, nullptr, nullptr, nullptr);
     HIPCHK(c, hipGetLastError());
@@ -894,6 +1001,7 @@ lbm_status lbm_set_free_body(lbm_ctx* c, int32_t solid_id, double rho_s, double 
                             rot, sizeof(rot), hipMemcpyHostToDevice));
     c->movers_h = presc;
     c->frees_h = frees;
+    drop_graphs(c);
     c->is_free[solid_id] = 1;
     return LBM_OK;
 }
@@ -904,6 +1012,7 @@ lbm_status lbm_set_gravity(lbm_ctx* c, double gx, double gy, int32_t scheme) {
     c->Gx = gx;
     c->Gy = gy;
     c->dyn_scheme = scheme;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -1009,10 +1118,15 @@ lbm_status lbm_link_forces(lbm_ctx* c, double* d_out, int64_t max, int64_t* n) {
     return LBM_OK;
 }
 
+// Bytes of the state of one step: populations and, for 16-bit storage, the
+// FP32 side array and the reference table.
+size_t ckpt_pop_bytes(const lbm_ctx* c) { return c->L.pbytes + c->L.sbytes + c->L.rbytes; }
+
 lbm_status lbm_checkpoint_bytes(const lbm_ctx* c, size_t* bytes) {
     if (!c || !bytes) return LBM_EINVAL;
-    // populations (current buffer), both owner maps, links + counts, counters
-    *bytes = 64 + c->L.fbytes + 2 * (c->L.own[1] - c->L.own[0]) +
+    // populations (current buffer and, for 16-bit storage, its FP32 side
+    // array), both owner maps, links + counts, counters
+    *bytes = 64 + ckpt_pop_bytes(c) + 2 * (c->L.own[1] - c->L.own[0]) +
              4 * (size_t)std::max<int64_t>(c->link_cap_total, 1) + 4 * (size_t)(c->n + 1);
     return LBM_OK;
 }
@@ -1032,12 +1146,16 @@ lbm_status lbm_save(lbm_ctx* c, void* d_dst, size_t bytes) {
     char* d = (char*)d_dst;
     int64_t hdr[8] = {0x6c626d63, (int64_t)LBM_ABI_VERSION, c->t, c->g.nx, c->g.ny, c->g.dtype, c->n, 0};
     const int p = (int)(c->t & 1);
-    const size_t fb = c->L.fbytes;
+    const size_t fb = c->L.pbytes, sb = c->L.sbytes, rb = c->L.rbytes;
     const size_t ob = c->L.own[1] - c->L.own[0];
     HIPCHK(c, hipMemcpyAsync(d, hdr, 64, hipMemcpyHostToDevice, c->stream));
     size_t o = 64;
     HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.f[p], fb, hipMemcpyDeviceToDevice, c->stream));
     o += fb;
+    if (sb) HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.f[p] + c->L.side_off, sb, hipMemcpyDeviceToDevice, c->stream));
+    o += sb;
+    if (rb) HIPCHK(c, hipMemcpyAsync(d + o, c->ws + c->L.f[p] + c->L.ref_off, rb, hipMemcpyDeviceToDevice, c->stream));
+    o += rb;
     HIPCHK(c, hipMemcpyAsync(d + o, own_ptr(c, p), ob, hipMemcpyDeviceToDevice, c->stream));
     o += ob;
     HIPCHK(c, hipMemcpyAsync(d + o, own_ptr(c, p ^ 1), ob, hipMemcpyDeviceToDevice, c->stream));
@@ -1072,11 +1190,15 @@ lbm_status lbm_load(lbm_ctx* c, const void* d_src, size_t bytes) {
     }
     c->t = hdr[2];
     const int p = (int)(c->t & 1);
-    const size_t fb = c->L.fbytes;
+    const size_t fb = c->L.pbytes, sb = c->L.sbytes, rb = c->L.rbytes;
     const size_t ob = c->L.own[1] - c->L.own[0];
     size_t o = 64;
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.f[p], s + o, fb, hipMemcpyDeviceToDevice, c->stream));
     o += fb;
+    if (sb) HIPCHK(c, hipMemcpyAsync(c->ws + c->L.f[p] + c->L.side_off, s + o, sb, hipMemcpyDeviceToDevice, c->stream));
+    o += sb;
+    if (rb) HIPCHK(c, hipMemcpyAsync(c->ws + c->L.f[p] + c->L.ref_off, s + o, rb, hipMemcpyDeviceToDevice, c->stream));
+    o += rb;
     HIPCHK(c, hipMemcpyAsync(own_ptr(c, p), s + o, ob, hipMemcpyDeviceToDevice, c->stream));
     o += ob;
     if (c->L.n_movers > 0)
@@ -1088,6 +1210,7 @@ lbm_status lbm_load(lbm_ctx* c, const void* d_src, size_t bytes) {
     HIPCHK(c, hipMemcpyAsync(c->ws + c->L.seg_cnt[p], s + o, 4 * (size_t)(c->n + 1), hipMemcpyDeviceToDevice, c->stream));
     k_set_counters<<<1, 1, 0, c->stream>>>(wsp<int64_t>(c, c->L.tctr), c->t, wsp<int>(c, c->L.err));
     c->hist_first = c->t;  // force records before the checkpoint are not restored
+    c->fin_pending = false;
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
 }
@@ -1127,6 +1250,8 @@ lbm_status lbm_status_check(lbm_ctx* c) {
 
 void lbm_destroy(lbm_ctx* c) {
     if (!c) return;
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }

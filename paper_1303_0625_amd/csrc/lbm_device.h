@@ -4,8 +4,8 @@
 // (arXiv:1303.0625); weights 4/9, 1/9, 1/36.  Populations are stored as
 // deviations d_i = f_i - w_i rho0 from the rest equilibrium, in one of four
 // storage types; collision arithmetic runs in double (double and float
-// storage) or float (half and bfloat16 storage, whose error is set by the
-// 11- and 8-bit significands, not by the arithmetic).
+// storage) or float (half and bfloat16 storage, whose nodes next to a solid
+// keep FP32 populations).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,11 +38,16 @@ struct bf16_t {
 
 template <typename T>
 struct Sto;
+// kSplit: the storage type keeps the populations of the nodes next to a solid
+// in FP32 instead (see the marker of the 16-bit types below).
 template <>
 struct Sto<double> {
     using C = double;
+    static constexpr bool kSplit = false;
     __device__ static inline double ld(double v) { return v; }
     __device__ static inline double st(double c) { return c; }
+    __device__ static inline bool marked(double) { return false; }
+    __device__ static inline double mark() { return 0.0; }
 };
 // FP32 storage collides in double: the moment sums and the equilibrium are
 // formed from deviations ~1e-4 whose float partial sums lose digits in a way
@@ -53,30 +58,50 @@ struct Sto<double> {
 template <>
 struct Sto<float> {
     using C = double;
+    static constexpr bool kSplit = false;
     __device__ static inline double ld(float v) { return (double)v; }
     __device__ static inline float st(double c) { return (float)c; }
+    __device__ static inline bool marked(float) { return false; }
+    __device__ static inline float mark() { return 0.0f; }
 };
+// Half and bfloat16 storage: the populations of a fluid node next to a solid
+// (or a wall row) are kept in FP32, because the momentum the links exchange
+// is formed from them and the slow flow next to the surface does not carry
+// their rounding away (in a CPU emulation of the periodic single-cylinder
+// run, rounding only these nodes to 16 bits gives the whole drag error of
+// 16-bit storage; keeping them in FP32 leaves that of the FP32 arithmetic).
+// Such a node's 16-bit slots hold a marker, a signalling-NaN pattern that no
+// conversion of a computed value produces (conversions return quiet NaNs),
+// and the FP32 value sits in a float array beside the population buffer at
+// the same element index.
+constexpr uint16_t kMarkF16 = 0x7c01;   // exponent all ones, quiet bit clear
+constexpr uint16_t kMarkBF16 = 0x7f81;  // the same for bfloat16
 template <>
 struct Sto<_Float16> {
     using C = float;
+    static constexpr bool kSplit = true;
     __device__ static inline float ld(_Float16 v) { return (float)v; }
     // hardware conversion rounds to nearest even; subnormals are kept
     __device__ static inline _Float16 st(float c) { return (_Float16)c; }
+    __device__ static inline bool marked(_Float16 v) { return __builtin_bit_cast(uint16_t, v) == kMarkF16; }
+    __device__ static inline _Float16 mark() { return __builtin_bit_cast(_Float16, kMarkF16); }
 };
 template <>
 struct Sto<bf16_t> {
     using C = float;
-    __device__ static inline float ld(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
-    // round to nearest even on the upper 16 bits; NaN stays NaN
-    __device__ static inline bf16_t st(float c) {
-        uint32_t u = __float_as_uint(c);
+    static constexpr bool kSplit = true;
+    __device__ static inline bool marked(bf16_t v) { return v.bits == kMarkBF16; }
+    __device__ static inline bf16_t mark() {
         bf16_t r;
-        if ((u & 0x7fffffffu) > 0x7f800000u) {
-            r.bits = (uint16_t)((u >> 16) | 0x40u);
-        } else {
-            u += 0x7fffu + ((u >> 16) & 1u);
-            r.bits = (uint16_t)(u >> 16);
-        }
+        r.bits = kMarkBF16;
+        return r;
+    }
+    __device__ static inline float ld(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+    // the hardware conversion (v_cvt_pk_bf16_f32 on gfx950) rounds to
+    // nearest even and returns quiet NaNs
+    __device__ static inline bf16_t st(float c) {
+        bf16_t r;
+        r.bits = __builtin_bit_cast(uint16_t, (__bf16)c);
         return r;
     }
 };
@@ -136,8 +161,9 @@ __device__ inline C relax_one(int i, C di, const Moments<C>& m, const CollidePar
 // the rest direction keeps (1 - omega) d_0 + w_0 z.  Half the arithmetic of
 // nine independent relax_one calls.
 template <typename C>
-__device__ inline void collide(C d[9], const CollideParams<C>& p) {
+__device__ inline void collide(C d[9], const CollideParams<C>& p, Moments<C>* mo_out = nullptr) {
     const Moments<C> m = moments<C>(d, p);
+    if (mo_out) *mo_out = m;
     const C om = p.omega, keep = C(1) - p.omega;
     const C Fx = m.rho * p.gx, Fy = m.rho * p.gy;
     const C uu = m.ux * m.ux + m.uy * m.uy;
@@ -172,8 +198,9 @@ __device__ inline void collide(C d[9], const CollideParams<C>& p) {
 // and drops out of m - m_eq.  The rows of M are orthogonal with squared
 // norms (9, 36, 36, 6, 12, 6, 12, 4, 4), so M^-1 = M^T diag(1 / norms).
 template <typename C>
-__device__ inline void collide_mrt(C d[9], const CollideParams<C>& p) {
+__device__ inline void collide_mrt(C d[9], const CollideParams<C>& p, Moments<C>* mo_out = nullptr) {
     const Moments<C> mo = moments<C>(d, p);
+    if (mo_out) *mo_out = mo;
     const C drho = mo.drho, rho = mo.rho, ux = mo.ux, uy = mo.uy;
     const C s14 = (d[1] + d[2]) + (d[3] + d[4]);
     const C s58 = (d[5] + d[6]) + (d[7] + d[8]);

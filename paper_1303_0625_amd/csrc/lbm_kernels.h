@@ -38,31 +38,102 @@ struct StepArgs {
     int walls;
     double rho0;
     int ibb = 0;       // interpolated bounce-back on body links
+    // 16-bit storage: bytes from the start of a population buffer to its
+    // float array of FP32 populations of the nodes next to a solid (the same
+    // for both buffers; element e of a buffer <-> float element e there),
+    // and to its reference table (kSeg floats of the reference equilibrium per
+    // kRefNodes-node row segment, nseg segments per row)
+    int64_t side_off = 0;
+    int64_t ref_off = 0;
+    int nseg = 0;
 };
 
-// ------------------------------------------------------------------ pull
-// Post-advection deviation of direction i at node (x, y) from the
-// post-collision buffer: the value streaming in from x - e_i, or, when that
-// node is solid in G_t (or is a wall row), the half-way bounce-back of the
-// node's own opposite population plus 6 w_i rho0 (e_i . v_solid).
-template <typename T, typename C>
-__device__ inline C pull_one(const T* __restrict__ f, const uint8_t* __restrict__ own,
-                             const double* __restrict__ vtab, const StepArgs& a, int x, int y,
-                             int i) {
-    int xs = x - ex_(i), ys = y - ey_(i);
-    xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
-    int sid;
-    if (a.walls && (ys < 0 || ys >= a.ny)) {
-        sid = 0;
-    } else {
-        ys = ys < 0 ? ys + a.ny : (ys >= a.ny ? ys - a.ny : ys);
-        int o = own[(int64_t)ys * a.opitch + xs];
-        if (o == 0) return Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)ys * a.ystride + xs]);
-        sid = o;
+// ------------------------------------------------------------------ split storage
+// 16-bit storage keeps the FP32 arithmetic's result on two scales.  The
+// populations of a node next to a solid are kept in FP32 (their 16-bit
+// slots hold the storage type's marker).  Every other node stores, per
+// direction, its deviation from a reference equilibrium of its 16-node row
+// segment, w_i (drho_s + 3 e_i . u_s) with (drho_s, u_s) the segment's mean
+// density deviation and Guo velocity, written by the segment's update beside
+// the populations; rounding then acts on the departure from the local flow,
+// not on the flow itself (round to nearest even of f_i - w_i rho0 biases the
+// momentum of a slowly accelerating flow by ~1e-2 over thousands of steps).
+constexpr int kRefShift = 4;            // 16 nodes per reference segment
+constexpr int kRefNodes = 1 << kRefShift;
+constexpr int kSeg = 9;                 // floats per segment: the nine r_i
+
+template <typename T>
+__device__ inline const float* side_of(const T* base, int64_t side_off) {
+    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + side_off);
+}
+template <typename T>
+__device__ inline float* side_of(T* base, int64_t side_off) {
+    return reinterpret_cast<float*>(reinterpret_cast<char*>(base) + side_off);
+}
+// reference of direction i for node (x, y): table[(y nseg + x / 16) 9 + i]
+__device__ inline int64_t ref_index(int nseg, int i, int x, int y) {
+    return ((int64_t)y * nseg + (x >> kRefShift)) * kSeg + i;
+}
+
+// Deviation f_i - w_i rho0 of direction i at node (x, y) of the population
+// buffer base (A: any argument block with istride, ystride, side_off, ref_off
+// and nseg).
+template <typename T, typename A>
+__device__ inline typename Sto<T>::C pop_at(const T* base, const A& a, int i, int x, int y) {
+    using C = typename Sto<T>::C;
+    const int64_t e = (int64_t)i * a.istride + (int64_t)y * a.ystride + x;
+    const T v = base[e];
+    if constexpr (Sto<T>::kSplit) {
+        if (Sto<T>::marked(v)) return (C)side_of(base, a.side_off)[e];
+        return Sto<T>::ld(v) + (C)side_of(base, a.ref_off)[ref_index(a.nseg, i, x, y)];
     }
-    C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-    C m = C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
-    return Sto<T>::ld(f[(int64_t)opp_(i) * a.istride + (int64_t)y * a.ystride + x]) + m;
+    return Sto<T>::ld(v);
+}
+
+// Store of a node next to a solid (any storage type; 16-bit storage keeps
+// it in FP32), direction i at (x, y).
+template <typename T, typename A>
+__device__ inline void st_near(T* base, const A& a, int i, int x, int y, typename Sto<T>::C v) {
+    const int64_t e = (int64_t)i * a.istride + (int64_t)y * a.ystride + x;
+    if constexpr (Sto<T>::kSplit) {
+        side_of(base, a.side_off)[e] = (float)v;
+        base[e] = Sto<T>::mark();
+    } else {
+        base[e] = Sto<T>::st(v);
+    }
+}
+
+// Sum of v over the 16 lanes of a DPP row (an aligned quarter of the wave),
+// the same in every lane: four rotate-and-add steps within the row, each
+// adding two partial sums of the same lanes (every lane of the row must be
+// active).
+__device__ inline float row16_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));  // ror 8
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));  // ror 4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xf, 0xf, false));  // ror 2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));  // ror 1
+    return v;
+}
+
+// The nine reference deviations w_i (drho + 3 e_i . u) of a segment.
+__device__ inline void ref_eq(float drho, float ux, float uy, float r[9]) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = w_<float>(i) * (drho + 3.0f * ((float)ex_(i) * ux + (float)ey_(i) * uy));
+}
+
+// A fluid node with a solid neighbour (or a wall row) in the owner map.
+__device__ inline bool next_to_solid(const uint8_t* __restrict__ own, const StepArgs& a, int x, int y) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        int xs = x + ex_(i), ys = y + ey_(i);
+        xs = xs < 0 ? xs + a.nx : (xs >= a.nx ? xs - a.nx : xs);
+        if (ys < 0 || ys >= a.ny) {
+            if (a.walls) return true;
+            ys = ys < 0 ? ys + a.ny : ys - a.ny;
+        }
+        if (own[(int64_t)ys * a.opitch + xs] != 0) return true;
+    }
+    return false;
 }
 
 // ------------------------------------------------------------------ step
@@ -124,7 +195,7 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
                                  const double* __restrict__ rtab, const SolidDev* __restrict__ sol, int64_t t,
                                  const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp,
-                                 const BndSolid* bs = nullptr);
+                                 const BndSolid* bs = nullptr, bool lane_ok = true);
 
 template <typename T, bool NT, bool MRT, bool GEO>
 __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restrict__ fin,
@@ -138,8 +209,11 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
     const uint32_t gw = b * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int y = (int)(gw / wpr);
     const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
-    if (y >= a.ny || x >= a.nx) return;
-    step_node<T, NT, MRT, GEO>(x, y, fin, fout, own_t, vtab, rtab, sol, t, a, cp);
+    if (y >= a.ny) return;
+    if constexpr (!Sto<T>::kSplit) {
+        if (x >= a.nx) return;
+    }
+    step_node<T, NT, MRT, GEO>(x, y, fin, fout, own_t, vtab, rtab, sol, t, a, cp, nullptr, x < a.nx);
 }
 
 // The update of node (x, y): pull, bounce-back, collide (BGK, or MRT when
@@ -154,8 +228,15 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
                                  const double* __restrict__ rtab, const SolidDev* __restrict__ sol, int64_t t,
                                  const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp,
-                                 const BndSolid* bs) {
+                                 const BndSolid* bs, bool lane_ok) {
     using C = typename Sto<T>::C;
+    // 16-bit storage outside the boundary role: the nodes of each 16-node row
+    // segment store against their segment's reference equilibrium, which the
+    // segment's lanes form together, so every lane (also a solid one, or one
+    // past the row's end with lane_ok false) stays to the end
+    constexpr bool kSeg16 = Sto<T>::kSplit && !BND;
+    const int xr = x;  // the lane's own column (reference table slot)
+    if (!lane_ok) x = a.nx - 1;  // addresses stay in the lattice
 
     const int xm = x == 0 ? a.nx - 1 : x - 1;
     const int xp = x == a.nx - 1 ? 0 : x + 1;
@@ -197,6 +278,29 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
     raw[6] = ld_stream<NT>(row_at(rm + 6 * P, uxp));
     raw[7] = ld_stream<NT>(row_at(rp + 7 * P, uxp));
     raw[8] = ld_stream<NT>(row_at(rp + 8 * P, uxm));
+    // 16-bit storage: the reference of each source's segment, loaded with the
+    // populations (a segment's lanes read the same words)
+    C rr[9];
+    // row bases of the table (wave-uniform) and 32-bit segment offsets
+    const float* Rr0 = nullptr;
+    uint32_t u0 = 0;
+    if constexpr (Sto<T>::kSplit) {
+        const float* R = side_of(fin, a.ref_off);
+        Rr0 = R + (int64_t)y * a.nseg * kSeg;
+        const float* Rrm = R + (int64_t)ym * a.nseg * kSeg;
+        const float* Rrp = R + (int64_t)yp * a.nseg * kSeg;
+        u0 = (uint32_t)(x >> kRefShift) * kSeg;
+        const uint32_t um = (uint32_t)(xm >> kRefShift) * kSeg, uq = (uint32_t)(xp >> kRefShift) * kSeg;
+        rr[0] = (C)*row_at(Rr0 + 0, u0);
+        rr[1] = (C)*row_at(Rr0 + 1, um);
+        rr[2] = (C)*row_at(Rrm + 2, u0);
+        rr[3] = (C)*row_at(Rr0 + 3, uq);
+        rr[4] = (C)*row_at(Rrp + 4, u0);
+        rr[5] = (C)*row_at(Rrm + 5, um);
+        rr[6] = (C)*row_at(Rrm + 6, uq);
+        rr[7] = (C)*row_at(Rrp + 7, uq);
+        rr[8] = (C)*row_at(Rrp + 8, um);
+    }
     // boundary role: the node's own populations, which the interpolated rule
     // takes, are loaded with the streamed ones
     T own9[9];
@@ -204,79 +308,182 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
 #pragma unroll
         for (int i = 1; i < 9; ++i) own9[i] = ld_stream<NT>(row_at(r0 + i * P, ux));
     }
-    if (self) return;  // solid at t (a newborn node is refilled by the mover role)
-    if constexpr (GEO && !BND)
-        if (a.ibb && (s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0) return;  // boundary role
+    const bool near = (s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0 || wall_lo || wall_hi;
+    // solid at t (a newborn node is refilled by the mover role), or left to
+    // the boundary role
+    bool live = self == 0u;
+    if constexpr (GEO && !BND) live = live && !(a.ibb && (s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0);
+    if constexpr (!kSeg16) {
+        if (!live) return;
+    } else {
+        live = live && lane_ok;
+    }
+    // element offsets of the rows y, y - 1, y + 1 (FP32 copies of 16-bit storage)
+    const int64_t e0 = (int64_t)y * a.ystride, em = (int64_t)ym * a.ystride, ep = (int64_t)yp * a.ystride;
     C d[9];
+    Moments<C> mo{};
+    if (live) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
-    if ((s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0 || wall_lo || wall_hi) {
-        // half-way bounce-back for the directions whose source is solid or a
-        // wall row: the node's own opposite population plus the moving-wall
-        // term; the loads are independent and issue together
-        const uint32_t src[9] = {0u, s1, s2, s3, s4, s5, s6, s7, s8};
+        for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
+        if constexpr (Sto<T>::kSplit) {
 #pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const bool wall = (ey_(i) == 1 && wall_lo) || (ey_(i) == -1 && wall_hi);
-            const uint32_t sid = wall ? 0u : src[i];
-            if (wall || sid != 0u) {
-                C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
-                if constexpr (GEO && !BND) {
-                    const double om = rtab[kRot * sid];
-                    if (om != 0.0) {
-                        const double rx = min_image((double)x - 0.5 * ex_(i) - rtab[kRot * sid + 1], a.nx);
-                        double ry = (double)y - 0.5 * ey_(i) - rtab[kRot * sid + 2];
-                        if (!a.walls) ry = min_image(ry, a.ny);
-                        vx = (C)((double)vtab[2 * sid] - om * ry);
-                        vy = (C)((double)vtab[2 * sid + 1] + om * rx);
-                    }
-                }
-                if constexpr (BND) {
-                    if (sid != 0u) {
-                        double X = bs->X, Y = bs->Y, om = bs->om;
-                        const SolidDev* B = &bs->S;
-                        if ((int)sid != bs->s) {
-                            solid_centre(sol, rtab, (int)sid, t, X, Y);
-                            om = rtab[kRot * sid];
-                            B = &sol[sid];
-                        }
-                        const double q = a.ibb ? link_fraction(*B, X, Y, x, y, -ex_(i), -ey_(i), a.nx, a.ny,
-                                                               a.walls)
-                                               : 0.5;
+            for (int i = 0; i < 9; ++i) d[i] += rr[i];
+            // a source next to a solid holds its FP32 populations in the side array
+            const bool m0 = Sto<T>::marked(raw[0]), m1 = Sto<T>::marked(raw[1]), m2 = Sto<T>::marked(raw[2]);
+            const bool m3 = Sto<T>::marked(raw[3]), m4 = Sto<T>::marked(raw[4]), m5 = Sto<T>::marked(raw[5]);
+            const bool m6 = Sto<T>::marked(raw[6]), m7 = Sto<T>::marked(raw[7]), m8 = Sto<T>::marked(raw[8]);
+            if (m0 | m1 | m2 | m3 | m4 | m5 | m6 | m7 | m8) {
+                const float* sd = side_of(fin, a.side_off);
+                if (m0) d[0] = (C)sd[e0 + x];
+                if (m1) d[1] = (C)sd[e0 + P + xm];
+                if (m2) d[2] = (C)sd[em + 2 * P + x];
+                if (m3) d[3] = (C)sd[e0 + 3 * P + xp];
+                if (m4) d[4] = (C)sd[ep + 4 * P + x];
+                if (m5) d[5] = (C)sd[em + 5 * P + xm];
+                if (m6) d[6] = (C)sd[em + 6 * P + xp];
+                if (m7) d[7] = (C)sd[ep + 7 * P + xp];
+                if (m8) d[8] = (C)sd[ep + 8 * P + xm];
+            }
+        }
+        // the node's own population of direction j (bounce-back, interpolated rule)
+        auto own_pop = [&](T v, int j) -> C {
+            if constexpr (Sto<T>::kSplit) {
+                if (Sto<T>::marked(v)) return (C)side_of(fin, a.side_off)[e0 + j * P + x];
+                return Sto<T>::ld(v) + (C)*row_at(Rr0 + j, u0);
+            }
+            return Sto<T>::ld(v);
+        };
+        if (near) {
+            // half-way bounce-back for the directions whose source is solid or a
+            // wall row: the node's own opposite population plus the moving-wall
+            // term; the loads are independent and issue together
+            const uint32_t src[9] = {0u, s1, s2, s3, s4, s5, s6, s7, s8};
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const bool wall = (ey_(i) == 1 && wall_lo) || (ey_(i) == -1 && wall_hi);
+                const uint32_t sid = wall ? 0u : src[i];
+                if (wall || sid != 0u) {
+                    C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                    if constexpr (GEO && !BND) {
+                        const double om = rtab[kRot * sid];
                         if (om != 0.0) {
-                            const double rx = min_image((double)x - q * ex_(i) - X, a.nx);
-                            double ry = (double)y - q * ey_(i) - Y;
+                            const double rx = min_image((double)x - 0.5 * ex_(i) - rtab[kRot * sid + 1], a.nx);
+                            double ry = (double)y - 0.5 * ey_(i) - rtab[kRot * sid + 2];
                             if (!a.walls) ry = min_image(ry, a.ny);
                             vx = (C)((double)vtab[2 * sid] - om * ry);
                             vy = (C)((double)vtab[2 * sid + 1] + om * rx);
                         }
-                        const C m = C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
-                        // the node behind, x + e_i, is the source of the
-                        // opposite direction o; when it is fluid, d[o] still
-                        // holds the value streamed from it (only directions
-                        // with a solid or wall source are replaced)
-                        const int o = opp_(i);
-                        const bool owall = (ey_(o) == 1 && wall_lo) || (ey_(o) == -1 && wall_hi);
-                        const bool behind = !owall && src[o] == 0u;
-                        d[i] = ibb_value<C>(q, Sto<T>::ld(own9[o]), Sto<T>::ld(own9[i]), d[o], behind, m);
-                        continue;
                     }
+                    if constexpr (BND) {
+                        if (sid != 0u) {
+                            double X = bs->X, Y = bs->Y, om = bs->om;
+                            const SolidDev* B = &bs->S;
+                            if ((int)sid != bs->s) {
+                                solid_centre(sol, rtab, (int)sid, t, X, Y);
+                                om = rtab[kRot * sid];
+                                B = &sol[sid];
+                            }
+                            const double q = a.ibb ? link_fraction(*B, X, Y, x, y, -ex_(i), -ey_(i), a.nx, a.ny,
+                                                                   a.walls)
+                                                   : 0.5;
+                            if (om != 0.0) {
+                                const double rx = min_image((double)x - q * ex_(i) - X, a.nx);
+                                double ry = (double)y - q * ey_(i) - Y;
+                                if (!a.walls) ry = min_image(ry, a.ny);
+                                vx = (C)((double)vtab[2 * sid] - om * ry);
+                                vy = (C)((double)vtab[2 * sid + 1] + om * rx);
+                            }
+                            const C m = C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
+                            // the node behind, x + e_i, is the source of the
+                            // opposite direction o; when it is fluid, d[o] still
+                            // holds the value streamed from it (only directions
+                            // with a solid or wall source are replaced)
+                            const int o = opp_(i);
+                            const bool owall = (ey_(o) == 1 && wall_lo) || (ey_(o) == -1 && wall_hi);
+                            const bool behind = !owall && src[o] == 0u;
+                            d[i] = ibb_value<C>(q, own_pop(own9[o], o), own_pop(own9[i], i), d[o], behind, m);
+                            continue;
+                        }
+                    }
+                    d[i] = own_pop(*row_at(r0 + opp_(i) * P, ux), opp_(i)) +
+                           C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
                 }
-                d[i] = Sto<T>::ld(*row_at(r0 + opp_(i) * P, ux)) +
-                       C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
             }
         }
+        if constexpr (MRT)
+            collide_mrt<C>(d, cp, &mo);
+        else
+            collide<C>(d, cp, &mo);
     }
-    if constexpr (MRT)
-        collide_mrt<C>(d, cp);
-    else
-        collide<C>(d, cp);
     T* w0 = fout + (int64_t)y * a.ystride;
+    if constexpr (kSeg16) {
+        // the segment's reference: w_i (drho_s + 3 e_i . u_s) from the means
+        // over its live nodes (16 lanes, an aligned quarter of the wave)
+        const float sr = row16_sum(live ? (float)mo.drho : 0.0f);
+        const float sx = row16_sum(live ? (float)mo.ux : 0.0f);
+        const float sy = row16_sum(live ? (float)mo.uy : 0.0f);
+        const int lane = (int)(threadIdx.x & 63);
+        const uint64_t bl = __ballot(live);
+        const int cnt = __popcll((bl >> (lane & ~(kRefNodes - 1))) & ((1ull << kRefNodes) - 1));
+        const float inv = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
+        float r[9];
+        ref_eq(sr * inv, sx * inv, sy * inv, r);
+        // lanes 0..8 of the segment record it for the readers of the next step
+        const int j = xr & (kRefNodes - 1);
+        if (j < kSeg) {
+            float rj = r[0];
+#pragma unroll
+            for (int k = 1; k < 9; ++k) rj = j == k ? r[k] : rj;
+            side_of(fout, a.ref_off)[((int64_t)y * a.nseg + (xr >> kRefShift)) * kSeg + j] = rj;
+        }
+        if (!live) return;
+        // a node next to a solid keeps its populations in FP32
+        if (near) {
+            float* sw = side_of(fout, a.side_off) + e0 + x;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) sw[i * P] = (float)d[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            st_stream<NT>(row_at(w0 + i * P, ux), near ? Sto<T>::mark() : Sto<T>::st(d[i] - (C)r[i]));
+        return;
+    } else if constexpr (Sto<T>::kSplit) {
+        // the boundary role's nodes are next to a body: FP32
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_near<T>(fout, a, i, x, y, d[i]);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) st_stream<NT>(row_at(w0 + i * P, ux), Sto<T>::st(d[i]));
 }
 
 // ------------------------------------------------------------------ init
+// Store of an initial state: a node next to a solid through st_near, every
+// other one as its plain deviation (the reference table of the buffer, zeroed
+// by ref_zero, holds no reference yet).
+template <typename T>
+__device__ inline void st_init(T* f, const uint8_t* own, const StepArgs& a, int x, int y,
+                               const typename Sto<T>::C d[9]) {
+    const bool near = Sto<T>::kSplit && next_to_solid(own, a, x, y);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if (near)
+            st_near<T>(f, a, i, x, y, d[i]);
+        else
+            f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x] = Sto<T>::st(d[i]);
+    }
+}
+
+// 16-bit storage: node (x, y) of a row (x < rowlen) zeroes its share of the
+// buffer's reference table.
+template <typename T>
+__device__ inline void ref_zero(T* f, const StepArgs& a, int x, int y) {
+    if constexpr (Sto<T>::kSplit) {
+        const int j = x & (kRefNodes - 1);
+        if (j < kSeg) side_of(f, a.ref_off)[ref_index(a.nseg, j, x, y)] = 0.0f;
+    }
+}
+
 // f = f_eq(rho, u) at every fluid node (uniform rho0, u0 when the field
 // pointers are NULL; otherwise u - g/2 from the fields so that the Guo
 // velocity is u), collided once.  Solid nodes are zeroed.
@@ -290,7 +497,9 @@ __global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int y = (int)(idx / a.rowlen);
     const int x = (int)(idx - (int64_t)y * a.rowlen);
-    if (y >= a.ny || x >= a.nx) return;
+    if (y >= a.ny) return;
+    ref_zero<T>(f, a, x, y);
+    if (x >= a.nx) return;
     T* w0 = f + (int64_t)y * a.ystride + x;
     if (own[(int64_t)y * a.opitch + x] != 0) {
 #pragma unroll
@@ -305,8 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_init(T* __restrict__ f, const uint8_
         feq_dev<C>((C)rho[n], (C)a.rho0, (C)ux[n] - C(0.5) * cp.gx, (C)uy[n] - C(0.5) * cp.gy, d);
     }
     collide_any<C>(d, cp);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(d[i]);
+    st_init<T>(f, own, a, x, y, d);
 }
 
 // f = f_eq(rho0, u_P(y) - g/2), collided once, at every fluid node: the exact
@@ -323,7 +531,9 @@ __global__ __launch_bounds__(kBlock) void k_init_poiseuille(T* __restrict__ f, c
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int y = (int)(idx / a.rowlen);
     const int x = (int)(idx - (int64_t)y * a.rowlen);
-    if (y >= a.ny || x >= a.nx) return;
+    if (y >= a.ny) return;
+    ref_zero<T>(f, a, x, y);
+    if (x >= a.nx) return;
     T* w0 = f + (int64_t)y * a.ystride + x;
     if (own[(int64_t)y * a.opitch + x] != 0) {
 #pragma unroll
@@ -340,8 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_init_poiseuille(T* __restrict__ f, c
     C d[9];
     feq_dev<C>((C)a.rho0, (C)a.rho0, (C)(u - 0.5 * gx), (C)(-0.5 * (double)cp.gy), d);
     collide_any<C>(d, cp);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) w0[i * a.istride] = Sto<T>::st(d[i]);
+    st_init<T>(f, own, a, x, y, d);
 }
 
 // ------------------------------------------------------------------ fields
@@ -365,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_fields(const T* __restrict__ f,
     if (o == 0) {
         double d[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = (double)Sto<T>::ld(f[i * a.istride + (int64_t)y * a.ystride + x]);
+        for (int i = 0; i < 9; ++i) d[i] = (double)pop_at(f, a, i, x, y);
         double drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
         r = a.rho0 + drho;
         double jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
@@ -393,8 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_populations(const T* __restrict__ f,
     const int64_t nn = (int64_t)a.nx * a.ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        double v = fl ? w_<double>(i) * a.rho0 + (double)Sto<T>::ld(f[i * a.istride + (int64_t)y * a.ystride + x])
-                      : 0.0;
+        double v = fl ? w_<double>(i) * a.rho0 + (double)pop_at(f, a, i, x, y) : 0.0;
         out[i * nn + (int64_t)y * a.nx + x] = v;
     }
 }
@@ -576,6 +784,9 @@ struct MoveArgs {
     int box_bytes;  // capacity of each LDS byte map
     int n_movers;   // translating bodies (mover workgroups: 2 n_movers)
     int ibb = 0;    // interpolated bounce-back on body links
+    int64_t side_off = 0;  // 16-bit storage: FP32 side array and reference
+    int64_t ref_off = 0;   // table (as in StepArgs)
+    int nseg = 0;
 };
 
 // Bounding range of the body centred at (Xa, Ya) (step t - 1) and at
@@ -839,7 +1050,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                 // surface point gx - q e_j of a body link (q = 1/2 unless
                 // interpolated), step t; a spinning free body moves there at
                 // V + Omega z x (point - centre)
-                const C fo = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)gy * a.ystride + gx]);
+                const C fo = pop_at(fin, a, opp_(j), gx, gy);
                 double q = 0.5;
                 C fi = C(0), fb = C(0);
                 bool behind = false;
@@ -850,12 +1061,12 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                         // the opposite one of the node behind, gx + e_j (in
                         // the box: at most 4 nodes from the newborn node, like
                         // the sources)
-                        fi = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx]);
+                        fi = pop_at(fin, a, j, gx, gy);
                         const int qb = qm + (ey_(j) * W + ex_(j));
                         int bx, by;
                         behind = ot[qb] == 0 && gidx(qb, bx, by);
                         if (behind)
-                            fb = Sto<T>::ld(fin[(int64_t)opp_(j) * a.istride + (int64_t)by * a.ystride + bx]);
+                            fb = pop_at(fin, a, opp_(j), bx, by);
                     }
                     // this body's record and centre are at hand; another
                     // body's come from the tables
@@ -880,7 +1091,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
             } else {
                 int sx, sy;
                 gidx(qs, sx, sy);
-                v = Sto<T>::ld(fin[(int64_t)j * a.istride + (int64_t)sy * a.ystride + sx]);
+                v = pop_at(fin, a, j, sx, sy);
             }
             sm.nb_val[bb][k - 1][mm - 1][j] = v;
         }
@@ -933,7 +1144,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
                 const int bb = threadIdx.x / 9, j = threadIdx.x % 9;
                 int gx, gy;
                 gidx(sm.nb_list[base + bb], gx, gy);
-                fout[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx] = Sto<T>::st(sm.nb_new[bb][j]);
+                st_near<T>(fout, a, j, gx, gy, sm.nb_new[bb][j]);
             }
             __syncthreads();
             continue;
@@ -956,7 +1167,7 @@ __device__ inline void move_role(int m, uint8_t* __restrict__ lds, MoveShared<T>
             const C dj = relax_one<C>(j, sm.nb_new[bb][j], mo, cp);
             int gx, gy;
             gidx(sm.nb_list[base + bb], gx, gy);
-            fout[(int64_t)j * a.istride + (int64_t)gy * a.ystride + gx] = Sto<T>::st(dj);
+            st_near<T>(fout, a, j, gx, gy, dj);
         }
         __syncthreads();
     }
@@ -974,6 +1185,9 @@ struct ForceArgs {
     int nchunks;  // force workgroups
     int opitch = 0;  // bytes per owner-map row
     int ibb = 0;     // interpolated bounce-back on body links
+    int64_t side_off = 0;  // 16-bit storage: FP32 side array and reference
+    int64_t ref_off = 0;   // table (as in StepArgs)
+    int nseg = 0;
 };
 
 // One fluid-solid link (x_f, i) of solid s, in FP64 on full populations:
@@ -1004,7 +1218,7 @@ __device__ inline LinkEval eval_link(const T* __restrict__ f, const uint8_t* __r
     }
     L.vx = vbx - om * L.ry;
     L.vy = vby + om * L.rx;
-    L.av = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)y * a.ystride + x]);
+    L.av = w * a.rho0 + (double)pop_at(f, a, i, x, y);
     const double m = 6.0 * w * a.rho0 * (ex * L.vx + ey * L.vy);
     L.bv = L.av - m;
     if constexpr (!GEO) return L;
@@ -1018,11 +1232,11 @@ __device__ inline LinkEval eval_link(const T* __restrict__ f, const uint8_t* __r
         else
             yb = yb < 0 ? yb + a.ny : (yb >= a.ny ? yb - a.ny : yb);
         if (ok && own_t[(int64_t)yb * a.opitch + xb] == 0) {
-            const double fb = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)i * a.istride + (int64_t)yb * a.ystride + xb]);
+            const double fb = w * a.rho0 + (double)pop_at(f, a, i, xb, yb);
             L.bv = 2.0 * q * L.av + (1.0 - 2.0 * q) * fb - m;
         }
     } else if (q > 0.5) {
-        const double fo = w * a.rho0 + (double)Sto<T>::ld(f[(int64_t)opp_(i) * a.istride + (int64_t)y * a.ystride + x]);
+        const double fo = w * a.rho0 + (double)pop_at(f, a, opp_(i), x, y);
         const double h = 0.5 / q;
         L.bv = h * (L.av - m) + (1.0 - h) * fo;
     }

@@ -909,6 +909,25 @@ lbm_status lbm_warm_project(int32_t nx, int32_t ny, int32_t n_fields, const uint
     return LBM_OK;
 }
 
+lbm_status lbm_warm_check(int32_t nx, int32_t ny, int32_t n_fields, const uint8_t* d_owner, const float* d_rho,
+                          const float* d_ux, const float* d_uy, double rho0, double u_max, int32_t* d_ok,
+                          void* hip_stream) {
+    if (nx < 1 || ny < 1 || n_fields < 1 || !d_owner || !d_rho || !d_ux || !d_uy || !d_ok || !(rho0 > 0.0) ||
+        !(u_max > 0.0)) {
+        nn_set_err(g_nn_err, "sizes must be >= 1, pointers non-NULL, rho0 and u_max > 0");
+        return LBM_EINVAL;
+    }
+    const hipStream_t st = (hipStream_t)hip_stream;
+    k_fill_i32<<<blocks(n_fields), kEw, 0, st>>>(d_ok, n_fields, 1);
+    k_warm_check<<<n_fields, kEw, 0, st>>>(d_owner, d_rho, d_ux, d_uy, nx, ny, rho0, u_max, d_ok);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        nn_set_err(g_nn_err, "start check launch failed: %s", hipGetErrorString(e));
+        return LBM_EDEVICE;
+    }
+    return LBM_OK;
+}
+
 void lbm_nn_destroy(lbm_nn* n) {
     if (!n) return;
     (void)hipStreamSynchronize(n->st);

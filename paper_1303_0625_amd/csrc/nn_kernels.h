@@ -1162,6 +1162,32 @@ __global__ __launch_bounds__(kEw) void k_unpack_fields(const float* __restrict__
 // in a fixed order.
 constexpr int kProjMax = 2048;  // largest nx and ny of a projected field (LDS: 52 KB)
 
+__global__ __launch_bounds__(kEw) void k_fill_i32(int* __restrict__ p, int64_t n, int v) {
+    const int64_t q = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    if (q < n) p[q] = v;
+}
+
+// Start check of warm fields: workgroup k clears ok[k] when a fluid node of
+// field set k has a density that is not finite or outside (0, 2 rho0), or a
+// velocity that is not finite or of magnitude above u_max (the flag is set
+// to 1 first by the host).
+__global__ __launch_bounds__(kEw) void k_warm_check(const uint8_t* __restrict__ own,
+                                                    const float* __restrict__ rho, const float* __restrict__ ux,
+                                                    const float* __restrict__ uy, int nx, int ny, double rho0,
+                                                    double u_max, int* __restrict__ ok) {
+    const int k = blockIdx.x;
+    const int64_t n = (int64_t)nx * ny, base = (int64_t)k * n;
+    bool bad = false;
+    for (int64_t q = threadIdx.x; q < n; q += kEw) {
+        if (own[base + q] != 0) continue;
+        const double r = rho[base + q], u = ux[base + q], v = uy[base + q];
+        const double uu = u * u + v * v;
+        // comparisons written so that NaN fails them
+        if (!(r > 0.0 && r < 2.0 * rho0) || !(uu <= u_max * u_max)) bad = true;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) ok[k] = 0;
+}
+
 // a = (a + b) / 2 elementwise (the mean of the fields of two consecutive
 // steps: modes that change sign every step cancel, slowly varying ones stay).
 __global__ __launch_bounds__(kEw) void k_average(float* __restrict__ a, const float* __restrict__ b, int64_t n) {

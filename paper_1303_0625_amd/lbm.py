@@ -136,6 +136,7 @@ _SIG = {
                            ctypes.POINTER(ctypes.c_double)]),
     "lbm_nn_infer": (_I32, [_VP, _VP, _VP, _VP, _VP, _I32, _VP, _VP, _VP]),
     "lbm_warm_project": (_I32, [_I32, _I32, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP]),
+    "lbm_warm_check": (_I32, [_I32, _I32, _I32, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, _VP, _VP]),
     "lbm_nn_destroy": (None, [_VP]),
     "lbm_nn_last_error": (ctypes.c_char_p, [_VP]),
     "lbm3d_workspace_bytes": (_I32, [ctypes.POINTER(lbm3d_grid), ctypes.POINTER(lbm3d_sphere), _I32, _I64,
@@ -519,6 +520,28 @@ def warm_project(owner, rho, ux, uy, rho0=1.0, second=None):
                      torch.cuda.current_stream(rho.device).cuda_stream)
 
 
+def lbm_warm_check(nx: int, ny: int, n_fields: int, d_owner, d_rho, d_ux, d_uy, rho0: float, u_max: float,
+                   d_ok, hip_stream) -> None:
+    _ncheck(load_library().lbm_warm_check(nx, ny, n_fields, d_owner, d_rho, d_ux, d_uy, rho0, u_max, d_ok,
+                                          hip_stream), None)
+
+
+def warm_check(owner, rho, ux, uy, rho0=1.0, u_max=0.3):
+    """Per channel, whether warm-start fields (torch CUDA tensors [n][ny][nx]:
+    owner uint8, rho/ux/uy float32) are safe to start from: int32 tensor [n],
+    1 when every fluid node has a finite density in (0, 2 rho0) and a finite
+    speed <= u_max."""
+    import torch
+
+    for t in (owner, rho, ux, uy):
+        assert t.is_contiguous() and t.is_cuda
+    n, ny, nx = rho.shape
+    ok = torch.empty(n, dtype=torch.int32, device=rho.device)
+    lbm_warm_check(nx, ny, n, owner.data_ptr(), rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), rho0, u_max,
+                   ok.data_ptr(), torch.cuda.current_stream(rho.device).cuda_stream)
+    return ok
+
+
 def lbm_nn_destroy(n) -> None:
     load_library().lbm_nn_destroy(n)
 
@@ -587,12 +610,12 @@ class Lattice:
             history_steps = max(1, int(case.get("steps", 0)) or 1024)
         self.history_steps = int(history_steps)
         solids = case.get("bodies", ())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._destroy = load_library().lbm_destroy  # usable at interpreter exit
         nbytes = lbm_workspace_bytes(self.grid, solids, self.history_steps)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
-        self._destroy = load_library().lbm_destroy  # usable at interpreter exit
         self.ctx = lbm_create(self.grid, float(case["tau"]), solids, self.history_steps,
                               self._ws_ptr, nbytes, self.stream.cuda_stream)
         if mrt is not None:
@@ -791,6 +814,10 @@ class LatticeBatch:
         dt = LBM_F64 if rho.dtype == self.torch.float64 else LBM_F32
         rho, ux, uy = (a.contiguous() for a in (rho, ux, uy))
         lbm_batch_init_fields(self.b, case_id, rho.data_ptr(), ux.data_ptr(), uy.data_ptr(), dt)
+
+    def init_cold(self, case_id: int) -> None:
+        """Case case_id back to the cold start it was created with."""
+        lbm_batch_init_fields(self.b, case_id, None, None, None, LBM_F32)
 
 
 class WarmStartNet:

@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -51,7 +52,14 @@ def solve(batch, tol, check, cap, chunk=20000, log=_log, record=False, t0=None, 
             hist.append((time.perf_counter() - t0, step0 + batch.t, [d[0] for d in drag], list(res)))
         else:
             done = batch.run(min(chunk, cap - batch.t), tol, check)
-            conv = batch.status()[0]
+            conv, _, res, _ = batch.status()
+        # a start that diverged (its residual is no longer finite) falls back
+        # to the cold start
+        for k, r in enumerate(res):
+            if not conv[k] and not math.isfinite(r):
+                batch.init_cold(k)
+                getattr(batch, "fallback", set()).add(k)
+                log(f"  case {k}: residual not finite at step {batch.t}, restarted cold")
         if all(conv) or done == 0:
             break
         if time.perf_counter() - last > 20.0:
@@ -199,6 +207,7 @@ def start_batch(cases, kind, net=None, dtype="f32", project=True, fields=None, d
     import torch
 
     b = lbm.LatticeBatch(cases, dtype=dtype)
+    b.fallback = set()  # cases started cold instead (warm fields failed the start check)
     if kind == "cold":
         return b
     _init_warm(b, cases, kind, net, project, fields)
@@ -208,9 +217,17 @@ def start_batch(cases, kind, net=None, dtype="f32", project=True, fields=None, d
         b.step(1)
         f2 = all_fields(b, len(cases))
         own = torch.stack([b.fields(k, "f32", owner=True)[3] for k in range(len(cases))]).contiguous()
-        lbm.warm_project(own, *f1, rho0=float(cases[0].get("rho0", 1.0)), second=f2)
+        rho0 = float(cases[0].get("rho0", 1.0))
+        lbm.warm_project(own, *f1, rho0=rho0, second=f2)
+        ok = lbm.warm_check(own, *f1, rho0=rho0).cpu()
         for k in range(len(cases)):
-            b.init_fields(k, f1[0][k].contiguous(), f1[1][k].contiguous(), f1[2][k].contiguous())
+            if k in b.fallback:
+                continue  # a cold start needs no de-staggering
+            if ok[k]:
+                b.init_fields(k, f1[0][k].contiguous(), f1[1][k].contiguous(), f1[2][k].contiguous())
+            else:
+                b.init_cold(k)
+                b.fallback.add(k)
     torch.cuda.synchronize()
     return b
 
@@ -236,10 +253,17 @@ def _init_warm(b, cases, kind, net, project, fields):
             gx = torch.tensor([c["gx"] for c in part], dtype=torch.float64, device=dev)
             tau = torch.tensor([c["tau"] for c in part], dtype=torch.float64, device=dev)
             rho, ux, uy = net.infer((own != 0).to(torch.uint8).contiguous(), re, gx, tau)
+        rho0 = float(part[0].get("rho0", 1.0))
         if project:
-            lbm.warm_project(own, rho, ux, uy, rho0=float(part[0].get("rho0", 1.0)))
+            lbm.warm_project(own, rho, ux, uy, rho0=rho0)
+        # the cold start is the fallback of fields that are not safe to start from
+        ok = lbm.warm_check(own, rho, ux, uy, rho0=rho0).cpu()
         for j in range(len(part)):
-            b.init_fields(k0 + j, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
+            if ok[j]:
+                b.init_fields(k0 + j, rho[j].contiguous(), ux[j].contiguous(), uy[j].contiguous())
+            else:
+                b.init_cold(k0 + j)
+                b.fallback.add(k0 + j)
 
 
 def all_fields(b, n):

@@ -13,10 +13,11 @@ from __future__ import annotations
 import numpy as np
 
 
-def oracle_sim(oracle, c, mrt=None):
+def oracle_sim(oracle, c, mrt=None, omp=False):
+    """The oracle for case c; omp: its multi-threaded build (same results)."""
     return oracle.OracleSim(c["nx"], c["ny"], c["tau"], walls_y=c["walls_y"], rho0=c["rho0"],
                             gx=c["gx"], gy=c["gy"], u0=c["u0"], wall_v=c["wall_v"],
-                            refill=c["refill"], bodies=c["bodies"], mrt=mrt)
+                            refill=c["refill"], bodies=c["bodies"], mrt=mrt, omp=omp)
 
 
 def rel_field_err(gpu, ref, mask):

