@@ -112,27 +112,32 @@ def run_batch(lc, pkg, torch, steps):
             "timing": "wall clock around graph replays, monitor included"}
 
 
-def run_batch_converge(lc, pkg, torch, cap, chunk=50_000):
-    """The 256 uneven cases from a cold start, FP32, to r < 1e-8 (checks every
-    100 steps, graph-replayed intervals, autotuned tiling), at most `cap`
-    steps: converged fraction, steps at retirement per case, wall time.  A
-    progress line per chunk of steps."""
+def run_batch_converge(lc, pkg, torch, cap, start="cold", wall_cap=0.0, chunk=50_000):
+    """The 256 uneven cases, FP32, from a cold start or from the exact
+    Poiseuille channel flow, to r < 1e-8 (checks every 100 steps,
+    graph-replayed intervals, autotuned tiling), at most `cap` steps (and at
+    most `wall_cap` seconds when > 0, checked between chunks): converged
+    fraction, steps at retirement per case, wall time.  A progress line per
+    chunk of steps."""
     cases = lc.uneven_channels()
     b = pkg.LatticeBatch(cases, dtype="f32")
     b.autotune(None)
+    if start == "poiseuille":
+        for k in range(len(cases)):
+            b.init_poiseuille(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while b.t < cap:
         done = b.run(min(chunk, cap - b.t), 1e-8, 100)
         conv = b.status()[0]
         print(f"# step {b.t}: {sum(conv)}/{len(conv)} converged, {time.perf_counter() - t0:.0f} s", flush=True)
-        if all(conv) or done == 0:
+        if all(conv) or done == 0 or (wall_cap > 0 and time.perf_counter() - t0 > wall_cap):
             break
     wall = time.perf_counter() - t0
     conv, steps, res, _ = b.status()
     re = [c["Re"] for c in cases]
     nodes = [c["nx"] * c["ny"] for c in cases]
-    return {"cases": len(cases), "cap": cap, "converged": int(sum(conv)),
+    return {"cases": len(cases), "start": start, "cap": cap, "steps_run": int(b.t), "converged": int(sum(conv)),
             "converged_fraction": round(sum(conv) / len(conv), 4), "wall_s": round(wall, 1),
             "steps": [int(s) if c else None for s, c in zip(steps, conv)],
             "residual_at_end": [float(r) for r in res], "Re": re, "nodes": nodes,
@@ -333,6 +338,9 @@ def main() -> int:
     ap.add_argument("--only-c4", type=int, default=0, metavar="CAP",
                     help="run only the 256 uneven channel/cylinder cases (FP32, cold start) to r < 1e-8, "
                          "at most CAP steps; prints progress and the converged fraction and steps per case")
+    ap.add_argument("--c4-start", choices=("cold", "poiseuille"), default="cold")
+    ap.add_argument("--c4-wall", type=float, default=0.0, metavar="S",
+                    help="stop the --only-c4 run after S seconds (checked between chunks of steps)")
     ap.add_argument("--only-copy", type=int, default=0, metavar="MIB",
                     help="run only a plain device copy of MIB MiB, three times (the known-size "
                          "reference that scales the HBM traffic counters)")
@@ -367,7 +375,7 @@ def main() -> int:
         print(json.dumps(run_network(pkg)), flush=True)
         return 0
     if args.only_c4:
-        print(json.dumps(run_batch_converge(lc, pkg, torch, args.only_c4)), flush=True)
+        print(json.dumps(run_batch_converge(lc, pkg, torch, args.only_c4, args.c4_start, args.c4_wall)), flush=True)
         return 0
     big = lc.periodic_cylinders()
     if args.only_hbm_case:

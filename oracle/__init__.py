@@ -331,6 +331,7 @@ def _load3():
     lib.orc3_link_force.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, dp]
     lib.orc3_get_f.argtypes = [ctypes.c_void_p, dp]
     lib.orc3_set_f.argtypes = [ctypes.c_void_p, dp]
+    lib.orc3_get_ft.argtypes = [ctypes.c_void_p, dp]
     lib.orc3_set_moving.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.orc3_set_moving.restype = ctypes.c_int
     lib.orc3_error.argtypes = [ctypes.c_void_p]
@@ -514,4 +515,11 @@ class OracleSim3D:
     def get_f(self) -> np.ndarray:
         f = np.zeros((19, self.nz, self.ny, self.nx))
         self._lib.orc3_get_f(self._h, _dp(f))
+        return f
+
+    def get_ft(self) -> np.ndarray:
+        """Post-collision populations of the last step [19][nz][ny][nx]
+        (the pressure planes' extrapolated state included)."""
+        f = np.zeros((19, self.nz, self.ny, self.nx))
+        self._lib.orc3_get_ft(self._h, _dp(f))
         return f

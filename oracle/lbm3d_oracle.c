@@ -644,6 +644,10 @@ void orc3_get_f(const orc3_sim* s, double* out) {
     memcpy(out, s->f, sizeof(double) * 19 * (size_t)s->nx * s->ny * s->nz);
 }
 
+void orc3_get_ft(const orc3_sim* s, double* out) {
+    memcpy(out, s->ft, sizeof(double) * 19 * (size_t)s->nx * s->ny * s->nz);
+}
+
 void orc3_set_f(orc3_sim* s, const double* in) {
     memcpy(s->f, in, sizeof(double) * 19 * (size_t)s->nx * s->ny * s->nz);
 }

@@ -77,6 +77,9 @@ long orc3_links(const orc3_sim* s, double* out, long max);
 /* pre-collision populations [19][nz][ny][nx] */
 void orc3_get_f(const orc3_sim* s, double* out);
 void orc3_set_f(orc3_sim* s, const double* in);
+/* post-collision populations of the last step [19][nz][ny][nx]; the pressure
+ * planes hold their extrapolated state (the one the next streaming reads) */
+void orc3_get_ft(const orc3_sim* s, double* out);
 
 #ifdef __cplusplus
 }

@@ -103,3 +103,24 @@ def force_errors(h, oh, case, tol=1e-10, load=None):
                 worst, where = norm, (s, c)
             worst_rel = max(worst_rel, rel)
     return worst, worst_rel, where
+
+
+def plane_state(oracle_mod, osim, own):
+    """The oracle's pressure-plane state: on x = 0 and x = nx - 1, where the
+    inner neighbour is fluid, the extrapolated post-collision populations
+    (what the GPU stores there in place of the streamed state, and what the
+    next step streams from).  The GPU holds the post-collision state of the
+    step it has reached, the oracle the streamed state before that step's
+    collision, so the oracle is advanced by one step here and its
+    post-collision state read (call this after every other comparison).
+    Returns (rho, u, mask); g = 0."""
+    osim.step(1)
+    ft = osim.get_ft()
+    e = np.array(oracle_mod.E3, dtype=float)
+    rho = ft.sum(0)
+    with np.errstate(invalid="ignore", divide="ignore"):  # solid nodes hold no populations
+        u = np.einsum("id,izyx->dzyx", e, ft) / rho
+    mask = np.zeros(own.shape, dtype=bool)
+    mask[:, :, 0] = (own[:, :, 0] == 0) & (own[:, :, 1] == 0)
+    mask[:, :, -1] = (own[:, :, -1] == 0) & (own[:, :, -2] == 0)
+    return rho, u, mask

@@ -10,6 +10,8 @@ import sys
 import numpy as np
 import pytest
 
+from tests.helpers import plane_state
+
 pytestmark = pytest.mark.gpu
 
 
@@ -315,9 +317,9 @@ def test_neutral_sphere_force_average_f64(oracle_mod, lbm_mod):
 def test_pressure_driven_tube_f64(oracle_mod, lbm_mod):
     """The Sec. IV.D duct driven by a pressure inlet and outlet (non-equilibrium
     extrapolation) instead of a body force, an off-axis sphere: FP64 fields on
-    the interior planes and per-step forces against the oracle (the boundary
-    planes' streamed state is replaced after each collision, so their fields
-    are not compared)."""
+    the interior planes, the boundary planes' extrapolated state (which
+    replaces their streamed state after each collision) against the oracle's
+    post-collision state there, and per-step forces."""
     c = dict(name="pressure_tube", nx=40, ny=24, nz=24, tau=0.7, duct=1, R=10.3,
              spheres=[dict(cx=17.4, cy=13.1, cz=10.6, r=4.3)])
     steps = 400
@@ -339,6 +341,13 @@ def test_pressure_driven_tube_f64(oracle_mod, lbm_mod):
     _say(f"interior field rel err rho={er:.3e} u={eu:.3e} (max |u| {np.abs(ou[:, fl]).max():.3e})")
     assert er <= 1e-12 and eu <= 1e-11
     assert force_err(lat, osim) <= 1e-10
+    prho, pu, pl = plane_state(oracle_mod, osim, own)
+    assert pl.sum() > 400
+    epr = np.abs(rho - prho)[pl].max() / prho[pl].max()
+    epu = np.abs(u[:, pl] - pu[:, pl]).max() / np.abs(ou[:, fl]).max()
+    _say(f"pressure-plane rel err rho={epr:.3e} u={epu:.3e}")
+    assert epr <= 1e-12 and epu <= 1e-11
+    assert np.abs(rho[:, :, 0][pl[:, :, 0]] - 1.0002).max() <= 1e-13  # the inlet's density
     assert ou[0][fl].mean() > 0  # flows from the inlet to the outlet
     moving = dict(c, spheres=[dict(cx=17.4, cy=13.1, cz=10.6, r=4.3, moves=True)])
     m = lbm_mod.Lattice3D(moving, dtype="f64", history_steps=4)

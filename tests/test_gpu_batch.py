@@ -84,9 +84,12 @@ def batch_forces(batch, k, nb, lbm_mod):
 # With 16-bit storage the batch and the lone kernel are two separately compiled
 # kernels whose FP32 arithmetic may fuse multiply-adds differently: a one-ulp
 # difference at a node kept in FP32 can flip a 16-bit rounding elsewhere, so
-# there the states agree to a few 16-bit units of the deviation instead of
-# bit for bit.
-SIXTEEN_BIT_TOL = 1e-5
+# there the states agree to about one 16-bit unit (BF16: 2^-8 of the value)
+# instead of bit for bit: velocities and forces within one unit relative to
+# their largest magnitude (a one-unit flip at one node moves its velocity by
+# ~1e-3 of the field's largest), densities within 1e-5.
+SIXTEEN_BIT_UNIT = 2.0 ** -8
+SIXTEEN_BIT_RHO = 1e-5
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
@@ -107,11 +110,12 @@ def test_batch_matches_lone_runs_bitwise(lbm_mod, dtype):
                 brho, bux, buy = (_np(a) for a in batch.fields(k, "f64"))
                 bf = batch_forces(batch, k, len(case["bodies"]), lbm_mod)
                 if dtype == "bf16":
-                    assert np.abs(brho - rho).max() <= SIXTEEN_BIT_TOL, (case["name"], waves, nt)
+                    assert np.abs(brho - rho).max() <= SIXTEEN_BIT_RHO, (case["name"], waves, nt)
                     umax = max(np.abs(ux).max(), np.abs(uy).max())
-                    assert np.abs(bux - ux).max() <= SIXTEEN_BIT_TOL * umax, (case["name"], waves, nt)
-                    assert np.abs(buy - uy).max() <= SIXTEEN_BIT_TOL * umax, (case["name"], waves, nt)
-                    assert np.abs(bf - h).max() <= SIXTEEN_BIT_TOL * max(np.abs(h).max(), 1e-12), case["name"]
+                    du = max(np.abs(bux - ux).max(), np.abs(buy - uy).max())
+                    _say(f"  {case['name']}: max |du| / max |u| = {du / umax:.2e}")
+                    assert du <= SIXTEEN_BIT_UNIT * umax, (case["name"], waves, nt)
+                    assert np.abs(bf - h).max() <= SIXTEEN_BIT_UNIT * max(np.abs(h).max(), 1e-12), case["name"]
                     continue
                 assert np.array_equal(brho, rho), (case["name"], waves, nt)
                 assert np.array_equal(bux, ux), (case["name"], waves, nt)

@@ -409,6 +409,36 @@ def test_pressure_driven_planes_poiseuille_3d(oracle_mod):
         m.set_pressure(1.001, 0.999)
 
 
+def test_pressure_plane_state_3d(oracle_mod):
+    """Non-equilibrium extrapolation moves the neighbour's post-collision
+    state to the plane's density at the same velocity: on every plane node
+    with a fluid neighbour, the post-collision density is exactly rho_b and
+    the velocity that of the neighbour (the equilibrium's first two moments:
+    sum w_i (1 + 3 e.u + ...) = 1, sum w_i e_i (...) = u).  A plane node
+    next to a sphere keeps its own update and is skipped."""
+    E3, _ = _lookup(oracle_mod)
+    rin, rout = 1.0004, 0.9996
+    s = oracle_mod.OracleSim3D(16, 14, 14, 0.7, duct=oracle_mod.TUBE3, R=5.6,
+                               spheres=[dict(cx=1.5, cy=7.9, cz=6.2, r=2.2)])
+    s.set_pressure(rin, rout)
+    s.step(60)
+    ft = s.get_ft()
+    own = s.fields()[2]
+    rho = ft.sum(0)
+    j = np.einsum("id,izyx->dzyx", E3.astype(float), ft)
+    kept = 0
+    for xb, xf, rb in ((0, 1, rin), (15, 14, rout)):
+        plane = (own[:, :, xb] == 0) & (own[:, :, xf] == 0)
+        kept += int(((own[:, :, xb] == 0) & (own[:, :, xf] != 0)).sum())
+        assert plane.sum() > 50
+        assert np.abs(rho[:, :, xb][plane] - rb).max() <= 8e-15
+        ub = j[:, :, :, xb][:, plane] / rho[:, :, xb][plane]
+        uf = j[:, :, :, xf][:, plane] / rho[:, :, xf][plane]
+        assert np.abs(uf).max() > 1e-6
+        assert np.abs(ub - uf).max() <= 4e-15
+    assert kept >= 1  # the sphere's side of the inlet
+
+
 # ---------------------------------------------------------------- interpolated bounce-back in 3D
 def test_ibb_sphere_link_fraction_3d(oracle_mod):
     """q of every link into a sphere is where the segment leaves the fluid,
