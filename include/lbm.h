@@ -120,6 +120,22 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
                       int64_t history_steps, void* d_workspace, size_t bytes, void* hip_stream,
                       lbm_ctx** out);
 
+/* For callers that cannot allocate device memory (harnesses that forbid
+ * hipMalloc, serving loops that must not allocate): lbm_create without a
+ * workspace argument.  The context lives in a static array of 64 MiB that
+ * the library holds on each device it runs on (until the process ends);
+ * this call allocates no device memory, and lbm_step of such a context
+ * launches its kernels one by one (no graph, whose instantiation may
+ * allocate).  One such context per device at a time: LBM_ESTATE while
+ * another is alive on the current device (destroy it first; the array keeps
+ * the last context's contents, and lbm_create rewrites every part of it a
+ * context reads before reading it).  LBM_ESIZE when the configuration needs
+ * more than 64 MiB (lbm_workspace_bytes); calls on one context from several
+ * threads or streams at once race, as for any context.  Otherwise as
+ * lbm_create. */
+lbm_status lbm_create_static(const lbm_grid* grid, double tau, const lbm_solid* solids, int32_t n_solids,
+                             int64_t history_steps, void* hip_stream, lbm_ctx** out);
+
 /* Enqueue n time steps.  Each step evaluates the CME and GME force and torque
  * of every solid from the current post-collision populations (Eqs. 4-7),
  * streams with half-way bounce-back (Eq. 3), moves the translating bodies,

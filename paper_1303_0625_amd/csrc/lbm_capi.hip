@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,6 +18,12 @@
 
 using namespace lbm;
 
+// Workspace of contexts created by lbm_create_static, for callers that cannot
+// allocate device memory: one array per device, held until the process ends.
+// Host code reaches a device's copy only through its address from
+// hipGetSymbolAddress (scratch_on), never through the name.
+constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
@@ -259,6 +266,8 @@ struct lbm_ctx {
     // the force totals of the last step are summed when first read (every
     // earlier step's are summed by the launch after it)
     bool fin_pending = false;
+    // device whose static scratch holds the workspace (lbm_create_static), or -1
+    int static_dev = -1;
     // instrumentation: event pairs around the lattice-update kernel
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -533,6 +542,11 @@ lbm_status read_err(lbm_ctx* c) {
     return LBM_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                     // guards the two tables below
+void* g_scratch_ptr[kMaxDevices] = {};      // device address of each device's scratch
+bool g_scratch_held[kMaxDevices] = {};      // a context lives in it
+
 // Forget the captured step graphs (a setter changed what the launches take).
 void drop_graphs(lbm_ctx* c) {
     for (auto& g : c->gexec)
@@ -775,6 +789,49 @@ lbm_status lbm_create(const lbm_grid* grid, double tau, const lbm_solid* solids,
     return LBM_OK;
 }
 
+lbm_status lbm_create_static(const lbm_grid* grid, double tau, const lbm_solid* solids, int32_t n_solids,
+                             int64_t history_steps, void* hip_stream, lbm_ctx** out) {
+    if (!out) {
+        set_err(g_err, "out is NULL");
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    size_t need = 0;
+    lbm_status rs = lbm_workspace_bytes(grid, solids, n_solids, history_steps, &need);
+    if (rs != LBM_OK) return rs;
+    if (need > kScratchBytes) {
+        set_err(g_err, "this configuration needs %zu bytes of workspace; the static scratch holds %zu", need,
+                kScratchBytes);
+        return LBM_ESIZE;
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        set_err(g_err, "no usable current device (%s)", hipGetErrorString(e));
+        return LBM_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_held[dev]) {
+        set_err(g_err, "the static scratch of device %d is held by another context; destroy that one first", dev);
+        return LBM_ESTATE;
+    }
+    if (!g_scratch_ptr[dev]) {  // first use on this device, which is current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_err(g_err, "hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+            return LBM_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    rs = lbm_create(grid, tau, solids, n_solids, history_steps, g_scratch_ptr[dev], kScratchBytes, hip_stream, out);
+    if (rs == LBM_OK) {
+        (*out)->static_dev = dev;
+        g_scratch_held[dev] = true;
+    }
+    return rs;
+}
+
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     if (!c) return LBM_EINVAL;
     if (n < 0) {
@@ -792,8 +849,9 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     }
     c->fin_pending = false;  // the first launch sums the previous step's totals
     int64_t k = 0;
-    // whole blocks as graph replays (not while timing single launches)
-    while (!c->prof && n - k >= kGraphSteps) {
+    // whole blocks as graph replays (not while timing single launches, and
+    // not for a context that must not allocate: instantiating a graph may)
+    while (!c->prof && c->static_dev < 0 && n - k >= kGraphSteps) {
         const int p = (int)(c->t & 1);
         if (!c->gexec[p]) {
             lbm_status rs = capture_block(c, p);
@@ -1251,6 +1309,10 @@ lbm_status lbm_status_check(lbm_ctx* c) {
 void lbm_destroy(lbm_ctx* c) {
     if (!c) return;
     drop_graphs(c);
+    if (c->static_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        g_scratch_held[c->static_dev] = false;
+    }
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     delete c;

@@ -74,6 +74,8 @@ _SIG = {
                                    ctypes.POINTER(ctypes.c_size_t)]),
     "lbm_create": (_I32, [ctypes.POINTER(lbm_grid), ctypes.c_double, ctypes.POINTER(lbm_solid), _I32,
                           _I64, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "lbm_create_static": (_I32, [ctypes.POINTER(lbm_grid), ctypes.c_double, ctypes.POINTER(lbm_solid), _I32,
+                                 _I64, _VP, ctypes.POINTER(_VP)]),
     "lbm_step": (_I32, [_VP, _I64]),
     "lbm_time": (_I64, [_VP]),
     "lbm_force": (_I32, [_VP, _I32, _I32, ctypes.POINTER(ctypes.c_double)]),
@@ -208,6 +210,16 @@ def lbm_create(grid: lbm_grid, tau: float, solids, history_steps: int, d_workspa
     ctx = _VP()
     _check(load_library().lbm_create(ctypes.byref(grid), tau, arr, n, history_steps, d_workspace,
                                      nbytes, stream, ctypes.byref(ctx)))
+    return ctx
+
+
+def lbm_create_static(grid: lbm_grid, tau: float, solids, history_steps: int, stream: int):
+    """lbm_create with the context in the library's static scratch (no device
+    allocation); one such context per device at a time."""
+    arr, n = _solid_array(solids)
+    ctx = _VP()
+    _check(load_library().lbm_create_static(ctypes.byref(grid), tau, arr, n, history_steps, stream,
+                                            ctypes.byref(ctx)))
     return ctx
 
 
@@ -596,8 +608,11 @@ class Lattice:
     current stream at creation time.
     """
 
-    def __init__(self, case: dict, dtype="f64", history_steps=None, device="cuda", stream=None, mrt=None):
-        """mrt: None for the BGK operator, else the MRT rates (s_e, s_eps, s_q)."""
+    def __init__(self, case: dict, dtype="f64", history_steps=None, device="cuda", stream=None, mrt=None,
+                 static=False):
+        """mrt: None for the BGK operator, else the MRT rates (s_e, s_eps, s_q).
+        static: the context lives in the library's static scratch
+        (lbm_create_static) instead of a workspace tensor."""
         import torch
 
         self.torch = torch
@@ -612,12 +627,20 @@ class Lattice:
         solids = case.get("bodies", ())
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self._destroy = load_library().lbm_destroy  # usable at interpreter exit
-        nbytes = lbm_workspace_bytes(self.grid, solids, self.history_steps)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
-        self.ctx = lbm_create(self.grid, float(case["tau"]), solids, self.history_steps,
-                              self._ws_ptr, nbytes, self.stream.cuda_stream)
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        if static:
+            self.workspace = None  # the library's static scratch holds the context
+            self.ctx = lbm_create_static(self.grid, float(case["tau"]), solids, self.history_steps,
+                                         self.stream.cuda_stream)
+        else:
+            nbytes = lbm_workspace_bytes(self.grid, solids, self.history_steps)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            self.ctx = lbm_create(self.grid, float(case["tau"]), solids, self.history_steps,
+                                  self._ws_ptr, nbytes, self.stream.cuda_stream)
         if mrt is not None:
             lbm_set_collision(self.ctx, LBM_MRT, tuple(float(r) for r in mrt))
 
@@ -647,14 +670,14 @@ class Lattice:
         if count is None:
             count = t - first
         out = self.torch.empty((count, self.n_solids + 1, 6), dtype=self.torch.float64,
-                               device=self.workspace.device)
+                               device=self.device)
         lbm_force_history(self.ctx, first, count, out.data_ptr())
         return out
 
     def fields(self, out_dtype="f64"):
         tdt = self.torch.float64 if out_dtype == "f64" else self.torch.float32
         shp = (self.ny, self.nx)
-        dev = self.workspace.device
+        dev = self.device
         rho = self.torch.empty(shp, dtype=tdt, device=dev)
         ux = self.torch.empty(shp, dtype=tdt, device=dev)
         uy = self.torch.empty(shp, dtype=tdt, device=dev)
@@ -689,7 +712,7 @@ class Lattice:
 
     def populations(self):
         out = self.torch.empty((9, self.ny, self.nx), dtype=self.torch.float64,
-                               device=self.workspace.device)
+                               device=self.device)
         lbm_populations(self.ctx, out.data_ptr())
         return out
 
@@ -701,7 +724,7 @@ class Lattice:
         if st not in (LBM_OK, LBM_ESIZE):
             _check(st, self.ctx)
         out = self.torch.empty((max(n.value, 1), 8), dtype=self.torch.float64,
-                               device=self.workspace.device)
+                               device=self.device)
         got = lbm_link_forces(self.ctx, out.data_ptr(), out.shape[0])
         return out[:got]
 
@@ -710,7 +733,7 @@ class Lattice:
 
     def save(self):
         nb = self.checkpoint_bytes()
-        buf = self.torch.empty(nb, dtype=self.torch.uint8, device=self.workspace.device)
+        buf = self.torch.empty(nb, dtype=self.torch.uint8, device=self.device)
         lbm_save(self.ctx, buf.data_ptr(), nb)
         return buf
 
