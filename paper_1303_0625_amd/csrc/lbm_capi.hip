@@ -349,6 +349,15 @@ int64_t node_blocks(const lbm_ctx* c) {
     return ((int64_t)c->g.ny * c->L.pitch + kBlock - 1) / kBlock;
 }
 
+// Update workgroups of the step launch: one node per lane, or two per lane
+// (128 consecutive x per wave) with 16-bit storage.
+template <typename T>
+int64_t update_blocks(const lbm_ctx* c) {
+    if constexpr (Sto<T>::kSplit)
+        return ((int64_t)c->g.ny * ((c->L.pitch + 127) / 128) + kBlock / 64 - 1) / (kBlock / 64);
+    return node_blocks(c);
+}
+
 // The two owner maps; with no translating body both views are the same map.
 uint8_t* own_ptr(lbm_ctx* c, int k) {
     if (c->L.n_movers == 0) k = 0;
@@ -400,7 +409,7 @@ lbm_status enqueue_step(lbm_ctx* c) {
     StepArgs sa = step_args(c);
     ForceArgs fa = force_args(c);
     CollideParams<C> cp = collide_params<C>(c);
-    const dim3 grid((unsigned)(rc.n_lead + node_blocks(c)));
+    const dim3 grid((unsigned)(rc.n_lead + update_blocks<T>(c)));
     const size_t lds = n_presc > 0 ? 2 * (size_t)c->L.box_bytes : 0;
     // both population buffers larger than the Infinity Cache: stream them
     const bool nt = 2 * c->L.pbytes > kStreamBytes;

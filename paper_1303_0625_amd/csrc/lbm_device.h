@@ -85,6 +85,9 @@ struct Sto<_Float16> {
     __device__ static inline _Float16 st(float c) { return (_Float16)c; }
     __device__ static inline bool marked(_Float16 v) { return __builtin_bit_cast(uint16_t, v) == kMarkF16; }
     __device__ static inline _Float16 mark() { return __builtin_bit_cast(_Float16, kMarkF16); }
+    // decode h + r and encode h = d - r (one rounding to half)
+    __device__ static inline float ld_add(_Float16 h, float r) { return (float)h + r; }
+    __device__ static inline _Float16 st_sub(float d, float r) { return (_Float16)(d - r); }
 };
 template <>
 struct Sto<bf16_t> {
@@ -97,6 +100,7 @@ struct Sto<bf16_t> {
         return r;
     }
     __device__ static inline float ld(bf16_t v) { return __uint_as_float(((uint32_t)v.bits) << 16); }
+    __device__ static inline float ld_add(bf16_t v, float r) { return ld(v) + r; }
     // the hardware conversion (v_cvt_pk_bf16_f32 on gfx950) rounds to
     // nearest even and returns quiet NaNs
     __device__ static inline bf16_t st(float c) {
@@ -104,6 +108,7 @@ struct Sto<bf16_t> {
         r.bits = __builtin_bit_cast(uint16_t, (__bf16)c);
         return r;
     }
+    __device__ static inline bf16_t st_sub(float d, float r) { return st(d - r); }
 };
 
 // ---------------------------------------------------------------- collision
@@ -118,6 +123,18 @@ struct CollideParams {
     C s_e, s_eps, s_q;            // its energy, energy-square and heat-flux rates
 };
 
+// 1/x: a correctly rounded division in FP64; in FP32, the arithmetic of the
+// 16-bit storages, the hardware reciprocal (within 1 ulp, far below the
+// storage's own rounding) instead of the ten-instruction IEEE division.
+template <typename C>
+__device__ inline C recip(C x) {
+    return C(1) / x;
+}
+template <>
+__device__ inline float recip<float>(float x) {
+    return __builtin_amdgcn_rcpf(x);
+}
+
 // Moments of one node: drho = sum d_i, rho = rho0 + drho, Guo velocity u.
 template <typename C>
 struct Moments {
@@ -131,7 +148,7 @@ __device__ inline Moments<C> moments(const C d[9], const CollideParams<C>& p) {
     m.rho = p.rho0 + m.drho;
     C jx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     C jy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-    C inv = C(1) / m.rho;
+    C inv = recip<C>(m.rho);
     m.ux = jx * inv + C(0.5) * p.gx;
     m.uy = jy * inv + C(0.5) * p.gy;
     return m;

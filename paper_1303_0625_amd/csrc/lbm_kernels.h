@@ -115,10 +115,23 @@ __device__ inline float row16_sum(float v) {
     return v;
 }
 
-// The nine reference deviations w_i (drho + 3 e_i . u) of a segment.
+// The nine reference deviations w_i (drho + 3 e_i . u) of a segment, written
+// per direction so that no product with a zero velocity component is formed
+// (the compiler may not drop 0 * u_x, which is not an identity for every
+// float): one fused multiply-add per direction.
 __device__ inline void ref_eq(float drho, float ux, float uy, float r[9]) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = w_<float>(i) * (drho + 3.0f * ((float)ex_(i) * ux + (float)ey_(i) * uy));
+    const float w0 = w_<float>(0), w1 = w_<float>(1), w5 = w_<float>(5);
+    const float a = 3.0f * ux, b = 3.0f * uy, p = a + b, m = b - a;
+    const float d1 = w1 * drho, d5 = w5 * drho;
+    r[0] = w0 * drho;
+    r[1] = __builtin_fmaf(w1, a, d1);
+    r[3] = __builtin_fmaf(-w1, a, d1);
+    r[2] = __builtin_fmaf(w1, b, d1);
+    r[4] = __builtin_fmaf(-w1, b, d1);
+    r[5] = __builtin_fmaf(w5, p, d5);
+    r[7] = __builtin_fmaf(-w5, p, d5);
+    r[6] = __builtin_fmaf(w5, m, d5);
+    r[8] = __builtin_fmaf(-w5, m, d5);
 }
 
 // A fluid node with a solid neighbour (or a wall row) in the owner map.
@@ -190,6 +203,217 @@ struct BndSolid {
     int s;
 };
 
+// Source rows and columns of node (x, y): x -/+ 1 periodic; y -/+ 1 periodic,
+// or, with walls at y, the node's own row where the source row is a wall.
+__device__ inline void sources(int x, int y, const StepArgs& a, int& xm, int& xp, int& ym, int& yp, bool& wall_lo,
+                               bool& wall_hi) {
+    xm = x == 0 ? a.nx - 1 : x - 1;
+    xp = x == a.nx - 1 ? 0 : x + 1;
+    wall_lo = false;
+    wall_hi = false;
+    if (a.walls) {
+        wall_lo = (y == 0);
+        wall_hi = (y == a.ny - 1);
+        ym = wall_lo ? y : y - 1;
+        yp = wall_hi ? y : y + 1;
+    } else {
+        ym = y == 0 ? a.ny - 1 : y - 1;
+        yp = y == a.ny - 1 ? 0 : y + 1;
+    }
+}
+
+// ---- 16-bit storage, update role.  A node's update is split into its loads
+// (seg16_load) and the rest (seg16_finish), so that a lane can issue the
+// loads of a second node before it updates the first.  The nodes of each
+// 16-node row segment store against their segment's reference equilibrium,
+// which the segment's lanes form together: every lane (also a solid one, or
+// one past the row's end with lane_ok false) runs seg16_finish to its
+// reference step.
+template <typename T>
+struct Seg16In {
+    T raw[9];        // streamed populations, as stored
+    float rr[9];     // reference of each source's segment
+    uint32_t self;   // owner of the node
+    uint32_t nb;     // OR of the owners of the eight sources
+    int x, xr;       // column (clamped into the lattice), the lane's own column
+    bool lane_ok;
+};
+
+template <typename T, bool NT>
+__device__ inline void seg16_load(Seg16In<T>& L, int x, int y, const T* __restrict__ fin,
+                                  const uint8_t* __restrict__ own_t, const StepArgs& a, bool lane_ok) {
+    L.xr = x;
+    L.lane_ok = lane_ok;
+    if (!lane_ok) x = a.nx - 1;  // addresses stay in the lattice
+    L.x = x;
+    int xm, xp, ym, yp;
+    bool wall_lo, wall_hi;
+    sources(x, y, a, xm, xp, ym, yp, wall_lo, wall_hi);
+    // wave-uniform row bases, unsigned 32-bit lane offsets
+    const uint32_t ux = (uint32_t)x, uxm = (uint32_t)xm, uxp = (uint32_t)xp;
+    const uint8_t* om = own_t + (int64_t)ym * a.opitch;
+    const uint8_t* o0 = own_t + (int64_t)y * a.opitch;
+    const uint8_t* op = own_t + (int64_t)yp * a.opitch;
+    L.self = o0[ux];
+    L.nb = (uint32_t)o0[uxm] | o0[uxp] | om[ux] | om[uxm] | om[uxp] | op[ux] | op[uxp] | op[uxm];
+    const int64_t P = a.istride;
+    const T* r0 = fin + (int64_t)y * a.ystride;
+    const T* rm = fin + (int64_t)ym * a.ystride;
+    const T* rp = fin + (int64_t)yp * a.ystride;
+    L.raw[0] = ld_stream<NT>(row_at(r0, ux));
+    L.raw[1] = ld_stream<NT>(row_at(r0 + P, uxm));
+    L.raw[2] = ld_stream<NT>(row_at(rm + 2 * P, ux));
+    L.raw[3] = ld_stream<NT>(row_at(r0 + 3 * P, uxp));
+    L.raw[4] = ld_stream<NT>(row_at(rp + 4 * P, ux));
+    L.raw[5] = ld_stream<NT>(row_at(rm + 5 * P, uxm));
+    L.raw[6] = ld_stream<NT>(row_at(rm + 6 * P, uxp));
+    L.raw[7] = ld_stream<NT>(row_at(rp + 7 * P, uxp));
+    L.raw[8] = ld_stream<NT>(row_at(rp + 8 * P, uxm));
+    // the reference of each source's segment (a segment's lanes read the same words)
+    const float* R = side_of(fin, a.ref_off);
+    const float* Rr0 = R + (int64_t)y * a.nseg * kSeg;
+    const float* Rrm = R + (int64_t)ym * a.nseg * kSeg;
+    const float* Rrp = R + (int64_t)yp * a.nseg * kSeg;
+    const uint32_t u0 = (uint32_t)(x >> kRefShift) * kSeg;
+    const uint32_t um = (uint32_t)(xm >> kRefShift) * kSeg, uq = (uint32_t)(xp >> kRefShift) * kSeg;
+    L.rr[0] = *row_at(Rr0 + 0, u0);
+    L.rr[1] = *row_at(Rr0 + 1, um);
+    L.rr[2] = *row_at(Rrm + 2, u0);
+    L.rr[3] = *row_at(Rr0 + 3, uq);
+    L.rr[4] = *row_at(Rrp + 4, u0);
+    L.rr[5] = *row_at(Rrm + 5, um);
+    L.rr[6] = *row_at(Rrm + 6, uq);
+    L.rr[7] = *row_at(Rrp + 7, uq);
+    L.rr[8] = *row_at(Rrp + 8, um);
+}
+
+// The update of the node whose loads L holds: decode, half-way bounce-back
+// (GEO: rigid surface motion of spinning bodies; nodes next to a body are
+// left to the boundary role under interpolated bounce-back), collide (BGK,
+// or MRT when MRT), the segment's reference, store.
+template <typename T, bool NT, bool MRT, bool GEO>
+__device__ inline void seg16_finish(const Seg16In<T>& L, int y, const T* __restrict__ fin, T* __restrict__ fout,
+                                    const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
+                                    const double* __restrict__ rtab, int64_t t, const StepArgs& a,
+                                    const CollideParams<float>& cp) {
+    using C = float;
+    const int x = L.x, xr = L.xr;
+    int xm, xp, ym, yp;
+    bool wall_lo, wall_hi;
+    sources(x, y, a, xm, xp, ym, yp, wall_lo, wall_hi);
+    const bool near = L.nb != 0u || wall_lo || wall_hi;
+    // solid at t (a newborn node is refilled by the mover role), past the
+    // row's end, or left to the boundary role
+    bool live = L.self == 0u && L.lane_ok;
+    if constexpr (GEO) live = live && !(a.ibb && L.nb != 0u);
+    const int64_t P = a.istride;
+    const uint32_t ux = (uint32_t)x;
+    // element offsets of the rows y, y - 1, y + 1 (FP32 copies beside the buffer)
+    const int64_t e0 = (int64_t)y * a.ystride, em = (int64_t)ym * a.ystride, ep = (int64_t)yp * a.ystride;
+    C d[9];
+    Moments<C> mo{};
+    if (live) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld_add(L.raw[i], L.rr[i]);
+        // a source next to a solid holds its FP32 populations in the side array
+        bool mk[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) mk[i] = Sto<T>::marked(L.raw[i]);
+        if (mk[0] | mk[1] | mk[2] | mk[3] | mk[4] | mk[5] | mk[6] | mk[7] | mk[8]) {
+            const float* sd = side_of(fin, a.side_off);
+            if (mk[0]) d[0] = sd[e0 + x];
+            if (mk[1]) d[1] = sd[e0 + P + xm];
+            if (mk[2]) d[2] = sd[em + 2 * P + x];
+            if (mk[3]) d[3] = sd[e0 + 3 * P + xp];
+            if (mk[4]) d[4] = sd[ep + 4 * P + x];
+            if (mk[5]) d[5] = sd[em + 5 * P + xm];
+            if (mk[6]) d[6] = sd[em + 6 * P + xp];
+            if (mk[7]) d[7] = sd[ep + 7 * P + xp];
+            if (mk[8]) d[8] = sd[ep + 8 * P + xm];
+        }
+        if (near) {
+            // half-way bounce-back for the directions whose source is solid or
+            // a wall row: the node's own opposite population plus the
+            // moving-wall term; the owners are read again here (cached)
+            const uint8_t* om = own_t + (int64_t)ym * a.opitch;
+            const uint8_t* o0 = own_t + (int64_t)y * a.opitch;
+            const uint8_t* op = own_t + (int64_t)yp * a.opitch;
+            const uint32_t src[9] = {0u, o0[xm], om[x], o0[xp], op[x], om[xm], om[xp], op[xp], op[xm]};
+            // the node's own population of direction j: FP32 beside the buffer
+            // when it was stored next to a solid, else against its segment's
+            // reference (a node that a moving body has just come next to)
+            const T* r0 = fin + e0;
+            const float* Rr0 = side_of(fin, a.ref_off) + (int64_t)y * a.nseg * kSeg;
+            const uint32_t u0 = (uint32_t)(x >> kRefShift) * kSeg;
+            auto own_pop = [&](int j) -> C {
+                const T v = *row_at(r0 + j * P, ux);
+                if (Sto<T>::marked(v)) return side_of(fin, a.side_off)[e0 + j * P + x];
+                return Sto<T>::ld_add(v, *row_at(Rr0 + j, u0));
+            };
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const bool wall = (ey_(i) == 1 && wall_lo) || (ey_(i) == -1 && wall_hi);
+                const uint32_t sid = wall ? 0u : src[i];
+                if (wall || sid != 0u) {
+                    C vx = (C)vtab[2 * sid], vy = (C)vtab[2 * sid + 1];
+                    if constexpr (GEO) {
+                        const double om_ = rtab[kRot * sid];
+                        if (om_ != 0.0) {
+                            const double rx = min_image((double)x - 0.5 * ex_(i) - rtab[kRot * sid + 1], a.nx);
+                            double ry = (double)y - 0.5 * ey_(i) - rtab[kRot * sid + 2];
+                            if (!a.walls) ry = min_image(ry, a.ny);
+                            vx = (C)((double)vtab[2 * sid] - om_ * ry);
+                            vy = (C)((double)vtab[2 * sid + 1] + om_ * rx);
+                        }
+                    }
+                    d[i] = own_pop(opp_(i)) + C(6) * w_<C>(i) * (C)a.rho0 * (C(ex_(i)) * vx + C(ey_(i)) * vy);
+                }
+            }
+        }
+        if constexpr (MRT)
+            collide_mrt<C>(d, cp, &mo);
+        else
+            collide<C>(d, cp, &mo);
+    }
+    // the segment's reference: w_i (drho_s + 3 e_i . u_s) from the means over
+    // its live nodes (16 lanes, an aligned quarter of the wave)
+    const float sr = row16_sum(live ? mo.drho : 0.0f);
+    const float sx = row16_sum(live ? mo.ux : 0.0f);
+    const float sy = row16_sum(live ? mo.uy : 0.0f);
+    // live lanes of the segment (any reference serves, as long as the table
+    // holds the one the stores subtract: the reciprocal need not be exact)
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t grp = (uint32_t)(__ballot(live) >> (lane & ~(uint32_t)(kRefNodes - 1))) & 0xffffu;
+    const float inv = grp != 0u ? __builtin_amdgcn_rcpf((float)__builtin_popcount(grp)) : 0.0f;
+    float r[9];
+    ref_eq(sr * inv, sx * inv, sy * inv, r);
+    // lanes 0..8 of the segment record it for the readers of the next step
+    // (segments of the padded row only)
+    const uint32_t j = (uint32_t)xr & (kRefNodes - 1);
+    if (j < (uint32_t)kSeg && ((uint32_t)xr >> kRefShift) < (uint32_t)a.nseg) {
+        float rj = r[0];
+#pragma unroll
+        for (int k = 1; k < 9; ++k) rj = j == (uint32_t)k ? r[k] : rj;
+        float* Rw = side_of(fout, a.ref_off) + (int64_t)y * a.nseg * kSeg;
+        *row_at(Rw, ((uint32_t)xr >> kRefShift) * kSeg + j) = rj;
+    }
+    if (!live) return;
+    T* w0 = fout + (int64_t)y * a.ystride;
+    // a node next to a solid keeps its populations in FP32
+    if (near) {
+        float* sw = side_of(fout, a.side_off) + e0 + x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) sw[i * P] = d[i];
+    }
+    // one scalar row base, 32-bit offsets i P + x (the encoded value is formed
+    // unconditionally, so that the marker is a select, not a branch)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const T v = Sto<T>::st_sub(d[i], r[i]);
+        st_stream<NT>(row_at(w0, ux + (uint32_t)i * (uint32_t)P), near ? Sto<T>::mark() : v);
+    }
+}
+
 template <typename T, bool NT, bool MRT = false, bool GEO = false, bool BND = false>
 __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __restrict__ fout,
                                  const uint8_t* __restrict__ own_t, const double* __restrict__ vtab,
@@ -205,15 +429,39 @@ __device__ inline void step_role(uint32_t bid, uint32_t nblk, const T* __restric
                                  const CollideParams<typename Sto<T>::C>& cp) {
     // row and column base are wave-uniform scalars
     const uint32_t b = xcd_remap(bid, nblk);
-    const uint32_t wpr = (uint32_t)a.rowlen >> 6;
-    const uint32_t gw = b * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int y = (int)(gw / wpr);
-    const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
-    if (y >= a.ny) return;
-    if constexpr (!Sto<T>::kSplit) {
-        if (x >= a.nx) return;
+    const uint32_t wl = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if constexpr (Sto<T>::kSplit) {
+        // 16-bit storage: each wave takes 128 consecutive x of a row, two
+        // nodes per lane (x and x + 64), and issues the second node's loads
+        // before the first node's update, so that a wave keeps both nodes'
+        // loads in flight (the 16-bit update is bound by load latency, not
+        // by bandwidth)
+        const uint32_t wpr = ((uint32_t)a.rowlen + 127u) >> 7;
+        const uint32_t gw = b * (kBlock / 64) + wl;
+        const int y = (int)(gw / wpr);
+        const int x = (int)((gw - (uint32_t)y * wpr) << 7) + (int)(threadIdx.x & 63);
+        if (y >= a.ny) return;
+        // (the second half of a row's last wave can lie past the padded row,
+        // whose length is a multiple of 64: its lanes are not live and write
+        // no reference; no branch around it, so that the counters of loads in
+        // flight stay exact)
+        Seg16In<T> A, B;
+        seg16_load<T, NT>(A, x, y, fin, own_t, a, x < a.nx);
+        // loads return in issue order: the first node's must be issued first
+        // (scheduling barriers keep the two groups apart and ahead of the update)
+        __builtin_amdgcn_sched_barrier(0);
+        seg16_load<T, NT>(B, x + 64, y, fin, own_t, a, x + 64 < a.nx);
+        __builtin_amdgcn_sched_barrier(0);
+        seg16_finish<T, NT, MRT, GEO>(A, y, fin, fout, own_t, vtab, rtab, t, a, cp);
+        seg16_finish<T, NT, MRT, GEO>(B, y, fin, fout, own_t, vtab, rtab, t, a, cp);
+    } else {
+        const uint32_t wpr = (uint32_t)a.rowlen >> 6;
+        const uint32_t gw = b * (kBlock / 64) + wl;
+        const int y = (int)(gw / wpr);
+        const int x = (int)((gw - (uint32_t)y * wpr) << 6) + (int)(threadIdx.x & 63);
+        if (y >= a.ny || x >= a.nx) return;
+        step_node<T, NT, MRT, GEO>(x, y, fin, fout, own_t, vtab, rtab, sol, t, a, cp);
     }
-    step_node<T, NT, MRT, GEO>(x, y, fin, fout, own_t, vtab, rtab, sol, t, a, cp, nullptr, x < a.nx);
 }
 
 // The update of node (x, y): pull, bounce-back, collide (BGK, or MRT when
@@ -230,27 +478,16 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
                                  const StepArgs& a, const CollideParams<typename Sto<T>::C>& cp,
                                  const BndSolid* bs, bool lane_ok) {
     using C = typename Sto<T>::C;
-    // 16-bit storage outside the boundary role: the nodes of each 16-node row
-    // segment store against their segment's reference equilibrium, which the
-    // segment's lanes form together, so every lane (also a solid one, or one
-    // past the row's end with lane_ok false) stays to the end
-    constexpr bool kSeg16 = Sto<T>::kSplit && !BND;
-    const int xr = x;  // the lane's own column (reference table slot)
-    if (!lane_ok) x = a.nx - 1;  // addresses stay in the lattice
-
-    const int xm = x == 0 ? a.nx - 1 : x - 1;
-    const int xp = x == a.nx - 1 ? 0 : x + 1;
-    bool wall_lo = false, wall_hi = false;  // source rows y-1 / y+1 are walls
-    int ym, yp;
-    if (a.walls) {
-        wall_lo = (y == 0);
-        wall_hi = (y == a.ny - 1);
-        ym = wall_lo ? y : y - 1;
-        yp = wall_hi ? y : y + 1;
-    } else {
-        ym = y == 0 ? a.ny - 1 : y - 1;
-        yp = y == a.ny - 1 ? 0 : y + 1;
+    if constexpr (Sto<T>::kSplit && !BND) {
+        // 16-bit storage outside the boundary role: one node's loads, then its update
+        Seg16In<T> L;
+        seg16_load<T, NT>(L, x, y, fin, own_t, a, lane_ok);
+        seg16_finish<T, NT, MRT, GEO>(L, y, fin, fout, own_t, vtab, rtab, t, a, cp);
+        return;
     }
+    int xm, xp, ym, yp;
+    bool wall_lo, wall_hi;  // source rows y-1 / y+1 are walls
+    sources(x, y, a, xm, xp, ym, yp, wall_lo, wall_hi);
     // Row bases are wave-uniform (a wave covers 64 x of one row); the lane
     // offsets are unsigned 32-bit, so every access is a scalar base plus a
     // 32-bit vector offset (no per-lane 64-bit address arithmetic).
@@ -313,21 +550,14 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
     // the boundary role
     bool live = self == 0u;
     if constexpr (GEO && !BND) live = live && !(a.ibb && (s1 | s2 | s3 | s4 | s5 | s6 | s7 | s8) != 0);
-    if constexpr (!kSeg16) {
-        if (!live) return;
-    } else {
-        live = live && lane_ok;
-    }
+    if (!live) return;
     // element offsets of the rows y, y - 1, y + 1 (FP32 copies of 16-bit storage)
     const int64_t e0 = (int64_t)y * a.ystride, em = (int64_t)ym * a.ystride, ep = (int64_t)yp * a.ystride;
     C d[9];
-    Moments<C> mo{};
-    if (live) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
+    {
         if constexpr (Sto<T>::kSplit) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) d[i] += rr[i];
+            for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld_add(raw[i], rr[i]);
             // a source next to a solid holds its FP32 populations in the side array
             const bool m0 = Sto<T>::marked(raw[0]), m1 = Sto<T>::marked(raw[1]), m2 = Sto<T>::marked(raw[2]);
             const bool m3 = Sto<T>::marked(raw[3]), m4 = Sto<T>::marked(raw[4]), m5 = Sto<T>::marked(raw[5]);
@@ -344,6 +574,9 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
                 if (m7) d[7] = (C)sd[ep + 7 * P + xp];
                 if (m8) d[8] = (C)sd[ep + 8 * P + xm];
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld(raw[i]);
         }
         // the node's own population of direction j (bounce-back, interpolated rule)
         auto own_pop = [&](T v, int j) -> C {
@@ -411,43 +644,12 @@ __device__ inline void step_node(int x, int y, const T* __restrict__ fin, T* __r
             }
         }
         if constexpr (MRT)
-            collide_mrt<C>(d, cp, &mo);
+            collide_mrt<C>(d, cp);
         else
-            collide<C>(d, cp, &mo);
+            collide<C>(d, cp);
     }
     T* w0 = fout + (int64_t)y * a.ystride;
-    if constexpr (kSeg16) {
-        // the segment's reference: w_i (drho_s + 3 e_i . u_s) from the means
-        // over its live nodes (16 lanes, an aligned quarter of the wave)
-        const float sr = row16_sum(live ? (float)mo.drho : 0.0f);
-        const float sx = row16_sum(live ? (float)mo.ux : 0.0f);
-        const float sy = row16_sum(live ? (float)mo.uy : 0.0f);
-        const int lane = (int)(threadIdx.x & 63);
-        const uint64_t bl = __ballot(live);
-        const int cnt = __popcll((bl >> (lane & ~(kRefNodes - 1))) & ((1ull << kRefNodes) - 1));
-        const float inv = cnt > 0 ? 1.0f / (float)cnt : 0.0f;
-        float r[9];
-        ref_eq(sr * inv, sx * inv, sy * inv, r);
-        // lanes 0..8 of the segment record it for the readers of the next step
-        const int j = xr & (kRefNodes - 1);
-        if (j < kSeg) {
-            float rj = r[0];
-#pragma unroll
-            for (int k = 1; k < 9; ++k) rj = j == k ? r[k] : rj;
-            side_of(fout, a.ref_off)[((int64_t)y * a.nseg + (xr >> kRefShift)) * kSeg + j] = rj;
-        }
-        if (!live) return;
-        // a node next to a solid keeps its populations in FP32
-        if (near) {
-            float* sw = side_of(fout, a.side_off) + e0 + x;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) sw[i * P] = (float)d[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            st_stream<NT>(row_at(w0 + i * P, ux), near ? Sto<T>::mark() : Sto<T>::st(d[i] - (C)r[i]));
-        return;
-    } else if constexpr (Sto<T>::kSplit) {
+    if constexpr (Sto<T>::kSplit) {
         // the boundary role's nodes are next to a body: FP32
 #pragma unroll
         for (int i = 0; i < 9; ++i) st_near<T>(fout, a, i, x, y, d[i]);
@@ -1426,7 +1628,7 @@ __device__ inline void boundary_role(int wg, const StepPtrs<T>& p, int64_t t, co
 // its boundary and refill roles would otherwise spill, and spill traffic
 // lengthens their dependent chains under the update's saturated HBM.
 template <typename T, bool NT, bool MRT, bool GEO>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GEO ? 4 : 8, 8))) void k_fused(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GEO ? 4 : (Sto<T>::kSplit ? 6 : 8), 8))) void k_fused(
     StepPtrs<T> p, int parity, RoleCounts rc, StepArgs sa, MoveArgs ma, ForceArgs fa,
     CollideParams<typename Sto<T>::C> cp) {
     extern __shared__ __align__(16) uint8_t dyn_lds[];
