@@ -178,8 +178,10 @@ __device__ inline C relax_one(int i, C di, const Moments<C>& m, const CollidePar
 // the rest direction keeps (1 - omega) d_0 + w_0 z.  Half the arithmetic of
 // nine independent relax_one calls.
 template <typename C>
-__device__ inline void collide(C d[9], const CollideParams<C>& p, Moments<C>* mo_out = nullptr) {
-    const Moments<C> m = moments<C>(d, p);
+__device__ inline void collide(C d[9], const CollideParams<C>& p, Moments<C>* mo_out = nullptr,
+                               const Moments<C>* mo_in = nullptr) {
+    // mo_in: the moments of d, when the caller has formed them already
+    const Moments<C> m = mo_in ? *mo_in : moments<C>(d, p);
     if (mo_out) *mo_out = m;
     const C om = p.omega, keep = C(1) - p.omega;
     const C Fx = m.rho * p.gx, Fy = m.rho * p.gy;
@@ -215,8 +217,9 @@ __device__ inline void collide(C d[9], const CollideParams<C>& p, Moments<C>* mo
 // and drops out of m - m_eq.  The rows of M are orthogonal with squared
 // norms (9, 36, 36, 6, 12, 6, 12, 4, 4), so M^-1 = M^T diag(1 / norms).
 template <typename C>
-__device__ inline void collide_mrt(C d[9], const CollideParams<C>& p, Moments<C>* mo_out = nullptr) {
-    const Moments<C> mo = moments<C>(d, p);
+__device__ inline void collide_mrt(C d[9], const CollideParams<C>& p, Moments<C>* mo_out = nullptr,
+                                   const Moments<C>* mo_in = nullptr) {
+    const Moments<C> mo = mo_in ? *mo_in : moments<C>(d, p);
     if (mo_out) *mo_out = mo;
     const C drho = mo.drho, rho = mo.rho, ux = mo.ux, uy = mo.uy;
     const C s14 = (d[1] + d[2]) + (d[3] + d[4]);

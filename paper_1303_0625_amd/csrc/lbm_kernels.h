@@ -312,10 +312,17 @@ __device__ inline void seg16_finish(const Seg16In<T>& L, int y, const T* __restr
     const int64_t e0 = (int64_t)y * a.ystride, em = (int64_t)ym * a.ystride, ep = (int64_t)yp * a.ystride;
     C d[9];
     Moments<C> mo{};
+    Moments<C> m0;
     if (live) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) d[i] = Sto<T>::ld_add(L.raw[i], L.rr[i]);
-        // a source next to a solid holds its FP32 populations in the side array
+        m0 = moments<C>(d, cp);
+    }
+    // A source next to a solid holds its FP32 populations in the side array
+    // and a marker, a NaN pattern, in its slot: the decoded density sum is
+    // NaN exactly then (or for a state that has blown up), so one test finds
+    // the nodes that need the side array or the bounce-back
+    if (live && (near || __builtin_isnan(m0.drho))) {
         bool mk[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) mk[i] = Sto<T>::marked(L.raw[i]);
@@ -370,10 +377,13 @@ __device__ inline void seg16_finish(const Seg16In<T>& L, int y, const T* __restr
                 }
             }
         }
+        m0 = moments<C>(d, cp);
+    }
+    if (live) {
         if constexpr (MRT)
-            collide_mrt<C>(d, cp, &mo);
+            collide_mrt<C>(d, cp, &mo, &m0);
         else
-            collide<C>(d, cp, &mo);
+            collide<C>(d, cp, &mo, &m0);
     }
     // the segment's reference: w_i (drho_s + 3 e_i . u_s) from the means over
     // its live nodes (16 lanes, an aligned quarter of the wave)
@@ -399,18 +409,18 @@ __device__ inline void seg16_finish(const Seg16In<T>& L, int y, const T* __restr
     }
     if (!live) return;
     T* w0 = fout + (int64_t)y * a.ystride;
-    // a node next to a solid keeps its populations in FP32
+    // one scalar row base, 32-bit offsets i P + x
     if (near) {
+        // a node next to a solid keeps its populations in FP32, its slots a marker
         float* sw = side_of(fout, a.side_off) + e0 + x;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) sw[i * P] = d[i];
-    }
-    // one scalar row base, 32-bit offsets i P + x (the encoded value is formed
-    // unconditionally, so that the marker is a select, not a branch)
+        for (int i = 0; i < 9; ++i) {
+            sw[i * P] = d[i];
+            st_stream<NT>(row_at(w0, ux + (uint32_t)i * (uint32_t)P), Sto<T>::mark());
+        }
+    } else {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const T v = Sto<T>::st_sub(d[i], r[i]);
-        st_stream<NT>(row_at(w0, ux + (uint32_t)i * (uint32_t)P), near ? Sto<T>::mark() : v);
+        for (int i = 0; i < 9; ++i) st_stream<NT>(row_at(w0, ux + (uint32_t)i * (uint32_t)P), Sto<T>::st_sub(d[i], r[i]));
     }
 }
 
