@@ -376,14 +376,24 @@ def main() -> int:
     torch.cuda.set_device(0)
 
     if args.only_copy:
+        # a plain device copy of known size: the reference that scales the
+        # traffic counters, and the bandwidth a streaming kernel reaches here
         n = args.only_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ms = []
         for _ in range(3):
+            e0.record()
             dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_mib": args.only_copy, "repeats": 3}), flush=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        moved = 2 * n * 4
+        print(json.dumps({"copy_mib": args.only_copy, "repeats": 3, "ms": [round(m, 4) for m in ms],
+                          "read_plus_write_GBs": round(moved / (min(ms) * 1e-3) / 1e9, 1)}), flush=True)
         return 0
     if args.only_network:
         print(json.dumps(run_network(pkg)), flush=True)

@@ -255,6 +255,8 @@ Args args3(const lbm3d_ctx* c) {
     a.ns = c->ns;
     a.rho0 = c->g.rho0;
     a.tau = c->g.tau;
+    a.omega = 1.0 / c->g.tau;
+    a.cs = 1.0 - 0.5 / c->g.tau;
     for (int d = 0; d < 3; ++d) a.g[d] = c->g.g[d];
     a.nchunks = c->L.nchunks;
     a.hist_cap = c->hist_cap;

@@ -50,6 +50,7 @@ struct Args {
     int refill;       // 0 A1, 1 A2, 2 A3
     int ibb;          // interpolated bounce-back on sphere links
     double rho_in, rho_out;  // pressure planes x = 0 and x = nx - 1
+    double omega, cs;        // 1 / tau and 1 - 1 / (2 tau), formed on the host
 };
 
 // Solid table row: X, r, V (3), Omega (3), moves, free; row 0 is the duct.
@@ -137,9 +138,12 @@ __device__ inline void collide3(double d[kQ], const Args& a) {
     }
     const double rho = a.rho0 + drho;
     const double Fx = rho * a.g[0], Fy = rho * a.g[1], Fz = rho * a.g[2];
-    const double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
+    // one correctly rounded reciprocal instead of three divisions (and the
+    // rates from the host: no division per node on the tau of the lattice)
+    const double inv = 1.0 / rho;
+    const double ux = (jx + 0.5 * Fx) * inv, uy = (jy + 0.5 * Fy) * inv, uz = (jz + 0.5 * Fz) * inv;
     const double uu = ux * ux + uy * uy + uz * uz;
-    const double om = 1.0 / a.tau, cs = 1.0 - 0.5 / a.tau;
+    const double om = a.omega, cs = a.cs;
     const double uF = ux * Fx + uy * Fy + uz * Fz;
     // equilibrium deviation w (rho - rho0) + w rho (3 eu + 4.5 eu^2 - 1.5 u^2)
     // and Guo source w [3 (e - u) + 9 (e . u) e] . F, split into the parts
@@ -348,14 +352,22 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
     const uint32_t ux = (uint32_t)x;
     const uint32_t uxm = (uint32_t)(x == 0 ? a.nx - 1 : x - 1), uxp = (uint32_t)(x == a.nx - 1 ? 0 : x + 1);
     const uint8_t self = *at3(p.own + line * a.pitch, ux);
+    // owner of the source x - e_i of direction i; only the OR of the
+    // eighteen is kept through the loads (registers for occupancy), the
+    // owners themselves are read again, from cache, where a source is solid
+    auto src_of = [&](int i) -> uint32_t {
+        const uint32_t xs = kE[i][0] == 1 ? uxm : (kE[i][0] == -1 ? uxp : ux);
+        const int ys = wrap3(y - kE[i][1], a.ny), zs = wrap3(z - kE[i][2], a.nz);
+        return *at3(p.own + ((int64_t)zs * a.ny + ys) * a.pitch, xs);
+    };
     T raw[kQ];
-    uint8_t src[kQ];
+    uint32_t any = 0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const uint32_t xs = kE[i][0] == 1 ? uxm : (kE[i][0] == -1 ? uxp : ux);
         const int ys = wrap3(y - kE[i][1], a.ny), zs = wrap3(z - kE[i][2], a.nz);
         const int64_t ls = (int64_t)zs * a.ny + ys;
-        src[i] = *at3(p.own + ls * a.pitch, xs);
+        if (i > 0) any |= *at3(p.own + ls * a.pitch, xs);
         const T* ptr = at3(fin + (ls * kQ + i) * a.pitch, xs);
         if constexpr (NT)
             raw[i] = __builtin_nontemporal_load(ptr);
@@ -366,10 +378,10 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
     double d[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) d[i] = (double)Sto<T>::ld(raw[i]);
-    uint32_t any = 0;
-#pragma unroll
-    for (int i = 1; i < kQ; ++i) any |= src[i];
     if (any) {
+        uint32_t src[kQ];
+#pragma unroll
+        for (int i = 1; i < kQ; ++i) src[i] = src_of(i);
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
             if (src[i] == 0) continue;
