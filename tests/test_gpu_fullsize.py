@@ -293,7 +293,7 @@ def test_tube_3d_fullsize(oracle_mod, pkg):
     fl[:, :, -1] = False
     # The drive of this workload is tiny (a pressure drop of 1.8e-5): after 100
     # steps |u| ~ 1e-5 and the sphere's drag is ~1e-4 of a single link's exchange,
-    # so the bars come from the arithmetic (R21): velocity within 64 eps
+    # so the bars come from the arithmetic: velocity within 64 eps
     # absolute (the oracle sums full populations of size <= 1/3), forces
     # within 1e-10 relative plus 16 eps times the summed link magnitudes
     # of each solid's own links (the sum of |link force components| over the
