@@ -349,3 +349,34 @@ def test_periodic_crop_reduced_precision_ibb(oracle_mod, pkg, dtype):
         assert final <= 1e-3 and hist <= 1e-3
     else:
         assert final <= BF16_LEVEL[0] and hist <= BF16_LEVEL[1]
+
+
+def test_batched_uneven_256_fullsize_matches_lone_runs(pkg):
+    """The 256 uneven channel/cylinder cases (49.5 M nodes, FP32) in the launch
+    configuration the benchmark times (autotuned tiling, graph-replayed
+    intervals of 100 steps with the residual monitor): after 300 steps the
+    smallest, the largest and two other cases equal the same cases advanced
+    alone bit for bit (fields), and every case's device residual is finite
+    and positive (none has converged yet)."""
+    cases = lc.uneven_channels()
+    steps = 300
+    _say(f"batched 256 uneven cases, FP32, {steps} steps, sampled cases vs lone runs")
+    b = pkg.LatticeBatch(cases, dtype="f32")
+    b.autotune(None)
+    assert b.run(steps, 1e-8, 100) == steps
+    conv, _, res, _ = b.status()
+    assert not any(conv)
+    assert all(np.isfinite(r) and r > 0 for r in res)
+    sizes = [c["nx"] * c["ny"] for c in cases]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 131})
+    for k in picks:
+        c = cases[k]
+        lat = pkg.Lattice(c, dtype="f32", history_steps=steps + 1)
+        lat.step(steps)
+        lone = [a.cpu().numpy() for a in lat.fields("f64")[:3]]
+        bat = [a.cpu().numpy() for a in b.fields(k, "f64")]
+        _say(f"  case {k} ({c['nx']}x{c['ny']}, tiling {b.tiling()}): max |d rho| "
+             f"{np.abs(lone[0] - bat[0]).max():.1e}")
+        for u, v in zip(lone, bat):
+            assert np.array_equal(u, v), (k, c["name"])
+        del lat
