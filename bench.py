@@ -56,6 +56,29 @@ def _note(msg: str) -> None:
     print(f"# {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
+def run_copy(torch, mib, repeats=3):
+    """A plain device copy of `mib` MiB (torch's copy kernel), timed with HIP
+    events: the read-plus-write bandwidth a streaming kernel reaches on this
+    device, the practical reference next to the 8 TB/s peak."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(repeats):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_mib": mib, "repeats": repeats, "ms": [round(m, 4) for m in ms],
+            "read_plus_write_GBs": round(2 * n * 4 / (min(ms) * 1e-3) / 1e9, 1)}
+
+
 def run_gpu(case, dtype, steps, warmup, torch, pkg, mrt=None, ibb=False):
     """Warm up, then time `steps` steps with HIP events around the whole timed
     region, on the lattice's stream.  Whole blocks of 32 steps replay one HIP
@@ -378,22 +401,7 @@ def main() -> int:
     if args.only_copy:
         # a plain device copy of known size: the reference that scales the
         # traffic counters, and the bandwidth a streaming kernel reaches here
-        n = args.only_copy * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        ms = []
-        for _ in range(3):
-            e0.record()
-            dst.copy_(src)
-            e1.record()
-            torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        moved = 2 * n * 4
-        print(json.dumps({"copy_mib": args.only_copy, "repeats": 3, "ms": [round(m, 4) for m in ms],
-                          "read_plus_write_GBs": round(moved / (min(ms) * 1e-3) / 1e9, 1)}), flush=True)
+        print(json.dumps(run_copy(torch, args.only_copy)), flush=True)
         return 0
     if args.only_network:
         print(json.dumps(run_network(pkg)), flush=True)
@@ -432,6 +440,11 @@ def main() -> int:
                 "alg_bytes_per_fluid_node": 18 * BYTES[args.dtype]}
     del lat
     torch.cuda.empty_cache()
+    # the same fraction against what a plain device copy reaches here (after
+    # the timed region, so that it does not warm the device for it)
+    cp = run_copy(torch, 1024)
+    roofline["copy_GBs"] = cp["read_plus_write_GBs"]
+    roofline["frac_of_copy"] = round(achieved / cp["read_plus_write_GBs"], 4)
 
     _note(f"headline {wl} done: {ms_per_step * 1e3:.2f} us per step")
     extra = {}
@@ -524,6 +537,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(big, args.cpu_sample_steps)
 
+    extra["headline_fluid_node_mlups"] = round(n_fluid * args.steps / (total_ms * 1e-3) / 1e6, 1)
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
