@@ -288,7 +288,17 @@ def run_network(pkg):
 
     r = ws.network_throughput(batch=8, steps=40)
     r["train_frac_of_bf16_peak"] = round(r["train_tflops"] / MFMA_BF16_PEAK_TFLOPS, 4)
-    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+    # the deep levels give too few output tiles at batch 8 to fill the
+    # device: the same kernels at larger batches
+    sweep = {}
+    for b in (32, 64):
+        q = ws.network_throughput(batch=b, steps=20)
+        sweep[str(b)] = {"train_step_ms": round(q["train_step_ms"], 4), "train_tflops": round(q["train_tflops"], 1),
+                         "train_frac_of_bf16_peak": round(q["train_tflops"] / MFMA_BF16_PEAK_TFLOPS, 4),
+                         "infer_ms": round(q["infer_ms"], 4), "infer_tflops": round(q["infer_tflops"], 1)}
+    out["batch_sweep"] = sweep
+    return out
 
 
 def run_warm_start(lc, pkg, n_cases):
