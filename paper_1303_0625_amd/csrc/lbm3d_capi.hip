@@ -32,7 +32,7 @@ size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 constexpr size_t kStreamBytes3 = 256ull << 20;  // Infinity Cache: stream above it
 
 struct Layout3 {
-    size_t f[2], own[2], links, seg_off, seg_cnt, chunk_solid, chunk_start, solid_chunk0, sol[2], partial, hist,
+    size_t f[2], own[2], flags[2], links, seg_off, seg_cnt, chunk_solid, chunk_start, solid_chunk0, sol[2], partial, hist,
         tctr, movers, mass, err, total;
     int pitch;
     int nchunks;
@@ -143,7 +143,8 @@ const char* validate(const lbm3d_grid* g, const lbm3d_sphere* sp, int ns) {
 
 // Geometry and link lists on the host; returns an error message or nullptr.
 const char* build_geometry(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, int pitch,
-                           std::vector<uint8_t>& own, std::vector<std::vector<uint32_t>>& seg) {
+                           std::vector<uint8_t>& own, std::vector<uint8_t>& flags,
+                           std::vector<std::vector<uint32_t>>& seg) {
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     own.assign((size_t)ny * nz * pitch, 0);
     bool overlap = false;
@@ -157,11 +158,15 @@ const char* build_geometry(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, 
                                  {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
                                  {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
     seg.assign(ns + 1, {});
+    flags.assign(own.size(), 0);
     size_t nfluid = 0;
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
-                if (own[((size_t)z * ny + y) * pitch + x] != 0) continue;
+                if (own[((size_t)z * ny + y) * pitch + x] != 0) {
+                    flags[((size_t)z * ny + y) * pitch + x] = kSolidNode;
+                    continue;
+                }
                 ++nfluid;
                 const uint32_t node = (uint32_t)(((int64_t)z * ny + y) * nx + x);
                 for (int i = 1; i < 19; ++i) {
@@ -169,6 +174,7 @@ const char* build_geometry(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, 
                               zb = (z + E[i][2] + nz) % nz;
                     const uint8_t o = own[((size_t)zb * ny + yb) * pitch + xb];
                     if (o == 0) continue;
+                    flags[((size_t)z * ny + y) * pitch + x] = kNearSolid;
                     if (o != kDuct && sp[o - 1].moves) continue;  // found by the box scan each step
                     seg[o == kDuct ? 0 : o].push_back(node << 5 | (uint32_t)i);
                 }
@@ -197,6 +203,8 @@ Layout3 make_layout(const lbm3d_grid& g, const lbm3d_sphere* sp, int ns, int pit
     off = al256(off + fbytes);
     for (int k = 0; k < 2; ++k) {
         L.own[k] = off;
+        off = al256(off + (size_t)g.ny * g.nz * pitch);
+        L.flags[k] = off;
         off = al256(off + (size_t)g.ny * g.nz * pitch);
     }
     int64_t nl = 0;
@@ -246,6 +254,15 @@ P* at(lbm3d_ctx* c, size_t off) {
     return reinterpret_cast<P*>(c->ws + off);
 }
 
+// Round-up multiplier m and shift l = ceil(log2 d) with n / d ==
+// (mulhi(n, m) + n) >> l for 0 <= n < 2^31, d >= 1 (Granlund and
+// Montgomery, PLDI 1994).
+void magic32(uint32_t d, uint32_t& m, uint32_t& l) {
+    l = 0;
+    while ((1ull << l) < d) ++l;
+    m = (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+}
+
 Args args3(const lbm3d_ctx* c) {
     Args a{};
     a.nx = c->g.nx;
@@ -267,6 +284,12 @@ Args args3(const lbm3d_ctx* c) {
     a.ibb = c->ibb;
     a.rho_in = c->rho_in;
     a.rho_out = c->rho_out;
+    // update workgroups per plane and waves per line, with their division
+    // multipliers
+    a.W = (uint32_t)(c->L.pitch / 64);
+    a.K = (uint32_t)((c->g.ny * a.W + kBlock / 64 - 1) / (kBlock / 64));
+    magic32(a.K, a.magK, a.shK);
+    magic32(a.W, a.magW, a.shW);
     return a;
 }
 
@@ -298,10 +321,10 @@ lbm_status lbm3d_workspace_bytes(const lbm3d_grid* g, const lbm3d_sphere* sphere
         set_err3(g_err3, "history_steps must be >= 1");
         return LBM_EINVAL;
     }
-    std::vector<uint8_t> own;
+    std::vector<uint8_t> own, flags;
     std::vector<std::vector<uint32_t>> seg;
     const int pitch = pitch_for(g->nx);
-    if (const char* why = build_geometry(*g, spheres, n_spheres, pitch, own, seg)) {
+    if (const char* why = build_geometry(*g, spheres, n_spheres, pitch, own, flags, seg)) {
         set_err3(g_err3, "%s", why);
         return LBM_EGEOM;
     }
@@ -330,9 +353,9 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
         return LBM_EINVAL;
     }
     const int pitch = pitch_for(g->nx);
-    std::vector<uint8_t> own;
+    std::vector<uint8_t> own, flags;
     std::vector<std::vector<uint32_t>> seg;
-    if (const char* why = build_geometry(*g, spheres, n_spheres, pitch, own, seg)) {
+    if (const char* why = build_geometry(*g, spheres, n_spheres, pitch, own, flags, seg)) {
         set_err3(g_err3, "%s", why);
         return LBM_EGEOM;
     }
@@ -386,6 +409,8 @@ lbm_status lbm3d_create(const lbm3d_grid* g, const lbm3d_sphere* spheres, int32_
     };
     up(L.own[0], own.data(), own.size());
     up(L.own[1], own.data(), own.size());
+    up(L.flags[0], flags.data(), flags.size());
+    up(L.flags[1], flags.data(), flags.size());
     up(L.movers, movers.data(), 4 * movers.size());
     up(L.links, links.data(), 4 * links.size());
     up(L.seg_off, seg_off.data(), 4 * seg_off.size());
@@ -473,9 +498,8 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
     const int n_fin = (c->ns + 1) * 12;  // one finalizer workgroup per (solid, component)
     const int n_lead = (c->L.nchunks + n_fin + 7) / 8 * 8;
     const int64_t lines = (int64_t)c->g.ny * c->g.nz;
-    const int64_t waves = lines * (c->L.pitch / 64);
-    const int64_t K = ((int64_t)c->g.ny * (c->L.pitch / 64) + kBlock / 64 - 1) / (kBlock / 64);
-    const int64_t n_upd = ((waves + kBlock / 64 - 1) / (kBlock / 64) + 8 * K - 1) / (8 * K) * (8 * K);
+    // the update workgroups: K per plane, the planes in groups of eight
+    const int64_t n_upd = (int64_t)((c->g.nz + 7) / 8) * 8 * a.K;
     const unsigned grid = (unsigned)(n_lead + n_upd);
     const size_t es = c->g.dtype == LBM_F64 ? 8 : 4;
     const bool nt = 2 * (size_t)19 * lines * c->L.pitch * es > kStreamBytes3;
@@ -495,6 +519,7 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
         p.fin = c->ws + c->L.f[par];
         p.fout = c->ws + c->L.f[par ^ 1];
         p.own = at<uint8_t>(c, c->L.own[par]);
+        p.flags = at<uint8_t>(c, c->L.flags[par]);
         p.sol = at<double>(c, c->L.sol[par]);
         const bool timed = c->prof && c->ev_used + 2 <= c->ev.size();
         if (timed) HIPCHK3(c, hipEventRecord(c->ev[c->ev_used], c->stream));
@@ -528,6 +553,8 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
             uint8_t* own_n = at<uint8_t>(c, c->L.own[par ^ 1]);
             const int64_t N = (int64_t)c->g.nx * c->g.ny * c->g.nz;
             k3_raster<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(sol_n, own_n, c->t + 1, a);
+            k3_flags<<<(unsigned)((N + kBlock - 1) / kBlock), kBlock, 0, c->stream>>>(
+                own_n, at<uint8_t>(c, c->L.flags[par ^ 1]), a);
             const int cpm = (int)(((int64_t)c->L.box * c->L.box * c->L.box + kBlock - 1) / kBlock);
             const unsigned nrb = (unsigned)(cpm * c->L.nmovers);
             const int* mv = at<int>(c, c->L.movers);

@@ -25,6 +25,9 @@ constexpr int kBlock = 256;
 constexpr int kChunk = 512;  // links per force workgroup
 constexpr int kQ = 19;
 constexpr uint8_t kDuct = 255;  // owner value of duct nodes (force slot 0)
+// Node flags kept beside the owners: the node is solid, or it is fluid and
+// some neighbour x + e_i (equally, some source x - e_i) is solid.
+constexpr uint8_t kSolidNode = 2, kNearSolid = 1;
 
 // Velocity set: rest, the axis directions (+x, -x, +y, -y, +z, -z), the
 // twelve edge diagonals in opposite pairs; opposite of i is i + 1 for odd
@@ -51,7 +54,26 @@ struct Args {
     int ibb;          // interpolated bounce-back on sphere links
     double rho_in, rho_out;  // pressure planes x = 0 and x = nx - 1
     double omega, cs;        // 1 / tau and 1 - 1 / (2 tau), formed on the host
+    // update workgroups per plane K and waves per line W, with the
+    // multipliers and shifts of their division (divq)
+    uint32_t K, magK, shK, W, magW, shW;
 };
+
+// n / d for 0 <= n < 2^31 from the round-up multiplier m and shift
+// l = ceil(log2 d) of d (Granlund and Montgomery, PLDI 1994).
+__device__ inline uint32_t divq(uint32_t n, uint32_t m, uint32_t l) { return (__umulhi(n, m) + n) >> l; }
+
+// Lines (y, z) that the duct makes solid at every x: the tube's outside, the
+// two planes.  The squares of the half-integer offsets and their sum are
+// exact in double, so the test is the same wherever it is evaluated.
+__device__ inline bool duct_solid3(int y, int z, const Args& a) {
+#pragma clang fp contract(off)
+    if (a.duct == 1) {
+        const double dy = (double)y - 0.5 * (a.ny - 1), dz = (double)z - 0.5 * (a.nz - 1);
+        return dy * dy + dz * dz > a.R * a.R;
+    }
+    return a.duct == 2 && (z == 0 || z == a.nz - 1);
+}
 
 // Solid table row: X, r, V (3), Omega (3), moves, free; row 0 is the duct.
 // One table per step parity: a free sphere's row holds its centre, velocity
@@ -126,7 +148,15 @@ __device__ inline double sphere_q3(const double* __restrict__ sol, int s, int64_
 }
 
 // BGK + Guo on deviations, in FP64: rho = rho0 + sum d, momentum sum e d
-// (the weights' first moment vanishes), u = (j + rho g/2)/rho.
+// (the weights' first moment vanishes), u = (j + rho g/2)/rho.  With
+// eu = e_i . u and eF = e_i . F the post-collision value is
+//   (1 - omega) d_i + w_i [C + eu (4.5 omega rho eu + 9 cs eF)]
+//                   + w_i [3 omega rho eu + 3 cs eF],
+// C = omega (drho - 1.5 rho u^2) - 3 cs u . F: the equilibrium deviation
+// w (rho - rho0) + w rho (3 eu + 4.5 eu^2 - 1.5 u^2) relaxed at omega plus
+// the Guo source w [3 (e - u) + 9 (e . u) e] . F at cs, grouped by parity
+// in e_i so that each opposite pair (i, i + 1) shares the even part and
+// takes the odd part with opposite signs.
 __device__ inline void collide3(double d[kQ], const Args& a) {
     double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
@@ -143,28 +173,21 @@ __device__ inline void collide3(double d[kQ], const Args& a) {
     const double inv = 1.0 / rho;
     const double ux = (jx + 0.5 * Fx) * inv, uy = (jy + 0.5 * Fy) * inv, uz = (jz + 0.5 * Fz) * inv;
     const double uu = ux * ux + uy * uy + uz * uz;
-    const double om = a.omega, cs = a.cs;
+    const double om = a.omega, cs = a.cs, keep = 1.0 - a.omega;
     const double uF = ux * Fx + uy * Fy + uz * Fz;
-    // equilibrium deviation w (rho - rho0) + w rho (3 eu + 4.5 eu^2 - 1.5 u^2)
-    // and Guo source w [3 (e - u) + 9 (e . u) e] . F, split into the parts
-    // even and odd in e_i, so that each opposite pair (i, i + 1) shares one
-    // evaluation
-    {
-        const double deq0 = w3(0) * (drho - rho * 1.5 * uu);
-        const double src0 = w3(0) * (-3.0 * uF);
-        d[0] = d[0] - om * (d[0] - deq0) + cs * src0;
-    }
+    const double C = om * (drho - 1.5 * rho * uu) - 3.0 * cs * uF;
+    const double P = 4.5 * om * rho, R = 3.0 * om * rho;
+    const double Q = 9.0 * cs, S = 3.0 * cs;
+    d[0] = keep * d[0] + w3(0) * C;
 #pragma unroll
     for (int i = 1; i < kQ; i += 2) {
         const double w = w3(i);
         const double eu = kE[i][0] * ux + kE[i][1] * uy + kE[i][2] * uz;
         const double eF = kE[i][0] * Fx + kE[i][1] * Fy + kE[i][2] * Fz;
-        const double ev = w * (drho + rho * (4.5 * eu * eu - 1.5 * uu));
-        const double od = w * (3.0 * rho * eu);
-        const double sev = w * (9.0 * eu * eF - 3.0 * uF);
-        const double sod = w * (3.0 * eF);
-        d[i] = d[i] - om * (d[i] - (ev + od)) + cs * (sev + sod);
-        d[i + 1] = d[i + 1] - om * (d[i + 1] - (ev - od)) + cs * (sev - sod);
+        const double ev = w * (C + eu * (P * eu + Q * eF));
+        const double od = w * (R * eu + S * eF);
+        d[i] = keep * d[i] + (ev + od);
+        d[i + 1] = keep * d[i + 1] + (ev - od);
     }
 }
 
@@ -172,6 +195,7 @@ struct Ptrs {
     const void* fin;
     void* fout;
     const uint8_t* own;
+    const uint8_t* flags;     // per node: kSolidNode, kNearSolid or 0
     const uint32_t* links;    // per link: node << 5 | i
     const int* seg_off;       // per solid slot
     const int* seg_cnt;
@@ -337,51 +361,61 @@ __device__ inline const T* at3(const T* base, uint32_t idx) {
 // the post-collision state in the same launch.
 template <typename T, bool NT, bool IBB, bool PR>
 __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& a, int64_t t) {
-    const T* fin = (const T*)p.fin;
-    T* fout = (T*)p.fout;
-    const int64_t line = (int64_t)z * a.ny + y;
+    const char* fin = (const char*)p.fin;
+    char* fout = (char*)p.fout;
+    const uint32_t ny = (uint32_t)a.ny, pitch = (uint32_t)a.pitch;
+    // byte strides of a population row and of a line's nineteen rows
+    const uint32_t rowB = pitch * (uint32_t)sizeof(T), lineB = (uint32_t)kQ * rowB;
+    // wave-uniform: the wrapped neighbour lines, and the line z_s ny + y_s
+    // that direction i pulls from
+    const uint32_t uy = (uint32_t)y, uz = (uint32_t)z;
+    const uint32_t ym = uy == 0 ? ny - 1 : uy - 1, yp = uy + 1 == ny ? 0 : uy + 1;
+    const uint32_t zm = uz == 0 ? (uint32_t)a.nz - 1 : uz - 1, zp = uz + 1 == (uint32_t)a.nz ? 0 : uz + 1;
+    auto src_line = [&](int i) -> uint32_t {
+        const uint32_t ys = kE[i][1] == 1 ? ym : (kE[i][1] == -1 ? yp : uy);
+        const uint32_t zs = kE[i][2] == 1 ? zm : (kE[i][2] == -1 ? zp : uz);
+        return zs * ny + ys;
+    };
+    const uint32_t line = uz * ny + uy;
+    auto own_at = [&](uint32_t L, uint32_t xs) -> uint32_t { return *at3(p.own + (uint64_t)L * pitch, xs); };
+    auto row_in = [&](uint32_t L, int i) -> const T* {
+        return (const T*)(fin + (uint64_t)L * lineB + (uint32_t)i * rowB);
+    };
     int x = xo;
     bool plane = false;
     if constexpr (PR) {
         if (xo == 0 || xo == a.nx - 1) {
             const int xf = xo == 0 ? 1 : a.nx - 2;
-            plane = *at3(p.own + line * a.pitch, (uint32_t)xo) == 0 && *at3(p.own + line * a.pitch, (uint32_t)xf) == 0;
+            plane = own_at(line, (uint32_t)xo) == 0 && own_at(line, (uint32_t)xf) == 0;
             if (plane) x = xf;
         }
     }
     const uint32_t ux = (uint32_t)x;
     const uint32_t uxm = (uint32_t)(x == 0 ? a.nx - 1 : x - 1), uxp = (uint32_t)(x == a.nx - 1 ? 0 : x + 1);
-    const uint8_t self = *at3(p.own + line * a.pitch, ux);
-    // owner of the source x - e_i of direction i; only the OR of the
-    // eighteen is kept through the loads (registers for occupancy), the
-    // owners themselves are read again, from cache, where a source is solid
-    auto src_of = [&](int i) -> uint32_t {
-        const uint32_t xs = kE[i][0] == 1 ? uxm : (kE[i][0] == -1 ? uxp : ux);
-        const int ys = wrap3(y - kE[i][1], a.ny), zs = wrap3(z - kE[i][2], a.nz);
-        return *at3(p.own + ((int64_t)zs * a.ny + ys) * a.pitch, xs);
-    };
+    auto src_x = [&](int i) -> uint32_t { return kE[i][0] == 1 ? uxm : (kE[i][0] == -1 ? uxp : ux); };
+    // every load is issued whatever the node's flags (a solid node's values
+    // are computed on and not stored: a test before the loads would cost a
+    // round trip to memory); the owners of the sources are read, from cache,
+    // only where the flags say that one of them is solid
+    const uint32_t flag = *at3(p.flags + (uint64_t)line * pitch, ux);
     T raw[kQ];
-    uint32_t any = 0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        const uint32_t xs = kE[i][0] == 1 ? uxm : (kE[i][0] == -1 ? uxp : ux);
-        const int ys = wrap3(y - kE[i][1], a.ny), zs = wrap3(z - kE[i][2], a.nz);
-        const int64_t ls = (int64_t)zs * a.ny + ys;
-        if (i > 0) any |= *at3(p.own + ls * a.pitch, xs);
-        const T* ptr = at3(fin + (ls * kQ + i) * a.pitch, xs);
+        const uint32_t L = src_line(i), xs = src_x(i);
+        const T* ptr = at3(row_in(L, i), xs);
         if constexpr (NT)
             raw[i] = __builtin_nontemporal_load(ptr);
         else
             raw[i] = *ptr;
     }
-    if (self) return;
     double d[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) d[i] = (double)Sto<T>::ld(raw[i]);
-    if (any) {
+    const bool self = (flag & kSolidNode) != 0;
+    if (flag == kNearSolid) {
         uint32_t src[kQ];
 #pragma unroll
-        for (int i = 1; i < kQ; ++i) src[i] = src_of(i);
+        for (int i = 1; i < kQ; ++i) src[i] = own_at(src_line(i), src_x(i));
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
             if (src[i] == 0) continue;
@@ -397,15 +431,15 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
                     surface_vel(p.sol, s, t, x - q * kE[i][0], y - q * kE[i][1], z - q * kE[i][2], a, v, r);
                     const double m = 6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
                     const int o = opp3(i);
-                    const double fo = (double)Sto<T>::ld(*at3(fin + (line * kQ + o) * a.pitch, ux));
-                    const double fi = (double)Sto<T>::ld(*at3(fin + (line * kQ + i) * a.pitch, ux));
+                    const double fo = (double)Sto<T>::ld(*at3(row_in(line, o), ux));
+                    const double fi = (double)Sto<T>::ld(*at3(row_in(line, i), ux));
                     d[i] = lbm::ibb_value<double>(q, fo, fi, d[o], src[o] == 0, m);
                     continue;
                 }
             }
             double v[3], r[3];
             surface_vel(p.sol, s, t, x - 0.5 * kE[i][0], y - 0.5 * kE[i][1], z - 0.5 * kE[i][2], a, v, r);
-            d[i] = (double)Sto<T>::ld(*at3(fin + (line * kQ + opp3(i)) * a.pitch, ux)) +
+            d[i] = (double)Sto<T>::ld(*at3(row_in(line, opp3(i)), ux)) +
                    6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
         }
     }
@@ -433,10 +467,11 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
             }
         }
     }
+    if (self) return;
     const uint32_t uxo = (uint32_t)xo;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        T* ptr = const_cast<T*>(at3(fout + (line * kQ + i) * a.pitch, uxo));
+        T* ptr = const_cast<T*>(at3((const T*)(fout + (uint64_t)line * lineB + (uint32_t)i * rowB), uxo));
         const T val = Sto<T>::st(d[i]);
         if constexpr (NT)
             __builtin_nontemporal_store(val, ptr);
@@ -465,32 +500,26 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
         }
         return;
     }
-    const uint32_t wpr = (uint32_t)a.pitch >> 6;
-    // XCD-aware order: workgroup b runs on XCD b % 8 (n_lead and the number
-    // of update workgroups are multiples of 8 K); the eight XCDs take eight
-    // consecutive z-planes (K workgroups each) at a time, so the lines y +- 1
-    // a node pulls from are in the XCD's own L2
-    const uint32_t K = ((uint32_t)a.ny * wpr + (kBlock / 64) - 1) / (kBlock / 64);
-    const uint32_t u = (uint32_t)(b - n_lead);
-    const uint32_t ub = (u / (8u * K)) * (8u * K) + (u & 7u) * K + (u >> 3) % K;
-    const uint32_t gw = ub * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t line = gw / wpr;
-    const int x = (int)((gw - line * wpr) << 6) + (int)(threadIdx.x & 63);
-    if (line >= (uint32_t)(a.ny * a.nz) || x >= a.nx) return;
-    update3<T, NT, IBB, PR>(x, (int)(line % (uint32_t)a.ny), (int)(line / (uint32_t)a.ny), p, a, p.tctr[parity]);
+    // XCD-aware order: workgroup b runs on XCD b % 8 (n_lead is a multiple
+    // of 8); the eight XCDs take eight consecutive z-planes, one each, at a
+    // time (K workgroups per plane), so the lines y +- 1 a node pulls from
+    // are in the XCD's own L2
+    const uint32_t u = (uint32_t)(b - n_lead), v = u >> 3;
+    const uint32_t grp = divq(v, a.magK, a.shK);
+    const uint32_t z = 8u * grp + (u & 7u);
+    const uint32_t q = (v - grp * a.K) * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t y = divq(q, a.magW, a.shW);
+    const int x = (int)((q - y * a.W) << 6) + (int)(threadIdx.x & 63);
+    // the duct's solid lines hold no fluid node: the whole wave leaves
+    if (z >= (uint32_t)a.nz || y >= (uint32_t)a.ny || duct_solid3((int)y, (int)z, a) || x >= a.nx) return;
+    update3<T, NT, IBB, PR>(x, (int)y, (int)z, p, a, p.tctr[parity]);
 }
 
 // Owner of node (x, y, z) at step t: the duct, then the spheres (minimum
 // image, separately rounded products and sums, ties solid).
 __device__ inline uint8_t owner3(const double* __restrict__ sol, int x, int y, int z, int64_t t, const Args& a) {
 #pragma clang fp contract(off)
-    uint8_t o = 0;
-    if (a.duct == 1) {
-        const double dy = (double)y - 0.5 * (a.ny - 1), dz = (double)z - 0.5 * (a.nz - 1);
-        if (dy * dy + dz * dz > a.R * a.R) o = kDuct;
-    } else if (a.duct == 2) {
-        if (z == 0 || z == a.nz - 1) o = kDuct;
-    }
+    uint8_t o = duct_solid3(y, z, a) ? kDuct : 0;
     for (int k = 1; k <= a.ns; ++k) {
         double X[3];
         centre3(sol, k, t, X);
@@ -513,6 +542,26 @@ __global__ __launch_bounds__(kBlock) void k3_raster(const double* __restrict__ s
     const int x = (int)(n % a.nx);
     const int64_t line = n / a.nx;
     own_n[line * a.pitch + x] = owner3(sol, x, (int)(line % a.ny), (int)(line / a.ny), t1, a);
+}
+
+// Flags of every node from the owners of step t + 1 (moving spheres).
+__global__ __launch_bounds__(kBlock) void k3_flags(const uint8_t* __restrict__ own_n, uint8_t* __restrict__ flags_n,
+                                                   Args a) {
+    const int64_t n = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n >= (int64_t)a.nx * a.ny * a.nz) return;
+    const int x = (int)(n % a.nx);
+    const int64_t line = n / a.nx;
+    const int y = (int)(line % a.ny), z = (int)(line / a.ny);
+    uint8_t f = 0;
+    if (own_n[line * a.pitch + x] != 0) {
+        f = kSolidNode;
+    } else {
+        for (int i = 1; i < kQ; ++i) {
+            const int xb = wrap3(x + kE[i][0], a.nx), yb = wrap3(y + kE[i][1], a.ny), zb = wrap3(z + kE[i][2], a.nz);
+            if (own_n[((int64_t)zb * a.ny + yb) * a.pitch + xb] != 0) f = kNearSolid;
+        }
+    }
+    flags_n[line * a.pitch + x] = f;
 }
 
 // Post-advection deviation of direction j at node (x, y, z) from step t's
