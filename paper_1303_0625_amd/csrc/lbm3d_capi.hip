@@ -290,6 +290,7 @@ Args args3(const lbm3d_ctx* c) {
     a.K = (uint32_t)((c->g.ny * a.W + kBlock / 64 - 1) / (kBlock / 64));
     magic32(a.K, a.magK, a.shK);
     magic32(a.W, a.magW, a.shW);
+    magic32((uint32_t)c->g.ny, a.magNy, a.shNy);
     return a;
 }
 
@@ -498,8 +499,10 @@ lbm_status lbm3d_step(lbm3d_ctx* c, int64_t n) {
     const int n_fin = (c->ns + 1) * 12;  // one finalizer workgroup per (solid, component)
     const int n_lead = (c->L.nchunks + n_fin + 7) / 8 * 8;
     const int64_t lines = (int64_t)c->g.ny * c->g.nz;
-    // the update workgroups: K per plane, the planes in groups of eight
-    const int64_t n_upd = (int64_t)((c->g.nz + 7) / 8) * 8 * a.K;
+    // the update workgroups: one wave per 64 nodes of a line, the grid
+    // padded to a multiple of 8 K
+    const int64_t waves = lines * (c->L.pitch / 64), K8 = 8 * (int64_t)a.K;
+    const int64_t n_upd = ((waves + kBlock / 64 - 1) / (kBlock / 64) + K8 - 1) / K8 * K8;
     const unsigned grid = (unsigned)(n_lead + n_upd);
     const size_t es = c->g.dtype == LBM_F64 ? 8 : 4;
     const bool nt = 2 * (size_t)19 * lines * c->L.pitch * es > kStreamBytes3;

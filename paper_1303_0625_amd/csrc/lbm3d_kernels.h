@@ -54,9 +54,9 @@ struct Args {
     int ibb;          // interpolated bounce-back on sphere links
     double rho_in, rho_out;  // pressure planes x = 0 and x = nx - 1
     double omega, cs;        // 1 / tau and 1 - 1 / (2 tau), formed on the host
-    // update workgroups per plane K and waves per line W, with the
+    // update workgroups per plane K, waves per line W and ny, with the
     // multipliers and shifts of their division (divq)
-    uint32_t K, magK, shK, W, magW, shW;
+    uint32_t K, magK, shK, W, magW, shW, magNy, shNy;
 };
 
 // n / d for 0 <= n < 2^31 from the round-up multiplier m and shift
@@ -395,13 +395,18 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
     auto src_x = [&](int i) -> uint32_t { return kE[i][0] == 1 ? uxm : (kE[i][0] == -1 ? uxp : ux); };
     // every load is issued whatever the node's flags (a solid node's values
     // are computed on and not stored: a test before the loads would cost a
-    // round trip to memory); the owners of the sources are read, from cache,
-    // only where the flags say that one of them is solid
+    // round trip to memory).  Streamed (large) lattices read the owners of
+    // the sources only where the flags say that one of them is solid; in a
+    // cache-resident lattice the step is latency-bound, so the eighteen
+    // owners come with the populations (only their OR is kept through the
+    // loads; they are read again, from cache, where a source is solid)
     const uint32_t flag = *at3(p.flags + (uint64_t)line * pitch, ux);
     T raw[kQ];
+    uint32_t any = 0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const uint32_t L = src_line(i), xs = src_x(i);
+        if (!NT && i > 0) any |= own_at(L, xs);
         const T* ptr = at3(row_in(L, i), xs);
         if constexpr (NT)
             raw[i] = __builtin_nontemporal_load(ptr);
@@ -412,7 +417,7 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
 #pragma unroll
     for (int i = 0; i < kQ; ++i) d[i] = (double)Sto<T>::ld(raw[i]);
     const bool self = (flag & kSolidNode) != 0;
-    if (flag == kNearSolid) {
+    if (NT ? flag == kNearSolid : (any != 0 && !self)) {
         uint32_t src[kQ];
 #pragma unroll
         for (int i = 1; i < kQ; ++i) src[i] = own_at(src_line(i), src_x(i));
@@ -500,18 +505,21 @@ __global__ __launch_bounds__(kBlock) void k3_step(Ptrs p, int parity, int n_lead
         }
         return;
     }
-    // XCD-aware order: workgroup b runs on XCD b % 8 (n_lead is a multiple
-    // of 8); the eight XCDs take eight consecutive z-planes, one each, at a
-    // time (K workgroups per plane), so the lines y +- 1 a node pulls from
-    // are in the XCD's own L2
+    // XCD-aware order: workgroup b runs on XCD b % 8 (n_lead and the number
+    // of update workgroups are multiples of 8 K); each XCD takes a run of K
+    // consecutive workgroups, one plane's worth of waves, and the eight XCDs
+    // eight consecutive runs at a time, so the lines y +- 1 a node pulls from
+    // are in the XCD's own L2 while all XCDs stay in one neighbourhood of
+    // planes.  The divisions use multipliers formed on the host.
     const uint32_t u = (uint32_t)(b - n_lead), v = u >> 3;
     const uint32_t grp = divq(v, a.magK, a.shK);
-    const uint32_t z = 8u * grp + (u & 7u);
-    const uint32_t q = (v - grp * a.K) * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t y = divq(q, a.magW, a.shW);
-    const int x = (int)((q - y * a.W) << 6) + (int)(threadIdx.x & 63);
+    const uint32_t ub = grp * 8u * a.K + (u & 7u) * a.K + (v - grp * a.K);
+    const uint32_t gw = ub * (kBlock / 64) + (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t line = divq(gw, a.magW, a.shW);
+    const int x = (int)((gw - line * a.W) << 6) + (int)(threadIdx.x & 63);
+    const uint32_t z = divq(line, a.magNy, a.shNy), y = line - z * (uint32_t)a.ny;
     // the duct's solid lines hold no fluid node: the whole wave leaves
-    if (z >= (uint32_t)a.nz || y >= (uint32_t)a.ny || duct_solid3((int)y, (int)z, a) || x >= a.nx) return;
+    if (z >= (uint32_t)a.nz || duct_solid3((int)y, (int)z, a) || x >= a.nx) return;
     update3<T, NT, IBB, PR>(x, (int)y, (int)z, p, a, p.tctr[parity]);
 }
 
