@@ -1,6 +1,6 @@
 """Learned warm start on held-out channels (GPU): with the committed weights
-(trained by `python -m paper_1303_0625_amd.warmstart train` on 512 channels of
-seed 5005), the held-out channels of seed 5006 with Re < 16 reach a steady drag
+(trained by `python -m paper_1303_0625_amd.warmstart train --train 2000
+--epochs 300` on the channels of seed 5005), the held-out channels of seed 5006 with Re < 16 reach a steady drag
 (within 1e-4 of an FP64 cold run solved to r < 1e-11) in fewer steps from the
 learned start than from rest and than from the exact Poiseuille flow; every
 start reaches the same steady drag."""
