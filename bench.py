@@ -272,7 +272,9 @@ def run_3d(pkg, torch, steps):
                      "achieved_GBs": round(152 * nf / (kus * 1e-6) / 1e9, 1),
                      "frac": round(152 * nf / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                      "drag_gme": lat.force(1, 1)[0], "drive": "pressure" if small else "body force",
-                     "sphere_boundary": "interpolated" if small else "half-way"}
+                     "sphere_boundary": "interpolated" if small else "half-way",
+                     "alg_bytes_per_launch": 152 * nf,
+                     "traffic": None if small else stored_traffic(name, "k3_step", "lbm3d")}
         del lat
         torch.cuda.empty_cache()
     return out
