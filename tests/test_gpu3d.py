@@ -188,6 +188,24 @@ def test_translating_sphere_f64(oracle_mod, lbm_mod, refill, steps):
     assert force_err(lat, osim) <= 1e-10
 
 
+def test_translating_sphere_streamed_lattice_f64(oracle_mod, lbm_mod):
+    """A lattice above the streaming threshold (2 x 19 x 903,168 FP64 nodes =
+    274 MB of populations) takes the update that reads one flag byte per node
+    and the owners only next to a solid, with the flags rebuilt after every
+    raster of the translating sphere: FP64 fields and per-step forces against
+    the oracle, as on the small lattices."""
+    c = dict(name="moving_sphere_streamed", nx=128, ny=84, nz=84, tau=0.7, duct=1, R=40.0,
+             g=(2e-5, 0.0, 0.0), refill=0,
+             spheres=[dict(cx=30.2, cy=45.1, cz=38.3, r=6.2, v=(0.05, 0.01, -0.008), omega=(0.001, 0.002, 0.0),
+                           moves=True)])
+    assert 2 * 19 * c["ny"] * c["nz"] * 128 * 8 > 256 << 20
+    lat, osim = run_pair(oracle_mod, lbm_mod, c, 60, chunks=3)
+    assert osim.error == 0
+    er, eu = field_err(lat, osim)
+    assert er <= 1e-12 and eu <= 1e-12
+    assert force_err(lat, osim) <= 1e-10
+
+
 def test_translating_sphere_comoving_gpu(lbm_mod):
     """A sphere translating with the uniform flow f_eq(1, U) across several
     nodes leaves the state uniform and feels no force."""
