@@ -421,6 +421,21 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
         uint32_t src[kQ];
 #pragma unroll
         for (int i = 1; i < kQ; ++i) src[i] = own_at(src_line(i), src_x(i));
+        // the node's own values that bounce back: with the interpolated rule
+        // (many solid directions per node, each with its own geometry) all of
+        // them are loaded together here instead of one round trip per
+        // direction; the half-way rule keeps the registers for occupancy
+        T mine[kQ];
+        if constexpr (IBB) {
+#pragma unroll
+            for (int i = 1; i < kQ; ++i) mine[i] = *at3(row_in(line, i), ux);
+        }
+        auto own_val = [&](int i) -> double {
+            if constexpr (IBB)
+                return (double)Sto<T>::ld(mine[i]);
+            else
+                return (double)Sto<T>::ld(*at3(row_in(line, i), ux));
+        };
 #pragma unroll
         for (int i = 1; i < kQ; ++i) {
             if (src[i] == 0) continue;
@@ -436,16 +451,13 @@ __device__ inline void update3(int xo, int y, int z, const Ptrs& p, const Args& 
                     surface_vel(p.sol, s, t, x - q * kE[i][0], y - q * kE[i][1], z - q * kE[i][2], a, v, r);
                     const double m = 6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
                     const int o = opp3(i);
-                    const double fo = (double)Sto<T>::ld(*at3(row_in(line, o), ux));
-                    const double fi = (double)Sto<T>::ld(*at3(row_in(line, i), ux));
-                    d[i] = lbm::ibb_value<double>(q, fo, fi, d[o], src[o] == 0, m);
+                    d[i] = lbm::ibb_value<double>(q, own_val(o), own_val(i), d[o], src[o] == 0, m);
                     continue;
                 }
             }
             double v[3], r[3];
             surface_vel(p.sol, s, t, x - 0.5 * kE[i][0], y - 0.5 * kE[i][1], z - 0.5 * kE[i][2], a, v, r);
-            d[i] = (double)Sto<T>::ld(*at3(row_in(line, opp3(i)), ux)) +
-                   6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
+            d[i] = own_val(opp3(i)) + 6.0 * w3(i) * a.rho0 * (kE[i][0] * v[0] + kE[i][1] * v[1] + kE[i][2] * v[2]);
         }
     }
     collide3(d, a);
