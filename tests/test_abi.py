@@ -104,6 +104,19 @@ def test_batch_workspace_validation(L):
         L.lbm_batch_workspace_bytes([], [], [])
 
 
+def test_3d_workspace_holds_maps(L):
+    """The 3D workspace holds the two population buffers (the second 1 MiB
+    past the end of the first) and, per step parity, an owner map and a
+    node-flag map of one byte per node of the padded lattice: the FP64 and
+    FP32 workspaces differ by the populations alone, and what is not
+    populations holds at least the four maps."""
+    case = dict(nx=24, ny=20, nz=20, tau=0.7, duct=L.LBM3D_TUBE, R=8.0)
+    nodes = 20 * 20 * 64  # lines x pitch
+    n64, n32 = (L.lbm3d_workspace_bytes(L.make_grid3(case, d), (), 16) for d in ("f64", "f32"))
+    assert n64 - n32 == 2 * 19 * nodes * 4
+    assert n32 - (2 * 19 * nodes * 4 + (1 << 20)) >= 4 * nodes
+
+
 def test_3d_validation(L):
     """lbm3d_workspace_bytes validates on the host (no device needed)."""
     tube = dict(nx=24, ny=20, nz=20, tau=0.7, duct=L.LBM3D_TUBE, R=8.0,
